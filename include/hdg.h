@@ -1,0 +1,183 @@
+/*
+ * hdg.h — C ABI of libhdg.so, the MI355X (gfx950) hot path of the matrix-free
+ * macro-element HDG method for compressible Navier-Stokes
+ * (Badrkhani, ten Eikelder, Hiemstra, Schillinger, arXiv 2402.11361).
+ *
+ * One Newton step of a DIRK stage (Sec. 3, Algorithm 1) is
+ *     hdg_linearize_stage -> hdg_condense -> hdg_fgmres_solve
+ *     (hdg_apply_global inside) -> hdg_local_backsolve -> hdg_axpy (update).
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers owned by the caller (e.g. torch
+ *     tensors) unless the name ends in _host.  They must stay valid until the
+ *     work queued on the context's stream has finished.
+ *   - Work is queued on the HIP stream given at setup, in call order.  Only
+ *     calls with a _host output or a stats struct synchronise.
+ *   - Errors are returned as hdg_status; the call then has no effect on its
+ *     outputs unless stated, and hdg_last_error(ctx) gives a message.
+ *     Invalid arguments give HDG_EINVAL before anything is queued.
+ *   - Layouts (FP64 at the boundary always):
+ *       u     [macro][comp][node]         comp = rho, rho v_1..v_d, rho E
+ *       q     [macro][dir][comp][node]    q = grad u (eq. C4)
+ *       uhat  [face][comp][facenode]      trace on the macro skeleton
+ *     Macros are numbered s_0 + n_seg0 (s_1 + n_seg1 s_2); macro nodes
+ *     i_0 + n_0 (i_1 + n_1 i_2) with n_k = m_k p + 1 (GLL points in every
+ *     element, C0 inside the macro).  Faces: all faces normal to axis 0, then
+ *     1, then 2; within an axis lexicographic over the face grid (positions
+ *     along the normal axis, macro segments along the others), axis 0
+ *     fastest; face nodes over the tangential axes in increasing order.
+ *   - Calls on one context are not thread safe.
+ */
+#ifndef HDG_H
+#define HDG_H
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hdg_ctx_s* hdg_ctx;
+
+typedef enum {
+  HDG_OK = 0,
+  HDG_EINVAL = 1,       /* bad argument (null, size, layout)                  */
+  HDG_ENOMEM = 2,       /* workspace missing or too small                     */
+  HDG_EDEVICE = 3,      /* HIP runtime error (message has the HIP string)     */
+  HDG_ESINGULAR = 4,    /* zero pivot in a local factorisation                */
+  HDG_ENOCONV = 5,      /* Krylov solve hit its iteration limit               */
+  HDG_EBREAKDOWN = 6,   /* Krylov breakdown                                   */
+  HDG_ENAN = 7,         /* non-finite residual                                */
+  HDG_EUNSUPPORTED = 8  /* configuration not built (dimension, degree, ...)  */
+} hdg_status;
+
+typedef enum { HDG_FP64 = 0, HDG_FP32 = 1 } hdg_prec;
+
+/* Box mesh on [lo, hi] with n_elem[k] uniform elements per axis, grouped into
+ * box macro-elements: along axis k the segments have seg_len[k][0..n_seg[k])
+ * elements (host arrays, summing to n_elem[k]).  Degree p in every element
+ * (p = 1..3).  dim = 2 or 3.  Paper Sec. 2.2 (mesh, patches, spaces). */
+typedef struct {
+  int dim;
+  int n_elem[3];
+  double lo[3], hi[3];
+  int periodic[3];
+  int n_seg[3];
+  const int* seg_len[3];
+  int p;
+} hdg_mesh_desc;
+
+/* Physics (Sec. 2.1, acoustic scaling): Re_c = Re / Mach, mu = 1.
+ * supg: 1 adds the SUPG term of eq. (C38b).  bc_state_host: global trace
+ * vector (n_glob values, host) holding the Dirichlet state on boundary faces
+ * (read at setup; may be NULL when every axis is periodic). */
+typedef struct {
+  double gamma, Pr, Re, Mach;
+  int supg;
+  const double* bc_state_host;
+} hdg_phys;
+
+typedef struct {
+  size_t n_macros;     /* number of macro-elements                           */
+  size_t n_glob;       /* global trace unknowns (length of uhat)             */
+  size_t n_u_tot;      /* length of u                                        */
+  size_t n_q_tot;      /* length of q                                        */
+  size_t n_u_macro;    /* u unknowns per macro (n_s N)                       */
+  size_t n_b_macro;    /* trace unknowns on one macro's boundary             */
+  size_t workspace_bytes; /* device workspace needed by hdg_bind_workspace   */
+} hdg_sizes;
+
+/* Krylov options (Sec. 4.2): outer right-preconditioned FGMRES(restart) whose
+ * preconditioner is inner_its steps of GMRES left-preconditioned by the
+ * inverse face blocks of A_uhat-uhat.  Convergence: ||b - A x||_2 <=
+ * max(rtol ||b||_2, atol).  inner_prec selects the precision of the condensed
+ * blocks used inside the preconditioner. */
+typedef struct {
+  double rtol, atol;
+  int restart, max_outer, inner_its;
+  hdg_prec inner_prec;
+} hdg_krylov_opts;
+
+typedef struct {
+  int outer_its, inner_its_total;
+  double res0, res_final;
+  double ms;
+} hdg_krylov_stats;
+
+/* Build the mesh topology, the reference tables of every macro shape and the
+ * face tables; queue uploads on `hip_stream` (a hipStream_t, NULL = default).
+ * Returns HDG_EINVAL for an inconsistent description. */
+hdg_status hdg_setup_mesh(const hdg_mesh_desc* mesh, const hdg_phys* phys, void* hip_stream,
+                          hdg_ctx* out);
+
+hdg_status hdg_query_sizes(hdg_ctx ctx, hdg_sizes* out);
+
+/* Node coordinates for building inputs: macro nodes [macro][node][dim] and
+ * trace nodes [face][facenode][dim], host arrays of n_u_tot/(dim+2)*dim and
+ * n_glob/(dim+2)*dim doubles (either may be NULL). */
+hdg_status hdg_node_coords(hdg_ctx ctx, double* macro_xyz_host, double* face_xyz_host);
+
+/* Caller-owned device workspace of at least workspace_bytes (256-byte
+ * aligned).  Must be bound before hdg_linearize_stage. */
+hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes);
+
+/* Linearise eq. (C242) at (q, u, uhat): residuals R_Q, R_U, R_Uhat and the
+ * Jacobian blocks of eq. (C312) of every macro, kept in the workspace.
+ * w: stage history with the discrete time derivative (d_ii u + w) / dt
+ * (w = sum_{j<i} d_ij (u^{n,j} - u^n) - d_ii u^n), layout of u; NULL = 0.
+ * dt = INFINITY: steady (no time term).  dtau: pseudo-time step of the
+ * continuation (adds M / dtau to A_uu); INFINITY = off.
+ * norms_host (may be NULL): ||R_Q||_2, ||R_U||_2, ||R_Uhat||_2 (synchronises). */
+hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, const double* uhat,
+                               const double* w, double dt, double d_ii, double dtau,
+                               double norms_host[3]);
+
+/* Second-layer static condensation (eq. AP12, ASC2a/b): per macro the Schur
+ * complement S = A_uu - A_uq A_qq^{-1} A_qu is LU-factored with partial
+ * pivoting and the condensed blocks A-hat^{T_i} and right-hand sides
+ * b-hat^{T_i} are formed; bhat (device, n_glob) receives the assembled b-hat
+ * of eq. (C44).  Also factors the face blocks of A_uhat-uhat used by the
+ * preconditioner.  prec selects the arithmetic of the factorisation. */
+hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat);
+
+/* y = A-hat x = sum_i P_i^T A-hat^{T_i} P_i x (Algorithm 2 with the condensed
+ * blocks formed by hdg_condense); x, y device, n_glob. */
+hdg_status hdg_apply_global(hdg_ctx ctx, const double* x, double* y);
+
+/* Solve A-hat x = b with the options above (Sec. 4.2).  x: initial guess on
+ * input, solution on output.  Returns HDG_ENOCONV (x = last iterate, stats
+ * filled) when max_outer is reached. */
+hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_krylov_opts* opts,
+                            hdg_krylov_stats* stats_host);
+
+/* Local recovery (eq. Csc4a then Csc4b): dU and dQ of every macro from the
+ * trace increment duhat (device, n_glob).  dq, du device, layouts of q, u. */
+hdg_status hdg_local_backsolve(hdg_ctx ctx, const double* duhat, double* dq, double* du);
+
+/* y += a x on n doubles (device): the Newton update. */
+hdg_status hdg_axpy(hdg_ctx ctx, size_t n, double a, const double* x, double* y);
+
+hdg_status hdg_destroy(hdg_ctx ctx);
+const char* hdg_status_string(hdg_status s);
+const char* hdg_last_error(hdg_ctx ctx);
+
+/* Inspection (tests): copy macro `macro`'s condensed block A-hat^{T_i}
+ * (n_b x n_b row-major) and b-hat^{T_i} (n_b) to host memory (synchronises).
+ * Valid after hdg_condense. */
+hdg_status hdg_get_condensed(hdg_ctx ctx, size_t macro, double* ahat_host, double* bhat_host);
+
+/* Inspection (tests): run only the formation step of hdg_condense and copy
+ * the augmented matrix [[S, -C, f], [D, E, g]] of macro `macro` to host
+ * ((n_u + n_b) x (n_u + n_b + 1) row-major), with C = -A_u,uhat + A_uq
+ * A_qq^{-1} A_q,uhat, f = A_uq A_qq^{-1} R_Q - R_U, D = A_uhat,u - A_uhat,q
+ * A_qq^{-1} A_qu, E = A_uhat,uhat - A_uhat,q A_qq^{-1} A_q,uhat, g = -R_Uhat +
+ * A_uhat,q A_qq^{-1} R_Q (eq. ASC2).  Valid after hdg_linearize_stage. */
+hdg_status hdg_get_formed(hdg_ctx ctx, size_t macro, double* w_host);
+
+/* Inspection (tests): residual vectors of the last linearisation (device
+ * outputs, layouts of q, u, uhat; R_Uhat summed over both sides). */
+hdg_status hdg_get_residuals(hdg_ctx ctx, double* rq, double* ru, double* rb);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,42 @@
+"""Build libhdg.so (HIP, gfx950) in-tree with hipcc."""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libhdg.so")
+SOURCES = ["host_setup.cpp", "capi.cpp", "k_linearize.hip", "k_form.hip", "k_lu.hip", "k_krylov.hip", "k_backsolve.hip"]
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-result", "-Wno-unused-variable"]
+
+
+def build(verbose=True, jobs=8):
+    os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    objs = []
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(HERE, "_build", os.path.splitext(src)[0] + ".o")
+        cmd = ["hipcc", "-c", *FLAGS, "-x", "hip", os.path.join(CSRC, src), "-o", obj]
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        objs.append(obj)
+    ok = True
+    for src, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            ok = False
+            sys.stderr.write(f"--- {src} failed ---\n{out}\n")
+        elif verbose and out.strip():
+            sys.stderr.write(f"--- {src} ---\n{out[-4000:]}\n")
+    if not ok:
+        raise RuntimeError("hipcc failed")
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build())

@@ -1,0 +1,473 @@
+// C ABI of libhdg.so (include/hdg.h): argument checks, workspace binding,
+// call sequencing and the Krylov drivers.
+//
+// Krylov (paper Sec. 4.2): right-preconditioned flexible GMRES(restart) with
+// two classical Gram-Schmidt passes; its preconditioner runs `inner_its`
+// Arnoldi steps of GMRES (zero start) on the system left-preconditioned by
+// the inverse face blocks of A_uh,uh.  The vector work runs in HIP kernels;
+// the (restart+1) x restart Hessenberg matrix, its Givens rotations and the
+// small least-squares solves stay on the host, one synchronisation per
+// Gram-Schmidt pass.
+#include "../../include/hdg.h"
+#include "context.h"
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+hipError_t launch_face_sum(HdgContext& c, const double* base, long long macro_stride, long long elem_stride, double* out);
+hipError_t launch_zero_ints(hipStream_t s, int* p, int n);
+
+namespace {
+
+hdg_status fail(HdgContext* c, hdg_status s, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+hdg_status hip_fail(HdgContext* c, hipError_t e, const char* where) {
+  return fail(c, HDG_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr)                                  \
+  do {                                                   \
+    hipError_t _e = (expr);                              \
+    if (_e != hipSuccess) return hip_fail(c, _e, #expr); \
+  } while (0)
+
+struct Pinned {
+  double* p = nullptr;
+  size_t n = 0;
+};
+
+struct Krylov {
+  HdgContext& c;
+  long long n;
+  double *V, *Z, *Vi, *r, *w, *t, *dev_coef, *partial;
+  int restart, inner;
+  double* host;  // pinned scratch
+  int inner_prec;
+  int inner_total = 0;
+
+  Krylov(HdgContext& cc, int rs, int in, double* hostbuf, int prec) : c(cc), restart(rs), inner(in), host(hostbuf), inner_prec(prec) {
+    n = c.md.n_glob;
+    double* k = c.ws.kry;
+    V = k; k += (size_t)(restart + 1) * n;
+    Z = k; k += (size_t)restart * n;
+    Vi = k; k += (size_t)(inner + 1) * n;
+    r = k; k += n;
+    w = k; k += n;
+    t = k; k += n;
+    dev_coef = c.ws.small + 64;   // up to 512 doubles
+    partial = c.ws.red;
+  }
+
+  hipError_t dots(int k, const double* Vb, const double* x, double* out_dev) {
+    return launch_multidot(c.stream, n, k, Vb, n, x, partial, out_dev);
+  }
+  hipError_t fetch(const double* dev, int k) {
+    hipError_t e = hipMemcpyAsync(host, dev, sizeof(double) * k, hipMemcpyDeviceToHost, c.stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(c.stream);
+  }
+  hipError_t norm(const double* x, double& out) {
+    hipError_t e = dots(1, x, x, dev_coef + 448);
+    if (e != hipSuccess) return e;
+    e = fetch(dev_coef + 448, 1);
+    out = std::sqrt(std::max(0.0, host[0]));
+    return e;
+  }
+  // CGS2 of w against rows 0..j of basis B; h (host, j+1 values) = total coefficients
+  hipError_t cgs2(const double* B, int j, double* w_, double* h) {
+    for (int pass = 0; pass < 2; ++pass) {
+      hipError_t e = dots(j + 1, B, w_, dev_coef);
+      if (e != hipSuccess) return e;
+      e = launch_multiaxpy(c.stream, n, j + 1, B, n, dev_coef, -1.0, w_);
+      if (e != hipSuccess) return e;
+      e = fetch(dev_coef, j + 1);
+      if (e != hipSuccess) return e;
+      for (int i = 0; i <= j; ++i) h[i] = (pass == 0 ? 0.0 : h[i]) + host[i];
+    }
+    return hipSuccess;
+  }
+  hipError_t apply_A(const double* x, double* y, int prec) { return launch_apply(c, x, y, prec); }
+  hipError_t apply_M(const double* x, double* y) { return launch_precond_apply(c, x, y); }
+
+  // z = inner GMRES(inner) on M^{-1} A z = M^{-1} v, zero start
+  hipError_t precond(const double* v, double* z) {
+    if (inner <= 0) return launch_precond_apply(c, v, z);
+    hipError_t e = apply_M(v, Vi);
+    if (e != hipSuccess) return e;
+    double beta;
+    if ((e = norm(Vi, beta)) != hipSuccess) return e;
+    if (beta == 0.0) return launch_scale_copy(c.stream, n, 0.0, v, z);
+    if ((e = launch_scale_copy(c.stream, n, 1.0 / beta, Vi, Vi)) != hipSuccess) return e;
+    std::vector<double> H((size_t)(inner + 1) * inner, 0.0);
+    int k = inner;
+    for (int j = 0; j < inner; ++j) {
+      if ((e = apply_A(Vi + (size_t)j * n, t, inner_prec)) != hipSuccess) return e;
+      if ((e = apply_M(t, Vi + (size_t)(j + 1) * n)) != hipSuccess) return e;
+      double h[64];
+      if ((e = cgs2(Vi, j, Vi + (size_t)(j + 1) * n, h)) != hipSuccess) return e;
+      double hn;
+      if ((e = norm(Vi + (size_t)(j + 1) * n, hn)) != hipSuccess) return e;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * inner + j] = h[i];
+      H[(size_t)(j + 1) * inner + j] = hn;
+      ++inner_total;
+      if (hn == 0.0) { k = j + 1; break; }
+      if ((e = launch_scale_copy(c.stream, n, 1.0 / hn, Vi + (size_t)(j + 1) * n, Vi + (size_t)(j + 1) * n)) != hipSuccess)
+        return e;
+    }
+    // least squares min || beta e1 - H y || by Givens rotations
+    std::vector<double> g(k + 1, 0.0), y(k, 0.0), cs(k), sn(k);
+    g[0] = beta;
+    std::vector<double> R((size_t)(k + 1) * k);
+    for (int i = 0; i <= k; ++i)
+      for (int j = 0; j < k; ++j) R[(size_t)i * k + j] = H[(size_t)i * inner + j];
+    for (int j = 0; j < k; ++j) {
+      for (int i = 0; i < j; ++i) {
+        double a = R[(size_t)i * k + j], b = R[(size_t)(i + 1) * k + j];
+        R[(size_t)i * k + j] = cs[i] * a + sn[i] * b;
+        R[(size_t)(i + 1) * k + j] = -sn[i] * a + cs[i] * b;
+      }
+      double a = R[(size_t)j * k + j], b = R[(size_t)(j + 1) * k + j];
+      double rr = std::hypot(a, b);
+      cs[j] = rr > 0 ? a / rr : 1.0;
+      sn[j] = rr > 0 ? b / rr : 0.0;
+      R[(size_t)j * k + j] = rr;
+      R[(size_t)(j + 1) * k + j] = 0.0;
+      double g0 = g[j];
+      g[j] = cs[j] * g0;
+      g[j + 1] = -sn[j] * g0;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int j = i + 1; j < k; ++j) s -= R[(size_t)i * k + j] * y[j];
+      y[i] = s / R[(size_t)i * k + i];
+    }
+    for (int i = 0; i < k; ++i) host[i] = y[i];
+    if ((e = hipMemcpyAsync(dev_coef + 256, host, sizeof(double) * k, hipMemcpyHostToDevice, c.stream)) != hipSuccess) return e;
+    e = launch_lincomb(c.stream, n, k, Vi, n, dev_coef + 256, z, 0);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(c.stream);  // host buffer reused next
+  }
+};
+
+}  // namespace
+
+struct hdg_ctx_s {
+  HdgContext c;
+  double* pinned = nullptr;
+};
+
+extern "C" {
+
+const char* hdg_status_string(hdg_status s) {
+  switch (s) {
+    case HDG_OK: return "ok";
+    case HDG_EINVAL: return "invalid argument";
+    case HDG_ENOMEM: return "workspace missing or too small";
+    case HDG_EDEVICE: return "HIP runtime error";
+    case HDG_ESINGULAR: return "singular local matrix";
+    case HDG_ENOCONV: return "Krylov solver did not converge";
+    case HDG_EBREAKDOWN: return "Krylov breakdown";
+    case HDG_ENAN: return "non-finite residual";
+    case HDG_EUNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+const char* hdg_last_error(hdg_ctx ctx) { return ctx ? ctx->c.last_error.c_str() : "null context"; }
+
+hdg_status hdg_setup_mesh(const hdg_mesh_desc* mesh, const hdg_phys* phys, void* hip_stream, hdg_ctx* out) {
+  if (!mesh || !phys || !out) return HDG_EINVAL;
+  *out = nullptr;
+  hdg_ctx h = new (std::nothrow) hdg_ctx_s();
+  if (!h) return HDG_ENOMEM;
+  HdgContext& c = h->c;
+  HdgMeshIn in{};
+  in.dim = mesh->dim;
+  in.p = mesh->p;
+  for (int k = 0; k < 3; ++k) {
+    in.n_elem[k] = mesh->n_elem[k]; in.lo[k] = mesh->lo[k]; in.hi[k] = mesh->hi[k];
+    in.periodic[k] = mesh->periodic[k]; in.n_seg[k] = mesh->n_seg[k]; in.seg_len[k] = mesh->seg_len[k];
+  }
+  std::string err;
+  if (!build_mesh(in, c.hm, err)) { delete h; return HDG_EINVAL; }
+  if (phys->supg) { delete h; return HDG_EUNSUPPORTED; }
+  if (!(phys->gamma > 1.0) || !(phys->Pr > 0) || !(phys->Re > 0) || !(phys->Mach > 0)) { delete h; return HDG_EINVAL; }
+  bool any_bnd = false;
+  for (int v : c.hm.macro_bnd) any_bnd |= (v != 0);
+  if (any_bnd && !phys->bc_state_host) { delete h; return HDG_EINVAL; }
+  if (mesh->dim == 3 && mesh->p == 3) { delete h; return HDG_EUNSUPPORTED; }
+  c.stream = static_cast<hipStream_t>(hip_stream);
+  build_class(c.hm, c.hc);
+  c.ph.gamma = phys->gamma; c.ph.Pr = phys->Pr; c.ph.Re = phys->Re; c.ph.Mach = phys->Mach; c.ph.mu = 1.0;
+  c.ph.Re_c = phys->Re / phys->Mach;
+  c.ph.kappa = c.ph.mu / (c.ph.Re_c * c.ph.Pr * (c.ph.gamma - 1.0));
+  c.ph.supg = phys->supg;
+  try {
+    upload_tables(c);
+    if (any_bnd) {
+      std::vector<double> bc(phys->bc_state_host, phys->bc_state_host + c.hm.n_glob);
+      void* p = nullptr;
+      if (hipMalloc(&p, bc.size() * sizeof(double)) != hipSuccess) throw std::runtime_error("hipMalloc bc");
+      c.dev_allocs.push_back(p);
+      if (hipMemcpy(p, bc.data(), bc.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        throw std::runtime_error("bc upload");
+      c.md.bc_state = static_cast<const double*>(p);
+    } else {
+      c.md.bc_state = nullptr;
+    }
+  } catch (const std::exception& ex) {
+    for (void* p : c.dev_allocs) (void)hipFree(p);
+    delete h;
+    return HDG_EDEVICE;
+  }
+  plan_workspace(c);
+  if (hipHostMalloc((void**)&h->pinned, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    for (void* p : c.dev_allocs) (void)hipFree(p);
+    delete h;
+    return HDG_EDEVICE;
+  }
+  *out = h;
+  return HDG_OK;
+}
+
+hdg_status hdg_query_sizes(hdg_ctx ctx, hdg_sizes* out) {
+  if (!ctx || !out) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  out->n_macros = c.hm.n_macros;
+  out->n_glob = c.hm.n_glob;
+  out->n_u_tot = c.n_u_tot;
+  out->n_q_tot = c.n_q_tot;
+  out->n_u_macro = c.hc.n_u;
+  out->n_b_macro = c.hc.n_b;
+  out->workspace_bytes = c.need_bytes;
+  return HDG_OK;
+}
+
+hdg_status hdg_node_coords(hdg_ctx ctx, double* macro_xyz, double* face_xyz) {
+  if (!ctx) return HDG_EINVAL;
+  node_coords(ctx->c, macro_xyz, face_xyz);
+  return HDG_OK;
+}
+
+hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx || !dev_ptr) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (bytes < c.need_bytes) return fail(&c, HDG_ENOMEM, "workspace smaller than hdg_query_sizes().workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % 256) return fail(&c, HDG_EINVAL, "workspace must be 256-byte aligned");
+  char* base = static_cast<char*>(dev_ptr);
+  if (c.ws_bound) {
+    // re-binding: offsets are relative to the previous base
+    const char* old = c.ws.base;
+    auto rebase = [&](auto*& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(base + (reinterpret_cast<const char*>(p) - old)); };
+    rebase(c.ws.Kq); rebase(c.ws.AUU); rebase(c.ws.AUQ); rebase(c.ws.RUe); rebase(c.ws.RQe); rebase(c.ws.SUB);
+    rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.Wm);
+    rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.ypart); rebase(c.ws.kry);
+    rebase(c.ws.red); rebase(c.ws.small);
+  } else {
+    auto rebase = [&](auto*& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(base + reinterpret_cast<uintptr_t>(p)); };
+    rebase(c.ws.Kq); rebase(c.ws.AUU); rebase(c.ws.AUQ); rebase(c.ws.RUe); rebase(c.ws.RQe); rebase(c.ws.SUB);
+    rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.Wm);
+    rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.ypart); rebase(c.ws.kry);
+    rebase(c.ws.red); rebase(c.ws.small);
+  }
+  c.ws.base = base;
+  c.ws.bytes = bytes;
+  c.ws_bound = true;
+  c.have_a32 = false;
+  return HDG_OK;
+}
+
+hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, const double* uhat, const double* w,
+                               double dt, double d_ii, double dtau, double norms_host[3]) {
+  if (!ctx || !q || !u || !uhat) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  if (!(dt > 0) || !(dtau > 0) || std::isnan(d_ii)) return fail(&c, HDG_EINVAL, "dt and dtau must be positive");
+  StageArgs sa{dt, d_ii, dtau};
+  HIPCHK(&c, launch_linearize(c, q, u, uhat, w, sa));
+  c.have_a32 = false;
+  if (norms_host) {
+    HIPCHK(&c, launch_norms(c, c.ws.small + 8));
+    HIPCHK(&c, hipMemcpyAsync(ctx->pinned, c.ws.small + 8, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(&c, hipStreamSynchronize(c.stream));
+    for (int i = 0; i < 3; ++i) norms_host[i] = ctx->pinned[i];
+    if (!std::isfinite(norms_host[0] + norms_host[1] + norms_host[2])) return fail(&c, HDG_ENAN, "non-finite residual");
+  }
+  return HDG_OK;
+}
+
+hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
+  if (!ctx || !bhat) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  if (prec != HDG_FP64) return fail(&c, HDG_EUNSUPPORTED, "only FP64 condensation is built");
+  int* status = reinterpret_cast<int*>(c.ws.small);
+  HIPCHK(&c, launch_zero_ints(c.stream, status, 2));
+  HIPCHK(&c, launch_form(c));
+  HIPCHK(&c, launch_lu(c));
+  HIPCHK(&c, launch_bhat(c, bhat));
+  HIPCHK(&c, launch_face_precond(c));
+  c.have_a32 = false;
+  int st[2] = {0, 0};
+  HIPCHK(&c, hipMemcpyAsync(ctx->pinned, status, sizeof(int) * 2, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  std::memcpy(st, ctx->pinned, sizeof(st));
+  if (st[0]) return fail(&c, HDG_ESINGULAR, "singular Schur complement in macro " + std::to_string(st[0] - 1));
+  if (st[1]) return fail(&c, HDG_ESINGULAR, "singular face block of A_uhat-uhat " + std::to_string(st[1] - 1));
+  return HDG_OK;
+}
+
+hdg_status hdg_apply_global(hdg_ctx ctx, const double* x, double* y) {
+  if (!ctx || !x || !y || x == y) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  HIPCHK(&c, launch_apply(c, x, y, 0));
+  return HDG_OK;
+}
+
+hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_krylov_opts* o, hdg_krylov_stats* st) {
+  if (!ctx || !b || !x || !o) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  if (o->restart < 1 || o->restart > c.kry_restart_max || o->inner_its < 0 || o->inner_its > c.kry_inner_max ||
+      o->max_outer < 1 || !(o->rtol >= 0) || !(o->atol >= 0))
+    return fail(&c, HDG_EINVAL, "bad Krylov options");
+  auto t0 = std::chrono::steady_clock::now();
+  if (o->inner_prec == HDG_FP32 && !c.have_a32) {
+    HIPCHK(&c, launch_cast_ahat(c));
+    c.have_a32 = true;
+  }
+  Krylov K(c, o->restart, o->inner_its, ctx->pinned, o->inner_prec == HDG_FP32 ? 1 : 0);
+  const long long n = K.n;
+  double bnorm, beta;
+  HIPCHK(&c, K.norm(b, bnorm));
+  const double tol = std::max(o->rtol * bnorm, o->atol);
+  HIPCHK(&c, K.apply_A(x, K.t, 0));
+  HIPCHK(&c, launch_sub(c.stream, n, b, K.t, K.r));
+  HIPCHK(&c, K.norm(K.r, beta));
+  int its = 0;
+  const int m = o->restart;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  while (beta > tol && its < o->max_outer) {
+    HIPCHK(&c, launch_scale_copy(c.stream, n, 1.0 / beta, K.r, K.V));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      HIPCHK(&c, K.precond(K.V + (size_t)j * n, K.Z + (size_t)j * n));
+      double* wv = K.V + (size_t)(j + 1) * n;
+      HIPCHK(&c, K.apply_A(K.Z + (size_t)j * n, wv, 0));
+      double h[128];
+      HIPCHK(&c, K.cgs2(K.V, j, wv, h));
+      double hn;
+      HIPCHK(&c, K.norm(wv, hn));
+      for (int i = 0; i < j; ++i) {
+        double a = h[i], bb = h[i + 1];
+        h[i] = cs[i] * a + sn[i] * bb;
+        h[i + 1] = -sn[i] * a + cs[i] * bb;
+      }
+      double rr = std::hypot(h[j], hn);
+      cs[j] = rr > 0 ? h[j] / rr : 1.0;
+      sn[j] = rr > 0 ? hn / rr : 0.0;
+      h[j] = rr;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
+      double g0 = g[j];
+      g[j] = cs[j] * g0;
+      g[j + 1] = -sn[j] * g0;
+      ++its;
+      k = j + 1;
+      if (hn == 0.0 || std::fabs(g[j + 1]) <= tol || its >= o->max_outer) break;
+      HIPCHK(&c, launch_scale_copy(c.stream, n, 1.0 / hn, wv, wv));
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int j = i + 1; j < k; ++j) s -= H[(size_t)i * m + j] * y[j];
+      y[i] = s / H[(size_t)i * m + i];
+    }
+    for (int i = 0; i < k; ++i) ctx->pinned[i] = y[i];
+    HIPCHK(&c, hipMemcpyAsync(K.dev_coef + 256, ctx->pinned, sizeof(double) * k, hipMemcpyHostToDevice, c.stream));
+    HIPCHK(&c, launch_lincomb(c.stream, n, k, K.Z, n, K.dev_coef + 256, x, 1));
+    HIPCHK(&c, K.apply_A(x, K.t, 0));
+    HIPCHK(&c, launch_sub(c.stream, n, b, K.t, K.r));
+    HIPCHK(&c, K.norm(K.r, beta));
+    if (!std::isfinite(beta)) return fail(&c, HDG_ENAN, "non-finite Krylov residual");
+  }
+  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  if (st) {
+    st->outer_its = its;
+    st->inner_its_total = K.inner_total;
+    st->res0 = bnorm;
+    st->res_final = beta;
+    st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (beta > tol) return fail(&c, HDG_ENOCONV, "FGMRES reached max_outer");
+  return HDG_OK;
+}
+
+hdg_status hdg_local_backsolve(hdg_ctx ctx, const double* duhat, double* dq, double* du) {
+  if (!ctx || !duhat || !dq || !du) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  HIPCHK(&c, launch_backsolve(c, duhat, dq, du));
+  return HDG_OK;
+}
+
+hdg_status hdg_axpy(hdg_ctx ctx, size_t n, double a, const double* x, double* y) {
+  if (!ctx || !x || !y) return HDG_EINVAL;
+  HIPCHK(&ctx->c, launch_axpy(ctx->c.stream, n, a, x, y));
+  return HDG_OK;
+}
+
+hdg_status hdg_destroy(hdg_ctx ctx) {
+  if (!ctx) return HDG_EINVAL;
+  (void)hipStreamSynchronize(ctx->c.stream);
+  for (void* p : ctx->c.dev_allocs) (void)hipFree(p);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  return HDG_OK;
+}
+
+hdg_status hdg_get_condensed(hdg_ctx ctx, size_t macro, double* ahat_host, double* bhat_host) {
+  if (!ctx) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound || macro >= (size_t)c.hm.n_macros) return HDG_EINVAL;
+  const int nb = c.hc.n_b, nu = c.hc.n_u;
+  const double* Wm = c.ws.Wm + macro * (size_t)c.n_rows * c.ldw;
+  if (ahat_host)
+    HIPCHK(&c, hipMemcpy2DAsync(ahat_host, nb * sizeof(double), Wm + (size_t)nu * c.ldw + nu, c.ldw * sizeof(double),
+                                nb * sizeof(double), nb, hipMemcpyDeviceToHost, c.stream));
+  if (bhat_host)
+    HIPCHK(&c, hipMemcpy2DAsync(bhat_host, sizeof(double), Wm + (size_t)nu * c.ldw + c.n_cols - 1, c.ldw * sizeof(double),
+                                sizeof(double), nb, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  return HDG_OK;
+}
+
+hdg_status hdg_get_formed(hdg_ctx ctx, size_t macro, double* w_host) {
+  if (!ctx || !w_host) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound || macro >= (size_t)c.hm.n_macros) return HDG_EINVAL;
+  HIPCHK(&c, launch_form(c));
+  const double* Wm = c.ws.Wm + macro * (size_t)c.n_rows * c.ldw;
+  HIPCHK(&c, hipMemcpy2DAsync(w_host, c.n_cols * sizeof(double), Wm, c.ldw * sizeof(double), c.n_cols * sizeof(double),
+                              c.n_rows, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  return HDG_OK;
+}
+
+hdg_status hdg_get_residuals(hdg_ctx ctx, double* rq, double* ru, double* rb) {
+  if (!ctx) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return HDG_EINVAL;
+  if (rq) HIPCHK(&c, hipMemcpyAsync(rq, c.ws.RQ, sizeof(double) * c.n_q_tot, hipMemcpyDeviceToDevice, c.stream));
+  if (ru) HIPCHK(&c, hipMemcpyAsync(ru, c.ws.RU, sizeof(double) * c.n_u_tot, hipMemcpyDeviceToDevice, c.stream));
+  if (rb) HIPCHK(&c, hipMemcpyAsync(rb, c.ws.RBglob, sizeof(double) * c.md.n_glob, hipMemcpyDeviceToDevice, c.stream));
+  return HDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Host-side context of libhdg.so: mesh topology, reference tables of the
+// macro shape, workspace layout.  Internal.
+#pragma once
+#include "internal.h"
+#include <array>
+#include <map>
+#include <memory>
+
+struct HostClass {
+  int dim, p, nq, ns;
+  int m[3], n1[3];
+  int N, E, A, Q, T, Fq, n_u, n_q, n_b, n_sub, nmax1;
+  double h[3];
+  int nf_nodes[HDG_MAXF], nf_off[HDG_MAXF];
+  std::vector<double> Phi, dPhi, W, Tvol, Mel, Psi, WF, C1D, Minv1D, M1D;
+  std::vector<int> fnode, finv, elem_nodes, elem_sub, sub_elem, sub_lf, sub_tid, node_ne, node_e, node_a,
+      tn_cnt, tn_sub, tn_t, tn_base;
+};
+
+struct HostMesh {
+  int dim, ns, p;
+  int n_elem[3], n_seg[3], periodic[3];
+  double lo[3], hi[3], h[3];
+  std::vector<int> seg_len[3], seg_start[3];
+  int n_macros, n_faces;
+  long long n_glob;
+  std::vector<int> macro_face, macro_bnd, face_axis, face_minus, face_plus, face_ndof, face_nodes;
+  std::vector<long long> face_off;
+  std::vector<int> face_tn[HDG_MAXF];  // unused placeholder
+  std::vector<std::array<int, 3>> face_grid;
+};
+
+struct Workspace {
+  char* base = nullptr;
+  size_t bytes = 0;
+  double* Kq = nullptr;     // pointwise flux-Jacobian scratch, [elements][Kstride]
+  double* AUU = nullptr;    // [elements][nsA][nsA]
+  double* AUQ = nullptr;    // [elements][nsA][d nsA]
+  double* RUe = nullptr;    // [elements][nsA]
+  double* RQe = nullptr;    // [elements][d nsA]
+  double* SUB = nullptr;    // [macros * n_sub][sub_stride]
+  double* RU = nullptr;     // [n_u_tot]
+  double* RQ = nullptr;     // [n_q_tot]
+  double* RQt = nullptr;    // [n_q_tot]  M^{-1} R_Q per direction and component
+  double* RBloc = nullptr;  // [macros][n_b] per-macro trace residual
+  double* RBglob = nullptr; // [n_glob]
+  double* Wm = nullptr;     // [macros][n_rows][ldw] augmented matrices
+  int* ipiv = nullptr;      // [macros][n_u]
+  double* FW = nullptr;     // [faces][2 nf][ldf] face preconditioner
+  int* fpiv = nullptr;      // [faces][nf]
+  float* A32 = nullptr;     // [macros][n_b][n_b] FP32 copy of A-hat (inner operator)
+  double* ypart = nullptr;  // [macros][n_b]
+  double* kry = nullptr;    // Krylov vectors
+  double* red = nullptr;    // reduction scratch
+  double* small = nullptr;  // small device scalars
+};
+
+struct HdgContext {
+  HostMesh hm;
+  HostClass hc;
+  ClassDev cd{};
+  PhysDev ph{};
+  MeshDev md{};
+  hipStream_t stream = nullptr;
+  std::vector<void*> dev_allocs;  // small tables owned by the context
+  Workspace ws;
+  bool ws_bound = false;
+  // sizes
+  long long n_u_tot = 0, n_q_tot = 0;
+  int n_rows = 0, n_cols = 0, ldw = 0;  // augmented matrix
+  int nsA = 0, dnsA = 0, sub_stride = 0, Kstride = 0;
+  int nf_max = 0, ldf = 0;
+  int kry_restart_max = 64, kry_inner_max = 16;
+  size_t need_bytes = 0;
+  // offsets of the sub-face block pieces
+  int off_AUB = 0, off_ABU = 0, off_ABQ = 0, off_ABB = 0, off_RB = 0;
+  bool have_a32 = false;
+  int last_prec = 0;
+  std::string last_error;
+};
+
+struct HdgMeshIn {
+  int dim;
+  int n_elem[3];
+  double lo[3], hi[3];
+  int periodic[3];
+  int n_seg[3];
+  const int* seg_len[3];
+  int p;
+};
+
+// host_setup.cpp
+bool build_mesh(const HdgMeshIn& in, HostMesh& hm, std::string& err);
+void build_class(const HostMesh& hm, HostClass& hc);
+void plan_workspace(HdgContext& c);
+void upload_tables(HdgContext& c);
+void node_coords(const HdgContext& c, double* macro_xyz, double* face_xyz);
+

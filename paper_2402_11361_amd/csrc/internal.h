@@ -1,0 +1,104 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// libhdg.so.  Nothing here is part of the public ABI (include/hdg.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#define HDG_MAXD 3
+#define HDG_MAXF 6
+
+// Reference tables of one macro shape (m per axis, degree p, element sizes h),
+// all device pointers.  Element-local node index a = a_0 + (p+1)(a_1 + (p+1)a_2);
+// quadrature index q likewise with nq = p + 2 Gauss points per direction.
+struct ClassDev {
+  int dim, p, nq, ns;
+  int m[3], n1[3];
+  int N, E, A, Q, T, Fq;
+  int n_u, n_q, n_b;
+  int nf_nodes[HDG_MAXF];  // trace nodes per local macro face
+  int nf_off[HDG_MAXF];    // dof offset of each local face in the macro trace vector
+  int n_sub;               // sub-faces (element faces on the macro boundary)
+  int nmax1;               // max n1
+  double h[3];
+  // element tables
+  const double* Phi;   // [Q][A]
+  const double* dPhi;  // [dim][Q][A] physical derivatives
+  const double* W;     // [Q] weights times Jacobian
+  const double* Tvol;  // [dim*Q][A*A]: -dPhi_k[q][a] * Phi[q][b]
+  const double* Mel;   // [A][A] element mass matrix
+  // face tables per local face lf (normal axis lf/2, side lf%2)
+  const double* Psi;   // [2d][Fq][T] trace basis at face quadrature points
+  const double* WF;    // [2d][Fq]
+  const int* fnode;    // [2d][T] element-local node of face node t
+  const int* finv;     // [2d][A] face node index t of element node a on local face lf, or -1
+  // topology
+  const int* elem_nodes;  // [E][A] macro node ids
+  const int* elem_sub;    // [E][2d] sub-face id or -1
+  const int* sub_elem;    // [n_sub]
+  const int* sub_lf;      // [n_sub]
+  const int* sub_tid;     // [n_sub][T] trace node ids on the macro face
+  const int* node_ne;     // [N] number of elements containing the node
+  const int* node_e;      // [N][8]
+  const int* node_a;      // [N][8]
+  const int* tn_cnt;      // [sum nf] sub-faces containing a trace node (per local face, concatenated)
+  const int* tn_sub;      // [sum nf][4]
+  const int* tn_t;        // [sum nf][4]
+  const int* tn_base;     // [2d] offset of each local face in the tn_ arrays
+  // 1D macro operators per axis (physical): C1D_k = M_k^{-1} B_k, Minv1D_k = M_k^{-1}
+  const double* C1D;      // [dim][nmax1][nmax1]
+  const double* Minv1D;   // [dim][nmax1][nmax1]
+  const double* M1D;      // [dim][nmax1][nmax1]
+};
+
+struct PhysDev {
+  double gamma, Pr, Re, Mach, mu, Re_c, kappa;  // kappa = mu / (Re_c Pr (gamma-1))
+  int supg;
+};
+
+// Per-Newton-step scalars of the linearisation.
+struct StageArgs {
+  double dt, dii, dtau;   // dt = inf: steady; dtau = inf: no continuation
+};
+
+// Device view of the mesh and workspace used by the kernels.
+struct MeshDev {
+  int dim, ns, n_macros, n_faces;
+  long long n_glob;
+  const int* macro_face;   // [n_macros][2d] global face id
+  const int* macro_bnd;    // [n_macros][2d] 1 = Dirichlet face
+  const long long* face_off;   // [n_faces] offset in the trace vector
+  const int* face_ndof;        // [n_faces]
+  const int* face_minus;       // [n_faces] macro on the low side or -1
+  const int* face_plus;        // [n_faces] macro on the high side or -1
+  const double* bc_state;      // [n_glob] Dirichlet data (or null)
+};
+
+// ---- kernel launchers (defined in the .hip files) ----------------------
+struct Workspace;
+struct HdgContext;
+
+hipError_t launch_linearize(HdgContext& c, const double* q, const double* u, const double* uhat,
+                            const double* w, StageArgs sa);
+hipError_t launch_form(HdgContext& c);
+hipError_t launch_lu(HdgContext& c);
+hipError_t launch_bhat(HdgContext& c, double* bhat);
+hipError_t launch_face_precond(HdgContext& c);
+hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec);
+hipError_t launch_precond_apply(HdgContext& c, const double* x, double* y);
+hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, double* du);
+hipError_t launch_axpy(hipStream_t s, size_t n, double a, const double* x, double* y);
+hipError_t launch_norms(HdgContext& c, double* out3_dev);
+hipError_t launch_cast_ahat(HdgContext& c);
+
+// vector kernels for the Krylov solver
+hipError_t launch_multidot(hipStream_t s, long long n, int k, const double* V, long long ldv,
+                           const double* w, double* partial, double* out);
+hipError_t launch_multiaxpy(hipStream_t s, long long n, int k, const double* V, long long ldv,
+                            const double* coef, double sign, double* w);
+hipError_t launch_scale_copy(hipStream_t s, long long n, double a, const double* x, double* y);
+hipError_t launch_lincomb(hipStream_t s, long long n, int k, const double* V, long long ldv,
+                          const double* coef_dev, double* y, int accumulate);
+hipError_t launch_sub(hipStream_t s, long long n, const double* a, const double* b, double* y);

@@ -1,0 +1,343 @@
+// Global trace operator and preconditioner (paper Algorithm 2, Sec. 4.2) and
+// the vector kernels of the Krylov solvers.
+//
+// y = A-hat x = sum_i P_i^T A-hat^{T_i} P_i x is applied in two passes: per
+// macro a gather of its 2d face segments of x into LDS and a GEMV with the
+// condensed block (rows streamed from HBM, one row per wave-iteration, four
+// rows in flight), then a deterministic two-sided face sum.  The
+// preconditioner applies the inverse face blocks of A_uh,uh (one dense
+// n_f x n_f GEMV per face).
+#include "context.h"
+#include <algorithm>
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// macro-local trace index -> local face
+__device__ __forceinline__ int local_face(const ClassDev& cd, int r) {
+  int lf = 0;
+  while (lf + 1 < 2 * cd.dim && r >= cd.nf_off[lf + 1]) ++lf;
+  return lf;
+}
+
+// out[g] = sum over the (one or two) sides of face F(g) of src(side macro, local index)
+__global__ void k_face_gather_sum(ClassDev cd, MeshDev md, const double* __restrict__ base, long long macro_stride,
+                                  long long elem_stride, double* __restrict__ out) {
+  const int d = cd.dim;
+  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < md.n_glob; g += (long long)gridDim.x * blockDim.x) {
+    int lo = 0, hi = md.n_faces - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) / 2;
+      if (md.face_off[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    const int F = lo;
+    const int r = (int)(g - md.face_off[F]);
+    const int mm = md.face_minus[F], mp = md.face_plus[F];
+    int k = 0;
+    const int m0 = mm >= 0 ? mm : mp;
+    for (int lf = 0; lf < 2 * d; ++lf)
+      if (md.macro_face[(size_t)m0 * 2 * d + lf] == F) { k = lf / 2; break; }
+    double s = 0.0;
+    if (mm >= 0) s += base[(size_t)mm * macro_stride + (size_t)(cd.nf_off[2 * k + 1] + r) * elem_stride];
+    if (mp >= 0) s += base[(size_t)mp * macro_stride + (size_t)(cd.nf_off[2 * k] + r) * elem_stride];
+    out[g] = s;
+  }
+}
+
+constexpr int APPLY_ROWS = 64;
+
+template <class TA>
+__global__ void __launch_bounds__(256) k_apply_local(ClassDev cd, MeshDev md, const TA* __restrict__ Ab,
+                                                     long long macro_stride, long long ld, const double* __restrict__ x,
+                                                     double* __restrict__ ypart) {
+  extern __shared__ double xs[];
+  const int macro = blockIdx.y;
+  const int nb = cd.n_b;
+  const int d = cd.dim;
+  for (int s = threadIdx.x; s < nb; s += blockDim.x) {
+    const int lf = local_face(cd, s);
+    const int F = md.macro_face[(size_t)macro * 2 * d + lf];
+    xs[s] = x[md.face_off[F] + (s - cd.nf_off[lf])];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * APPLY_ROWS + wave * (APPLY_ROWS / 4);
+  const TA* Am = Ab + (size_t)macro * macro_stride;
+  for (int rr = 0; rr < APPLY_ROWS / 4; rr += 4) {
+    const int r = r0 + rr;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const TA* p0 = Am + (size_t)min(r + 0, nb - 1) * ld;
+    const TA* p1 = Am + (size_t)min(r + 1, nb - 1) * ld;
+    const TA* p2 = Am + (size_t)min(r + 2, nb - 1) * ld;
+    const TA* p3 = Am + (size_t)min(r + 3, nb - 1) * ld;
+    for (int s = lane; s < nb; s += 64) {
+      const double xv = xs[s];
+      a0 += (double)p0[s] * xv;
+      a1 += (double)p1[s] * xv;
+      a2 += (double)p2[s] * xv;
+      a3 += (double)p3[s] * xv;
+    }
+    a0 = wave_sum(a0); a1 = wave_sum(a1); a2 = wave_sum(a2); a3 = wave_sum(a3);
+    if (lane == 0) {
+      double* yp = ypart + (size_t)macro * nb;
+      if (r + 0 < nb) yp[r + 0] = a0;
+      if (r + 1 < nb) yp[r + 1] = a1;
+      if (r + 2 < nb) yp[r + 2] = a2;
+      if (r + 3 < nb) yp[r + 3] = a3;
+    }
+  }
+}
+
+// FW[F] = [[A_F, -I], [I, 0]] with A_F the face block of A_uh,uh summed over
+// both macro sides (sub-face blocks scattered to face trace nodes).
+__global__ void k_face_build(ClassDev cd, MeshDev md, const double* __restrict__ SUB, int sub_stride, int off_ABB,
+                             double* __restrict__ FW, long long face_stride, int ldf) {
+  const int F = blockIdx.x;
+  const int nf = md.face_ndof[F];
+  const int nn = nf / cd.ns;
+  const int T = cd.T, ns = cd.ns, nst = ns * T;
+  double* M = FW + (size_t)F * face_stride;
+  for (int i = threadIdx.x; i < 2 * nf * ldf; i += blockDim.x) {
+    const int r = i / ldf, c = i % ldf;
+    double v = 0.0;
+    if (r < nf && c == nf + r) v = -1.0;
+    if (r >= nf && c == r - nf) v = 1.0;
+    M[i] = v;
+  }
+  __syncthreads();
+  const int d = cd.dim;
+  for (int side = 0; side < 2; ++side) {
+    const int macro = side == 0 ? md.face_minus[F] : md.face_plus[F];
+    if (macro < 0) continue;
+    int lf = -1;
+    for (int l = 0; l < 2 * d; ++l)
+      if (md.macro_face[(size_t)macro * 2 * d + l] == F && (l % 2) == (side == 0 ? 1 : 0)) { lf = l; break; }
+    if (lf < 0) continue;
+    for (int sid = 0; sid < cd.n_sub; ++sid) {
+      if (cd.sub_lf[sid] != lf) continue;
+      const double* abb = SUB + ((size_t)macro * cd.n_sub + sid) * sub_stride + off_ABB;
+      const int* tid = cd.sub_tid + (size_t)sid * T;
+      __syncthreads();
+      for (int i = threadIdx.x; i < nst * nst; i += blockDim.x) {
+        const int rr = i / nst, cc = i % nst;
+        const int c = rr / T, t = rr % T, cp = cc / T, tp = cc % T;
+        M[(size_t)(c * nn + tid[t]) * ldf + cp * nn + tid[tp]] += abb[i];
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_precond_apply(MeshDev md, const double* __restrict__ FW, long long face_stride,
+                                                       int ldf, const double* __restrict__ x, double* __restrict__ y) {
+  extern __shared__ double xs[];
+  const int F = blockIdx.x;
+  const int nf = md.face_ndof[F];
+  const long long off = md.face_off[F];
+  for (int i = threadIdx.x; i < nf; i += blockDim.x) xs[i] = x[off + i];
+  __syncthreads();
+  const double* Ai = FW + (size_t)F * face_stride + (size_t)nf * ldf + nf;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = wave; r < nf; r += 4) {
+    double s = 0.0;
+    for (int c = lane; c < nf; c += 64) s += Ai[(size_t)r * ldf + c] * xs[c];
+    s = wave_sum(s);
+    if (lane == 0) y[off + r] = s;
+  }
+}
+
+// A32[macro][r][c] = (float) A-hat^{T_i}[r][c]
+__global__ void k_cast_ahat(const double* __restrict__ W, long long macro_stride, long long ld, long long offs, int nb,
+                            float* __restrict__ out, long long total) {
+  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total; g += (long long)gridDim.x * blockDim.x) {
+    const long long macro = g / ((long long)nb * nb);
+    const long long rc = g % ((long long)nb * nb);
+    const int r = (int)(rc / nb), c = (int)(rc % nb);
+    out[g] = (float)W[macro * macro_stride + offs + (size_t)r * ld + c];
+  }
+}
+
+// ---- vector kernels -------------------------------------------------------
+constexpr int VEC_BLOCKS = 512;
+
+__global__ void k_multidot_partial(long long n, int k, const double* __restrict__ V, long long ldv,
+                                   const double* __restrict__ w, double* __restrict__ partial) {
+  __shared__ double sh[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = 0; j < k; ++j) {
+    double s = 0.0;
+    const double* v = V + (size_t)j * ldv;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+      s += v[i] * w[i];
+    s = wave_sum(s);
+    if (lane == 0) sh[wave][0] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * k + j] = sh[0][0] + sh[1][0] + sh[2][0] + sh[3][0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_multidot_final(int nblk, int k, const double* __restrict__ partial, double* __restrict__ out) {
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) s += partial[(size_t)b * k + j];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+__global__ void k_multiaxpy(long long n, int k, const double* __restrict__ V, long long ldv,
+                            const double* __restrict__ coef, double sign, double* __restrict__ w) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += coef[j] * V[(size_t)j * ldv + i];
+    w[i] += sign * s;
+  }
+}
+
+__global__ void k_lincomb(long long n, int k, const double* __restrict__ V, long long ldv, const double* __restrict__ coef,
+                          double* __restrict__ y, int accumulate) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double s = accumulate ? y[i] : 0.0;
+    for (int j = 0; j < k; ++j) s += coef[j] * V[(size_t)j * ldv + i];
+    y[i] = s;
+  }
+}
+
+__global__ void k_scale_copy(long long n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+
+__global__ void k_sub(long long n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = a[i] - b[i];
+}
+
+__global__ void k_axpy(long long n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+
+__global__ void k_zero_ints(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+inline unsigned grid_for(long long n) { return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4096)); }
+
+}  // namespace
+
+hipError_t launch_face_sum(HdgContext& c, const double* base, long long macro_stride, long long elem_stride, double* out) {
+  hipLaunchKernelGGL(k_face_gather_sum, dim3(grid_for(c.md.n_glob)), dim3(256), 0, c.stream, c.cd, c.md, base,
+                     macro_stride, elem_stride, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_ints(hipStream_t s, int* p, int n) {
+  hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_bhat(HdgContext& c, double* bhat) {
+  const double* base = c.ws.Wm + (size_t)c.hc.n_u * c.ldw + (c.n_cols - 1);
+  return launch_face_sum(c, base, (long long)c.n_rows * c.ldw, c.ldw, bhat);
+}
+
+hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec) {
+  const int nb = c.hc.n_b;
+  dim3 grid((nb + APPLY_ROWS - 1) / APPLY_ROWS, c.hm.n_macros);
+  const size_t shm = (size_t)nb * sizeof(double);
+  if (prec == 1 && c.have_a32) {
+    hipLaunchKernelGGL(k_apply_local<float>, grid, dim3(256), shm, c.stream, c.cd, c.md, c.ws.A32,
+                       (long long)nb * nb, (long long)nb, x, c.ws.ypart);
+  } else {
+    const double* Ab = c.ws.Wm + (size_t)c.hc.n_u * c.ldw + c.hc.n_u;
+    hipLaunchKernelGGL(k_apply_local<double>, grid, dim3(256), shm, c.stream, c.cd, c.md, Ab,
+                       (long long)c.n_rows * c.ldw, (long long)c.ldw, x, c.ws.ypart);
+  }
+  return launch_face_sum(c, c.ws.ypart, nb, 1, y);
+}
+
+hipError_t lu_eliminate(hipStream_t s, double* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
+                        int n_cols, int* ipiv, int ipiv_stride, int* status);
+
+hipError_t launch_face_precond(HdgContext& c) {
+  const long long fs = (long long)2 * c.nf_max * c.ldf;
+  hipLaunchKernelGGL(k_face_build, dim3(c.hm.n_faces), dim3(256), 0, c.stream, c.cd, c.md, c.ws.SUB, c.sub_stride,
+                     c.off_ABB, c.ws.FW, fs, c.ldf);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // uniform face sizes per mesh axis; faces of one size are eliminated together
+  // (all faces have nf = face_ndof; mixed sizes are handled per distinct size)
+  std::vector<int> sizes;
+  for (int f = 0; f < c.hm.n_faces; ++f)
+    if (std::find(sizes.begin(), sizes.end(), c.hm.face_ndof[f]) == sizes.end()) sizes.push_back(c.hm.face_ndof[f]);
+  if (sizes.size() == 1) {
+    const int nf = sizes[0];
+    return lu_eliminate(c.stream, c.ws.FW, c.hm.n_faces, fs, c.ldf, nf, 2 * nf, 2 * nf, c.ws.fpiv, c.nf_max,
+                        reinterpret_cast<int*>(c.ws.small) + 1);
+  }
+  // several face sizes: runs of consecutive faces with the same size
+  int f0 = 0;
+  while (f0 < c.hm.n_faces) {
+    int f1 = f0;
+    while (f1 < c.hm.n_faces && c.hm.face_ndof[f1] == c.hm.face_ndof[f0]) ++f1;
+    const int nf = c.hm.face_ndof[f0];
+    e = lu_eliminate(c.stream, c.ws.FW + (size_t)f0 * fs, f1 - f0, fs, c.ldf, nf, 2 * nf, 2 * nf,
+                     c.ws.fpiv + (size_t)f0 * c.nf_max, c.nf_max, reinterpret_cast<int*>(c.ws.small) + 1);
+    if (e != hipSuccess) return e;
+    f0 = f1;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_precond_apply(HdgContext& c, const double* x, double* y) {
+  const long long fs = (long long)2 * c.nf_max * c.ldf;
+  hipLaunchKernelGGL(k_precond_apply, dim3(c.hm.n_faces), dim3(256), (size_t)c.nf_max * sizeof(double), c.stream, c.md,
+                     c.ws.FW, fs, c.ldf, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_ahat(HdgContext& c) {
+  const int nb = c.hc.n_b;
+  const long long total = (long long)c.hm.n_macros * nb * nb;
+  hipLaunchKernelGGL(k_cast_ahat, dim3(grid_for(total)), dim3(256), 0, c.stream, c.ws.Wm, (long long)c.n_rows * c.ldw,
+                     (long long)c.ldw, (long long)c.hc.n_u * c.ldw + c.hc.n_u, nb, c.ws.A32, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_multidot(hipStream_t s, long long n, int k, const double* V, long long ldv, const double* w,
+                           double* partial, double* out) {
+  hipLaunchKernelGGL(k_multidot_partial, dim3(VEC_BLOCKS), dim3(256), 0, s, n, k, V, ldv, w, partial);
+  hipLaunchKernelGGL(k_multidot_final, dim3(k), dim3(64), 0, s, VEC_BLOCKS, k, partial, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_multiaxpy(hipStream_t s, long long n, int k, const double* V, long long ldv, const double* coef,
+                            double sign, double* w) {
+  hipLaunchKernelGGL(k_multiaxpy, dim3(grid_for(n)), dim3(256), 0, s, n, k, V, ldv, coef, sign, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb(hipStream_t s, long long n, int k, const double* V, long long ldv, const double* coef,
+                          double* y, int accumulate) {
+  hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n)), dim3(256), 0, s, n, k, V, ldv, coef, y, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(hipStream_t s, long long n, double a, const double* x, double* y) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(n)), dim3(256), 0, s, n, a, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub(hipStream_t s, long long n, const double* a, const double* b, double* y) {
+  hipLaunchKernelGGL(k_sub, dim3(grid_for(n)), dim3(256), 0, s, n, a, b, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(hipStream_t s, size_t n, double a, const double* x, double* y) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for((long long)n)), dim3(256), 0, s, (long long)n, a, x, y);
+  return hipGetLastError();
+}

@@ -1,0 +1,247 @@
+"""Thin ctypes binding of libhdg.so (include/hdg.h), same call names.
+
+Argument marshalling only: device arrays are passed as torch CUDA tensors
+(their data pointers), work is queued on torch's current stream.  Every step
+of the path runs in the library's HIP kernels; there is no fallback, and a
+missing library raises at import of this module's Context.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdg.so")
+
+HDG_FP64, HDG_FP32 = 0, 1
+_STATUS = {0: "HDG_OK", 1: "HDG_EINVAL", 2: "HDG_ENOMEM", 3: "HDG_EDEVICE", 4: "HDG_ESINGULAR",
+           5: "HDG_ENOCONV", 6: "HDG_EBREAKDOWN", 7: "HDG_ENAN", 8: "HDG_EUNSUPPORTED"}
+
+
+class HdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _MeshDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_elem", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("periodic", ctypes.c_int * 3), ("n_seg", ctypes.c_int * 3),
+                ("seg_len", ctypes.POINTER(ctypes.c_int) * 3), ("p", ctypes.c_int)]
+
+
+class _Phys(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("Pr", ctypes.c_double), ("Re", ctypes.c_double),
+                ("Mach", ctypes.c_double), ("supg", ctypes.c_int), ("bc_state_host", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Sizes(ctypes.Structure):
+    _fields_ = [("n_macros", ctypes.c_size_t), ("n_glob", ctypes.c_size_t), ("n_u_tot", ctypes.c_size_t),
+                ("n_q_tot", ctypes.c_size_t), ("n_u_macro", ctypes.c_size_t), ("n_b_macro", ctypes.c_size_t),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class KrylovOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("restart", ctypes.c_int),
+                ("max_outer", ctypes.c_int), ("inner_its", ctypes.c_int), ("inner_prec", ctypes.c_int)]
+
+
+class KrylovStats(ctypes.Structure):
+    _fields_ = [("outer_its", ctypes.c_int), ("inner_its_total", ctypes.c_int), ("res0", ctypes.c_double),
+                ("res_final", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
+EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_node_coords", "hdg_bind_workspace", "hdg_linearize_stage",
+           "hdg_condense", "hdg_apply_global", "hdg_fgmres_solve", "hdg_local_backsolve", "hdg_axpy",
+           "hdg_destroy", "hdg_status_string", "hdg_last_error", "hdg_get_condensed", "hdg_get_formed",
+           "hdg_get_residuals"]
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libhdg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2402_11361_amd/build.py")
+    lib = ctypes.CDLL(path)
+    vp, dp, sz, i = ctypes.c_void_p, ctypes.c_double, ctypes.c_size_t, ctypes.c_int
+    lib.hdg_setup_mesh.argtypes = [ctypes.POINTER(_MeshDesc), ctypes.POINTER(_Phys), vp, ctypes.POINTER(vp)]
+    lib.hdg_query_sizes.argtypes = [vp, ctypes.POINTER(_Sizes)]
+    lib.hdg_node_coords.argtypes = [vp, vp, vp]
+    lib.hdg_bind_workspace.argtypes = [vp, vp, sz]
+    lib.hdg_linearize_stage.argtypes = [vp, vp, vp, vp, vp, dp, dp, dp, vp]
+    lib.hdg_condense.argtypes = [vp, i, vp]
+    lib.hdg_apply_global.argtypes = [vp, vp, vp]
+    lib.hdg_fgmres_solve.argtypes = [vp, vp, vp, ctypes.POINTER(KrylovOpts), ctypes.POINTER(KrylovStats)]
+    lib.hdg_local_backsolve.argtypes = [vp, vp, vp, vp]
+    lib.hdg_axpy.argtypes = [vp, sz, dp, vp, vp]
+    lib.hdg_destroy.argtypes = [vp]
+    lib.hdg_status_string.argtypes = [i]
+    lib.hdg_status_string.restype = ctypes.c_char_p
+    lib.hdg_last_error.argtypes = [vp]
+    lib.hdg_last_error.restype = ctypes.c_char_p
+    lib.hdg_get_condensed.argtypes = [vp, sz, vp, vp]
+    lib.hdg_get_formed.argtypes = [vp, sz, vp]
+    lib.hdg_get_residuals.argtypes = [vp, vp, vp, vp]
+    for name in EXPORTS:
+        if name not in ("hdg_status_string", "hdg_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Context:
+    """One mesh + physics set-up (hdg_setup_mesh) with its bound workspace."""
+
+    def __init__(self, dim, n_elem, lo, hi, periodic, seg_len, p, gamma=1.4, Pr=0.71, Re=100.0, Mach=0.1,
+                 supg=False, bc_state=None, stream=None):
+        import torch
+        self.lib = load_library()
+        self.torch = torch
+        md = _MeshDesc()
+        md.dim = dim
+        md.p = p
+        self._segs = []
+        for k in range(3):
+            if k < dim:
+                seg = np.ascontiguousarray(seg_len[k], dtype=np.int32)
+                self._segs.append(seg)
+                md.n_elem[k] = int(n_elem[k])
+                md.lo[k] = float(lo[k])
+                md.hi[k] = float(hi[k])
+                md.periodic[k] = int(bool(periodic[k]))
+                md.n_seg[k] = seg.size
+                md.seg_len[k] = seg.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+            else:
+                md.n_elem[k] = 1
+                md.n_seg[k] = 1
+        ph = _Phys()
+        ph.gamma, ph.Pr, ph.Re, ph.Mach, ph.supg = gamma, Pr, Re, Mach, int(supg)
+        self._bc = None
+        if bc_state is not None:
+            self._bc = np.ascontiguousarray(bc_state, dtype=np.float64)
+            ph.bc_state_host = self._bc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        self._check(self.lib.hdg_setup_mesh(ctypes.byref(md), ctypes.byref(ph), ctypes.c_void_p(stream),
+                                            ctypes.byref(h)), ctx=None)
+        self.h = h
+        s = _Sizes()
+        self._check(self.lib.hdg_query_sizes(self.h, ctypes.byref(s)))
+        self.n_macros, self.n_glob = s.n_macros, s.n_glob
+        self.n_u_tot, self.n_q_tot = s.n_u_tot, s.n_q_tot
+        self.n_u_macro, self.n_b_macro = s.n_u_macro, s.n_b_macro
+        self.workspace_bytes = s.workspace_bytes
+        self.dim = dim
+        self.ws = None
+
+    def _check(self, code, ctx="self"):
+        if code != 0:
+            msg = self.lib.hdg_last_error(self.h).decode() if ctx == "self" else ""
+            raise HdgError(code, msg or self.lib.hdg_status_string(code).decode())
+
+    @classmethod
+    def from_mesh_spec(cls, spec, **kw):
+        return cls(spec["dim"], spec["n_elem"], spec["lo"], spec["hi"], spec["periodic"], spec["seg_len"], spec["p"], **kw)
+
+    def bind_workspace(self, ws=None):
+        """Allocate (torch) and bind the device workspace."""
+        t = self.torch
+        if ws is None:
+            ws = t.empty(self.workspace_bytes + 256, dtype=t.uint8, device="cuda")
+        base = ws.data_ptr()
+        off = (-base) % 256
+        self.ws = ws
+        self._check(self.lib.hdg_bind_workspace(self.h, ctypes.c_void_p(base + off), ctypes.c_size_t(ws.numel() - off)))
+        return ws
+
+    def node_coords(self):
+        d = self.dim
+        mx = np.zeros(self.n_u_tot // (d + 2) * d)
+        fx = np.zeros(self.n_glob // (d + 2) * d)
+        self._check(self.lib.hdg_node_coords(self.h, _np_ptr(mx), _np_ptr(fx)))
+        return mx.reshape(-1, d), fx.reshape(-1, d)
+
+    def linearize_stage(self, q, u, uhat, w=None, dt=math.inf, d_ii=1.0, dtau=math.inf, norms=True):
+        out = np.zeros(3) if norms else None
+        self._check(self.lib.hdg_linearize_stage(self.h, _ptr(q), _ptr(u), _ptr(uhat), _ptr(w), dt, d_ii, dtau,
+                                                 _np_ptr(out) if norms else None))
+        return out
+
+    def condense(self, bhat, prec=HDG_FP64):
+        self._check(self.lib.hdg_condense(self.h, prec, _ptr(bhat)))
+
+    def apply_global(self, x, y):
+        self._check(self.lib.hdg_apply_global(self.h, _ptr(x), _ptr(y)))
+
+    def fgmres_solve(self, b, x, rtol=1e-8, atol=0.0, restart=30, max_outer=300, inner_its=5,
+                     inner_prec=HDG_FP64, allow_noconv=False):
+        o = KrylovOpts(rtol, atol, restart, max_outer, inner_its, inner_prec)
+        st = KrylovStats()
+        code = self.lib.hdg_fgmres_solve(self.h, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(st))
+        if not (allow_noconv and code == 5):
+            self._check(code)
+        return dict(outer_its=st.outer_its, inner_its=st.inner_its_total, res0=st.res0, res=st.res_final,
+                    ms=st.ms, converged=(code == 0))
+
+    def local_backsolve(self, duhat, dq, du):
+        self._check(self.lib.hdg_local_backsolve(self.h, _ptr(duhat), _ptr(dq), _ptr(du)))
+
+    def axpy(self, a, x, y):
+        self._check(self.lib.hdg_axpy(self.h, ctypes.c_size_t(x.numel()), float(a), _ptr(x), _ptr(y)))
+
+    def get_condensed(self, macro):
+        nb = self.n_b_macro
+        A = np.zeros((nb, nb))
+        b = np.zeros(nb)
+        self._check(self.lib.hdg_get_condensed(self.h, ctypes.c_size_t(macro), _np_ptr(A), _np_ptr(b)))
+        return A, b
+
+    def get_formed(self, macro):
+        nr = self.n_u_macro + self.n_b_macro
+        W = np.zeros((nr, nr + 1))
+        self._check(self.lib.hdg_get_formed(self.h, ctypes.c_size_t(macro), _np_ptr(W)))
+        return W
+
+    def get_residuals(self):
+        t = self.torch
+        rq = t.empty(self.n_q_tot, dtype=t.float64, device="cuda")
+        ru = t.empty(self.n_u_tot, dtype=t.float64, device="cuda")
+        rb = t.empty(self.n_glob, dtype=t.float64, device="cuda")
+        self._check(self.lib.hdg_get_residuals(self.h, _ptr(rq), _ptr(ru), _ptr(rb)))
+        return rq, ru, rb
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hdg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mesh_spec_box(dim, n_elem, m, p, lo, hi, periodic):
+    n_elem = [n_elem] * dim if np.isscalar(n_elem) else list(n_elem)
+    m = [m] * dim if np.isscalar(m) else list(m)
+    lo = [lo] * dim if np.isscalar(lo) else list(lo)
+    hi = [hi] * dim if np.isscalar(hi) else list(hi)
+    per = [periodic] * dim if np.isscalar(periodic) else list(periodic)
+    seg = [[m[k]] * (n_elem[k] // m[k]) for k in range(dim)]
+    return dict(dim=dim, n_elem=n_elem, lo=lo, hi=hi, periodic=per, seg_len=seg, p=p)
