@@ -53,6 +53,7 @@ struct Workspace {
   double* kry = nullptr;    // Krylov vectors
   double* red = nullptr;    // reduction scratch
   double* small = nullptr;  // small device scalars
+  double* Uinv = nullptr;   // [max(macros, faces)][64][64] block inverses of the elimination
 };
 
 struct HdgContext {

@@ -390,7 +390,7 @@ void plan_workspace(HdgContext& c) {
   c.ldf = (int)align_up(2 * c.nf_max, 64);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, Wm, ipiv, FW, fpiv, A32, ypart, kry, red, small; } o;
+  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, Wm, ipiv, FW, fpiv, A32, ypart, kry, red, small, Uinv; } o;
   o.Kq = take(sizeof(double) * n_el * c.Kstride);
   o.AUU = take(sizeof(double) * n_el * c.nsA * c.nsA);
   o.AUQ = take(sizeof(double) * n_el * c.nsA * c.dnsA);
@@ -411,6 +411,8 @@ void plan_workspace(HdgContext& c) {
   o.kry = take(sizeof(double) * (size_t)(2 * c.kry_restart_max + c.kry_inner_max + 8) * hm.n_glob);
   o.red = take(sizeof(double) * (1 << 20));
   o.small = take(sizeof(double) * 4096);
+  // elimination scratch: per matrix a 64 x 64 block inverse and a row permutation
+  o.Uinv = take(sizeof(double) * (size_t)std::max(hm.n_macros, hm.n_faces) * (64 * 64 + 256));
   c.need_bytes = off;
   // remember offsets in the workspace struct (resolved on bind)
   c.ws.bytes = 0;
@@ -434,6 +436,7 @@ void plan_workspace(HdgContext& c) {
   c.ws.kry = reinterpret_cast<double*>(o.kry);
   c.ws.red = reinterpret_cast<double*>(o.red);
   c.ws.small = reinterpret_cast<double*>(o.small);
+  c.ws.Uinv = reinterpret_cast<double*>(o.Uinv);
 }
 
 void node_coords(const HdgContext& c, double* macro_xyz, double* face_xyz) {

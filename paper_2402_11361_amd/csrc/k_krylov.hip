@@ -261,7 +261,7 @@ hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec) {
 }
 
 hipError_t lu_eliminate(hipStream_t s, double* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
-                        int n_cols, int* ipiv, int ipiv_stride, int* status);
+                        int n_cols, int* ipiv, int ipiv_stride, int* status, double* scratch);
 
 hipError_t launch_face_precond(HdgContext& c) {
   const long long fs = (long long)2 * c.nf_max * c.ldf;
@@ -277,7 +277,7 @@ hipError_t launch_face_precond(HdgContext& c) {
   if (sizes.size() == 1) {
     const int nf = sizes[0];
     return lu_eliminate(c.stream, c.ws.FW, c.hm.n_faces, fs, c.ldf, nf, 2 * nf, 2 * nf, c.ws.fpiv, c.nf_max,
-                        reinterpret_cast<int*>(c.ws.small) + 1);
+                        reinterpret_cast<int*>(c.ws.small) + 1, c.ws.Uinv);
   }
   // several face sizes: runs of consecutive faces with the same size
   int f0 = 0;
@@ -286,7 +286,7 @@ hipError_t launch_face_precond(HdgContext& c) {
     while (f1 < c.hm.n_faces && c.hm.face_ndof[f1] == c.hm.face_ndof[f0]) ++f1;
     const int nf = c.hm.face_ndof[f0];
     e = lu_eliminate(c.stream, c.ws.FW + (size_t)f0 * fs, f1 - f0, fs, c.ldf, nf, 2 * nf, 2 * nf,
-                     c.ws.fpiv + (size_t)f0 * c.nf_max, c.nf_max, reinterpret_cast<int*>(c.ws.small) + 1);
+                     c.ws.fpiv + (size_t)f0 * c.nf_max, c.nf_max, reinterpret_cast<int*>(c.ws.small) + 1, c.ws.Uinv);
     if (e != hipSuccess) return e;
     f0 = f1;
   }

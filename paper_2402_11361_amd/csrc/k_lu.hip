@@ -36,14 +36,24 @@ struct LuArgs {
   int* ipiv;             // [batch][n_piv]
   int ipiv_stride;
   int* status;           // first singular matrix index + 1 (0 = none)
+  int* perm;             // [batch][PERM_STRIDE]: net row permutation of the current block
 };
+
+// Net effect of a block's row swaps: position j0 + i takes the old row
+// perm[i] (i < jb); nout further positions perm[NB + k] take perm[2 NB + k];
+// perm[3 NB] = nout.
+constexpr int PERM_STRIDE = 3 * 64 + 4;
+// two slots per matrix (consecutive 64-column blocks alternate)
+__device__ __forceinline__ int* perm_slot(const LuArgs& a, int mat, int j0) {
+  return a.perm + ((size_t)mat * 2 + ((j0 / 64) & 1)) * PERM_STRIDE;
+}
 
 __device__ __forceinline__ void argmax_update(double& bv, int& bi, double v, int i) {
   if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
 }
 
 template <int RPT>
-__global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int jb) {
+__global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int jb, int lcol0) {
   const int tid = threadIdx.x;
   const int mat = blockIdx.x;
   double* W = a.W + (size_t)mat * a.mat_stride;
@@ -128,8 +138,8 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
           }
         }
         // the rest of the block row (columns [j0, c0) and [c0 + pw, j0 + jb)) in memory
-        for (int k = tid; k < jb; k += PANEL_THREADS) {
-          const int cidx = j0 + k;
+        for (int k = tid; k < j0 + jb - lcol0; k += PANEL_THREADS) {
+          const int cidx = lcol0 + k;  // L columns of a previous block too (lcol0 < j0)
           if (cidx >= c0 && cidx < c0 + pw) continue;
           double t = W[(size_t)col * ld + cidx];
           W[(size_t)col * ld + cidx] = W[(size_t)prow * ld + cidx];
@@ -197,6 +207,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
       for (int i = 0; i < RPT; ++i) {
         const int r = c0 + tid + i * PANEL_THREADS;
         if (r >= c0 + pw && r < n_piv) {
+#pragma unroll 4
           for (int cidx = 0; cidx < nrest; ++cidx) {
             double s = W[(size_t)r * ld + rest0 + cidx];
 #pragma unroll
@@ -209,14 +220,37 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
       __syncthreads();
     }
   }
+  // net row permutation of the block's swaps, for the strips to the right
+  if (tid == 0) {
+    int* pm = perm_slot(a, mat, j0);
+    int s_in[NB];
+    int nout = 0;
+    for (int i = 0; i < NB; ++i) s_in[i] = j0 + i;
+    for (int r = 0; r < jb; ++r) {
+      const int pa = j0 + r, pb = ipiv[pa];
+      if (pb == pa) continue;
+      int* src_b = nullptr;
+      if (pb < j0 + jb) {
+        src_b = &s_in[pb - j0];
+      } else {
+        for (int k = 0; k < nout; ++k)
+          if (pm[NB + k] == pb) { src_b = &pm[2 * NB + k]; break; }
+        if (!src_b) { pm[NB + nout] = pb; pm[2 * NB + nout] = pb; src_b = &pm[2 * NB + nout]; ++nout; }
+      }
+      const int t = s_in[r];
+      s_in[r] = *src_b;
+      *src_b = t;
+    }
+    for (int i = 0; i < NB; ++i) pm[i] = s_in[i];
+    pm[3 * NB] = nout;
+  }
 }
 
-// L of the non-pivot rows [n_piv, n_rows) for the block: l = a U11^{-1}.
-// The workgroup first inverts the (identity-padded) upper triangle U11 in
-// LDS, column by column; every thread then multiplies one row by it.
-__global__ void __launch_bounds__(256) k_dtrsm(LuArgs a, int j0, int jb) {
-  const int mat = blockIdx.y;
-  double* W = a.W + (size_t)mat * a.mat_stride;
+// U11^{-1} of the block (identity-padded to NB x NB) into Uinv[mat]: one
+// thread per column, backward substitution in LDS.
+__global__ void __launch_bounds__(64) k_uinv(LuArgs a, int j0, int jb, double* __restrict__ Uinv) {
+  const int mat = blockIdx.x;
+  const double* W = a.W + (size_t)mat * a.mat_stride;
   const int ld = a.ld;
   __shared__ double sU[NB * NB];
   __shared__ double sI[NB * NB];
@@ -227,62 +261,65 @@ __global__ void __launch_bounds__(256) k_dtrsm(LuArgs a, int j0, int jb) {
     sU[i] = v;
   }
   __syncthreads();
-  if (threadIdx.x < NB) {
-    const int j = threadIdx.x;  // column j of U^{-1}: U x = e_j, x_i = 0 for i > j
-    for (int i = NB - 1; i >= 0; --i) {
-      double s = (i == j) ? 1.0 : 0.0;
-      for (int m = i + 1; m <= j; ++m) s -= sU[i * NB + m] * sI[m * NB + j];
-      const double dgl = sU[i * NB + i];
-      sI[i * NB + j] = (i <= j && dgl != 0.0) ? s / dgl : 0.0;
-    }
+  const int j = threadIdx.x;
+  for (int i = NB - 1; i >= 0; --i) {
+    double s = (i == j) ? 1.0 : 0.0;
+    for (int m = i + 1; m <= j; ++m) s -= sU[i * NB + m] * sI[m * NB + j];
+    const double dgl = sU[i * NB + i];
+    sI[i * NB + j] = (i <= j && dgl != 0.0) ? s / dgl : 0.0;
   }
   __syncthreads();
-  const int r = a.n_piv + blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= a.n_rows) return;
-  double av[NB];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) av[c] = (c < jb) ? W[(size_t)r * ld + j0 + c] : 0.0;
-  for (int c = 0; c < jb; ++c) {
-    double s = 0.0;
-#pragma unroll
-    for (int m = 0; m < NB; ++m) s += av[m] * sI[m * NB + c];
-    W[(size_t)r * ld + j0 + c] = s;
-  }
+  double* out = Uinv + (size_t)mat * NB * NB;
+  for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) out[i] = sI[i];
 }
 
-// Trailing update of one 64-column strip to the right of the block.  Strips
-// are aligned to multiples of NC; columns below j0 + jb (the block itself) or
-// at/after ld are masked out.
-__global__ void __launch_bounds__(256) k_update(LuArgs a, int j0, int jb, int strip0) {
+// Row swaps of the block and U12 = L11^{-1} A12 for one 64-column strip,
+// written back in place (rows [j0, j0 + jb) of the strip).  Columns below
+// live0 = j0 + jb or at/after ld are left alone.
+__global__ void __launch_bounds__(256) k_u12(LuArgs a, int j0, int jb, int strip0, int col_end) {
   const int mat = blockIdx.y;
-  const int cs = strip0 + blockIdx.x * NC;  // first column of the strip (multiple of NC)
+  const int cs = strip0 + blockIdx.x * NC;
   const int live0 = j0 + jb;
   double* W = a.W + (size_t)mat * a.mat_stride;
-  const int* ipiv = a.ipiv + (size_t)mat * a.ipiv_stride;
+  const int* pm = perm_slot(a, mat, j0);
   const int ld = a.ld, tid = threadIdx.x;
-  __shared__ double sL[NB * NB];   // unit lower L11
-  __shared__ double sU[NB * NC];   // U12 strip
+  __shared__ double sL[NB * NB];
+  __shared__ double sU[NB * NC];
   __shared__ double sP[4][NC];
-  // row swaps of the block applied to the strip (sequential order)
-  for (int r = 0; r < jb; ++r) {
-    const int pr = ipiv[j0 + r];
-    if (pr != j0 + r && tid < NC && cs + tid >= live0 && cs + tid < ld) {
-      double t = W[(size_t)(j0 + r) * ld + cs + tid];
-      W[(size_t)(j0 + r) * ld + cs + tid] = W[(size_t)pr * ld + cs + tid];
-      W[(size_t)pr * ld + cs + tid] = t;
-    }
-    __syncthreads();
-  }
-  for (int i = tid; i < NB * NB; i += 256) {
-    const int r = i / NB, c = i % NB;
-    sL[i] = (r < jb && c < jb) ? W[(size_t)(j0 + r) * ld + j0 + c] : 0.0;
-  }
-  for (int i = tid; i < NB * NC; i += 256) {
-    const int r = i / NC, c = i % NC;
-    sU[i] = (r < jb && cs + c >= live0 && cs + c < ld) ? W[(size_t)(j0 + r) * ld + cs + c] : 0.0;
+  __shared__ int s_src[2 * NB], s_dst[2 * NB];
+  // the block's swaps as one gather: block rows and the nout rows outside it
+  const int nout = pm[3 * NB];
+  for (int i = tid; i < jb; i += 256) { s_dst[i] = j0 + i; s_src[i] = pm[i]; }
+  for (int k = tid; k < nout; k += 256) { s_dst[jb + k] = pm[NB + k]; s_src[jb + k] = pm[2 * NB + k]; }
+  __syncthreads();
+  const int nt = jb + nout;
+  const int c = tid & (NC - 1);
+  const bool cok = cs + c >= live0 && cs + c < col_end;
+  // each thread gathers the values of its column for touched rows p = tid/64 + 4 j
+  double gv[2 * NB / 4];
+#pragma unroll
+  for (int j = 0; j < 2 * NB / 4; ++j) {
+    const int p = (tid >> 6) + 4 * j;
+    gv[j] = (p < nt && cok) ? W[(size_t)s_src[p] * ld + cs + c] : 0.0;
   }
   __syncthreads();
-  // U12 = L11^{-1} A12: row by row, the sum over m split in 4 parts
+#pragma unroll
+  for (int j = 0; j < 2 * NB / 4; ++j) {
+    const int p = (tid >> 6) + 4 * j;
+    if (p < nt && cok) {
+      if (p >= jb) W[(size_t)s_dst[p] * ld + cs + c] = gv[j];  // rows outside the block
+      else sU[p * NC + c] = gv[j];                             // block rows: to LDS for the solve
+    }
+  }
+  for (int i = tid; i < NB * NB; i += 256) {
+    const int r = i / NB, cc = i % NB;
+    sL[i] = (r < jb && cc < jb) ? W[(size_t)(j0 + r) * ld + j0 + cc] : 0.0;
+  }
+  for (int i = tid; i < NB * NC; i += 256) {
+    const int r = i / NC, cc = i % NC;
+    if (!(r < jb && cs + cc >= live0 && cs + cc < col_end)) sU[i] = 0.0;
+  }
+  __syncthreads();
   {
     const int col = tid % NC, part = tid / NC;
     for (int i = 1; i < jb; ++i) {
@@ -296,76 +333,265 @@ __global__ void __launch_bounds__(256) k_update(LuArgs a, int j0, int jb, int st
   }
   for (int i = tid; i < jb * NC; i += 256) {
     const int r = i / NC, c = i % NC;
-    if (cs + c >= live0 && cs + c < ld) W[(size_t)(j0 + r) * ld + cs + c] = sU[i];
+    if (cs + c >= live0 && cs + c < col_end) W[(size_t)(j0 + r) * ld + cs + c] = sU[i];
   }
-  // A22 -= L21 U12 with FP64 MFMA: each wave takes 16-row tiles of the strip
-  const int lane = tid & 63, wave = tid >> 6;
-  const int row_lo = j0 + jb;
-  const int ntile = (a.n_rows - row_lo + 15) / 16;
-  const int kq = (jb + 3) / 4;  // k-steps of 4
-  for (int tile = wave; tile < ntile; tile += 4) {
-    const int r0 = row_lo + tile * 16;
-    dbl4 acc[NC / 16];
+}
+
+// In-place unit-lower triangular solve X = L^{-1} X in LDS (L: n x n in sL
+// with leading dimension NB, X: n x 64 in sX), the inner sums split in four.
+__device__ void trsm_lds(const double* sL, double* sX, int n, double (*sP)[NC], int tid) {
+  const int col = tid % NC, part = tid / NC;
+  for (int i = 1; i < n; ++i) {
+    double s = 0.0;
+    for (int m = part; m < i; m += 4) s += sL[i * NB + m] * sX[m * NC + col];
+    sP[part][col] = s;
+    __syncthreads();
+    if (part == 0) sX[i * NC + col] -= sP[0][col] + sP[1][col] + sP[2][col] + sP[3][col];
+    __syncthreads();
+  }
+}
+
+// Two consecutive 64-column blocks b1 = [j0, j0 + 64), b2 = [j0 + 64, j0 + 64 + jb2)
+// applied to one strip right of both: the row swaps of b1 then b2, then
+//   U12_1 = L11^{-1} A12_1,  A12_2 -= L21(b2 rows, b1 cols) U12_1,  U12_2 = L22^{-1} A12_2,
+// written back to the rows [j0, j0 + 64 + jb2) of the strip.
+__global__ void __launch_bounds__(256) k_u12b2(LuArgs a, int j0, int jb2, int strip0) {
+  const int mat = blockIdx.y;
+  const int cs = strip0 + blockIdx.x * NC;
+  const int live0 = j0 + NB + jb2;
+  double* W = a.W + (size_t)mat * a.mat_stride;
+  const int ld = a.ld, tid = threadIdx.x;
+  __shared__ double sL[NB * NB];
+  __shared__ double sU1[NB * NC];
+  __shared__ double sU2[NB * NC];
+  __shared__ double sP[4][NC];
+  __shared__ int s_src[2 * NB], s_dst[2 * NB];
+  const int c = tid & (NC - 1);
+  const bool cok = cs + c >= live0 && cs + c < ld;
+  for (int blk = 0; blk < 2; ++blk) {
+    const int jj = j0 + blk * NB, jbb = blk ? jb2 : NB;
+    const int* pm = perm_slot(a, mat, jj);
+    const int nout = pm[3 * NB];
+    for (int i = tid; i < jbb; i += 256) { s_dst[i] = jj + i; s_src[i] = pm[i]; }
+    for (int k = tid; k < nout; k += 256) { s_dst[jbb + k] = pm[NB + k]; s_src[jbb + k] = pm[2 * NB + k]; }
+    __syncthreads();
+    const int nt = jbb + nout;
+    double gv[2 * NB / 4];
+#pragma unroll
+    for (int j = 0; j < 2 * NB / 4; ++j) {
+      const int p = (tid >> 6) + 4 * j;
+      gv[j] = (p < nt && cok) ? W[(size_t)s_src[p] * ld + cs + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 2 * NB / 4; ++j) {
+      const int p = (tid >> 6) + 4 * j;
+      if (p < nt && cok) W[(size_t)s_dst[p] * ld + cs + c] = gv[j];
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < NB * NB; i += 256) {
+    const int r = i / NB, cc = i % NB;
+    sL[i] = W[(size_t)(j0 + r) * ld + j0 + cc];
+  }
+  for (int i = tid; i < NB * NC; i += 256) {
+    const int r = i / NC, cc = i % NC;
+    const bool ok = cs + cc >= live0 && cs + cc < ld;
+    sU1[i] = ok ? W[(size_t)(j0 + r) * ld + cs + cc] : 0.0;
+    sU2[i] = (ok && r < jb2) ? W[(size_t)(j0 + NB + r) * ld + cs + cc] : 0.0;
+  }
+  __syncthreads();
+  trsm_lds(sL, sU1, NB, sP, tid);
+  for (int i = tid; i < NB * NB; i += 256) {
+    const int r = i / NB, cc = i % NB;
+    sL[i] = (r < jb2) ? W[(size_t)(j0 + NB + r) * ld + j0 + cc] : 0.0;
+  }
+  __syncthreads();
+  {
+    const int col = tid % NC, part = tid / NC;
+    for (int i = part; i < jb2; i += 4) {
+      double s = 0.0;
+      for (int m = 0; m < NB; ++m) s += sL[i * NB + m] * sU1[m * NC + col];
+      sU2[i * NC + col] -= s;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < NB * NB; i += 256) {
+    const int r = i / NB, cc = i % NB;
+    sL[i] = (r < jb2 && cc < jb2) ? W[(size_t)(j0 + NB + r) * ld + j0 + NB + cc] : 0.0;
+  }
+  __syncthreads();
+  trsm_lds(sL, sU2, jb2, sP, tid);
+  for (int i = tid; i < NB * NC; i += 256) {
+    const int r = i / NC, cc = i % NC;
+    if (cs + cc >= live0 && cs + cc < ld) {
+      W[(size_t)(j0 + r) * ld + cs + cc] = sU1[i];
+      if (r < jb2) W[(size_t)(j0 + NB + r) * ld + cs + cc] = sU2[i];
+    }
+  }
+}
+
+// C[r, cs:cs+64] = (beta ? C : 0) + alpha * A[r, ak0:ak0+K] * B[0:K, 0:64] on
+// FP64 MFMA for the rows [r_lo, r_hi) of one matrix, 16-row tiles, four waves
+// per workgroup and `TPW` tiles per wave.  B (K x 64, leading dimension ldb)
+// is staged in LDS.  The k index of an MFMA step is k = 16 (lane / 16) + step,
+// so every lane loads 16 consecutive A values of its row.  Columns outside
+// [c_lo, ld) are masked (read as 0, never written).
+struct GemmArgs {
+  double* W;
+  long long mat_stride;
+  int ld;
+  const double* B;
+  long long b_mat_stride;
+  int ldb;
+  int b_col_follow;  // 1: B columns are the strip columns (B rows of W); 0: fixed K x 64 B
+  int ak0, K, cs0, c_lo, c_hi, r_lo, r_hi;
+  double alpha;
+  int beta;
+  int tiles_per_wg;
+};
+
+template <int KB>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  constexpr int KS = KB / 4;  // MFMA k-steps; lane group grp covers k in [KS grp, KS grp + KS)
+  const int mat = blockIdx.z;
+  const int cs = g.cs0 + blockIdx.x * NC;
+  double* W = g.W + (size_t)mat * g.mat_stride;
+  const double* B = g.B + (size_t)mat * g.b_mat_stride;
+  const int ld = g.ld, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int grp = lane >> 4, col = lane & 15;
+  __shared__ double sB[KB * NC];
+  for (int i = tid; i < KB * NC; i += 256) {
+    const int k = i / NC, c = i % NC;
+    sB[i] = (k < g.K && cs + c >= g.c_lo && cs + c < g.c_hi) ? B[(size_t)k * g.ldb + (g.b_col_follow ? cs : 0) + c] : 0.0;
+  }
+  __syncthreads();
+  const int tile0 = blockIdx.y * g.tiles_per_wg;
+  auto load_a = [&](int r0, double* af) {
+    const int ra = r0 + col;
+    const bool rok = ra < g.r_hi;
+    const double* ap = W + (size_t)ra * ld + g.ak0 + KS * grp;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) af[s] = (rok && KS * grp + s < g.K) ? g.alpha * ap[s] : 0.0;
+  };
+  auto load_c = [&](int r0, dbl4* acc) {
 #pragma unroll
     for (int ct = 0; ct < NC / 16; ++ct) {
-      const int cc = cs + ct * 16 + (lane & 15);
-      const bool cok = cc >= live0 && cc < ld;
+      const int cc = cs + ct * 16 + col;
+      const bool cok = cc >= g.c_lo && cc < g.c_hi;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = r0 + 4 * i + (lane >> 4);  // f64 16x16x4: D[4 reg + lane/16][lane%16]
-        acc[ct][i] = (r < a.n_rows && cok) ? W[(size_t)r * ld + cc] : 0.0;
+        const int r = r0 + 4 * i + grp;  // f64 16x16x4: D[4 reg + lane/16][lane%16]
+        acc[ct][i] = (g.beta && r < g.r_hi && cok) ? W[(size_t)r * ld + cc] : 0.0;
       }
     }
-    const int ra = r0 + (lane & 15);
-    for (int ks = 0; ks < kq; ++ks) {
-      const int kk = 4 * ks + (lane >> 4);
-      const double av = (ra < a.n_rows && kk < jb) ? -W[(size_t)ra * ld + j0 + kk] : 0.0;
+  };
+  double af[KS], af2[KS];
+  dbl4 acc[NC / 16], acc2[NC / 16];
+  int t = wave;
+  int r0 = g.r_lo + (tile0 + t) * 16;
+  if (t >= g.tiles_per_wg || r0 >= g.r_hi) return;
+  load_a(r0, af);
+  load_c(r0, acc);
+  for (; t < g.tiles_per_wg; t += 4) {
+    r0 = g.r_lo + (tile0 + t) * 16;
+    const int rn = r0 + 64;
+    const bool more = (t + 4 < g.tiles_per_wg) && rn < g.r_hi;
+    if (more) { load_a(rn, af2); load_c(rn, acc2); }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
 #pragma unroll
       for (int ct = 0; ct < NC / 16; ++ct) {
-        const double bv = (kk < jb) ? sU[kk * NC + ct * 16 + (lane & 15)] : 0.0;
-        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[ct], 0, 0, 0);
+        const double bv = sB[(KS * grp + s) * NC + ct * 16 + col];
+        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s], bv, acc[ct], 0, 0, 0);
       }
     }
 #pragma unroll
     for (int ct = 0; ct < NC / 16; ++ct) {
-      const int cc = cs + ct * 16 + (lane & 15);
-      const bool cok = cc >= live0 && cc < ld;
+      const int cc = cs + ct * 16 + col;
+      const bool cok = cc >= g.c_lo && cc < g.c_hi;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = r0 + 4 * i + (lane >> 4);  // f64 16x16x4: D[4 reg + lane/16][lane%16]
-        if (r < a.n_rows && cok) W[(size_t)r * ld + cc] = acc[ct][i];
+        const int r = r0 + 4 * i + grp;
+        if (r < g.r_hi && cok) W[(size_t)r * ld + cc] = acc[ct][i];
       }
     }
+    if (!more) break;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) af[s] = af2[s];
+#pragma unroll
+    for (int ct = 0; ct < NC / 16; ++ct) acc[ct] = acc2[ct];
   }
 }
 
 }  // namespace
 
 // Eliminate the first n_piv columns of `batch` matrices (see file comment).
+// scratch: batch * NB * NB doubles for the block inverses.
 hipError_t lu_eliminate(hipStream_t s, double* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
-                        int n_cols, int* ipiv, int ipiv_stride, int* status) {
-  LuArgs a{W, mat_stride, ld, n_piv, n_rows, n_cols, ipiv, ipiv_stride, status};
+                        int n_cols, int* ipiv, int ipiv_stride, int* status, double* scratch) {
+  // scratch: batch NB x NB block inverses, then batch x 2 PERM_STRIDE ints
+  int* perm = reinterpret_cast<int*>(scratch + (size_t)batch * NB * NB);
+  LuArgs a{W, mat_stride, ld, n_piv, n_rows, n_cols, ipiv, ipiv_stride, status, perm};
   if (ld % NC != 0) return hipErrorInvalidValue;
   const int rpt = (n_piv + PANEL_THREADS - 1) / PANEL_THREADS;
-  for (int j0 = 0; j0 < n_piv; j0 += NB) {
-    const int jb = std::min(NB, n_piv - j0);
-    if (rpt <= 1) hipLaunchKernelGGL(k_panel<1>, dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb);
-    else if (rpt <= 2) hipLaunchKernelGGL(k_panel<2>, dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb);
-    else if (rpt <= 4) hipLaunchKernelGGL(k_panel<4>, dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb);
-    else if (rpt <= 8) hipLaunchKernelGGL(k_panel<8>, dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb);
-    else return hipErrorInvalidValue;
-    if (n_rows > n_piv)
-      hipLaunchKernelGGL(k_dtrsm, dim3((n_rows - n_piv + 255) / 256, batch), dim3(256), 0, s, a, j0, jb);
-    // strips aligned to NC covering the live columns [j0 + jb, n_cols)
-    const int live0 = j0 + jb;
-    const int strip0 = live0 / NC * NC;
+  constexpr int TPW = 32;  // 16-row tiles per workgroup (8 per wave)
+  auto panel = [&](int j0, int jb, int lcol0) {
+    if (rpt <= 1) hipLaunchKernelGGL(k_panel<1>, dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
+    else if (rpt <= 2) hipLaunchKernelGGL(k_panel<2>, dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
+    else if (rpt <= 4) hipLaunchKernelGGL(k_panel<4>, dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
+    else hipLaunchKernelGGL(k_panel<8>, dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
+  };
+  auto drows = [&](int j0, int jb) {  // L of the non-pivot rows: A_D,block U11^{-1}
+    if (n_rows <= n_piv) return;
+    hipLaunchKernelGGL(k_uinv, dim3(batch), dim3(NB), 0, s, a, j0, jb, scratch);
+    GemmArgs g{W, mat_stride, ld, scratch, (long long)NB * NB, NB, 0, j0, jb, j0, j0, j0 + jb, n_piv, n_rows, 1.0, 0, TPW};
+    const int ntile = (n_rows - n_piv + 15) / 16;
+    hipLaunchKernelGGL(k_gemm<64>, dim3(1, (ntile + TPW - 1) / TPW, batch), dim3(256), 0, s, g);
+  };
+  // A22 -= L21 U12 for the strips [strip0, ...) with U12 in rows [j0, j0 + K) of W
+  auto update = [&](int j0, int K, int live0, int strip0, int nstrip, int col_end) {
+    if (n_rows <= live0 || nstrip <= 0) return;
+    GemmArgs g{W, mat_stride, ld, W + (size_t)j0 * ld, mat_stride, ld, 1, j0, K, strip0, live0, col_end, live0, n_rows,
+               -1.0, 1, TPW};
+    const int ntile = (n_rows - live0 + 15) / 16;
+    dim3 grid(nstrip, (ntile + TPW - 1) / TPW, batch);
+    if (K > NB) hipLaunchKernelGGL(k_gemm<2 * NB>, grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(k_gemm<NB>, grid, dim3(256), 0, s, g);
+  };
+  if (rpt > 8) return hipErrorInvalidValue;
+  for (int j0 = 0; j0 < n_piv; j0 += 2 * NB) {
+    const int jb1 = std::min(NB, n_piv - j0);
+    panel(j0, jb1, j0);
+    drows(j0, jb1);
+    const bool two = (jb1 == NB) && (j0 + NB < n_piv);
+    if (!two) {
+      const int live0 = j0 + jb1, strip0 = live0 / NC * NC;
+      const int nstrip = (n_cols > live0) ? (n_cols - strip0 + NC - 1) / NC : 0;
+      if (nstrip > 0) {
+        hipLaunchKernelGGL(k_u12, dim3(nstrip, batch), dim3(256), 0, s, a, j0, jb1, strip0, ld);
+        update(j0, jb1, live0, strip0, nstrip, ld);
+      }
+      continue;
+    }
+    // look-ahead: bring the second block's columns up to date with the first
+    hipLaunchKernelGGL(k_u12, dim3(1, batch), dim3(256), 0, s, a, j0, NB, j0 + NB, j0 + NB + std::min(NB, n_piv - (j0 + NB)));
+    update(j0, NB, j0 + NB, j0 + NB, 1, j0 + NB + std::min(NB, n_piv - (j0 + NB)));
+    const int jb2 = std::min(NB, n_piv - (j0 + NB));
+    panel(j0 + NB, jb2, j0);  // also swaps the first block's L columns
+    drows(j0 + NB, jb2);
+    // both blocks on the remaining strips with one K = 64 + jb2 update
+    const int live0 = j0 + NB + jb2, strip0 = live0 / NC * NC;
     const int nstrip = (n_cols > live0) ? (n_cols - strip0 + NC - 1) / NC : 0;
-    if (nstrip > 0) hipLaunchKernelGGL(k_update, dim3(nstrip, batch), dim3(256), 0, s, a, j0, jb, strip0);
+    if (nstrip > 0) {
+      hipLaunchKernelGGL(k_u12b2, dim3(nstrip, batch), dim3(256), 0, s, a, j0, jb2, strip0);
+      update(j0, NB + jb2, live0, strip0, nstrip, ld);
+    }
   }
   return hipGetLastError();
 }
 
 hipError_t launch_lu(HdgContext& c) {
   return lu_eliminate(c.stream, c.ws.Wm, c.hm.n_macros, (long long)c.n_rows * c.ldw, c.ldw, c.hc.n_u, c.n_rows,
-                      c.n_cols, c.ws.ipiv, c.hc.n_u, reinterpret_cast<int*>(c.ws.small));
+                      c.n_cols, c.ws.ipiv, c.hc.n_u, reinterpret_cast<int*>(c.ws.small), c.ws.Uinv);
 }
