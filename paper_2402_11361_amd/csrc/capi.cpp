@@ -16,7 +16,8 @@
 #include <cstring>
 #include <new>
 
-hipError_t launch_face_sum(HdgContext& c, const double* base, long long macro_stride, long long elem_stride, double* out);
+hipError_t launch_face_sum(HdgContext& c, const double* base, long long macro_stride, long long elem_stride, double* out,
+                           long long tiled_rc);
 hipError_t launch_zero_ints(hipStream_t s, int* p, int n);
 
 namespace {
@@ -432,19 +433,28 @@ hdg_status hdg_destroy(hdg_ctx ctx) {
   return HDG_OK;
 }
 
+static hdg_status copy_tiled_macro(hdg_ctx ctx, size_t macro, std::vector<double>& out) {
+  HdgContext& c = ctx->c;
+  out.assign((size_t)c.wstride, 0.0);
+  HIPCHK(&c, hipMemcpyAsync(out.data(), c.ws.Wm + macro * (size_t)c.wstride, sizeof(double) * c.wstride,
+                            hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  return HDG_OK;
+}
+
 hdg_status hdg_get_condensed(hdg_ctx ctx, size_t macro, double* ahat_host, double* bhat_host) {
   if (!ctx) return HDG_EINVAL;
   HdgContext& c = ctx->c;
   if (!c.ws_bound || macro >= (size_t)c.hm.n_macros) return HDG_EINVAL;
   const int nb = c.hc.n_b, nu = c.hc.n_u;
-  const double* Wm = c.ws.Wm + macro * (size_t)c.n_rows * c.ldw;
-  if (ahat_host)
-    HIPCHK(&c, hipMemcpy2DAsync(ahat_host, nb * sizeof(double), Wm + (size_t)nu * c.ldw + nu, c.ldw * sizeof(double),
-                                nb * sizeof(double), nb, hipMemcpyDeviceToHost, c.stream));
-  if (bhat_host)
-    HIPCHK(&c, hipMemcpy2DAsync(bhat_host, sizeof(double), Wm + (size_t)nu * c.ldw + c.n_cols - 1, c.ldw * sizeof(double),
-                                sizeof(double), nb, hipMemcpyDeviceToHost, c.stream));
-  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  std::vector<double> tiled;
+  hdg_status s = copy_tiled_macro(ctx, macro, tiled);
+  if (s != HDG_OK) return s;
+  for (int r = 0; r < nb; ++r) {
+    if (ahat_host)
+      for (int k = 0; k < nb; ++k) ahat_host[(size_t)r * nb + k] = tiled[wtix(nu + r, nu + k, c.ldw)];
+    if (bhat_host) bhat_host[r] = tiled[wtix(nu + r, c.n_cols - 1, c.ldw)];
+  }
   return HDG_OK;
 }
 
@@ -453,10 +463,11 @@ hdg_status hdg_get_formed(hdg_ctx ctx, size_t macro, double* w_host) {
   HdgContext& c = ctx->c;
   if (!c.ws_bound || macro >= (size_t)c.hm.n_macros) return HDG_EINVAL;
   HIPCHK(&c, launch_form(c));
-  const double* Wm = c.ws.Wm + macro * (size_t)c.n_rows * c.ldw;
-  HIPCHK(&c, hipMemcpy2DAsync(w_host, c.n_cols * sizeof(double), Wm, c.ldw * sizeof(double), c.n_cols * sizeof(double),
-                              c.n_rows, hipMemcpyDeviceToHost, c.stream));
-  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  std::vector<double> tiled;
+  hdg_status s = copy_tiled_macro(ctx, macro, tiled);
+  if (s != HDG_OK) return s;
+  for (int r = 0; r < c.n_rows; ++r)
+    for (int k = 0; k < c.n_cols; ++k) w_host[(size_t)r * c.n_cols + k] = tiled[wtix(r, k, c.ldw)];
   return HDG_OK;
 }
 

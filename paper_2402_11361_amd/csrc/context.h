@@ -69,6 +69,8 @@ struct HdgContext {
   // sizes
   long long n_u_tot = 0, n_q_tot = 0;
   int n_rows = 0, n_cols = 0, ldw = 0;  // augmented matrix
+  long long wstride = 0;                // doubles per tiled macro matrix
+  long long fstride = 0;                // doubles per tiled face-preconditioner block
   int nsA = 0, dnsA = 0, sub_stride = 0, Kstride = 0;
   int nf_max = 0, ldf = 0;
   int kry_restart_max = 64, kry_inner_max = 16;

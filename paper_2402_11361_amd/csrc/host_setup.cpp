@@ -402,9 +402,11 @@ void plan_workspace(HdgContext& c) {
   o.RQt = take(sizeof(double) * c.n_q_tot);
   o.RBloc = take(sizeof(double) * (size_t)hm.n_macros * hc.n_b);
   o.RBglob = take(sizeof(double) * hm.n_glob);
-  o.Wm = take(sizeof(double) * (size_t)hm.n_macros * c.n_rows * c.ldw);
+  c.wstride = (long long)align_up(c.n_rows, 16) * c.ldw;
+  c.fstride = (long long)align_up(2 * c.nf_max, 16) * c.ldf;
+  o.Wm = take(sizeof(double) * (size_t)hm.n_macros * c.wstride);
   o.ipiv = take(sizeof(int) * (size_t)hm.n_macros * hc.n_u);
-  o.FW = take(sizeof(double) * (size_t)hm.n_faces * 2 * c.nf_max * c.ldf);
+  o.FW = take(sizeof(double) * (size_t)hm.n_faces * c.fstride);
   o.fpiv = take(sizeof(int) * (size_t)hm.n_faces * c.nf_max);
   o.A32 = take(sizeof(float) * (size_t)hm.n_macros * hc.n_b * hc.n_b);
   o.ypart = take(sizeof(double) * (size_t)hm.n_macros * hc.n_b);

@@ -76,6 +76,15 @@ struct MeshDev {
   const double* bc_state;      // [n_glob] Dirichlet data (or null)
 };
 
+// Storage of the augmented macro matrices (and of the face-preconditioner
+// blocks): 16 x 64 tiles, each tile contiguous and row-major, tiles ordered
+// row-major; ld is the padded width (a multiple of 64) and the row count is
+// padded to a multiple of 16.  A 16-row slab of a 64-column strip is one
+// contiguous 8 KB block, which keeps the MFMA trailing update streaming.
+__host__ __device__ __forceinline__ size_t wtix(long long r, long long c, long long ld) {
+  return ((size_t)(r >> 4) * (size_t)(ld >> 6) + (size_t)(c >> 6)) * 1024 + (size_t)(r & 15) * 64 + (size_t)(c & 63);
+}
+
 // ---- kernel launchers (defined in the .hip files) ----------------------
 struct Workspace;
 struct HdgContext;

@@ -38,11 +38,10 @@ __global__ void __launch_bounds__(256) k_bs_rhs(ClassDev cd, MeshDev md, const d
   for (int rr = wave; rr < BS_ROWS; rr += 4) {
     const int r = blockIdx.x * BS_ROWS + rr;
     if (r >= nu) break;
-    const double* row = Wmac + (size_t)r * ld + nu;
     double s = 0.0;
-    for (int c = lane; c < nb; c += 64) s += row[c] * xs[c];
+    for (int c = lane; c < nb; c += 64) s += Wmac[wtix(r, nu + c, ld)] * xs[c];
     s = wave_sum(s);
-    if (lane == 0) z[(size_t)macro * nu + r] = Wmac[(size_t)r * ld + n_cols - 1] - s;
+    if (lane == 0) z[(size_t)macro * nu + r] = Wmac[wtix(r, n_cols - 1, ld)] - s;
   }
 }
 
@@ -64,13 +63,13 @@ __global__ void __launch_bounds__(256) k_bs_trsv(ClassDev cd, const double* __re
     for (int rr = wave; rr < nr; rr += 4) {
       const int r = i0 + rr;
       double s = 0.0;
-      for (int c = i1 + lane; c < nu; c += 64) s += U[(size_t)r * ld + c] * x[c];
+      for (int c = i1 + lane; c < nu; c += 64) s += U[wtix(r, c, ld)] * x[c];
       s = wave_sum(s);
       if (lane == 0) sz[rr] = x[r] - s;
     }
     for (int i = threadIdx.x; i < nr * nr; i += blockDim.x) {
       const int r = i / nr, c = i % nr;
-      sU[r][c] = U[(size_t)(i0 + r) * ld + i0 + c];
+      sU[r][c] = U[wtix(i0 + r, i0 + c, ld)];
     }
     __syncthreads();
     if (wave == 0) {
@@ -127,7 +126,7 @@ __global__ void k_bs_dq(ClassDev cd, MeshDev md, const double* __restrict__ RQt,
 
 hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, double* du) {
   const int nu = c.hc.n_u, nb = c.hc.n_b, nm = c.hm.n_macros;
-  const long long ms = (long long)c.n_rows * c.ldw;
+  const long long ms = c.wstride;
   hipLaunchKernelGGL(k_bs_rhs, dim3((nu + BS_ROWS - 1) / BS_ROWS, nm), dim3(256), (size_t)nb * sizeof(double), c.stream,
                      c.cd, c.md, c.ws.Wm, ms, c.ldw, c.n_cols, duhat, du);
   hipLaunchKernelGGL(k_bs_trsv, dim3(nm), dim3(256), 0, c.stream, c.cd, c.ws.Wm, ms, c.ldw, du);

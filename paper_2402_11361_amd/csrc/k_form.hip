@@ -28,6 +28,7 @@ struct FormPtrs {
   const double *AUU, *AUQ, *SUB, *RU, *RQt, *RBloc;
   double* Wm;
   int nsA, dnsA, sub_stride, off_AUB, off_ABU, off_ABQ, off_ABB, ldw, n_cols;
+  long long mstride;  // doubles per macro matrix (tiled, rows padded to 16)
 };
 
 __device__ __forceinline__ void digits(int x, int base, int d, int* out) {
@@ -207,15 +208,15 @@ __global__ void __launch_bounds__(FORM_THREADS) k_form(ClassDev cd, MeshDev md, 
     if (tid == 0) row[fp.n_cols - 1] = red[0] - fp.RBloc[(size_t)macro * cd.n_b + rho];
   }
   __syncthreads();
-  double* dst = fp.Wm + ((size_t)macro * n_rows + r) * fp.ldw;
-  for (int i = tid; i < fp.ldw; i += FORM_THREADS) dst[i] = (i < fp.n_cols) ? row[i] : 0.0;
+  double* Wmac = fp.Wm + (size_t)macro * fp.mstride;
+  for (int i = tid; i < fp.ldw; i += FORM_THREADS) Wmac[wtix(r, i, fp.ldw)] = (i < fp.n_cols) ? row[i] : 0.0;
 }
 
 }  // namespace
 
 hipError_t launch_form(HdgContext& c) {
   FormPtrs fp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.ws.RQt, c.ws.RBloc, c.ws.Wm,
-              c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.ldw, c.n_cols};
+              c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.ldw, c.n_cols, c.wstride};
   const long long nblk = (long long)c.hm.n_macros * c.n_rows;
   hipLaunchKernelGGL(k_form, dim3((unsigned)nblk), dim3(FORM_THREADS), (size_t)c.n_cols * sizeof(double), c.stream,
                      c.cd, c.md, fp);

@@ -25,8 +25,11 @@ __device__ __forceinline__ int local_face(const ClassDev& cd, int r) {
 }
 
 // out[g] = sum over the (one or two) sides of face F(g) of src(side macro, local index)
+// elem_stride < 0 selects the tiled macro matrices: element r of a macro is
+// entry (row0 + r, col) of its tiled matrix with leading dimension -elem_stride,
+// where row0 and col are packed in `tiled_rc` (row0 * 2^32 + col).
 __global__ void k_face_gather_sum(ClassDev cd, MeshDev md, const double* __restrict__ base, long long macro_stride,
-                                  long long elem_stride, double* __restrict__ out) {
+                                  long long elem_stride, double* __restrict__ out, long long tiled_rc) {
   const int d = cd.dim;
   for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < md.n_glob; g += (long long)gridDim.x * blockDim.x) {
     int lo = 0, hi = md.n_faces - 1;
@@ -42,18 +45,25 @@ __global__ void k_face_gather_sum(ClassDev cd, MeshDev md, const double* __restr
     for (int lf = 0; lf < 2 * d; ++lf)
       if (md.macro_face[(size_t)m0 * 2 * d + lf] == F) { k = lf / 2; break; }
     double s = 0.0;
-    if (mm >= 0) s += base[(size_t)mm * macro_stride + (size_t)(cd.nf_off[2 * k + 1] + r) * elem_stride];
-    if (mp >= 0) s += base[(size_t)mp * macro_stride + (size_t)(cd.nf_off[2 * k] + r) * elem_stride];
+    auto at = [&](int macro, int idx) {
+      if (elem_stride >= 0) return base[(size_t)macro * macro_stride + (size_t)idx * elem_stride];
+      const long long row0 = tiled_rc >> 32, col = tiled_rc & 0xffffffffLL;
+      return base[(size_t)macro * macro_stride + wtix(row0 + idx, col, -elem_stride)];
+    };
+    if (mm >= 0) s += at(mm, cd.nf_off[2 * k + 1] + r);
+    if (mp >= 0) s += at(mp, cd.nf_off[2 * k] + r);
     out[g] = s;
   }
 }
 
 constexpr int APPLY_ROWS = 64;
 
-template <class TA>
+// TILED: Ab is the tiled augmented matrix, A-hat at offset (off, off) with
+// leading dimension ld; otherwise a compact row-major n_b x n_b block.
+template <class TA, bool TILED>
 __global__ void __launch_bounds__(256) k_apply_local(ClassDev cd, MeshDev md, const TA* __restrict__ Ab,
                                                      long long macro_stride, long long ld, const double* __restrict__ x,
-                                                     double* __restrict__ ypart) {
+                                                     double* __restrict__ ypart, int off) {
   extern __shared__ double xs[];
   const int macro = blockIdx.y;
   const int nb = cd.n_b;
@@ -70,16 +80,28 @@ __global__ void __launch_bounds__(256) k_apply_local(ClassDev cd, MeshDev md, co
   for (int rr = 0; rr < APPLY_ROWS / 4; rr += 4) {
     const int r = r0 + rr;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    const TA* p0 = Am + (size_t)min(r + 0, nb - 1) * ld;
-    const TA* p1 = Am + (size_t)min(r + 1, nb - 1) * ld;
-    const TA* p2 = Am + (size_t)min(r + 2, nb - 1) * ld;
-    const TA* p3 = Am + (size_t)min(r + 3, nb - 1) * ld;
-    for (int s = lane; s < nb; s += 64) {
-      const double xv = xs[s];
-      a0 += (double)p0[s] * xv;
-      a1 += (double)p1[s] * xv;
-      a2 += (double)p2[s] * xv;
-      a3 += (double)p3[s] * xv;
+    if (TILED) {
+      const int q0 = off + min(r + 0, nb - 1), q1 = off + min(r + 1, nb - 1);
+      const int q2 = off + min(r + 2, nb - 1), q3 = off + min(r + 3, nb - 1);
+      for (int s = lane; s < nb; s += 64) {
+        const double xv = xs[s];
+        a0 += (double)Am[wtix(q0, off + s, ld)] * xv;
+        a1 += (double)Am[wtix(q1, off + s, ld)] * xv;
+        a2 += (double)Am[wtix(q2, off + s, ld)] * xv;
+        a3 += (double)Am[wtix(q3, off + s, ld)] * xv;
+      }
+    } else {
+      const TA* p0 = Am + (size_t)min(r + 0, nb - 1) * ld;
+      const TA* p1 = Am + (size_t)min(r + 1, nb - 1) * ld;
+      const TA* p2 = Am + (size_t)min(r + 2, nb - 1) * ld;
+      const TA* p3 = Am + (size_t)min(r + 3, nb - 1) * ld;
+      for (int s = lane; s < nb; s += 64) {
+        const double xv = xs[s];
+        a0 += (double)p0[s] * xv;
+        a1 += (double)p1[s] * xv;
+        a2 += (double)p2[s] * xv;
+        a3 += (double)p3[s] * xv;
+      }
     }
     a0 = wave_sum(a0); a1 = wave_sum(a1); a2 = wave_sum(a2); a3 = wave_sum(a3);
     if (lane == 0) {
@@ -106,7 +128,7 @@ __global__ void k_face_build(ClassDev cd, MeshDev md, const double* __restrict__
     double v = 0.0;
     if (r < nf && c == nf + r) v = -1.0;
     if (r >= nf && c == r - nf) v = 1.0;
-    M[i] = v;
+    M[wtix(r, c, ldf)] = v;
   }
   __syncthreads();
   const int d = cd.dim;
@@ -125,7 +147,7 @@ __global__ void k_face_build(ClassDev cd, MeshDev md, const double* __restrict__
       for (int i = threadIdx.x; i < nst * nst; i += blockDim.x) {
         const int rr = i / nst, cc = i % nst;
         const int c = rr / T, t = rr % T, cp = cc / T, tp = cc % T;
-        M[(size_t)(c * nn + tid[t]) * ldf + cp * nn + tid[tp]] += abb[i];
+        M[wtix(c * nn + tid[t], cp * nn + tid[tp], ldf)] += abb[i];
       }
     }
   }
@@ -139,11 +161,11 @@ __global__ void __launch_bounds__(256) k_precond_apply(MeshDev md, const double*
   const long long off = md.face_off[F];
   for (int i = threadIdx.x; i < nf; i += blockDim.x) xs[i] = x[off + i];
   __syncthreads();
-  const double* Ai = FW + (size_t)F * face_stride + (size_t)nf * ldf + nf;
+  const double* Ai = FW + (size_t)F * face_stride;  // A^{-1} at (nf, nf) of the tiled block
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int r = wave; r < nf; r += 4) {
     double s = 0.0;
-    for (int c = lane; c < nf; c += 64) s += Ai[(size_t)r * ldf + c] * xs[c];
+    for (int c = lane; c < nf; c += 64) s += Ai[wtix(nf + r, nf + c, ldf)] * xs[c];
     s = wave_sum(s);
     if (lane == 0) y[off + r] = s;
   }
@@ -156,7 +178,7 @@ __global__ void k_cast_ahat(const double* __restrict__ W, long long macro_stride
     const long long macro = g / ((long long)nb * nb);
     const long long rc = g % ((long long)nb * nb);
     const int r = (int)(rc / nb), c = (int)(rc % nb);
-    out[g] = (float)W[macro * macro_stride + offs + (size_t)r * ld + c];
+    out[g] = (float)W[macro * macro_stride + wtix(offs + r, offs + c, ld)];
   }
 }
 
@@ -229,9 +251,10 @@ inline unsigned grid_for(long long n) { return (unsigned)std::max<long long>(1, 
 
 }  // namespace
 
-hipError_t launch_face_sum(HdgContext& c, const double* base, long long macro_stride, long long elem_stride, double* out) {
+hipError_t launch_face_sum(HdgContext& c, const double* base, long long macro_stride, long long elem_stride, double* out,
+                           long long tiled_rc) {
   hipLaunchKernelGGL(k_face_gather_sum, dim3(grid_for(c.md.n_glob)), dim3(256), 0, c.stream, c.cd, c.md, base,
-                     macro_stride, elem_stride, out);
+                     macro_stride, elem_stride, out, tiled_rc);
   return hipGetLastError();
 }
 
@@ -241,8 +264,9 @@ hipError_t launch_zero_ints(hipStream_t s, int* p, int n) {
 }
 
 hipError_t launch_bhat(HdgContext& c, double* bhat) {
-  const double* base = c.ws.Wm + (size_t)c.hc.n_u * c.ldw + (c.n_cols - 1);
-  return launch_face_sum(c, base, (long long)c.n_rows * c.ldw, c.ldw, bhat);
+  // b-hat^{T_i}: column n_cols - 1 of rows [n_u, n_u + n_b) of each tiled matrix
+  const long long rc = ((long long)c.hc.n_u << 32) | (long long)(c.n_cols - 1);
+  return launch_face_sum(c, c.ws.Wm, c.wstride, -(long long)c.ldw, bhat, rc);
 }
 
 hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec) {
@@ -250,21 +274,20 @@ hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec) {
   dim3 grid((nb + APPLY_ROWS - 1) / APPLY_ROWS, c.hm.n_macros);
   const size_t shm = (size_t)nb * sizeof(double);
   if (prec == 1 && c.have_a32) {
-    hipLaunchKernelGGL(k_apply_local<float>, grid, dim3(256), shm, c.stream, c.cd, c.md, c.ws.A32,
-                       (long long)nb * nb, (long long)nb, x, c.ws.ypart);
+    hipLaunchKernelGGL((k_apply_local<float, false>), grid, dim3(256), shm, c.stream, c.cd, c.md, c.ws.A32,
+                       (long long)nb * nb, (long long)nb, x, c.ws.ypart, 0);
   } else {
-    const double* Ab = c.ws.Wm + (size_t)c.hc.n_u * c.ldw + c.hc.n_u;
-    hipLaunchKernelGGL(k_apply_local<double>, grid, dim3(256), shm, c.stream, c.cd, c.md, Ab,
-                       (long long)c.n_rows * c.ldw, (long long)c.ldw, x, c.ws.ypart);
+    hipLaunchKernelGGL((k_apply_local<double, true>), grid, dim3(256), shm, c.stream, c.cd, c.md, c.ws.Wm,
+                       c.wstride, (long long)c.ldw, x, c.ws.ypart, c.hc.n_u);
   }
-  return launch_face_sum(c, c.ws.ypart, nb, 1, y);
+  return launch_face_sum(c, c.ws.ypart, nb, 1, y, 0);
 }
 
 hipError_t lu_eliminate(hipStream_t s, double* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
                         int n_cols, int* ipiv, int ipiv_stride, int* status, double* scratch);
 
 hipError_t launch_face_precond(HdgContext& c) {
-  const long long fs = (long long)2 * c.nf_max * c.ldf;
+  const long long fs = c.fstride;
   hipLaunchKernelGGL(k_face_build, dim3(c.hm.n_faces), dim3(256), 0, c.stream, c.cd, c.md, c.ws.SUB, c.sub_stride,
                      c.off_ABB, c.ws.FW, fs, c.ldf);
   hipError_t e = hipGetLastError();
@@ -294,7 +317,7 @@ hipError_t launch_face_precond(HdgContext& c) {
 }
 
 hipError_t launch_precond_apply(HdgContext& c, const double* x, double* y) {
-  const long long fs = (long long)2 * c.nf_max * c.ldf;
+  const long long fs = c.fstride;
   hipLaunchKernelGGL(k_precond_apply, dim3(c.hm.n_faces), dim3(256), (size_t)c.nf_max * sizeof(double), c.stream, c.md,
                      c.ws.FW, fs, c.ldf, x, y);
   return hipGetLastError();
@@ -303,8 +326,8 @@ hipError_t launch_precond_apply(HdgContext& c, const double* x, double* y) {
 hipError_t launch_cast_ahat(HdgContext& c) {
   const int nb = c.hc.n_b;
   const long long total = (long long)c.hm.n_macros * nb * nb;
-  hipLaunchKernelGGL(k_cast_ahat, dim3(grid_for(total)), dim3(256), 0, c.stream, c.ws.Wm, (long long)c.n_rows * c.ldw,
-                     (long long)c.ldw, (long long)c.hc.n_u * c.ldw + c.hc.n_u, nb, c.ws.A32, total);
+  hipLaunchKernelGGL(k_cast_ahat, dim3(grid_for(total)), dim3(256), 0, c.stream, c.ws.Wm, c.wstride,
+                     (long long)c.ldw, (long long)c.hc.n_u, nb, c.ws.A32, total);
   return hipGetLastError();
 }
 

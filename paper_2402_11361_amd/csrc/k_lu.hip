@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
     for (int i = 0; i < RPT; ++i) {
       const int r = c0 + tid + i * PANEL_THREADS;
 #pragma unroll
-      for (int cc = 0; cc < PW; ++cc) v[i][cc] = (r < n_piv && cc < pw) ? W[(size_t)r * ld + c0 + cc] : 0.0;
+      for (int cc = 0; cc < PW; ++cc) v[i][cc] = (r < n_piv && cc < pw) ? W[wtix(r, c0 + cc, ld)] : 0.0;
     }
     for (int cc = 0; cc < pw; ++cc) {
       {
@@ -141,9 +141,9 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
         for (int k = tid; k < j0 + jb - lcol0; k += PANEL_THREADS) {
           const int cidx = lcol0 + k;  // L columns of a previous block too (lcol0 < j0)
           if (cidx >= c0 && cidx < c0 + pw) continue;
-          double t = W[(size_t)col * ld + cidx];
-          W[(size_t)col * ld + cidx] = W[(size_t)prow * ld + cidx];
-          W[(size_t)prow * ld + cidx] = t;
+          double t = W[wtix(col, cidx, ld)];
+          W[wtix(col, cidx, ld)] = W[wtix(prow, cidx, ld)];
+          W[wtix(prow, cidx, ld)] = t;
         }
       }
       // broadcast the pivot row
@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
       if (r < n_piv) {
 #pragma unroll
         for (int cc = 0; cc < PW; ++cc)
-          if (cc < pw) W[(size_t)r * ld + c0 + cc] = v[i][cc];
+          if (cc < pw) W[wtix(r, c0 + cc, ld)] = v[i][cc];
       }
     }
     // right-looking update of the rest of the block: columns [c0 + pw, j0 + jb)
@@ -192,15 +192,15 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
       // U rows of the sub-panel: L_sub^{-1} A[c0:c0+pw, rest]  (unit lower, sequential rows)
       for (int k = tid; k < nrest; k += PANEL_THREADS) {
         for (int i = 0; i < pw; ++i) {
-          double s = W[(size_t)(c0 + i) * ld + rest0 + k];
-          for (int m = 0; m < i; ++m) s -= W[(size_t)(c0 + i) * ld + c0 + m] * s_U[m * NB + k];
+          double s = W[wtix((c0 + i), rest0 + k, ld)];
+          for (int m = 0; m < i; ++m) s -= W[wtix((c0 + i), c0 + m, ld)] * s_U[m * NB + k];
           s_U[i * NB + k] = s;
         }
       }
       __syncthreads();
       for (int k = tid; k < pw * nrest; k += PANEL_THREADS) {
         const int i = k / nrest, cidx = k % nrest;
-        W[(size_t)(c0 + i) * ld + rest0 + cidx] = s_U[i * NB + cidx];
+        W[wtix((c0 + i), rest0 + cidx, ld)] = s_U[i * NB + cidx];
       }
       // rows below the sub-panel: A[r, rest] -= L[r, c0:c0+pw] U
 #pragma unroll
@@ -209,11 +209,11 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
         if (r >= c0 + pw && r < n_piv) {
 #pragma unroll 4
           for (int cidx = 0; cidx < nrest; ++cidx) {
-            double s = W[(size_t)r * ld + rest0 + cidx];
+            double s = W[wtix(r, rest0 + cidx, ld)];
 #pragma unroll
             for (int m = 0; m < PW; ++m)
               if (m < pw) s -= v[i][m] * s_U[m * NB + cidx];
-            W[(size_t)r * ld + rest0 + cidx] = s;
+            W[wtix(r, rest0 + cidx, ld)] = s;
           }
         }
       }
@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(64) k_uinv(LuArgs a, int j0, int jb, double* _
   for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) {
     const int r = i / NB, c = i % NB;
     double v = (r == c) ? 1.0 : 0.0;
-    if (r < jb && c < jb) v = W[(size_t)(j0 + r) * ld + j0 + c];
+    if (r < jb && c < jb) v = W[wtix((j0 + r), j0 + c, ld)];
     sU[i] = v;
   }
   __syncthreads();
@@ -300,20 +300,20 @@ __global__ void __launch_bounds__(256) k_u12(LuArgs a, int j0, int jb, int strip
 #pragma unroll
   for (int j = 0; j < 2 * NB / 4; ++j) {
     const int p = (tid >> 6) + 4 * j;
-    gv[j] = (p < nt && cok) ? W[(size_t)s_src[p] * ld + cs + c] : 0.0;
+    gv[j] = (p < nt && cok) ? W[wtix(s_src[p], cs + c, ld)] : 0.0;
   }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < 2 * NB / 4; ++j) {
     const int p = (tid >> 6) + 4 * j;
     if (p < nt && cok) {
-      if (p >= jb) W[(size_t)s_dst[p] * ld + cs + c] = gv[j];  // rows outside the block
+      if (p >= jb) W[wtix(s_dst[p], cs + c, ld)] = gv[j];  // rows outside the block
       else sU[p * NC + c] = gv[j];                             // block rows: to LDS for the solve
     }
   }
   for (int i = tid; i < NB * NB; i += 256) {
     const int r = i / NB, cc = i % NB;
-    sL[i] = (r < jb && cc < jb) ? W[(size_t)(j0 + r) * ld + j0 + cc] : 0.0;
+    sL[i] = (r < jb && cc < jb) ? W[wtix((j0 + r), j0 + cc, ld)] : 0.0;
   }
   for (int i = tid; i < NB * NC; i += 256) {
     const int r = i / NC, cc = i % NC;
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(256) k_u12(LuArgs a, int j0, int jb, int strip
   }
   for (int i = tid; i < jb * NC; i += 256) {
     const int r = i / NC, c = i % NC;
-    if (cs + c >= live0 && cs + c < col_end) W[(size_t)(j0 + r) * ld + cs + c] = sU[i];
+    if (cs + c >= live0 && cs + c < col_end) W[wtix((j0 + r), cs + c, ld)] = sU[i];
   }
 }
 
@@ -380,31 +380,31 @@ __global__ void __launch_bounds__(256) k_u12b2(LuArgs a, int j0, int jb2, int st
 #pragma unroll
     for (int j = 0; j < 2 * NB / 4; ++j) {
       const int p = (tid >> 6) + 4 * j;
-      gv[j] = (p < nt && cok) ? W[(size_t)s_src[p] * ld + cs + c] : 0.0;
+      gv[j] = (p < nt && cok) ? W[wtix(s_src[p], cs + c, ld)] : 0.0;
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 2 * NB / 4; ++j) {
       const int p = (tid >> 6) + 4 * j;
-      if (p < nt && cok) W[(size_t)s_dst[p] * ld + cs + c] = gv[j];
+      if (p < nt && cok) W[wtix(s_dst[p], cs + c, ld)] = gv[j];
     }
     __syncthreads();
   }
   for (int i = tid; i < NB * NB; i += 256) {
     const int r = i / NB, cc = i % NB;
-    sL[i] = W[(size_t)(j0 + r) * ld + j0 + cc];
+    sL[i] = W[wtix((j0 + r), j0 + cc, ld)];
   }
   for (int i = tid; i < NB * NC; i += 256) {
     const int r = i / NC, cc = i % NC;
     const bool ok = cs + cc >= live0 && cs + cc < ld;
-    sU1[i] = ok ? W[(size_t)(j0 + r) * ld + cs + cc] : 0.0;
-    sU2[i] = (ok && r < jb2) ? W[(size_t)(j0 + NB + r) * ld + cs + cc] : 0.0;
+    sU1[i] = ok ? W[wtix((j0 + r), cs + cc, ld)] : 0.0;
+    sU2[i] = (ok && r < jb2) ? W[wtix((j0 + NB + r), cs + cc, ld)] : 0.0;
   }
   __syncthreads();
   trsm_lds(sL, sU1, NB, sP, tid);
   for (int i = tid; i < NB * NB; i += 256) {
     const int r = i / NB, cc = i % NB;
-    sL[i] = (r < jb2) ? W[(size_t)(j0 + NB + r) * ld + j0 + cc] : 0.0;
+    sL[i] = (r < jb2) ? W[wtix((j0 + NB + r), j0 + cc, ld)] : 0.0;
   }
   __syncthreads();
   {
@@ -418,15 +418,15 @@ __global__ void __launch_bounds__(256) k_u12b2(LuArgs a, int j0, int jb2, int st
   __syncthreads();
   for (int i = tid; i < NB * NB; i += 256) {
     const int r = i / NB, cc = i % NB;
-    sL[i] = (r < jb2 && cc < jb2) ? W[(size_t)(j0 + NB + r) * ld + j0 + NB + cc] : 0.0;
+    sL[i] = (r < jb2 && cc < jb2) ? W[wtix((j0 + NB + r), j0 + NB + cc, ld)] : 0.0;
   }
   __syncthreads();
   trsm_lds(sL, sU2, jb2, sP, tid);
   for (int i = tid; i < NB * NC; i += 256) {
     const int r = i / NC, cc = i % NC;
     if (cs + cc >= live0 && cs + cc < ld) {
-      W[(size_t)(j0 + r) * ld + cs + cc] = sU1[i];
-      if (r < jb2) W[(size_t)(j0 + NB + r) * ld + cs + cc] = sU2[i];
+      W[wtix((j0 + r), cs + cc, ld)] = sU1[i];
+      if (r < jb2) W[wtix((j0 + NB + r), cs + cc, ld)] = sU2[i];
     }
   }
 }
@@ -444,7 +444,8 @@ struct GemmArgs {
   const double* B;
   long long b_mat_stride;
   int ldb;
-  int b_col_follow;  // 1: B columns are the strip columns (B rows of W); 0: fixed K x 64 B
+  int b_col_follow;  // 1: B = rows [b_row0, b_row0 + K) of the strip in W itself; 0: plain K x 64 B
+  int b_row0;
   int ak0, K, cs0, c_lo, c_hi, r_lo, r_hi;
   double alpha;
   int beta;
@@ -463,16 +464,22 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   __shared__ double sB[KB * NC];
   for (int i = tid; i < KB * NC; i += 256) {
     const int k = i / NC, c = i % NC;
-    sB[i] = (k < g.K && cs + c >= g.c_lo && cs + c < g.c_hi) ? B[(size_t)k * g.ldb + (g.b_col_follow ? cs : 0) + c] : 0.0;
+    sB[i] = (k < g.K && cs + c >= g.c_lo && cs + c < g.c_hi) ? (g.b_col_follow ? W[wtix(g.b_row0 + k, cs + c, ld)] : B[(size_t)k * g.ldb + c]) : 0.0;
   }
   __syncthreads();
   const int tile0 = blockIdx.y * g.tiles_per_wg;
   auto load_a = [&](int r0, double* af) {
     const int ra = r0 + col;
-    const bool rok = ra < g.r_hi;
-    const double* ap = W + (size_t)ra * ld + g.ak0 + KS * grp;
+    const int kb = KS * grp;
+    // the KS consecutive columns of a lane group lie inside one 64-column tile
+    const double* ap = W + wtix(ra, g.ak0 + kb, ld);
+    if (ra < g.r_hi && kb + KS <= g.K) {  // fast path: unmasked contiguous loads
 #pragma unroll
-    for (int s = 0; s < KS; ++s) af[s] = (rok && KS * grp + s < g.K) ? g.alpha * ap[s] : 0.0;
+      for (int s = 0; s < KS; ++s) af[s] = g.alpha * ap[s];
+    } else {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) af[s] = (ra < g.r_hi && kb + s < g.K) ? g.alpha * ap[s] : 0.0;
+    }
   };
   auto load_c = [&](int r0, dbl4* acc) {
 #pragma unroll
@@ -482,22 +489,17 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = r0 + 4 * i + grp;  // f64 16x16x4: D[4 reg + lane/16][lane%16]
-        acc[ct][i] = (g.beta && r < g.r_hi && cok) ? W[(size_t)r * ld + cc] : 0.0;
+        acc[ct][i] = (g.beta && r < g.r_hi && cok) ? W[wtix(r, cc, ld)] : 0.0;
       }
     }
   };
-  double af[KS], af2[KS];
-  dbl4 acc[NC / 16], acc2[NC / 16];
-  int t = wave;
-  int r0 = g.r_lo + (tile0 + t) * 16;
-  if (t >= g.tiles_per_wg || r0 >= g.r_hi) return;
-  load_a(r0, af);
-  load_c(r0, acc);
-  for (; t < g.tiles_per_wg; t += 4) {
-    r0 = g.r_lo + (tile0 + t) * 16;
-    const int rn = r0 + 64;
-    const bool more = (t + 4 < g.tiles_per_wg) && rn < g.r_hi;
-    if (more) { load_a(rn, af2); load_c(rn, acc2); }
+  double af[KS];
+  dbl4 acc[NC / 16];
+  for (int t = wave; t < g.tiles_per_wg; t += 4) {
+    const int r0 = g.r_lo + (tile0 + t) * 16;
+    if (r0 >= g.r_hi) break;
+    load_a(r0, af);
+    load_c(r0, acc);
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
 #pragma unroll
@@ -513,14 +515,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = r0 + 4 * i + grp;
-        if (r < g.r_hi && cok) W[(size_t)r * ld + cc] = acc[ct][i];
+        if (r < g.r_hi && cok) W[wtix(r, cc, ld)] = acc[ct][i];
       }
     }
-    if (!more) break;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) af[s] = af2[s];
-#pragma unroll
-    for (int ct = 0; ct < NC / 16; ++ct) acc[ct] = acc2[ct];
   }
 }
 
@@ -545,14 +542,14 @@ hipError_t lu_eliminate(hipStream_t s, double* W, int batch, long long mat_strid
   auto drows = [&](int j0, int jb) {  // L of the non-pivot rows: A_D,block U11^{-1}
     if (n_rows <= n_piv) return;
     hipLaunchKernelGGL(k_uinv, dim3(batch), dim3(NB), 0, s, a, j0, jb, scratch);
-    GemmArgs g{W, mat_stride, ld, scratch, (long long)NB * NB, NB, 0, j0, jb, j0, j0, j0 + jb, n_piv, n_rows, 1.0, 0, TPW};
+    GemmArgs g{W, mat_stride, ld, scratch, (long long)NB * NB, NB, 0, 0, j0, jb, j0, j0, j0 + jb, n_piv, n_rows, 1.0, 0, TPW};
     const int ntile = (n_rows - n_piv + 15) / 16;
     hipLaunchKernelGGL(k_gemm<64>, dim3(1, (ntile + TPW - 1) / TPW, batch), dim3(256), 0, s, g);
   };
   // A22 -= L21 U12 for the strips [strip0, ...) with U12 in rows [j0, j0 + K) of W
   auto update = [&](int j0, int K, int live0, int strip0, int nstrip, int col_end) {
     if (n_rows <= live0 || nstrip <= 0) return;
-    GemmArgs g{W, mat_stride, ld, W + (size_t)j0 * ld, mat_stride, ld, 1, j0, K, strip0, live0, col_end, live0, n_rows,
+    GemmArgs g{W, mat_stride, ld, W, mat_stride, ld, 1, j0, j0, K, strip0, live0, col_end, live0, n_rows,
                -1.0, 1, TPW};
     const int ntile = (n_rows - live0 + 15) / 16;
     dim3 grid(nstrip, (ntile + TPW - 1) / TPW, batch);
@@ -592,6 +589,6 @@ hipError_t lu_eliminate(hipStream_t s, double* W, int batch, long long mat_strid
 }
 
 hipError_t launch_lu(HdgContext& c) {
-  return lu_eliminate(c.stream, c.ws.Wm, c.hm.n_macros, (long long)c.n_rows * c.ldw, c.ldw, c.hc.n_u, c.n_rows,
+  return lu_eliminate(c.stream, c.ws.Wm, c.hm.n_macros, c.wstride, c.ldw, c.hc.n_u, c.n_rows,
                       c.n_cols, c.ws.ipiv, c.hc.n_u, reinterpret_cast<int*>(c.ws.small), c.ws.Uinv);
 }
