@@ -58,3 +58,21 @@ def newton_solve(S, q, u, uhat, w=None, dt=np.inf, dii=1.0, ptc=False, tau_init=
             dtau = min(dtau * rU_prev / max(rU, 1e-300), tau_max)
             rU_prev = rU
     return q, u, uhat, dict(res_hist=hist, its=len(hist) - 1)
+
+
+def dirk_step(S, q, u, uhat, dt, newton_kw=None):
+    """One step of the DIRK(3,3) scheme (eq. C242 stages, eq. C241 update) with
+    a Newton solve per stage; returns (q, u, uhat, infos)."""
+    from . import dirk
+    A, b, c = dirk.dirk33()
+    Ai = np.linalg.inv(A)
+    u_n = u.copy()
+    stages, infos = [], []
+    kw = dict(newton_kw or {})
+    for i in range(3):
+        w = dirk.stage_history(Ai, i, u_n, stages)
+        q, u, uhat, info = newton_solve(S, q, u, uhat, w=w, dt=dt, dii=Ai[i, i], **kw)
+        stages.append(u.copy())
+        infos.append(info)
+    u = dirk.update(Ai, b, u_n, stages)
+    return q, u, uhat, infos
