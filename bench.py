@@ -1,6 +1,6 @@
-"""Benchmark: one Newton step of a DIRK stage of the macro-element HDG method
-on one MI355X (linearise -> second-layer condensation -> FGMRES to 1e-8 ->
-local recovery -> update), on the Taylor-Green workload: 24^3 periodic hexes
+"""Benchmark: one DIRK stage of the macro-element HDG method solved by Newton's
+method on one MI355X (each Newton step: linearise -> second-layer condensation
+-> FGMRES to 1e-8 -> local recovery -> update), on the Taylor-Green workload: 24^3 periodic hexes
 on [-pi, pi]^3, macros of 3^3 elements (512 macros), p = 2, Mach 0.1,
 Re 1600, seeded 1e-4 noise, first stage of Alexander's DIRK(3,3) with
 dt = CFL h / (V0 (p+1)), CFL = 1.
@@ -24,7 +24,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DIRK-stage solve time to FGMRES tol 1e-8 + condense TFLOP/s, plain vs mixed/learned"
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+
+# HBM bytes per hdg_condense call of the FP64 path on this workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by what the counters
+# read for a 1 GiB device copy in the same run (profiles/stage_solve_tgv24_m3_p2_fp64.md),
+# valid only while the kernel sources hash to `sha`.
+CONDENSE_TRAFFIC = {"sha": "730ce05da64df8bb", "bytes": 1117.4e9}
+CONDENSE_SOURCES = ("k_form.hip", "k_lu.hip", "k_krylov.hip", "internal.h")
+
+
+def sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in CONDENSE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2402_11361_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def workload_arrays(ctx, cfg, seed=0):
@@ -42,23 +59,42 @@ def workload_arrays(ctx, cfg, seed=0):
     return u, q, uh
 
 
-def condense_flops(n_u, n_b):
-    """Algorithmic flops of the elimination of one augmented macro matrix:
-    LU of S (2/3 n_u^3) + S^{-1} C (2 n_u^2 n_b) + D Y (2 n_b^2 n_u)."""
-    return (2.0 / 3.0) * n_u ** 3 + 2.0 * n_u ** 2 * n_b + 2.0 * n_b ** 2 * n_u
+def condense_flops(cfg, n_u, n_b):
+    """Algorithmic flops of the condensation of one macro: LU of S (2/3 n_u^3),
+    S^{-1} C (2 n_u^2 n_b), D Y (2 n_b^2 n_u), plus the formation of S
+    (F_S = 2 d n_s^2 (p+1)^{2d} N m^d) and of the coupling blocks
+    (F_C = 4 d n_s^2 (p+1)^{2d} (n_b / n_s) m^d) from element-blocked products."""
+    d, p, m = cfg["dim"], cfg["p"], cfg["m"]
+    ns = d + 2
+    N = n_u // ns
+    F_S = 2.0 * d * ns ** 2 * (p + 1) ** (2 * d) * N * m ** d
+    F_C = 4.0 * d * ns ** 2 * (p + 1) ** (2 * d) * (n_b / ns) * m ** d
+    return (2.0 / 3.0) * n_u ** 3 + 2.0 * n_u ** 2 * n_b + 2.0 * n_b ** 2 * n_u + F_S + F_C
 
 
-def cpu_baseline(cfg, n_sample=2):
-    """Oracle leg: complex-step linearisation and route-B condensation of
-    n_sample macros of the same workload, extrapolated to all macros (the
-    global direct solve is not included)."""
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
+def blas_threads():
+    """Threads the oracle's LAPACK/BLAS calls use (NumPy's BLAS pool)."""
+    try:
+        from threadpoolctl import threadpool_info
+        n = [i["num_threads"] for i in threadpool_info() if i.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(cfg, newton_its, n_sample=2):
+    """Oracle leg: complex-step linearisation, route-B condensation and local
+    recovery of n_sample macros of the same workload, scaled to all macros and
+    to the Newton iterations the GPU took for one stage (the oracle's global
+    solve is not included, so this under-counts the CPU time)."""
     from oracle.mesh import box_mesh
     from oracle.physics import Phys
     from oracle.system import System
     from oracle import dirk
     from paper_2402_11361_amd import inputs
-    M = box_mesh(3, cfg["n_elem"], cfg["m"], cfg["p"], lo=cfg["lo"], hi=cfg["hi"], periodic=True)
+    M = box_mesh(cfg["dim"], cfg["n_elem"], cfg["m"], cfg["p"], lo=cfg["lo"], hi=cfg["hi"], periodic=cfg["periodic"])
     S = System(M, Phys(Re=cfg["Re"], Mach=cfg["mach"]))
     mc = [M.macro_node_coords(i) for i in range(M.n_macros)]
     fc = [M.face_node_coords(f) for f in range(M.n_faces)]
@@ -67,23 +103,31 @@ def cpu_baseline(cfg, n_sample=2):
     dii = 1.0 / A[0, 0]
     dt = inputs.cfl_dt(cfg)
     w = -dii * u
+    sample = list(range(n_sample))
     t0 = time.perf_counter()
-    lin = S.linearize(q, u, uh, w=w, dt=dt, dii=dii, macros=list(range(n_sample)))
+    lin = S.linearize(q, u, uh, w=w, dt=dt, dii=dii, macros=sample)
     t1 = time.perf_counter()
-    S.condense(lin, "B")
+    con = S.condense(lin, "B")
     t2 = time.perf_counter()
-    per_macro_ms = 1e3 * (t2 - t0) / n_sample
-    return dict(value=per_macro_ms * M.n_macros, unit="ms/Newton-step (linearise+condense, extrapolated)",
-                cores=len(os.sched_getaffinity(0)), kind="oracle",
-                sample=f"{n_sample} of {M.n_macros} macros: complex-step linearisation "
+    x = np.random.default_rng(5).uniform(-1, 1, M.n_glob)
+    S.backsolve(lin, con, x)
+    t3 = time.perf_counter()
+    per_macro = (t3 - t0) / n_sample
+    scale = M.n_macros * max(newton_its, 1)
+    return dict(value=round(1e3 * per_macro * scale, 1),
+                unit="ms/DIRK-stage (local work only, extrapolated)",
+                cores=blas_threads(), kind="oracle",
+                sample=f"{n_sample} of {M.n_macros} macros, one Newton step: complex-step linearisation "
                        f"{1e3 * (t1 - t0) / n_sample:.0f} ms/macro + LAPACK route-B condensation "
-                       f"{1e3 * (t2 - t1) / n_sample:.0f} ms/macro, x{M.n_macros // n_sample}; global solve excluded")
+                       f"{1e3 * (t2 - t1) / n_sample:.0f} ms/macro + recovery "
+                       f"{1e3 * (t3 - t2) / n_sample:.0f} ms/macro, scaled x{M.n_macros} macros "
+                       f"x{max(newton_its, 1)} Newton steps; oracle global solve excluded")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -95,6 +139,7 @@ def main():
         sys.exit(2)
     import torch
     from paper_2402_11361_amd import inputs
+    from paper_2402_11361_amd.driver import StageDriver, alexander_dirk33
     from paper_2402_11361_amd.hdg import Context, mesh_spec_box
 
     cfg = dict(inputs.CONFIGS[args.config])
@@ -104,17 +149,12 @@ def main():
     ctx.bind_workspace()
     u0, q0, uh0 = workload_arrays(ctx, cfg)
     dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
-    u_n = dev(u0)
     q_init, u_init, uh_init = dev(q0), dev(u0), dev(uh0)
-    alpha = 0.435866521508459
-    dii = 1.0 / alpha
+    A, _, _ = alexander_dirk33()
+    dii = 1.0 / A[0, 0]
     dt = inputs.cfl_dt(cfg)
-    w = -dii * u_n
+    w = -dii * u_init
     q, u, uh = q_init.clone(), u_init.clone(), uh_init.clone()
-    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
-    x = torch.zeros_like(bhat)
-    dq = torch.zeros_like(q)
-    du = torch.zeros_like(u)
     rtol = cfg["rtol"]
 
     def ev():
@@ -122,37 +162,46 @@ def main():
         e.record(stream)
         return e
 
-    def newton_step(record):
+    # plain copy of 1 GiB: the reference for scaling HBM byte counters
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0 = ev(); dst.copy_(src); c1 = ev()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * src.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+
+    marks = []
+    drv = StageDriver(ctx, rtol=rtol, restart=30, inner_its=5, max_outer=300,
+                      mark=lambda phase: marks.append((phase, ev())))
+
+    def stage():
         q.copy_(q_init); u.copy_(u_init); uh.copy_(uh_init)
-        e0 = ev()
-        nrm = ctx.linearize_stage(q, u, uh, w, dt, dii)
-        e1 = ev()
-        ctx.condense(bhat)
-        e2 = ev()
-        x.zero_()
-        info = ctx.fgmres_solve(bhat, x, rtol=rtol, restart=30, max_outer=300, inner_its=5)
-        e3 = ev()
-        ctx.local_backsolve(x, dq, du)
-        ctx.axpy(1.0, dq, q); ctx.axpy(1.0, du, u); ctx.axpy(1.0, x, uh)
-        e4 = ev()
-        if record is not None:
-            record.append((e0, e1, e2, e3, e4, info, nrm))
+        return drv.solve_stage(q, u, uh, w, dt, dii)
 
     for _ in range(args.warmup):
-        newton_step(None)
+        stage()
     torch.cuda.synchronize()
-    rec = []
+    marks.clear()
+    infos = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        newton_step(rec)
+        infos.append(stage())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    phases = np.array([[a.elapsed_time(b) for a, b in ((r[0], r[1]), (r[1], r[2]), (r[2], r[3]), (r[3], r[4]))]
-                       for r in rec])
     ms_step = 1e3 * wall / args.steps
-    lin_ms, cond_ms, kry_ms, bs_ms = phases.mean(axis=0)
-    its = [r[5]["outer_its"] for r in rec]
-    inner = [r[5]["inner_its"] for r in rec]
+    phase_ms = {}
+    cond_calls = []
+    for (ph, e), (_, e2) in zip(marks[:-1], marks[1:]):
+        if ph == "end":
+            continue
+        t = e.elapsed_time(e2)
+        phase_ms[ph] = phase_ms.get(ph, 0.0) + t / args.steps
+        if ph == "condense":
+            cond_calls.append(t)
+    newton_its = infos[-1]["newton_its"]
+    outer = [[k["outer_its"] for k in inf["krylov"]] for inf in infos]
+    inner = [[k["inner_its"] for k in inf["krylov"]] for inf in infos]
     # global apply on its own (HBM-bound GEMV over the condensed blocks)
     xa = torch.randn(ctx.n_glob, dtype=torch.float64, device="cuda")
     ya = torch.zeros_like(xa)
@@ -168,27 +217,33 @@ def main():
     nb, nu, nm = ctx.n_b_macro, ctx.n_u_macro, ctx.n_macros
     apply_bytes = 8.0 * nm * nb * nb + 8.0 * nm * nb + 8.0 * nm * nb + 8.0 * ctx.n_glob
     apply_gbs = apply_bytes / (apply_ms * 1e-3) / 1e9
-    flops = condense_flops(nu, nb) * nm
+    flops = condense_flops(cfg, nu, nb) * nm
+    cond_ms = float(np.mean(cond_calls))
     cond_tflops = flops / (cond_ms * 1e-3) / 1e12
-    # dominant kernel: the batched elimination inside hdg_condense (MFMA-bound)
+    # dominant work: hdg_condense, one launch sequence per Newton step (MFMA-bound)
+    traffic = CONDENSE_TRAFFIC["bytes"] if sources_sha() == CONDENSE_TRAFFIC["sha"] else None
     roofline = dict(bound="mfma", achieved=round(cond_tflops, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                    frac=round(cond_tflops / PEAK_FP64_TFLOPS, 4), traffic=None,
-                    kernel="hdg_condense (form + batched FP64 LU/TRSM/GEMM elimination)",
-                    flops_per_launch=flops, ms_per_launch=round(float(cond_ms), 3))
-    out = dict(metric=METRIC, value=round(ms_step, 3), unit="ms/Newton-step", n_gpus=1, steps=args.steps,
+                    frac=round(cond_tflops / PEAK_FP64_TFLOPS, 4), traffic=traffic,
+                    kernel="hdg_condense: k_form + batched FP64 elimination (k_panel, k_uinv, k_u12, k_u12b2, "
+                           "k_gemm) + face-preconditioner factorisation",
+                    flops_per_launch=flops, ms_per_launch=round(cond_ms, 3), launches=len(cond_calls))
+    out = dict(metric=METRIC, value=round(ms_step, 3), unit="ms/DIRK-stage", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_step, 3), higher_is_better=False, scaling="weak",
                vs_baseline=None, dtype="f64", data="synthetic",
-               config=dict(workload=f"{args.config}: TGV 24^3 periodic hex, 3^3-element macros (512), p=2, "
-                                    f"Mach 0.1, Re 1600, DIRK(3,3) stage 1, FGMRES rtol {rtol}",
-                           n_macros=nm, n_u_macro=nu, n_b_macro=nb, n_glob=ctx.n_glob),
-               phases_ms=dict(linearize=round(float(lin_ms), 3), condense=round(float(cond_ms), 3),
-                              fgmres=round(float(kry_ms), 3), backsolve_update=round(float(bs_ms), 3)),
-               fgmres=dict(outer_its=its, inner_its=inner, rel_res=[r[5]["res"] / r[5]["res0"] for r in rec]),
-               condense_tflops=round(cond_tflops, 3), apply_ms=round(apply_ms, 4), apply_gbs=round(apply_gbs, 1),
-               apply_frac_hbm=round(apply_gbs / PEAK_HBM_GBS, 4), residual_norms=[float(v) for v in rec[0][6]],
+               config=dict(workload=f"{args.config}: Taylor-Green 24^3 periodic hexes on [-pi,pi]^3, 3^3-element "
+                                    f"macros (512), p=2, Mach 0.1, Re 1600, 1e-4 seeded noise; DIRK(3,3) stage 1 "
+                                    f"solved by Newton to max(1e-10, 1e-8 |R0|), FGMRES(30) rtol {rtol} with "
+                                    f"5 inner GMRES steps",
+                           n_macros=nm, n_u_macro=nu, n_b_macro=nb, n_glob=ctx.n_glob, variant="plain FP64"),
+               phases_ms={k: round(v, 3) for k, v in phase_ms.items()},
+               newton_its=newton_its, newton_res=infos[-1]["res_hist"],
+               fgmres=dict(outer_its=outer, inner_its=inner),
+               condense_tflops=round(cond_tflops, 3), condense_ms=round(cond_ms, 3),
+               apply_ms=round(apply_ms, 4), apply_gbs=round(apply_gbs, 1),
+               apply_frac_hbm=round(apply_gbs / PEAK_HBM_GBS, 4), copy_gbs=round(copy_gbs, 1),
                roofline=roofline)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg)
+        out["cpu_baseline"] = cpu_baseline(cfg, newton_its)
     print(json.dumps(out), flush=True)
 
 

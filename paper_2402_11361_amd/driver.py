@@ -40,9 +40,12 @@ class StageDriver:
     """Newton solves of DIRK stages on one library context."""
 
     def __init__(self, ctx, rtol=1e-8, restart=30, inner_its=5, max_outer=300, newton_abs=1e-10, newton_rel=1e-8,
-                 max_newton=20, inner_prec=HDG_FP64, condense_prec=HDG_FP64):
+                 max_newton=20, inner_prec=HDG_FP64, condense_prec=HDG_FP64, mark=None):
         import torch
         self.ctx = ctx
+        # optional callback mark(phase) at phase boundaries ("linearize", "condense",
+        # "fgmres", "backsolve"), e.g. to record stream events
+        self.mark = mark if mark is not None else (lambda phase: None)
         self.t = torch
         self.kry = dict(rtol=rtol, restart=restart, inner_its=inner_its, max_outer=max_outer, inner_prec=inner_prec)
         self.newton_abs, self.newton_rel, self.max_newton = newton_abs, newton_rel, max_newton
@@ -62,7 +65,9 @@ class StageDriver:
         hist, krylov = [], []
         rU_prev = None
         r0 = None
+        mark = self.mark
         for it in range(self.max_newton + 1):
+            mark("linearize")
             nrm = ctx.linearize_stage(q, u, uh, w, dt, dii, dtau)
             rn = float(np.sqrt(np.sum(nrm ** 2)))
             hist.append(rn)
@@ -74,13 +79,17 @@ class StageDriver:
             rU_prev = nrm[1]
             if rn <= max(self.newton_abs, self.newton_rel * r0) or it == self.max_newton:
                 break
+            mark("condense")
             ctx.condense(self.bhat, self.condense_prec)
+            mark("fgmres")
             self.x.zero_()
             krylov.append(ctx.fgmres_solve(self.bhat, self.x, **self.kry))
+            mark("backsolve")
             ctx.local_backsolve(self.x, self.dq, self.du)
             ctx.axpy(1.0, self.dq, q)
             ctx.axpy(1.0, self.du, u)
             ctx.axpy(1.0, self.x, uh)
+        mark("end")
         return dict(newton_its=len(hist) - 1, res_hist=hist, krylov=krylov)
 
     def step(self, q, u, uh, dt):
