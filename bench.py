@@ -132,6 +132,7 @@ def main():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--applies", type=int, default=20)
+    ap.add_argument("--plain-only", action="store_true", help="time only the plain FP64 variant")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
@@ -140,7 +141,7 @@ def main():
     import torch
     from paper_2402_11361_amd import inputs
     from paper_2402_11361_amd.driver import StageDriver, alexander_dirk33
-    from paper_2402_11361_amd.hdg import Context, mesh_spec_box
+    from paper_2402_11361_amd.hdg import HDG_FP32, HDG_FP64, Context, mesh_spec_box
 
     cfg = dict(inputs.CONFIGS[args.config])
     spec = mesh_spec_box(cfg["dim"], cfg["n_elem"], cfg["m"], cfg["p"], cfg["lo"], cfg["hi"], cfg["periodic"])
@@ -171,53 +172,81 @@ def main():
     copy_gbs = 2.0 * src.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
     del src, dst
 
-    marks = []
-    drv = StageDriver(ctx, rtol=rtol, restart=30, inner_its=5, max_outer=300,
-                      mark=lambda phase: marks.append((phase, ev())))
+    def run_variant(cond_prec, inner_prec, steps, warmup):
+        """Warm-up stages, then `steps` timed stage solves from the same state."""
+        marks = []
+        drv = StageDriver(ctx, rtol=rtol, restart=30, inner_its=5, max_outer=300, condense_prec=cond_prec,
+                          inner_prec=inner_prec, mark=lambda phase: marks.append((phase, ev())))
 
-    def stage():
-        q.copy_(q_init); u.copy_(u_init); uh.copy_(uh_init)
-        return drv.solve_stage(q, u, uh, w, dt, dii)
+        def stage():
+            q.copy_(q_init); u.copy_(u_init); uh.copy_(uh_init)
+            return drv.solve_stage(q, u, uh, w, dt, dii)
 
-    for _ in range(args.warmup):
-        stage()
-    torch.cuda.synchronize()
-    marks.clear()
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        infos.append(stage())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = 1e3 * wall / args.steps
-    phase_ms = {}
-    cond_calls = []
-    for (ph, e), (_, e2) in zip(marks[:-1], marks[1:]):
-        if ph == "end":
-            continue
-        t = e.elapsed_time(e2)
-        phase_ms[ph] = phase_ms.get(ph, 0.0) + t / args.steps
-        if ph == "condense":
-            cond_calls.append(t)
-    newton_its = infos[-1]["newton_its"]
-    outer = [[k["outer_its"] for k in inf["krylov"]] for inf in infos]
-    inner = [[k["inner_its"] for k in inf["krylov"]] for inf in infos]
-    # global apply on its own (HBM-bound GEMV over the condensed blocks)
-    xa = torch.randn(ctx.n_glob, dtype=torch.float64, device="cuda")
-    ya = torch.zeros_like(xa)
-    for _ in range(3):
-        ctx.apply_global(xa, ya)
-    torch.cuda.synchronize()
-    ea = ev()
-    for _ in range(args.applies):
-        ctx.apply_global(xa, ya)
-    eb = ev()
-    torch.cuda.synchronize()
-    apply_ms = ea.elapsed_time(eb) / args.applies
+        for _ in range(warmup):
+            stage()
+        torch.cuda.synchronize()
+        marks.clear()
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            infos.append(stage())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        phase_ms, cond_calls = {}, []
+        for (ph, e), (_, e2) in zip(marks[:-1], marks[1:]):
+            if ph == "end":
+                continue
+            t = e.elapsed_time(e2)
+            phase_ms[ph] = phase_ms.get(ph, 0.0) + t / steps
+            if ph == "condense":
+                cond_calls.append(t)
+        return dict(ms_per_stage=1e3 * wall / steps, phase_ms=phase_ms, cond_calls=cond_calls,
+                    newton_its=infos[-1]["newton_its"], newton_res=infos[-1]["res_hist"],
+                    outer=[[k["outer_its"] for k in inf["krylov"]] for inf in infos],
+                    inner=[[k["inner_its"] for k in inf["krylov"]] for inf in infos],
+                    u=u.clone(), uh=uh.clone())
+
+    def time_apply():
+        """Global apply on its own (HBM-bound GEMV over the condensed blocks)."""
+        xa = torch.randn(ctx.n_glob, dtype=torch.float64, device="cuda")
+        ya = torch.zeros_like(xa)
+        for _ in range(3):
+            ctx.apply_global(xa, ya)
+        torch.cuda.synchronize()
+        ea = ev()
+        for _ in range(args.applies):
+            ctx.apply_global(xa, ya)
+        eb = ev()
+        torch.cuda.synchronize()
+        return ea.elapsed_time(eb) / args.applies
+
     nb, nu, nm = ctx.n_b_macro, ctx.n_u_macro, ctx.n_macros
+    flops = condense_flops(cfg, nu, nb) * nm
+    plain = run_variant(HDG_FP64, HDG_FP64, args.steps, args.warmup)
+    apply_ms = time_apply()
+    ms_step = plain["ms_per_stage"]
+    phase_ms, cond_calls = plain["phase_ms"], plain["cond_calls"]
+    newton_its, outer, inner = plain["newton_its"], plain["outer"], plain["inner"]
+    variants = {}
+    if not args.plain_only:
+        mixed = run_variant(HDG_FP32, HDG_FP64, args.steps, args.warmup)
+        cm = float(np.mean(mixed["cond_calls"]))
+        apply32_ms = time_apply()
+        du = float((mixed["u"] - plain["u"]).abs().max() / plain["u"].abs().max())
+        duh = float((mixed["uh"] - plain["uh"]).abs().max() / plain["uh"].abs().max())
+        variants["mixed_fp32_condense"] = dict(
+            ms_per_stage=round(mixed["ms_per_stage"], 3),
+            speedup_vs_plain=round(ms_step / mixed["ms_per_stage"], 3),
+            phases_ms={k: round(v, 3) for k, v in mixed["phase_ms"].items()},
+            newton_its=mixed["newton_its"], newton_res=mixed["newton_res"],
+            fgmres=dict(outer_its=mixed["outer"], inner_its=mixed["inner"]),
+            condense_ms=round(cm, 3), condense_tflops=round(flops / (cm * 1e-3) / 1e12, 3),
+            condense_frac_fp32_peak=round(flops / (cm * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+            stage_solution_rel_diff_vs_plain=dict(u=du, uhat=duh),
+            apply_ms=round(apply32_ms, 4),
+            apply_gbs=round((4.0 * nm * nb * nb + 16.0 * nm * nb + 8.0 * ctx.n_glob) / (apply32_ms * 1e-3) / 1e9, 1))
     apply_bytes = 8.0 * nm * nb * nb + 8.0 * nm * nb + 8.0 * nm * nb + 8.0 * ctx.n_glob
     apply_gbs = apply_bytes / (apply_ms * 1e-3) / 1e9
-    flops = condense_flops(cfg, nu, nb) * nm
     cond_ms = float(np.mean(cond_calls))
     cond_tflops = flops / (cond_ms * 1e-3) / 1e12
     # dominant work: hdg_condense, one launch sequence per Newton step (MFMA-bound)
@@ -236,12 +265,12 @@ def main():
                                     f"5 inner GMRES steps",
                            n_macros=nm, n_u_macro=nu, n_b_macro=nb, n_glob=ctx.n_glob, variant="plain FP64"),
                phases_ms={k: round(v, 3) for k, v in phase_ms.items()},
-               newton_its=newton_its, newton_res=infos[-1]["res_hist"],
+               newton_its=newton_its, newton_res=plain["newton_res"],
                fgmres=dict(outer_its=outer, inner_its=inner),
                condense_tflops=round(cond_tflops, 3), condense_ms=round(cond_ms, 3),
                apply_ms=round(apply_ms, 4), apply_gbs=round(apply_gbs, 1),
                apply_frac_hbm=round(apply_gbs / PEAK_HBM_GBS, 4), copy_gbs=round(copy_gbs, 1),
-               roofline=roofline)
+               roofline=roofline, variants=variants)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, newton_its)
     print(json.dumps(out), flush=True)

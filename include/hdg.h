@@ -90,17 +90,32 @@ typedef struct {
  * preconditioner is inner_its steps of GMRES left-preconditioned by the
  * inverse face blocks of A_uhat-uhat.  Convergence: ||b - A x||_2 <=
  * max(rtol ||b||_2, atol).  inner_prec selects the precision of the condensed
- * blocks used inside the preconditioner. */
+ * blocks used inside the preconditioner: HDG_FP32 after an FP64 condensation
+ * uses an FP32 copy of A-hat there (made on first use); after an FP32
+ * condensation both levels use the FP32 blocks. */
 typedef struct {
   double rtol, atol;
   int restart, max_outer, inner_its;
   hdg_prec inner_prec;
+  /* 1: add the learned coarse correction bound by hdg_learned_bind to every
+   * preconditioner application, with fallback to the plain preconditioner
+   * for the rest of the solve once the learned steps reduce the residual
+   * less, on average over at least 3 steps, than the plain steps seen so far
+   * on this context (or once a learned step fails to reduce it). */
+  int use_learned;
+  /* optional (device, may be NULL): the vectors the preconditioner is
+   * applied to are copied here, harvest_max vectors of n_glob doubles at
+   * most, in the order they occur (training data of the learned stage). */
+  double* harvest;
+  int harvest_max;
 } hdg_krylov_opts;
 
 typedef struct {
   int outer_its, inner_its_total;
   double res0, res_final;
   double ms;
+  int fallbacks;   /* 1 if the learned stage was switched off during the solve */
+  int harvested;   /* vectors written to opts.harvest */
 } hdg_krylov_stats;
 
 /* Build the mesh topology, the reference tables of every macro shape and the
@@ -136,11 +151,22 @@ hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, co
  * pivoting and the condensed blocks A-hat^{T_i} and right-hand sides
  * b-hat^{T_i} are formed; bhat (device, n_glob) receives the assembled b-hat
  * of eq. (C44).  Also factors the face blocks of A_uhat-uhat used by the
- * preconditioner.  prec selects the arithmetic of the factorisation. */
+ * preconditioner.
+ * prec = HDG_FP64: formation and elimination in FP64 (FP64 MFMA).
+ * prec = HDG_FP32: the augmented matrices are formed (accumulated in FP64)
+ *   and stored in FP32 and eliminated with FP32 arithmetic (FP32 MFMA); the
+ *   condensed blocks, b-hat, the operator of hdg_apply_global and the factors
+ *   used by hdg_local_backsolve then carry FP32 rounding (vectors, sums and
+ *   the recovery stay FP64).  A Newton iteration whose residuals are
+ *   evaluated in FP64 (hdg_linearize_stage) refines the result back to the
+ *   FP64 level.  The precision stays in effect until the next hdg_condense.
+ * The face blocks of the preconditioner are always FP64.
+ * Returns HDG_ESINGULAR (message names the macro) on a zero pivot. */
 hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat);
 
 /* y = A-hat x = sum_i P_i^T A-hat^{T_i} P_i x (Algorithm 2 with the condensed
- * blocks formed by hdg_condense); x, y device, n_glob. */
+ * blocks formed by hdg_condense, in the precision of that call; sums in
+ * FP64); x, y device, n_glob, must not alias. */
 hdg_status hdg_apply_global(hdg_ctx ctx, const double* x, double* y);
 
 /* Solve A-hat x = b with the options above (Sec. 4.2).  x: initial guess on
@@ -155,6 +181,68 @@ hdg_status hdg_local_backsolve(hdg_ctx ctx, const double* duhat, double* dq, dou
 
 /* y += a x on n doubles (device): the Newton update. */
 hdg_status hdg_axpy(hdg_ctx ctx, size_t n, double a, const double* x, double* y);
+
+/* Plain preconditioner stage on its own: z = inner_its steps of GMRES (zero
+ * start) on A-hat left-preconditioned by the inverse face blocks of
+ * A_uhat-uhat (Sec. 4.2), plus the learned coarse correction if use_learned
+ * and a network is bound.  v, z device, n_glob, must not alias.  Valid after
+ * hdg_condense. */
+hdg_status hdg_precond_apply(hdg_ctx ctx, const double* v, double* z, int inner_its, hdg_prec inner_prec,
+                             int use_learned);
+
+/* ---- learned coarse correction --------------------------------------------
+ * Not part of the paper: a stage that FGMRES's flexibility (Sec. 4.2)
+ * admits.  Coarse space: per macro face and component, the multilinear
+ * functions of the tangential face coordinates (scaled to [0, 1] over the
+ * face); 2d n_s 2^(d-1) coefficients per macro (120 in 3D), ordered
+ * [local face][component][function] with functions (1-s)(1-t), s(1-t),
+ * (1-s)t, st (3D; 1-s, s in 2D). */
+
+/* Number of coarse coefficients per macro. */
+hdg_status hdg_coarse_size(hdg_ctx ctx, int* n_features);
+
+/* X [n_macros][n_features] (device, FP32) = discrete L2 projection of the
+ * face fields of v (device, n_glob) onto the coarse functions, with the
+ * composite Gauss-Lobatto rule of the face nodes as inner product. */
+hdg_status hdg_coarse_restrict(hdg_ctx ctx, const double* v, float* X);
+
+/* z += alpha * (coarse functions with coefficients Y evaluated at the face
+ * nodes), each face taking the mean over the macros that own it. */
+hdg_status hdg_coarse_prolong(hdg_ctx ctx, const float* Y, double alpha, double* z);
+
+/* Two-layer network y = ||x|| (W2 tanh(W1 x / ||x|| + b1) + b2) (y = 0 for
+ * x = 0).  All arrays are caller-owned device memory in FP32. */
+typedef struct {
+  int n_in, n_hidden, n_out;  /* n_hidden <= 512 for hdg_learned_bind */
+  int max_batch;              /* rows per call of the training entry points */
+  float* params;  /* W1 [n_hidden][n_in], b1 [n_hidden], W2 [n_out][n_hidden], b2 [n_out] */
+  float* grads;   /* layout of params (written by hdg_mlp_loss_grad) */
+  float* adam_m;  /* layout of params, zero before the first hdg_mlp_adam */
+  float* adam_v;  /* layout of params, zero before the first hdg_mlp_adam */
+  float* work;    /* hdg_mlp_work_floats() floats of scratch */
+} hdg_mlp;
+
+size_t hdg_mlp_param_count(int n_in, int n_hidden, int n_out);
+size_t hdg_mlp_work_floats(int n_in, int n_hidden, int n_out, int max_batch);
+
+/* Y [batch][n_out] = network applied to the rows idx[0..batch) of X (idx
+ * device, NULL = rows 0..batch-1); FP32.  batch <= max_batch. */
+hdg_status hdg_mlp_forward(hdg_ctx ctx, const hdg_mlp* net, const float* X, const int* idx, int batch, float* Y);
+
+/* Mean squared error over the batch and the outputs between the network
+ * before rescaling and T / ||x|| (normalised units), and its gradient with
+ * respect to params (into net->grads).  loss_dev (device, may be NULL)
+ * receives the loss. */
+hdg_status hdg_mlp_loss_grad(hdg_ctx ctx, const hdg_mlp* net, const float* X, const float* T, const int* idx,
+                             int batch, float* loss_dev);
+
+/* One Adam step (Kingma and Ba) on params with net->grads; step counts from 1. */
+hdg_status hdg_mlp_adam(hdg_ctx ctx, const hdg_mlp* net, float lr, float beta1, float beta2, float eps, int step);
+
+/* Copy the network's parameters to BF16 inside the context for use by the
+ * preconditioner (n_in = n_out = hdg_coarse_size, n_hidden <= 512); NULL
+ * unbinds.  The copy is taken when the call's work runs on the stream. */
+hdg_status hdg_learned_bind(hdg_ctx ctx, const hdg_mlp* net);
 
 hdg_status hdg_destroy(hdg_ctx ctx);
 const char* hdg_status_string(hdg_status s);

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhdg.so")
-SOURCES = ["host_setup.cpp", "capi.cpp", "k_linearize.hip", "k_form.hip", "k_lu.hip", "k_krylov.hip", "k_backsolve.hip"]
+SOURCES = ["host_setup.cpp", "capi.cpp", "k_linearize.hip", "k_form.hip", "k_lu.hip", "k_krylov.hip", "k_backsolve.hip",
+           "k_learned.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-Wno-unused-variable"]
@@ -32,7 +33,7 @@ def build(verbose=True, jobs=8):
     if not ok:
         raise RuntimeError("hipcc failed")
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
+    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", "-Wl,--no-undefined", *objs, "-o", tmp]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

@@ -50,6 +50,7 @@ struct Krylov {
   double* host;  // pinned scratch
   int inner_prec;
   int inner_total = 0;
+  bool learned = false;  // add the learned coarse correction in precond()
 
   Krylov(HdgContext& cc, int rs, int in, double* hostbuf, int prec) : c(cc), restart(rs), inner(in), host(hostbuf), inner_prec(prec) {
     n = c.md.n_glob;
@@ -95,8 +96,13 @@ struct Krylov {
   hipError_t apply_A(const double* x, double* y, int prec) { return launch_apply(c, x, y, prec); }
   hipError_t apply_M(const double* x, double* y) { return launch_precond_apply(c, x, y); }
 
-  // z = inner GMRES(inner) on M^{-1} A z = M^{-1} v, zero start
+  // z = inner GMRES(inner) on M^{-1} A z = M^{-1} v, zero start (+ learned correction)
   hipError_t precond(const double* v, double* z) {
+    hipError_t e = precond_plain(v, z);
+    if (e != hipSuccess || !learned) return e;
+    return launch_learned_correction(c, v, z);
+  }
+  hipError_t precond_plain(const double* v, double* z) {
     if (inner <= 0) return launch_precond_apply(c, v, z);
     hipError_t e = apply_M(v, Vi);
     if (e != hipSuccess) return e;
@@ -266,17 +272,18 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
     const char* old = c.ws.base;
     auto rebase = [&](auto*& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(base + (reinterpret_cast<const char*>(p) - old)); };
     rebase(c.ws.Kq); rebase(c.ws.AUU); rebase(c.ws.AUQ); rebase(c.ws.RUe); rebase(c.ws.RQe); rebase(c.ws.SUB);
-    rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.Wm);
+    rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.gloc); rebase(c.ws.Wm);
     rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.ypart); rebase(c.ws.kry);
-    rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv);
+    rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn);
   } else {
     auto rebase = [&](auto*& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(base + reinterpret_cast<uintptr_t>(p)); };
     rebase(c.ws.Kq); rebase(c.ws.AUU); rebase(c.ws.AUQ); rebase(c.ws.RUe); rebase(c.ws.RQe); rebase(c.ws.SUB);
-    rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.Wm);
+    rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.gloc); rebase(c.ws.Wm);
     rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.ypart); rebase(c.ws.kry);
-    rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv);
+    rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn);
   }
   c.ws.base = base;
+  c.lrn_bound = false;
   c.ws.bytes = bytes;
   c.ws_bound = true;
   c.have_a32 = false;
@@ -306,13 +313,15 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
   if (!ctx || !bhat) return HDG_EINVAL;
   HdgContext& c = ctx->c;
   if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
-  if (prec != HDG_FP64) return fail(&c, HDG_EUNSUPPORTED, "only FP64 condensation is built");
+  if (prec != HDG_FP64 && prec != HDG_FP32) return fail(&c, HDG_EUNSUPPORTED, "condensation precision not built");
+  const int p32 = (prec == HDG_FP32) ? 1 : 0;
   int* status = reinterpret_cast<int*>(c.ws.small);
   HIPCHK(&c, launch_zero_ints(c.stream, status, 2));
-  HIPCHK(&c, launch_form(c));
-  HIPCHK(&c, launch_lu(c));
-  HIPCHK(&c, launch_bhat(c, bhat));
+  HIPCHK(&c, launch_form(c, p32));
+  HIPCHK(&c, launch_lu(c, p32));
+  HIPCHK(&c, launch_bhat(c, bhat, p32));
   HIPCHK(&c, launch_face_precond(c));
+  c.cond_prec = p32;
   c.have_a32 = false;
   int st[2] = {0, 0};
   HIPCHK(&c, hipMemcpyAsync(ctx->pinned, status, sizeof(int) * 2, hipMemcpyDeviceToHost, c.stream));
@@ -339,12 +348,18 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
       o->max_outer < 1 || !(o->rtol >= 0) || !(o->atol >= 0))
     return fail(&c, HDG_EINVAL, "bad Krylov options");
   auto t0 = std::chrono::steady_clock::now();
-  if (o->inner_prec == HDG_FP32 && !c.have_a32) {
+  if (o->inner_prec == HDG_FP32 && c.cond_prec == 0 && !c.have_a32) {
     HIPCHK(&c, launch_cast_ahat(c));
     c.have_a32 = true;
   }
+  if (o->use_learned && !c.lrn_bound) return fail(&c, HDG_EINVAL, "use_learned without a bound network");
+  if (o->harvest_max < 0 || (o->harvest_max > 0 && !o->harvest)) return fail(&c, HDG_EINVAL, "bad harvest buffer");
   Krylov K(c, o->restart, o->inner_its, ctx->pinned, o->inner_prec == HDG_FP32 ? 1 : 0);
+  K.learned = o->use_learned != 0;
   const long long n = K.n;
+  int harvested = 0, fallbacks = 0;
+  double lrn_log = 0.0;
+  int lrn_steps = 0;
   double bnorm, beta;
   HIPCHK(&c, K.norm(b, bnorm));
   const double tol = std::max(o->rtol * bnorm, o->atol);
@@ -360,6 +375,12 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
     g[0] = beta;
     int k = 0;
     for (int j = 0; j < m; ++j) {
+      if (harvested < o->harvest_max) {
+        HIPCHK(&c, hipMemcpyAsync(o->harvest + (size_t)harvested * n, K.V + (size_t)j * n, sizeof(double) * n,
+                                  hipMemcpyDeviceToDevice, c.stream));
+        ++harvested;
+      }
+      const bool step_learned = K.learned;
       HIPCHK(&c, K.precond(K.V + (size_t)j * n, K.Z + (size_t)j * n));
       double* wv = K.V + (size_t)(j + 1) * n;
       HIPCHK(&c, K.apply_A(K.Z + (size_t)j * n, wv, 0));
@@ -381,6 +402,24 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
       g[j] = cs[j] * g0;
       g[j + 1] = -sn[j] * g0;
       ++its;
+      // residual reduction of this step: plain steps feed the context's running
+      // average; learned steps are compared with it (fallback rule of the options)
+      const double rate = std::fabs(g0) > 0.0 ? std::fabs(g[j + 1]) / std::fabs(g0) : 0.0;
+      if (rate > 0.0) {
+        if (!step_learned) {
+          c.plain_log_rate += std::log(rate);
+          ++c.plain_steps;
+        } else {
+          lrn_log += std::log(rate);
+          ++lrn_steps;
+          const bool worse_than_plain = lrn_steps >= 3 && c.plain_steps >= 3 &&
+                                        lrn_log / lrn_steps > c.plain_log_rate / c.plain_steps;
+          if (rate >= 1.0 || worse_than_plain) {
+            K.learned = false;
+            fallbacks = 1;
+          }
+        }
+      }
       k = j + 1;
       if (hn == 0.0 || std::fabs(g[j + 1]) <= tol || its >= o->max_outer) break;
       HIPCHK(&c, launch_scale_copy(c.stream, n, 1.0 / hn, wv, wv));
@@ -405,8 +444,103 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
     st->res0 = bnorm;
     st->res_final = beta;
     st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st->fallbacks = fallbacks;
+    st->harvested = harvested;
   }
   if (beta > tol) return fail(&c, HDG_ENOCONV, "FGMRES reached max_outer");
+  return HDG_OK;
+}
+
+hdg_status hdg_precond_apply(hdg_ctx ctx, const double* v, double* z, int inner_its, hdg_prec inner_prec,
+                             int use_learned) {
+  if (!ctx || !v || !z || v == z) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  if (inner_its < 0 || inner_its > c.kry_inner_max) return fail(&c, HDG_EINVAL, "bad inner_its");
+  if (use_learned && !c.lrn_bound) return fail(&c, HDG_EINVAL, "use_learned without a bound network");
+  if (inner_prec == HDG_FP32 && c.cond_prec == 0 && !c.have_a32) {
+    HIPCHK(&c, launch_cast_ahat(c));
+    c.have_a32 = true;
+  }
+  Krylov K(c, 1, inner_its, ctx->pinned, inner_prec == HDG_FP32 ? 1 : 0);
+  K.learned = use_learned != 0;
+  HIPCHK(&c, K.precond(v, z));
+  return HDG_OK;
+}
+
+hdg_status hdg_coarse_size(hdg_ctx ctx, int* n_features) {
+  if (!ctx || !n_features) return HDG_EINVAL;
+  *n_features = ctx->c.cd.cF;
+  return HDG_OK;
+}
+
+hdg_status hdg_coarse_restrict(hdg_ctx ctx, const double* v, float* X) {
+  if (!ctx || !v || !X) return HDG_EINVAL;
+  HIPCHK(&ctx->c, launch_coarse_restrict(ctx->c, v, X));
+  return HDG_OK;
+}
+
+hdg_status hdg_coarse_prolong(hdg_ctx ctx, const float* Y, double alpha, double* z) {
+  if (!ctx || !Y || !z) return HDG_EINVAL;
+  HIPCHK(&ctx->c, launch_coarse_prolong(ctx->c, Y, alpha, z));
+  return HDG_OK;
+}
+
+size_t hdg_mlp_param_count(int n_in, int n_hidden, int n_out) {
+  if (n_in <= 0 || n_hidden <= 0 || n_out <= 0) return 0;
+  return mlp_param_count(n_in, n_hidden, n_out);
+}
+
+size_t hdg_mlp_work_floats(int n_in, int n_hidden, int n_out, int max_batch) {
+  if (n_in <= 0 || n_hidden <= 0 || n_out <= 0 || max_batch <= 0) return 0;
+  return mlp_work_floats(n_in, n_hidden, n_out, max_batch);
+}
+
+static bool mlp_ok(const hdg_mlp* net, int batch) {
+  return net && net->params && net->work && net->n_in > 0 && net->n_hidden > 0 && net->n_out > 0 && batch > 0 &&
+         batch <= net->max_batch;
+}
+
+hdg_status hdg_mlp_forward(hdg_ctx ctx, const hdg_mlp* net, const float* X, const int* idx, int batch, float* Y) {
+  if (!ctx || !mlp_ok(net, batch) || !X || !Y) return HDG_EINVAL;
+  HIPCHK(&ctx->c, launch_mlp_forward(ctx->c.stream, net->n_in, net->n_hidden, net->n_out, net->params, net->work, X,
+                                     idx, batch, Y));
+  return HDG_OK;
+}
+
+hdg_status hdg_mlp_loss_grad(hdg_ctx ctx, const hdg_mlp* net, const float* X, const float* T, const int* idx,
+                             int batch, float* loss_dev) {
+  if (!ctx || !mlp_ok(net, batch) || !net->grads || !X || !T) return HDG_EINVAL;
+  HIPCHK(&ctx->c, launch_mlp_loss_grad(ctx->c.stream, net->n_in, net->n_hidden, net->n_out, net->params, net->grads,
+                                       net->work, X, T, idx, batch, loss_dev));
+  return HDG_OK;
+}
+
+hdg_status hdg_mlp_adam(hdg_ctx ctx, const hdg_mlp* net, float lr, float beta1, float beta2, float eps, int step) {
+  if (!ctx || !net || !net->params || !net->grads || !net->adam_m || !net->adam_v || step < 1 || !(lr > 0) ||
+      !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return HDG_EINVAL;
+  const long long n = (long long)mlp_param_count(net->n_in, net->n_hidden, net->n_out);
+  HIPCHK(&ctx->c, launch_mlp_adam(ctx->c.stream, n, net->params, net->grads, net->adam_m, net->adam_v, lr, beta1,
+                                  beta2, eps, step));
+  return HDG_OK;
+}
+
+hdg_status hdg_learned_bind(hdg_ctx ctx, const hdg_mlp* net) {
+  if (!ctx) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!net) {
+    c.lrn_bound = false;
+    return HDG_OK;
+  }
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  if (!net->params || net->n_in != c.cd.cF || net->n_out != c.cd.cF || net->n_hidden <= 0 ||
+      net->n_hidden > LRN_MAX_HIDDEN)
+    return fail(&c, HDG_EINVAL, "network shape does not match the coarse space (or n_hidden > 512)");
+  unsigned short* q = reinterpret_cast<unsigned short*>(c.ws.lrn + 2 * (size_t)c.hm.n_macros * c.cd.cF);
+  HIPCHK(&c, launch_to_bf16(c.stream, (long long)mlp_param_count(net->n_in, net->n_hidden, net->n_out), net->params, q));
+  c.lrn_hidden = net->n_hidden;
+  c.lrn_bound = true;
   return HDG_OK;
 }
 
@@ -433,9 +567,18 @@ hdg_status hdg_destroy(hdg_ctx ctx) {
   return HDG_OK;
 }
 
-static hdg_status copy_tiled_macro(hdg_ctx ctx, size_t macro, std::vector<double>& out) {
+// one tiled macro matrix to the host, widened to double if stored in FP32
+static hdg_status copy_tiled_macro(hdg_ctx ctx, size_t macro, std::vector<double>& out, int prec) {
   HdgContext& c = ctx->c;
   out.assign((size_t)c.wstride, 0.0);
+  if (prec == 1) {
+    std::vector<float> f((size_t)c.wstride);
+    HIPCHK(&c, hipMemcpyAsync(f.data(), reinterpret_cast<const float*>(c.ws.Wm) + macro * (size_t)c.wstride,
+                              sizeof(float) * c.wstride, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(&c, hipStreamSynchronize(c.stream));
+    for (size_t i = 0; i < f.size(); ++i) out[i] = f[i];
+    return HDG_OK;
+  }
   HIPCHK(&c, hipMemcpyAsync(out.data(), c.ws.Wm + macro * (size_t)c.wstride, sizeof(double) * c.wstride,
                             hipMemcpyDeviceToHost, c.stream));
   HIPCHK(&c, hipStreamSynchronize(c.stream));
@@ -448,12 +591,18 @@ hdg_status hdg_get_condensed(hdg_ctx ctx, size_t macro, double* ahat_host, doubl
   if (!c.ws_bound || macro >= (size_t)c.hm.n_macros) return HDG_EINVAL;
   const int nb = c.hc.n_b, nu = c.hc.n_u;
   std::vector<double> tiled;
-  hdg_status s = copy_tiled_macro(ctx, macro, tiled);
+  hdg_status s = copy_tiled_macro(ctx, macro, tiled, c.cond_prec);
   if (s != HDG_OK) return s;
+  std::vector<double> g(nb, 0.0);  // FP32 condensation keeps g in FP64 outside W
+  if (c.cond_prec == 1) {
+    HIPCHK(&c, hipMemcpyAsync(g.data(), c.ws.gloc + macro * (size_t)nb, sizeof(double) * nb, hipMemcpyDeviceToHost,
+                              c.stream));
+    HIPCHK(&c, hipStreamSynchronize(c.stream));
+  }
   for (int r = 0; r < nb; ++r) {
     if (ahat_host)
       for (int k = 0; k < nb; ++k) ahat_host[(size_t)r * nb + k] = tiled[wtix(nu + r, nu + k, c.ldw)];
-    if (bhat_host) bhat_host[r] = tiled[wtix(nu + r, c.n_cols - 1, c.ldw)];
+    if (bhat_host) bhat_host[r] = g[r] + tiled[wtix(nu + r, c.n_cols - 1, c.ldw)];
   }
   return HDG_OK;
 }
@@ -462,9 +611,10 @@ hdg_status hdg_get_formed(hdg_ctx ctx, size_t macro, double* w_host) {
   if (!ctx || !w_host) return HDG_EINVAL;
   HdgContext& c = ctx->c;
   if (!c.ws_bound || macro >= (size_t)c.hm.n_macros) return HDG_EINVAL;
-  HIPCHK(&c, launch_form(c));
+  HIPCHK(&c, launch_form(c, 0));
+  c.cond_prec = 0;
   std::vector<double> tiled;
-  hdg_status s = copy_tiled_macro(ctx, macro, tiled);
+  hdg_status s = copy_tiled_macro(ctx, macro, tiled, 0);
   if (s != HDG_OK) return s;
   for (int r = 0; r < c.n_rows; ++r)
     for (int k = 0; k < c.n_cols; ++k) w_host[(size_t)r * c.n_cols + k] = tiled[wtix(r, k, c.ldw)];

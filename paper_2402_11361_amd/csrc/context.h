@@ -13,6 +13,8 @@ struct HostClass {
   double h[3];
   int nf_nodes[HDG_MAXF], nf_off[HDG_MAXF];
   std::vector<double> Phi, dPhi, W, Tvol, Mel, Psi, WF, C1D, Minv1D, M1D;
+  int cq = 0, cF = 0, cmaxf = 0;
+  std::vector<double> cR, cPhi;
   std::vector<int> fnode, finv, elem_nodes, elem_sub, sub_elem, sub_lf, sub_tid, node_ne, node_e, node_a,
       tn_cnt, tn_sub, tn_t, tn_base;
 };
@@ -44,7 +46,8 @@ struct Workspace {
   double* RQt = nullptr;    // [n_q_tot]  M^{-1} R_Q per direction and component
   double* RBloc = nullptr;  // [macros][n_b] per-macro trace residual
   double* RBglob = nullptr; // [n_glob]
-  double* Wm = nullptr;     // [macros][n_rows][ldw] augmented matrices
+  double* gloc = nullptr;   // [macros][n_b] g of eq. ASC2b in FP64 (FP32 condensation keeps it out of W)
+  double* Wm = nullptr;     // [macros][n_rows][ldw] augmented matrices (FP64, or FP32 in the first half)
   int* ipiv = nullptr;      // [macros][n_u]
   double* FW = nullptr;     // [faces][2 nf][ldf] face preconditioner
   int* fpiv = nullptr;      // [faces][nf]
@@ -54,6 +57,7 @@ struct Workspace {
   double* red = nullptr;    // reduction scratch
   double* small = nullptr;  // small device scalars
   double* Uinv = nullptr;   // [max(macros, faces)][64][64] block inverses of the elimination
+  float* lrn = nullptr;     // learned stage: X, Y [macros][cF] each, then the BF16 network
 };
 
 struct HdgContext {
@@ -78,7 +82,12 @@ struct HdgContext {
   // offsets of the sub-face block pieces
   int off_AUB = 0, off_ABU = 0, off_ABQ = 0, off_ABB = 0, off_RB = 0;
   bool have_a32 = false;
-  int last_prec = 0;
+  int cond_prec = 0;
+  // learned coarse correction
+  bool lrn_bound = false;
+  int lrn_hidden = 0;
+  double plain_log_rate = 0.0;  // sum of log(residual reduction) over plain FGMRES steps
+  long long plain_steps = 0;  // element type of the condensed matrices in Wm: 0 FP64, 1 FP32
   std::string last_error;
 };
 

@@ -192,6 +192,69 @@ bool build_mesh(const HdgMeshIn& in, HostMesh& hm, std::string& err) {
   return true;
 }
 
+// Coarse multilinear functions of the tangential face coordinates (scaled to
+// [0, 1] over the macro face) and the discrete L2 projection onto them with
+// the composite Gauss-Lobatto rule of the face nodes as inner product.
+static void build_coarse(HostClass& hc) {
+  const int d = hc.dim, p = hc.p;
+  hc.cq = 1 << (d - 1);
+  hc.cF = 2 * d * hc.ns * hc.cq;
+  hc.cmaxf = 0;
+  for (int lf = 0; lf < 2 * d; ++lf) hc.cmaxf = std::max(hc.cmaxf, hc.nf_nodes[lf]);
+  const std::vector<double> x = gll(p);
+  std::vector<double> w(p + 1);
+  for (int a = 0; a <= p; ++a) {  // Lobatto weights 2 / (p (p+1) P_p(x_a)^2)
+    double P, dP;
+    legendre(p, x[a], P, dP);
+    w[a] = 2.0 / (p * (p + 1.0) * P * P);
+  }
+  auto composite = [&](int m, std::vector<double>& pos, std::vector<double>& wt) {
+    pos.assign(m * p + 1, 0.0);
+    wt.assign(m * p + 1, 0.0);
+    for (int e = 0; e < m; ++e)
+      for (int a = 0; a <= p; ++a) {
+        pos[e * p + a] = (e + (x[a] + 1.0) / 2.0) / m;
+        wt[e * p + a] += w[a] / (2.0 * m);
+      }
+  };
+  const int cq = hc.cq, mf = hc.cmaxf;
+  hc.cR.assign((size_t)d * cq * mf, 0.0);
+  hc.cPhi.assign((size_t)d * mf * cq, 0.0);
+  for (int k = 0; k < d; ++k) {
+    int tang[2] = {0, 0}, nt = 0;
+    for (int a = 0; a < d; ++a)
+      if (a != k) tang[nt++] = a;
+    std::vector<double> s, ws, t(1, 0.0), wt(1, 1.0);
+    composite(hc.m[tang[0]], s, ws);
+    if (d == 3) composite(hc.m[tang[1]], t, wt);
+    const int n0 = (int)s.size(), nn = n0 * (int)t.size();
+    std::vector<double> phi((size_t)nn * cq), wq(nn);
+    for (int j = 0; j < nn; ++j) {
+      const double S = s[j % n0], T = t[j / n0];
+      wq[j] = ws[j % n0] * wt[j / n0];
+      if (d == 2) {
+        phi[j * cq + 0] = 1.0 - S; phi[j * cq + 1] = S;
+      } else {
+        phi[j * cq + 0] = (1.0 - S) * (1.0 - T); phi[j * cq + 1] = S * (1.0 - T);
+        phi[j * cq + 2] = (1.0 - S) * T;         phi[j * cq + 3] = S * T;
+      }
+    }
+    std::vector<double> G(cq * cq, 0.0);
+    for (int j = 0; j < nn; ++j)
+      for (int a = 0; a < cq; ++a)
+        for (int b = 0; b < cq; ++b) G[a * cq + b] += phi[j * cq + a] * wq[j] * phi[j * cq + b];
+    const std::vector<double> Gi = invert(G, cq);
+    for (int a = 0; a < cq; ++a)
+      for (int j = 0; j < nn; ++j) {
+        double r = 0.0;
+        for (int b = 0; b < cq; ++b) r += Gi[a * cq + b] * phi[j * cq + b] * wq[j];
+        hc.cR[((size_t)k * cq + a) * mf + j] = r;
+      }
+    for (int j = 0; j < nn; ++j)
+      for (int a = 0; a < cq; ++a) hc.cPhi[((size_t)k * mf + j) * cq + a] = phi[j * cq + a];
+  }
+}
+
 void build_class(const HostMesh& hm, HostClass& hc) {
   const int d = hm.dim, p = hm.p, ns = hm.ns;
   hc.dim = d; hc.p = p; hc.ns = ns; hc.nq = p + 2;
@@ -362,6 +425,7 @@ void build_class(const HostMesh& hm, HostClass& hc) {
         hc.M1D[((size_t)k * nm + a) * nm + b] = M[a * n + b];
       }
   }
+  build_coarse(hc);
 }
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -390,7 +454,7 @@ void plan_workspace(HdgContext& c) {
   c.ldf = (int)align_up(2 * c.nf_max, 64);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, Wm, ipiv, FW, fpiv, A32, ypart, kry, red, small, Uinv; } o;
+  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, gloc, Wm, ipiv, FW, fpiv, A32, ypart, kry, red, small, Uinv, lrn; } o;
   o.Kq = take(sizeof(double) * n_el * c.Kstride);
   o.AUU = take(sizeof(double) * n_el * c.nsA * c.nsA);
   o.AUQ = take(sizeof(double) * n_el * c.nsA * c.dnsA);
@@ -402,6 +466,7 @@ void plan_workspace(HdgContext& c) {
   o.RQt = take(sizeof(double) * c.n_q_tot);
   o.RBloc = take(sizeof(double) * (size_t)hm.n_macros * hc.n_b);
   o.RBglob = take(sizeof(double) * hm.n_glob);
+  o.gloc = take(sizeof(double) * (size_t)hm.n_macros * hc.n_b);
   c.wstride = (long long)align_up(c.n_rows, 16) * c.ldw;
   c.fstride = (long long)align_up(2 * c.nf_max, 16) * c.ldf;
   o.Wm = take(sizeof(double) * (size_t)hm.n_macros * c.wstride);
@@ -415,6 +480,9 @@ void plan_workspace(HdgContext& c) {
   o.small = take(sizeof(double) * 4096);
   // elimination scratch: per matrix a 64 x 64 block inverse and a row permutation
   o.Uinv = take(sizeof(double) * (size_t)std::max(hm.n_macros, hm.n_faces) * (64 * 64 + 256));
+  // learned stage: X and Y per macro, then the BF16 copy of the largest network
+  o.lrn = take(sizeof(float) * (2 * (size_t)hm.n_macros * hc.cF + 16) +
+               sizeof(unsigned short) * mlp_param_count(hc.cF, LRN_MAX_HIDDEN, hc.cF));
   c.need_bytes = off;
   // remember offsets in the workspace struct (resolved on bind)
   c.ws.bytes = 0;
@@ -429,6 +497,7 @@ void plan_workspace(HdgContext& c) {
   c.ws.RQt = reinterpret_cast<double*>(o.RQt);
   c.ws.RBloc = reinterpret_cast<double*>(o.RBloc);
   c.ws.RBglob = reinterpret_cast<double*>(o.RBglob);
+  c.ws.gloc = reinterpret_cast<double*>(o.gloc);
   c.ws.Wm = reinterpret_cast<double*>(o.Wm);
   c.ws.ipiv = reinterpret_cast<int*>(o.ipiv);
   c.ws.FW = reinterpret_cast<double*>(o.FW);
@@ -439,6 +508,7 @@ void plan_workspace(HdgContext& c) {
   c.ws.red = reinterpret_cast<double*>(o.red);
   c.ws.small = reinterpret_cast<double*>(o.small);
   c.ws.Uinv = reinterpret_cast<double*>(o.Uinv);
+  c.ws.lrn = reinterpret_cast<float*>(o.lrn);
 }
 
 void node_coords(const HdgContext& c, double* macro_xyz, double* face_xyz) {
@@ -514,6 +584,8 @@ void upload_tables(HdgContext& c) {
   cd.node_e = up(c, hc.node_e); cd.node_a = up(c, hc.node_a); cd.tn_cnt = up(c, hc.tn_cnt);
   cd.tn_sub = up(c, hc.tn_sub); cd.tn_t = up(c, hc.tn_t); cd.tn_base = up(c, hc.tn_base);
   cd.C1D = up(c, hc.C1D); cd.Minv1D = up(c, hc.Minv1D); cd.M1D = up(c, hc.M1D);
+  cd.cq = hc.cq; cd.cF = hc.cF; cd.cmaxf = hc.cmaxf;
+  cd.cR = up(c, hc.cR); cd.cPhi = up(c, hc.cPhi);
   HostMesh& hm = c.hm;
   MeshDev& md = c.md;
   md.dim = hm.dim; md.ns = hm.ns; md.n_macros = hm.n_macros; md.n_faces = hm.n_faces; md.n_glob = hm.n_glob;

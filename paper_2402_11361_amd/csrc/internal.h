@@ -51,6 +51,12 @@ struct ClassDev {
   const double* C1D;      // [dim][nmax1][nmax1]
   const double* Minv1D;   // [dim][nmax1][nmax1]
   const double* M1D;      // [dim][nmax1][nmax1]
+  // coarse multilinear space on the macro faces (learned correction):
+  // cq = 2^(d-1) functions per face and component, cF = 2d ns cq features per
+  // macro, tables per normal axis k over the face nodes (lower axis fastest)
+  int cq, cF, cmaxf;
+  const double* cR;       // [dim][cq][cmaxf] discrete L2 projection (G^{-1} Phi^T W)
+  const double* cPhi;     // [dim][cmaxf][cq] coarse functions at the face nodes
 };
 
 struct PhysDev {
@@ -91,9 +97,10 @@ struct HdgContext;
 
 hipError_t launch_linearize(HdgContext& c, const double* q, const double* u, const double* uhat,
                             const double* w, StageArgs sa);
-hipError_t launch_form(HdgContext& c);
-hipError_t launch_lu(HdgContext& c);
-hipError_t launch_bhat(HdgContext& c, double* bhat);
+// prec: 0 FP64, 1 FP32 element type of the augmented matrices
+hipError_t launch_form(HdgContext& c, int prec);
+hipError_t launch_lu(HdgContext& c, int prec);
+hipError_t launch_bhat(HdgContext& c, double* bhat, int prec);
 hipError_t launch_face_precond(HdgContext& c);
 hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec);
 hipError_t launch_precond_apply(HdgContext& c, const double* x, double* y);
@@ -101,6 +108,21 @@ hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, doub
 hipError_t launch_axpy(hipStream_t s, size_t n, double a, const double* x, double* y);
 hipError_t launch_norms(HdgContext& c, double* out3_dev);
 hipError_t launch_cast_ahat(HdgContext& c);
+
+// learned coarse correction
+constexpr int LRN_MAX_HIDDEN = 512;
+size_t mlp_param_count(int n_in, int n_hidden, int n_out);
+size_t mlp_work_floats(int n_in, int n_hidden, int n_out, int max_batch);
+hipError_t launch_coarse_restrict(HdgContext& c, const double* v, float* X);
+hipError_t launch_coarse_prolong(HdgContext& c, const float* Y, double alpha, double* z);
+hipError_t launch_mlp_forward(hipStream_t s, int n_in, int n_hidden, int n_out, const float* params, float* work,
+                              const float* X, const int* idx, int batch, float* Y);
+hipError_t launch_mlp_loss_grad(hipStream_t s, int n_in, int n_hidden, int n_out, const float* params, float* grads,
+                                float* work, const float* X, const float* T, const int* idx, int batch, float* loss);
+hipError_t launch_mlp_adam(hipStream_t s, long long n, float* p, const float* g, float* m, float* v, float lr,
+                           float b1, float b2, float eps, int t);
+hipError_t launch_to_bf16(hipStream_t s, long long n, const float* p, unsigned short* q);
+hipError_t launch_learned_correction(HdgContext& c, const double* v, double* z);
 
 // vector kernels for the Krylov solver
 hipError_t launch_multidot(hipStream_t s, long long n, int k, const double* V, long long ldv,

@@ -22,7 +22,10 @@ __device__ __forceinline__ int local_face(const ClassDev& cd, int r) {
 constexpr int BS_ROWS = 64;
 
 // z = w - U12 duhat_i for rows [blockIdx.x * 64, +64) of one macro.
-__global__ void __launch_bounds__(256) k_bs_rhs(ClassDev cd, MeshDev md, const double* __restrict__ Wm, long long mstride,
+// W is the eliminated matrix in its storage type T (double or float); the
+// recovery itself runs in FP64.
+template <class T>
+__global__ void __launch_bounds__(256) k_bs_rhs(ClassDev cd, MeshDev md, const T* __restrict__ Wm, long long mstride,
                                                 int ld, int n_cols, const double* __restrict__ x, double* __restrict__ z) {
   extern __shared__ double xs[];
   const int macro = blockIdx.y;
@@ -34,26 +37,27 @@ __global__ void __launch_bounds__(256) k_bs_rhs(ClassDev cd, MeshDev md, const d
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double* Wmac = Wm + (size_t)macro * mstride;
+  const T* Wmac = Wm + (size_t)macro * mstride;
   for (int rr = wave; rr < BS_ROWS; rr += 4) {
     const int r = blockIdx.x * BS_ROWS + rr;
     if (r >= nu) break;
     double s = 0.0;
-    for (int c = lane; c < nb; c += 64) s += Wmac[wtix(r, nu + c, ld)] * xs[c];
+    for (int c = lane; c < nb; c += 64) s += (double)Wmac[wtix(r, nu + c, ld)] * xs[c];
     s = wave_sum(s);
-    if (lane == 0) z[(size_t)macro * nu + r] = Wmac[wtix(r, n_cols - 1, ld)] - s;
+    if (lane == 0) z[(size_t)macro * nu + r] = (double)Wmac[wtix(r, n_cols - 1, ld)] - s;
   }
 }
 
 // Backward substitution U du = z in place (z -> du), one workgroup per macro,
 // blocks of 64 rows from the bottom.
-__global__ void __launch_bounds__(256) k_bs_trsv(ClassDev cd, const double* __restrict__ Wm, long long mstride, int ld,
+template <class T>
+__global__ void __launch_bounds__(256) k_bs_trsv(ClassDev cd, const T* __restrict__ Wm, long long mstride, int ld,
                                                  double* __restrict__ du) {
   __shared__ double sU[BS_ROWS][BS_ROWS + 1];
   __shared__ double sz[BS_ROWS];
   const int macro = blockIdx.x;
   const int nu = cd.n_u;
-  const double* U = Wm + (size_t)macro * mstride;
+  const T* U = Wm + (size_t)macro * mstride;
   double* x = du + (size_t)macro * nu;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nblk = (nu + BS_ROWS - 1) / BS_ROWS;
@@ -63,13 +67,13 @@ __global__ void __launch_bounds__(256) k_bs_trsv(ClassDev cd, const double* __re
     for (int rr = wave; rr < nr; rr += 4) {
       const int r = i0 + rr;
       double s = 0.0;
-      for (int c = i1 + lane; c < nu; c += 64) s += U[wtix(r, c, ld)] * x[c];
+      for (int c = i1 + lane; c < nu; c += 64) s += (double)U[wtix(r, c, ld)] * x[c];
       s = wave_sum(s);
       if (lane == 0) sz[rr] = x[r] - s;
     }
     for (int i = threadIdx.x; i < nr * nr; i += blockDim.x) {
       const int r = i / nr, c = i % nr;
-      sU[r][c] = U[wtix(i0 + r, i0 + c, ld)];
+      sU[r][c] = (double)U[wtix(i0 + r, i0 + c, ld)];
     }
     __syncthreads();
     if (wave == 0) {
@@ -127,9 +131,17 @@ __global__ void k_bs_dq(ClassDev cd, MeshDev md, const double* __restrict__ RQt,
 hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, double* du) {
   const int nu = c.hc.n_u, nb = c.hc.n_b, nm = c.hm.n_macros;
   const long long ms = c.wstride;
-  hipLaunchKernelGGL(k_bs_rhs, dim3((nu + BS_ROWS - 1) / BS_ROWS, nm), dim3(256), (size_t)nb * sizeof(double), c.stream,
-                     c.cd, c.md, c.ws.Wm, ms, c.ldw, c.n_cols, duhat, du);
-  hipLaunchKernelGGL(k_bs_trsv, dim3(nm), dim3(256), 0, c.stream, c.cd, c.ws.Wm, ms, c.ldw, du);
+  const dim3 grid_rhs((nu + BS_ROWS - 1) / BS_ROWS, nm);
+  if (c.cond_prec == 1) {
+    const float* W32 = reinterpret_cast<const float*>(c.ws.Wm);
+    hipLaunchKernelGGL(k_bs_rhs<float>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.cd, c.md, W32, ms,
+                       c.ldw, c.n_cols, duhat, du);
+    hipLaunchKernelGGL(k_bs_trsv<float>, dim3(nm), dim3(256), 0, c.stream, c.cd, W32, ms, c.ldw, du);
+  } else {
+    hipLaunchKernelGGL(k_bs_rhs<double>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.cd, c.md, c.ws.Wm,
+                       ms, c.ldw, c.n_cols, duhat, du);
+    hipLaunchKernelGGL(k_bs_trsv<double>, dim3(nm), dim3(256), 0, c.stream, c.cd, c.ws.Wm, ms, c.ldw, du);
+  }
   hipLaunchKernelGGL(k_bs_dq, dim3(nm * c.cd.dim * c.cd.ns), dim3(256), 0, c.stream, c.cd, c.md, c.ws.RQt, du, duhat, dq);
   return hipGetLastError();
 }

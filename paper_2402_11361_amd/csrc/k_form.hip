@@ -26,9 +26,9 @@ constexpr int FORM_THREADS = 256;
 
 struct FormPtrs {
   const double *AUU, *AUQ, *SUB, *RU, *RQt, *RBloc;
-  double* Wm;
+  double* gloc;  // non-null: g goes here in FP64 and its W entries are 0
   int nsA, dnsA, sub_stride, off_AUB, off_ABU, off_ABQ, off_ABB, ldw, n_cols;
-  long long mstride;  // doubles per macro matrix (tiled, rows padded to 16)
+  long long mstride;  // elements per macro matrix (tiled, rows padded to 16)
 };
 
 __device__ __forceinline__ void digits(int x, int base, int d, int* out) {
@@ -103,7 +103,9 @@ __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, doubl
   }
 }
 
-__global__ void __launch_bounds__(FORM_THREADS) k_form(ClassDev cd, MeshDev md, FormPtrs fp) {
+// The row is accumulated in FP64 and stored as TW (double or float).
+template <class TW>
+__global__ void __launch_bounds__(FORM_THREADS) k_form(ClassDev cd, MeshDev md, FormPtrs fp, TW* __restrict__ Wm) {
   extern __shared__ double row[];
   __shared__ double red[FORM_THREADS];
   const int tid = threadIdx.x;
@@ -205,20 +207,34 @@ __global__ void __launch_bounds__(FORM_THREADS) k_form(ClassDev cd, MeshDev md, 
       if (tid < w) red[tid] += red[tid + w];
       __syncthreads();
     }
-    if (tid == 0) row[fp.n_cols - 1] = red[0] - fp.RBloc[(size_t)macro * cd.n_b + rho];
+    if (tid == 0) {
+      const double g = red[0] - fp.RBloc[(size_t)macro * cd.n_b + rho];
+      if (fp.gloc) {
+        fp.gloc[(size_t)macro * cd.n_b + rho] = g;
+        row[fp.n_cols - 1] = 0.0;
+      } else {
+        row[fp.n_cols - 1] = g;
+      }
+    }
   }
   __syncthreads();
-  double* Wmac = fp.Wm + (size_t)macro * fp.mstride;
-  for (int i = tid; i < fp.ldw; i += FORM_THREADS) Wmac[wtix(r, i, fp.ldw)] = (i < fp.n_cols) ? row[i] : 0.0;
+  TW* Wmac = Wm + (size_t)macro * fp.mstride;
+  for (int i = tid; i < fp.ldw; i += FORM_THREADS) Wmac[wtix(r, i, fp.ldw)] = (i < fp.n_cols) ? (TW)row[i] : TW(0);
 }
 
 }  // namespace
 
-hipError_t launch_form(HdgContext& c) {
-  FormPtrs fp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.ws.RQt, c.ws.RBloc, c.ws.Wm,
+hipError_t launch_form(HdgContext& c, int prec) {
+  // FP32 storage: g of the trace rows stays in FP64 (it is O(1) per macro but
+  // cancels between the two sides of a face in the assembled b-hat)
+  FormPtrs fp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.ws.RQt, c.ws.RBloc, prec == 1 ? c.ws.gloc : nullptr,
               c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.ldw, c.n_cols, c.wstride};
   const long long nblk = (long long)c.hm.n_macros * c.n_rows;
-  hipLaunchKernelGGL(k_form, dim3((unsigned)nblk), dim3(FORM_THREADS), (size_t)c.n_cols * sizeof(double), c.stream,
-                     c.cd, c.md, fp);
+  const size_t shm = (size_t)c.n_cols * sizeof(double);
+  if (prec == 1)
+    hipLaunchKernelGGL(k_form<float>, dim3((unsigned)nblk), dim3(FORM_THREADS), shm, c.stream, c.cd, c.md, fp,
+                       reinterpret_cast<float*>(c.ws.Wm));
+  else
+    hipLaunchKernelGGL(k_form<double>, dim3((unsigned)nblk), dim3(FORM_THREADS), shm, c.stream, c.cd, c.md, fp, c.ws.Wm);
   return hipGetLastError();
 }

@@ -28,8 +28,10 @@ __device__ __forceinline__ int local_face(const ClassDev& cd, int r) {
 // elem_stride < 0 selects the tiled macro matrices: element r of a macro is
 // entry (row0 + r, col) of its tiled matrix with leading dimension -elem_stride,
 // where row0 and col are packed in `tiled_rc` (row0 * 2^32 + col).
-__global__ void k_face_gather_sum(ClassDev cd, MeshDev md, const double* __restrict__ base, long long macro_stride,
-                                  long long elem_stride, double* __restrict__ out, long long tiled_rc) {
+// accumulate != 0 adds to out instead of overwriting it.
+template <class TB>
+__global__ void k_face_gather_sum(ClassDev cd, MeshDev md, const TB* __restrict__ base, long long macro_stride,
+                                  long long elem_stride, double* __restrict__ out, long long tiled_rc, int accumulate) {
   const int d = cd.dim;
   for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < md.n_glob; g += (long long)gridDim.x * blockDim.x) {
     int lo = 0, hi = md.n_faces - 1;
@@ -45,14 +47,14 @@ __global__ void k_face_gather_sum(ClassDev cd, MeshDev md, const double* __restr
     for (int lf = 0; lf < 2 * d; ++lf)
       if (md.macro_face[(size_t)m0 * 2 * d + lf] == F) { k = lf / 2; break; }
     double s = 0.0;
-    auto at = [&](int macro, int idx) {
-      if (elem_stride >= 0) return base[(size_t)macro * macro_stride + (size_t)idx * elem_stride];
+    auto at = [&](int macro, int idx) -> double {
+      if (elem_stride >= 0) return (double)base[(size_t)macro * macro_stride + (size_t)idx * elem_stride];
       const long long row0 = tiled_rc >> 32, col = tiled_rc & 0xffffffffLL;
-      return base[(size_t)macro * macro_stride + wtix(row0 + idx, col, -elem_stride)];
+      return (double)base[(size_t)macro * macro_stride + wtix(row0 + idx, col, -elem_stride)];
     };
     if (mm >= 0) s += at(mm, cd.nf_off[2 * k + 1] + r);
     if (mp >= 0) s += at(mp, cd.nf_off[2 * k] + r);
-    out[g] = s;
+    out[g] = accumulate ? out[g] + s : s;
   }
 }
 
@@ -253,8 +255,8 @@ inline unsigned grid_for(long long n) { return (unsigned)std::max<long long>(1, 
 
 hipError_t launch_face_sum(HdgContext& c, const double* base, long long macro_stride, long long elem_stride, double* out,
                            long long tiled_rc) {
-  hipLaunchKernelGGL(k_face_gather_sum, dim3(grid_for(c.md.n_glob)), dim3(256), 0, c.stream, c.cd, c.md, base,
-                     macro_stride, elem_stride, out, tiled_rc);
+  hipLaunchKernelGGL(k_face_gather_sum<double>, dim3(grid_for(c.md.n_glob)), dim3(256), 0, c.stream, c.cd, c.md, base,
+                     macro_stride, elem_stride, out, tiled_rc, 0);
   return hipGetLastError();
 }
 
@@ -263,9 +265,17 @@ hipError_t launch_zero_ints(hipStream_t s, int* p, int n) {
   return hipGetLastError();
 }
 
-hipError_t launch_bhat(HdgContext& c, double* bhat) {
+hipError_t launch_bhat(HdgContext& c, double* bhat, int prec) {
   // b-hat^{T_i}: column n_cols - 1 of rows [n_u, n_u + n_b) of each tiled matrix
   const long long rc = ((long long)c.hc.n_u << 32) | (long long)(c.n_cols - 1);
+  if (prec == 1) {
+    // FP64 g first, then the FP32 correction -D S^{-1} f on top
+    hipError_t e = launch_face_sum(c, c.ws.gloc, c.hc.n_b, 1, bhat, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_face_gather_sum<float>, dim3(grid_for(c.md.n_glob)), dim3(256), 0, c.stream, c.cd, c.md,
+                       reinterpret_cast<const float*>(c.ws.Wm), c.wstride, -(long long)c.ldw, bhat, rc, 1);
+    return hipGetLastError();
+  }
   return launch_face_sum(c, c.ws.Wm, c.wstride, -(long long)c.ldw, bhat, rc);
 }
 
@@ -273,7 +283,10 @@ hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec) {
   const int nb = c.hc.n_b;
   dim3 grid((nb + APPLY_ROWS - 1) / APPLY_ROWS, c.hm.n_macros);
   const size_t shm = (size_t)nb * sizeof(double);
-  if (prec == 1 && c.have_a32) {
+  if (c.cond_prec == 1) {  // FP32 condensation: the operator itself is FP32
+    hipLaunchKernelGGL((k_apply_local<float, true>), grid, dim3(256), shm, c.stream, c.cd, c.md,
+                       reinterpret_cast<const float*>(c.ws.Wm), c.wstride, (long long)c.ldw, x, c.ws.ypart, c.hc.n_u);
+  } else if (prec == 1 && c.have_a32) {
     hipLaunchKernelGGL((k_apply_local<float, false>), grid, dim3(256), shm, c.stream, c.cd, c.md, c.ws.A32,
                        (long long)nb * nb, (long long)nb, x, c.ws.ypart, 0);
   } else {
@@ -283,8 +296,9 @@ hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec) {
   return launch_face_sum(c, c.ws.ypart, nb, 1, y, 0);
 }
 
-hipError_t lu_eliminate(hipStream_t s, double* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
-                        int n_cols, int* ipiv, int ipiv_stride, int* status, double* scratch);
+template <class T>
+hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
+                        int n_cols, int* ipiv, int ipiv_stride, int* status, T* scratch);
 
 hipError_t launch_face_precond(HdgContext& c) {
   const long long fs = c.fstride;
@@ -299,7 +313,7 @@ hipError_t launch_face_precond(HdgContext& c) {
     if (std::find(sizes.begin(), sizes.end(), c.hm.face_ndof[f]) == sizes.end()) sizes.push_back(c.hm.face_ndof[f]);
   if (sizes.size() == 1) {
     const int nf = sizes[0];
-    return lu_eliminate(c.stream, c.ws.FW, c.hm.n_faces, fs, c.ldf, nf, 2 * nf, 2 * nf, c.ws.fpiv, c.nf_max,
+    return lu_eliminate<double>(c.stream, c.ws.FW, c.hm.n_faces, fs, c.ldf, nf, 2 * nf, 2 * nf, c.ws.fpiv, c.nf_max,
                         reinterpret_cast<int*>(c.ws.small) + 1, c.ws.Uinv);
   }
   // several face sizes: runs of consecutive faces with the same size
@@ -308,7 +322,7 @@ hipError_t launch_face_precond(HdgContext& c) {
     int f1 = f0;
     while (f1 < c.hm.n_faces && c.hm.face_ndof[f1] == c.hm.face_ndof[f0]) ++f1;
     const int nf = c.hm.face_ndof[f0];
-    e = lu_eliminate(c.stream, c.ws.FW + (size_t)f0 * fs, f1 - f0, fs, c.ldf, nf, 2 * nf, 2 * nf,
+    e = lu_eliminate<double>(c.stream, c.ws.FW + (size_t)f0 * fs, f1 - f0, fs, c.ldf, nf, 2 * nf, 2 * nf,
                      c.ws.fpiv + (size_t)f0 * c.nf_max, c.nf_max, reinterpret_cast<int*>(c.ws.small) + 1, c.ws.Uinv);
     if (e != hipSuccess) return e;
     f0 = f1;

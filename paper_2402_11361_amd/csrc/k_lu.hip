@@ -17,21 +17,41 @@
 //   k_dtrsm   L of the non-pivot rows: A_D,block U11^{-1};
 //   k_update  one workgroup per (matrix, 64-column strip): row swaps, the
 //             strip of U12 = L11^{-1} A12, and A22 -= L21 U12 on FP64 MFMA
-//             (v_mfma_f64_16x16x4f64).
+//             (v_mfma_f64_16x16x4f64 in FP64, v_mfma_f32_16x16x4f32 in FP32).
+// Every kernel is a template on the storage and arithmetic type T (double or
+// float); the FP32 instance is the low-precision condensation.
 #include "context.h"
 
 namespace {
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
+// 16x16x4 MFMA per element type.  Operands: lane l supplies A[l % 16][k] and
+// B[k][l % 16] with k = l / 16; result register i of lane l holds
+// D[row(i, l / 16)][l % 16].
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int i, int grp) { return 4 * i + grp; }
+};
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int i, int grp) { return 4 * grp + i; }
+};
 
 constexpr int NB = 64;     // block width of the trailing update
 constexpr int PW = 16;     // sub-panel width held in registers
 constexpr int PANEL_THREADS = 512;
 constexpr int NC = 64;     // strip width of the trailing update
 
+template <class T>
 struct LuArgs {
-  double* W;
-  long long mat_stride;  // doubles between matrices
+  T* W;
+  long long mat_stride;  // elements between matrices
   int ld, n_piv, n_rows, n_cols;
   int* ipiv;             // [batch][n_piv]
   int ipiv_stride;
@@ -44,63 +64,65 @@ struct LuArgs {
 // perm[3 NB] = nout.
 constexpr int PERM_STRIDE = 3 * 64 + 4;
 // two slots per matrix (consecutive 64-column blocks alternate)
-__device__ __forceinline__ int* perm_slot(const LuArgs& a, int mat, int j0) {
+template <class T>
+__device__ __forceinline__ int* perm_slot(const LuArgs<T>& a, int mat, int j0) {
   return a.perm + ((size_t)mat * 2 + ((j0 / 64) & 1)) * PERM_STRIDE;
 }
 
-__device__ __forceinline__ void argmax_update(double& bv, int& bi, double v, int i) {
+template <class T>
+__device__ __forceinline__ void argmax_update(T& bv, int& bi, T v, int i) {
   if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
 }
 
-template <int RPT>
-__global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int jb, int lcol0) {
+template <class T, int RPT>
+__global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs<T> a, int j0, int jb, int lcol0) {
   const int tid = threadIdx.x;
   const int mat = blockIdx.x;
-  double* W = a.W + (size_t)mat * a.mat_stride;
+  T* W = a.W + (size_t)mat * a.mat_stride;
   int* ipiv = a.ipiv + (size_t)mat * a.ipiv_stride;
   const int ld = a.ld, n_piv = a.n_piv;
-  __shared__ double s_bv[PANEL_THREADS / 64];
+  __shared__ T s_bv[PANEL_THREADS / 64];
   __shared__ int s_bi[PANEL_THREADS / 64];
   __shared__ int s_prow;
-  __shared__ double s_urow[PW];
-  __shared__ double s_swap[2][PW];
-  __shared__ double s_U[PW * NB];
+  __shared__ T s_urow[PW];
+  __shared__ T s_swap[2][PW];
+  __shared__ T s_U[PW * NB];
   for (int c0 = j0; c0 < j0 + jb; c0 += PW) {
     const int pw = min(PW, j0 + jb - c0);
     // rows owned by this thread: c0 + tid + i * PANEL_THREADS
-    double v[RPT][PW];
+    T v[RPT][PW];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = c0 + tid + i * PANEL_THREADS;
 #pragma unroll
-      for (int cc = 0; cc < PW; ++cc) v[i][cc] = (r < n_piv && cc < pw) ? W[wtix(r, c0 + cc, ld)] : 0.0;
+      for (int cc = 0; cc < PW; ++cc) v[i][cc] = (r < n_piv && cc < pw) ? W[wtix(r, c0 + cc, ld)] : T(0);
     }
     for (int cc = 0; cc < pw; ++cc) {
       {
       const int col = c0 + cc;
       // pivot search over rows [col, n_piv)
-      double bv = -1.0;
+      T bv = T(-1);
       int bi = 0x7fffffff;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const int r = c0 + tid + i * PANEL_THREADS;
-        double vc = v[i][0];
+        T vc = v[i][0];
 #pragma unroll
         for (int k = 1; k < PW; ++k) vc = (k == cc) ? v[i][k] : vc;
-        if (r >= col && r < n_piv) argmax_update(bv, bi, fabs(vc), r);
+        if (r >= col && r < n_piv) argmax_update<T>(bv, bi, fabs(vc), r);
       }
       for (int off = 32; off > 0; off >>= 1) {
-        double ov = __shfl_xor(bv, off, 64);
+        T ov = __shfl_xor(bv, off, 64);
         int oi = __shfl_xor(bi, off, 64);
-        argmax_update(bv, bi, ov, oi);
+        argmax_update<T>(bv, bi, ov, oi);
       }
       if ((tid & 63) == 0) { s_bv[tid >> 6] = bv; s_bi[tid >> 6] = bi; }
       __syncthreads();
       if (tid == 0) {
-        double b = s_bv[0];
+        T b = s_bv[0];
         int bi0 = s_bi[0];
-        for (int w = 1; w < PANEL_THREADS / 64; ++w) argmax_update(b, bi0, s_bv[w], s_bi[w]);
-        if (!(b > 0.0)) {  // zero or NaN column: singular
+        for (int w = 1; w < PANEL_THREADS / 64; ++w) argmax_update<T>(b, bi0, s_bv[w], s_bi[w]);
+        if (!(b > T(0))) {  // zero or NaN column: singular
           if (a.status) atomicCAS(a.status, 0, mat + 1);
           bi0 = col;
         }
@@ -141,7 +163,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
         for (int k = tid; k < j0 + jb - lcol0; k += PANEL_THREADS) {
           const int cidx = lcol0 + k;  // L columns of a previous block too (lcol0 < j0)
           if (cidx >= c0 && cidx < c0 + pw) continue;
-          double t = W[wtix(col, cidx, ld)];
+          T t = W[wtix(col, cidx, ld)];
           W[wtix(col, cidx, ld)] = W[wtix(prow, cidx, ld)];
           W[wtix(prow, cidx, ld)] = t;
         }
@@ -155,16 +177,16 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
         }
       }
       __syncthreads();
-      const double piv = s_urow[cc];
-      const double ipv = (piv != 0.0) ? 1.0 / piv : 0.0;
+      const T piv = s_urow[cc];
+      const T ipv = (piv != T(0)) ? T(1) / piv : T(0);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
         const int r = c0 + tid + i * PANEL_THREADS;
         if (r > col && r < n_piv) {
-          double vc = v[i][0];
+          T vc = v[i][0];
 #pragma unroll
           for (int k = 1; k < PW; ++k) vc = (k == cc) ? v[i][k] : vc;
-          const double l = vc * ipv;
+          const T l = vc * ipv;
 #pragma unroll
           for (int k = 0; k < PW; ++k) {
             if (k == cc) v[i][k] = l;
@@ -192,7 +214,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
       // U rows of the sub-panel: L_sub^{-1} A[c0:c0+pw, rest]  (unit lower, sequential rows)
       for (int k = tid; k < nrest; k += PANEL_THREADS) {
         for (int i = 0; i < pw; ++i) {
-          double s = W[wtix((c0 + i), rest0 + k, ld)];
+          T s = W[wtix((c0 + i), rest0 + k, ld)];
           for (int m = 0; m < i; ++m) s -= W[wtix((c0 + i), c0 + m, ld)] * s_U[m * NB + k];
           s_U[i * NB + k] = s;
         }
@@ -209,7 +231,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
         if (r >= c0 + pw && r < n_piv) {
 #pragma unroll 4
           for (int cidx = 0; cidx < nrest; ++cidx) {
-            double s = W[wtix(r, rest0 + cidx, ld)];
+            T s = W[wtix(r, rest0 + cidx, ld)];
 #pragma unroll
             for (int m = 0; m < PW; ++m)
               if (m < pw) s -= v[i][m] * s_U[m * NB + cidx];
@@ -248,44 +270,46 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs a, int j0, int j
 
 // U11^{-1} of the block (identity-padded to NB x NB) into Uinv[mat]: one
 // thread per column, backward substitution in LDS.
-__global__ void __launch_bounds__(64) k_uinv(LuArgs a, int j0, int jb, double* __restrict__ Uinv) {
+template <class T>
+__global__ void __launch_bounds__(64) k_uinv(LuArgs<T> a, int j0, int jb, T* __restrict__ Uinv) {
   const int mat = blockIdx.x;
-  const double* W = a.W + (size_t)mat * a.mat_stride;
+  const T* W = a.W + (size_t)mat * a.mat_stride;
   const int ld = a.ld;
-  __shared__ double sU[NB * NB];
-  __shared__ double sI[NB * NB];
+  __shared__ T sU[NB * NB];
+  __shared__ T sI[NB * NB];
   for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) {
     const int r = i / NB, c = i % NB;
-    double v = (r == c) ? 1.0 : 0.0;
+    T v = (r == c) ? T(1) : T(0);
     if (r < jb && c < jb) v = W[wtix((j0 + r), j0 + c, ld)];
     sU[i] = v;
   }
   __syncthreads();
   const int j = threadIdx.x;
   for (int i = NB - 1; i >= 0; --i) {
-    double s = (i == j) ? 1.0 : 0.0;
+    T s = (i == j) ? T(1) : T(0);
     for (int m = i + 1; m <= j; ++m) s -= sU[i * NB + m] * sI[m * NB + j];
-    const double dgl = sU[i * NB + i];
-    sI[i * NB + j] = (i <= j && dgl != 0.0) ? s / dgl : 0.0;
+    const T dgl = sU[i * NB + i];
+    sI[i * NB + j] = (i <= j && dgl != T(0)) ? s / dgl : T(0);
   }
   __syncthreads();
-  double* out = Uinv + (size_t)mat * NB * NB;
+  T* out = Uinv + (size_t)mat * NB * NB;
   for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) out[i] = sI[i];
 }
 
 // Row swaps of the block and U12 = L11^{-1} A12 for one 64-column strip,
 // written back in place (rows [j0, j0 + jb) of the strip).  Columns below
 // live0 = j0 + jb or at/after ld are left alone.
-__global__ void __launch_bounds__(256) k_u12(LuArgs a, int j0, int jb, int strip0, int col_end) {
+template <class T>
+__global__ void __launch_bounds__(256) k_u12(LuArgs<T> a, int j0, int jb, int strip0, int col_end) {
   const int mat = blockIdx.y;
   const int cs = strip0 + blockIdx.x * NC;
   const int live0 = j0 + jb;
-  double* W = a.W + (size_t)mat * a.mat_stride;
+  T* W = a.W + (size_t)mat * a.mat_stride;
   const int* pm = perm_slot(a, mat, j0);
   const int ld = a.ld, tid = threadIdx.x;
-  __shared__ double sL[NB * NB];
-  __shared__ double sU[NB * NC];
-  __shared__ double sP[4][NC];
+  __shared__ T sL[NB * NB];
+  __shared__ T sU[NB * NC];
+  __shared__ T sP[4][NC];
   __shared__ int s_src[2 * NB], s_dst[2 * NB];
   // the block's swaps as one gather: block rows and the nout rows outside it
   const int nout = pm[3 * NB];
@@ -296,11 +320,11 @@ __global__ void __launch_bounds__(256) k_u12(LuArgs a, int j0, int jb, int strip
   const int c = tid & (NC - 1);
   const bool cok = cs + c >= live0 && cs + c < col_end;
   // each thread gathers the values of its column for touched rows p = tid/64 + 4 j
-  double gv[2 * NB / 4];
+  T gv[2 * NB / 4];
 #pragma unroll
   for (int j = 0; j < 2 * NB / 4; ++j) {
     const int p = (tid >> 6) + 4 * j;
-    gv[j] = (p < nt && cok) ? W[wtix(s_src[p], cs + c, ld)] : 0.0;
+    gv[j] = (p < nt && cok) ? W[wtix(s_src[p], cs + c, ld)] : T(0);
   }
   __syncthreads();
 #pragma unroll
@@ -313,17 +337,17 @@ __global__ void __launch_bounds__(256) k_u12(LuArgs a, int j0, int jb, int strip
   }
   for (int i = tid; i < NB * NB; i += 256) {
     const int r = i / NB, cc = i % NB;
-    sL[i] = (r < jb && cc < jb) ? W[wtix((j0 + r), j0 + cc, ld)] : 0.0;
+    sL[i] = (r < jb && cc < jb) ? W[wtix((j0 + r), j0 + cc, ld)] : T(0);
   }
   for (int i = tid; i < NB * NC; i += 256) {
     const int r = i / NC, cc = i % NC;
-    if (!(r < jb && cs + cc >= live0 && cs + cc < col_end)) sU[i] = 0.0;
+    if (!(r < jb && cs + cc >= live0 && cs + cc < col_end)) sU[i] = T(0);
   }
   __syncthreads();
   {
     const int col = tid % NC, part = tid / NC;
     for (int i = 1; i < jb; ++i) {
-      double s = 0.0;
+      T s = T(0);
       for (int m = part; m < i; m += 4) s += sL[i * NB + m] * sU[m * NC + col];
       sP[part][col] = s;
       __syncthreads();
@@ -339,10 +363,11 @@ __global__ void __launch_bounds__(256) k_u12(LuArgs a, int j0, int jb, int strip
 
 // In-place unit-lower triangular solve X = L^{-1} X in LDS (L: n x n in sL
 // with leading dimension NB, X: n x 64 in sX), the inner sums split in four.
-__device__ void trsm_lds(const double* sL, double* sX, int n, double (*sP)[NC], int tid) {
+template <class T>
+__device__ void trsm_lds(const T* sL, T* sX, int n, T (*sP)[NC], int tid) {
   const int col = tid % NC, part = tid / NC;
   for (int i = 1; i < n; ++i) {
-    double s = 0.0;
+    T s = T(0);
     for (int m = part; m < i; m += 4) s += sL[i * NB + m] * sX[m * NC + col];
     sP[part][col] = s;
     __syncthreads();
@@ -355,16 +380,17 @@ __device__ void trsm_lds(const double* sL, double* sX, int n, double (*sP)[NC], 
 // applied to one strip right of both: the row swaps of b1 then b2, then
 //   U12_1 = L11^{-1} A12_1,  A12_2 -= L21(b2 rows, b1 cols) U12_1,  U12_2 = L22^{-1} A12_2,
 // written back to the rows [j0, j0 + 64 + jb2) of the strip.
-__global__ void __launch_bounds__(256) k_u12b2(LuArgs a, int j0, int jb2, int strip0) {
+template <class T>
+__global__ void __launch_bounds__(256) k_u12b2(LuArgs<T> a, int j0, int jb2, int strip0) {
   const int mat = blockIdx.y;
   const int cs = strip0 + blockIdx.x * NC;
   const int live0 = j0 + NB + jb2;
-  double* W = a.W + (size_t)mat * a.mat_stride;
+  T* W = a.W + (size_t)mat * a.mat_stride;
   const int ld = a.ld, tid = threadIdx.x;
-  __shared__ double sL[NB * NB];
-  __shared__ double sU1[NB * NC];
-  __shared__ double sU2[NB * NC];
-  __shared__ double sP[4][NC];
+  __shared__ T sL[NB * NB];
+  __shared__ T sU1[NB * NC];
+  __shared__ T sU2[NB * NC];
+  __shared__ T sP[4][NC];
   __shared__ int s_src[2 * NB], s_dst[2 * NB];
   const int c = tid & (NC - 1);
   const bool cok = cs + c >= live0 && cs + c < ld;
@@ -376,11 +402,11 @@ __global__ void __launch_bounds__(256) k_u12b2(LuArgs a, int j0, int jb2, int st
     for (int k = tid; k < nout; k += 256) { s_dst[jbb + k] = pm[NB + k]; s_src[jbb + k] = pm[2 * NB + k]; }
     __syncthreads();
     const int nt = jbb + nout;
-    double gv[2 * NB / 4];
+    T gv[2 * NB / 4];
 #pragma unroll
     for (int j = 0; j < 2 * NB / 4; ++j) {
       const int p = (tid >> 6) + 4 * j;
-      gv[j] = (p < nt && cok) ? W[wtix(s_src[p], cs + c, ld)] : 0.0;
+      gv[j] = (p < nt && cok) ? W[wtix(s_src[p], cs + c, ld)] : T(0);
     }
     __syncthreads();
 #pragma unroll
@@ -397,20 +423,20 @@ __global__ void __launch_bounds__(256) k_u12b2(LuArgs a, int j0, int jb2, int st
   for (int i = tid; i < NB * NC; i += 256) {
     const int r = i / NC, cc = i % NC;
     const bool ok = cs + cc >= live0 && cs + cc < ld;
-    sU1[i] = ok ? W[wtix((j0 + r), cs + cc, ld)] : 0.0;
-    sU2[i] = (ok && r < jb2) ? W[wtix((j0 + NB + r), cs + cc, ld)] : 0.0;
+    sU1[i] = ok ? W[wtix((j0 + r), cs + cc, ld)] : T(0);
+    sU2[i] = (ok && r < jb2) ? W[wtix((j0 + NB + r), cs + cc, ld)] : T(0);
   }
   __syncthreads();
   trsm_lds(sL, sU1, NB, sP, tid);
   for (int i = tid; i < NB * NB; i += 256) {
     const int r = i / NB, cc = i % NB;
-    sL[i] = (r < jb2) ? W[wtix((j0 + NB + r), j0 + cc, ld)] : 0.0;
+    sL[i] = (r < jb2) ? W[wtix((j0 + NB + r), j0 + cc, ld)] : T(0);
   }
   __syncthreads();
   {
     const int col = tid % NC, part = tid / NC;
     for (int i = part; i < jb2; i += 4) {
-      double s = 0.0;
+      T s = T(0);
       for (int m = 0; m < NB; ++m) s += sL[i * NB + m] * sU1[m * NC + col];
       sU2[i * NC + col] -= s;
     }
@@ -418,7 +444,7 @@ __global__ void __launch_bounds__(256) k_u12b2(LuArgs a, int j0, int jb2, int st
   __syncthreads();
   for (int i = tid; i < NB * NB; i += 256) {
     const int r = i / NB, cc = i % NB;
-    sL[i] = (r < jb2 && cc < jb2) ? W[wtix((j0 + NB + r), j0 + NB + cc, ld)] : 0.0;
+    sL[i] = (r < jb2 && cc < jb2) ? W[wtix((j0 + NB + r), j0 + NB + cc, ld)] : T(0);
   }
   __syncthreads();
   trsm_lds(sL, sU2, jb2, sP, tid);
@@ -437,64 +463,66 @@ __global__ void __launch_bounds__(256) k_u12b2(LuArgs a, int j0, int jb2, int st
 // is staged in LDS.  The k index of an MFMA step is k = 16 (lane / 16) + step,
 // so every lane loads 16 consecutive A values of its row.  Columns outside
 // [c_lo, ld) are masked (read as 0, never written).
+template <class T>
 struct GemmArgs {
-  double* W;
+  T* W;
   long long mat_stride;
   int ld;
-  const double* B;
+  const T* B;
   long long b_mat_stride;
   int ldb;
   int b_col_follow;  // 1: B = rows [b_row0, b_row0 + K) of the strip in W itself; 0: plain K x 64 B
   int b_row0;
   int ak0, K, cs0, c_lo, c_hi, r_lo, r_hi;
-  double alpha;
+  T alpha;
   int beta;
   int tiles_per_wg;
 };
 
-template <int KB>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+template <class T, int KB>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> g) {
+  typedef typename Mfma<T>::v4 v4;
   constexpr int KS = KB / 4;  // MFMA k-steps; lane group grp covers k in [KS grp, KS grp + KS)
   const int mat = blockIdx.z;
   const int cs = g.cs0 + blockIdx.x * NC;
-  double* W = g.W + (size_t)mat * g.mat_stride;
-  const double* B = g.B + (size_t)mat * g.b_mat_stride;
+  T* W = g.W + (size_t)mat * g.mat_stride;
+  const T* B = g.B + (size_t)mat * g.b_mat_stride;
   const int ld = g.ld, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int grp = lane >> 4, col = lane & 15;
-  __shared__ double sB[KB * NC];
+  __shared__ T sB[KB * NC];
   for (int i = tid; i < KB * NC; i += 256) {
     const int k = i / NC, c = i % NC;
-    sB[i] = (k < g.K && cs + c >= g.c_lo && cs + c < g.c_hi) ? (g.b_col_follow ? W[wtix(g.b_row0 + k, cs + c, ld)] : B[(size_t)k * g.ldb + c]) : 0.0;
+    sB[i] = (k < g.K && cs + c >= g.c_lo && cs + c < g.c_hi) ? (g.b_col_follow ? W[wtix(g.b_row0 + k, cs + c, ld)] : B[(size_t)k * g.ldb + c]) : T(0);
   }
   __syncthreads();
   const int tile0 = blockIdx.y * g.tiles_per_wg;
-  auto load_a = [&](int r0, double* af) {
+  auto load_a = [&](int r0, T* af) {
     const int ra = r0 + col;
     const int kb = KS * grp;
     // the KS consecutive columns of a lane group lie inside one 64-column tile
-    const double* ap = W + wtix(ra, g.ak0 + kb, ld);
+    const T* ap = W + wtix(ra, g.ak0 + kb, ld);
     if (ra < g.r_hi && kb + KS <= g.K) {  // fast path: unmasked contiguous loads
 #pragma unroll
       for (int s = 0; s < KS; ++s) af[s] = g.alpha * ap[s];
     } else {
 #pragma unroll
-      for (int s = 0; s < KS; ++s) af[s] = (ra < g.r_hi && kb + s < g.K) ? g.alpha * ap[s] : 0.0;
+      for (int s = 0; s < KS; ++s) af[s] = (ra < g.r_hi && kb + s < g.K) ? g.alpha * ap[s] : T(0);
     }
   };
-  auto load_c = [&](int r0, dbl4* acc) {
+  auto load_c = [&](int r0, v4* acc) {
 #pragma unroll
     for (int ct = 0; ct < NC / 16; ++ct) {
       const int cc = cs + ct * 16 + col;
       const bool cok = cc >= g.c_lo && cc < g.c_hi;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = r0 + 4 * i + grp;  // f64 16x16x4: D[4 reg + lane/16][lane%16]
-        acc[ct][i] = (g.beta && r < g.r_hi && cok) ? W[wtix(r, cc, ld)] : 0.0;
+        const int r = r0 + Mfma<T>::row(i, grp);
+        acc[ct][i] = (g.beta && r < g.r_hi && cok) ? W[wtix(r, cc, ld)] : T(0);
       }
     }
   };
-  double af[KS];
-  dbl4 acc[NC / 16];
+  T af[KS];
+  v4 acc[NC / 16];
   for (int t = wave; t < g.tiles_per_wg; t += 4) {
     const int r0 = g.r_lo + (tile0 + t) * 16;
     if (r0 >= g.r_hi) break;
@@ -504,8 +532,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     for (int s = 0; s < KS; ++s) {
 #pragma unroll
       for (int ct = 0; ct < NC / 16; ++ct) {
-        const double bv = sB[(KS * grp + s) * NC + ct * 16 + col];
-        acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s], bv, acc[ct], 0, 0, 0);
+        const T bv = sB[(KS * grp + s) * NC + ct * 16 + col];
+        acc[ct] = Mfma<T>::op(af[s], bv, acc[ct]);
       }
     }
 #pragma unroll
@@ -514,7 +542,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       const bool cok = cc >= g.c_lo && cc < g.c_hi;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = r0 + 4 * i + grp;
+        const int r = r0 + Mfma<T>::row(i, grp);
         if (r < g.r_hi && cok) W[wtix(r, cc, ld)] = acc[ct][i];
       }
     }
@@ -524,37 +552,37 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 }  // namespace
 
 // Eliminate the first n_piv columns of `batch` matrices (see file comment).
-// scratch: batch * NB * NB doubles for the block inverses.
-hipError_t lu_eliminate(hipStream_t s, double* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
-                        int n_cols, int* ipiv, int ipiv_stride, int* status, double* scratch) {
-  // scratch: batch NB x NB block inverses, then batch x 2 PERM_STRIDE ints
+// scratch: batch NB x NB block inverses (type T), then batch x 2 PERM_STRIDE ints.
+template <class T>
+hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
+                        int n_cols, int* ipiv, int ipiv_stride, int* status, T* scratch) {
   int* perm = reinterpret_cast<int*>(scratch + (size_t)batch * NB * NB);
-  LuArgs a{W, mat_stride, ld, n_piv, n_rows, n_cols, ipiv, ipiv_stride, status, perm};
+  LuArgs<T> a{W, mat_stride, ld, n_piv, n_rows, n_cols, ipiv, ipiv_stride, status, perm};
   if (ld % NC != 0) return hipErrorInvalidValue;
   const int rpt = (n_piv + PANEL_THREADS - 1) / PANEL_THREADS;
   constexpr int TPW = 32;  // 16-row tiles per workgroup (8 per wave)
   auto panel = [&](int j0, int jb, int lcol0) {
-    if (rpt <= 1) hipLaunchKernelGGL(k_panel<1>, dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
-    else if (rpt <= 2) hipLaunchKernelGGL(k_panel<2>, dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
-    else if (rpt <= 4) hipLaunchKernelGGL(k_panel<4>, dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
-    else hipLaunchKernelGGL(k_panel<8>, dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
+    if (rpt <= 1) hipLaunchKernelGGL((k_panel<T, 1>), dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
+    else if (rpt <= 2) hipLaunchKernelGGL((k_panel<T, 2>), dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
+    else if (rpt <= 4) hipLaunchKernelGGL((k_panel<T, 4>), dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
+    else hipLaunchKernelGGL((k_panel<T, 8>), dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
   };
   auto drows = [&](int j0, int jb) {  // L of the non-pivot rows: A_D,block U11^{-1}
     if (n_rows <= n_piv) return;
-    hipLaunchKernelGGL(k_uinv, dim3(batch), dim3(NB), 0, s, a, j0, jb, scratch);
-    GemmArgs g{W, mat_stride, ld, scratch, (long long)NB * NB, NB, 0, 0, j0, jb, j0, j0, j0 + jb, n_piv, n_rows, 1.0, 0, TPW};
+    hipLaunchKernelGGL(k_uinv<T>, dim3(batch), dim3(NB), 0, s, a, j0, jb, scratch);
+    GemmArgs<T> g{W, mat_stride, ld, scratch, (long long)NB * NB, NB, 0, 0, j0, jb, j0, j0, j0 + jb, n_piv, n_rows, T(1), 0, TPW};
     const int ntile = (n_rows - n_piv + 15) / 16;
-    hipLaunchKernelGGL(k_gemm<64>, dim3(1, (ntile + TPW - 1) / TPW, batch), dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_gemm<T, 64>), dim3(1, (ntile + TPW - 1) / TPW, batch), dim3(256), 0, s, g);
   };
   // A22 -= L21 U12 for the strips [strip0, ...) with U12 in rows [j0, j0 + K) of W
   auto update = [&](int j0, int K, int live0, int strip0, int nstrip, int col_end) {
     if (n_rows <= live0 || nstrip <= 0) return;
-    GemmArgs g{W, mat_stride, ld, W, mat_stride, ld, 1, j0, j0, K, strip0, live0, col_end, live0, n_rows,
-               -1.0, 1, TPW};
+    GemmArgs<T> g{W, mat_stride, ld, W, mat_stride, ld, 1, j0, j0, K, strip0, live0, col_end, live0, n_rows,
+                  T(-1), 1, TPW};
     const int ntile = (n_rows - live0 + 15) / 16;
     dim3 grid(nstrip, (ntile + TPW - 1) / TPW, batch);
-    if (K > NB) hipLaunchKernelGGL(k_gemm<2 * NB>, grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL(k_gemm<NB>, grid, dim3(256), 0, s, g);
+    if (K > NB) hipLaunchKernelGGL((k_gemm<T, 2 * NB>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_gemm<T, NB>), grid, dim3(256), 0, s, g);
   };
   if (rpt > 8) return hipErrorInvalidValue;
   for (int j0 = 0; j0 < n_piv; j0 += 2 * NB) {
@@ -566,13 +594,13 @@ hipError_t lu_eliminate(hipStream_t s, double* W, int batch, long long mat_strid
       const int live0 = j0 + jb1, strip0 = live0 / NC * NC;
       const int nstrip = (n_cols > live0) ? (n_cols - strip0 + NC - 1) / NC : 0;
       if (nstrip > 0) {
-        hipLaunchKernelGGL(k_u12, dim3(nstrip, batch), dim3(256), 0, s, a, j0, jb1, strip0, ld);
+        hipLaunchKernelGGL(k_u12<T>, dim3(nstrip, batch), dim3(256), 0, s, a, j0, jb1, strip0, ld);
         update(j0, jb1, live0, strip0, nstrip, ld);
       }
       continue;
     }
     // look-ahead: bring the second block's columns up to date with the first
-    hipLaunchKernelGGL(k_u12, dim3(1, batch), dim3(256), 0, s, a, j0, NB, j0 + NB, j0 + NB + std::min(NB, n_piv - (j0 + NB)));
+    hipLaunchKernelGGL(k_u12<T>, dim3(1, batch), dim3(256), 0, s, a, j0, NB, j0 + NB, j0 + NB + std::min(NB, n_piv - (j0 + NB)));
     update(j0, NB, j0 + NB, j0 + NB, 1, j0 + NB + std::min(NB, n_piv - (j0 + NB)));
     const int jb2 = std::min(NB, n_piv - (j0 + NB));
     panel(j0 + NB, jb2, j0);  // also swaps the first block's L columns
@@ -581,14 +609,23 @@ hipError_t lu_eliminate(hipStream_t s, double* W, int batch, long long mat_strid
     const int live0 = j0 + NB + jb2, strip0 = live0 / NC * NC;
     const int nstrip = (n_cols > live0) ? (n_cols - strip0 + NC - 1) / NC : 0;
     if (nstrip > 0) {
-      hipLaunchKernelGGL(k_u12b2, dim3(nstrip, batch), dim3(256), 0, s, a, j0, jb2, strip0);
+      hipLaunchKernelGGL(k_u12b2<T>, dim3(nstrip, batch), dim3(256), 0, s, a, j0, jb2, strip0);
       update(j0, NB + jb2, live0, strip0, nstrip, ld);
     }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_lu(HdgContext& c) {
-  return lu_eliminate(c.stream, c.ws.Wm, c.hm.n_macros, c.wstride, c.ldw, c.hc.n_u, c.n_rows,
-                      c.n_cols, c.ws.ipiv, c.hc.n_u, reinterpret_cast<int*>(c.ws.small), c.ws.Uinv);
+template hipError_t lu_eliminate<double>(hipStream_t, double*, int, long long, int, int, int, int, int*, int, int*,
+                                         double*);
+template hipError_t lu_eliminate<float>(hipStream_t, float*, int, long long, int, int, int, int, int*, int, int*,
+                                        float*);
+
+hipError_t launch_lu(HdgContext& c, int prec) {
+  if (prec == 1)
+    return lu_eliminate<float>(c.stream, reinterpret_cast<float*>(c.ws.Wm), c.hm.n_macros, c.wstride, c.ldw, c.hc.n_u,
+                               c.n_rows, c.n_cols, c.ws.ipiv, c.hc.n_u, reinterpret_cast<int*>(c.ws.small),
+                               reinterpret_cast<float*>(c.ws.Uinv));
+  return lu_eliminate<double>(c.stream, c.ws.Wm, c.hm.n_macros, c.wstride, c.ldw, c.hc.n_u, c.n_rows,
+                              c.n_cols, c.ws.ipiv, c.hc.n_u, reinterpret_cast<int*>(c.ws.small), c.ws.Uinv);
 }

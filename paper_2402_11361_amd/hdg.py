@@ -44,18 +44,29 @@ class _Sizes(ctypes.Structure):
 
 class KrylovOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("restart", ctypes.c_int),
-                ("max_outer", ctypes.c_int), ("inner_its", ctypes.c_int), ("inner_prec", ctypes.c_int)]
+                ("max_outer", ctypes.c_int), ("inner_its", ctypes.c_int), ("inner_prec", ctypes.c_int),
+                ("use_learned", ctypes.c_int), ("harvest", ctypes.c_void_p), ("harvest_max", ctypes.c_int)]
 
 
 class KrylovStats(ctypes.Structure):
     _fields_ = [("outer_its", ctypes.c_int), ("inner_its_total", ctypes.c_int), ("res0", ctypes.c_double),
-                ("res_final", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("res_final", ctypes.c_double), ("ms", ctypes.c_double), ("fallbacks", ctypes.c_int),
+                ("harvested", ctypes.c_int)]
+
+
+class Mlp(ctypes.Structure):
+    """hdg_mlp: shape and device pointers of a two-layer network."""
+    _fields_ = [("n_in", ctypes.c_int), ("n_hidden", ctypes.c_int), ("n_out", ctypes.c_int),
+                ("max_batch", ctypes.c_int), ("params", ctypes.c_void_p), ("grads", ctypes.c_void_p),
+                ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p), ("work", ctypes.c_void_p)]
 
 
 EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_node_coords", "hdg_bind_workspace", "hdg_linearize_stage",
            "hdg_condense", "hdg_apply_global", "hdg_fgmres_solve", "hdg_local_backsolve", "hdg_axpy",
            "hdg_destroy", "hdg_status_string", "hdg_last_error", "hdg_get_condensed", "hdg_get_formed",
-           "hdg_get_residuals"]
+           "hdg_get_residuals", "hdg_precond_apply", "hdg_coarse_size", "hdg_coarse_restrict",
+           "hdg_coarse_prolong", "hdg_mlp_param_count", "hdg_mlp_work_floats", "hdg_mlp_forward",
+           "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind"]
 
 _lib = None
 
@@ -87,9 +98,23 @@ def load_library(path=LIB_PATH):
     lib.hdg_get_condensed.argtypes = [vp, sz, vp, vp]
     lib.hdg_get_formed.argtypes = [vp, sz, vp]
     lib.hdg_get_residuals.argtypes = [vp, vp, vp, vp]
+    fl = ctypes.c_float
+    mp = ctypes.POINTER(Mlp)
+    lib.hdg_precond_apply.argtypes = [vp, vp, vp, i, i, i]
+    lib.hdg_coarse_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.hdg_coarse_restrict.argtypes = [vp, vp, vp]
+    lib.hdg_coarse_prolong.argtypes = [vp, vp, dp, vp]
+    lib.hdg_mlp_param_count.argtypes = [i, i, i]
+    lib.hdg_mlp_work_floats.argtypes = [i, i, i, i]
+    lib.hdg_mlp_forward.argtypes = [vp, mp, vp, vp, i, vp]
+    lib.hdg_mlp_loss_grad.argtypes = [vp, mp, vp, vp, vp, i, vp]
+    lib.hdg_mlp_adam.argtypes = [vp, mp, fl, fl, fl, fl, i]
+    lib.hdg_learned_bind.argtypes = [vp, mp]
     for name in EXPORTS:
         if name not in ("hdg_status_string", "hdg_last_error"):
             getattr(lib, name).restype = ctypes.c_int
+    lib.hdg_mlp_param_count.restype = ctypes.c_size_t
+    lib.hdg_mlp_work_floats.restype = ctypes.c_size_t
     _lib = lib
     return lib
 
@@ -189,14 +214,45 @@ class Context:
         self._check(self.lib.hdg_apply_global(self.h, _ptr(x), _ptr(y)))
 
     def fgmres_solve(self, b, x, rtol=1e-8, atol=0.0, restart=30, max_outer=300, inner_its=5,
-                     inner_prec=HDG_FP64, allow_noconv=False):
-        o = KrylovOpts(rtol, atol, restart, max_outer, inner_its, inner_prec)
+                     inner_prec=HDG_FP64, allow_noconv=False, use_learned=False, harvest=None):
+        """harvest: optional device tensor [k, n_glob] receiving the vectors the
+        preconditioner is applied to (first k)."""
+        hv = _ptr(harvest) if harvest is not None else None
+        hk = int(harvest.shape[0]) if harvest is not None else 0
+        o = KrylovOpts(rtol, atol, restart, max_outer, inner_its, inner_prec, int(bool(use_learned)), hv, hk)
         st = KrylovStats()
         code = self.lib.hdg_fgmres_solve(self.h, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(st))
         if not (allow_noconv and code == 5):
             self._check(code)
         return dict(outer_its=st.outer_its, inner_its=st.inner_its_total, res0=st.res0, res=st.res_final,
-                    ms=st.ms, converged=(code == 0))
+                    ms=st.ms, converged=(code == 0), fallbacks=st.fallbacks, harvested=st.harvested)
+
+    def precond_apply(self, v, z, inner_its=5, inner_prec=HDG_FP64, use_learned=False):
+        self._check(self.lib.hdg_precond_apply(self.h, _ptr(v), _ptr(z), inner_its, inner_prec, int(bool(use_learned))))
+
+    def coarse_size(self):
+        n = ctypes.c_int()
+        self._check(self.lib.hdg_coarse_size(self.h, ctypes.byref(n)))
+        return n.value
+
+    def coarse_restrict(self, v, X):
+        self._check(self.lib.hdg_coarse_restrict(self.h, _ptr(v), _ptr(X)))
+
+    def coarse_prolong(self, Y, alpha, z):
+        self._check(self.lib.hdg_coarse_prolong(self.h, _ptr(Y), float(alpha), _ptr(z)))
+
+    def mlp_forward(self, net, X, idx, batch, Y):
+        self._check(self.lib.hdg_mlp_forward(self.h, ctypes.byref(net), _ptr(X), _ptr(idx), int(batch), _ptr(Y)))
+
+    def mlp_loss_grad(self, net, X, T, idx, batch, loss):
+        self._check(self.lib.hdg_mlp_loss_grad(self.h, ctypes.byref(net), _ptr(X), _ptr(T), _ptr(idx), int(batch),
+                                               _ptr(loss)))
+
+    def mlp_adam(self, net, lr, beta1, beta2, eps, step):
+        self._check(self.lib.hdg_mlp_adam(self.h, ctypes.byref(net), lr, beta1, beta2, eps, int(step)))
+
+    def learned_bind(self, net):
+        self._check(self.lib.hdg_learned_bind(self.h, ctypes.byref(net) if net is not None else None))
 
     def local_backsolve(self, duhat, dq, du):
         self._check(self.lib.hdg_local_backsolve(self.h, _ptr(duhat), _ptr(dq), _ptr(du)))
