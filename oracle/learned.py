@@ -19,7 +19,9 @@ stage.  Definitions used here:
 * Network: y = W2 tanh(W1 x~ + b1) + b2 applied to x~ = x / ||x||_2 and
   rescaled by ||x||_2 (homogeneous of degree one in x); x = 0 maps to 0.
 * Loss on a batch (x_b, t_b): mean over the batch and the outputs of
-  (W2 tanh(W1 x~_b + b1) + b2 - t_b / ||x_b||)^2, i.e. in normalised units.
+  (W2 tanh(W1 x~_b + b1) + b2 - t~_b)^2 with t~_b = t_b / ||x_b||, i.e. in
+  normalised units; a row with x_b = 0 (which the network maps to 0 whatever
+  its weights) is normalised to x~_b = 0 and t~_b = 0.
 * Adam (Kingma and Ba): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
   p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 """
@@ -145,9 +147,9 @@ def loss_and_grads(P, X, T):
     """Mean squared error in normalised units and its gradient (plain chain
     rule through the two layers)."""
     s = _norms(X)
-    safe = np.where(s > 0, s, 1.0)
-    Xn = X / safe[:, None]
-    Tn = T / safe[:, None]
+    inv = np.where(s > 0, 1.0 / np.where(s > 0, s, 1.0), 0.0)
+    Xn = X * inv[:, None]
+    Tn = T * inv[:, None]
     Z = Xn @ P["W1"].T + P["b1"]
     H = np.tanh(Z)
     Y = H @ P["W2"].T + P["b2"]

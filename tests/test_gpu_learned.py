@@ -1,0 +1,186 @@
+"""Learned coarse correction of the FGMRES preconditioner: the library's
+coarse restriction/prolongation, network forward, loss gradient and Adam
+kernels against the FP64 oracle (oracle/learned.py), BF16 inference inside
+the preconditioner, the fallback rule, and what the trained network gains
+over the plain multi-level preconditioner."""
+import numpy as np
+import pytest
+
+from gpu_common import make_pair, to_dev, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+@pytest.mark.parametrize("case", [dict(dim=3, n_elem=4, m=2, p=2, periodic=True),
+                                  dict(dim=2, n_elem=6, m=3, p=2, periodic=False, state="shear", mach=0.2)])
+def test_coarse_restrict_prolong(case):
+    import torch
+    from oracle import learned as Ld
+    say(f"[coarse] {case}")
+    S, inp, ctx = make_pair(case)
+    M = S.mesh
+    F = ctx.coarse_size()
+    assert F == Ld.n_features(M.dim)
+    v = np.random.default_rng(11).standard_normal(M.n_glob)
+    X = torch.empty(M.n_macros, F, dtype=torch.float32, device="cuda")
+    ctx.coarse_restrict(to_dev(v), X)
+    Xo = Ld.coarse_restrict(M, v)
+    e = _rel(X.cpu().numpy(), Xo)
+    say(f"[coarse] restrict rel err {e:.2e}")
+    assert e < 1e-6
+    Y = np.random.default_rng(12).standard_normal((M.n_macros, F)).astype(np.float32)
+    z0 = np.random.default_rng(13).standard_normal(M.n_glob)
+    z = to_dev(z0)
+    ctx.coarse_prolong(torch.tensor(Y, device="cuda"), 0.5, z)
+    zo = z0 + 0.5 * Ld.coarse_prolong(M, Y.astype(np.float64))
+    e = _rel(z.cpu().numpy(), zo)
+    say(f"[coarse] prolong rel err {e:.2e}")
+    assert e < 1e-13
+
+
+def _net_pair(ctx, hidden, batch, seed):
+    import torch
+    from oracle import learned as Ld
+    from paper_2402_11361_amd.learned import CoarseCorrection
+    cc = CoarseCorrection(ctx, hidden=hidden, max_batch=batch, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    F = cc.F
+    P = Ld.init_params(F, hidden, F, rng)
+    P["b1"] = 0.1 * rng.standard_normal(hidden)
+    P["b2"] = 0.1 * rng.standard_normal(F)
+    flat32 = Ld.flat(P).astype(np.float32)
+    cc.params.copy_(torch.tensor(flat32, device="cuda"))
+    P32 = Ld.unflat(flat32.astype(np.float64), F, hidden, F)
+    return cc, P32
+
+
+def test_mlp_forward_gradient_adam_against_oracle():
+    import torch
+    from oracle import learned as Ld
+    say("[mlp] forward / gradient / Adam")
+    S, inp, ctx = make_pair(dict(dim=3, n_elem=4, m=2, p=2, periodic=True))
+    hidden, batch, N = 256, 96, 160
+    cc, P = _net_pair(ctx, hidden, batch, seed=4)
+    F = cc.F
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((N, F)).astype(np.float32)
+    X[7] = 0.0  # a zero row maps to zero
+    T = (0.3 * rng.standard_normal((N, F))).astype(np.float32)
+    idx = rng.choice(N, batch, replace=False).astype(np.int32)
+    Xd, Td = torch.tensor(X, device="cuda"), torch.tensor(T, device="cuda")
+    idd = torch.tensor(idx, device="cuda")
+    Y = torch.empty(batch, F, dtype=torch.float32, device="cuda")
+    ctx.mlp_forward(cc.net, Xd, idd, batch, Y)
+    Yo = Ld.forward(P, X[idx].astype(np.float64))
+    e = _rel(Y.cpu().numpy(), Yo)
+    say(f"[mlp] forward rel err {e:.2e}")
+    assert e < 1e-5
+    ctx.mlp_loss_grad(cc.net, Xd, Td, idd, batch, cc.loss)
+    lo, Go = Ld.loss_and_grads(P, X[idx].astype(np.float64), T[idx].astype(np.float64))
+    g = cc.grads.cpu().numpy().astype(np.float64)
+    Gg = Ld.unflat(g, F, hidden, F)
+    el = abs(float(cc.loss.item()) - lo) / lo
+    say(f"[mlp] loss {lo:.6e} rel err {el:.2e}")
+    assert el < 1e-5
+    for k in ("W1", "b1", "W2", "b2"):
+        e = _rel(Gg[k], Go[k])
+        say(f"[mlp] grad {k} rel err {e:.2e}")
+        assert e < 1e-5
+    # one Adam step from zero moments with the GPU gradient
+    Mo = {k: np.zeros_like(v) for k, v in P.items()}
+    Vo = {k: np.zeros_like(v) for k, v in P.items()}
+    Po = {k: v.copy() for k, v in P.items()}
+    Ld.adam_step(Po, Gg, Mo, Vo, 1, lr=1e-3)
+    ctx.mlp_adam(cc.net, 1e-3, 0.9, 0.999, 1e-8, 1)
+    Pg = Ld.unflat(cc.params.cpu().numpy().astype(np.float64), F, hidden, F)
+    for k in Po:
+        e = np.abs(Pg[k] - Po[k]).max()
+        assert e < 1e-6, (k, e)
+
+
+def test_bf16_inference_in_preconditioner():
+    import torch
+    from oracle import learned as Ld
+    say("[bf16] learned stage inside the preconditioner")
+    S, inp, ctx = make_pair(dict(dim=3, n_elem=4, m=2, p=2, periodic=True))
+    d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
+    ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    ctx.condense(bhat)
+    cc, P = _net_pair(ctx, 256, 64, seed=8)
+    cc.bind()
+    v = np.random.default_rng(9).standard_normal(ctx.n_glob)
+    zp = torch.empty(ctx.n_glob, dtype=torch.float64, device="cuda")
+    zl = torch.empty_like(zp)
+    ctx.precond_apply(to_dev(v), zp, 5)
+    ctx.precond_apply(to_dev(v), zl, 5, use_learned=True)
+    got = (zl - zp).cpu().numpy()
+    M = S.mesh
+    ref = Ld.coarse_prolong(M, Ld.forward(P, Ld.coarse_restrict(M, v)))
+    e = _rel(got, ref)
+    say(f"[bf16] correction rel err vs FP64 oracle {e:.2e}")
+    # BF16 weights (8-bit significand, relative rounding 2^-9) with FP32 sums
+    assert e < 2e-2
+    assert e > 1e-6  # the BF16 copy is what ran
+
+
+def test_training_gain_and_fallback():
+    """Train on pairs harvested from two seeded states, evaluate on a third."""
+    import torch
+    from paper_2402_11361_amd.learned import CoarseCorrection
+    case = dict(dim=3, n_elem=8, m=2, p=2, periodic=True, mach=0.1, Re=1600.0, noise=1e-4)
+    say("[train] harvesting")
+    cc = None
+    ctxs = []
+    for seed in (0, 1):
+        S, inp, ctx = make_pair(dict(case, seed=seed))
+        d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
+        ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
+        bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+        ctx.condense(bhat)
+        if cc is None:
+            cc = CoarseCorrection(ctx, hidden=256, max_batch=512, seed=0)
+        else:
+            cc.ctx = ctx
+        k = cc.harvest(bhat, n_vectors=30)
+        say(f"[train] seed {seed}: {k} vectors, {cc.n_pairs()} pairs")
+        ctxs.append(ctx)
+    X = torch.cat(cc.X)
+    T = torch.cat(cc.T)
+    loss0 = cc.eval_loss(X, T)
+    hist = cc.train(epochs=150, lr=1e-3, batch=512)
+    loss1 = cc.eval_loss(X, T)
+    say(f"[train] loss {loss0:.4e} -> {loss1:.4e} (epochs: first {hist[0]:.4e} last {hist[-1]:.4e})")
+    assert loss1 < 0.7 * loss0
+    # held-out state
+    S, inp, ctx = make_pair(dict(case, seed=5))
+    cc.ctx = ctx
+    d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
+    ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    ctx.condense(bhat)
+    xp = torch.zeros_like(bhat)
+    ip = ctx.fgmres_solve(bhat, xp, rtol=1e-10, restart=30, inner_its=5)
+    cc.bind()
+    xl = torch.zeros_like(bhat)
+    il = ctx.fgmres_solve(bhat, xl, rtol=1e-10, restart=30, inner_its=5, use_learned=True)
+    say(f"[gain] plain: {ip['outer_its']} outer its, {ip['ms']:.1f} ms;  learned: {il['outer_its']} outer its, "
+        f"{il['ms']:.1f} ms, fallbacks {il['fallbacks']}")
+    assert ip["converged"] and il["converged"]
+    e = float((xl - xp).norm() / xp.norm())
+    say(f"[gain] solution difference learned vs plain {e:.2e}")
+    assert e < 1e-6
+    # the learned stage either helps or the fallback switched it off
+    assert il["outer_its"] <= ip["outer_its"] or il["fallbacks"] == 1
+    # fallback: a deliberately perturbed network is switched off and the solve still converges
+    cc.params.mul_(40.0)
+    cc.bind()
+    xb = torch.zeros_like(bhat)
+    ib = ctx.fgmres_solve(bhat, xb, rtol=1e-10, restart=30, inner_its=5, use_learned=True)
+    say(f"[fallback] scaled network: {ib['outer_its']} outer its, fallbacks {ib['fallbacks']}")
+    assert ib["converged"] and ib["fallbacks"] == 1
+    assert float((xb - xp).norm() / xp.norm()) < 1e-6

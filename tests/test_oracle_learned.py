@@ -140,3 +140,18 @@ def test_adam_first_step_is_signed_lr():
     for k in P:
         expect = P0[k] - lr * G[k] / (np.abs(G[k]) + eps)
         assert np.allclose(P[k], expect, rtol=0, atol=1e-15)
+
+
+def test_zero_rows_carry_no_loss_gradient_of_the_input_layer():
+    """A row with x = 0 is normalised to x~ = 0, t~ = 0: it adds (b-term)^2 to
+    the loss and nothing to the gradient of W1."""
+    rng = np.random.default_rng(6)
+    P = Ld.init_params(3, 4, 2, rng)
+    X = np.zeros((1, 3))
+    T = rng.standard_normal((1, 2))
+    P["b2"] = np.array([0.5, -1.0])
+    loss, G = Ld.loss_and_grads(P, X, T)
+    h0 = np.tanh(P["b1"])
+    y0 = P["W2"] @ h0 + P["b2"]
+    assert abs(loss - np.mean(y0 ** 2)) < 1e-15
+    assert np.all(G["W1"] == 0.0)
