@@ -72,6 +72,37 @@ def condense_flops(cfg, n_u, n_b):
     return (2.0 / 3.0) * n_u ** 3 + 2.0 * n_u ** 2 * n_b + 2.0 * n_b ** 2 * n_u + F_S + F_C
 
 
+def train_learned(ctx, cfg, dev, dii, dt, args):
+    """Train the learned coarse correction on pairs harvested from plain FGMRES
+    solves of the first Newton step on states with other noise seeds (1, 2, ...);
+    the timed stage (seed 0) is held out.  Returns a summary."""
+    import torch
+    from paper_2402_11361_amd import inputs
+    from paper_2402_11361_amd.hdg import HDG_FP32
+    from paper_2402_11361_amd.learned import CoarseCorrection
+    t0 = time.perf_counter()
+    cc = CoarseCorrection(ctx, hidden=256, max_batch=1024, seed=0)
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    for s in range(1, args.train_seeds + 1):
+        u0, q0, uh0 = workload_arrays(ctx, cfg, seed=s)
+        q, u, uh = dev(q0), dev(u0), dev(uh0)
+        ctx.linearize_stage(q, u, uh, -dii * u, dt, dii)
+        ctx.condense(bhat, HDG_FP32)
+        cc.harvest(bhat, n_vectors=args.train_vectors)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    X, T = torch.cat(cc.X), torch.cat(cc.T)
+    loss0 = cc.eval_loss(X, T)
+    hist = cc.train(epochs=args.train_epochs, lr=1e-3, batch=1024)
+    loss1 = cc.eval_loss(X, T)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    cc.bind()
+    return dict(pairs=cc.n_pairs(), seeds=list(range(1, args.train_seeds + 1)), harvest_s=round(t1 - t0, 2),
+                train_s=round(t2 - t1, 2), epochs=args.train_epochs, loss_initial=loss0, loss_final=loss1,
+                hidden=256, inference="BF16 weights, FP32 accumulation")
+
+
 def blas_threads():
     """Threads the oracle's LAPACK/BLAS calls use (NumPy's BLAS pool)."""
     try:
@@ -133,6 +164,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--applies", type=int, default=20)
     ap.add_argument("--plain-only", action="store_true", help="time only the plain FP64 variant")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction variant")
+    ap.add_argument("--train-seeds", type=int, default=2)
+    ap.add_argument("--train-vectors", type=int, default=40)
+    ap.add_argument("--train-epochs", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
@@ -172,11 +207,12 @@ def main():
     copy_gbs = 2.0 * src.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
     del src, dst
 
-    def run_variant(cond_prec, inner_prec, steps, warmup):
+    def run_variant(cond_prec, inner_prec, steps, warmup, use_learned=False):
         """Warm-up stages, then `steps` timed stage solves from the same state."""
         marks = []
         drv = StageDriver(ctx, rtol=rtol, restart=30, inner_its=5, max_outer=300, condense_prec=cond_prec,
-                          inner_prec=inner_prec, mark=lambda phase: marks.append((phase, ev())))
+                          inner_prec=inner_prec, mark=lambda phase: marks.append((phase, ev())),
+                          use_learned=use_learned)
 
         def stage():
             q.copy_(q_init); u.copy_(u_init); uh.copy_(uh_init)
@@ -204,6 +240,7 @@ def main():
                     newton_its=infos[-1]["newton_its"], newton_res=infos[-1]["res_hist"],
                     outer=[[k["outer_its"] for k in inf["krylov"]] for inf in infos],
                     inner=[[k["inner_its"] for k in inf["krylov"]] for inf in infos],
+                    fallbacks=[[k.get("fallbacks", 0) for k in inf["krylov"]] for inf in infos],
                     u=u.clone(), uh=uh.clone())
 
     def time_apply():
@@ -245,6 +282,20 @@ def main():
             stage_solution_rel_diff_vs_plain=dict(u=du, uhat=duh),
             apply_ms=round(apply32_ms, 4),
             apply_gbs=round((4.0 * nm * nb * nb + 16.0 * nm * nb + 8.0 * ctx.n_glob) / (apply32_ms * 1e-3) / 1e9, 1))
+        if not args.no_learned:
+            lrn = train_learned(ctx, cfg, dev, dii, dt, args)
+            ml = run_variant(HDG_FP32, HDG_FP64, args.steps, args.warmup, use_learned=True)
+            variants["mixed_fp32_condense_learned"] = dict(
+                ms_per_stage=round(ml["ms_per_stage"], 3),
+                speedup_vs_plain=round(ms_step / ml["ms_per_stage"], 3),
+                phases_ms={k: round(v, 3) for k, v in ml["phase_ms"].items()},
+                newton_its=ml["newton_its"], newton_res=ml["newton_res"],
+                fgmres=dict(outer_its=ml["outer"], inner_its=ml["inner"], fallbacks=ml["fallbacks"]),
+                stage_solution_rel_diff_vs_plain=dict(
+                    u=float((ml["u"] - plain["u"]).abs().max() / plain["u"].abs().max()),
+                    uhat=float((ml["uh"] - plain["uh"]).abs().max() / plain["uh"].abs().max())),
+                training=lrn)
+            ctx.learned_bind(None)
     apply_bytes = 8.0 * nm * nb * nb + 8.0 * nm * nb + 8.0 * nm * nb + 8.0 * ctx.n_glob
     apply_gbs = apply_bytes / (apply_ms * 1e-3) / 1e9
     cond_ms = float(np.mean(cond_calls))
