@@ -31,8 +31,8 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by what the counters
 # read for a 1 GiB device copy in the same run (profiles/stage_solve_tgv24_m3_p2_fp64.md),
 # valid only while the kernel sources hash to `sha`.
-CONDENSE_TRAFFIC = {"sha": "730ce05da64df8bb", "bytes": 1117.4e9}
-CONDENSE_SOURCES = ("k_form.hip", "k_lu.hip", "k_krylov.hip", "internal.h")
+CONDENSE_TRAFFIC = {"sha": "4fe62eacee8e1cd2", "bytes": 1135.0e9}
+CONDENSE_SOURCES = ("k_form.hip", "k_lu.hip")
 
 
 def sources_sha():
@@ -165,6 +165,7 @@ def main():
     ap.add_argument("--applies", type=int, default=20)
     ap.add_argument("--plain-only", action="store_true", help="time only the plain FP64 variant")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction variant")
+    ap.add_argument("--graph-steps", type=int, default=10, help="FGMRES steps per captured HIP graph")
     ap.add_argument("--train-seeds", type=int, default=2)
     ap.add_argument("--train-vectors", type=int, default=40)
     ap.add_argument("--train-epochs", type=int, default=60)
@@ -207,12 +208,12 @@ def main():
     copy_gbs = 2.0 * src.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
     del src, dst
 
-    def run_variant(cond_prec, inner_prec, steps, warmup, use_learned=False):
+    def run_variant(cond_prec, inner_prec, steps, warmup, use_learned=False, graph_steps=0):
         """Warm-up stages, then `steps` timed stage solves from the same state."""
         marks = []
         drv = StageDriver(ctx, rtol=rtol, restart=30, inner_its=5, max_outer=300, condense_prec=cond_prec,
                           inner_prec=inner_prec, mark=lambda phase: marks.append((phase, ev())),
-                          use_learned=use_learned)
+                          use_learned=use_learned, graph_steps=graph_steps)
 
         def stage():
             q.copy_(q_init); u.copy_(u_init); uh.copy_(uh_init)
@@ -282,6 +283,15 @@ def main():
             stage_solution_rel_diff_vs_plain=dict(u=du, uhat=duh),
             apply_ms=round(apply32_ms, 4),
             apply_gbs=round((4.0 * nm * nb * nb + 16.0 * nm * nb + 8.0 * ctx.n_glob) / (apply32_ms * 1e-3) / 1e9, 1))
+        for name, cp in (("plain_fp64_graph", HDG_FP64), ("mixed_fp32_condense_graph", HDG_FP32)):
+            gv = run_variant(cp, HDG_FP64, args.steps, args.warmup, graph_steps=args.graph_steps)
+            variants[name] = dict(
+                ms_per_stage=round(gv["ms_per_stage"], 3), speedup_vs_plain=round(ms_step / gv["ms_per_stage"], 3),
+                phases_ms={k: round(v, 3) for k, v in gv["phase_ms"].items()}, newton_its=gv["newton_its"],
+                fgmres=dict(outer_its=gv["outer"], inner_its=gv["inner"]), graph_steps=args.graph_steps,
+                stage_solution_rel_diff_vs_plain=dict(
+                    u=float((gv["u"] - plain["u"]).abs().max() / plain["u"].abs().max()),
+                    uhat=float((gv["uh"] - plain["uh"]).abs().max() / plain["uh"].abs().max())))
         if not args.no_learned:
             lrn = train_learned(ctx, cfg, dev, dii, dt, args)
             ml = run_variant(HDG_FP32, HDG_FP64, args.steps, args.warmup, use_learned=True)
@@ -304,8 +314,8 @@ def main():
     traffic = CONDENSE_TRAFFIC["bytes"] if sources_sha() == CONDENSE_TRAFFIC["sha"] else None
     roofline = dict(bound="mfma", achieved=round(cond_tflops, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
                     frac=round(cond_tflops / PEAK_FP64_TFLOPS, 4), traffic=traffic,
-                    kernel="hdg_condense: k_form + batched FP64 elimination (k_panel, k_uinv, k_u12, k_u12b2, "
-                           "k_gemm) + face-preconditioner factorisation",
+                    kernel="hdg_condense: k_form + batched FP64 elimination (k_panel, k_uinv, k_u12, k_linv2, "
+                           "k_u12lin, k_gemm) + face-preconditioner factorisation",
                     flops_per_launch=flops, ms_per_launch=round(cond_ms, 3), launches=len(cond_calls))
     out = dict(metric=METRIC, value=round(ms_step, 3), unit="ms/DIRK-stage", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_step, 3), higher_is_better=False, scaling="weak",

@@ -108,6 +108,16 @@ typedef struct {
    * most, in the order they occur (training data of the learned stage). */
   double* harvest;
   int harvest_max;
+  /* 0: Arnoldi control on the host (one synchronisation per Gram-Schmidt
+   * pass).  k >= 1: the whole Arnoldi step (inner GMRES with its small
+   * least-squares solve, CGS2, normalisation, Givens update) stays on the
+   * device; each step is captured once per context in a HIP graph and
+   * replayed; up to k steps are launched between two synchronisations (the
+   * convergence test), fewer when the observed reduction per step says
+   * fewer will reach the tolerance; steps past convergence in a batch are
+   * computed and discarded.  Not combined with harvest (k is ignored while
+   * harvesting). */
+  int graph_steps;
 } hdg_krylov_opts;
 
 typedef struct {

@@ -22,6 +22,11 @@ hipError_t launch_zero_ints(hipStream_t s, int* p, int n);
 
 namespace {
 
+void clear_graphs(HdgContext& c) {
+  for (auto& kv : c.graphs) (void)hipGraphExecDestroy(kv.second);
+  c.graphs.clear();
+}
+
 hdg_status fail(HdgContext* c, hdg_status s, const std::string& msg) {
   if (c) c->last_error = msg;
   return s;
@@ -95,6 +100,100 @@ struct Krylov {
   }
   hipError_t apply_A(const double* x, double* y, int prec) { return launch_apply(c, x, y, prec); }
   hipError_t apply_M(const double* x, double* y) { return launch_precond_apply(c, x, y); }
+
+  // ---- device-resident Arnoldi steps (no host synchronisation) -------------
+  // control block: H [(restart+1) x restart], cs, sn [restart], g [restart+1],
+  // res [restart] (|g_{j+1}| after step j), inner Hessenberg, scalars, dots
+  double *dH = nullptr, *dcs = nullptr, *dsn = nullptr, *dg = nullptr, *dres = nullptr, *dHin = nullptr,
+         *dsc = nullptr, *dyin = nullptr, *ddot = nullptr;
+  void dev_init() {
+    double* kc = c.ws.kctl;
+    dH = kc; dcs = kc + 4160; dsn = kc + 4224; dg = kc + 4288; dres = kc + 4360;
+    dHin = kc + 4432; dsc = kc + 4704; dyin = kc + 4720; ddot = kc + 4800;
+  }
+  // CGS2 of w against rows 0..j of B; the summed coefficients go to col[i * stride]
+  hipError_t cgs2_dev(const double* B, int j, double* w_, double* col, int stride) {
+    for (int pass = 0; pass < 2; ++pass) {
+      hipError_t e = dots(j + 1, B, w_, ddot);
+      if (e != hipSuccess) return e;
+      if ((e = launch_multiaxpy(c.stream, n, j + 1, B, n, ddot, -1.0, w_)) != hipSuccess) return e;
+      if ((e = launch_accum_col(c.stream, j + 1, ddot, col, stride, pass)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  // h_out = ||w||, w /= ||w|| (w = 0 stays 0)
+  hipError_t normalize_dev(double* w_, double* h_out) {
+    hipError_t e = dots(1, w_, w_, dsc + 0);
+    if (e != hipSuccess) return e;
+    if ((e = launch_norm_finish(c.stream, dsc + 0, h_out, dsc + 2)) != hipSuccess) return e;
+    return launch_scale_dev(c.stream, n, dsc + 2, w_, w_);
+  }
+  hipError_t precond_dev(const double* v, double* z) {
+    hipError_t e;
+    if (inner <= 0) {
+      e = launch_precond_apply(c, v, z);
+    } else {
+      if ((e = apply_M(v, Vi)) != hipSuccess) return e;
+      if ((e = normalize_dev(Vi, dsc + 1)) != hipSuccess) return e;  // beta of the inner solve
+      for (int j = 0; j < inner; ++j) {
+        double* vn = Vi + (size_t)(j + 1) * n;
+        if ((e = apply_A(Vi + (size_t)j * n, t, inner_prec)) != hipSuccess) return e;
+        if ((e = apply_M(t, vn)) != hipSuccess) return e;
+        if ((e = cgs2_dev(Vi, j, vn, dHin + j, inner)) != hipSuccess) return e;
+        if ((e = normalize_dev(vn, dHin + (size_t)(j + 1) * inner + j)) != hipSuccess) return e;
+        ++inner_total;
+      }
+      if ((e = launch_small_ls(c.stream, inner, inner, dHin, dsc + 1, dyin)) != hipSuccess) return e;
+      e = launch_lincomb(c.stream, n, inner, Vi, n, dyin, z, 0);
+    }
+    if (e != hipSuccess || !learned) return e;
+    return launch_learned_correction(c, v, z);
+  }
+  // outer step j of a cycle of length m (Z_j, V_{j+1}, column j of H, Givens)
+  hipError_t step_dev(int j, int m) {
+    hipError_t e;
+    double* wv = V + (size_t)(j + 1) * n;
+    if ((e = precond_dev(V + (size_t)j * n, Z + (size_t)j * n)) != hipSuccess) return e;
+    if ((e = apply_A(Z + (size_t)j * n, wv, 0)) != hipSuccess) return e;
+    if ((e = cgs2_dev(V, j, wv, dH + j, m)) != hipSuccess) return e;
+    if ((e = normalize_dev(wv, dH + (size_t)(j + 1) * m + j)) != hipSuccess) return e;
+    return launch_givens_step(c.stream, j, m, dH, dcs, dsn, dg, dres);
+  }
+  // steps [j0, j0 + kk): one captured graph per step (built on first use),
+  // launched back to back with no host synchronisation in between
+  hipError_t steps_graph(int j0, int kk, int m) {
+    for (int j = j0; j < j0 + kk; ++j) {
+      hipError_t e = step_graph(j, m);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  hipError_t step_graph(int j0, int m) {
+    const int kk = 1;
+    const std::array<int, 8> key{j0, kk, m, inner, inner_prec, c.cond_prec, learned ? 1 : 0, c.have_a32 ? 1 : 0};
+    auto it = c.graphs.find(key);
+    if (it == c.graphs.end()) {
+      hipError_t e;
+      if (!c.cap_stream && (e = hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking)) != hipSuccess) return e;
+      hipStream_t user = c.stream;
+      c.stream = c.cap_stream;
+      e = hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal);
+      const int tot0 = inner_total;
+      for (int j = j0; j < j0 + kk && e == hipSuccess; ++j) e = step_dev(j, m);
+      inner_total = tot0;
+      hipGraph_t graph = nullptr;
+      hipError_t e2 = hipStreamEndCapture(c.cap_stream, &graph);
+      c.stream = user;
+      if (e == hipSuccess) e = e2;
+      hipGraphExec_t exec = nullptr;
+      if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return e;
+      it = c.graphs.emplace(key, exec).first;
+    }
+    inner_total += kk * inner;
+    return hipGraphLaunch(it->second, c.stream);
+  }
 
   // z = inner GMRES(inner) on M^{-1} A z = M^{-1} v, zero start (+ learned correction)
   hipError_t precond(const double* v, double* z) {
@@ -233,7 +332,7 @@ hdg_status hdg_setup_mesh(const hdg_mesh_desc* mesh, const hdg_phys* phys, void*
     return HDG_EDEVICE;
   }
   plan_workspace(c);
-  if (hipHostMalloc((void**)&h->pinned, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&h->pinned, 8192 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     for (void* p : c.dev_allocs) (void)hipFree(p);
     delete h;
     return HDG_EDEVICE;
@@ -274,16 +373,17 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
     rebase(c.ws.Kq); rebase(c.ws.AUU); rebase(c.ws.AUQ); rebase(c.ws.RUe); rebase(c.ws.RQe); rebase(c.ws.SUB);
     rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.gloc); rebase(c.ws.Wm);
     rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.ypart); rebase(c.ws.kry);
-    rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn);
+    rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn); rebase(c.ws.kctl);
   } else {
     auto rebase = [&](auto*& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(base + reinterpret_cast<uintptr_t>(p)); };
     rebase(c.ws.Kq); rebase(c.ws.AUU); rebase(c.ws.AUQ); rebase(c.ws.RUe); rebase(c.ws.RQe); rebase(c.ws.SUB);
     rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.gloc); rebase(c.ws.Wm);
     rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.ypart); rebase(c.ws.kry);
-    rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn);
+    rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn); rebase(c.ws.kctl);
   }
   c.ws.base = base;
   c.lrn_bound = false;
+  clear_graphs(c);
   c.ws.bytes = bytes;
   c.ws_bound = true;
   c.have_a32 = false;
@@ -345,7 +445,7 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
   HdgContext& c = ctx->c;
   if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
   if (o->restart < 1 || o->restart > c.kry_restart_max || o->inner_its < 0 || o->inner_its > c.kry_inner_max ||
-      o->max_outer < 1 || !(o->rtol >= 0) || !(o->atol >= 0))
+      o->max_outer < 1 || !(o->rtol >= 0) || !(o->atol >= 0) || o->graph_steps < 0)
     return fail(&c, HDG_EINVAL, "bad Krylov options");
   auto t0 = std::chrono::steady_clock::now();
   if (o->inner_prec == HDG_FP32 && c.cond_prec == 0 && !c.have_a32) {
@@ -369,12 +469,78 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
   int its = 0;
   const int m = o->restart;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  // residual reduction of one step: plain steps feed the context's running
+  // average; learned steps are compared with it (fallback rule of the options)
+  auto account = [&](bool step_learned, double rate) {
+    if (!(rate > 0.0)) return;
+    if (!step_learned) {
+      c.plain_log_rate += std::log(rate);
+      ++c.plain_steps;
+      return;
+    }
+    lrn_log += std::log(rate);
+    ++lrn_steps;
+    const bool worse_than_plain =
+        lrn_steps >= 3 && c.plain_steps >= 3 && lrn_log / lrn_steps > c.plain_log_rate / c.plain_steps;
+    if (rate >= 1.0 || worse_than_plain) {
+      K.learned = false;
+      fallbacks = 1;
+    }
+  };
+  const bool dev_mode = o->graph_steps > 0 && o->harvest_max == 0;
+  if (dev_mode) K.dev_init();
   while (beta > tol && its < o->max_outer) {
     HIPCHK(&c, launch_scale_copy(c.stream, n, 1.0 / beta, K.r, K.V));
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int k = 0;
-    for (int j = 0; j < m; ++j) {
+    if (dev_mode) {
+      // Arnoldi steps on the device, graph_steps at a time; the host only
+      // reads |g_{j+1}| after each batch for the convergence test
+      double* hb = ctx->pinned;
+      for (int i = 0; i <= m; ++i) hb[i] = g[i];
+      HIPCHK(&c, hipMemcpyAsync(K.dg, hb, sizeof(double) * (m + 1), hipMemcpyHostToDevice, c.stream));
+      double prev = beta;
+      bool done = false;
+      int batch = o->graph_steps;
+      for (int j = 0; j < m && !done;) {
+        const int kk = std::min(std::min(batch, m - j), o->max_outer - its);
+        const double res_in = prev;
+        const bool step_learned = K.learned;
+        HIPCHK(&c, K.steps_graph(j, kk, m));
+        HIPCHK(&c, hipMemcpyAsync(hb, K.dres + j, sizeof(double) * kk, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(&c, hipStreamSynchronize(c.stream));
+        for (int jj = 0; jj < kk; ++jj) {
+          const double res = hb[jj];
+          ++its;
+          k = j + jj + 1;
+          account(step_learned, prev > 0.0 ? res / prev : 0.0);
+          prev = res;
+          if (!std::isfinite(res)) return fail(&c, HDG_ENAN, "non-finite Krylov residual");
+          if (res <= tol || res == 0.0 || its >= o->max_outer) { done = true; break; }
+        }
+        j += kk;
+        // next batch: the steps that the observed mean reduction per step still
+        // needs to reach tol (at least 1, at most graph_steps), so that few
+        // steps past convergence are computed
+        if (!done && prev > 0.0 && res_in > 0.0 && prev < res_in) {
+          const double rate = std::pow(prev / res_in, 1.0 / kk);
+          const double need = std::ceil(std::log(tol / prev) / std::log(rate));
+          batch = (int)std::max(1.0, std::min((double)o->graph_steps, need));
+        } else {
+          batch = o->graph_steps;
+        }
+      }
+      // the k x k triangle of H and g to the host
+      HIPCHK(&c, hipMemcpyAsync(hb, K.dH, sizeof(double) * (size_t)k * m, hipMemcpyDeviceToHost, c.stream));
+      HIPCHK(&c, hipMemcpyAsync(hb + (size_t)k * m, K.dg, sizeof(double) * k, hipMemcpyDeviceToHost, c.stream));
+      HIPCHK(&c, hipStreamSynchronize(c.stream));
+      for (int i = 0; i < k; ++i) {
+        g[i] = hb[(size_t)k * m + i];
+        for (int j = 0; j < k; ++j) H[(size_t)i * m + j] = hb[(size_t)i * m + j];
+      }
+    }
+    for (int j = 0; j < m && !dev_mode; ++j) {
       if (harvested < o->harvest_max) {
         HIPCHK(&c, hipMemcpyAsync(o->harvest + (size_t)harvested * n, K.V + (size_t)j * n, sizeof(double) * n,
                                   hipMemcpyDeviceToDevice, c.stream));
@@ -402,24 +568,7 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
       g[j] = cs[j] * g0;
       g[j + 1] = -sn[j] * g0;
       ++its;
-      // residual reduction of this step: plain steps feed the context's running
-      // average; learned steps are compared with it (fallback rule of the options)
-      const double rate = std::fabs(g0) > 0.0 ? std::fabs(g[j + 1]) / std::fabs(g0) : 0.0;
-      if (rate > 0.0) {
-        if (!step_learned) {
-          c.plain_log_rate += std::log(rate);
-          ++c.plain_steps;
-        } else {
-          lrn_log += std::log(rate);
-          ++lrn_steps;
-          const bool worse_than_plain = lrn_steps >= 3 && c.plain_steps >= 3 &&
-                                        lrn_log / lrn_steps > c.plain_log_rate / c.plain_steps;
-          if (rate >= 1.0 || worse_than_plain) {
-            K.learned = false;
-            fallbacks = 1;
-          }
-        }
-      }
+      account(step_learned, std::fabs(g0) > 0.0 ? std::fabs(g[j + 1]) / std::fabs(g0) : 0.0);
       k = j + 1;
       if (hn == 0.0 || std::fabs(g[j + 1]) <= tol || its >= o->max_outer) break;
       HIPCHK(&c, launch_scale_copy(c.stream, n, 1.0 / hn, wv, wv));
@@ -427,7 +576,7 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
     for (int i = k - 1; i >= 0; --i) {
       double s = g[i];
       for (int j = i + 1; j < k; ++j) s -= H[(size_t)i * m + j] * y[j];
-      y[i] = s / H[(size_t)i * m + i];
+      y[i] = H[(size_t)i * m + i] != 0.0 ? s / H[(size_t)i * m + i] : 0.0;
     }
     for (int i = 0; i < k; ++i) ctx->pinned[i] = y[i];
     HIPCHK(&c, hipMemcpyAsync(K.dev_coef + 256, ctx->pinned, sizeof(double) * k, hipMemcpyHostToDevice, c.stream));
@@ -561,6 +710,8 @@ hdg_status hdg_axpy(hdg_ctx ctx, size_t n, double a, const double* x, double* y)
 hdg_status hdg_destroy(hdg_ctx ctx) {
   if (!ctx) return HDG_EINVAL;
   (void)hipStreamSynchronize(ctx->c.stream);
+  clear_graphs(ctx->c);
+  if (ctx->c.cap_stream) (void)hipStreamDestroy(ctx->c.cap_stream);
   for (void* p : ctx->c.dev_allocs) (void)hipFree(p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;

@@ -58,6 +58,7 @@ struct Workspace {
   double* small = nullptr;  // small device scalars
   double* Uinv = nullptr;   // [max(macros, faces)][64][64] block inverses of the elimination
   float* lrn = nullptr;     // learned stage: X, Y [macros][cF] each, then the BF16 network
+  double* kctl = nullptr;   // device-resident Krylov control block (Hessenbergs, rotations, scalars)
 };
 
 struct HdgContext {
@@ -87,7 +88,11 @@ struct HdgContext {
   bool lrn_bound = false;
   int lrn_hidden = 0;
   double plain_log_rate = 0.0;  // sum of log(residual reduction) over plain FGMRES steps
-  long long plain_steps = 0;  // element type of the condensed matrices in Wm: 0 FP64, 1 FP32
+  long long plain_steps = 0;
+  // captured FGMRES steps: key (first step, steps, restart, inner its, inner prec,
+  // condensed prec, learned, FP32 copy present) -> executable graph
+  std::map<std::array<int, 8>, hipGraphExec_t> graphs;
+  hipStream_t cap_stream = nullptr;  // private stream used only for capture  // element type of the condensed matrices in Wm: 0 FP64, 1 FP32
   std::string last_error;
 };
 

@@ -454,7 +454,7 @@ void plan_workspace(HdgContext& c) {
   c.ldf = (int)align_up(2 * c.nf_max, 64);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, gloc, Wm, ipiv, FW, fpiv, A32, ypart, kry, red, small, Uinv, lrn; } o;
+  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, gloc, Wm, ipiv, FW, fpiv, A32, ypart, kry, red, small, Uinv, lrn, kctl; } o;
   o.Kq = take(sizeof(double) * n_el * c.Kstride);
   o.AUU = take(sizeof(double) * n_el * c.nsA * c.nsA);
   o.AUQ = take(sizeof(double) * n_el * c.nsA * c.dnsA);
@@ -478,11 +478,13 @@ void plan_workspace(HdgContext& c) {
   o.kry = take(sizeof(double) * (size_t)(2 * c.kry_restart_max + c.kry_inner_max + 8) * hm.n_glob);
   o.red = take(sizeof(double) * (1 << 20));
   o.small = take(sizeof(double) * 4096);
-  // elimination scratch: per matrix a 64 x 64 block inverse and a row permutation
-  o.Uinv = take(sizeof(double) * (size_t)std::max(hm.n_macros, hm.n_faces) * (64 * 64 + 256));
+  // elimination scratch per matrix: a 64 x 64 block inverse, two row permutations
+  // and a 128 x 128 unit-lower block inverse
+  o.Uinv = take(sizeof(double) * ((size_t)std::max(hm.n_macros, hm.n_faces) * (64 * 64 + 128 * 128 + 512) + 64));
   // learned stage: X and Y per macro, then the BF16 copy of the largest network
   o.lrn = take(sizeof(float) * (2 * (size_t)hm.n_macros * hc.cF + 16) +
                sizeof(unsigned short) * mlp_param_count(hc.cF, LRN_MAX_HIDDEN, hc.cF));
+  o.kctl = take(sizeof(double) * 8192);
   c.need_bytes = off;
   // remember offsets in the workspace struct (resolved on bind)
   c.ws.bytes = 0;
@@ -509,6 +511,7 @@ void plan_workspace(HdgContext& c) {
   c.ws.small = reinterpret_cast<double*>(o.small);
   c.ws.Uinv = reinterpret_cast<double*>(o.Uinv);
   c.ws.lrn = reinterpret_cast<float*>(o.lrn);
+  c.ws.kctl = reinterpret_cast<double*>(o.kctl);
 }
 
 void node_coords(const HdgContext& c, double* macro_xyz, double* face_xyz) {

@@ -133,3 +133,9 @@ hipError_t launch_scale_copy(hipStream_t s, long long n, double a, const double*
 hipError_t launch_lincomb(hipStream_t s, long long n, int k, const double* V, long long ldv,
                           const double* coef_dev, double* y, int accumulate);
 hipError_t launch_sub(hipStream_t s, long long n, const double* a, const double* b, double* y);
+// device-resident Krylov control
+hipError_t launch_accum_col(hipStream_t s, int n, const double* coef, double* col, int stride, int pass);
+hipError_t launch_norm_finish(hipStream_t s, const double* dot, double* h_out, double* inv_out);
+hipError_t launch_scale_dev(hipStream_t s, long long n, const double* a, const double* x, double* y);
+hipError_t launch_givens_step(hipStream_t s, int j, int m, double* H, double* cs, double* sn, double* g, double* res);
+hipError_t launch_small_ls(hipStream_t s, int k, int ldh, const double* Hin, const double* beta, double* y);

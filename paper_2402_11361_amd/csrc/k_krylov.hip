@@ -249,6 +249,81 @@ __global__ void k_zero_ints(int* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
+// ---- device-resident Krylov control (no host synchronisation per step) ------
+
+// col[i * stride] = (pass ? col[i * stride] : 0) + coef[i], i < n
+__global__ void k_accum_col(int n, const double* __restrict__ coef, double* __restrict__ col, int stride, int pass) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) col[(size_t)i * stride] = (pass ? col[(size_t)i * stride] : 0.0) + coef[i];
+}
+
+// h = sqrt(max(dot, 0)); inv = 1 / h (0 if h = 0)
+__global__ void k_norm_finish(const double* __restrict__ dot, double* __restrict__ h_out, double* __restrict__ inv_out) {
+  const double h = sqrt(fmax(0.0, dot[0]));
+  if (h_out) h_out[0] = h;
+  inv_out[0] = h > 0.0 ? 1.0 / h : 0.0;
+}
+
+__global__ void k_scale_dev(long long n, const double* __restrict__ a, const double* __restrict__ x, double* __restrict__ y) {
+  const double s = a[0];
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = s * x[i];
+}
+
+// Column j of the (m+1) x m Hessenberg H (row-major, ld m): apply the
+// previous rotations, form the new one, rotate g; res[j] = |g[j+1]|.
+__global__ void k_givens_step(int j, int m, double* __restrict__ H, double* __restrict__ cs, double* __restrict__ sn,
+                              double* __restrict__ g, double* __restrict__ res) {
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < j; ++i) {
+    const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+    H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+    H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+  const double rr = hypot(a, b);
+  cs[j] = rr > 0 ? a / rr : 1.0;
+  sn[j] = rr > 0 ? b / rr : 0.0;
+  H[(size_t)j * m + j] = rr;
+  H[(size_t)(j + 1) * m + j] = 0.0;
+  const double g0 = g[j];
+  g[j] = cs[j] * g0;
+  g[j + 1] = -sn[j] * g0;
+  res[j] = fabs(g[j + 1]);
+}
+
+// y = argmin || beta e1 - H y || for the (k+1) x k Hessenberg H (ld ldh) by
+// Givens rotations and back substitution (a zero pivot gives y_i = 0).
+__global__ void k_small_ls(int k, int ldh, const double* __restrict__ Hin, const double* __restrict__ beta,
+                           double* __restrict__ y) {
+  if (threadIdx.x != 0) return;
+  double R[17 * 16], g[17], cs[16], sn[16];
+  for (int i = 0; i <= k; ++i)  // entries below the subdiagonal are not stored
+    for (int j = 0; j < k; ++j) R[i * k + j] = (i <= j + 1) ? Hin[(size_t)i * ldh + j] : 0.0;
+  for (int i = 0; i <= k; ++i) g[i] = 0.0;
+  g[0] = beta[0];
+  for (int j = 0; j < k; ++j) {
+    for (int i = 0; i < j; ++i) {
+      const double a = R[i * k + j], b = R[(i + 1) * k + j];
+      R[i * k + j] = cs[i] * a + sn[i] * b;
+      R[(i + 1) * k + j] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = R[j * k + j], b = R[(j + 1) * k + j];
+    const double rr = hypot(a, b);
+    cs[j] = rr > 0 ? a / rr : 1.0;
+    sn[j] = rr > 0 ? b / rr : 0.0;
+    R[j * k + j] = rr;
+    R[(j + 1) * k + j] = 0.0;
+    const double g0 = g[j];
+    g[j] = cs[j] * g0;
+    g[j + 1] = -sn[j] * g0;
+  }
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int j = i + 1; j < k; ++j) s -= R[i * k + j] * y[j];
+    y[i] = R[i * k + i] != 0.0 ? s / R[i * k + i] : 0.0;
+  }
+}
+
 inline unsigned grid_for(long long n) { return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4096)); }
 
 }  // namespace
@@ -376,5 +451,31 @@ hipError_t launch_sub(hipStream_t s, long long n, const double* a, const double*
 
 hipError_t launch_axpy(hipStream_t s, size_t n, double a, const double* x, double* y) {
   hipLaunchKernelGGL(k_axpy, dim3(grid_for((long long)n)), dim3(256), 0, s, (long long)n, a, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_accum_col(hipStream_t s, int n, const double* coef, double* col, int stride, int pass) {
+  hipLaunchKernelGGL(k_accum_col, dim3(1), dim3(64), 0, s, n, coef, col, stride, pass);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_finish(hipStream_t s, const double* dot, double* h_out, double* inv_out) {
+  hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(1), 0, s, dot, h_out, inv_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_dev(hipStream_t s, long long n, const double* a, const double* x, double* y) {
+  hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(n)), dim3(256), 0, s, n, a, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_givens_step(hipStream_t s, int j, int m, double* H, double* cs, double* sn, double* g, double* res) {
+  hipLaunchKernelGGL(k_givens_step, dim3(1), dim3(64), 0, s, j, m, H, cs, sn, g, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_ls(hipStream_t s, int k, int ldh, const double* Hin, const double* beta, double* y) {
+  if (k > 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_small_ls, dim3(1), dim3(64), 0, s, k, ldh, Hin, beta, y);
   return hipGetLastError();
 }

@@ -10,13 +10,18 @@
 // The same kernels invert the face blocks of A_uh,uh for the preconditioner
 // ([[A, -I], [I, 0]] -> A^{-1} in the bottom-right corner).
 //
-// Per block of NB columns:
-//   k_panel   one workgroup per matrix factors the S rows of the block in
+// Columns are eliminated in pairs of NB = 64-column blocks (look-ahead):
+//   k_panel   one workgroup per matrix factors the S rows of a block in
 //             sub-panels of PW columns held in registers (pivot search by a
-//             workgroup arg-max, first maximum wins as in LAPACK);
-//   k_dtrsm   L of the non-pivot rows: A_D,block U11^{-1};
-//   k_update  one workgroup per (matrix, 64-column strip): row swaps, the
-//             strip of U12 = L11^{-1} A12, and A22 -= L21 U12 on FP64 MFMA
+//             workgroup arg-max, first maximum wins as in LAPACK) and records
+//             the block's net row permutation;
+//   k_uinv + k_gemm   L of the non-pivot rows: A_D,block U11^{-1};
+//   k_u12     row swaps and U12 = L11^{-1} A12 of one block for one strip
+//             (used to bring the second block of a pair up to date);
+//   k_linv2 + k_u12lin   the inverse of the pair's 128 x 128 unit-lower
+//             diagonal block, then per 64-column strip the row swaps of both
+//             blocks and U12 = L^{-1} A12 as an MFMA product;
+//   k_gemm    A22 -= L21 U12 for all strips, K = 128, on MFMA
 //             (v_mfma_f64_16x16x4f64 in FP64, v_mfma_f32_16x16x4f32 in FP32).
 // Every kernel is a template on the storage and arithmetic type T (double or
 // float); the FP32 instance is the low-precision condensation.
@@ -361,36 +366,69 @@ __global__ void __launch_bounds__(256) k_u12(LuArgs<T> a, int j0, int jb, int st
   }
 }
 
-// In-place unit-lower triangular solve X = L^{-1} X in LDS (L: n x n in sL
-// with leading dimension NB, X: n x 64 in sX), the inner sums split in four.
+// Inverse of the unit-lower 128 x 128 diagonal block of two consecutive
+// 64-column blocks b1 = [j0, j0 + 64), b2 = [j0 + 64, j0 + 64 + jb2):
+//   L = [[L11, 0], [L21, L22]],  L^{-1} = [[L11^{-1}, 0], [-L22^{-1} L21 L11^{-1}, L22^{-1}]],
+// identity-padded beyond 64 + jb2, row-major into Linv[mat] (128 x 128).
+// One workgroup per matrix.
 template <class T>
-__device__ void trsm_lds(const T* sL, T* sX, int n, T (*sP)[NC], int tid) {
-  const int col = tid % NC, part = tid / NC;
-  for (int i = 1; i < n; ++i) {
+__global__ void __launch_bounds__(256) k_linv2(LuArgs<T> a, int j0, int jb2, T* __restrict__ Linv) {
+  const int mat = blockIdx.x, tid = threadIdx.x;
+  const T* W = a.W + (size_t)mat * a.mat_stride;
+  const int ld = a.ld;
+  __shared__ T sL[2][NB][NB + 1];   // L11, L22 (unit lower, strict parts used)
+  __shared__ T sI[2][NB][NB + 1];   // their inverses
+  for (int i = tid; i < NB * NB; i += 256) {
+    const int r = i / NB, c = i % NB;
+    sL[0][r][c] = (c < r) ? W[wtix(j0 + r, j0 + c, ld)] : T(0);
+    sL[1][r][c] = (c < r && r < jb2) ? W[wtix(j0 + NB + r, j0 + NB + c, ld)] : T(0);
+  }
+  __syncthreads();
+  if (tid < 2 * NB) {  // forward substitution, one column per thread
+    const int b = tid / NB, j = tid % NB;
+    for (int i = 0; i < NB; ++i) {
+      T x = (i == j) ? T(1) : T(0);
+      if (i > j)
+        for (int k = j; k < i; ++k) x -= sL[b][i][k] * sI[b][k][j];
+      sI[b][i][j] = (i >= j) ? x : T(0);
+    }
+  }
+  __syncthreads();
+  // sL[0] <- L21 L11^{-1} (rows beyond jb2 are zero)
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e / NB, c = e % NB;
     T s = T(0);
-    for (int m = part; m < i; m += 4) s += sL[i * NB + m] * sX[m * NC + col];
-    sP[part][col] = s;
-    __syncthreads();
-    if (part == 0) sX[i * NC + col] -= sP[0][col] + sP[1][col] + sP[2][col] + sP[3][col];
-    __syncthreads();
+    if (r < jb2)
+      for (int k = c; k < NB; ++k) s += W[wtix(j0 + NB + r, j0 + k, ld)] * sI[0][k][c];
+    sL[0][r][c] = s;
+  }
+  __syncthreads();
+  T* out = Linv + (size_t)mat * 4 * NB * NB;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e / NB, c = e % NB;
+    T s = T(0);
+    for (int k = 0; k <= r; ++k) s += sI[1][r][k] * sL[0][k][c];
+    out[(size_t)r * 2 * NB + c] = sI[0][r][c];
+    out[(size_t)r * 2 * NB + NB + c] = T(0);
+    out[(size_t)(NB + r) * 2 * NB + c] = -s;
+    out[(size_t)(NB + r) * 2 * NB + NB + c] = sI[1][r][c];
   }
 }
 
-// Two consecutive 64-column blocks b1 = [j0, j0 + 64), b2 = [j0 + 64, j0 + 64 + jb2)
-// applied to one strip right of both: the row swaps of b1 then b2, then
-//   U12_1 = L11^{-1} A12_1,  A12_2 -= L21(b2 rows, b1 cols) U12_1,  U12_2 = L22^{-1} A12_2,
-// written back to the rows [j0, j0 + 64 + jb2) of the strip.
+// Two consecutive 64-column blocks applied to one 64-column strip right of
+// both: the row swaps of b1 then b2 (as gathers), then
+//   [U12_1; U12_2] = L^{-1} [A12_1; A12_2]
+// with the 128 x 128 inverse of k_linv2, on MFMA, written back to the rows
+// [j0, j0 + 64 + jb2) of the strip.
 template <class T>
-__global__ void __launch_bounds__(256) k_u12b2(LuArgs<T> a, int j0, int jb2, int strip0) {
+__global__ void __launch_bounds__(256) k_u12lin(LuArgs<T> a, int j0, int jb2, int strip0, const T* __restrict__ Linv) {
+  typedef typename Mfma<T>::v4 v4;
   const int mat = blockIdx.y;
   const int cs = strip0 + blockIdx.x * NC;
   const int live0 = j0 + NB + jb2;
   T* W = a.W + (size_t)mat * a.mat_stride;
   const int ld = a.ld, tid = threadIdx.x;
-  __shared__ T sL[NB * NB];
-  __shared__ T sU1[NB * NC];
-  __shared__ T sU2[NB * NC];
-  __shared__ T sP[4][NC];
+  __shared__ T sB[2 * NB * NC];
   __shared__ int s_src[2 * NB], s_dst[2 * NB];
   const int c = tid & (NC - 1);
   const bool cok = cs + c >= live0 && cs + c < ld;
@@ -416,43 +454,43 @@ __global__ void __launch_bounds__(256) k_u12b2(LuArgs<T> a, int j0, int jb2, int
     }
     __syncthreads();
   }
-  for (int i = tid; i < NB * NB; i += 256) {
-    const int r = i / NB, cc = i % NB;
-    sL[i] = W[wtix((j0 + r), j0 + cc, ld)];
-  }
-  for (int i = tid; i < NB * NC; i += 256) {
+  const int nr = NB + jb2;
+  for (int i = tid; i < 2 * NB * NC; i += 256) {
     const int r = i / NC, cc = i % NC;
-    const bool ok = cs + cc >= live0 && cs + cc < ld;
-    sU1[i] = ok ? W[wtix((j0 + r), cs + cc, ld)] : T(0);
-    sU2[i] = (ok && r < jb2) ? W[wtix((j0 + NB + r), cs + cc, ld)] : T(0);
+    const bool ok = r < nr && cs + cc >= live0 && cs + cc < ld;
+    sB[i] = ok ? W[wtix(j0 + r, cs + cc, ld)] : T(0);
   }
   __syncthreads();
-  trsm_lds(sL, sU1, NB, sP, tid);
-  for (int i = tid; i < NB * NB; i += 256) {
-    const int r = i / NB, cc = i % NB;
-    sL[i] = (r < jb2) ? W[wtix((j0 + NB + r), j0 + cc, ld)] : T(0);
-  }
-  __syncthreads();
-  {
-    const int col = tid % NC, part = tid / NC;
-    for (int i = part; i < jb2; i += 4) {
-      T s = T(0);
-      for (int m = 0; m < NB; ++m) s += sL[i * NB + m] * sU1[m * NC + col];
-      sU2[i * NC + col] -= s;
+  constexpr int KS = 2 * NB / 4;  // k-steps per lane group (K = 128)
+  const int lane = tid & 63, wave = tid >> 6, grp = lane >> 4, col = lane & 15;
+  const T* Lm = Linv + (size_t)mat * 4 * NB * NB;
+  for (int t = wave; t < 2 * NB / 16; t += 4) {
+    const int r0 = t * 16;
+    if (r0 >= nr) break;
+    T af[KS];
+    const T* ap = Lm + (size_t)(r0 + col) * 2 * NB + KS * grp;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) af[s] = ap[s];
+    v4 acc[NC / 16];
+#pragma unroll
+    for (int ct = 0; ct < NC / 16; ++ct)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[ct][i] = T(0);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+#pragma unroll
+      for (int ct = 0; ct < NC / 16; ++ct)
+        acc[ct] = Mfma<T>::op(af[s], sB[(KS * grp + s) * NC + ct * 16 + col], acc[ct]);
     }
-  }
-  __syncthreads();
-  for (int i = tid; i < NB * NB; i += 256) {
-    const int r = i / NB, cc = i % NB;
-    sL[i] = (r < jb2 && cc < jb2) ? W[wtix((j0 + NB + r), j0 + NB + cc, ld)] : T(0);
-  }
-  __syncthreads();
-  trsm_lds(sL, sU2, jb2, sP, tid);
-  for (int i = tid; i < NB * NC; i += 256) {
-    const int r = i / NC, cc = i % NC;
-    if (cs + cc >= live0 && cs + cc < ld) {
-      W[wtix((j0 + r), cs + cc, ld)] = sU1[i];
-      if (r < jb2) W[wtix((j0 + NB + r), cs + cc, ld)] = sU2[i];
+#pragma unroll
+    for (int ct = 0; ct < NC / 16; ++ct) {
+      const int cc = cs + ct * 16 + col;
+      if (cc < live0 || cc >= ld) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = r0 + Mfma<T>::row(i, grp);
+        if (r < nr) W[wtix(j0 + r, cc, ld)] = acc[ct][i];
+      }
     }
   }
 }
@@ -480,7 +518,7 @@ struct GemmArgs {
 };
 
 template <class T, int KB>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> g) {
+__global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs<T> g) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int KS = KB / 4;  // MFMA k-steps; lane group grp covers k in [KS grp, KS grp + KS)
   const int mat = blockIdx.z;
@@ -552,11 +590,14 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs<T> g) {
 }  // namespace
 
 // Eliminate the first n_piv columns of `batch` matrices (see file comment).
-// scratch: batch NB x NB block inverses (type T), then batch x 2 PERM_STRIDE ints.
+// scratch: batch NB x NB block inverses (type T), batch x 2 PERM_STRIDE ints,
+// then (256-byte aligned) batch 128 x 128 unit-lower block inverses (type T).
 template <class T>
 hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
                         int n_cols, int* ipiv, int ipiv_stride, int* status, T* scratch) {
   int* perm = reinterpret_cast<int*>(scratch + (size_t)batch * NB * NB);
+  T* Linv = reinterpret_cast<T*>(
+      (reinterpret_cast<uintptr_t>(perm + (size_t)batch * 2 * PERM_STRIDE) + 255) & ~uintptr_t(255));
   LuArgs<T> a{W, mat_stride, ld, n_piv, n_rows, n_cols, ipiv, ipiv_stride, status, perm};
   if (ld % NC != 0) return hipErrorInvalidValue;
   const int rpt = (n_piv + PANEL_THREADS - 1) / PANEL_THREADS;
@@ -609,7 +650,8 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
     const int live0 = j0 + NB + jb2, strip0 = live0 / NC * NC;
     const int nstrip = (n_cols > live0) ? (n_cols - strip0 + NC - 1) / NC : 0;
     if (nstrip > 0) {
-      hipLaunchKernelGGL(k_u12b2<T>, dim3(nstrip, batch), dim3(256), 0, s, a, j0, jb2, strip0);
+      hipLaunchKernelGGL(k_linv2<T>, dim3(batch), dim3(256), 0, s, a, j0, jb2, Linv);
+      hipLaunchKernelGGL(k_u12lin<T>, dim3(nstrip, batch), dim3(256), 0, s, a, j0, jb2, strip0, Linv);
       update(j0, NB + jb2, live0, strip0, nstrip, ld);
     }
   }

@@ -40,7 +40,8 @@ class StageDriver:
     """Newton solves of DIRK stages on one library context."""
 
     def __init__(self, ctx, rtol=1e-8, restart=30, inner_its=5, max_outer=300, newton_abs=1e-10, newton_rel=1e-8,
-                 max_newton=20, inner_prec=HDG_FP64, condense_prec=HDG_FP64, mark=None, use_learned=False):
+                 max_newton=20, inner_prec=HDG_FP64, condense_prec=HDG_FP64, mark=None, use_learned=False,
+                 graph_steps=0):
         import torch
         self.ctx = ctx
         # optional callback mark(phase) at phase boundaries ("linearize", "condense",
@@ -48,7 +49,7 @@ class StageDriver:
         self.mark = mark if mark is not None else (lambda phase: None)
         self.t = torch
         self.kry = dict(rtol=rtol, restart=restart, inner_its=inner_its, max_outer=max_outer, inner_prec=inner_prec,
-                        use_learned=use_learned)
+                        use_learned=use_learned, graph_steps=graph_steps)
         self.newton_abs, self.newton_rel, self.max_newton = newton_abs, newton_rel, max_newton
         self.condense_prec = condense_prec
         dev = dict(dtype=torch.float64, device="cuda")
