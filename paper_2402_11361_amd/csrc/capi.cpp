@@ -301,7 +301,6 @@ hdg_status hdg_setup_mesh(const hdg_mesh_desc* mesh, const hdg_phys* phys, void*
   }
   std::string err;
   if (!build_mesh(in, c.hm, err)) { delete h; return HDG_EINVAL; }
-  if (phys->supg) { delete h; return HDG_EUNSUPPORTED; }
   if (!(phys->gamma > 1.0) || !(phys->Pr > 0) || !(phys->Re > 0) || !(phys->Mach > 0)) { delete h; return HDG_EINVAL; }
   bool any_bnd = false;
   for (int v : c.hm.macro_bnd) any_bnd |= (v != 0);
@@ -373,13 +372,13 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
     rebase(c.ws.Kq); rebase(c.ws.AUU); rebase(c.ws.AUQ); rebase(c.ws.RUe); rebase(c.ws.RQe); rebase(c.ws.SUB);
     rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.gloc); rebase(c.ws.Wm);
     rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.ypart); rebase(c.ws.kry);
-    rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn); rebase(c.ws.kctl);
+    rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn); rebase(c.ws.kctl); rebase(c.ws.supg);
   } else {
     auto rebase = [&](auto*& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(base + reinterpret_cast<uintptr_t>(p)); };
     rebase(c.ws.Kq); rebase(c.ws.AUU); rebase(c.ws.AUQ); rebase(c.ws.RUe); rebase(c.ws.RQe); rebase(c.ws.SUB);
     rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.gloc); rebase(c.ws.Wm);
     rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.ypart); rebase(c.ws.kry);
-    rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn); rebase(c.ws.kctl);
+    rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn); rebase(c.ws.kctl); rebase(c.ws.supg);
   }
   c.ws.base = base;
   c.lrn_bound = false;

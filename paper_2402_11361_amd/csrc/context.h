@@ -59,6 +59,7 @@ struct Workspace {
   double* Uinv = nullptr;   // [max(macros, faces)][64][64] block inverses of the elimination
   float* lrn = nullptr;     // learned stage: X, Y [macros][cF] each, then the BF16 network
   double* kctl = nullptr;   // device-resident Krylov control block (Hessenbergs, rotations, scalars)
+  double* supg = nullptr;   // SUPG products of a chunk of elements (only with SUPG on)
 };
 
 struct HdgContext {
@@ -84,6 +85,7 @@ struct HdgContext {
   int off_AUB = 0, off_ABU = 0, off_ABQ = 0, off_ABB = 0, off_RB = 0;
   bool have_a32 = false;
   int cond_prec = 0;
+  long long supg_chunk = 0;  // elements per SUPG product batch
   // learned coarse correction
   bool lrn_bound = false;
   int lrn_hidden = 0;

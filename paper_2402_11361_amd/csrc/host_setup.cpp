@@ -454,7 +454,7 @@ void plan_workspace(HdgContext& c) {
   c.ldf = (int)align_up(2 * c.nf_max, 64);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, gloc, Wm, ipiv, FW, fpiv, A32, ypart, kry, red, small, Uinv, lrn, kctl; } o;
+  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, gloc, Wm, ipiv, FW, fpiv, A32, ypart, kry, red, small, Uinv, lrn, kctl, supg; } o;
   o.Kq = take(sizeof(double) * n_el * c.Kstride);
   o.AUU = take(sizeof(double) * n_el * c.nsA * c.nsA);
   o.AUQ = take(sizeof(double) * n_el * c.nsA * c.dnsA);
@@ -485,6 +485,9 @@ void plan_workspace(HdgContext& c) {
   o.lrn = take(sizeof(float) * (2 * (size_t)hm.n_macros * hc.cF + 16) +
                sizeof(unsigned short) * mlp_param_count(hc.cF, LRN_MAX_HIDDEN, hc.cF));
   o.kctl = take(sizeof(double) * 8192);
+  // SUPG: the per-element products are formed in batches of up to 4096 elements
+  c.supg_chunk = c.ph.supg ? std::min<long long>((long long)hm.n_macros * hc.E, 4096) : 0;
+  o.supg = take(sizeof(double) * (size_t)c.supg_chunk * (c.ph.supg ? supg_scratch_per_element(hc.dim, hc.p) : 0));
   c.need_bytes = off;
   // remember offsets in the workspace struct (resolved on bind)
   c.ws.bytes = 0;
@@ -512,6 +515,7 @@ void plan_workspace(HdgContext& c) {
   c.ws.Uinv = reinterpret_cast<double*>(o.Uinv);
   c.ws.lrn = reinterpret_cast<float*>(o.lrn);
   c.ws.kctl = reinterpret_cast<double*>(o.kctl);
+  c.ws.supg = reinterpret_cast<double*>(o.supg);
 }
 
 void node_coords(const HdgContext& c, double* macro_xyz, double* face_xyz) {

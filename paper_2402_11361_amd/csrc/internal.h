@@ -107,6 +107,8 @@ hipError_t launch_precond_apply(HdgContext& c, const double* x, double* y);
 hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, double* du);
 hipError_t launch_axpy(hipStream_t s, size_t n, double a, const double* x, double* y);
 hipError_t launch_norms(HdgContext& c, double* out3_dev);
+hipError_t launch_supg(HdgContext& c, const double* q, const double* u, const double* w, StageArgs sa);
+size_t supg_scratch_per_element(int dim, int p);
 hipError_t launch_cast_ahat(HdgContext& c);
 
 // learned coarse correction

@@ -518,6 +518,7 @@ hipError_t launch_linearize(HdgContext& c, const double* q, const double* u, con
   else if (D == 3 && P == 2) e = lin_dispatch<3, 2>(c, q, u, uhat, w, sa);
   else if (D == 3 && P == 3) e = lin_dispatch<3, 3>(c, q, u, uhat, w, sa);
   if (e != hipSuccess) return e;
+  if (c.ph.supg && (e = launch_supg(c, q, u, w, sa)) != hipSuccess) return e;
   const int nm = c.hm.n_macros;
   const long long nn = (long long)nm * c.cd.N;
   hipLaunchKernelGGL(k_gather_res, dim3((unsigned)std::min<long long>((nn + 255) / 256, 65535)), dim3(256), 0, c.stream,

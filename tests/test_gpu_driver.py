@@ -9,13 +9,16 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("case", [dict(dim=2, n_elem=4, m=2, p=2, periodic=True, mach=0.1, Re=100.0),
-                                  dict(dim=2, n_elem=4, m=2, p=1, periodic=False, state="shear", mach=0.2)])
+                                  dict(dim=2, n_elem=4, m=2, p=1, periodic=False, state="shear", mach=0.2),
+                                  dict(dim=2, n_elem=4, m=2, p=2, periodic=True, mach=0.1, Re=100.0, supg=True)])
 def test_dirk_step_matches_oracle(case):
     from oracle.newton import dirk_step
     from paper_2402_11361_amd.driver import StageDriver, alexander_dirk33
     from oracle import dirk
     say(f"[driver] {case}")
-    S, inp, ctx = make_pair(case)
+    case = dict(case)
+    supg = case.pop("supg", False)
+    S, inp, ctx = make_pair(case, supg=supg)
     A, b, c = alexander_dirk33()
     Ao, bo, co = dirk.dirk33()
     assert np.allclose(A, Ao, rtol=0, atol=1e-14)

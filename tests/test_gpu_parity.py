@@ -17,6 +17,10 @@ CASES = {
     "C1_2d_16x16_m4_p2": dict(dim=2, n_elem=16, m=4, p=2, periodic=False, state="shear", mach=0.2, Re=100.0),
     "3d_per_p2": dict(dim=3, n_elem=4, m=2, p=2, periodic=True),
     "3d_dir_p1": dict(dim=3, n_elem=4, m=2, p=1, periodic=False, state="shear", mach=0.2),
+    # SUPG on (frozen A_k and tau; strong residual in group form)
+    "2d_dir_p2_supg": dict(dim=2, n_elem=6, m=3, p=2, periodic=False, state="shear", mach=0.2, supg=True),
+    "2d_per_p3_supg": dict(dim=2, n_elem=4, m=2, p=3, periodic=True, supg=True),
+    "3d_per_p2_supg": dict(dim=3, n_elem=4, m=2, p=2, periodic=True, supg=True),
 }
 
 
@@ -37,7 +41,9 @@ def pairs():
 def _get(pairs, name):
     if name not in pairs:
         say(f"[setup] {name}")
-        S, inp, ctx = make_pair(CASES[name])
+        case = dict(CASES[name])
+        supg = case.pop("supg", False)
+        S, inp, ctx = make_pair(case, supg=supg)
         d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
         nrm = ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
         macros = list(range(S.mesh.n_macros)) if S.mesh.n_macros <= 16 else [0, 5, S.mesh.n_macros - 1]
