@@ -46,15 +46,7 @@ def sources_sha():
 
 def workload_arrays(ctx, cfg, seed=0):
     from paper_2402_11361_amd import inputs
-    mx, fx = ctx.node_coords()
-    N = ctx.n_u_macro // (cfg["dim"] + 2)
-    nf_nodes = None
-    macro_coords = [mx[i * N:(i + 1) * N] for i in range(ctx.n_macros)]
-    # faces: uniform size on this workload
-    nfn = (ctx.n_glob // (cfg["dim"] + 2))
-    n_faces = 3 * ctx.n_macros
-    per = nfn // n_faces
-    face_coords = [fx[f * per:(f + 1) * per] for f in range(n_faces)]
+    macro_coords, face_coords = ctx.node_coords_split()
     u, q, uh = inputs.make_state(cfg, macro_coords, face_coords, seed=seed)
     return u, q, uh
 

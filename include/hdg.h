@@ -20,6 +20,8 @@
  *       u     [macro][comp][node]         comp = rho, rho v_1..v_d, rho E
  *       q     [macro][dir][comp][node]    q = grad u (eq. C4)
  *       uhat  [face][comp][facenode]      trace on the macro skeleton
+ *     Macros may differ in size (segment lengths per axis): macro i starts at
+ *     u_off[i] in u and at dim * u_off[i] in q (hdg_macro_offsets).
  *     Macros are numbered s_0 + n_seg0 (s_1 + n_seg1 s_2); macro nodes
  *     i_0 + n_0 (i_1 + n_1 i_2) with n_k = m_k p + 1 (GLL points in every
  *     element, C0 inside the macro).  Faces: all faces normal to axis 0, then
@@ -54,8 +56,10 @@ typedef enum { HDG_FP64 = 0, HDG_FP32 = 1 } hdg_prec;
 
 /* Box mesh on [lo, hi] with n_elem[k] uniform elements per axis, grouped into
  * box macro-elements: along axis k the segments have seg_len[k][0..n_seg[k])
- * elements (host arrays, summing to n_elem[k]).  Degree p in every element
- * (p = 1..3).  dim = 2 or 3.  Paper Sec. 2.2 (mesh, patches, spaces). */
+ * elements (host arrays, summing to n_elem[k]; lengths may differ, giving
+ * macros of several shapes, each shape one class of reference tables).
+ * Degree p in every element (p = 1..3; 3D p = 3 is HDG_EUNSUPPORTED).
+ * dim = 2 or 3.  Paper Sec. 2.2 (mesh, patches, spaces). */
 typedef struct {
   int dim;
   int n_elem[3];
@@ -81,9 +85,10 @@ typedef struct {
   size_t n_glob;       /* global trace unknowns (length of uhat)             */
   size_t n_u_tot;      /* length of u                                        */
   size_t n_q_tot;      /* length of q                                        */
-  size_t n_u_macro;    /* u unknowns per macro (n_s N)                       */
-  size_t n_b_macro;    /* trace unknowns on one macro's boundary             */
+  size_t n_u_macro;    /* u unknowns per macro (n_s N), largest macro        */
+  size_t n_b_macro;    /* trace unknowns on a macro's boundary, largest macro */
   size_t workspace_bytes; /* device workspace needed by hdg_bind_workspace   */
+  size_t n_faces;      /* macro faces (entries of face_off)                  */
 } hdg_sizes;
 
 /* Krylov options (Sec. 4.2): outer right-preconditioned FGMRES(restart) whose
@@ -135,6 +140,15 @@ hdg_status hdg_setup_mesh(const hdg_mesh_desc* mesh, const hdg_phys* phys, void*
                           hdg_ctx* out);
 
 hdg_status hdg_query_sizes(hdg_ctx ctx, hdg_sizes* out);
+
+/* Per-macro offsets (host arrays of n_macros + 1 entries, either may be
+ * NULL): u_off[i] = first entry of macro i in u (q: dim * u_off[i]);
+ * b_off[i] = first entry of macro i's boundary trace vector in the
+ * concatenation of all macros' local trace vectors (n_b per macro). */
+hdg_status hdg_macro_offsets(hdg_ctx ctx, long long* u_off, long long* b_off);
+
+/* face_off (host, n_faces + 1 entries): first entry of each face in uhat. */
+hdg_status hdg_face_offsets(hdg_ctx ctx, long long* face_off);
 
 /* Node coordinates for building inputs: macro nodes [macro][node][dim] and
  * trace nodes [face][facenode][dim], host arrays of n_u_tot/(dim+2)*dim and
@@ -259,13 +273,14 @@ const char* hdg_status_string(hdg_status s);
 const char* hdg_last_error(hdg_ctx ctx);
 
 /* Inspection (tests): copy macro `macro`'s condensed block A-hat^{T_i}
- * (n_b x n_b row-major) and b-hat^{T_i} (n_b) to host memory (synchronises).
+ * (n_b x n_b row-major, n_b of that macro) and b-hat^{T_i} (n_b) to host
+ * memory (synchronises).
  * Valid after hdg_condense. */
 hdg_status hdg_get_condensed(hdg_ctx ctx, size_t macro, double* ahat_host, double* bhat_host);
 
 /* Inspection (tests): run only the formation step of hdg_condense and copy
  * the augmented matrix [[S, -C, f], [D, E, g]] of macro `macro` to host
- * ((n_u + n_b) x (n_u + n_b + 1) row-major), with C = -A_u,uhat + A_uq
+ * ((n_u + n_b) x (n_u + n_b + 1) row-major, sizes of that macro), with C = -A_u,uhat + A_uq
  * A_qq^{-1} A_q,uhat, f = A_uq A_qq^{-1} R_Q - R_U, D = A_uhat,u - A_uhat,q
  * A_qq^{-1} A_qu, E = A_uhat,uhat - A_uhat,q A_qq^{-1} A_q,uhat, g = -R_Uhat +
  * A_uhat,q A_qq^{-1} R_Q (eq. ASC2).  Valid after hdg_linearize_stage. */

@@ -16,8 +16,7 @@
 #include <cstring>
 #include <new>
 
-hipError_t launch_face_sum(HdgContext& c, const double* base, long long macro_stride, long long elem_stride, double* out,
-                           long long tiled_rc);
+hipError_t launch_face_sum(HdgContext& c, const double* base, double* out);
 hipError_t launch_zero_ints(hipStream_t s, int* p, int n);
 
 namespace {
@@ -66,7 +65,7 @@ struct Krylov {
     r = k; k += n;
     w = k; k += n;
     t = k; k += n;
-    dev_coef = c.ws.small + 64;   // up to 512 doubles
+    dev_coef = c.ws.small + 1024;  // up to 512 doubles (the first 1024 hold the status flags)
     partial = c.ws.red;
   }
 
@@ -307,11 +306,14 @@ hdg_status hdg_setup_mesh(const hdg_mesh_desc* mesh, const hdg_phys* phys, void*
   if (any_bnd && !phys->bc_state_host) { delete h; return HDG_EINVAL; }
   if (mesh->dim == 3 && mesh->p == 3) { delete h; return HDG_EUNSUPPORTED; }
   c.stream = static_cast<hipStream_t>(hip_stream);
-  build_class(c.hm, c.hc);
+  c.hcs.resize(c.hm.n_classes);
+  for (int k = 0; k < c.hm.n_classes; ++k) build_class(c.hm, c.hcs[k], c.hm.class_m[k]);
+  c.hc = c.hcs[0];
   c.ph.gamma = phys->gamma; c.ph.Pr = phys->Pr; c.ph.Re = phys->Re; c.ph.Mach = phys->Mach; c.ph.mu = 1.0;
   c.ph.Re_c = phys->Re / phys->Mach;
   c.ph.kappa = c.ph.mu / (c.ph.Re_c * c.ph.Pr * (c.ph.gamma - 1.0));
   c.ph.supg = phys->supg;
+  plan_workspace(c);
   try {
     upload_tables(c);
     if (any_bnd) {
@@ -330,7 +332,6 @@ hdg_status hdg_setup_mesh(const hdg_mesh_desc* mesh, const hdg_phys* phys, void*
     delete h;
     return HDG_EDEVICE;
   }
-  plan_workspace(c);
   if (hipHostMalloc((void**)&h->pinned, 8192 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     for (void* p : c.dev_allocs) (void)hipFree(p);
     delete h;
@@ -347,9 +348,32 @@ hdg_status hdg_query_sizes(hdg_ctx ctx, hdg_sizes* out) {
   out->n_glob = c.hm.n_glob;
   out->n_u_tot = c.n_u_tot;
   out->n_q_tot = c.n_q_tot;
-  out->n_u_macro = c.hc.n_u;
-  out->n_b_macro = c.hc.n_b;
+  out->n_u_macro = 0;
+  out->n_b_macro = 0;
+  for (const HostClass& k : c.hcs) {
+    out->n_u_macro = std::max(out->n_u_macro, (size_t)k.n_u);
+    out->n_b_macro = std::max(out->n_b_macro, (size_t)k.n_b);
+  }
   out->workspace_bytes = c.need_bytes;
+  out->n_faces = c.hm.n_faces;
+  return HDG_OK;
+}
+
+hdg_status hdg_macro_offsets(hdg_ctx ctx, long long* u_off, long long* b_off) {
+  if (!ctx) return HDG_EINVAL;
+  const HostMesh& hm = ctx->c.hm;
+  for (int i = 0; i <= hm.n_macros; ++i) {
+    if (u_off) u_off[i] = hm.u_off[i];
+    if (b_off) b_off[i] = hm.b_off[i];
+  }
+  return HDG_OK;
+}
+
+hdg_status hdg_face_offsets(hdg_ctx ctx, long long* face_off) {
+  if (!ctx || !face_off) return HDG_EINVAL;
+  const HostMesh& hm = ctx->c.hm;
+  for (int f = 0; f < hm.n_faces; ++f) face_off[f] = hm.face_off[f];
+  face_off[hm.n_faces] = hm.n_glob;
   return HDG_OK;
 }
 
@@ -399,8 +423,8 @@ hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, co
   HIPCHK(&c, launch_linearize(c, q, u, uhat, w, sa));
   c.have_a32 = false;
   if (norms_host) {
-    HIPCHK(&c, launch_norms(c, c.ws.small + 8));
-    HIPCHK(&c, hipMemcpyAsync(ctx->pinned, c.ws.small + 8, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(&c, launch_norms(c, c.ws.small + 2048));
+    HIPCHK(&c, hipMemcpyAsync(ctx->pinned, c.ws.small + 2048, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
     HIPCHK(&c, hipStreamSynchronize(c.stream));
     for (int i = 0; i < 3; ++i) norms_host[i] = ctx->pinned[i];
     if (!std::isfinite(norms_host[0] + norms_host[1] + norms_host[2])) return fail(&c, HDG_ENAN, "non-finite residual");
@@ -414,20 +438,29 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
   if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
   if (prec != HDG_FP64 && prec != HDG_FP32) return fail(&c, HDG_EUNSUPPORTED, "condensation precision not built");
   const int p32 = (prec == HDG_FP32) ? 1 : 0;
+  // status flags: one per macro class, then one for the face blocks
+  const int ncl = c.hm.n_classes;
   int* status = reinterpret_cast<int*>(c.ws.small);
-  HIPCHK(&c, launch_zero_ints(c.stream, status, 2));
+  HIPCHK(&c, launch_zero_ints(c.stream, status, ncl + 1));
   HIPCHK(&c, launch_form(c, p32));
   HIPCHK(&c, launch_lu(c, p32));
   HIPCHK(&c, launch_bhat(c, bhat, p32));
   HIPCHK(&c, launch_face_precond(c));
   c.cond_prec = p32;
   c.have_a32 = false;
-  int st[2] = {0, 0};
-  HIPCHK(&c, hipMemcpyAsync(ctx->pinned, status, sizeof(int) * 2, hipMemcpyDeviceToHost, c.stream));
+  std::vector<int> st(ncl + 1, 0);
+  HIPCHK(&c, hipMemcpyAsync(ctx->pinned, status, sizeof(int) * (ncl + 1), hipMemcpyDeviceToHost, c.stream));
   HIPCHK(&c, hipStreamSynchronize(c.stream));
-  std::memcpy(st, ctx->pinned, sizeof(st));
-  if (st[0]) return fail(&c, HDG_ESINGULAR, "singular Schur complement in macro " + std::to_string(st[0] - 1));
-  if (st[1]) return fail(&c, HDG_ESINGULAR, "singular face block of A_uhat-uhat " + std::to_string(st[1] - 1));
+  std::memcpy(st.data(), ctx->pinned, sizeof(int) * (ncl + 1));
+  for (int k = 0; k < ncl; ++k) {
+    if (!st[k]) continue;
+    // the st[k]-th macro of class k (macros of a class in increasing order)
+    int rank = st[k] - 1, macro = -1;
+    for (int i = 0; i < c.hm.n_macros && macro < 0; ++i)
+      if (c.hm.macro_class[i] == k && rank-- == 0) macro = i;
+    return fail(&c, HDG_ESINGULAR, "singular Schur complement in macro " + std::to_string(macro));
+  }
+  if (st[ncl]) return fail(&c, HDG_ESINGULAR, "singular face block of A_uhat-uhat " + std::to_string(st[ncl] - 1));
   return HDG_OK;
 }
 
@@ -720,17 +753,18 @@ hdg_status hdg_destroy(hdg_ctx ctx) {
 // one tiled macro matrix to the host, widened to double if stored in FP32
 static hdg_status copy_tiled_macro(hdg_ctx ctx, size_t macro, std::vector<double>& out, int prec) {
   HdgContext& c = ctx->c;
-  out.assign((size_t)c.wstride, 0.0);
+  const long long ws = c.hcs[c.hm.macro_class[macro]].wstride;
+  const long long wo = c.hm.w_off[macro];
+  out.assign((size_t)ws, 0.0);
   if (prec == 1) {
-    std::vector<float> f((size_t)c.wstride);
-    HIPCHK(&c, hipMemcpyAsync(f.data(), reinterpret_cast<const float*>(c.ws.Wm) + macro * (size_t)c.wstride,
-                              sizeof(float) * c.wstride, hipMemcpyDeviceToHost, c.stream));
+    std::vector<float> f((size_t)ws);
+    HIPCHK(&c, hipMemcpyAsync(f.data(), reinterpret_cast<const float*>(c.ws.Wm) + wo, sizeof(float) * ws,
+                              hipMemcpyDeviceToHost, c.stream));
     HIPCHK(&c, hipStreamSynchronize(c.stream));
     for (size_t i = 0; i < f.size(); ++i) out[i] = f[i];
     return HDG_OK;
   }
-  HIPCHK(&c, hipMemcpyAsync(out.data(), c.ws.Wm + macro * (size_t)c.wstride, sizeof(double) * c.wstride,
-                            hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(&c, hipMemcpyAsync(out.data(), c.ws.Wm + wo, sizeof(double) * ws, hipMemcpyDeviceToHost, c.stream));
   HIPCHK(&c, hipStreamSynchronize(c.stream));
   return HDG_OK;
 }
@@ -739,20 +773,21 @@ hdg_status hdg_get_condensed(hdg_ctx ctx, size_t macro, double* ahat_host, doubl
   if (!ctx) return HDG_EINVAL;
   HdgContext& c = ctx->c;
   if (!c.ws_bound || macro >= (size_t)c.hm.n_macros) return HDG_EINVAL;
-  const int nb = c.hc.n_b, nu = c.hc.n_u;
+  const HostClass& hk = c.hcs[c.hm.macro_class[macro]];
+  const int nb = hk.n_b, nu = hk.n_u;
   std::vector<double> tiled;
   hdg_status s = copy_tiled_macro(ctx, macro, tiled, c.cond_prec);
   if (s != HDG_OK) return s;
   std::vector<double> g(nb, 0.0);  // FP32 condensation keeps g in FP64 outside W
   if (c.cond_prec == 1) {
-    HIPCHK(&c, hipMemcpyAsync(g.data(), c.ws.gloc + macro * (size_t)nb, sizeof(double) * nb, hipMemcpyDeviceToHost,
+    HIPCHK(&c, hipMemcpyAsync(g.data(), c.ws.gloc + c.hm.b_off[macro], sizeof(double) * nb, hipMemcpyDeviceToHost,
                               c.stream));
     HIPCHK(&c, hipStreamSynchronize(c.stream));
   }
   for (int r = 0; r < nb; ++r) {
     if (ahat_host)
-      for (int k = 0; k < nb; ++k) ahat_host[(size_t)r * nb + k] = tiled[wtix(nu + r, nu + k, c.ldw)];
-    if (bhat_host) bhat_host[r] = g[r] + tiled[wtix(nu + r, c.n_cols - 1, c.ldw)];
+      for (int k = 0; k < nb; ++k) ahat_host[(size_t)r * nb + k] = tiled[wtix(nu + r, nu + k, hk.ldw)];
+    if (bhat_host) bhat_host[r] = g[r] + tiled[wtix(nu + r, hk.n_cols - 1, hk.ldw)];
   }
   return HDG_OK;
 }
@@ -766,8 +801,9 @@ hdg_status hdg_get_formed(hdg_ctx ctx, size_t macro, double* w_host) {
   std::vector<double> tiled;
   hdg_status s = copy_tiled_macro(ctx, macro, tiled, 0);
   if (s != HDG_OK) return s;
-  for (int r = 0; r < c.n_rows; ++r)
-    for (int k = 0; k < c.n_cols; ++k) w_host[(size_t)r * c.n_cols + k] = tiled[wtix(r, k, c.ldw)];
+  const HostClass& hk = c.hcs[c.hm.macro_class[macro]];
+  for (int r = 0; r < hk.n_rows; ++r)
+    for (int k = 0; k < hk.n_cols; ++k) w_host[(size_t)r * hk.n_cols + k] = tiled[wtix(r, k, hk.ldw)];
   return HDG_OK;
 }
 

@@ -15,6 +15,9 @@ struct HostClass {
   std::vector<double> Phi, dPhi, W, Tvol, Mel, Psi, WF, C1D, Minv1D, M1D;
   int cq = 0, cF = 0, cmaxf = 0;
   std::vector<double> cR, cPhi;
+  // tiled augmented matrix
+  int ldw = 0, n_rows = 0, n_cols = 0;
+  long long wstride = 0;
   std::vector<int> fnode, finv, elem_nodes, elem_sub, sub_elem, sub_lf, sub_tid, node_ne, node_e, node_a,
       tn_cnt, tn_sub, tn_t, tn_base;
 };
@@ -28,8 +31,16 @@ struct HostMesh {
   long long n_glob;
   std::vector<int> macro_face, macro_bnd, face_axis, face_minus, face_plus, face_ndof, face_nodes;
   std::vector<long long> face_off;
-  std::vector<int> face_tn[HDG_MAXF];  // unused placeholder
   std::vector<std::array<int, 3>> face_grid;
+  // macro classes (distinct m per axis) and per-macro offsets
+  int n_classes = 0;
+  std::vector<std::array<int, 3>> class_m;        // m per axis of each class
+  std::vector<int> macro_class;                   // [n_macros]
+  std::vector<long long> u_off, b_off, el_off, sub_off, row_off, a32_off;  // [n_macros + 1]
+  std::vector<int> elem_macro;
+  std::vector<long long> w_off, ipiv_off;         // [n_macros], grouped by class
+  std::vector<long long> class_w_base, class_ipiv_base;
+  std::vector<int> class_count, class_first;      // macros per class; first macro of the class
 };
 
 struct Workspace {
@@ -64,8 +75,10 @@ struct Workspace {
 
 struct HdgContext {
   HostMesh hm;
-  HostClass hc;
-  ClassDev cd{};
+  HostClass hc;               // class 0 (degree-dependent tables are the same for every class)
+  ClassDev cd{};              // device view of class 0
+  std::vector<HostClass> hcs; // every class
+  std::vector<ClassDev> cds;  // device views of every class (uploaded as MeshDev::cls)
   PhysDev ph{};
   MeshDev md{};
   hipStream_t stream = nullptr;
@@ -110,7 +123,7 @@ struct HdgMeshIn {
 
 // host_setup.cpp
 bool build_mesh(const HdgMeshIn& in, HostMesh& hm, std::string& err);
-void build_class(const HostMesh& hm, HostClass& hc);
+void build_class(const HostMesh& hm, HostClass& hc, const std::array<int, 3>& m);
 void plan_workspace(HdgContext& c);
 void upload_tables(HdgContext& c);
 void node_coords(const HdgContext& c, double* macro_xyz, double* face_xyz);

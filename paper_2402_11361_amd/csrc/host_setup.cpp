@@ -139,9 +139,6 @@ bool build_mesh(const HdgMeshIn& in, HostMesh& hm, std::string& err) {
       s += hm.seg_len[k][i];
     }
     if (s != in.n_elem[k]) { err = "segments must cover the mesh"; return false; }
-    // one macro shape per mesh in this build
-    for (int i = 1; i < in.n_seg[k]; ++i)
-      if (hm.seg_len[k][i] != hm.seg_len[k][0]) { err = "non-uniform macro sizes are not supported"; return false; }
   }
   const int d = hm.dim;
   hm.n_macros = 1;
@@ -189,6 +186,20 @@ bool build_mesh(const HdgMeshIn& in, HostMesh& hm, std::string& err) {
   long long off = 0;
   for (int f = 0; f < hm.n_faces; ++f) { hm.face_off[f] = off; off += hm.face_ndof[f]; }
   hm.n_glob = off;
+  // macro classes: distinct element counts per axis, numbered in order of first appearance
+  hm.class_m.clear();
+  hm.macro_class.assign(hm.n_macros, 0);
+  for (int i = 0; i < hm.n_macros; ++i) {
+    std::array<int, 3> m{1, 1, 1};
+    int t = i;
+    for (int k = 0; k < d; ++k) { m[k] = hm.seg_len[k][t % hm.n_seg[k]]; t /= hm.n_seg[k]; }
+    int cls = -1;
+    for (int j = 0; j < (int)hm.class_m.size(); ++j)
+      if (hm.class_m[j] == m) { cls = j; break; }
+    if (cls < 0) { cls = (int)hm.class_m.size(); hm.class_m.push_back(m); }
+    hm.macro_class[i] = cls;
+  }
+  hm.n_classes = (int)hm.class_m.size();
   return true;
 }
 
@@ -255,11 +266,11 @@ static void build_coarse(HostClass& hc) {
   }
 }
 
-void build_class(const HostMesh& hm, HostClass& hc) {
+void build_class(const HostMesh& hm, HostClass& hc, const std::array<int, 3>& m) {
   const int d = hm.dim, p = hm.p, ns = hm.ns;
   hc.dim = d; hc.p = p; hc.ns = ns; hc.nq = p + 2;
   for (int k = 0; k < 3; ++k) { hc.m[k] = 1; hc.n1[k] = 1; hc.h[k] = hm.h[k]; }
-  for (int k = 0; k < d; ++k) { hc.m[k] = hm.seg_len[k][0]; hc.n1[k] = hc.m[k] * p + 1; }
+  for (int k = 0; k < d; ++k) { hc.m[k] = m[k]; hc.n1[k] = hc.m[k] * p + 1; }
   hc.N = hc.n1[0] * hc.n1[1] * hc.n1[2];
   hc.E = hc.m[0] * hc.m[1] * hc.m[2];
   const int A1 = p + 1, nq = hc.nq;
@@ -431,11 +442,10 @@ void build_class(const HostMesh& hm, HostClass& hc) {
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 void plan_workspace(HdgContext& c) {
-  const HostClass& hc = c.hc;
-  const HostMesh& hm = c.hm;
+  const HostClass& hc = c.hc;  // degree-dependent sizes (the same for every class)
+  HostMesh& hm = c.hm;
   const int d = hc.dim, ns = hc.ns, A = hc.A, T = hc.T, Q = hc.Q;
   c.nsA = ns * A; c.dnsA = d * ns * A;
-  const long long n_el = (long long)hm.n_macros * hc.E;
   const int nsT = ns * T;
   c.off_AUB = 0;
   c.off_ABU = c.off_AUB + nsT * nsT;
@@ -444,11 +454,59 @@ void plan_workspace(HdgContext& c) {
   c.off_RB = c.off_ABB + nsT * nsT;
   c.sub_stride = (int)align_up(c.off_RB + nsT, 4);
   c.Kstride = ns * ns * (1 + d) * d * Q;
-  c.n_u_tot = (long long)hm.n_macros * hc.n_u;
-  c.n_q_tot = (long long)hm.n_macros * hc.n_q;
-  c.n_rows = hc.n_u + hc.n_b;
-  c.n_cols = hc.n_u + hc.n_b + 1;
-  c.ldw = (int)align_up(c.n_cols, 64);
+  // tiled augmented matrix of every class
+  for (HostClass& k : c.hcs) {
+    k.n_rows = k.n_u + k.n_b;
+    k.n_cols = k.n_u + k.n_b + 1;
+    k.ldw = (int)align_up(k.n_cols, 64);
+    k.wstride = (long long)align_up(k.n_rows, 16) * k.ldw;
+  }
+  // per-macro offsets; matrices and pivots grouped by class
+  const int nm = hm.n_macros;
+  hm.u_off.assign(nm + 1, 0); hm.b_off.assign(nm + 1, 0); hm.el_off.assign(nm + 1, 0);
+  hm.sub_off.assign(nm + 1, 0); hm.row_off.assign(nm + 1, 0); hm.a32_off.assign(nm + 1, 0);
+  for (int i = 0; i < nm; ++i) {
+    const HostClass& k = c.hcs[hm.macro_class[i]];
+    hm.u_off[i + 1] = hm.u_off[i] + k.n_u;
+    hm.b_off[i + 1] = hm.b_off[i] + k.n_b;
+    hm.el_off[i + 1] = hm.el_off[i] + k.E;
+    hm.sub_off[i + 1] = hm.sub_off[i] + k.n_sub;
+    hm.row_off[i + 1] = hm.row_off[i] + k.n_rows;
+    hm.a32_off[i + 1] = hm.a32_off[i] + (long long)k.n_b * k.n_b;
+  }
+  hm.elem_macro.assign(hm.el_off[nm], 0);
+  for (int i = 0; i < nm; ++i)
+    for (long long e = hm.el_off[i]; e < hm.el_off[i + 1]; ++e) hm.elem_macro[e] = i;
+  const int ncl = hm.n_classes;
+  hm.class_count.assign(ncl, 0); hm.class_first.assign(ncl, -1);
+  for (int i = 0; i < nm; ++i) {
+    const int k = hm.macro_class[i];
+    if (hm.class_first[k] < 0) hm.class_first[k] = i;
+    ++hm.class_count[k];
+  }
+  hm.class_w_base.assign(ncl, 0); hm.class_ipiv_base.assign(ncl, 0);
+  long long wb = 0, pb = 0;
+  for (int k = 0; k < ncl; ++k) {
+    hm.class_w_base[k] = wb; hm.class_ipiv_base[k] = pb;
+    wb += hm.class_count[k] * c.hcs[k].wstride;
+    pb += (long long)hm.class_count[k] * c.hcs[k].n_u;
+  }
+  hm.w_off.assign(nm, 0); hm.ipiv_off.assign(nm, 0);
+  std::vector<int> rank(ncl, 0);
+  for (int i = 0; i < nm; ++i) {
+    const int k = hm.macro_class[i];
+    hm.w_off[i] = hm.class_w_base[k] + rank[k] * c.hcs[k].wstride;
+    hm.ipiv_off[i] = hm.class_ipiv_base[k] + (long long)rank[k] * c.hcs[k].n_u;
+    ++rank[k];
+  }
+  const long long n_el = hm.el_off[nm];
+  c.n_u_tot = hm.u_off[nm];
+  c.n_q_tot = (long long)d * hm.u_off[nm];
+  c.n_rows = 0; c.n_cols = 0; c.ldw = 0; c.wstride = 0;
+  for (const HostClass& k : c.hcs) {
+    c.n_rows = std::max(c.n_rows, k.n_rows); c.n_cols = std::max(c.n_cols, k.n_cols);
+    c.ldw = std::max(c.ldw, k.ldw); c.wstride = std::max(c.wstride, k.wstride);
+  }
   c.nf_max = 0;
   for (int f = 0; f < hm.n_faces; ++f) c.nf_max = std::max(c.nf_max, hm.face_ndof[f]);
   c.ldf = (int)align_up(2 * c.nf_max, 64);
@@ -460,21 +518,22 @@ void plan_workspace(HdgContext& c) {
   o.AUQ = take(sizeof(double) * n_el * c.nsA * c.dnsA);
   o.RUe = take(sizeof(double) * n_el * c.nsA);
   o.RQe = take(sizeof(double) * n_el * c.dnsA);
-  o.SUB = take(sizeof(double) * (size_t)hm.n_macros * hc.n_sub * c.sub_stride);
+  o.SUB = take(sizeof(double) * (size_t)hm.sub_off[nm] * c.sub_stride);
   o.RU = take(sizeof(double) * c.n_u_tot);
   o.RQ = take(sizeof(double) * c.n_q_tot);
   o.RQt = take(sizeof(double) * c.n_q_tot);
-  o.RBloc = take(sizeof(double) * (size_t)hm.n_macros * hc.n_b);
+  o.RBloc = take(sizeof(double) * (size_t)hm.b_off[nm]);
   o.RBglob = take(sizeof(double) * hm.n_glob);
-  o.gloc = take(sizeof(double) * (size_t)hm.n_macros * hc.n_b);
-  c.wstride = (long long)align_up(c.n_rows, 16) * c.ldw;
+  o.gloc = take(sizeof(double) * (size_t)hm.b_off[nm]);
   c.fstride = (long long)align_up(2 * c.nf_max, 16) * c.ldf;
-  o.Wm = take(sizeof(double) * (size_t)hm.n_macros * c.wstride);
-  o.ipiv = take(sizeof(int) * (size_t)hm.n_macros * hc.n_u);
+  long long w_total = 0;
+  for (int k = 0; k < hm.n_classes; ++k) w_total += hm.class_count[k] * c.hcs[k].wstride;
+  o.Wm = take(sizeof(double) * (size_t)w_total);
+  o.ipiv = take(sizeof(int) * (size_t)c.n_u_tot);
   o.FW = take(sizeof(double) * (size_t)hm.n_faces * c.fstride);
   o.fpiv = take(sizeof(int) * (size_t)hm.n_faces * c.nf_max);
-  o.A32 = take(sizeof(float) * (size_t)hm.n_macros * hc.n_b * hc.n_b);
-  o.ypart = take(sizeof(double) * (size_t)hm.n_macros * hc.n_b);
+  o.A32 = take(sizeof(float) * (size_t)hm.a32_off[nm]);
+  o.ypart = take(sizeof(double) * (size_t)hm.b_off[nm]);
   o.kry = take(sizeof(double) * (size_t)(2 * c.kry_restart_max + c.kry_inner_max + 8) * hm.n_glob);
   o.red = take(sizeof(double) * (1 << 20));
   o.small = take(sizeof(double) * 4096);
@@ -486,7 +545,7 @@ void plan_workspace(HdgContext& c) {
                sizeof(unsigned short) * mlp_param_count(hc.cF, LRN_MAX_HIDDEN, hc.cF));
   o.kctl = take(sizeof(double) * 8192);
   // SUPG: the per-element products are formed in batches of up to 4096 elements
-  c.supg_chunk = c.ph.supg ? std::min<long long>((long long)hm.n_macros * hc.E, 4096) : 0;
+  c.supg_chunk = c.ph.supg ? std::min<long long>(n_el, 4096) : 0;
   o.supg = take(sizeof(double) * (size_t)c.supg_chunk * (c.ph.supg ? supg_scratch_per_element(hc.dim, hc.p) : 0));
   c.need_bytes = off;
   // remember offsets in the workspace struct (resolved on bind)
@@ -520,7 +579,6 @@ void plan_workspace(HdgContext& c) {
 
 void node_coords(const HdgContext& c, double* macro_xyz, double* face_xyz) {
   const HostMesh& hm = c.hm;
-  const HostClass& hc = c.hc;
   const int d = hm.dim, p = hm.p;
   std::vector<double> g = gll(p);
   auto axis_coord = [&](int k, int seg, int i) {
@@ -534,6 +592,7 @@ void node_coords(const HdgContext& c, double* macro_xyz, double* face_xyz) {
     for (int i = 0; i < hm.n_macros; ++i) {
       int s[3] = {0, 0, 0}, t = i;
       for (int k = 0; k < d; ++k) { s[k] = t % hm.n_seg[k]; t /= hm.n_seg[k]; }
+      const HostClass& hc = c.hcs[hm.macro_class[i]];
       for (int n = 0; n < hc.N; ++n) {
         int ni[3] = {0, 0, 0}, tn = n;
         for (int k = 0; k < d; ++k) { ni[k] = tn % hc.n1[k]; tn /= hc.n1[k]; }
@@ -576,9 +635,8 @@ static const Tv* up(HdgContext& c, const std::vector<Tv>& v) {
   return static_cast<const Tv*>(p);
 }
 
-void upload_tables(HdgContext& c) {
-  HostClass& hc = c.hc;
-  ClassDev& cd = c.cd;
+static ClassDev upload_class(HdgContext& c, const HostClass& hc) {
+  ClassDev cd{};
   cd.dim = hc.dim; cd.p = hc.p; cd.nq = hc.nq; cd.ns = hc.ns;
   for (int k = 0; k < 3; ++k) { cd.m[k] = hc.m[k]; cd.n1[k] = hc.n1[k]; cd.h[k] = hc.h[k]; }
   cd.N = hc.N; cd.E = hc.E; cd.A = hc.A; cd.Q = hc.Q; cd.T = hc.T; cd.Fq = hc.Fq;
@@ -593,9 +651,25 @@ void upload_tables(HdgContext& c) {
   cd.C1D = up(c, hc.C1D); cd.Minv1D = up(c, hc.Minv1D); cd.M1D = up(c, hc.M1D);
   cd.cq = hc.cq; cd.cF = hc.cF; cd.cmaxf = hc.cmaxf;
   cd.cR = up(c, hc.cR); cd.cPhi = up(c, hc.cPhi);
+  cd.ldw = hc.ldw; cd.n_rows = hc.n_rows; cd.n_cols = hc.n_cols; cd.wstride = hc.wstride;
+  return cd;
+}
+
+// Device tables of every class and the mesh (after plan_workspace, which
+// fixes the per-class matrix layouts and the per-macro offsets).
+void upload_tables(HdgContext& c) {
+  c.cds.clear();
+  for (const HostClass& hc : c.hcs) c.cds.push_back(upload_class(c, hc));
+  c.cd = c.cds[0];
   HostMesh& hm = c.hm;
   MeshDev& md = c.md;
   md.dim = hm.dim; md.ns = hm.ns; md.n_macros = hm.n_macros; md.n_faces = hm.n_faces; md.n_glob = hm.n_glob;
   md.macro_face = up(c, hm.macro_face); md.macro_bnd = up(c, hm.macro_bnd); md.face_off = up(c, hm.face_off);
   md.face_ndof = up(c, hm.face_ndof); md.face_minus = up(c, hm.face_minus); md.face_plus = up(c, hm.face_plus);
+  md.cls = up(c, c.cds);
+  md.macro_class = up(c, hm.macro_class);
+  md.u_off = up(c, hm.u_off); md.b_off = up(c, hm.b_off); md.el_off = up(c, hm.el_off);
+  md.elem_macro = up(c, hm.elem_macro); md.sub_off = up(c, hm.sub_off); md.row_off = up(c, hm.row_off);
+  md.w_off = up(c, hm.w_off); md.a32_off = up(c, hm.a32_off);
 }
+

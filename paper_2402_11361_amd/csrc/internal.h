@@ -11,7 +11,8 @@
 #define HDG_MAXF 6
 
 // Reference tables of one macro shape (m per axis, degree p, element sizes h),
-// all device pointers.  Element-local node index a = a_0 + (p+1)(a_1 + (p+1)a_2);
+// all device pointers.  A mesh may hold several shapes (classes); every
+// macro refers to its class through MeshDev::macro_class.  Element-local node index a = a_0 + (p+1)(a_1 + (p+1)a_2);
 // quadrature index q likewise with nq = p + 2 Gauss points per direction.
 struct ClassDev {
   int dim, p, nq, ns;
@@ -57,6 +58,9 @@ struct ClassDev {
   int cq, cF, cmaxf;
   const double* cR;       // [dim][cq][cmaxf] discrete L2 projection (G^{-1} Phi^T W)
   const double* cPhi;     // [dim][cmaxf][cq] coarse functions at the face nodes
+  // tiled augmented matrix of the class
+  int ldw, n_rows, n_cols;
+  long long wstride;      // elements per matrix
 };
 
 struct PhysDev {
@@ -80,7 +84,32 @@ struct MeshDev {
   const int* face_minus;       // [n_faces] macro on the low side or -1
   const int* face_plus;        // [n_faces] macro on the high side or -1
   const double* bc_state;      // [n_glob] Dirichlet data (or null)
+  // macro classes and per-macro offsets (variable macro sizes)
+  const ClassDev* cls;         // [n_classes]
+  const int* macro_class;      // [n_macros]
+  const long long* u_off;      // [n_macros + 1] offset of the macro in u (and R_U); q offsets are dim * u_off
+  const long long* b_off;      // [n_macros + 1] offset in per-macro trace vectors (R_Uhat^(i), g, partial products)
+  const long long* el_off;     // [n_macros + 1] first global element
+  const int* elem_macro;       // [n_elements]
+  const long long* sub_off;    // [n_macros + 1] first global sub-face
+  const long long* row_off;    // [n_macros + 1] first row of the macro in the list of all augmented rows
+  const long long* w_off;      // [n_macros] offset (elements) of the macro's tiled matrix, grouped by class
+  const long long* a32_off;    // [n_macros + 1] offset of the macro's compact FP32 copy of A-hat
 };
+
+__device__ __forceinline__ const ClassDev& class_of(const MeshDev& md, int macro) {
+  return md.cls[md.macro_class[macro]];
+}
+
+// largest i in [0, n) with off[i] <= g (off ascending, off[0] = 0)
+__device__ __forceinline__ int find_in(const long long* off, int n, long long g) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (off[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
 
 // Storage of the augmented macro matrices (and of the face-preconditioner
 // blocks): 16 x 64 tiles, each tile contiguous and row-major, tiles ordered

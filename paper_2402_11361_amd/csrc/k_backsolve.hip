@@ -5,6 +5,7 @@
 //     dQ_k = A_qq^{-1}(-R_Q - A_qu dU - A_q,uh duhat)_k
 //          = -M^{-1} R_Q,k - C_k dU + sum_s sign_s M_k^{-1}[:, end_s] (x) duhat_(k,s)   (Csc4b)
 #include "context.h"
+#include <algorithm>
 
 namespace {
 
@@ -25,11 +26,13 @@ constexpr int BS_ROWS = 64;
 // W is the eliminated matrix in its storage type T (double or float); the
 // recovery itself runs in FP64.
 template <class T>
-__global__ void __launch_bounds__(256) k_bs_rhs(ClassDev cd, MeshDev md, const T* __restrict__ Wm, long long mstride,
-                                                int ld, int n_cols, const double* __restrict__ x, double* __restrict__ z) {
+__global__ void __launch_bounds__(256) k_bs_rhs(MeshDev md, const T* __restrict__ Wm, const double* __restrict__ x,
+                                                double* __restrict__ z) {
   extern __shared__ double xs[];
   const int macro = blockIdx.y;
-  const int nb = cd.n_b, nu = cd.n_u, d = cd.dim;
+  const ClassDev& cd = class_of(md, macro);
+  const int nb = cd.n_b, nu = cd.n_u, d = cd.dim, ld = cd.ldw, n_cols = cd.n_cols;
+  if (blockIdx.x * BS_ROWS >= nu) return;
   for (int s = threadIdx.x; s < nb; s += blockDim.x) {
     const int lf = local_face(cd, s);
     const int F = md.macro_face[(size_t)macro * 2 * d + lf];
@@ -37,28 +40,28 @@ __global__ void __launch_bounds__(256) k_bs_rhs(ClassDev cd, MeshDev md, const T
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const T* Wmac = Wm + (size_t)macro * mstride;
+  const T* Wmac = Wm + md.w_off[macro];
   for (int rr = wave; rr < BS_ROWS; rr += 4) {
     const int r = blockIdx.x * BS_ROWS + rr;
     if (r >= nu) break;
     double s = 0.0;
     for (int c = lane; c < nb; c += 64) s += (double)Wmac[wtix(r, nu + c, ld)] * xs[c];
     s = wave_sum(s);
-    if (lane == 0) z[(size_t)macro * nu + r] = (double)Wmac[wtix(r, n_cols - 1, ld)] - s;
+    if (lane == 0) z[md.u_off[macro] + r] = (double)Wmac[wtix(r, n_cols - 1, ld)] - s;
   }
 }
 
 // Backward substitution U du = z in place (z -> du), one workgroup per macro,
 // blocks of 64 rows from the bottom.
 template <class T>
-__global__ void __launch_bounds__(256) k_bs_trsv(ClassDev cd, const T* __restrict__ Wm, long long mstride, int ld,
-                                                 double* __restrict__ du) {
+__global__ void __launch_bounds__(256) k_bs_trsv(MeshDev md, const T* __restrict__ Wm, double* __restrict__ du) {
   __shared__ double sU[BS_ROWS][BS_ROWS + 1];
   __shared__ double sz[BS_ROWS];
   const int macro = blockIdx.x;
-  const int nu = cd.n_u;
-  const T* U = Wm + (size_t)macro * mstride;
-  double* x = du + (size_t)macro * nu;
+  const ClassDev& cd = class_of(md, macro);
+  const int nu = cd.n_u, ld = cd.ldw;
+  const T* U = Wm + md.w_off[macro];
+  double* x = du + md.u_off[macro];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nblk = (nu + BS_ROWS - 1) / BS_ROWS;
   for (int b = nblk - 1; b >= 0; --b) {
@@ -91,16 +94,18 @@ __global__ void __launch_bounds__(256) k_bs_trsv(ClassDev cd, const T* __restric
 }
 
 // dQ for one (macro, direction k, component c) field.
-__global__ void k_bs_dq(ClassDev cd, MeshDev md, const double* __restrict__ RQt, const double* __restrict__ du,
+__global__ void k_bs_dq(MeshDev md, const double* __restrict__ RQt, const double* __restrict__ du,
                         const double* __restrict__ duhat, double* __restrict__ dq) {
-  const int ns = cd.ns, d = cd.dim, N = cd.N, nm = cd.nmax1;
+  const int ns = md.ns, d = md.dim;
   const int macro = blockIdx.x / (d * ns), f = blockIdx.x % (d * ns);
+  const ClassDev& cd = class_of(md, macro);
+  const int N = cd.N, nm = cd.nmax1;
   const int k = f / ns, c = f % ns;
   const int nk = cd.n1[k];
   const int stride = (k == 0) ? 1 : (k == 1 ? cd.n1[0] : cd.n1[0] * cd.n1[1]);
   const double* Ck = cd.C1D + (size_t)k * nm * nm;
   const double* Mk = cd.Minv1D + (size_t)k * nm * nm;
-  const double* u = du + (size_t)macro * cd.n_u + (size_t)c * N;
+  const double* u = du + md.u_off[macro] + (size_t)c * N;
   const int Fm = md.macro_face[(size_t)macro * 2 * d + 2 * k];
   const int Fp = md.macro_face[(size_t)macro * 2 * d + 2 * k + 1];
   const int nf = cd.nf_nodes[2 * k];
@@ -121,7 +126,7 @@ __global__ void k_bs_dq(ClassDev cd, MeshDev md, const double* __restrict__ RQt,
     const double hm = duhat[md.face_off[Fm] + (size_t)c * nf + jt];
     const double hp = duhat[md.face_off[Fp] + (size_t)c * nf + jt];
     const double face = -Mk[ik * nm + 0] * hm + Mk[ik * nm + nk - 1] * hp;
-    const size_t o = (size_t)macro * cd.n_q + (size_t)(k * ns + c) * N + i;
+    const size_t o = (size_t)d * md.u_off[macro] + (size_t)(k * ns + c) * N + i;
     dq[o] = -RQt[o] - s + face;
   }
 }
@@ -129,19 +134,19 @@ __global__ void k_bs_dq(ClassDev cd, MeshDev md, const double* __restrict__ RQt,
 }  // namespace
 
 hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, double* du) {
-  const int nu = c.hc.n_u, nb = c.hc.n_b, nm = c.hm.n_macros;
-  const long long ms = c.wstride;
+  int nu = 0, nb = 0;
+  for (const HostClass& k : c.hcs) { nu = std::max(nu, k.n_u); nb = std::max(nb, k.n_b); }
+  const int nm = c.hm.n_macros;
   const dim3 grid_rhs((nu + BS_ROWS - 1) / BS_ROWS, nm);
   if (c.cond_prec == 1) {
     const float* W32 = reinterpret_cast<const float*>(c.ws.Wm);
-    hipLaunchKernelGGL(k_bs_rhs<float>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.cd, c.md, W32, ms,
-                       c.ldw, c.n_cols, duhat, du);
-    hipLaunchKernelGGL(k_bs_trsv<float>, dim3(nm), dim3(256), 0, c.stream, c.cd, W32, ms, c.ldw, du);
+    hipLaunchKernelGGL(k_bs_rhs<float>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, W32, duhat, du);
+    hipLaunchKernelGGL(k_bs_trsv<float>, dim3(nm), dim3(256), 0, c.stream, c.md, W32, du);
   } else {
-    hipLaunchKernelGGL(k_bs_rhs<double>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.cd, c.md, c.ws.Wm,
-                       ms, c.ldw, c.n_cols, duhat, du);
-    hipLaunchKernelGGL(k_bs_trsv<double>, dim3(nm), dim3(256), 0, c.stream, c.cd, c.ws.Wm, ms, c.ldw, du);
+    hipLaunchKernelGGL(k_bs_rhs<double>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, c.ws.Wm, duhat,
+                       du);
+    hipLaunchKernelGGL(k_bs_trsv<double>, dim3(nm), dim3(256), 0, c.stream, c.md, c.ws.Wm, du);
   }
-  hipLaunchKernelGGL(k_bs_dq, dim3(nm * c.cd.dim * c.cd.ns), dim3(256), 0, c.stream, c.cd, c.md, c.ws.RQt, du, duhat, dq);
+  hipLaunchKernelGGL(k_bs_dq, dim3(nm * c.cd.dim * c.cd.ns), dim3(256), 0, c.stream, c.md, c.ws.RQt, du, duhat, dq);
   return hipGetLastError();
 }

@@ -27,8 +27,7 @@ constexpr int FORM_THREADS = 256;
 struct FormPtrs {
   const double *AUU, *AUQ, *SUB, *RU, *RQt, *RBloc;
   double* gloc;  // non-null: g goes here in FP64 and its W entries are 0
-  int nsA, dnsA, sub_stride, off_AUB, off_ABU, off_ABQ, off_ABB, ldw, n_cols;
-  long long mstride;  // elements per macro matrix (tiled, rows padded to 16)
+  int nsA, dnsA, sub_stride, off_AUB, off_ABU, off_ABQ, off_ABB;
 };
 
 __device__ __forceinline__ void digits(int x, int base, int d, int* out) {
@@ -104,19 +103,23 @@ __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, doubl
 }
 
 // The row is accumulated in FP64 and stored as TW (double or float).
+// One workgroup per row of all macros' augmented matrices (row offsets
+// MeshDev::row_off; each macro takes the layout of its class).
 template <class TW>
-__global__ void __launch_bounds__(FORM_THREADS) k_form(ClassDev cd, MeshDev md, FormPtrs fp, TW* __restrict__ Wm) {
+__global__ void __launch_bounds__(FORM_THREADS) k_form(MeshDev md, FormPtrs fp, TW* __restrict__ Wm) {
   extern __shared__ double row[];
   __shared__ double red[FORM_THREADS];
   const int tid = threadIdx.x;
-  const int n_rows = cd.n_u + cd.n_b;
   const long long gr = blockIdx.x;
-  const int macro = (int)(gr / n_rows), r = (int)(gr % n_rows);
+  const int macro = find_in(md.row_off, md.n_macros, gr);
+  const int r = (int)(gr - md.row_off[macro]);
+  const ClassDev& cd = class_of(md, macro);
   const int ns = cd.ns, d = cd.dim, A = cd.A, T = cd.T, N = cd.N;
   const int nsA = fp.nsA, dnsA = fp.dnsA;
-  for (int i = tid; i < fp.n_cols; i += FORM_THREADS) row[i] = 0.0;
+  const int n_cols = cd.n_cols;
+  for (int i = tid; i < n_cols; i += FORM_THREADS) row[i] = 0.0;
   __syncthreads();
-  const double* RQt = fp.RQt + (size_t)macro * cd.n_q;
+  const double* RQt = fp.RQt + (size_t)d * md.u_off[macro];
   double fpart = 0.0;
   if (r < cd.n_u) {
     // ---- u-row (c, a) ----
@@ -124,7 +127,7 @@ __global__ void __launch_bounds__(FORM_THREADS) k_form(ClassDev cd, MeshDev md, 
     const int cnt = cd.node_ne[a];
     for (int ie = 0; ie < cnt; ++ie) {
       const int e = cd.node_e[a * 8 + ie], ae = cd.node_a[a * 8 + ie];
-      const long long el = (long long)macro * cd.E + e;
+      const long long el = md.el_off[macro] + e;
       const double* auu = fp.AUU + ((size_t)el * nsA + (size_t)(c * A + ae)) * nsA;
       const double* auq = fp.AUQ + ((size_t)el * nsA + (size_t)(c * A + ae)) * dnsA;
       const int* en = cd.elem_nodes + (size_t)e * A;
@@ -147,7 +150,7 @@ __global__ void __launch_bounds__(FORM_THREADS) k_form(ClassDev cd, MeshDev md, 
         const int ta = cd.finv[(size_t)lf * A + ae];
         if (ta < 0) continue;
         __syncthreads();
-        const double* aub = fp.SUB + ((size_t)macro * cd.n_sub + sid) * fp.sub_stride + fp.off_AUB;
+        const double* aub = fp.SUB + ((size_t)md.sub_off[macro] + sid) * fp.sub_stride + fp.off_AUB;
         const int nst = ns * T;
         const int nf = cd.nf_nodes[lf];
         for (int i = tid; i < nst; i += FORM_THREADS) {
@@ -162,7 +165,7 @@ __global__ void __launch_bounds__(FORM_THREADS) k_form(ClassDev cd, MeshDev md, 
       if (tid < w) red[tid] += red[tid + w];
       __syncthreads();
     }
-    if (tid == 0) row[fp.n_cols - 1] = red[0] - fp.RU[(size_t)macro * cd.n_u + r];
+    if (tid == 0) row[n_cols - 1] = red[0] - fp.RU[md.u_off[macro] + r];
   } else {
     // ---- trace row (lf, c, j) ----
     const int rho = r - cd.n_u;
@@ -175,7 +178,7 @@ __global__ void __launch_bounds__(FORM_THREADS) k_form(ClassDev cd, MeshDev md, 
     for (int is = 0; is < cd.tn_cnt[tj]; ++is) {
       const int sid = cd.tn_sub[tj * 4 + is], t = cd.tn_t[tj * 4 + is];
       const int e = cd.sub_elem[sid];
-      const double* SB = fp.SUB + ((size_t)macro * cd.n_sub + sid) * fp.sub_stride;
+      const double* SB = fp.SUB + ((size_t)md.sub_off[macro] + sid) * fp.sub_stride;
       const double* abu = SB + fp.off_ABU + (size_t)(c * T + t) * nst;
       const double* abb = SB + fp.off_ABB + (size_t)(c * T + t) * nst;
       const double* abq = SB + fp.off_ABQ + (size_t)(c * T + t) * (d * nst);
@@ -208,18 +211,18 @@ __global__ void __launch_bounds__(FORM_THREADS) k_form(ClassDev cd, MeshDev md, 
       __syncthreads();
     }
     if (tid == 0) {
-      const double g = red[0] - fp.RBloc[(size_t)macro * cd.n_b + rho];
+      const double g = red[0] - fp.RBloc[md.b_off[macro] + rho];
       if (fp.gloc) {
-        fp.gloc[(size_t)macro * cd.n_b + rho] = g;
-        row[fp.n_cols - 1] = 0.0;
+        fp.gloc[md.b_off[macro] + rho] = g;
+        row[n_cols - 1] = 0.0;
       } else {
-        row[fp.n_cols - 1] = g;
+        row[n_cols - 1] = g;
       }
     }
   }
   __syncthreads();
-  TW* Wmac = Wm + (size_t)macro * fp.mstride;
-  for (int i = tid; i < fp.ldw; i += FORM_THREADS) Wmac[wtix(r, i, fp.ldw)] = (i < fp.n_cols) ? (TW)row[i] : TW(0);
+  TW* Wmac = Wm + md.w_off[macro];
+  for (int i = tid; i < cd.ldw; i += FORM_THREADS) Wmac[wtix(r, i, cd.ldw)] = (i < n_cols) ? (TW)row[i] : TW(0);
 }
 
 }  // namespace
@@ -228,13 +231,13 @@ hipError_t launch_form(HdgContext& c, int prec) {
   // FP32 storage: g of the trace rows stays in FP64 (it is O(1) per macro but
   // cancels between the two sides of a face in the assembled b-hat)
   FormPtrs fp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.ws.RQt, c.ws.RBloc, prec == 1 ? c.ws.gloc : nullptr,
-              c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.ldw, c.n_cols, c.wstride};
-  const long long nblk = (long long)c.hm.n_macros * c.n_rows;
-  const size_t shm = (size_t)c.n_cols * sizeof(double);
+              c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB};
+  const long long nblk = c.hm.row_off[c.hm.n_macros];
+  const size_t shm = (size_t)c.n_cols * sizeof(double);  // largest class
   if (prec == 1)
-    hipLaunchKernelGGL(k_form<float>, dim3((unsigned)nblk), dim3(FORM_THREADS), shm, c.stream, c.cd, c.md, fp,
+    hipLaunchKernelGGL(k_form<float>, dim3((unsigned)nblk), dim3(FORM_THREADS), shm, c.stream, c.md, fp,
                        reinterpret_cast<float*>(c.ws.Wm));
   else
-    hipLaunchKernelGGL(k_form<double>, dim3((unsigned)nblk), dim3(FORM_THREADS), shm, c.stream, c.cd, c.md, fp, c.ws.Wm);
+    hipLaunchKernelGGL(k_form<double>, dim3((unsigned)nblk), dim3(FORM_THREADS), shm, c.stream, c.md, fp, c.ws.Wm);
   return hipGetLastError();
 }

@@ -24,22 +24,17 @@ __device__ __forceinline__ int local_face(const ClassDev& cd, int r) {
   return lf;
 }
 
-// out[g] = sum over the (one or two) sides of face F(g) of src(side macro, local index)
-// elem_stride < 0 selects the tiled macro matrices: element r of a macro is
-// entry (row0 + r, col) of its tiled matrix with leading dimension -elem_stride,
-// where row0 and col are packed in `tiled_rc` (row0 * 2^32 + col).
+// out[g] = sum over the (one or two) sides of face F(g) of src(side macro, local index):
+//   tiled == 0: src = base[b_off[macro] + index] (per-macro trace vectors),
+//   tiled == 1: src = entry (n_u + index, n_cols - 1) of the macro's tiled matrix
+//               (b-hat^{T_i} in the last column of the eliminated W).
 // accumulate != 0 adds to out instead of overwriting it.
 template <class TB>
-__global__ void k_face_gather_sum(ClassDev cd, MeshDev md, const TB* __restrict__ base, long long macro_stride,
-                                  long long elem_stride, double* __restrict__ out, long long tiled_rc, int accumulate) {
-  const int d = cd.dim;
+__global__ void k_face_gather_sum(MeshDev md, const TB* __restrict__ base, int tiled, double* __restrict__ out,
+                                  int accumulate) {
+  const int d = md.dim;
   for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < md.n_glob; g += (long long)gridDim.x * blockDim.x) {
-    int lo = 0, hi = md.n_faces - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) / 2;
-      if (md.face_off[mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    const int F = lo;
+    const int F = find_in(md.face_off, md.n_faces, g);
     const int r = (int)(g - md.face_off[F]);
     const int mm = md.face_minus[F], mp = md.face_plus[F];
     int k = 0;
@@ -47,28 +42,32 @@ __global__ void k_face_gather_sum(ClassDev cd, MeshDev md, const TB* __restrict_
     for (int lf = 0; lf < 2 * d; ++lf)
       if (md.macro_face[(size_t)m0 * 2 * d + lf] == F) { k = lf / 2; break; }
     double s = 0.0;
-    auto at = [&](int macro, int idx) -> double {
-      if (elem_stride >= 0) return (double)base[(size_t)macro * macro_stride + (size_t)idx * elem_stride];
-      const long long row0 = tiled_rc >> 32, col = tiled_rc & 0xffffffffLL;
-      return (double)base[(size_t)macro * macro_stride + wtix(row0 + idx, col, -elem_stride)];
+    auto at = [&](int macro, int lf) -> double {
+      const ClassDev& cd = class_of(md, macro);
+      const int idx = cd.nf_off[lf] + r;
+      if (!tiled) return (double)base[md.b_off[macro] + idx];
+      return (double)base[md.w_off[macro] + wtix(cd.n_u + idx, cd.n_cols - 1, cd.ldw)];
     };
-    if (mm >= 0) s += at(mm, cd.nf_off[2 * k + 1] + r);
-    if (mp >= 0) s += at(mp, cd.nf_off[2 * k] + r);
+    if (mm >= 0) s += at(mm, 2 * k + 1);
+    if (mp >= 0) s += at(mp, 2 * k);
     out[g] = accumulate ? out[g] + s : s;
   }
 }
 
 constexpr int APPLY_ROWS = 64;
 
-// TILED: Ab is the tiled augmented matrix, A-hat at offset (off, off) with
-// leading dimension ld; otherwise a compact row-major n_b x n_b block.
+// ypart[b_off[macro] + r] = (A-hat^{T_i} x_i)_r.  TILED: A-hat inside the
+// macro's tiled augmented matrix at (n_u, n_u); otherwise the compact
+// row-major copy at a32_off[macro].  blockIdx.x covers 64 rows (the grid is
+// sized for the largest class; rows beyond the macro's n_b do nothing).
 template <class TA, bool TILED>
-__global__ void __launch_bounds__(256) k_apply_local(ClassDev cd, MeshDev md, const TA* __restrict__ Ab,
-                                                     long long macro_stride, long long ld, const double* __restrict__ x,
-                                                     double* __restrict__ ypart, int off) {
+__global__ void __launch_bounds__(256) k_apply_local(MeshDev md, const TA* __restrict__ Ab, const double* __restrict__ x,
+                                                     double* __restrict__ ypart) {
   extern __shared__ double xs[];
   const int macro = blockIdx.y;
+  const ClassDev& cd = class_of(md, macro);
   const int nb = cd.n_b;
+  if (blockIdx.x * APPLY_ROWS >= nb) return;
   const int d = cd.dim;
   for (int s = threadIdx.x; s < nb; s += blockDim.x) {
     const int lf = local_face(cd, s);
@@ -78,7 +77,9 @@ __global__ void __launch_bounds__(256) k_apply_local(ClassDev cd, MeshDev md, co
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r0 = blockIdx.x * APPLY_ROWS + wave * (APPLY_ROWS / 4);
-  const TA* Am = Ab + (size_t)macro * macro_stride;
+  const TA* Am = Ab + (TILED ? md.w_off[macro] : md.a32_off[macro]);
+  const long long ld = TILED ? cd.ldw : nb;
+  const int off = TILED ? cd.n_u : 0;
   for (int rr = 0; rr < APPLY_ROWS / 4; rr += 4) {
     const int r = r0 + rr;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -107,7 +108,7 @@ __global__ void __launch_bounds__(256) k_apply_local(ClassDev cd, MeshDev md, co
     }
     a0 = wave_sum(a0); a1 = wave_sum(a1); a2 = wave_sum(a2); a3 = wave_sum(a3);
     if (lane == 0) {
-      double* yp = ypart + (size_t)macro * nb;
+      double* yp = ypart + md.b_off[macro];
       if (r + 0 < nb) yp[r + 0] = a0;
       if (r + 1 < nb) yp[r + 1] = a1;
       if (r + 2 < nb) yp[r + 2] = a2;
@@ -118,12 +119,11 @@ __global__ void __launch_bounds__(256) k_apply_local(ClassDev cd, MeshDev md, co
 
 // FW[F] = [[A_F, -I], [I, 0]] with A_F the face block of A_uh,uh summed over
 // both macro sides (sub-face blocks scattered to face trace nodes).
-__global__ void k_face_build(ClassDev cd, MeshDev md, const double* __restrict__ SUB, int sub_stride, int off_ABB,
+__global__ void k_face_build(MeshDev md, const double* __restrict__ SUB, int sub_stride, int off_ABB,
                              double* __restrict__ FW, long long face_stride, int ldf) {
   const int F = blockIdx.x;
   const int nf = md.face_ndof[F];
-  const int nn = nf / cd.ns;
-  const int T = cd.T, ns = cd.ns, nst = ns * T;
+  const int nn = nf / md.ns;
   double* M = FW + (size_t)F * face_stride;
   for (int i = threadIdx.x; i < 2 * nf * ldf; i += blockDim.x) {
     const int r = i / ldf, c = i % ldf;
@@ -133,17 +133,19 @@ __global__ void k_face_build(ClassDev cd, MeshDev md, const double* __restrict__
     M[wtix(r, c, ldf)] = v;
   }
   __syncthreads();
-  const int d = cd.dim;
+  const int d = md.dim;
   for (int side = 0; side < 2; ++side) {
     const int macro = side == 0 ? md.face_minus[F] : md.face_plus[F];
     if (macro < 0) continue;
+    const ClassDev& cd = class_of(md, macro);
+    const int T = cd.T, ns = cd.ns, nst = ns * T;
     int lf = -1;
     for (int l = 0; l < 2 * d; ++l)
       if (md.macro_face[(size_t)macro * 2 * d + l] == F && (l % 2) == (side == 0 ? 1 : 0)) { lf = l; break; }
     if (lf < 0) continue;
     for (int sid = 0; sid < cd.n_sub; ++sid) {
       if (cd.sub_lf[sid] != lf) continue;
-      const double* abb = SUB + ((size_t)macro * cd.n_sub + sid) * sub_stride + off_ABB;
+      const double* abb = SUB + ((size_t)md.sub_off[macro] + sid) * sub_stride + off_ABB;
       const int* tid = cd.sub_tid + (size_t)sid * T;
       __syncthreads();
       for (int i = threadIdx.x; i < nst * nst; i += blockDim.x) {
@@ -173,14 +175,15 @@ __global__ void __launch_bounds__(256) k_precond_apply(MeshDev md, const double*
   }
 }
 
-// A32[macro][r][c] = (float) A-hat^{T_i}[r][c]
-__global__ void k_cast_ahat(const double* __restrict__ W, long long macro_stride, long long ld, long long offs, int nb,
-                            float* __restrict__ out, long long total) {
+// A32[a32_off[macro] + r n_b + c] = (float) A-hat^{T_i}[r][c]
+__global__ void k_cast_ahat(MeshDev md, const double* __restrict__ W, float* __restrict__ out) {
+  const long long total = md.a32_off[md.n_macros];
   for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total; g += (long long)gridDim.x * blockDim.x) {
-    const long long macro = g / ((long long)nb * nb);
-    const long long rc = g % ((long long)nb * nb);
-    const int r = (int)(rc / nb), c = (int)(rc % nb);
-    out[g] = (float)W[macro * macro_stride + wtix(offs + r, offs + c, ld)];
+    const int macro = find_in(md.a32_off, md.n_macros, g);
+    const ClassDev& cd = class_of(md, macro);
+    const long long rc = g - md.a32_off[macro];
+    const int r = (int)(rc / cd.n_b), c = (int)(rc % cd.n_b);
+    out[g] = (float)W[md.w_off[macro] + wtix(cd.n_u + r, cd.n_u + c, cd.ldw)];
   }
 }
 
@@ -328,10 +331,11 @@ inline unsigned grid_for(long long n) { return (unsigned)std::max<long long>(1, 
 
 }  // namespace
 
-hipError_t launch_face_sum(HdgContext& c, const double* base, long long macro_stride, long long elem_stride, double* out,
-                           long long tiled_rc) {
-  hipLaunchKernelGGL(k_face_gather_sum<double>, dim3(grid_for(c.md.n_glob)), dim3(256), 0, c.stream, c.cd, c.md, base,
-                     macro_stride, elem_stride, out, tiled_rc, 0);
+// out = sum over the sides of every face of the per-macro trace vector `base`
+// (offsets b_off)
+hipError_t launch_face_sum(HdgContext& c, const double* base, double* out) {
+  hipLaunchKernelGGL(k_face_gather_sum<double>, dim3(grid_for(c.md.n_glob)), dim3(256), 0, c.stream, c.md, base, 0, out,
+                     0);
   return hipGetLastError();
 }
 
@@ -342,33 +346,33 @@ hipError_t launch_zero_ints(hipStream_t s, int* p, int n) {
 
 hipError_t launch_bhat(HdgContext& c, double* bhat, int prec) {
   // b-hat^{T_i}: column n_cols - 1 of rows [n_u, n_u + n_b) of each tiled matrix
-  const long long rc = ((long long)c.hc.n_u << 32) | (long long)(c.n_cols - 1);
   if (prec == 1) {
     // FP64 g first, then the FP32 correction -D S^{-1} f on top
-    hipError_t e = launch_face_sum(c, c.ws.gloc, c.hc.n_b, 1, bhat, 0);
+    hipError_t e = launch_face_sum(c, c.ws.gloc, bhat);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_face_gather_sum<float>, dim3(grid_for(c.md.n_glob)), dim3(256), 0, c.stream, c.cd, c.md,
-                       reinterpret_cast<const float*>(c.ws.Wm), c.wstride, -(long long)c.ldw, bhat, rc, 1);
+    hipLaunchKernelGGL(k_face_gather_sum<float>, dim3(grid_for(c.md.n_glob)), dim3(256), 0, c.stream, c.md,
+                       reinterpret_cast<const float*>(c.ws.Wm), 1, bhat, 1);
     return hipGetLastError();
   }
-  return launch_face_sum(c, c.ws.Wm, c.wstride, -(long long)c.ldw, bhat, rc);
+  hipLaunchKernelGGL(k_face_gather_sum<double>, dim3(grid_for(c.md.n_glob)), dim3(256), 0, c.stream, c.md, c.ws.Wm, 1,
+                     bhat, 0);
+  return hipGetLastError();
 }
 
 hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec) {
-  const int nb = c.hc.n_b;
+  int nb = 0;
+  for (const HostClass& k : c.hcs) nb = std::max(nb, k.n_b);
   dim3 grid((nb + APPLY_ROWS - 1) / APPLY_ROWS, c.hm.n_macros);
   const size_t shm = (size_t)nb * sizeof(double);
   if (c.cond_prec == 1) {  // FP32 condensation: the operator itself is FP32
-    hipLaunchKernelGGL((k_apply_local<float, true>), grid, dim3(256), shm, c.stream, c.cd, c.md,
-                       reinterpret_cast<const float*>(c.ws.Wm), c.wstride, (long long)c.ldw, x, c.ws.ypart, c.hc.n_u);
+    hipLaunchKernelGGL((k_apply_local<float, true>), grid, dim3(256), shm, c.stream, c.md,
+                       reinterpret_cast<const float*>(c.ws.Wm), x, c.ws.ypart);
   } else if (prec == 1 && c.have_a32) {
-    hipLaunchKernelGGL((k_apply_local<float, false>), grid, dim3(256), shm, c.stream, c.cd, c.md, c.ws.A32,
-                       (long long)nb * nb, (long long)nb, x, c.ws.ypart, 0);
+    hipLaunchKernelGGL((k_apply_local<float, false>), grid, dim3(256), shm, c.stream, c.md, c.ws.A32, x, c.ws.ypart);
   } else {
-    hipLaunchKernelGGL((k_apply_local<double, true>), grid, dim3(256), shm, c.stream, c.cd, c.md, c.ws.Wm,
-                       c.wstride, (long long)c.ldw, x, c.ws.ypart, c.hc.n_u);
+    hipLaunchKernelGGL((k_apply_local<double, true>), grid, dim3(256), shm, c.stream, c.md, c.ws.Wm, x, c.ws.ypart);
   }
-  return launch_face_sum(c, c.ws.ypart, nb, 1, y, 0);
+  return launch_face_sum(c, c.ws.ypart, y);
 }
 
 template <class T>
@@ -377,7 +381,7 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
 
 hipError_t launch_face_precond(HdgContext& c) {
   const long long fs = c.fstride;
-  hipLaunchKernelGGL(k_face_build, dim3(c.hm.n_faces), dim3(256), 0, c.stream, c.cd, c.md, c.ws.SUB, c.sub_stride,
+  hipLaunchKernelGGL(k_face_build, dim3(c.hm.n_faces), dim3(256), 0, c.stream, c.md, c.ws.SUB, c.sub_stride,
                      c.off_ABB, c.ws.FW, fs, c.ldf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -389,7 +393,7 @@ hipError_t launch_face_precond(HdgContext& c) {
   if (sizes.size() == 1) {
     const int nf = sizes[0];
     return lu_eliminate<double>(c.stream, c.ws.FW, c.hm.n_faces, fs, c.ldf, nf, 2 * nf, 2 * nf, c.ws.fpiv, c.nf_max,
-                        reinterpret_cast<int*>(c.ws.small) + 1, c.ws.Uinv);
+                        reinterpret_cast<int*>(c.ws.small) + c.hm.n_classes, c.ws.Uinv);
   }
   // several face sizes: runs of consecutive faces with the same size
   int f0 = 0;
@@ -398,7 +402,8 @@ hipError_t launch_face_precond(HdgContext& c) {
     while (f1 < c.hm.n_faces && c.hm.face_ndof[f1] == c.hm.face_ndof[f0]) ++f1;
     const int nf = c.hm.face_ndof[f0];
     e = lu_eliminate<double>(c.stream, c.ws.FW + (size_t)f0 * fs, f1 - f0, fs, c.ldf, nf, 2 * nf, 2 * nf,
-                     c.ws.fpiv + (size_t)f0 * c.nf_max, c.nf_max, reinterpret_cast<int*>(c.ws.small) + 1, c.ws.Uinv);
+                     c.ws.fpiv + (size_t)f0 * c.nf_max, c.nf_max, reinterpret_cast<int*>(c.ws.small) + c.hm.n_classes,
+                     c.ws.Uinv);
     if (e != hipSuccess) return e;
     f0 = f1;
   }
@@ -413,10 +418,8 @@ hipError_t launch_precond_apply(HdgContext& c, const double* x, double* y) {
 }
 
 hipError_t launch_cast_ahat(HdgContext& c) {
-  const int nb = c.hc.n_b;
-  const long long total = (long long)c.hm.n_macros * nb * nb;
-  hipLaunchKernelGGL(k_cast_ahat, dim3(grid_for(total)), dim3(256), 0, c.stream, c.ws.Wm, c.wstride,
-                     (long long)c.ldw, (long long)c.hc.n_u, nb, c.ws.A32, total);
+  const long long total = c.hm.a32_off[c.hm.n_macros];
+  hipLaunchKernelGGL(k_cast_ahat, dim3(grid_for(total)), dim3(256), 0, c.stream, c.md, c.ws.Wm, c.ws.A32);
   return hipGetLastError();
 }
 

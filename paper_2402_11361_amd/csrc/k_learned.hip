@@ -161,8 +161,9 @@ __global__ void k_to_bf16(long long n, const float* __restrict__ p, unsigned sho
 }
 
 // Per macro: X[macro][(lf ns + c) cq + a] = sum_j cR[k][a][j] v[face(lf)][c][j].
-__global__ void k_coarse_restrict(ClassDev cd, MeshDev md, const double* __restrict__ v, float* __restrict__ X) {
+__global__ void k_coarse_restrict(MeshDev md, const double* __restrict__ v, float* __restrict__ X) {
   const int macro = blockIdx.x;
+  const ClassDev& cd = class_of(md, macro);
   const int d = cd.dim, ns = cd.ns, cq = cd.cq;
   for (int f = threadIdx.x; f < cd.cF; f += blockDim.x) {
     const int lf = f / (ns * cq), c = (f / cq) % ns, a = f % cq;
@@ -178,9 +179,8 @@ __global__ void k_coarse_restrict(ClassDev cd, MeshDev md, const double* __restr
 }
 
 // z[g] += alpha * mean over the owning macros of sum_a cPhi[k][j][a] Y[macro][(lf ns + c) cq + a]
-__global__ void k_coarse_prolong(ClassDev cd, MeshDev md, const float* __restrict__ Y, double alpha,
-                                 double* __restrict__ z) {
-  const int d = cd.dim, ns = cd.ns, cq = cd.cq;
+__global__ void k_coarse_prolong(MeshDev md, const float* __restrict__ Y, double alpha, double* __restrict__ z) {
+  const int d = md.dim, ns = md.ns;
   for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < md.n_glob;
        g += (long long)gridDim.x * blockDim.x) {
     int lo = 0, hi = md.n_faces - 1;
@@ -195,6 +195,8 @@ __global__ void k_coarse_prolong(ClassDev cd, MeshDev md, const float* __restric
     int k = 0;
     for (int lf = 0; lf < 2 * d; ++lf)
       if (md.macro_face[(size_t)m0 * 2 * d + lf] == F) { k = lf / 2; break; }
+    const ClassDev& cd = class_of(md, m0);  // both sides see the same face grid
+    const int cq = cd.cq;
     const int nn = cd.nf_nodes[2 * k];
     const int c = r / nn, j = r % nn;
     const double* phi = cd.cPhi + ((size_t)k * cd.cmaxf + j) * cq;
@@ -273,12 +275,12 @@ size_t mlp_work_floats(int n_in, int n_hidden, int n_out, int max_batch) {
 }
 
 hipError_t launch_coarse_restrict(HdgContext& c, const double* v, float* X) {
-  hipLaunchKernelGGL(k_coarse_restrict, dim3(c.hm.n_macros), dim3(128), 0, c.stream, c.cd, c.md, v, X);
+  hipLaunchKernelGGL(k_coarse_restrict, dim3(c.hm.n_macros), dim3(128), 0, c.stream, c.md, v, X);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_prolong(HdgContext& c, const float* Y, double alpha, double* z) {
-  hipLaunchKernelGGL(k_coarse_prolong, dim3(grid1(c.md.n_glob)), dim3(256), 0, c.stream, c.cd, c.md, Y, alpha, z);
+  hipLaunchKernelGGL(k_coarse_prolong, dim3(grid1(c.md.n_glob)), dim3(256), 0, c.stream, c.md, Y, alpha, z);
   return hipGetLastError();
 }
 

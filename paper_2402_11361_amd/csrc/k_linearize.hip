@@ -37,15 +37,16 @@ constexpr int KCHUNK = 64;
 
 template <int D, int P>
 __global__ void __launch_bounds__(LIN_THREADS)
-k_lin_elem(ClassDev cd, MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg,
+k_lin_elem(MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg,
            const double* __restrict__ ug, const double* __restrict__ uhg, const double* __restrict__ wg, LinPtrs lp) {
   using S_ = Sz<D, P>;
   constexpr int NS = S_::NS, A = S_::A, Q = S_::Q, T = S_::T, FQ = S_::FQ;
   constexpr int NSA = S_::NSA, DNSA = S_::DNSA, KC = S_::KC, NST = S_::NST;
   const int tid = threadIdx.x;
   const long long el = blockIdx.x;
-  const int E = cd.E;
-  const int macro = (int)(el / E), e = (int)(el % E);
+  const int macro = md.elem_macro[el];
+  const int e = (int)(el - md.el_off[macro]);
+  const ClassDev& cd = class_of(md, macro);
   const bool steady = !(sa.dt < 1e300);
   const double tcoef = steady ? 0.0 : sa.dii / sa.dt;
   const double ptc = (sa.dtau < 1e300) ? 1.0 / sa.dtau : 0.0;
@@ -60,12 +61,12 @@ k_lin_elem(ClassDev cd, MeshDev md, PhysDev ph, StageArgs sa, const double* __re
   const int* en = cd.elem_nodes + (size_t)e * A;
   for (int i = tid; i < A; i += LIN_THREADS) s_nodes[i] = en[i];
   __syncthreads();
-  const double* um = ug + (size_t)macro * cd.n_u;
-  const double* qm = qg + (size_t)macro * cd.n_q;
+  const double* um = ug + md.u_off[macro];
+  const double* qm = qg + (size_t)D * md.u_off[macro];
   for (int i = tid; i < NS * A; i += LIN_THREADS) {
     int c = i / A, a = i % A;
     s_u[i] = um[(size_t)c * cd.N + s_nodes[a]];
-    s_w[i] = wg ? wg[(size_t)macro * cd.n_u + (size_t)c * cd.N + s_nodes[a]] : 0.0;
+    s_w[i] = wg ? wg[md.u_off[macro] + (size_t)c * cd.N + s_nodes[a]] : 0.0;
   }
   for (int i = tid; i < D * NS * A; i += LIN_THREADS) {
     int lc = i / A, a = i % A;
@@ -292,7 +293,7 @@ k_lin_elem(ClassDev cd, MeshDev md, PhysDev ph, StageArgs sa, const double* __re
         }
     }
     __syncthreads();
-    double* SB = lp.SUB + ((size_t)macro * cd.n_sub + sid) * lp.sub_stride;
+    double* SB = lp.SUB + ((size_t)md.sub_off[macro] + sid) * lp.sub_stride;
     // residual rows
     for (int i = tid; i < NS * T; i += LIN_THREADS) {
       int c = i / T, t = i % T;
@@ -358,42 +359,54 @@ k_lin_elem(ClassDev cd, MeshDev md, PhysDev ph, StageArgs sa, const double* __re
 
 // R_U and R_Q node values: sum of the element contributions of the elements
 // containing the node, in a fixed order.
-__global__ void k_gather_res(ClassDev cd, int NSA, int DNSA, const double* __restrict__ RUe,
+// Grid over the nodes of all macros (node offsets u_off / n_s).
+__global__ void k_gather_res(MeshDev md, int NSA, int DNSA, const double* __restrict__ RUe,
                              const double* __restrict__ RQe, double* __restrict__ RU, double* __restrict__ RQ,
-                             int n_macros) {
-  const int ns = cd.ns, d = cd.dim, N = cd.N, A = cd.A;
-  const long long total = (long long)n_macros * N;
-  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total; g += (long long)gridDim.x * blockDim.x) {
-    const int macro = (int)(g / N), n = (int)(g % N);
+                             long long total_nodes) {
+  const int ns = md.ns, d = md.dim;
+  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total_nodes;
+       g += (long long)gridDim.x * blockDim.x) {
+    // macro of node g: largest i with u_off[i] / ns <= g
+    int lo = 0, hi = md.n_macros - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (md.u_off[mid] / ns <= g) lo = mid; else hi = mid - 1;
+    }
+    const int macro = lo;
+    const ClassDev& cd = class_of(md, macro);
+    const int N = cd.N, A = cd.A;
+    const int n = (int)(g - md.u_off[macro] / ns);
     const int cnt = cd.node_ne[n];
+    const long long e0 = md.el_off[macro];
     for (int c = 0; c < ns; ++c) {
       double s = 0.0;
       for (int i = 0; i < cnt; ++i) {
-        const long long el = (long long)macro * cd.E + cd.node_e[n * 8 + i];
+        const long long el = e0 + cd.node_e[n * 8 + i];
         s += RUe[el * NSA + c * A + cd.node_a[n * 8 + i]];
       }
-      RU[(size_t)macro * cd.n_u + (size_t)c * N + n] = s;
+      RU[md.u_off[macro] + (size_t)c * N + n] = s;
     }
     for (int kc = 0; kc < d * ns; ++kc) {
       double s = 0.0;
       for (int i = 0; i < cnt; ++i) {
-        const long long el = (long long)macro * cd.E + cd.node_e[n * 8 + i];
+        const long long el = e0 + cd.node_e[n * 8 + i];
         s += RQe[el * DNSA + kc * A + cd.node_a[n * 8 + i]];
       }
-      RQ[(size_t)macro * cd.n_q + (size_t)kc * N + n] = s;
+      RQ[(size_t)d * md.u_off[macro] + (size_t)kc * N + n] = s;
     }
   }
 }
 
 // Per-macro trace residual R_Uhat^(i): sum over the sub-faces containing each
 // trace node.
-__global__ void k_gather_rb(ClassDev cd, MeshDev md, const double* __restrict__ SUB, int sub_stride, int off_RB,
+__global__ void k_gather_rb(MeshDev md, const double* __restrict__ SUB, int sub_stride, int off_RB,
                             double* __restrict__ RBloc) {
-  const int ns = cd.ns, T = cd.T;
-  const long long total = (long long)md.n_macros * cd.n_b;
+  const long long total = md.b_off[md.n_macros];
   for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total; g += (long long)gridDim.x * blockDim.x) {
-    const int macro = (int)(g / cd.n_b);
-    int r = (int)(g % cd.n_b);
+    const int macro = find_in(md.b_off, md.n_macros, g);
+    const ClassDev& cd = class_of(md, macro);
+    const int T = cd.T;
+    int r = (int)(g - md.b_off[macro]);
     int lf = 0;
     while (lf + 1 < 2 * cd.dim && r >= cd.nf_off[lf + 1]) ++lf;
     const int nf = cd.nf_nodes[lf];
@@ -403,15 +416,15 @@ __global__ void k_gather_rb(ClassDev cd, MeshDev md, const double* __restrict__ 
     double s = 0.0;
     for (int i = 0; i < cd.tn_cnt[tj]; ++i) {
       const int sid = cd.tn_sub[tj * 4 + i], t = cd.tn_t[tj * 4 + i];
-      s += SUB[((size_t)macro * cd.n_sub + sid) * sub_stride + off_RB + c * T + t];
+      s += SUB[((size_t)md.sub_off[macro] + sid) * sub_stride + off_RB + c * T + t];
     }
     RBloc[g] = s;
   }
 }
 
 // Global R_Uhat: sum of the (one or two) macro sides of every face.
-__global__ void k_face_sum(ClassDev cd, MeshDev md, const double* __restrict__ loc, double* __restrict__ out) {
-  const int d = cd.dim;
+__global__ void k_face_sum(MeshDev md, const double* __restrict__ loc, double* __restrict__ out) {
+  const int d = md.dim;
   for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < md.n_glob; g += (long long)gridDim.x * blockDim.x) {
     // locate face by binary search on face_off
     int lo = 0, hi = md.n_faces - 1;
@@ -430,22 +443,29 @@ __global__ void k_face_sum(ClassDev cd, MeshDev md, const double* __restrict__ l
       for (int lf = 0; lf < 2 * d; ++lf)
         if (md.macro_face[(size_t)m * 2 * d + lf] == F) { k = lf / 2; break; }
     }
-    if (md.face_minus[F] >= 0) s += loc[(size_t)md.face_minus[F] * cd.n_b + cd.nf_off[2 * k + 1] + r];
-    if (md.face_plus[F] >= 0) s += loc[(size_t)md.face_plus[F] * cd.n_b + cd.nf_off[2 * k] + r];
+    if (md.face_minus[F] >= 0) {
+      const int m = md.face_minus[F];
+      s += loc[md.b_off[m] + class_of(md, m).nf_off[2 * k + 1] + r];
+    }
+    if (md.face_plus[F] >= 0) {
+      const int m = md.face_plus[F];
+      s += loc[md.b_off[m] + class_of(md, m).nf_off[2 * k] + r];
+    }
     out[g] = s;
   }
 }
 
 // RQt[k][c] = M^{-1} R_Q[k][c] with M = M_0 (x) M_1 (x) M_2 (tensor-product
 // inverse applied axis by axis).  One workgroup per (macro, field).
-__global__ void k_minv_fields(ClassDev cd, const double* __restrict__ in, double* __restrict__ out, int nfield,
-                              long long stride_macro) {
+__global__ void k_minv_fields(MeshDev md, const double* __restrict__ in, double* __restrict__ out, int nfield) {
   extern __shared__ double sh[];
+  const int macro = blockIdx.x / nfield, fld = blockIdx.x % nfield;
+  const ClassDev& cd = class_of(md, macro);
   const int N = cd.N, nm = cd.nmax1;
   double* a = sh;
   double* b = sh + N;
-  const int macro = blockIdx.x / nfield, fld = blockIdx.x % nfield;
-  const double* src = in + (size_t)macro * stride_macro + (size_t)fld * N;
+  const size_t base = (size_t)md.dim * md.u_off[macro];
+  const double* src = in + base + (size_t)fld * N;
   for (int i = threadIdx.x; i < N; i += blockDim.x) a[i] = src[i];
   __syncthreads();
   for (int k = 0; k < cd.dim; ++k) {
@@ -462,7 +482,7 @@ __global__ void k_minv_fields(ClassDev cd, const double* __restrict__ in, double
     __syncthreads();
     double* t = a; a = b; b = t;
   }
-  double* dst = out + (size_t)macro * stride_macro + (size_t)fld * N;
+  double* dst = out + base + (size_t)fld * N;
   for (int i = threadIdx.x; i < N; i += blockDim.x) dst[i] = a[i];
 }
 
@@ -499,8 +519,8 @@ hipError_t lin_dispatch(HdgContext& c, const double* q, const double* u, const d
                         StageArgs sa) {
   LinPtrs lp{c.ws.Kq, c.ws.AUU, c.ws.AUQ, c.ws.RUe, c.ws.RQe, c.ws.SUB,
              c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.off_RB};
-  const long long nel = (long long)c.hm.n_macros * c.cd.E;
-  hipLaunchKernelGGL((k_lin_elem<D, P>), dim3((unsigned)nel), dim3(LIN_THREADS), 0, c.stream, c.cd, c.md, c.ph, sa,
+  const long long nel = c.hm.el_off[c.hm.n_macros];
+  hipLaunchKernelGGL((k_lin_elem<D, P>), dim3((unsigned)nel), dim3(LIN_THREADS), 0, c.stream, c.md, c.ph, sa,
                      q, u, uhat, w, lp);
   return hipGetLastError();
 }
@@ -520,17 +540,19 @@ hipError_t launch_linearize(HdgContext& c, const double* q, const double* u, con
   if (e != hipSuccess) return e;
   if (c.ph.supg && (e = launch_supg(c, q, u, w, sa)) != hipSuccess) return e;
   const int nm = c.hm.n_macros;
-  const long long nn = (long long)nm * c.cd.N;
+  const long long nn = c.n_u_tot / c.cd.ns;
   hipLaunchKernelGGL(k_gather_res, dim3((unsigned)std::min<long long>((nn + 255) / 256, 65535)), dim3(256), 0, c.stream,
-                     c.cd, c.nsA, c.dnsA, c.ws.RUe, c.ws.RQe, c.ws.RU, c.ws.RQ, nm);
-  const long long nb = (long long)nm * c.cd.n_b;
+                     c.md, c.nsA, c.dnsA, c.ws.RUe, c.ws.RQe, c.ws.RU, c.ws.RQ, nn);
+  const long long nb = c.hm.b_off[nm];
   hipLaunchKernelGGL(k_gather_rb, dim3((unsigned)std::min<long long>((nb + 255) / 256, 65535)), dim3(256), 0, c.stream,
-                     c.cd, c.md, c.ws.SUB, c.sub_stride, c.off_RB, c.ws.RBloc);
+                     c.md, c.ws.SUB, c.sub_stride, c.off_RB, c.ws.RBloc);
   hipLaunchKernelGGL(k_face_sum, dim3((unsigned)std::min<long long>((c.md.n_glob + 255) / 256, 65535)), dim3(256), 0,
-                     c.stream, c.cd, c.md, c.ws.RBloc, c.ws.RBglob);
+                     c.stream, c.md, c.ws.RBloc, c.ws.RBglob);
   const int nfield = c.cd.dim * c.cd.ns;
-  hipLaunchKernelGGL(k_minv_fields, dim3((unsigned)(nm * nfield)), dim3(256), 2 * c.cd.N * sizeof(double), c.stream,
-                     c.cd, c.ws.RQ, c.ws.RQt, nfield, (long long)c.cd.n_q);
+  int nmax = 0;
+  for (const HostClass& k : c.hcs) nmax = std::max(nmax, k.N);
+  hipLaunchKernelGGL(k_minv_fields, dim3((unsigned)(nm * nfield)), dim3(256), 2 * nmax * sizeof(double), c.stream,
+                     c.md, c.ws.RQ, c.ws.RQt, nfield);
   return hipGetLastError();
 }
 

@@ -663,11 +663,23 @@ template hipError_t lu_eliminate<double>(hipStream_t, double*, int, long long, i
 template hipError_t lu_eliminate<float>(hipStream_t, float*, int, long long, int, int, int, int, int*, int, int*,
                                         float*);
 
+// One batched elimination per macro class (the matrices of a class are
+// stored consecutively); status flag k of the context belongs to class k.
 hipError_t launch_lu(HdgContext& c, int prec) {
-  if (prec == 1)
-    return lu_eliminate<float>(c.stream, reinterpret_cast<float*>(c.ws.Wm), c.hm.n_macros, c.wstride, c.ldw, c.hc.n_u,
-                               c.n_rows, c.n_cols, c.ws.ipiv, c.hc.n_u, reinterpret_cast<int*>(c.ws.small),
-                               reinterpret_cast<float*>(c.ws.Uinv));
-  return lu_eliminate<double>(c.stream, c.ws.Wm, c.hm.n_macros, c.wstride, c.ldw, c.hc.n_u, c.n_rows,
-                              c.n_cols, c.ws.ipiv, c.hc.n_u, reinterpret_cast<int*>(c.ws.small), c.ws.Uinv);
+  int* status = reinterpret_cast<int*>(c.ws.small);
+  for (int k = 0; k < c.hm.n_classes; ++k) {
+    const HostClass& h = c.hcs[k];
+    int* ipiv = c.ws.ipiv + c.hm.class_ipiv_base[k];
+    const int batch = c.hm.class_count[k];
+    hipError_t e;
+    if (prec == 1)
+      e = lu_eliminate<float>(c.stream, reinterpret_cast<float*>(c.ws.Wm) + c.hm.class_w_base[k], batch, h.wstride,
+                              h.ldw, h.n_u, h.n_rows, h.n_cols, ipiv, h.n_u, status + k,
+                              reinterpret_cast<float*>(c.ws.Uinv));
+    else
+      e = lu_eliminate<double>(c.stream, c.ws.Wm + c.hm.class_w_base[k], batch, h.wstride, h.ldw, h.n_u, h.n_rows,
+                               h.n_cols, ipiv, h.n_u, status + k, c.ws.Uinv);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }

@@ -34,14 +34,16 @@ constexpr int SUPG_THREADS = 256;
 
 template <int D, int P>
 __global__ void __launch_bounds__(SUPG_THREADS)
-k_supg_prep(ClassDev cd, PhysDev ph, StageArgs sa, const double* __restrict__ qg, const double* __restrict__ ug,
+k_supg_prep(MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg, const double* __restrict__ ug,
             const double* __restrict__ wg, long long el0, double* __restrict__ RUe, double* __restrict__ Lbuf,
             double* __restrict__ Rbuf) {
   using Z = SupgSz<D, P>;
   constexpr int NS = Z::NS, A = Z::A, Q = Z::Q, NSA = Z::NSA, QY = Z::QY, NCOL = Z::NCOL;
   const int tid = threadIdx.x;
   const long long el = el0 + blockIdx.x;
-  const int macro = (int)(el / cd.E), e = (int)(el % cd.E);
+  const int macro = md.elem_macro[el];
+  const int e = (int)(el - md.el_off[macro]);
+  const ClassDev& cd = class_of(md, macro);
   const bool steady = !(sa.dt < 1e300);
   const double tcoef = steady ? 0.0 : sa.dii / sa.dt;
 
@@ -56,12 +58,12 @@ k_supg_prep(ClassDev cd, PhysDev ph, StageArgs sa, const double* __restrict__ qg
   const int* en = cd.elem_nodes + (size_t)e * A;
   for (int i = tid; i < A; i += SUPG_THREADS) s_nodes[i] = en[i];
   __syncthreads();
-  const double* um = ug + (size_t)macro * cd.n_u;
-  const double* qm = qg + (size_t)macro * cd.n_q;
+  const double* um = ug + md.u_off[macro];
+  const double* qm = qg + (size_t)D * md.u_off[macro];
   for (int i = tid; i < NS * A; i += SUPG_THREADS) {
     const int c = i / A, a = i % A;
     s_u[i] = um[(size_t)c * cd.N + s_nodes[a]];
-    s_w[i] = wg ? wg[(size_t)macro * cd.n_u + (size_t)c * cd.N + s_nodes[a]] : 0.0;
+    s_w[i] = wg ? wg[md.u_off[macro] + (size_t)c * cd.N + s_nodes[a]] : 0.0;
   }
   for (int i = tid; i < D * NS * A; i += SUPG_THREADS) {
     const int lc = i / A, a = i % A;
@@ -249,13 +251,13 @@ __global__ void __launch_bounds__(256) k_supg_gemm(int M, int N, int K, const do
 template <int D, int P>
 hipError_t supg_dispatch(HdgContext& c, const double* q, const double* u, const double* w, StageArgs sa) {
   using Z = SupgSz<D, P>;
-  const long long nel = (long long)c.hm.n_macros * c.cd.E;
+  const long long nel = c.hm.el_off[c.hm.n_macros];
   const long long chunk = c.supg_chunk;
   double* Lbuf = c.ws.supg;
   double* Rbuf = Lbuf + (size_t)chunk * Z::NSA * Z::QY;
   for (long long el0 = 0; el0 < nel; el0 += chunk) {
     const long long ne = std::min(chunk, nel - el0);
-    hipLaunchKernelGGL((k_supg_prep<D, P>), dim3((unsigned)ne), dim3(SUPG_THREADS), 0, c.stream, c.cd, c.ph, sa, q, u,
+    hipLaunchKernelGGL((k_supg_prep<D, P>), dim3((unsigned)ne), dim3(SUPG_THREADS), 0, c.stream, c.md, c.ph, sa, q, u,
                        w, el0, c.ws.RUe, Lbuf, Rbuf);
     // A_uu^e += L Ru,  A_uq^e += L Rq
     dim3 g1((Z::NSA + GT - 1) / GT, (Z::NSA + GT - 1) / GT, (unsigned)ne);

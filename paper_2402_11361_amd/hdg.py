@@ -39,7 +39,7 @@ class _Phys(ctypes.Structure):
 class _Sizes(ctypes.Structure):
     _fields_ = [("n_macros", ctypes.c_size_t), ("n_glob", ctypes.c_size_t), ("n_u_tot", ctypes.c_size_t),
                 ("n_q_tot", ctypes.c_size_t), ("n_u_macro", ctypes.c_size_t), ("n_b_macro", ctypes.c_size_t),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("n_faces", ctypes.c_size_t)]
 
 
 class KrylovOpts(ctypes.Structure):
@@ -62,7 +62,7 @@ class Mlp(ctypes.Structure):
                 ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p), ("work", ctypes.c_void_p)]
 
 
-EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_node_coords", "hdg_bind_workspace", "hdg_linearize_stage",
+EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_offsets", "hdg_node_coords", "hdg_bind_workspace", "hdg_linearize_stage",
            "hdg_condense", "hdg_apply_global", "hdg_fgmres_solve", "hdg_local_backsolve", "hdg_axpy",
            "hdg_destroy", "hdg_status_string", "hdg_last_error", "hdg_get_condensed", "hdg_get_formed",
            "hdg_get_residuals", "hdg_precond_apply", "hdg_coarse_size", "hdg_coarse_restrict",
@@ -83,6 +83,8 @@ def load_library(path=LIB_PATH):
     vp, dp, sz, i = ctypes.c_void_p, ctypes.c_double, ctypes.c_size_t, ctypes.c_int
     lib.hdg_setup_mesh.argtypes = [ctypes.POINTER(_MeshDesc), ctypes.POINTER(_Phys), vp, ctypes.POINTER(vp)]
     lib.hdg_query_sizes.argtypes = [vp, ctypes.POINTER(_Sizes)]
+    lib.hdg_macro_offsets.argtypes = [vp, vp, vp]
+    lib.hdg_face_offsets.argtypes = [vp, vp]
     lib.hdg_node_coords.argtypes = [vp, vp, vp]
     lib.hdg_bind_workspace.argtypes = [vp, vp, sz]
     lib.hdg_linearize_stage.argtypes = [vp, vp, vp, vp, vp, dp, dp, dp, vp]
@@ -174,6 +176,13 @@ class Context:
         self.workspace_bytes = s.workspace_bytes
         self.dim = dim
         self.ws = None
+        # per-macro offsets in u (q: dim * u_off) and in the local trace vectors
+        self.u_off = np.zeros(self.n_macros + 1, dtype=np.int64)
+        self.b_off = np.zeros(self.n_macros + 1, dtype=np.int64)
+        self._check(self.lib.hdg_macro_offsets(self.h, _np_ptr(self.u_off), _np_ptr(self.b_off)))
+        self.n_faces = s.n_faces
+        self.face_off = np.zeros(self.n_faces + 1, dtype=np.int64)
+        self._check(self.lib.hdg_face_offsets(self.h, _np_ptr(self.face_off)))
 
     def _check(self, code, ctx="self"):
         if code != 0:
@@ -201,6 +210,16 @@ class Context:
         fx = np.zeros(self.n_glob // (d + 2) * d)
         self._check(self.lib.hdg_node_coords(self.h, _np_ptr(mx), _np_ptr(fx)))
         return mx.reshape(-1, d), fx.reshape(-1, d)
+
+    def node_coords_split(self):
+        """Node coordinates as lists: one [N_i, d] array per macro and one
+        [n_nodes_f, d] array per face."""
+        mx, fx = self.node_coords()
+        ns = self.dim + 2
+        mo = self.u_off // ns
+        fo = self.face_off // ns
+        return ([mx[mo[i]:mo[i + 1]] for i in range(self.n_macros)],
+                [fx[fo[f]:fo[f + 1]] for f in range(self.n_faces)])
 
     def linearize_stage(self, q, u, uhat, w=None, dt=math.inf, d_ii=1.0, dtau=math.inf, norms=True):
         out = np.zeros(3) if norms else None
@@ -264,14 +283,14 @@ class Context:
         self._check(self.lib.hdg_axpy(self.h, ctypes.c_size_t(x.numel()), float(a), _ptr(x), _ptr(y)))
 
     def get_condensed(self, macro):
-        nb = self.n_b_macro
+        nb = int(self.b_off[macro + 1] - self.b_off[macro])
         A = np.zeros((nb, nb))
         b = np.zeros(nb)
         self._check(self.lib.hdg_get_condensed(self.h, ctypes.c_size_t(macro), _np_ptr(A), _np_ptr(b)))
         return A, b
 
     def get_formed(self, macro):
-        nr = self.n_u_macro + self.n_b_macro
+        nr = int(self.u_off[macro + 1] - self.u_off[macro] + self.b_off[macro + 1] - self.b_off[macro])
         W = np.zeros((nr, nr + 1))
         self._check(self.lib.hdg_get_formed(self.h, ctypes.c_size_t(macro), _np_ptr(W)))
         return W

@@ -22,6 +22,7 @@ CASES = {
     "2d_per_p2": dict(dim=2, n_elem=4, m=2, p=2, periodic=True),
     "2d_dir_p3": dict(dim=2, n_elem=4, m=2, p=3, periodic=False, state="shear", mach=0.2),
     "3d_per_p2": dict(dim=3, n_elem=4, m=2, p=2, periodic=True),
+    "3d_per_uneven_p2": dict(dim=3, seg=[[2, 3], [3, 2], [2, 2]], p=2, periodic=True),
 }
 
 
@@ -73,7 +74,7 @@ def test_fp32_condensed_objects(name):
     assert _rel(y.cpu().numpy(), A @ x) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["2d_dir_p3", "3d_per_p2"])
+@pytest.mark.parametrize("name", ["2d_dir_p3", "3d_per_p2", "3d_per_uneven_p2"])
 def test_fp32_condensation_refined_by_newton(name):
     from oracle.newton import newton_solve
     from paper_2402_11361_amd.driver import StageDriver

@@ -21,6 +21,11 @@ CASES = {
     "2d_dir_p2_supg": dict(dim=2, n_elem=6, m=3, p=2, periodic=False, state="shear", mach=0.2, supg=True),
     "2d_per_p3_supg": dict(dim=2, n_elem=4, m=2, p=3, periodic=True, supg=True),
     "3d_per_p2_supg": dict(dim=3, n_elem=4, m=2, p=2, periodic=True, supg=True),
+    # macros of different sizes in one mesh (several classes in one launch)
+    "2d_dir_uneven_p2": dict(dim=2, seg=[[2, 3], [3, 2]], p=2, periodic=False, state="shear", mach=0.2),
+    "3d_per_uneven_p2": dict(dim=3, seg=[[2, 3], [3, 2], [2, 2]], p=2, periodic=True),
+    "3d_dir_uneven_p1_supg": dict(dim=3, seg=[[1, 2], [2, 1], [2, 2]], p=1, periodic=False, state="shear",
+                                  mach=0.2, supg=True),
 }
 
 
