@@ -51,17 +51,79 @@ def workload_arrays(ctx, cfg, seed=0):
     return u, q, uh
 
 
-def condense_flops(cfg, n_u, n_b):
+def condense_flops(cfg, n_u, n_b, elems=None):
     """Algorithmic flops of the condensation of one macro: LU of S (2/3 n_u^3),
     S^{-1} C (2 n_u^2 n_b), D Y (2 n_b^2 n_u), plus the formation of S
-    (F_S = 2 d n_s^2 (p+1)^{2d} N m^d) and of the coupling blocks
-    (F_C = 4 d n_s^2 (p+1)^{2d} (n_b / n_s) m^d) from element-blocked products."""
-    d, p, m = cfg["dim"], cfg["p"], cfg["m"]
+    (F_S = 2 d n_s^2 (p+1)^{2d} N E) and of the coupling blocks
+    (F_C = 4 d n_s^2 (p+1)^{2d} (n_b / n_s) E) from element-blocked products,
+    E = m^d elements per macro."""
+    d, p = cfg["dim"], cfg["p"]
+    E = elems if elems is not None else cfg["m"] ** d
     ns = d + 2
     N = n_u // ns
-    F_S = 2.0 * d * ns ** 2 * (p + 1) ** (2 * d) * N * m ** d
-    F_C = 4.0 * d * ns ** 2 * (p + 1) ** (2 * d) * (n_b / ns) * m ** d
+    F_S = 2.0 * d * ns ** 2 * (p + 1) ** (2 * d) * N * E
+    F_C = 4.0 * d * ns ** 2 * (p + 1) ** (2 * d) * (n_b / ns) * E
     return (2.0 / 3.0) * n_u ** 3 + 2.0 * n_u ** 2 * n_b + 2.0 * n_b ** 2 * n_u + F_S + F_C
+
+
+def uneven_variant(args, dev_fn, variants):
+    """Stage solves on the 32^3 mesh cut into seeded segments of 2, 3 and 4
+    elements per axis (27 macro shapes in one mesh), plain FP64 and FP32
+    condensation."""
+    import torch
+    from paper_2402_11361_amd import inputs
+    from paper_2402_11361_amd.driver import StageDriver, alexander_dirk33
+    from paper_2402_11361_amd.hdg import HDG_FP32, HDG_FP64, Context
+    cfg = dict(inputs.CONFIGS["C3"])
+    seg = inputs.segments(cfg)
+    spec = dict(dim=3, n_elem=[cfg["n_elem"]] * 3, lo=[cfg["lo"]] * 3, hi=[cfg["hi"]] * 3, periodic=[True] * 3,
+                seg_len=seg, p=cfg["p"])
+    stream = torch.cuda.current_stream()
+    ctx = Context.from_mesh_spec(spec, Re=cfg["Re"], Mach=cfg["mach"], stream=stream.cuda_stream)
+    ctx.bind_workspace()
+    u0, q0, uh0 = workload_arrays(ctx, cfg)
+    q_i, u_i, uh_i = dev_fn(q0), dev_fn(u0), dev_fn(uh0)
+    A, _, _ = alexander_dirk33()
+    dii = 1.0 / A[0, 0]
+    dt = inputs.cfl_dt(cfg)
+    w = -dii * u_i
+    q, u, uh = q_i.clone(), u_i.clone(), uh_i.clone()
+    flops = 0.0
+    # per-macro element counts in macro order (axis 0 fastest)
+    elems = [a * b * c for c in seg[2] for b in seg[1] for a in seg[0]]
+    for i in range(ctx.n_macros):
+        nu = int(ctx.u_off[i + 1] - ctx.u_off[i])
+        nb = int(ctx.b_off[i + 1] - ctx.b_off[i])
+        flops += condense_flops(cfg, nu, nb, elems[i])
+    out = dict(workload="32^3 periodic Taylor-Green, segments of 2/3/4 elements per axis (seed 3), p=2, "
+                        f"{ctx.n_macros} macros of 27 shapes, n_glob {ctx.n_glob}",
+               n_macros=ctx.n_macros, n_glob=ctx.n_glob, condense_flops=flops)
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    for name, prec in (("plain_fp64", HDG_FP64), ("mixed_fp32", HDG_FP32)):
+        marks = []
+        drv = StageDriver(ctx, rtol=cfg["rtol"], condense_prec=prec, mark=lambda ph: marks.append((ph, ev())))
+        for rep in range(2):  # warm-up, then timed
+            q.copy_(q_i); u.copy_(u_i); uh.copy_(uh_i)
+            marks.clear()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = drv.solve_stage(q, u, uh, w, dt, dii)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        cond = [e.elapsed_time(e2) for (ph, e), (_, e2) in zip(marks[:-1], marks[1:]) if ph == "condense"]
+        cm = float(np.mean(cond))
+        peak = PEAK_FP64_TFLOPS if prec == HDG_FP64 else PEAK_FP32_TFLOPS
+        out[name] = dict(ms_per_stage=round(1e3 * wall, 3), newton_its=info["newton_its"],
+                         fgmres_outer=[k["outer_its"] for k in info["krylov"]], condense_ms=round(cm, 3),
+                         condense_tflops=round(flops / (cm * 1e-3) / 1e12, 3),
+                         condense_frac_peak=round(flops / (cm * 1e-3) / 1e12 / peak, 4))
+    variants["uneven_macros_32cubed"] = out
+    ctx.close()
 
 
 def train_learned(ctx, cfg, dev, dii, dt, args):
@@ -157,6 +219,7 @@ def main():
     ap.add_argument("--applies", type=int, default=20)
     ap.add_argument("--plain-only", action="store_true", help="time only the plain FP64 variant")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction variant")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-macro 32^3 variant")
     ap.add_argument("--graph-steps", type=int, default=10, help="FGMRES steps per captured HIP graph")
     ap.add_argument("--train-seeds", type=int, default=2)
     ap.add_argument("--train-vectors", type=int, default=40)
@@ -326,6 +389,14 @@ def main():
                roofline=roofline, variants=variants)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, newton_its)
+    if not args.plain_only and not args.no_uneven:
+        # free the 24^3 workspace first
+        ctx.close()
+        del ctx
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+        uneven_variant(args, dev, variants)
     print(json.dumps(out), flush=True)
 
 

@@ -744,6 +744,8 @@ hdg_status hdg_destroy(hdg_ctx ctx) {
   (void)hipStreamSynchronize(ctx->c.stream);
   clear_graphs(ctx->c);
   if (ctx->c.cap_stream) (void)hipStreamDestroy(ctx->c.cap_stream);
+  for (auto s : ctx->c.lu_streams) (void)hipStreamDestroy(s);
+  for (auto ev : ctx->c.lu_events) (void)hipEventDestroy(ev);
   for (void* p : ctx->c.dev_allocs) (void)hipFree(p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;

@@ -41,6 +41,10 @@ struct HostMesh {
   std::vector<long long> w_off, ipiv_off;         // [n_macros], grouped by class
   std::vector<long long> class_w_base, class_ipiv_base;
   std::vector<int> class_count, class_first;      // macros per class; first macro of the class
+  // face-preconditioner blocks stored grouped by face size: slot of each face,
+  // and per distinct size (trace unknowns, first slot, count)
+  std::vector<int> face_slot;
+  std::vector<std::array<int, 3>> face_groups;
 };
 
 struct Workspace {
@@ -107,7 +111,11 @@ struct HdgContext {
   // captured FGMRES steps: key (first step, steps, restart, inner its, inner prec,
   // condensed prec, learned, FP32 copy present) -> executable graph
   std::map<std::array<int, 8>, hipGraphExec_t> graphs;
-  hipStream_t cap_stream = nullptr;  // private stream used only for capture  // element type of the condensed matrices in Wm: 0 FP64, 1 FP32
+  hipStream_t cap_stream = nullptr;  // private stream used only for capture
+  // streams on which the per-class eliminations run concurrently (created on
+  // first use when the mesh has several macro classes), with fork/join events
+  std::vector<hipStream_t> lu_streams;
+  std::vector<hipEvent_t> lu_events;  // element type of the condensed matrices in Wm: 0 FP64, 1 FP32
   std::string last_error;
 };
 

@@ -510,6 +510,21 @@ void plan_workspace(HdgContext& c) {
   c.nf_max = 0;
   for (int f = 0; f < hm.n_faces; ++f) c.nf_max = std::max(c.nf_max, hm.face_ndof[f]);
   c.ldf = (int)align_up(2 * c.nf_max, 64);
+  // face blocks grouped by size (each group eliminated as one batch)
+  {
+    std::vector<int> order(hm.n_faces);
+    for (int f = 0; f < hm.n_faces; ++f) order[f] = f;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hm.face_ndof[a] < hm.face_ndof[b]; });
+    hm.face_slot.assign(hm.n_faces, 0);
+    hm.face_groups.clear();
+    for (int s = 0; s < hm.n_faces; ++s) {
+      const int f = order[s];
+      hm.face_slot[f] = s;
+      if (hm.face_groups.empty() || hm.face_groups.back()[0] != hm.face_ndof[f])
+        hm.face_groups.push_back({hm.face_ndof[f], s, 0});
+      ++hm.face_groups.back()[2];
+    }
+  }
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
   struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, gloc, Wm, ipiv, FW, fpiv, A32, ypart, kry, red, small, Uinv, lrn, kctl, supg; } o;
@@ -539,7 +554,9 @@ void plan_workspace(HdgContext& c) {
   o.small = take(sizeof(double) * 4096);
   // elimination scratch per matrix: a 64 x 64 block inverse, two row permutations
   // and a 128 x 128 unit-lower block inverse
-  o.Uinv = take(sizeof(double) * ((size_t)std::max(hm.n_macros, hm.n_faces) * (64 * 64 + 128 * 128 + 512) + 64));
+  // (per class slices when there are several classes)
+  o.Uinv = take(sizeof(double) * ((size_t)std::max(hm.n_macros, hm.n_faces) * (64 * 64 + 128 * 128 + 512) +
+                                  64 * (size_t)hm.n_classes + 64));
   // learned stage: X and Y per macro, then the BF16 copy of the largest network
   o.lrn = take(sizeof(float) * (2 * (size_t)hm.n_macros * hc.cF + 16) +
                sizeof(unsigned short) * mlp_param_count(hc.cF, LRN_MAX_HIDDEN, hc.cF));
@@ -671,5 +688,6 @@ void upload_tables(HdgContext& c) {
   md.u_off = up(c, hm.u_off); md.b_off = up(c, hm.b_off); md.el_off = up(c, hm.el_off);
   md.elem_macro = up(c, hm.elem_macro); md.sub_off = up(c, hm.sub_off); md.row_off = up(c, hm.row_off);
   md.w_off = up(c, hm.w_off); md.a32_off = up(c, hm.a32_off);
+  md.face_slot = up(c, hm.face_slot);
 }
 

@@ -95,6 +95,7 @@ struct MeshDev {
   const long long* row_off;    // [n_macros + 1] first row of the macro in the list of all augmented rows
   const long long* w_off;      // [n_macros] offset (elements) of the macro's tiled matrix, grouped by class
   const long long* a32_off;    // [n_macros + 1] offset of the macro's compact FP32 copy of A-hat
+  const int* face_slot;        // [n_faces] slot of the face's preconditioner block (grouped by size)
 };
 
 __device__ __forceinline__ const ClassDev& class_of(const MeshDev& md, int macro) {

@@ -124,7 +124,7 @@ __global__ void k_face_build(MeshDev md, const double* __restrict__ SUB, int sub
   const int F = blockIdx.x;
   const int nf = md.face_ndof[F];
   const int nn = nf / md.ns;
-  double* M = FW + (size_t)F * face_stride;
+  double* M = FW + (size_t)md.face_slot[F] * face_stride;
   for (int i = threadIdx.x; i < 2 * nf * ldf; i += blockDim.x) {
     const int r = i / ldf, c = i % ldf;
     double v = 0.0;
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(256) k_precond_apply(MeshDev md, const double*
   const long long off = md.face_off[F];
   for (int i = threadIdx.x; i < nf; i += blockDim.x) xs[i] = x[off + i];
   __syncthreads();
-  const double* Ai = FW + (size_t)F * face_stride;  // A^{-1} at (nf, nf) of the tiled block
+  const double* Ai = FW + (size_t)md.face_slot[F] * face_stride;  // A^{-1} at (nf, nf) of the tiled block
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int r = wave; r < nf; r += 4) {
     double s = 0.0;
@@ -385,27 +385,13 @@ hipError_t launch_face_precond(HdgContext& c) {
                      c.off_ABB, c.ws.FW, fs, c.ldf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // uniform face sizes per mesh axis; faces of one size are eliminated together
-  // (all faces have nf = face_ndof; mixed sizes are handled per distinct size)
-  std::vector<int> sizes;
-  for (int f = 0; f < c.hm.n_faces; ++f)
-    if (std::find(sizes.begin(), sizes.end(), c.hm.face_ndof[f]) == sizes.end()) sizes.push_back(c.hm.face_ndof[f]);
-  if (sizes.size() == 1) {
-    const int nf = sizes[0];
-    return lu_eliminate<double>(c.stream, c.ws.FW, c.hm.n_faces, fs, c.ldf, nf, 2 * nf, 2 * nf, c.ws.fpiv, c.nf_max,
-                        reinterpret_cast<int*>(c.ws.small) + c.hm.n_classes, c.ws.Uinv);
-  }
-  // several face sizes: runs of consecutive faces with the same size
-  int f0 = 0;
-  while (f0 < c.hm.n_faces) {
-    int f1 = f0;
-    while (f1 < c.hm.n_faces && c.hm.face_ndof[f1] == c.hm.face_ndof[f0]) ++f1;
-    const int nf = c.hm.face_ndof[f0];
-    e = lu_eliminate<double>(c.stream, c.ws.FW + (size_t)f0 * fs, f1 - f0, fs, c.ldf, nf, 2 * nf, 2 * nf,
-                     c.ws.fpiv + (size_t)f0 * c.nf_max, c.nf_max, reinterpret_cast<int*>(c.ws.small) + c.hm.n_classes,
-                     c.ws.Uinv);
+  // blocks are stored grouped by face size; one batched elimination per size
+  for (const auto& g : c.hm.face_groups) {
+    const int nf = g[0], s0 = g[1], cnt = g[2];
+    e = lu_eliminate<double>(c.stream, c.ws.FW + (size_t)s0 * fs, cnt, fs, c.ldf, nf, 2 * nf, 2 * nf,
+                             c.ws.fpiv + (size_t)s0 * c.nf_max, c.nf_max,
+                             reinterpret_cast<int*>(c.ws.small) + c.hm.n_classes, c.ws.Uinv);
     if (e != hipSuccess) return e;
-    f0 = f1;
   }
   return hipSuccess;
 }

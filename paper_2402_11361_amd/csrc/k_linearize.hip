@@ -1,7 +1,10 @@
 // Linearisation of the macro-element HDG residuals (paper eq. C38 / C242,
 // Newton blocks of eq. C312) on gfx950.
 //
-// One workgroup per element.  Pointwise fluxes and their derivatives come
+// One workgroup per element; the element tables (basis values, weights,
+// geometric contraction table, face tables) are the same for every macro
+// class and come by value, the macro-level ones through the macro's class.
+// Pointwise fluxes and their derivatives come
 // from physics.h (forward mode for d/du, exact linearity for d/dq).  Element
 // blocks are contractions of the pointwise derivative tensors K[(c,c')][(k,q)]
 // with the geometric table Tvol[(k,q)][(a,b)] = -dphi_k(x_q)_a phi(x_q)_b;
@@ -37,7 +40,7 @@ constexpr int KCHUNK = 64;
 
 template <int D, int P>
 __global__ void __launch_bounds__(LIN_THREADS)
-k_lin_elem(MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg,
+k_lin_elem(ClassDev ce, MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg,
            const double* __restrict__ ug, const double* __restrict__ uhg, const double* __restrict__ wg, LinPtrs lp) {
   using S_ = Sz<D, P>;
   constexpr int NS = S_::NS, A = S_::A, Q = S_::Q, T = S_::T, FQ = S_::FQ;
@@ -77,7 +80,7 @@ k_lin_elem(MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg,
   double* Ke = lp.Kq + (size_t)el * S_::KR * KC;
   // ---- pointwise volume terms ------------------------------------------
   for (int qp = tid; qp < Q; qp += LIN_THREADS) {
-    const double* phi = cd.Phi + (size_t)qp * A;
+    const double* phi = ce.Phi + (size_t)qp * A;
     double uq[NS], qq[D * NS], wq[NS];
 #pragma unroll
     for (int c = 0; c < NS; ++c) { uq[c] = 0.0; wq[c] = 0.0; }
@@ -90,7 +93,7 @@ k_lin_elem(MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg,
 #pragma unroll
       for (int i = 0; i < D * NS; ++i) qq[i] += f * s_q[i * A + a];
     }
-    const double Wq = cd.W[qp];
+    const double Wq = ce.W[qp];
     double fg[D * NS];
 #pragma unroll
     for (int i = 0; i < D * NS; ++i) fg[i] = 0.0;
@@ -138,16 +141,16 @@ k_lin_elem(MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg,
   for (int i = tid; i < NSA; i += LIN_THREADS) {
     int c = i / A, a = i % A;
     double s = 0.0;
-    for (int qp = 0; qp < Q; ++qp) s += cd.Phi[(size_t)qp * A + a] * s_Wtt[c * Q + qp];
+    for (int qp = 0; qp < Q; ++qp) s += ce.Phi[(size_t)qp * A + a] * s_Wtt[c * Q + qp];
     for (int k = 0; k < D; ++k)
-      for (int qp = 0; qp < Q; ++qp) s -= cd.dPhi[((size_t)k * Q + qp) * A + a] * s_WFG[(k * NS + c) * Q + qp];
+      for (int qp = 0; qp < Q; ++qp) s -= ce.dPhi[((size_t)k * Q + qp) * A + a] * s_WFG[(k * NS + c) * Q + qp];
     RUe[i] = s;
   }
   for (int i = tid; i < DNSA; i += LIN_THREADS) {
     int kc = i / A, a = i % A, k = kc / NS, c = kc % NS;
     double s = 0.0;
     for (int qp = 0; qp < Q; ++qp)
-      s += cd.Phi[(size_t)qp * A + a] * s_Wqq[kc * Q + qp] + cd.dPhi[((size_t)k * Q + qp) * A + a] * s_Wuq[c * Q + qp];
+      s += ce.Phi[(size_t)qp * A + a] * s_Wqq[kc * Q + qp] + ce.dPhi[((size_t)k * Q + qp) * A + a] * s_Wuq[c * Q + qp];
     RQe[i] = s;
   }
 
@@ -176,7 +179,7 @@ k_lin_elem(MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg,
 #pragma unroll
           for (int j = 0; j < CPT; ++j) {
             int col = cb + j * LIN_THREADS + tid;
-            t[j] = (col < NCOL) ? cd.Tvol[(size_t)(k0 + kk) * NCOL + col] : 0.0;
+            t[j] = (col < NCOL) ? ce.Tvol[(size_t)(k0 + kk) * NCOL + col] : 0.0;
           }
 #pragma unroll
           for (int r = 0; r < NS * NS; ++r) {
@@ -192,7 +195,7 @@ k_lin_elem(MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg,
         if (col >= NCOL) continue;
         int a = col / A, b = col % A;
         if (pass == 0) {
-          double mass = (tcoef + ptc) * cd.Mel[a * A + b];
+          double mass = (tcoef + ptc) * ce.Mel[a * A + b];
 #pragma unroll
           for (int c = 0; c < NS; ++c)
 #pragma unroll
@@ -222,9 +225,9 @@ k_lin_elem(MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg,
     const int bnd = md.macro_bnd[(size_t)macro * 2 * D + lf];
     const int nf = cd.nf_nodes[lf];
     const int* tidp = cd.sub_tid + (size_t)sid * T;
-    const int* fn = cd.fnode + lf * T;
-    const double* Psi = cd.Psi + (size_t)lf * FQ * T;
-    const double* WF = cd.WF + (size_t)lf * FQ;
+    const int* fn = ce.fnode + lf * T;
+    const double* Psi = ce.Psi + (size_t)lf * FQ * T;
+    const double* WF = ce.WF + (size_t)lf * FQ;
     __syncthreads();
     for (int i = tid; i < NS * T; i += LIN_THREADS) {
       int c = i / T, t = i % T;
@@ -520,7 +523,7 @@ hipError_t lin_dispatch(HdgContext& c, const double* q, const double* u, const d
   LinPtrs lp{c.ws.Kq, c.ws.AUU, c.ws.AUQ, c.ws.RUe, c.ws.RQe, c.ws.SUB,
              c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.off_RB};
   const long long nel = c.hm.el_off[c.hm.n_macros];
-  hipLaunchKernelGGL((k_lin_elem<D, P>), dim3((unsigned)nel), dim3(LIN_THREADS), 0, c.stream, c.md, c.ph, sa,
+  hipLaunchKernelGGL((k_lin_elem<D, P>), dim3((unsigned)nel), dim3(LIN_THREADS), 0, c.stream, c.cd, c.md, c.ph, sa,
                      q, u, uhat, w, lp);
   return hipGetLastError();
 }

@@ -26,6 +26,7 @@
 // Every kernel is a template on the storage and arithmetic type T (double or
 // float); the FP32 instance is the low-precision condensation.
 #include "context.h"
+#include <algorithm>
 
 namespace {
 
@@ -79,26 +80,26 @@ __device__ __forceinline__ void argmax_update(T& bv, int& bi, T v, int i) {
   if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
 }
 
-template <class T, int RPT>
-__global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs<T> a, int j0, int jb, int lcol0) {
+template <class T, int RPT, int NT>
+__global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int lcol0) {
   const int tid = threadIdx.x;
   const int mat = blockIdx.x;
   T* W = a.W + (size_t)mat * a.mat_stride;
   int* ipiv = a.ipiv + (size_t)mat * a.ipiv_stride;
   const int ld = a.ld, n_piv = a.n_piv;
-  __shared__ T s_bv[PANEL_THREADS / 64];
-  __shared__ int s_bi[PANEL_THREADS / 64];
+  __shared__ T s_bv[NT / 64];
+  __shared__ int s_bi[NT / 64];
   __shared__ int s_prow;
   __shared__ T s_urow[PW];
   __shared__ T s_swap[2][PW];
   __shared__ T s_U[PW * NB];
   for (int c0 = j0; c0 < j0 + jb; c0 += PW) {
     const int pw = min(PW, j0 + jb - c0);
-    // rows owned by this thread: c0 + tid + i * PANEL_THREADS
+    // rows owned by this thread: c0 + tid + i * NT
     T v[RPT][PW];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int r = c0 + tid + i * PANEL_THREADS;
+      const int r = c0 + tid + i * NT;
 #pragma unroll
       for (int cc = 0; cc < PW; ++cc) v[i][cc] = (r < n_piv && cc < pw) ? W[wtix(r, c0 + cc, ld)] : T(0);
     }
@@ -110,7 +111,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs<T> a, int j0, in
       int bi = 0x7fffffff;
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        const int r = c0 + tid + i * PANEL_THREADS;
+        const int r = c0 + tid + i * NT;
         T vc = v[i][0];
 #pragma unroll
         for (int k = 1; k < PW; ++k) vc = (k == cc) ? v[i][k] : vc;
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs<T> a, int j0, in
       if (tid == 0) {
         T b = s_bv[0];
         int bi0 = s_bi[0];
-        for (int w = 1; w < PANEL_THREADS / 64; ++w) argmax_update<T>(b, bi0, s_bv[w], s_bi[w]);
+        for (int w = 1; w < NT / 64; ++w) argmax_update<T>(b, bi0, s_bv[w], s_bi[w]);
         if (!(b > T(0))) {  // zero or NaN column: singular
           if (a.status) atomicCAS(a.status, 0, mat + 1);
           bi0 = col;
@@ -141,7 +142,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs<T> a, int j0, in
       if (prow != col) {
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-          const int rl = tid + i * PANEL_THREADS;
+          const int rl = tid + i * NT;
           if (rl == oc) {
 #pragma unroll
             for (int k = 0; k < PW; ++k) s_swap[0][k] = v[i][k];
@@ -154,7 +155,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs<T> a, int j0, in
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
-          const int rl = tid + i * PANEL_THREADS;
+          const int rl = tid + i * NT;
           if (rl == oc) {
 #pragma unroll
             for (int k = 0; k < PW; ++k) v[i][k] = s_swap[1][k];
@@ -165,7 +166,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs<T> a, int j0, in
           }
         }
         // the rest of the block row (columns [j0, c0) and [c0 + pw, j0 + jb)) in memory
-        for (int k = tid; k < j0 + jb - lcol0; k += PANEL_THREADS) {
+        for (int k = tid; k < j0 + jb - lcol0; k += NT) {
           const int cidx = lcol0 + k;  // L columns of a previous block too (lcol0 < j0)
           if (cidx >= c0 && cidx < c0 + pw) continue;
           T t = W[wtix(col, cidx, ld)];
@@ -176,7 +177,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs<T> a, int j0, in
       // broadcast the pivot row
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        if (tid + i * PANEL_THREADS == oc) {
+        if (tid + i * NT == oc) {
 #pragma unroll
           for (int k = 0; k < PW; ++k) s_urow[k] = v[i][k];
         }
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs<T> a, int j0, in
       const T ipv = (piv != T(0)) ? T(1) / piv : T(0);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        const int r = c0 + tid + i * PANEL_THREADS;
+        const int r = c0 + tid + i * NT;
         if (r > col && r < n_piv) {
           T vc = v[i][0];
 #pragma unroll
@@ -205,7 +206,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs<T> a, int j0, in
     // write the factored sub-panel back
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int r = c0 + tid + i * PANEL_THREADS;
+      const int r = c0 + tid + i * NT;
       if (r < n_piv) {
 #pragma unroll
         for (int cc = 0; cc < PW; ++cc)
@@ -217,7 +218,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs<T> a, int j0, in
     __syncthreads();
     if (nrest > 0) {
       // U rows of the sub-panel: L_sub^{-1} A[c0:c0+pw, rest]  (unit lower, sequential rows)
-      for (int k = tid; k < nrest; k += PANEL_THREADS) {
+      for (int k = tid; k < nrest; k += NT) {
         for (int i = 0; i < pw; ++i) {
           T s = W[wtix((c0 + i), rest0 + k, ld)];
           for (int m = 0; m < i; ++m) s -= W[wtix((c0 + i), c0 + m, ld)] * s_U[m * NB + k];
@@ -225,14 +226,14 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_panel(LuArgs<T> a, int j0, in
         }
       }
       __syncthreads();
-      for (int k = tid; k < pw * nrest; k += PANEL_THREADS) {
+      for (int k = tid; k < pw * nrest; k += NT) {
         const int i = k / nrest, cidx = k % nrest;
         W[wtix((c0 + i), rest0 + cidx, ld)] = s_U[i * NB + cidx];
       }
       // rows below the sub-panel: A[r, rest] -= L[r, c0:c0+pw] U
 #pragma unroll
       for (int i = 0; i < RPT; ++i) {
-        const int r = c0 + tid + i * PANEL_THREADS;
+        const int r = c0 + tid + i * NT;
         if (r >= c0 + pw && r < n_piv) {
 #pragma unroll 4
           for (int cidx = 0; cidx < nrest; ++cidx) {
@@ -601,12 +602,13 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
   LuArgs<T> a{W, mat_stride, ld, n_piv, n_rows, n_cols, ipiv, ipiv_stride, status, perm};
   if (ld % NC != 0) return hipErrorInvalidValue;
   const int rpt = (n_piv + PANEL_THREADS - 1) / PANEL_THREADS;
+  // up to 2048 rows: 512 threads, 1..4 rows each; up to 4096: 1024 threads, 4 rows each
   constexpr int TPW = 32;  // 16-row tiles per workgroup (8 per wave)
   auto panel = [&](int j0, int jb, int lcol0) {
-    if (rpt <= 1) hipLaunchKernelGGL((k_panel<T, 1>), dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
-    else if (rpt <= 2) hipLaunchKernelGGL((k_panel<T, 2>), dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
-    else if (rpt <= 4) hipLaunchKernelGGL((k_panel<T, 4>), dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
-    else hipLaunchKernelGGL((k_panel<T, 8>), dim3(batch), dim3(PANEL_THREADS), 0, s, a, j0, jb, lcol0);
+    if (rpt <= 1) hipLaunchKernelGGL((k_panel<T, 1, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
+    else if (rpt <= 2) hipLaunchKernelGGL((k_panel<T, 2, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
+    else if (rpt <= 4) hipLaunchKernelGGL((k_panel<T, 4, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
+    else hipLaunchKernelGGL((k_panel<T, 4, 1024>), dim3(batch), dim3(1024), 0, s, a, j0, jb, lcol0);
   };
   auto drows = [&](int j0, int jb) {  // L of the non-pivot rows: A_D,block U11^{-1}
     if (n_rows <= n_piv) return;
@@ -625,7 +627,7 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
     if (K > NB) hipLaunchKernelGGL((k_gemm<T, 2 * NB>), grid, dim3(256), 0, s, g);
     else hipLaunchKernelGGL((k_gemm<T, NB>), grid, dim3(256), 0, s, g);
   };
-  if (rpt > 8) return hipErrorInvalidValue;
+  if (n_piv > 4 * 1024) return hipErrorInvalidValue;
   for (int j0 = 0; j0 < n_piv; j0 += 2 * NB) {
     const int jb1 = std::min(NB, n_piv - j0);
     panel(j0, jb1, j0);
@@ -663,23 +665,63 @@ template hipError_t lu_eliminate<double>(hipStream_t, double*, int, long long, i
 template hipError_t lu_eliminate<float>(hipStream_t, float*, int, long long, int, int, int, int, int*, int, int*,
                                         float*);
 
+// Elimination scratch of one class: Uinv, permutations and Linv for `batch`
+// matrices, in doubles (with room for the 256-byte alignment of Linv).
+static size_t class_scratch_doubles(int batch) {
+  return (size_t)batch * (NB * NB + 4 * NB * NB + (2 * PERM_STRIDE + 1) / 2) + 64;
+}
+
 // One batched elimination per macro class (the matrices of a class are
 // stored consecutively); status flag k of the context belongs to class k.
+// With several classes they run concurrently on a few streams (fork from and
+// join back to the context's stream), each class with its own scratch slice.
 hipError_t launch_lu(HdgContext& c, int prec) {
   int* status = reinterpret_cast<int*>(c.ws.small);
-  for (int k = 0; k < c.hm.n_classes; ++k) {
+  const int ncl = c.hm.n_classes;
+  const int nstreams = ncl > 1 ? std::min(ncl, 4) : 0;
+  hipError_t e;
+  if (nstreams > 0 && c.lu_streams.empty()) {
+    c.lu_streams.resize(nstreams, nullptr);
+    c.lu_events.resize(nstreams + 1, nullptr);
+    for (auto& s : c.lu_streams)
+      if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return e;
+    for (auto& ev : c.lu_events)
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  if (nstreams > 0) {  // fork
+    if ((e = hipEventRecord(c.lu_events[nstreams], c.stream)) != hipSuccess) return e;
+    for (auto s : c.lu_streams)
+      if ((e = hipStreamWaitEvent(s, c.lu_events[nstreams], 0)) != hipSuccess) return e;
+  }
+  // largest classes first (their eliminations take longest)
+  std::vector<int> order(ncl);
+  for (int k = 0; k < ncl; ++k) order[k] = k;
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    return (double)c.hcs[a].n_u * c.hcs[a].n_u * c.hm.class_count[a] >
+           (double)c.hcs[b].n_u * c.hcs[b].n_u * c.hm.class_count[b];
+  });
+  size_t scr = 0;
+  for (int i = 0; i < ncl; ++i) {
+    const int k = order[i];
     const HostClass& h = c.hcs[k];
     int* ipiv = c.ws.ipiv + c.hm.class_ipiv_base[k];
     const int batch = c.hm.class_count[k];
-    hipError_t e;
+    hipStream_t s = nstreams > 0 ? c.lu_streams[i % nstreams] : c.stream;
+    double* scratch = c.ws.Uinv + scr;
+    scr += class_scratch_doubles(batch);
     if (prec == 1)
-      e = lu_eliminate<float>(c.stream, reinterpret_cast<float*>(c.ws.Wm) + c.hm.class_w_base[k], batch, h.wstride,
-                              h.ldw, h.n_u, h.n_rows, h.n_cols, ipiv, h.n_u, status + k,
-                              reinterpret_cast<float*>(c.ws.Uinv));
+      e = lu_eliminate<float>(s, reinterpret_cast<float*>(c.ws.Wm) + c.hm.class_w_base[k], batch, h.wstride, h.ldw,
+                              h.n_u, h.n_rows, h.n_cols, ipiv, h.n_u, status + k, reinterpret_cast<float*>(scratch));
     else
-      e = lu_eliminate<double>(c.stream, c.ws.Wm + c.hm.class_w_base[k], batch, h.wstride, h.ldw, h.n_u, h.n_rows,
-                               h.n_cols, ipiv, h.n_u, status + k, c.ws.Uinv);
+      e = lu_eliminate<double>(s, c.ws.Wm + c.hm.class_w_base[k], batch, h.wstride, h.ldw, h.n_u, h.n_rows, h.n_cols,
+                               ipiv, h.n_u, status + k, scratch);
     if (e != hipSuccess) return e;
+  }
+  if (nstreams > 0) {  // join
+    for (int i = 0; i < nstreams; ++i) {
+      if ((e = hipEventRecord(c.lu_events[i], c.lu_streams[i])) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(c.stream, c.lu_events[i], 0)) != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }

@@ -66,7 +66,45 @@ CONFIGS = {
                mach=0.1, Re=1600.0, noise=1e-4, rtol=1e-8),
     "C5": dict(dim=3, n_elem=48, m=4, p=2, lo=-np.pi, hi=np.pi, periodic=True, state="tgv",
                mach=0.1, Re=1600.0, noise=1e-4, rtol=1e-8),
+    # macros of uneven sizes: every axis of the 32^3 mesh cut into seeded
+    # segments of 2, 3 or 4 elements (one degree for the whole mesh)
+    "C3": dict(dim=3, n_elem=32, m=None, parts=(2, 3, 4), seg_seed=3, p=2, lo=-np.pi, hi=np.pi, periodic=True,
+               state="tgv", mach=0.1, Re=1600.0, noise=1e-4, rtol=1e-8),
 }
+
+
+def random_segments(n, parts, seed):
+    """Seeded cut of n elements into consecutive segments whose lengths are
+    drawn uniformly from `parts` among the choices that leave a remainder
+    that can still be cut (the last piece closes exactly)."""
+    rng = np.random.default_rng(seed)
+    out, left = [], n
+    small = min(parts)
+
+    def ok(r):
+        return r == 0 or any(r - x == 0 or (r - x >= small and ok_cache(r - x)) for x in parts)
+
+    memo = {}
+
+    def ok_cache(r):
+        if r not in memo:
+            memo[r] = ok(r)
+        return memo[r]
+
+    while left > 0:
+        choices = [x for x in parts if x <= left and ok_cache(left - x)]
+        x = int(rng.choice(choices))
+        out.append(x)
+        left -= x
+    return out
+
+
+def segments(cfg):
+    """Per-axis segment lengths of a workload (uniform m, or seeded parts)."""
+    d, n = cfg["dim"], cfg["n_elem"]
+    if cfg.get("m"):
+        return [[cfg["m"]] * (n // cfg["m"]) for _ in range(d)]
+    return [random_segments(n, cfg["parts"], cfg["seg_seed"] + k) for k in range(d)]
 
 
 def cfl_dt(cfg, cfl=1.0):
