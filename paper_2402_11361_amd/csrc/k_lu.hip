@@ -518,8 +518,8 @@ struct GemmArgs {
   int tiles_per_wg;
 };
 
-template <class T, int KB>
-__global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs<T> g) {
+template <class T, int KB, int NT>
+__device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int KS = KB / 4;  // MFMA k-steps; lane group grp covers k in [KS grp, KS grp + KS)
   const int mat = blockIdx.z;
@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs<T> g) {
   const int ld = g.ld, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int grp = lane >> 4, col = lane & 15;
   __shared__ T sB[KB * NC];
-  for (int i = tid; i < KB * NC; i += 256) {
+  for (int i = tid; i < KB * NC; i += NT) {
     const int k = i / NC, c = i % NC;
     sB[i] = (k < g.K && cs + c >= g.c_lo && cs + c < g.c_hi) ? (g.b_col_follow ? W[wtix(g.b_row0 + k, cs + c, ld)] : B[(size_t)k * g.ldb + c]) : T(0);
   }
@@ -562,7 +562,7 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs<T> g) {
   };
   T af[KS];
   v4 acc[NC / 16];
-  for (int t = wave; t < g.tiles_per_wg; t += 4) {
+  for (int t = wave; t < g.tiles_per_wg; t += NT / 64) {
     const int r0 = g.r_lo + (tile0 + t) * 16;
     if (r0 >= g.r_hi) break;
     load_a(r0, af);
@@ -586,6 +586,12 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs<T> g) {
       }
     }
   }
+}
+
+// Four waves (256 threads); at most two workgroups per CU for FP64 (LDS).
+template <class T, int KB>
+__global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs<T> g) {
+  gemm_body<T, KB, 256>(g);
 }
 
 }  // namespace
