@@ -31,7 +31,7 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by what the counters
 # read for a 1 GiB device copy in the same run (profiles/stage_solve_tgv24_m3_p2_fp64.md),
 # valid only while the kernel sources hash to `sha`.
-CONDENSE_TRAFFIC = {"sha": "4fe62eacee8e1cd2", "bytes": 1135.0e9}
+CONDENSE_TRAFFIC = {"sha": "2cc0a9ab23aa76d8", "bytes": 1133.0e9}
 CONDENSE_SOURCES = ("k_form.hip", "k_lu.hip")
 
 
