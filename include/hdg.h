@@ -58,7 +58,8 @@ typedef enum { HDG_FP64 = 0, HDG_FP32 = 1 } hdg_prec;
  * box macro-elements: along axis k the segments have seg_len[k][0..n_seg[k])
  * elements (host arrays, summing to n_elem[k]; lengths may differ, giving
  * macros of several shapes, each shape one class of reference tables).
- * Degree p in every element (p = 1..3; 3D p = 3 is HDG_EUNSUPPORTED).
+ * Degree p in every element (p = 1..3; the SUPG term with 3D p = 3 is
+ * HDG_EUNSUPPORTED).
  * dim = 2 or 3.  Paper Sec. 2.2 (mesh, patches, spaces). */
 typedef struct {
   int dim;
@@ -158,6 +159,23 @@ hdg_status hdg_node_coords(hdg_ctx ctx, double* macro_xyz_host, double* face_xyz
 /* Caller-owned device workspace of at least workspace_bytes (256-byte
  * aligned).  Must be bound before hdg_linearize_stage. */
 hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes);
+
+/* Chunked condensation, for meshes whose augmented macro matrices
+ * (n_u + n_b)^2 per macro do not fit in device memory at once (the local
+ * problems are independent per macro, Sec. 3.3, so they can be processed in
+ * groups).  macros_per_chunk > 0 and below n_macros: hdg_condense forms and
+ * eliminates consecutive ranges of that many macros through one buffer and
+ * keeps only the condensed blocks A-hat^{T_i} (compact, in the condensation
+ * precision) and b-hat^{T_i}; hdg_local_backsolve forms and factors each
+ * range's S again (the S rows only: LU and L^{-1} P (-C), no trace-row
+ * update).  0 (default) or >= n_macros: everything at once.
+ * Re-plans the workspace: call hdg_query_sizes and hdg_bind_workspace again
+ * afterwards (any bound workspace and learned network are released).
+ * With chunking, an FP32 inner operator (hdg_krylov_opts.inner_prec) needs
+ * an FP32 condensation (HDG_EUNSUPPORTED otherwise), and
+ * hdg_get_formed forms only the macro's chunk.  HDG_EINVAL when the number
+ * of chunks times the number of macro classes exceeds 4095. */
+hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk);
 
 /* Linearise eq. (C242) at (q, u, uhat): residuals R_Q, R_U, R_Uhat and the
  * Jacobian blocks of eq. (C312) of every macro, kept in the workspace.

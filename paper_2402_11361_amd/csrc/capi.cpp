@@ -304,7 +304,8 @@ hdg_status hdg_setup_mesh(const hdg_mesh_desc* mesh, const hdg_phys* phys, void*
   bool any_bnd = false;
   for (int v : c.hm.macro_bnd) any_bnd |= (v != 0);
   if (any_bnd && !phys->bc_state_host) { delete h; return HDG_EINVAL; }
-  if (mesh->dim == 3 && mesh->p == 3) { delete h; return HDG_EUNSUPPORTED; }
+  // the SUPG element kernel keeps its 3D p = 3 tables in LDS, which do not fit
+  if (phys->supg && mesh->dim == 3 && mesh->p == 3) { delete h; return HDG_EUNSUPPORTED; }
   c.stream = static_cast<hipStream_t>(hip_stream);
   c.hcs.resize(c.hm.n_classes);
   for (int k = 0; k < c.hm.n_classes; ++k) build_class(c.hm, c.hcs[k], c.hm.class_m[k]);
@@ -383,6 +384,30 @@ hdg_status hdg_node_coords(hdg_ctx ctx, double* macro_xyz, double* face_xyz) {
   return HDG_OK;
 }
 
+hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk) {
+  if (!ctx) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (macros_per_chunk < 0) return fail(&c, HDG_EINVAL, "macros_per_chunk must be >= 0");
+  const int nm = c.hm.n_macros;
+  const int per = (macros_per_chunk > 0 && macros_per_chunk < nm) ? macros_per_chunk : nm;
+  if ((long long)((nm + per - 1) / per) * c.hm.n_classes + 1 > 4096)
+    return fail(&c, HDG_EINVAL, "too many chunks (n_chunks * n_classes must stay below 4096)");
+  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  c.hm.chunk_macros = macros_per_chunk;
+  plan_workspace(c);
+  try {
+    upload_w_offsets(c);
+  } catch (const std::exception& ex) {
+    return fail(&c, HDG_EDEVICE, ex.what());
+  }
+  // the previous binding no longer matches the layout
+  c.ws_bound = false;
+  c.lrn_bound = false;
+  c.have_a32 = false;
+  clear_graphs(c);
+  return HDG_OK;
+}
+
 hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
   if (!ctx || !dev_ptr) return HDG_EINVAL;
   HdgContext& c = ctx->c;
@@ -397,12 +422,14 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
     rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.gloc); rebase(c.ws.Wm);
     rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.ypart); rebase(c.ws.kry);
     rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn); rebase(c.ws.kctl); rebase(c.ws.supg);
+    rebase(c.ws.Ac); rebase(c.ws.bloc);
   } else {
     auto rebase = [&](auto*& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(base + reinterpret_cast<uintptr_t>(p)); };
     rebase(c.ws.Kq); rebase(c.ws.AUU); rebase(c.ws.AUQ); rebase(c.ws.RUe); rebase(c.ws.RQe); rebase(c.ws.SUB);
     rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.gloc); rebase(c.ws.Wm);
     rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.ypart); rebase(c.ws.kry);
     rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn); rebase(c.ws.kctl); rebase(c.ws.supg);
+    rebase(c.ws.Ac); rebase(c.ws.bloc);
   }
   c.ws.base = base;
   c.lrn_bound = false;
@@ -438,29 +465,34 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
   if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
   if (prec != HDG_FP64 && prec != HDG_FP32) return fail(&c, HDG_EUNSUPPORTED, "condensation precision not built");
   const int p32 = (prec == HDG_FP32) ? 1 : 0;
-  // status flags: one per macro class, then one for the face blocks
-  const int ncl = c.hm.n_classes;
+  // status flags: one per (chunk, macro class), then one for the face blocks
+  const int ncl = c.hm.n_classes, nch = c.hm.n_chunks(), nst = nch * ncl;
   int* status = reinterpret_cast<int*>(c.ws.small);
-  HIPCHK(&c, launch_zero_ints(c.stream, status, ncl + 1));
-  HIPCHK(&c, launch_form(c, p32));
-  HIPCHK(&c, launch_lu(c, p32));
+  HIPCHK(&c, launch_zero_ints(c.stream, status, nst + 1));
+  for (int j = 0; j < nch; ++j) {
+    HIPCHK(&c, launch_form(c, p32, c.hm.chunk_first[j], c.hm.chunk_first[j + 1]));
+    HIPCHK(&c, launch_lu(c, p32, j, false));
+    if (c.hm.chunked()) HIPCHK(&c, launch_extract(c, p32, j));
+  }
   HIPCHK(&c, launch_bhat(c, bhat, p32));
   HIPCHK(&c, launch_face_precond(c));
   c.cond_prec = p32;
   c.have_a32 = false;
-  std::vector<int> st(ncl + 1, 0);
-  HIPCHK(&c, hipMemcpyAsync(ctx->pinned, status, sizeof(int) * (ncl + 1), hipMemcpyDeviceToHost, c.stream));
+  std::vector<int> st(nst + 1, 0);
+  HIPCHK(&c, hipMemcpyAsync(ctx->pinned, status, sizeof(int) * (nst + 1), hipMemcpyDeviceToHost, c.stream));
   HIPCHK(&c, hipStreamSynchronize(c.stream));
-  std::memcpy(st.data(), ctx->pinned, sizeof(int) * (ncl + 1));
-  for (int k = 0; k < ncl; ++k) {
-    if (!st[k]) continue;
-    // the st[k]-th macro of class k (macros of a class in increasing order)
-    int rank = st[k] - 1, macro = -1;
-    for (int i = 0; i < c.hm.n_macros && macro < 0; ++i)
-      if (c.hm.macro_class[i] == k && rank-- == 0) macro = i;
-    return fail(&c, HDG_ESINGULAR, "singular Schur complement in macro " + std::to_string(macro));
-  }
-  if (st[ncl]) return fail(&c, HDG_ESINGULAR, "singular face block of A_uhat-uhat " + std::to_string(st[ncl] - 1));
+  std::memcpy(st.data(), ctx->pinned, sizeof(int) * (nst + 1));
+  for (int j = 0; j < nch; ++j)
+    for (int k = 0; k < ncl; ++k) {
+      const int v = st[(size_t)j * ncl + k];
+      if (!v) continue;
+      // the v-th macro of class k within chunk j (macros of a class in increasing order)
+      int rank = v - 1, macro = -1;
+      for (int i = c.hm.chunk_first[j]; i < c.hm.chunk_first[j + 1] && macro < 0; ++i)
+        if (c.hm.macro_class[i] == k && rank-- == 0) macro = i;
+      return fail(&c, HDG_ESINGULAR, "singular Schur complement in macro " + std::to_string(macro));
+    }
+  if (st[nst]) return fail(&c, HDG_ESINGULAR, "singular face block of A_uhat-uhat " + std::to_string(st[nst] - 1));
   return HDG_OK;
 }
 
@@ -480,6 +512,8 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
       o->max_outer < 1 || !(o->rtol >= 0) || !(o->atol >= 0) || o->graph_steps < 0)
     return fail(&c, HDG_EINVAL, "bad Krylov options");
   auto t0 = std::chrono::steady_clock::now();
+  if (o->inner_prec == HDG_FP32 && c.cond_prec == 0 && c.hm.chunked())
+    return fail(&c, HDG_EUNSUPPORTED, "FP32 inner operator with chunked FP64 condensation (condense in FP32 instead)");
   if (o->inner_prec == HDG_FP32 && c.cond_prec == 0 && !c.have_a32) {
     HIPCHK(&c, launch_cast_ahat(c));
     c.have_a32 = true;
@@ -639,6 +673,8 @@ hdg_status hdg_precond_apply(hdg_ctx ctx, const double* v, double* z, int inner_
   if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
   if (inner_its < 0 || inner_its > c.kry_inner_max) return fail(&c, HDG_EINVAL, "bad inner_its");
   if (use_learned && !c.lrn_bound) return fail(&c, HDG_EINVAL, "use_learned without a bound network");
+  if (inner_prec == HDG_FP32 && c.cond_prec == 0 && c.hm.chunked())
+    return fail(&c, HDG_EUNSUPPORTED, "FP32 inner operator with chunked FP64 condensation (condense in FP32 instead)");
   if (inner_prec == HDG_FP32 && c.cond_prec == 0 && !c.have_a32) {
     HIPCHK(&c, launch_cast_ahat(c));
     c.have_a32 = true;
@@ -777,6 +813,23 @@ hdg_status hdg_get_condensed(hdg_ctx ctx, size_t macro, double* ahat_host, doubl
   if (!c.ws_bound || macro >= (size_t)c.hm.n_macros) return HDG_EINVAL;
   const HostClass& hk = c.hcs[c.hm.macro_class[macro]];
   const int nb = hk.n_b, nu = hk.n_u;
+  if (c.hm.chunked()) {  // compact copies
+    const long long ao = c.hm.a32_off[macro], n2 = (long long)nb * nb;
+    if (ahat_host && c.cond_prec == 1) {
+      std::vector<float> f((size_t)n2);
+      HIPCHK(&c, hipMemcpyAsync(f.data(), reinterpret_cast<const float*>(c.ws.Ac) + ao, sizeof(float) * n2,
+                                hipMemcpyDeviceToHost, c.stream));
+      HIPCHK(&c, hipStreamSynchronize(c.stream));
+      for (long long i = 0; i < n2; ++i) ahat_host[i] = f[i];
+    } else if (ahat_host) {
+      HIPCHK(&c, hipMemcpyAsync(ahat_host, c.ws.Ac + ao, sizeof(double) * n2, hipMemcpyDeviceToHost, c.stream));
+    }
+    if (bhat_host)
+      HIPCHK(&c, hipMemcpyAsync(bhat_host, c.ws.bloc + c.hm.b_off[macro], sizeof(double) * nb, hipMemcpyDeviceToHost,
+                                c.stream));
+    HIPCHK(&c, hipStreamSynchronize(c.stream));
+    return HDG_OK;
+  }
   std::vector<double> tiled;
   hdg_status s = copy_tiled_macro(ctx, macro, tiled, c.cond_prec);
   if (s != HDG_OK) return s;
@@ -798,8 +851,10 @@ hdg_status hdg_get_formed(hdg_ctx ctx, size_t macro, double* w_host) {
   if (!ctx || !w_host) return HDG_EINVAL;
   HdgContext& c = ctx->c;
   if (!c.ws_bound || macro >= (size_t)c.hm.n_macros) return HDG_EINVAL;
-  HIPCHK(&c, launch_form(c, 0));
-  c.cond_prec = 0;
+  int j = 0;  // the chunk holding the macro
+  while (c.hm.chunk_first[j + 1] <= (int)macro) ++j;
+  HIPCHK(&c, launch_form(c, 0, c.hm.chunk_first[j], c.hm.chunk_first[j + 1]));
+  if (!c.hm.chunked()) c.cond_prec = 0;  // W no longer holds the condensed operator
   std::vector<double> tiled;
   hdg_status s = copy_tiled_macro(ctx, macro, tiled, 0);
   if (s != HDG_OK) return s;

@@ -45,6 +45,17 @@ struct HostMesh {
   // and per distinct size (trace unknowns, first slot, count)
   std::vector<int> face_slot;
   std::vector<std::array<int, 3>> face_groups;
+  // chunked condensation: the macros are condensed in consecutive ranges
+  // [chunk_first[j], chunk_first[j + 1]) through one W buffer sized for the
+  // largest range; w_off is then relative to that buffer.  Per (chunk, class):
+  // offset of the class's matrices in the buffer, their count and the rank
+  // (within the class) of the first of them.
+  int chunk_macros = 0;                  // requested macros per chunk (0: all at once)
+  std::vector<int> chunk_first;          // [n_chunks + 1]
+  std::vector<long long> chunk_class_w;  // [n_chunks * n_classes]
+  std::vector<int> chunk_class_cnt, chunk_class_rank0;
+  int n_chunks() const { return (int)chunk_first.size() - 1; }
+  bool chunked() const { return n_chunks() > 1; }
 };
 
 struct Workspace {
@@ -75,6 +86,9 @@ struct Workspace {
   float* lrn = nullptr;     // learned stage: X, Y [macros][cF] each, then the BF16 network
   double* kctl = nullptr;   // device-resident Krylov control block (Hessenbergs, rotations, scalars)
   double* supg = nullptr;   // SUPG products of a chunk of elements (only with SUPG on)
+  // chunked condensation only (Wm then holds one chunk and shares its memory with Kq)
+  double* Ac = nullptr;     // [macros][n_b][n_b] compact A-hat (FP64, or FP32 in the first half)
+  double* bloc = nullptr;   // [macros][n_b] b-hat^{T_i}
 };
 
 struct HdgContext {
@@ -134,5 +148,6 @@ bool build_mesh(const HdgMeshIn& in, HostMesh& hm, std::string& err);
 void build_class(const HostMesh& hm, HostClass& hc, const std::array<int, 3>& m);
 void plan_workspace(HdgContext& c);
 void upload_tables(HdgContext& c);
+void upload_w_offsets(HdgContext& c);
 void node_coords(const HdgContext& c, double* macro_xyz, double* face_xyz);
 

@@ -491,13 +491,37 @@ void plan_workspace(HdgContext& c) {
     wb += hm.class_count[k] * c.hcs[k].wstride;
     pb += (long long)hm.class_count[k] * c.hcs[k].n_u;
   }
+  // chunks of consecutive macros; inside a chunk's W buffer the matrices are
+  // grouped by class (one chunk holding every macro when chunking is off)
+  const int per = (hm.chunk_macros > 0 && hm.chunk_macros < nm) ? hm.chunk_macros : nm;
+  hm.chunk_first.clear();
+  for (int i = 0; i < nm; i += per) hm.chunk_first.push_back(i);
+  hm.chunk_first.push_back(nm);
+  const int nch = hm.n_chunks();
+  hm.chunk_class_w.assign((size_t)nch * ncl, 0);
+  hm.chunk_class_cnt.assign((size_t)nch * ncl, 0);
+  hm.chunk_class_rank0.assign((size_t)nch * ncl, 0);
   hm.w_off.assign(nm, 0); hm.ipiv_off.assign(nm, 0);
   std::vector<int> rank(ncl, 0);
-  for (int i = 0; i < nm; ++i) {
-    const int k = hm.macro_class[i];
-    hm.w_off[i] = hm.class_w_base[k] + rank[k] * c.hcs[k].wstride;
-    hm.ipiv_off[i] = hm.class_ipiv_base[k] + (long long)rank[k] * c.hcs[k].n_u;
-    ++rank[k];
+  long long w_chunk_max = 0;
+  for (int j = 0; j < nch; ++j) {
+    int* cnt = &hm.chunk_class_cnt[(size_t)j * ncl];
+    for (int i = hm.chunk_first[j]; i < hm.chunk_first[j + 1]; ++i) ++cnt[hm.macro_class[i]];
+    long long wb_j = 0;
+    for (int k = 0; k < ncl; ++k) {
+      hm.chunk_class_w[(size_t)j * ncl + k] = wb_j;
+      hm.chunk_class_rank0[(size_t)j * ncl + k] = rank[k];
+      wb_j += cnt[k] * c.hcs[k].wstride;
+    }
+    w_chunk_max = std::max(w_chunk_max, wb_j);
+    std::vector<int> r(ncl, 0);
+    for (int i = hm.chunk_first[j]; i < hm.chunk_first[j + 1]; ++i) {
+      const int k = hm.macro_class[i];
+      hm.w_off[i] = hm.chunk_class_w[(size_t)j * ncl + k] + r[k] * c.hcs[k].wstride;
+      hm.ipiv_off[i] = hm.class_ipiv_base[k] + (long long)(rank[k] + r[k]) * c.hcs[k].n_u;
+      ++r[k];
+    }
+    for (int k = 0; k < ncl; ++k) rank[k] += cnt[k];
   }
   const long long n_el = hm.el_off[nm];
   c.n_u_tot = hm.u_off[nm];
@@ -527,8 +551,11 @@ void plan_workspace(HdgContext& c) {
   }
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, gloc, Wm, ipiv, FW, fpiv, A32, ypart, kry, red, small, Uinv, lrn, kctl, supg; } o;
-  o.Kq = take(sizeof(double) * n_el * c.Kstride);
+  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, gloc, Wm, ipiv, FW, fpiv, A32, ypart, kry, red, small, Uinv, lrn, kctl, supg, Ac, bloc; } o;
+  const bool chunked = hm.chunked();
+  const size_t kq_bytes = sizeof(double) * n_el * c.Kstride;
+  // chunked: Kq (used only inside the linearisation) shares the W buffer
+  o.Kq = chunked ? 0 : take(kq_bytes);
   o.AUU = take(sizeof(double) * n_el * c.nsA * c.nsA);
   o.AUQ = take(sizeof(double) * n_el * c.nsA * c.dnsA);
   o.RUe = take(sizeof(double) * n_el * c.nsA);
@@ -541,13 +568,13 @@ void plan_workspace(HdgContext& c) {
   o.RBglob = take(sizeof(double) * hm.n_glob);
   o.gloc = take(sizeof(double) * (size_t)hm.b_off[nm]);
   c.fstride = (long long)align_up(2 * c.nf_max, 16) * c.ldf;
-  long long w_total = 0;
-  for (int k = 0; k < hm.n_classes; ++k) w_total += hm.class_count[k] * c.hcs[k].wstride;
-  o.Wm = take(sizeof(double) * (size_t)w_total);
+  o.Wm = take(std::max(sizeof(double) * (size_t)w_chunk_max, chunked ? kq_bytes : 0));
+  if (chunked) o.Kq = o.Wm;
   o.ipiv = take(sizeof(int) * (size_t)c.n_u_tot);
   o.FW = take(sizeof(double) * (size_t)hm.n_faces * c.fstride);
   o.fpiv = take(sizeof(int) * (size_t)hm.n_faces * c.nf_max);
-  o.A32 = take(sizeof(float) * (size_t)hm.a32_off[nm]);
+  // FP32 copy of A-hat for the inner solver (not kept when chunked)
+  o.A32 = take(chunked ? 0 : sizeof(float) * (size_t)hm.a32_off[nm]);
   o.ypart = take(sizeof(double) * (size_t)hm.b_off[nm]);
   o.kry = take(sizeof(double) * (size_t)(2 * c.kry_restart_max + c.kry_inner_max + 8) * hm.n_glob);
   o.red = take(sizeof(double) * (1 << 20));
@@ -564,6 +591,8 @@ void plan_workspace(HdgContext& c) {
   // SUPG: the per-element products are formed in batches of up to 4096 elements
   c.supg_chunk = c.ph.supg ? std::min<long long>(n_el, 4096) : 0;
   o.supg = take(sizeof(double) * (size_t)c.supg_chunk * (c.ph.supg ? supg_scratch_per_element(hc.dim, hc.p) : 0));
+  o.Ac = take(chunked ? sizeof(double) * (size_t)hm.a32_off[nm] : 0);
+  o.bloc = take(chunked ? sizeof(double) * (size_t)hm.b_off[nm] : 0);
   c.need_bytes = off;
   // remember offsets in the workspace struct (resolved on bind)
   c.ws.bytes = 0;
@@ -592,6 +621,8 @@ void plan_workspace(HdgContext& c) {
   c.ws.lrn = reinterpret_cast<float*>(o.lrn);
   c.ws.kctl = reinterpret_cast<double*>(o.kctl);
   c.ws.supg = reinterpret_cast<double*>(o.supg);
+  c.ws.Ac = reinterpret_cast<double*>(o.Ac);
+  c.ws.bloc = reinterpret_cast<double*>(o.bloc);
 }
 
 void node_coords(const HdgContext& c, double* macro_xyz, double* face_xyz) {
@@ -689,5 +720,17 @@ void upload_tables(HdgContext& c) {
   md.elem_macro = up(c, hm.elem_macro); md.sub_off = up(c, hm.sub_off); md.row_off = up(c, hm.row_off);
   md.w_off = up(c, hm.w_off); md.a32_off = up(c, hm.a32_off);
   md.face_slot = up(c, hm.face_slot);
+}
+
+// Replaces the device copy of the per-macro W offsets (after a new chunking).
+void upload_w_offsets(HdgContext& c) {
+  const void* old = c.md.w_off;
+  c.md.w_off = up(c, c.hm.w_off);
+  for (auto it = c.dev_allocs.begin(); it != c.dev_allocs.end(); ++it)
+    if (*it == old) {
+      (void)hipFree(*it);
+      c.dev_allocs.erase(it);
+      break;
+    }
 }
 

@@ -128,8 +128,12 @@ struct HdgContext;
 hipError_t launch_linearize(HdgContext& c, const double* q, const double* u, const double* uhat,
                             const double* w, StageArgs sa);
 // prec: 0 FP64, 1 FP32 element type of the augmented matrices
-hipError_t launch_form(HdgContext& c, int prec);
-hipError_t launch_lu(HdgContext& c, int prec);
+// formation and elimination of the macros [m0, m1) = chunk j (rows of the
+// trace block skipped in the elimination when top_only)
+hipError_t launch_form(HdgContext& c, int prec, int m0, int m1);
+hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only);
+// chunked condensation: A-hat^{T_i} and b-hat^{T_i} of chunk j out of W
+hipError_t launch_extract(HdgContext& c, int prec, int chunk);
 hipError_t launch_bhat(HdgContext& c, double* bhat, int prec);
 hipError_t launch_face_precond(HdgContext& c);
 hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec);

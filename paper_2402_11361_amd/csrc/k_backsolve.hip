@@ -26,10 +26,10 @@ constexpr int BS_ROWS = 64;
 // W is the eliminated matrix in its storage type T (double or float); the
 // recovery itself runs in FP64.
 template <class T>
-__global__ void __launch_bounds__(256) k_bs_rhs(MeshDev md, const T* __restrict__ Wm, const double* __restrict__ x,
-                                                double* __restrict__ z) {
+__global__ void __launch_bounds__(256) k_bs_rhs(MeshDev md, int m0, const T* __restrict__ Wm,
+                                                const double* __restrict__ x, double* __restrict__ z) {
   extern __shared__ double xs[];
-  const int macro = blockIdx.y;
+  const int macro = m0 + blockIdx.y;
   const ClassDev& cd = class_of(md, macro);
   const int nb = cd.n_b, nu = cd.n_u, d = cd.dim, ld = cd.ldw, n_cols = cd.n_cols;
   if (blockIdx.x * BS_ROWS >= nu) return;
@@ -54,10 +54,11 @@ __global__ void __launch_bounds__(256) k_bs_rhs(MeshDev md, const T* __restrict_
 // Backward substitution U du = z in place (z -> du), one workgroup per macro,
 // blocks of 64 rows from the bottom.
 template <class T>
-__global__ void __launch_bounds__(256) k_bs_trsv(MeshDev md, const T* __restrict__ Wm, double* __restrict__ du) {
+__global__ void __launch_bounds__(256) k_bs_trsv(MeshDev md, int m0, const T* __restrict__ Wm,
+                                                 double* __restrict__ du) {
   __shared__ double sU[BS_ROWS][BS_ROWS + 1];
   __shared__ double sz[BS_ROWS];
-  const int macro = blockIdx.x;
+  const int macro = m0 + blockIdx.x;
   const ClassDev& cd = class_of(md, macro);
   const int nu = cd.n_u, ld = cd.ldw;
   const T* U = Wm + md.w_off[macro];
@@ -133,19 +134,41 @@ __global__ void k_bs_dq(MeshDev md, const double* __restrict__ RQt, const double
 
 }  // namespace
 
+// Macros [m0, m1) from their eliminated matrices in W.
+static hipError_t backsolve_range(HdgContext& c, const double* duhat, double* du, int m0, int m1, int nu, int nb) {
+  const int nm = m1 - m0;
+  if (nm <= 0) return hipSuccess;
+  const dim3 grid_rhs((nu + BS_ROWS - 1) / BS_ROWS, nm);
+  if (c.cond_prec == 1) {
+    const float* W32 = reinterpret_cast<const float*>(c.ws.Wm);
+    hipLaunchKernelGGL(k_bs_rhs<float>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, m0, W32,
+                       duhat, du);
+    hipLaunchKernelGGL(k_bs_trsv<float>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, W32, du);
+  } else {
+    hipLaunchKernelGGL(k_bs_rhs<double>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, m0, c.ws.Wm,
+                       duhat, du);
+    hipLaunchKernelGGL(k_bs_trsv<double>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, c.ws.Wm, du);
+  }
+  return hipGetLastError();
+}
+
+// Unchunked: W still holds every macro's elimination.  Chunked: each chunk
+// is formed and its S rows eliminated again (the trace rows are not needed),
+// in the precision of the last condensation, then recovered.
 hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, double* du) {
   int nu = 0, nb = 0;
   for (const HostClass& k : c.hcs) { nu = std::max(nu, k.n_u); nb = std::max(nb, k.n_b); }
   const int nm = c.hm.n_macros;
-  const dim3 grid_rhs((nu + BS_ROWS - 1) / BS_ROWS, nm);
-  if (c.cond_prec == 1) {
-    const float* W32 = reinterpret_cast<const float*>(c.ws.Wm);
-    hipLaunchKernelGGL(k_bs_rhs<float>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, W32, duhat, du);
-    hipLaunchKernelGGL(k_bs_trsv<float>, dim3(nm), dim3(256), 0, c.stream, c.md, W32, du);
+  hipError_t e;
+  if (!c.hm.chunked()) {
+    if ((e = backsolve_range(c, duhat, du, 0, nm, nu, nb)) != hipSuccess) return e;
   } else {
-    hipLaunchKernelGGL(k_bs_rhs<double>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, c.ws.Wm, duhat,
-                       du);
-    hipLaunchKernelGGL(k_bs_trsv<double>, dim3(nm), dim3(256), 0, c.stream, c.md, c.ws.Wm, du);
+    for (int j = 0; j < c.hm.n_chunks(); ++j) {
+      const int m0 = c.hm.chunk_first[j], m1 = c.hm.chunk_first[j + 1];
+      if ((e = launch_form(c, c.cond_prec, m0, m1)) != hipSuccess) return e;
+      if ((e = launch_lu(c, c.cond_prec, j, true)) != hipSuccess) return e;
+      if ((e = backsolve_range(c, duhat, du, m0, m1, nu, nb)) != hipSuccess) return e;
+    }
   }
   hipLaunchKernelGGL(k_bs_dq, dim3(nm * c.cd.dim * c.cd.ns), dim3(256), 0, c.stream, c.md, c.ws.RQt, du, duhat, dq);
   return hipGetLastError();

@@ -28,6 +28,7 @@ struct FormPtrs {
   const double *AUU, *AUQ, *SUB, *RU, *RQt, *RBloc;
   double* gloc;  // non-null: g goes here in FP64 and its W entries are 0
   int nsA, dnsA, sub_stride, off_AUB, off_ABU, off_ABQ, off_ABB;
+  long long row0;  // first row of the launch (rows of all macros numbered consecutively)
 };
 
 __device__ __forceinline__ void digits(int x, int base, int d, int* out) {
@@ -110,7 +111,7 @@ __global__ void __launch_bounds__(FORM_THREADS) k_form(MeshDev md, FormPtrs fp, 
   extern __shared__ double row[];
   __shared__ double red[FORM_THREADS];
   const int tid = threadIdx.x;
-  const long long gr = blockIdx.x;
+  const long long gr = fp.row0 + blockIdx.x;
   const int macro = find_in(md.row_off, md.n_macros, gr);
   const int r = (int)(gr - md.row_off[macro]);
   const ClassDev& cd = class_of(md, macro);
@@ -227,12 +228,13 @@ __global__ void __launch_bounds__(FORM_THREADS) k_form(MeshDev md, FormPtrs fp, 
 
 }  // namespace
 
-hipError_t launch_form(HdgContext& c, int prec) {
+hipError_t launch_form(HdgContext& c, int prec, int m0, int m1) {
   // FP32 storage: g of the trace rows stays in FP64 (it is O(1) per macro but
   // cancels between the two sides of a face in the assembled b-hat)
   FormPtrs fp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.ws.RQt, c.ws.RBloc, prec == 1 ? c.ws.gloc : nullptr,
-              c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB};
-  const long long nblk = c.hm.row_off[c.hm.n_macros];
+              c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.hm.row_off[m0]};
+  const long long nblk = c.hm.row_off[m1] - c.hm.row_off[m0];
+  if (nblk <= 0) return hipSuccess;
   const size_t shm = (size_t)c.n_cols * sizeof(double);  // largest class
   if (prec == 1)
     hipLaunchKernelGGL(k_form<float>, dim3((unsigned)nblk), dim3(FORM_THREADS), shm, c.stream, c.md, fp,

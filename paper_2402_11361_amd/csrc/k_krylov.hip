@@ -187,6 +187,27 @@ __global__ void k_cast_ahat(MeshDev md, const double* __restrict__ W, float* __r
   }
 }
 
+// Chunked condensation: A-hat^{T_i} (rows and columns [n_u, n_u + n_b) of
+// the eliminated matrix) to the compact row-major copy at a32_off[macro], and
+// b-hat^{T_i} (last column, plus the FP64 g kept outside W by the FP32 path)
+// to bloc.  One workgroup per (row band, macro of the chunk).
+template <class T>
+__global__ void k_extract(MeshDev md, int m0, const T* __restrict__ W, T* __restrict__ Ac,
+                          const double* __restrict__ gloc, double* __restrict__ bloc) {
+  const int macro = m0 + blockIdx.y;
+  const ClassDev& cd = class_of(md, macro);
+  const int nb = cd.n_b, nu = cd.n_u;
+  const T* Wm = W + md.w_off[macro];
+  T* A = Ac + md.a32_off[macro];
+  for (int r = blockIdx.x; r < nb; r += gridDim.x) {
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) A[(size_t)r * nb + k] = Wm[wtix(nu + r, nu + k, cd.ldw)];
+    if (threadIdx.x == 0) {
+      const double b = (double)Wm[wtix(nu + r, cd.n_cols - 1, cd.ldw)];
+      bloc[md.b_off[macro] + r] = gloc ? gloc[md.b_off[macro] + r] + b : b;
+    }
+  }
+}
+
 // ---- vector kernels -------------------------------------------------------
 constexpr int VEC_BLOCKS = 512;
 
@@ -345,6 +366,7 @@ hipError_t launch_zero_ints(hipStream_t s, int* p, int n) {
 }
 
 hipError_t launch_bhat(HdgContext& c, double* bhat, int prec) {
+  if (c.hm.chunked()) return launch_face_sum(c, c.ws.bloc, bhat);  // k_extract filled bloc
   // b-hat^{T_i}: column n_cols - 1 of rows [n_u, n_u + n_b) of each tiled matrix
   if (prec == 1) {
     // FP64 g first, then the FP32 correction -D S^{-1} f on top
@@ -364,7 +386,13 @@ hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec) {
   for (const HostClass& k : c.hcs) nb = std::max(nb, k.n_b);
   dim3 grid((nb + APPLY_ROWS - 1) / APPLY_ROWS, c.hm.n_macros);
   const size_t shm = (size_t)nb * sizeof(double);
-  if (c.cond_prec == 1) {  // FP32 condensation: the operator itself is FP32
+  if (c.hm.chunked()) {  // compact copy of every macro's A-hat
+    if (c.cond_prec == 1)
+      hipLaunchKernelGGL((k_apply_local<float, false>), grid, dim3(256), shm, c.stream, c.md,
+                         reinterpret_cast<const float*>(c.ws.Ac), x, c.ws.ypart);
+    else
+      hipLaunchKernelGGL((k_apply_local<double, false>), grid, dim3(256), shm, c.stream, c.md, c.ws.Ac, x, c.ws.ypart);
+  } else if (c.cond_prec == 1) {  // FP32 condensation: the operator itself is FP32
     hipLaunchKernelGGL((k_apply_local<float, true>), grid, dim3(256), shm, c.stream, c.md,
                        reinterpret_cast<const float*>(c.ws.Wm), x, c.ws.ypart);
   } else if (prec == 1 && c.have_a32) {
@@ -390,7 +418,7 @@ hipError_t launch_face_precond(HdgContext& c) {
     const int nf = g[0], s0 = g[1], cnt = g[2];
     e = lu_eliminate<double>(c.stream, c.ws.FW + (size_t)s0 * fs, cnt, fs, c.ldf, nf, 2 * nf, 2 * nf,
                              c.ws.fpiv + (size_t)s0 * c.nf_max, c.nf_max,
-                             reinterpret_cast<int*>(c.ws.small) + c.hm.n_classes, c.ws.Uinv);
+                             reinterpret_cast<int*>(c.ws.small) + c.hm.n_chunks() * c.hm.n_classes, c.ws.Uinv);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -400,6 +428,21 @@ hipError_t launch_precond_apply(HdgContext& c, const double* x, double* y) {
   const long long fs = c.fstride;
   hipLaunchKernelGGL(k_precond_apply, dim3(c.hm.n_faces), dim3(256), (size_t)c.nf_max * sizeof(double), c.stream, c.md,
                      c.ws.FW, fs, c.ldf, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract(HdgContext& c, int prec, int chunk) {
+  const int m0 = c.hm.chunk_first[chunk], nmc = c.hm.chunk_first[chunk + 1] - m0;
+  int nb = 0;
+  for (const HostClass& k : c.hcs) nb = std::max(nb, k.n_b);
+  const dim3 grid((unsigned)std::min(nb, 1024), (unsigned)nmc);
+  if (prec == 1)
+    hipLaunchKernelGGL(k_extract<float>, grid, dim3(256), 0, c.stream, c.md, m0,
+                       reinterpret_cast<const float*>(c.ws.Wm), reinterpret_cast<float*>(c.ws.Ac), c.ws.gloc,
+                       c.ws.bloc);
+  else
+    hipLaunchKernelGGL(k_extract<double>, grid, dim3(256), 0, c.stream, c.md, m0, c.ws.Wm, c.ws.Ac,
+                       static_cast<const double*>(nullptr), c.ws.bloc);
   return hipGetLastError();
 }
 

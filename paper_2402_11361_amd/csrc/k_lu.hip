@@ -677,18 +677,25 @@ static size_t class_scratch_doubles(int batch) {
   return (size_t)batch * (NB * NB + 4 * NB * NB + (2 * PERM_STRIDE + 1) / 2) + 64;
 }
 
-// One batched elimination per macro class (the matrices of a class are
-// stored consecutively); status flag k of the context belongs to class k.
-// With several classes they run concurrently on a few streams (fork from and
-// join back to the context's stream), each class with its own scratch slice.
-hipError_t launch_lu(HdgContext& c, int prec) {
-  int* status = reinterpret_cast<int*>(c.ws.small);
+// One batched elimination per macro class of chunk j (the chunk's matrices
+// of a class are stored consecutively); status flag j * n_classes + k
+// belongs to class k of chunk j.  With several classes they run
+// concurrently on a few streams (fork from and join back to the context's
+// stream), each class with its own scratch slice.  top_only: only the rows
+// of S are eliminated (U, L^{-1} P (-C) and L^{-1} P f for the recovery).
+hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only) {
   const int ncl = c.hm.n_classes;
-  const int nstreams = ncl > 1 ? std::min(ncl, 4) : 0;
+  int* status = reinterpret_cast<int*>(c.ws.small) + (size_t)chunk * ncl;
+  const int* cnt = &c.hm.chunk_class_cnt[(size_t)chunk * ncl];
+  int nact = 0;
+  for (int k = 0; k < ncl; ++k) nact += cnt[k] > 0;
+  const int nstreams = nact > 1 ? std::min(nact, 4) : 0;
   hipError_t e;
-  if (nstreams > 0 && c.lu_streams.empty()) {
-    c.lu_streams.resize(nstreams, nullptr);
-    c.lu_events.resize(nstreams + 1, nullptr);
+  if (nstreams > 0 && (int)c.lu_streams.size() < nstreams) {
+    for (auto s : c.lu_streams) (void)hipStreamDestroy(s);
+    for (auto ev : c.lu_events) (void)hipEventDestroy(ev);
+    c.lu_streams.assign(nstreams, nullptr);
+    c.lu_events.assign(nstreams + 1, nullptr);
     for (auto& s : c.lu_streams)
       if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return e;
     for (auto& ev : c.lu_events)
@@ -696,30 +703,32 @@ hipError_t launch_lu(HdgContext& c, int prec) {
   }
   if (nstreams > 0) {  // fork
     if ((e = hipEventRecord(c.lu_events[nstreams], c.stream)) != hipSuccess) return e;
-    for (auto s : c.lu_streams)
-      if ((e = hipStreamWaitEvent(s, c.lu_events[nstreams], 0)) != hipSuccess) return e;
+    for (int i = 0; i < nstreams; ++i)
+      if ((e = hipStreamWaitEvent(c.lu_streams[i], c.lu_events[nstreams], 0)) != hipSuccess) return e;
   }
   // largest classes first (their eliminations take longest)
-  std::vector<int> order(ncl);
-  for (int k = 0; k < ncl; ++k) order[k] = k;
+  std::vector<int> order;
+  for (int k = 0; k < ncl; ++k)
+    if (cnt[k] > 0) order.push_back(k);
   std::sort(order.begin(), order.end(), [&](int a, int b) {
-    return (double)c.hcs[a].n_u * c.hcs[a].n_u * c.hm.class_count[a] >
-           (double)c.hcs[b].n_u * c.hcs[b].n_u * c.hm.class_count[b];
+    return (double)c.hcs[a].n_u * c.hcs[a].n_u * cnt[a] > (double)c.hcs[b].n_u * c.hcs[b].n_u * cnt[b];
   });
   size_t scr = 0;
-  for (int i = 0; i < ncl; ++i) {
+  for (size_t i = 0; i < order.size(); ++i) {
     const int k = order[i];
     const HostClass& h = c.hcs[k];
-    int* ipiv = c.ws.ipiv + c.hm.class_ipiv_base[k];
-    const int batch = c.hm.class_count[k];
+    const size_t ck = (size_t)chunk * ncl + k;
+    int* ipiv = c.ws.ipiv + c.hm.class_ipiv_base[k] + (long long)c.hm.chunk_class_rank0[ck] * h.n_u;
+    const int batch = cnt[k];
+    const int n_rows = top_only ? h.n_u : h.n_rows;
     hipStream_t s = nstreams > 0 ? c.lu_streams[i % nstreams] : c.stream;
     double* scratch = c.ws.Uinv + scr;
     scr += class_scratch_doubles(batch);
     if (prec == 1)
-      e = lu_eliminate<float>(s, reinterpret_cast<float*>(c.ws.Wm) + c.hm.class_w_base[k], batch, h.wstride, h.ldw,
-                              h.n_u, h.n_rows, h.n_cols, ipiv, h.n_u, status + k, reinterpret_cast<float*>(scratch));
+      e = lu_eliminate<float>(s, reinterpret_cast<float*>(c.ws.Wm) + c.hm.chunk_class_w[ck], batch, h.wstride, h.ldw,
+                              h.n_u, n_rows, h.n_cols, ipiv, h.n_u, status + k, reinterpret_cast<float*>(scratch));
     else
-      e = lu_eliminate<double>(s, c.ws.Wm + c.hm.class_w_base[k], batch, h.wstride, h.ldw, h.n_u, h.n_rows, h.n_cols,
+      e = lu_eliminate<double>(s, c.ws.Wm + c.hm.chunk_class_w[ck], batch, h.wstride, h.ldw, h.n_u, n_rows, h.n_cols,
                                ipiv, h.n_u, status + k, scratch);
     if (e != hipSuccess) return e;
   }

@@ -67,7 +67,7 @@ EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_o
            "hdg_destroy", "hdg_status_string", "hdg_last_error", "hdg_get_condensed", "hdg_get_formed",
            "hdg_get_residuals", "hdg_precond_apply", "hdg_coarse_size", "hdg_coarse_restrict",
            "hdg_coarse_prolong", "hdg_mlp_param_count", "hdg_mlp_work_floats", "hdg_mlp_forward",
-           "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind"]
+           "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking"]
 
 _lib = None
 
@@ -87,6 +87,7 @@ def load_library(path=LIB_PATH):
     lib.hdg_face_offsets.argtypes = [vp, vp]
     lib.hdg_node_coords.argtypes = [vp, vp, vp]
     lib.hdg_bind_workspace.argtypes = [vp, vp, sz]
+    lib.hdg_set_chunking.argtypes = [vp, i]
     lib.hdg_linearize_stage.argtypes = [vp, vp, vp, vp, vp, dp, dp, dp, vp]
     lib.hdg_condense.argtypes = [vp, i, vp]
     lib.hdg_apply_global.argtypes = [vp, vp, vp]
@@ -174,6 +175,7 @@ class Context:
         self.n_u_tot, self.n_q_tot = s.n_u_tot, s.n_q_tot
         self.n_u_macro, self.n_b_macro = s.n_u_macro, s.n_b_macro
         self.workspace_bytes = s.workspace_bytes
+        self.chunk_macros = 0
         self.dim = dim
         self.ws = None
         # per-macro offsets in u (q: dim * u_off) and in the local trace vectors
@@ -192,6 +194,38 @@ class Context:
     @classmethod
     def from_mesh_spec(cls, spec, **kw):
         return cls(spec["dim"], spec["n_elem"], spec["lo"], spec["hi"], spec["periodic"], spec["seg_len"], spec["p"], **kw)
+
+    def set_chunking(self, macros_per_chunk):
+        """Condense in ranges of macros_per_chunk macros (0: all at once).
+        Re-plans the workspace; bind_workspace() must follow."""
+        self._check(self.lib.hdg_set_chunking(self.h, int(macros_per_chunk)))
+        self.ws = None
+        s = _Sizes()
+        self._check(self.lib.hdg_query_sizes(self.h, ctypes.byref(s)))
+        self.workspace_bytes = s.workspace_bytes
+        self.chunk_macros = int(macros_per_chunk)
+
+    def fit_chunking(self, budget_bytes):
+        """Largest macros per chunk (0 = no chunking) whose workspace fits in
+        budget_bytes; returns it after applying it."""
+        if self.workspace_bytes <= budget_bytes and self.chunk_macros == 0:
+            return 0
+        lo, hi = 1, self.n_macros
+        self.set_chunking(0)
+        if self.workspace_bytes <= budget_bytes:
+            return 0
+        best = None
+        while lo <= hi:
+            mid = (lo + hi) // 2
+            self.set_chunking(mid)
+            if self.workspace_bytes <= budget_bytes:
+                best, lo = mid, mid + 1
+            else:
+                hi = mid - 1
+        if best is None:
+            raise HdgError(2, f"workspace does not fit in {budget_bytes} bytes even with one macro per chunk")
+        self.set_chunking(best)
+        return best
 
     def bind_workspace(self, ws=None):
         """Allocate (torch) and bind the device workspace."""
