@@ -92,6 +92,17 @@ class System:
             np.add.at(RB, self.mesh.macro_trace_index(i), rb.reshape(-1))
         return RQ, RU, RB
 
+    def macro_residuals(self, q, u, uhat, w=None, dt=np.inf, dii=1.0, macros=()):
+        """Per-macro residual pieces {i: (R_Q^(i), R_U^(i), R_Uhat^(i))} of the
+        listed macros (R_Uhat^(i): this macro's side of its faces)."""
+        out = {}
+        for i in macros:
+            mc = self.cls(i)
+            qi, ui, bi, wi = self.local(i, q, u, uhat, w)
+            rq, ru, rb = macro_residual(mc, self.ph, qi[None], ui[None], bi[None], **self._kw(i, wi, dt, dii))
+            out[i] = (rq.reshape(-1), ru.reshape(-1), rb.reshape(-1))
+        return out
+
     # ---- linearisation --------------------------------------------------
     def linearize(self, q, u, uhat, w=None, dt=np.inf, dii=1.0, dtau=np.inf, macros=None):
         """Per-macro Jacobian blocks (eq. C312) and residuals.  Pseudo-time

@@ -80,7 +80,7 @@ __device__ __forceinline__ void argmax_update(T& bv, int& bi, T v, int i) {
   if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
 }
 
-template <class T, int RPT, int NT>
+template <class T, int RPT, int NT, int PWT = PW>
 __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int lcol0) {
   const int tid = threadIdx.x;
   const int mat = blockIdx.x;
@@ -90,18 +90,18 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
   __shared__ T s_bv[NT / 64];
   __shared__ int s_bi[NT / 64];
   __shared__ int s_prow;
-  __shared__ T s_urow[PW];
-  __shared__ T s_swap[2][PW];
-  __shared__ T s_U[PW * NB];
-  for (int c0 = j0; c0 < j0 + jb; c0 += PW) {
-    const int pw = min(PW, j0 + jb - c0);
+  __shared__ T s_urow[PWT];
+  __shared__ T s_swap[2][PWT];
+  __shared__ T s_U[PWT * NB];
+  for (int c0 = j0; c0 < j0 + jb; c0 += PWT) {
+    const int pw = min(PWT, j0 + jb - c0);
     // rows owned by this thread: c0 + tid + i * NT
-    T v[RPT][PW];
+    T v[RPT][PWT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = c0 + tid + i * NT;
 #pragma unroll
-      for (int cc = 0; cc < PW; ++cc) v[i][cc] = (r < n_piv && cc < pw) ? W[wtix(r, c0 + cc, ld)] : T(0);
+      for (int cc = 0; cc < PWT; ++cc) v[i][cc] = (r < n_piv && cc < pw) ? W[wtix(r, c0 + cc, ld)] : T(0);
     }
     for (int cc = 0; cc < pw; ++cc) {
       {
@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
         const int r = c0 + tid + i * NT;
         T vc = v[i][0];
 #pragma unroll
-        for (int k = 1; k < PW; ++k) vc = (k == cc) ? v[i][k] : vc;
+        for (int k = 1; k < PWT; ++k) vc = (k == cc) ? v[i][k] : vc;
         if (r >= col && r < n_piv) argmax_update<T>(bv, bi, fabs(vc), r);
       }
       for (int off = 32; off > 0; off >>= 1) {
@@ -145,11 +145,11 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
           const int rl = tid + i * NT;
           if (rl == oc) {
 #pragma unroll
-            for (int k = 0; k < PW; ++k) s_swap[0][k] = v[i][k];
+            for (int k = 0; k < PWT; ++k) s_swap[0][k] = v[i][k];
           }
           if (rl == op) {
 #pragma unroll
-            for (int k = 0; k < PW; ++k) s_swap[1][k] = v[i][k];
+            for (int k = 0; k < PWT; ++k) s_swap[1][k] = v[i][k];
           }
         }
         __syncthreads();
@@ -158,11 +158,11 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
           const int rl = tid + i * NT;
           if (rl == oc) {
 #pragma unroll
-            for (int k = 0; k < PW; ++k) v[i][k] = s_swap[1][k];
+            for (int k = 0; k < PWT; ++k) v[i][k] = s_swap[1][k];
           }
           if (rl == op) {
 #pragma unroll
-            for (int k = 0; k < PW; ++k) v[i][k] = s_swap[0][k];
+            for (int k = 0; k < PWT; ++k) v[i][k] = s_swap[0][k];
           }
         }
         // the rest of the block row (columns [j0, c0) and [c0 + pw, j0 + jb)) in memory
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
       for (int i = 0; i < RPT; ++i) {
         if (tid + i * NT == oc) {
 #pragma unroll
-          for (int k = 0; k < PW; ++k) s_urow[k] = v[i][k];
+          for (int k = 0; k < PWT; ++k) s_urow[k] = v[i][k];
         }
       }
       __syncthreads();
@@ -191,10 +191,10 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
         if (r > col && r < n_piv) {
           T vc = v[i][0];
 #pragma unroll
-          for (int k = 1; k < PW; ++k) vc = (k == cc) ? v[i][k] : vc;
+          for (int k = 1; k < PWT; ++k) vc = (k == cc) ? v[i][k] : vc;
           const T l = vc * ipv;
 #pragma unroll
-          for (int k = 0; k < PW; ++k) {
+          for (int k = 0; k < PWT; ++k) {
             if (k == cc) v[i][k] = l;
             if (k > cc) v[i][k] -= l * s_urow[k];
           }
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
       const int r = c0 + tid + i * NT;
       if (r < n_piv) {
 #pragma unroll
-        for (int cc = 0; cc < PW; ++cc)
+        for (int cc = 0; cc < PWT; ++cc)
           if (cc < pw) W[wtix(r, c0 + cc, ld)] = v[i][cc];
       }
     }
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
           for (int cidx = 0; cidx < nrest; ++cidx) {
             T s = W[wtix(r, rest0 + cidx, ld)];
 #pragma unroll
-            for (int m = 0; m < PW; ++m)
+            for (int m = 0; m < PWT; ++m)
               if (m < pw) s -= v[i][m] * s_U[m * NB + cidx];
             W[wtix(r, rest0 + cidx, ld)] = s;
           }
@@ -608,13 +608,15 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
   LuArgs<T> a{W, mat_stride, ld, n_piv, n_rows, n_cols, ipiv, ipiv_stride, status, perm};
   if (ld % NC != 0) return hipErrorInvalidValue;
   const int rpt = (n_piv + PANEL_THREADS - 1) / PANEL_THREADS;
-  // up to 2048 rows: 512 threads, 1..4 rows each; up to 4096: 1024 threads, 4 rows each
+  // up to 2048 rows: 512 threads, 1..4 rows each; up to 4096: 1024 threads, 4 rows each;
+  // up to 12288: 512 threads, 24 rows each of 4-column sub-panels (register budget)
   constexpr int TPW = 32;  // 16-row tiles per workgroup (8 per wave)
   auto panel = [&](int j0, int jb, int lcol0) {
     if (rpt <= 1) hipLaunchKernelGGL((k_panel<T, 1, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
     else if (rpt <= 2) hipLaunchKernelGGL((k_panel<T, 2, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
     else if (rpt <= 4) hipLaunchKernelGGL((k_panel<T, 4, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
-    else hipLaunchKernelGGL((k_panel<T, 4, 1024>), dim3(batch), dim3(1024), 0, s, a, j0, jb, lcol0);
+    else if (n_piv <= 4 * 1024) hipLaunchKernelGGL((k_panel<T, 4, 1024>), dim3(batch), dim3(1024), 0, s, a, j0, jb, lcol0);
+    else hipLaunchKernelGGL((k_panel<T, 24, 512, 4>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
   };
   auto drows = [&](int j0, int jb) {  // L of the non-pivot rows: A_D,block U11^{-1}
     if (n_rows <= n_piv) return;
@@ -633,7 +635,7 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
     if (K > NB) hipLaunchKernelGGL((k_gemm<T, 2 * NB>), grid, dim3(256), 0, s, g);
     else hipLaunchKernelGGL((k_gemm<T, NB>), grid, dim3(256), 0, s, g);
   };
-  if (n_piv > 4 * 1024) return hipErrorInvalidValue;
+  if (n_piv > 12 * 1024) return hipErrorInvalidValue;
   for (int j0 = 0; j0 < n_piv; j0 += 2 * NB) {
     const int jb1 = std::min(NB, n_piv - j0);
     panel(j0, jb1, j0);
