@@ -518,7 +518,7 @@ struct GemmArgs {
   int tiles_per_wg;
 };
 
-template <class T, int KB, int NT>
+template <class T, int KB, int NT, bool PIPE>
 __device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int KS = KB / 4;  // MFMA k-steps; lane group grp covers k in [KS grp, KS grp + KS)
@@ -560,21 +560,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
       }
     }
   };
-  T af[KS];
-  v4 acc[NC / 16];
-  for (int t = wave; t < g.tiles_per_wg; t += NT / 64) {
-    const int r0 = g.r_lo + (tile0 + t) * 16;
-    if (r0 >= g.r_hi) break;
-    load_a(r0, af);
-    load_c(r0, acc);
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-#pragma unroll
-      for (int ct = 0; ct < NC / 16; ++ct) {
-        const T bv = sB[(KS * grp + s) * NC + ct * 16 + col];
-        acc[ct] = Mfma<T>::op(af[s], bv, acc[ct]);
-      }
-    }
+  auto store_c = [&](int r0, const v4* acc) {
 #pragma unroll
     for (int ct = 0; ct < NC / 16; ++ct) {
       const int cc = cs + ct * 16 + col;
@@ -585,13 +571,52 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
         if (r < g.r_hi && cok) W[wtix(r, cc, ld)] = acc[ct][i];
       }
     }
+  };
+  auto mma = [&](const T* af, v4* acc) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+#pragma unroll
+      for (int ct = 0; ct < NC / 16; ++ct) {
+        const T bv = sB[(KS * grp + s) * NC + ct * 16 + col];
+        acc[ct] = Mfma<T>::op(af[s], bv, acc[ct]);
+      }
+    }
+  };
+  T af[KS];
+  v4 acc[NC / 16];
+  if constexpr (PIPE) {
+    // C is loaded after A and added after the MFMA chain, so its latency
+    // hides behind the chain (the chain starts from zero)
+    v4 cv[NC / 16];
+    for (int t = wave; t < g.tiles_per_wg; t += NT / 64) {
+      const int r0 = g.r_lo + (tile0 + t) * 16;
+      if (r0 >= g.r_hi) break;
+      load_a(r0, af);
+      load_c(r0, cv);
+#pragma unroll
+      for (int ct = 0; ct < NC / 16; ++ct) acc[ct] = v4{T(0), T(0), T(0), T(0)};
+      mma(af, acc);
+#pragma unroll
+      for (int ct = 0; ct < NC / 16; ++ct) acc[ct] += cv[ct];
+      store_c(r0, acc);
+    }
+  } else {
+    for (int t = wave; t < g.tiles_per_wg; t += NT / 64) {
+      const int r0 = g.r_lo + (tile0 + t) * 16;
+      if (r0 >= g.r_hi) break;
+      load_a(r0, af);
+      load_c(r0, acc);
+      mma(af, acc);
+      store_c(r0, acc);
+    }
   }
 }
 
 // Four waves (256 threads); at most two workgroups per CU for FP64 (LDS).
+// FP64: C joins after the MFMA chain (see gemm_body).
 template <class T, int KB>
 __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs<T> g) {
-  gemm_body<T, KB, 256>(g);
+  gemm_body<T, KB, 256, (sizeof(T) == 8)>(g);
 }
 
 }  // namespace
