@@ -16,37 +16,39 @@
 //   A_qq^{-1} A_q,uh = -(I (x) M^{-1} E_k), whose columns for the face (k, s)
 //                      are sign_s M_k^{-1}[:, end_s] along axis k times the
 //                      identity on the tangential node indices.
-// One workgroup builds one row; contributions are added element by element
-// (and direction by direction) into an LDS row buffer, in a fixed order.
+// One workgroup builds the NR rows of one group (NR = n_s: the rows of the
+// n_s components of one node, which share every target index; NR = 1 for
+// classes whose n_s rows do not fit in LDS); contributions are added element
+// by element (and direction by direction) into LDS row buffers, in a fixed
+// order.
 #include "context.h"
 
 namespace {
 
-constexpr int FORM_THREADS = 256;
 
 struct FormPtrs {
   const double *AUU, *AUQ, *SUB, *RU, *RQt, *RBloc;
   double* gloc;  // non-null: g goes here in FP64 and its W entries are 0
   int nsA, dnsA, sub_stride, off_AUB, off_ABU, off_ABQ, off_ABB;
-  long long row0;  // first row of the launch (rows of all macros numbered consecutively)
+  long long group0;  // first row group of the launch (groups of all macros numbered consecutively)
+  int coef_off;      // LDS offset (doubles) of the staged coefficient rows, after the row buffers
 };
 
 __device__ __forceinline__ void digits(int x, int base, int d, int* out) {
   for (int k = 0; k < d; ++k) { out[k] = x % base; x /= base; }
 }
 
-// Adds, for direction k, the contributions of one coefficient row
-// coef[(k, cp, b)] (element-local nodes b of element e) through
-//   line targets  row[cp*N + node(b with b_k -> n_k)] += sgn_line * sum_bk coef * C1D_k[e_k p + b_k][n_k]
-//   face targets  row[n_u + nf_off[2k+s] + cp*nf + j(b_tan)] += sgn_face * sign_s * sum_bk coef * Minv_k[e_k p + b_k][end_s]
-// mask(b) selects which element nodes carry coefficients (all for u-rows,
-// the face nodes of a sub-face for trace rows).
-template <class Coef>
+// Adds, for direction k, the contributions of NR coefficient rows
+// coef(rr, k, cp, b) (element-local nodes b of element e) through
+//   line targets  row_rr[cp*N + node(b with b_k -> n_k)] += sgn_line * sum_bk coef * C1D_k[e_k p + b_k][n_k]
+//   face targets  row_rr[n_u + nf_off[2k+s] + cp*nf + j(b_tan)] += sgn_face * sign_s * sum_bk coef * Minv_k[e_k p + b_k][end_s]
+// (row_rr = row + rr * ldr).  The coefficient functor returns 0 for element
+// nodes that carry none (trace rows use only the nodes of their sub-face).
+template <int NR, int NT, class Coef>
 __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, double sgn_line, double sgn_face,
-                              double* row, int tid) {
+                              double* row, int ldr, int tid) {
   const int d = cd.dim, p = cd.p, A1 = p + 1, ns = cd.ns;
   int eidx[3] = {0, 0, 0};
-  digits(e, 1, 0, eidx);
   {
     int t = e;
     for (int j = 0; j < d; ++j) { eidx[j] = t % cd.m[j]; t /= cd.m[j]; }
@@ -57,25 +59,30 @@ __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, doubl
   const double* Mk = cd.Minv1D + (size_t)k * nm * nm;
   int stride[3] = {1, cd.n1[0], cd.n1[0] * cd.n1[1]};
   // line targets
-  for (int i = tid; i < ns * T * nk; i += FORM_THREADS) {
+  for (int i = tid; i < ns * T * nk; i += NT) {
     const int cp = i / (T * nk), r = i % (T * nk), t = r / nk, n = r % nk;
     int td[2] = {0, 0};
     digits(t, A1, d - 1, td);
     int bd[3] = {0, 0, 0}, ti = 0;
     for (int j = 0; j < d; ++j) if (j != k) bd[j] = td[ti++];
-    double s = 0.0;
+    double s[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) s[rr] = 0.0;
     int node0 = 0;
     for (int j = 0; j < d; ++j) if (j != k) node0 += (eidx[j] * p + bd[j]) * stride[j];
     for (int bk = 0; bk < A1; ++bk) {
       bd[k] = bk;
       const int b = bd[0] + A1 * (bd[1] + A1 * bd[2]);
-      const double cv = coef(k, cp, b);
-      if (cv != 0.0) s += cv * Ck[(eidx[k] * p + bk) * nm + n];
+      const double ck = Ck[(eidx[k] * p + bk) * nm + n];
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr) s[rr] += coef(rr, k, cp, b) * ck;
     }
-    if (s != 0.0) row[cp * cd.N + node0 + n * stride[k]] += sgn_line * s;
+    const int col = cp * cd.N + node0 + n * stride[k];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += sgn_line * s[rr];
   }
   // face targets on the two macro faces normal to k
-  for (int i = tid; i < 2 * ns * T; i += FORM_THREADS) {
+  for (int i = tid; i < 2 * ns * T; i += NT) {
     const int sidx = i / (ns * T), r = i % (ns * T), cp = r / T, t = r % T;
     int td[2] = {0, 0};
     digits(t, A1, d - 1, td);
@@ -83,14 +90,16 @@ __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, doubl
     for (int j = 0; j < d; ++j) if (j != k) bd[j] = td[ti++];
     const int end = (sidx == 0) ? 0 : nk - 1;
     const double sgn = (sidx == 0) ? -1.0 : 1.0;
-    double s = 0.0;
+    double s[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) s[rr] = 0.0;
     for (int bk = 0; bk < A1; ++bk) {
       bd[k] = bk;
       const int b = bd[0] + A1 * (bd[1] + A1 * bd[2]);
-      const double cv = coef(k, cp, b);
-      if (cv != 0.0) s += cv * Mk[(eidx[k] * p + bk) * nm + end];
+      const double mk = Mk[(eidx[k] * p + bk) * nm + end];
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr) s[rr] += coef(rr, k, cp, b) * mk;
     }
-    if (s == 0.0) continue;
     // trace node id on face (k, sidx): tangential macro coordinates, lower axis fastest
     int j = 0, mul = 1;
     for (int a = 0; a < d; ++a) {
@@ -99,147 +108,240 @@ __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, doubl
       mul *= cd.n1[a];
     }
     const int lf = 2 * k + sidx;
-    row[cd.n_u + cd.nf_off[lf] + cp * cd.nf_nodes[lf] + j] += sgn_face * sgn * s;
+    const int col = cd.n_u + cd.nf_off[lf] + cp * cd.nf_nodes[lf] + j;
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += sgn_face * sgn * s[rr];
   }
 }
 
-// The row is accumulated in FP64 and stored as TW (double or float).
-// One workgroup per row of all macros' augmented matrices (row offsets
-// MeshDev::row_off; each macro takes the layout of its class).
-template <class TW>
-__global__ void __launch_bounds__(FORM_THREADS) k_form(MeshDev md, FormPtrs fp, TW* __restrict__ Wm) {
+// Sum over the workgroup of NR per-thread values (wave shuffles, then LDS).
+template <int NR, int NT>
+__device__ void block_sum(double* v, double* red, int tid) {
+#pragma unroll
+  for (int rr = 0; rr < NR; ++rr)
+    for (int off = 32; off > 0; off >>= 1) v[rr] += __shfl_xor(v[rr], off, 64);
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) red[rr * (NT / 64) + (tid >> 6)] = v[rr];
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < NR; ++rr) {
+    double t = 0.0;
+    for (int w = 0; w < NT / 64; ++w) t += red[rr * (NT / 64) + w];
+    v[rr] = t;
+  }
+}
+
+// The rows are accumulated in FP64 and stored as TW (double or float).
+// One workgroup per row group; NR = 1: group = one row (rows of all macros
+// numbered consecutively by MeshDev::row_off); NR = n_s: group = the n_s
+// component rows of one u-node or one trace node (row_off / n_s groups
+// before each macro).  Each macro takes the layout of its class.
+template <class TW, int NR, int NT>
+__global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __restrict__ Wm) {
   extern __shared__ double row[];
-  __shared__ double red[FORM_THREADS];
+  __shared__ double red[NR * (NT / 64)];
   const int tid = threadIdx.x;
-  const long long gr = fp.row0 + blockIdx.x;
-  const int macro = find_in(md.row_off, md.n_macros, gr);
-  const int r = (int)(gr - md.row_off[macro]);
+  const long long G = fp.group0 + blockIdx.x;
+  const int macro = find_in(md.row_off, md.n_macros, G * NR);
+  const int g = (int)(G - md.row_off[macro] / NR);
   const ClassDev& cd = class_of(md, macro);
   const int ns = cd.ns, d = cd.dim, A = cd.A, T = cd.T, N = cd.N;
   const int nsA = fp.nsA, dnsA = fp.dnsA;
-  const int n_cols = cd.n_cols;
-  for (int i = tid; i < n_cols; i += FORM_THREADS) row[i] = 0.0;
+  const int n_cols = cd.n_cols, ldr = n_cols;
+  double* sc = row + fp.coef_off;  // staged coefficient rows
+  for (int i = tid; i < NR * n_cols; i += NT) row[i] = 0.0;
+  // rows of the group: r_rr = r0 + rr * rstride
+  int r0, rstride;
+  bool urow;
+  int a = 0, c0 = 0, lf = 0, j = 0, nf = 0;
+  if (NR == 1) {
+    const int r = g;
+    urow = r < cd.n_u;
+    if (urow) {
+      c0 = r / N; a = r % N;
+    } else {
+      const int rho = r - cd.n_u;
+      while (lf + 1 < 2 * d && rho >= cd.nf_off[lf + 1]) ++lf;
+      nf = cd.nf_nodes[lf];
+      const int loc = rho - cd.nf_off[lf];
+      c0 = loc / nf; j = loc % nf;
+    }
+    r0 = r; rstride = 0;
+  } else {
+    urow = g < N;
+    if (urow) {
+      a = g; c0 = 0;
+      r0 = a; rstride = N;
+    } else {
+      int rho = g - N;  // trace node index over the local faces
+      while (lf + 1 < 2 * d && rho >= cd.nf_nodes[lf]) { rho -= cd.nf_nodes[lf]; ++lf; }
+      nf = cd.nf_nodes[lf];
+      j = rho; c0 = 0;
+      r0 = cd.n_u + cd.nf_off[lf] + j; rstride = nf;
+    }
+  }
   __syncthreads();
   const double* RQt = fp.RQt + (size_t)d * md.u_off[macro];
-  double fpart = 0.0;
-  if (r < cd.n_u) {
-    // ---- u-row (c, a) ----
-    const int c = r / N, a = r % N;
+  double fpart[NR];
+#pragma unroll
+  for (int rr = 0; rr < NR; ++rr) fpart[rr] = 0.0;
+  if (urow) {
+    // ---- u-rows (c0 + rr, a) ----
     const int cnt = cd.node_ne[a];
     for (int ie = 0; ie < cnt; ++ie) {
       const int e = cd.node_e[a * 8 + ie], ae = cd.node_a[a * 8 + ie];
       const long long el = md.el_off[macro] + e;
-      const double* auu = fp.AUU + ((size_t)el * nsA + (size_t)(c * A + ae)) * nsA;
-      const double* auq = fp.AUQ + ((size_t)el * nsA + (size_t)(c * A + ae)) * dnsA;
+      // row (c, ae) of the element blocks; component rows are A apart
+      const double* auu = fp.AUU + ((size_t)el * nsA + (size_t)(c0 * A + ae)) * nsA;
+      const double* auq = fp.AUQ + ((size_t)el * nsA + (size_t)(c0 * A + ae)) * dnsA;
+      const size_t su = (size_t)A * nsA, sq = (size_t)A * dnsA;
       const int* en = cd.elem_nodes + (size_t)e * A;
       __syncthreads();
-      for (int i = tid; i < nsA; i += FORM_THREADS) row[(i / A) * N + en[i % A]] += auu[i];
+      // the NR rows of A_uq^e, read by every line and face target, go to LDS
+      for (int i = tid; i < NR * dnsA; i += NT) sc[i] = auq[(i / dnsA) * sq + i % dnsA];
+      for (int i = tid; i < nsA; i += NT) {
+        const int col = (i / A) * N + en[i % A];
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += auu[rr * su + i];
+      }
+      __syncthreads();
       // f: A_uq A_qq^{-1} R_Q
-      for (int i = tid; i < dnsA; i += FORM_THREADS) {
+      for (int i = tid; i < dnsA; i += NT) {
         const int lc = i / A, b = i % A;
-        fpart += auq[i] * RQt[(size_t)lc * N + en[b]];
+        const double rq = RQt[(size_t)lc * N + en[b]];
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) fpart[rr] += sc[rr * dnsA + i] * rq;
       }
       for (int k = 0; k < d; ++k) {
-        __syncthreads();
-        auto coef = [&](int kk, int cp, int b) { return auq[(kk * ns + cp) * A + b]; };
-        add_direction(cd, e, k, coef, -1.0, 1.0, row, tid);
+        if (k > 0) __syncthreads();
+        auto coef = [&](int rr, int kk, int cp, int b) { return sc[rr * dnsA + (kk * ns + cp) * A + b]; };
+        add_direction<NR, NT>(cd, e, k, coef, -1.0, 1.0, row, ldr, tid);
       }
       // A_u,uh on the element's macro-boundary faces through node a
-      for (int lf = 0; lf < 2 * d; ++lf) {
-        const int sid = cd.elem_sub[(size_t)e * 2 * d + lf];
+      for (int lf2 = 0; lf2 < 2 * d; ++lf2) {
+        const int sid = cd.elem_sub[(size_t)e * 2 * d + lf2];
         if (sid < 0) continue;
-        const int ta = cd.finv[(size_t)lf * A + ae];
+        const int ta = cd.finv[(size_t)lf2 * A + ae];
         if (ta < 0) continue;
         __syncthreads();
         const double* aub = fp.SUB + ((size_t)md.sub_off[macro] + sid) * fp.sub_stride + fp.off_AUB;
         const int nst = ns * T;
-        const int nf = cd.nf_nodes[lf];
-        for (int i = tid; i < nst; i += FORM_THREADS) {
+        const int nf2 = cd.nf_nodes[lf2];
+        for (int i = tid; i < nst; i += NT) {
           const int cp = i / T, tp = i % T;
-          row[cd.n_u + cd.nf_off[lf] + cp * nf + cd.sub_tid[(size_t)sid * T + tp]] += aub[(size_t)(c * T + ta) * nst + i];
+          const int col = cd.n_u + cd.nf_off[lf2] + cp * nf2 + cd.sub_tid[(size_t)sid * T + tp];
+#pragma unroll
+          for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += aub[(size_t)((c0 + rr) * T + ta) * nst + i];
         }
       }
     }
-    red[tid] = fpart;
-    __syncthreads();
-    for (int w = FORM_THREADS / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    if (tid == 0) row[n_cols - 1] = red[0] - fp.RU[md.u_off[macro] + r];
+    block_sum<NR, NT>(fpart, red, tid);
+    if (tid == 0)
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr)
+        row[rr * ldr + n_cols - 1] = fpart[rr] - fp.RU[md.u_off[macro] + r0 + rr * rstride];
   } else {
-    // ---- trace row (lf, c, j) ----
-    const int rho = r - cd.n_u;
-    int lf = 0;
-    while (lf + 1 < 2 * d && rho >= cd.nf_off[lf + 1]) ++lf;
-    const int nf = cd.nf_nodes[lf];
-    const int loc = rho - cd.nf_off[lf], c = loc / nf, j = loc % nf;
+    // ---- trace rows (lf, c0 + rr, j) ----
     const int tj = cd.tn_base[lf] + j;
     const int nst = ns * T;
     for (int is = 0; is < cd.tn_cnt[tj]; ++is) {
       const int sid = cd.tn_sub[tj * 4 + is], t = cd.tn_t[tj * 4 + is];
       const int e = cd.sub_elem[sid];
       const double* SB = fp.SUB + ((size_t)md.sub_off[macro] + sid) * fp.sub_stride;
-      const double* abu = SB + fp.off_ABU + (size_t)(c * T + t) * nst;
-      const double* abb = SB + fp.off_ABB + (size_t)(c * T + t) * nst;
-      const double* abq = SB + fp.off_ABQ + (size_t)(c * T + t) * (d * nst);
+      const double* abu = SB + fp.off_ABU + (size_t)(c0 * T + t) * nst;
+      const double* abb = SB + fp.off_ABB + (size_t)(c0 * T + t) * nst;
+      const double* abq = SB + fp.off_ABQ + (size_t)(c0 * T + t) * (d * nst);
+      const size_t sb = (size_t)T * nst, sbq = (size_t)T * d * nst;  // next component row
       const int* en = cd.elem_nodes + (size_t)e * A;
       const int* fn = cd.fnode + lf * T;
       const int* finv = cd.finv + (size_t)lf * A;
       __syncthreads();
-      for (int i = tid; i < nst; i += FORM_THREADS) {
+      const int dnst = d * nst;
+      for (int i = tid; i < NR * dnst; i += NT) sc[i] = abq[(i / dnst) * sbq + i % dnst];
+      for (int i = tid; i < nst; i += NT) {
         const int cp = i / T, tp = i % T;
-        row[cp * N + en[fn[tp]]] += abu[i];
-        row[cd.n_u + cd.nf_off[lf] + cp * nf + cd.sub_tid[(size_t)sid * T + tp]] += abb[i];
+        const int cu = cp * N + en[fn[tp]];
+        const int cb = cd.n_u + cd.nf_off[lf] + cp * nf + cd.sub_tid[(size_t)sid * T + tp];
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) {
+          row[rr * ldr + cu] += abu[rr * sb + i];
+          row[rr * ldr + cb] += abb[rr * sb + i];
+        }
       }
-      for (int i = tid; i < d * nst; i += FORM_THREADS) {
+      __syncthreads();
+      for (int i = tid; i < d * nst; i += NT) {
         const int lc = i / T, tp = i % T;
-        fpart += abq[i] * RQt[(size_t)lc * N + en[fn[tp]]];
+        const double rq = RQt[(size_t)lc * N + en[fn[tp]]];
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) fpart[rr] += sc[rr * dnst + i] * rq;
       }
       for (int k = 0; k < d; ++k) {
-        __syncthreads();
-        auto coef = [&](int kk, int cp, int b) {
+        if (k > 0) __syncthreads();
+        auto coef = [&](int rr, int kk, int cp, int b) {
           const int tb = finv[b];
-          return tb < 0 ? 0.0 : abq[(kk * ns + cp) * T + tb];
+          return tb < 0 ? 0.0 : sc[rr * dnst + (kk * ns + cp) * T + tb];
         };
-        add_direction(cd, e, k, coef, -1.0, 1.0, row, tid);
+        add_direction<NR, NT>(cd, e, k, coef, -1.0, 1.0, row, ldr, tid);
       }
     }
-    red[tid] = fpart;
-    __syncthreads();
-    for (int w = FORM_THREADS / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
+    block_sum<NR, NT>(fpart, red, tid);
     if (tid == 0) {
-      const double g = red[0] - fp.RBloc[md.b_off[macro] + rho];
-      if (fp.gloc) {
-        fp.gloc[md.b_off[macro] + rho] = g;
-        row[n_cols - 1] = 0.0;
-      } else {
-        row[n_cols - 1] = g;
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr) {
+        const int rho = r0 + rr * rstride - cd.n_u;
+        const double gv = fpart[rr] - fp.RBloc[md.b_off[macro] + rho];
+        if (fp.gloc) {
+          fp.gloc[md.b_off[macro] + rho] = gv;
+          row[rr * ldr + n_cols - 1] = 0.0;
+        } else {
+          row[rr * ldr + n_cols - 1] = gv;
+        }
       }
     }
   }
   __syncthreads();
   TW* Wmac = Wm + md.w_off[macro];
-  for (int i = tid; i < cd.ldw; i += FORM_THREADS) Wmac[wtix(r, i, cd.ldw)] = (i < n_cols) ? (TW)row[i] : TW(0);
+  for (int i = tid; i < NR * cd.ldw; i += NT) {
+    const int rr = i / cd.ldw, cidx = i % cd.ldw;
+    Wmac[wtix(r0 + rr * rstride, cidx, cd.ldw)] = (cidx < n_cols) ? (TW)row[rr * ldr + cidx] : TW(0);
+  }
+}
+
+// Row buffers of the largest class and its staged coefficient rows
+// (A_uq^e rows: d n_s A values; trace rows use d n_s T <= that).
+size_t form_lds_bytes(const HdgContext& c, int nr) {
+  return sizeof(double) * (size_t)nr * ((size_t)c.n_cols + (size_t)c.dnsA);
+}
+
+template <class TW, int NR, int NT>
+hipError_t form_launch(HdgContext& c, int m0, int m1, TW* W, double* gloc) {
+  FormPtrs fp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.ws.RQt, c.ws.RBloc, gloc,
+              c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.hm.row_off[m0] / NR,
+              NR * c.n_cols};
+  const long long nblk = (c.hm.row_off[m1] - c.hm.row_off[m0]) / NR;
+  if (nblk <= 0) return hipSuccess;
+  const size_t shm = form_lds_bytes(c, NR);
+  hipLaunchKernelGGL((k_form<TW, NR, NT>), dim3((unsigned)nblk), dim3(NT), shm, c.stream, c.md, fp, W);
+  return hipGetLastError();
 }
 
 }  // namespace
 
+// Groups of n_s rows when their row buffers fit in LDS (every row of a
+// group shares its target indices; one such workgroup per CU, so 512
+// threads), single rows of 256 threads otherwise.
 hipError_t launch_form(HdgContext& c, int prec, int m0, int m1) {
   // FP32 storage: g of the trace rows stays in FP64 (it is O(1) per macro but
   // cancels between the two sides of a face in the assembled b-hat)
-  FormPtrs fp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.ws.RQt, c.ws.RBloc, prec == 1 ? c.ws.gloc : nullptr,
-              c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.hm.row_off[m0]};
-  const long long nblk = c.hm.row_off[m1] - c.hm.row_off[m0];
-  if (nblk <= 0) return hipSuccess;
-  const size_t shm = (size_t)c.n_cols * sizeof(double);  // largest class
-  if (prec == 1)
-    hipLaunchKernelGGL(k_form<float>, dim3((unsigned)nblk), dim3(FORM_THREADS), shm, c.stream, c.md, fp,
-                       reinterpret_cast<float*>(c.ws.Wm));
-  else
-    hipLaunchKernelGGL(k_form<double>, dim3((unsigned)nblk), dim3(FORM_THREADS), shm, c.stream, c.md, fp, c.ws.Wm);
-  return hipGetLastError();
+  double* gloc = prec == 1 ? c.ws.gloc : nullptr;
+  const int ns = c.hm.ns;
+  const bool grouped = form_lds_bytes(c, ns) <= 150 * 1024;
+  if (prec == 1) {
+    float* W = reinterpret_cast<float*>(c.ws.Wm);
+    if (!grouped) return form_launch<float, 1, 256>(c, m0, m1, W, gloc);
+    return ns == 5 ? form_launch<float, 5, 512>(c, m0, m1, W, gloc) : form_launch<float, 4, 512>(c, m0, m1, W, gloc);
+  }
+  if (!grouped) return form_launch<double, 1, 256>(c, m0, m1, c.ws.Wm, gloc);
+  return ns == 5 ? form_launch<double, 5, 512>(c, m0, m1, c.ws.Wm, gloc) : form_launch<double, 4, 512>(c, m0, m1, c.ws.Wm, gloc);
 }

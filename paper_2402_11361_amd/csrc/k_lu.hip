@@ -613,10 +613,10 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
 }
 
 // Four waves (256 threads); at most two workgroups per CU for FP64 (LDS).
-// FP64: C joins after the MFMA chain (see gemm_body).
+// C joins after the MFMA chain (see gemm_body).
 template <class T, int KB>
 __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs<T> g) {
-  gemm_body<T, KB, 256, (sizeof(T) == 8)>(g);
+  gemm_body<T, KB, 256, true>(g);
 }
 
 }  // namespace
