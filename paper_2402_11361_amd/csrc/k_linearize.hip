@@ -174,6 +174,9 @@ k_lin_elem(ClassDev ce, MeshDev md, PhysDev ph, StageArgs sa, const double* __re
           s_K[r * KCHUNK + kk] = Ke[(size_t)(pass * NS * NS + r) * KC + k0 + kk];
         }
         __syncthreads();
+        // unrolled so that the Tvol loads of several k are in flight at once
+        // (one wave per SIMD leaves nothing else to hide their latency)
+#pragma unroll 4
         for (int kk = 0; kk < kn; ++kk) {
           double t[CPT];
 #pragma unroll
