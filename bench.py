@@ -104,6 +104,12 @@ def uneven_variant(args, dev_fn, variants):
         e.record(stream)
         return e
 
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        ctx.linearize_stage(q_i, u_i, uh_i, w, dt, dii, norms=False)
+        for prec in (HDG_FP64, HDG_FP32):
+            ctx.autotune(prec, args.tune_cache)
+        out["autotune_seconds"] = round(time.perf_counter() - t0, 2)
     for name, prec in (("plain_fp64", HDG_FP64), ("mixed_fp32", HDG_FP32)):
         marks = []
         drv = StageDriver(ctx, rtol=cfg["rtol"], condense_prec=prec, mark=lambda ph: marks.append((ph, ev())))
@@ -221,6 +227,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction variant")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-macro 32^3 variant")
     ap.add_argument("--graph-steps", type=int, default=10, help="FGMRES steps per captured HIP graph")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default elimination launch shapes")
+    ap.add_argument("--tune-cache", default=None, help="text file of earlier autotuner choices (read and appended)")
     ap.add_argument("--train-seeds", type=int, default=2)
     ap.add_argument("--train-vectors", type=int, default=40)
     ap.add_argument("--train-epochs", type=int, default=60)
@@ -253,6 +261,17 @@ def main():
         e = torch.cuda.Event(enable_timing=True)
         e.record(stream)
         return e
+
+    # elimination launch shapes per macro class from the autotuner, timed on
+    # the linearisation at the initial state (outside the timed region)
+    tuning = {}
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        ctx.linearize_stage(q_init, u_init, uh_init, w, dt, dii, norms=False)
+        for name, prec in (("fp64", HDG_FP64), ("fp32", HDG_FP32)):
+            ctx.autotune(prec, args.tune_cache)
+            tuning[name] = [list(ctx.tuning(k, prec)) for k in range(ctx.class_count())]
+        tuning["seconds"] = round(time.perf_counter() - t0, 2)
 
     # plain copy of 1 GiB: the reference for scaling HBM byte counters
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").uniform_()
@@ -386,7 +405,7 @@ def main():
                condense_tflops=round(cond_tflops, 3), condense_ms=round(cond_ms, 3),
                apply_ms=round(apply_ms, 4), apply_gbs=round(apply_gbs, 1),
                apply_frac_hbm=round(apply_gbs / PEAK_HBM_GBS, 4), copy_gbs=round(copy_gbs, 1),
-               roofline=roofline, variants=variants)
+               roofline=roofline, variants=variants, autotune=tuning)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, newton_its)
     if not args.plain_only and not args.no_uneven:

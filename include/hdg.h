@@ -177,6 +177,30 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes);
  * of chunks times the number of macro classes exceeds 4095. */
 hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk);
 
+/* Autotuner of the batched elimination of hdg_condense: for every macro
+ * class (one per macro shape) and the given condensation precision, times
+ * the class's elimination (HIP events on the context's stream, after one
+ * untimed trial) for each candidate launch shape -- 8, 16, 32 or 64
+ * sixteen-row tiles per workgroup of the trailing update with the 512-thread
+ * panel factorisation, then the 1024-thread panel with the best of those --
+ * on the current linearisation, and keeps the fastest.
+ * cache_path (host string, may be NULL): text file of earlier choices, one
+ * line per (GPU architecture, HIP runtime version, precision, class shape,
+ * batch size); classes found there are not timed, new choices are appended.
+ * n_timed (host, may be NULL) receives the number of classes timed.
+ * Needs a bound workspace and a prior hdg_linearize_stage; the trials
+ * overwrite the condensed blocks, so hdg_condense must follow.  The choices
+ * change launch shapes only, not results beyond rounding order. */
+hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int* n_timed);
+
+/* Number of macro classes (distinct macro shapes) of the mesh. */
+hdg_status hdg_class_count(hdg_ctx ctx, int* n_classes);
+
+/* Launch shape in use for class macro_class (0 .. n_classes - 1) and the
+ * given precision: tiles per workgroup of the trailing update (default 32)
+ * and the wide-panel flag (default 0). */
+hdg_status hdg_get_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int* tpw, int* panel_wide);
+
 /* Linearise eq. (C242) at (q, u, uhat): residuals R_Q, R_U, R_Uhat and the
  * Jacobian blocks of eq. (C312) of every macro, kept in the workspace.
  * w: stage history with the discrete time derivative (d_ii u + w) / dt

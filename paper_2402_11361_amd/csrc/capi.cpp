@@ -14,7 +14,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
+#include <sstream>
 
 hipError_t launch_face_sum(HdgContext& c, const double* base, double* out);
 hipError_t launch_zero_ints(hipStream_t s, int* p, int n);
@@ -437,6 +440,129 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
   c.ws.bytes = bytes;
   c.ws_bound = true;
   c.have_a32 = false;
+  c.linearized = false;
+  return HDG_OK;
+}
+
+hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int* n_timed) {
+  if (!ctx) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  if (!c.linearized) return fail(&c, HDG_EINVAL, "autotune needs a linearisation (hdg_linearize_stage) first");
+  if (prec != HDG_FP64 && prec != HDG_FP32) return fail(&c, HDG_EUNSUPPORTED, "condensation precision not built");
+  const int p32 = prec == HDG_FP32 ? 1 : 0;
+  int dev = 0, rt = 0;
+  HIPCHK(&c, hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(&c, hipGetDeviceProperties(&prop, dev));
+  HIPCHK(&c, hipRuntimeGetVersion(&rt));
+  std::string arch(prop.gcnArchName);
+  arch = arch.substr(0, arch.find(':'));
+  // cache: one line per (arch, runtime, precision, class shape, batch):
+  //   key fields ... tpw panel_wide ms
+  std::map<std::string, LuTune> cache;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string a, pr;
+      int r, d, m0, m1, m2, p, batch, tpw, wide;
+      double ms;
+      if (ls >> a >> r >> pr >> d >> m0 >> m1 >> m2 >> p >> batch >> tpw >> wide >> ms) {
+        std::ostringstream key;
+        key << a << ' ' << r << ' ' << pr << ' ' << d << ' ' << m0 << ' ' << m1 << ' ' << m2 << ' ' << p << ' ' << batch;
+        LuTune t;
+        t.tpw = tpw;
+        t.panel_wide = wide;
+        if (tpw >= 4 && tpw % 4 == 0) cache[key.str()] = t;
+      }
+    }
+  }
+  const int ncl = c.hm.n_classes, nch = c.hm.n_chunks();
+  int* status = reinterpret_cast<int*>(c.ws.small);
+  hipEvent_t ev0, ev1;
+  HIPCHK(&c, hipEventCreate(&ev0));
+  HIPCHK(&c, hipEventCreate(&ev1));
+  std::vector<std::string> fresh;
+  int timed = 0;
+  hdg_status st = HDG_OK;
+  for (int k = 0; k < ncl && st == HDG_OK; ++k) {
+    HostClass& h = c.hcs[k];
+    int jbest = 0;  // the chunk holding most macros of the class
+    for (int j = 1; j < nch; ++j)
+      if (c.hm.chunk_class_cnt[(size_t)j * ncl + k] > c.hm.chunk_class_cnt[(size_t)jbest * ncl + k]) jbest = j;
+    const int batch = c.hm.chunk_class_cnt[(size_t)jbest * ncl + k];
+    std::ostringstream key;
+    key << arch << ' ' << rt << ' ' << (p32 ? "fp32" : "fp64") << ' ' << h.dim << ' ' << h.m[0] << ' ' << h.m[1] << ' '
+        << h.m[2] << ' ' << h.p << ' ' << batch;
+    auto it = cache.find(key.str());
+    if (it != cache.end()) {
+      h.tune[p32] = it->second;
+      continue;
+    }
+    // tiles per workgroup 8..64 with the default panel, then the wide panel
+    // with the best of those; one untimed trial first (code loading)
+    float best = 1e30f;
+    LuTune pick;
+    const int cand[6][2] = {{32, 0}, {8, 0}, {16, 0}, {32, 0}, {64, 0}, {-1, 1}};
+    for (int ci = 0; ci < 6 && st == HDG_OK; ++ci) {
+      {
+        LuTune t;
+        t.tpw = cand[ci][0] > 0 ? cand[ci][0] : pick.tpw;
+        t.panel_wide = cand[ci][1];
+        h.tune[p32] = t;
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 1 && st == HDG_OK; ++rep) {
+          hipError_t e = launch_zero_ints(c.stream, status, nch * ncl + 1);
+          if (e == hipSuccess) e = launch_form(c, p32, c.hm.chunk_first[jbest], c.hm.chunk_first[jbest + 1], k);
+          if (e == hipSuccess) e = hipEventRecord(ev0, c.stream);
+          if (e == hipSuccess) e = launch_lu(c, p32, jbest, false, k);
+          if (e == hipSuccess) e = hipEventRecord(ev1, c.stream);
+          if (e == hipSuccess) e = hipEventSynchronize(ev1);
+          float ms = 0.0f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+          if (e != hipSuccess) {
+            st = fail(&c, HDG_EDEVICE, hipGetErrorString(e));
+            break;
+          }
+          tmin = std::min(tmin, ms);
+        }
+        if (ci > 0 && tmin < best) { best = tmin; pick = t; }
+      }
+    }
+    h.tune[p32] = pick;
+    ++timed;
+    std::ostringstream line;
+    line << key.str() << ' ' << pick.tpw << ' ' << pick.panel_wide << ' ' << best;
+    fresh.push_back(line.str());
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  if (st != HDG_OK) return st;
+  if (cache_path && !fresh.empty()) {
+    std::ofstream out(cache_path, std::ios::app);
+    for (const std::string& l : fresh) out << l << '\n';
+    if (!out) return fail(&c, HDG_EINVAL, std::string("cannot write the tuning cache ") + cache_path);
+  }
+  if (n_timed) *n_timed = timed;
+  // the trials overwrote the condensed matrices
+  c.have_a32 = false;
+  return HDG_OK;
+}
+
+hdg_status hdg_class_count(hdg_ctx ctx, int* n_classes) {
+  if (!ctx || !n_classes) return HDG_EINVAL;
+  *n_classes = ctx->c.hm.n_classes;
+  return HDG_OK;
+}
+
+hdg_status hdg_get_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int* tpw, int* panel_wide) {
+  if (!ctx || macro_class < 0 || macro_class >= ctx->c.hm.n_classes || (prec != HDG_FP64 && prec != HDG_FP32))
+    return HDG_EINVAL;
+  const LuTune& t = ctx->c.hcs[macro_class].tune[prec == HDG_FP32 ? 1 : 0];
+  if (tpw) *tpw = t.tpw;
+  if (panel_wide) *panel_wide = t.panel_wide;
   return HDG_OK;
 }
 
@@ -448,6 +574,7 @@ hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, co
   if (!(dt > 0) || !(dtau > 0) || std::isnan(d_ii)) return fail(&c, HDG_EINVAL, "dt and dtau must be positive");
   StageArgs sa{dt, d_ii, dtau};
   HIPCHK(&c, launch_linearize(c, q, u, uhat, w, sa));
+  c.linearized = true;
   c.have_a32 = false;
   if (norms_host) {
     HIPCHK(&c, launch_norms(c, c.ws.small + 2048));

@@ -18,6 +18,7 @@ struct HostClass {
   // tiled augmented matrix
   int ldw = 0, n_rows = 0, n_cols = 0;
   long long wstride = 0;
+  LuTune tune[2];  // elimination launch choices for FP64 and FP32 storage
   std::vector<int> fnode, finv, elem_nodes, elem_sub, sub_elem, sub_lf, sub_tid, node_ne, node_e, node_a,
       tn_cnt, tn_sub, tn_t, tn_base;
 };
@@ -115,6 +116,7 @@ struct HdgContext {
   // offsets of the sub-face block pieces
   int off_AUB = 0, off_ABU = 0, off_ABQ = 0, off_ABB = 0, off_RB = 0;
   bool have_a32 = false;
+  bool linearized = false;  // element blocks hold a linearisation
   int cond_prec = 0;
   long long supg_chunk = 0;  // elements per SUPG product batch
   // learned coarse correction

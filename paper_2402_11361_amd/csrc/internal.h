@@ -121,6 +121,15 @@ __host__ __device__ __forceinline__ size_t wtix(long long r, long long c, long l
   return ((size_t)(r >> 4) * (size_t)(ld >> 6) + (size_t)(c >> 6)) * 1024 + (size_t)(r & 15) * 64 + (size_t)(c & 63);
 }
 
+// Launch choices of the batched elimination, picked per macro class and
+// precision by hdg_autotune: tpw = 16-row tiles per workgroup of the
+// trailing update (4 waves), panel_wide = 1024-thread panel factorisation
+// (fewer rows per thread) where 512 threads would also do.
+struct LuTune {
+  int tpw = 32;
+  int panel_wide = 0;
+};
+
 // ---- kernel launchers (defined in the .hip files) ----------------------
 struct Workspace;
 struct HdgContext;
@@ -130,8 +139,8 @@ hipError_t launch_linearize(HdgContext& c, const double* q, const double* u, con
 // prec: 0 FP64, 1 FP32 element type of the augmented matrices
 // formation and elimination of the macros [m0, m1) = chunk j (rows of the
 // trace block skipped in the elimination when top_only)
-hipError_t launch_form(HdgContext& c, int prec, int m0, int m1);
-hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only);
+hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class = -1);
+hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only_class = -1);
 // chunked condensation: A-hat^{T_i} and b-hat^{T_i} of chunk j out of W
 hipError_t launch_extract(HdgContext& c, int prec, int chunk);
 hipError_t launch_bhat(HdgContext& c, double* bhat, int prec);

@@ -32,6 +32,7 @@ struct FormPtrs {
   int nsA, dnsA, sub_stride, off_AUB, off_ABU, off_ABQ, off_ABB;
   long long group0;  // first row group of the launch (groups of all macros numbered consecutively)
   int coef_off;      // LDS offset (doubles) of the staged coefficient rows, after the row buffers
+  int only_class;    // >= 0: rows of other macro classes are skipped
 };
 
 __device__ __forceinline__ void digits(int x, int base, int d, int* out) {
@@ -145,6 +146,7 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
   const long long G = fp.group0 + blockIdx.x;
   const int macro = find_in(md.row_off, md.n_macros, G * NR);
   const int g = (int)(G - md.row_off[macro] / NR);
+  if (fp.only_class >= 0 && md.macro_class[macro] != fp.only_class) return;
   const ClassDev& cd = class_of(md, macro);
   const int ns = cd.ns, d = cd.dim, A = cd.A, T = cd.T, N = cd.N;
   const int nsA = fp.nsA, dnsA = fp.dnsA;
@@ -315,10 +317,10 @@ size_t form_lds_bytes(const HdgContext& c, int nr) {
 }
 
 template <class TW, int NR, int NT>
-hipError_t form_launch(HdgContext& c, int m0, int m1, TW* W, double* gloc) {
+hipError_t form_launch(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only_class) {
   FormPtrs fp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.ws.RQt, c.ws.RBloc, gloc,
               c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.hm.row_off[m0] / NR,
-              NR * c.n_cols};
+              NR * c.n_cols, only_class};
   const long long nblk = (c.hm.row_off[m1] - c.hm.row_off[m0]) / NR;
   if (nblk <= 0) return hipSuccess;
   const size_t shm = form_lds_bytes(c, NR);
@@ -331,7 +333,7 @@ hipError_t form_launch(HdgContext& c, int m0, int m1, TW* W, double* gloc) {
 // Groups of n_s rows when their row buffers fit in LDS (every row of a
 // group shares its target indices; one such workgroup per CU, so 512
 // threads), single rows of 256 threads otherwise.
-hipError_t launch_form(HdgContext& c, int prec, int m0, int m1) {
+hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class) {
   // FP32 storage: g of the trace rows stays in FP64 (it is O(1) per macro but
   // cancels between the two sides of a face in the assembled b-hat)
   double* gloc = prec == 1 ? c.ws.gloc : nullptr;
@@ -339,9 +341,9 @@ hipError_t launch_form(HdgContext& c, int prec, int m0, int m1) {
   const bool grouped = form_lds_bytes(c, ns) <= 150 * 1024;
   if (prec == 1) {
     float* W = reinterpret_cast<float*>(c.ws.Wm);
-    if (!grouped) return form_launch<float, 1, 256>(c, m0, m1, W, gloc);
-    return ns == 5 ? form_launch<float, 5, 512>(c, m0, m1, W, gloc) : form_launch<float, 4, 512>(c, m0, m1, W, gloc);
+    if (!grouped) return form_launch<float, 1, 256>(c, m0, m1, W, gloc, only_class);
+    return ns == 5 ? form_launch<float, 5, 512>(c, m0, m1, W, gloc, only_class) : form_launch<float, 4, 512>(c, m0, m1, W, gloc, only_class);
   }
-  if (!grouped) return form_launch<double, 1, 256>(c, m0, m1, c.ws.Wm, gloc);
-  return ns == 5 ? form_launch<double, 5, 512>(c, m0, m1, c.ws.Wm, gloc) : form_launch<double, 4, 512>(c, m0, m1, c.ws.Wm, gloc);
+  if (!grouped) return form_launch<double, 1, 256>(c, m0, m1, c.ws.Wm, gloc, only_class);
+  return ns == 5 ? form_launch<double, 5, 512>(c, m0, m1, c.ws.Wm, gloc, only_class) : form_launch<double, 4, 512>(c, m0, m1, c.ws.Wm, gloc, only_class);
 }

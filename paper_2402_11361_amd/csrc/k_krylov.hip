@@ -405,7 +405,7 @@ hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec) {
 
 template <class T>
 hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
-                        int n_cols, int* ipiv, int ipiv_stride, int* status, T* scratch);
+                        int n_cols, int* ipiv, int ipiv_stride, int* status, T* scratch, LuTune tune);
 
 hipError_t launch_face_precond(HdgContext& c) {
   const long long fs = c.fstride;
@@ -418,7 +418,8 @@ hipError_t launch_face_precond(HdgContext& c) {
     const int nf = g[0], s0 = g[1], cnt = g[2];
     e = lu_eliminate<double>(c.stream, c.ws.FW + (size_t)s0 * fs, cnt, fs, c.ldf, nf, 2 * nf, 2 * nf,
                              c.ws.fpiv + (size_t)s0 * c.nf_max, c.nf_max,
-                             reinterpret_cast<int*>(c.ws.small) + c.hm.n_chunks() * c.hm.n_classes, c.ws.Uinv);
+                             reinterpret_cast<int*>(c.ws.small) + c.hm.n_chunks() * c.hm.n_classes, c.ws.Uinv,
+                             LuTune{});
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -626,7 +626,7 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs<T> g) {
 // then (256-byte aligned) batch 128 x 128 unit-lower block inverses (type T).
 template <class T>
 hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
-                        int n_cols, int* ipiv, int ipiv_stride, int* status, T* scratch) {
+                        int n_cols, int* ipiv, int ipiv_stride, int* status, T* scratch, LuTune tune) {
   int* perm = reinterpret_cast<int*>(scratch + (size_t)batch * NB * NB);
   T* Linv = reinterpret_cast<T*>(
       (reinterpret_cast<uintptr_t>(perm + (size_t)batch * 2 * PERM_STRIDE) + 255) & ~uintptr_t(255));
@@ -635,9 +635,14 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
   const int rpt = (n_piv + PANEL_THREADS - 1) / PANEL_THREADS;
   // up to 2048 rows: 512 threads, 1..4 rows each; up to 4096: 1024 threads, 4 rows each;
   // up to 12288: 512 threads, 24 rows each of 4-column sub-panels (register budget)
-  constexpr int TPW = 32;  // 16-row tiles per workgroup (8 per wave)
+  const int TPW = tune.tpw;  // 16-row tiles per workgroup (TPW / 4 per wave)
+  if (TPW < 4 || TPW % 4) return hipErrorInvalidValue;
   auto panel = [&](int j0, int jb, int lcol0) {
-    if (rpt <= 1) hipLaunchKernelGGL((k_panel<T, 1, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
+    if (tune.panel_wide && rpt <= 1)
+      hipLaunchKernelGGL((k_panel<T, 1, 1024>), dim3(batch), dim3(1024), 0, s, a, j0, jb, lcol0);
+    else if (tune.panel_wide && rpt <= 4)
+      hipLaunchKernelGGL((k_panel<T, 2, 1024>), dim3(batch), dim3(1024), 0, s, a, j0, jb, lcol0);
+    else if (rpt <= 1) hipLaunchKernelGGL((k_panel<T, 1, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
     else if (rpt <= 2) hipLaunchKernelGGL((k_panel<T, 2, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
     else if (rpt <= 4) hipLaunchKernelGGL((k_panel<T, 4, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
     else if (n_piv <= 4 * 1024) hipLaunchKernelGGL((k_panel<T, 4, 1024>), dim3(batch), dim3(1024), 0, s, a, j0, jb, lcol0);
@@ -694,9 +699,9 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
 }
 
 template hipError_t lu_eliminate<double>(hipStream_t, double*, int, long long, int, int, int, int, int*, int, int*,
-                                         double*);
+                                         double*, LuTune);
 template hipError_t lu_eliminate<float>(hipStream_t, float*, int, long long, int, int, int, int, int*, int, int*,
-                                        float*);
+                                        float*, LuTune);
 
 // Elimination scratch of one class: Uinv, permutations and Linv for `batch`
 // matrices, in doubles (with room for the 256-byte alignment of Linv).
@@ -710,7 +715,8 @@ static size_t class_scratch_doubles(int batch) {
 // concurrently on a few streams (fork from and join back to the context's
 // stream), each class with its own scratch slice.  top_only: only the rows
 // of S are eliminated (U, L^{-1} P (-C) and L^{-1} P f for the recovery).
-hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only) {
+// only_class >= 0: that class alone (timing by the autotuner).
+hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only_class) {
   const int ncl = c.hm.n_classes;
   int* status = reinterpret_cast<int*>(c.ws.small) + (size_t)chunk * ncl;
   const int* cnt = &c.hm.chunk_class_cnt[(size_t)chunk * ncl];
@@ -751,12 +757,15 @@ hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only) {
     hipStream_t s = nstreams > 0 ? c.lu_streams[i % nstreams] : c.stream;
     double* scratch = c.ws.Uinv + scr;
     scr += class_scratch_doubles(batch);
+    if (only_class >= 0 && k != only_class) continue;
+    const LuTune tune = h.tune[prec == 1 ? 1 : 0];
     if (prec == 1)
       e = lu_eliminate<float>(s, reinterpret_cast<float*>(c.ws.Wm) + c.hm.chunk_class_w[ck], batch, h.wstride, h.ldw,
-                              h.n_u, n_rows, h.n_cols, ipiv, h.n_u, status + k, reinterpret_cast<float*>(scratch));
+                              h.n_u, n_rows, h.n_cols, ipiv, h.n_u, status + k, reinterpret_cast<float*>(scratch),
+                              tune);
     else
       e = lu_eliminate<double>(s, c.ws.Wm + c.hm.chunk_class_w[ck], batch, h.wstride, h.ldw, h.n_u, n_rows, h.n_cols,
-                               ipiv, h.n_u, status + k, scratch);
+                               ipiv, h.n_u, status + k, scratch, tune);
     if (e != hipSuccess) return e;
   }
   if (nstreams > 0) {  // join

@@ -67,7 +67,8 @@ EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_o
            "hdg_destroy", "hdg_status_string", "hdg_last_error", "hdg_get_condensed", "hdg_get_formed",
            "hdg_get_residuals", "hdg_precond_apply", "hdg_coarse_size", "hdg_coarse_restrict",
            "hdg_coarse_prolong", "hdg_mlp_param_count", "hdg_mlp_work_floats", "hdg_mlp_forward",
-           "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking"]
+           "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking",
+           "hdg_autotune", "hdg_class_count", "hdg_get_tuning"]
 
 _lib = None
 
@@ -88,6 +89,10 @@ def load_library(path=LIB_PATH):
     lib.hdg_node_coords.argtypes = [vp, vp, vp]
     lib.hdg_bind_workspace.argtypes = [vp, vp, sz]
     lib.hdg_set_chunking.argtypes = [vp, i]
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.hdg_autotune.argtypes = [vp, i, ctypes.c_char_p, ip]
+    lib.hdg_class_count.argtypes = [vp, ip]
+    lib.hdg_get_tuning.argtypes = [vp, i, i, ip, ip]
     lib.hdg_linearize_stage.argtypes = [vp, vp, vp, vp, vp, dp, dp, dp, vp]
     lib.hdg_condense.argtypes = [vp, i, vp]
     lib.hdg_apply_global.argtypes = [vp, vp, vp]
@@ -226,6 +231,25 @@ class Context:
             raise HdgError(2, f"workspace does not fit in {budget_bytes} bytes even with one macro per chunk")
         self.set_chunking(best)
         return best
+
+    def autotune(self, prec=HDG_FP64, cache_path=None):
+        """Pick the elimination launch shapes per macro class (needs a
+        linearisation; condense afterwards).  Returns the number of classes
+        timed (the others came from cache_path)."""
+        n = ctypes.c_int(0)
+        cp = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self.lib.hdg_autotune(self.h, prec, cp, ctypes.byref(n)))
+        return n.value
+
+    def class_count(self):
+        n = ctypes.c_int(0)
+        self._check(self.lib.hdg_class_count(self.h, ctypes.byref(n)))
+        return n.value
+
+    def tuning(self, macro_class, prec=HDG_FP64):
+        tpw, wide = ctypes.c_int(0), ctypes.c_int(0)
+        self._check(self.lib.hdg_get_tuning(self.h, macro_class, prec, ctypes.byref(tpw), ctypes.byref(wide)))
+        return tpw.value, wide.value
 
     def bind_workspace(self, ws=None):
         """Allocate (torch) and bind the device workspace."""

@@ -1,0 +1,55 @@
+"""The elimination autotuner: launch shapes picked per macro class and
+precision by timing, cached in a text file, and condensation results that
+still match the oracle with the chosen shapes."""
+import numpy as np
+import pytest
+
+from gpu_common import make_pair, to_dev, say
+
+pytestmark = pytest.mark.gpu
+
+CASE = dict(dim=3, seg=[[2, 3], [3, 2], [2, 2]], p=2, periodic=True)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_autotune_caches_and_keeps_parity(tmp_path):
+    import torch
+    from paper_2402_11361_amd.hdg import HDG_FP32, HDG_FP64, HdgError
+    say("[autotune] uneven 3D p=2")
+    S, inp, ctx = make_pair(CASE)
+    with pytest.raises(HdgError, match="linearisation"):
+        ctx.autotune(HDG_FP64)
+    d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
+    ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
+    ncl = ctx.class_count()
+    assert ncl == 4
+    cache = tmp_path / "lu_tuning.txt"
+    assert ctx.autotune(HDG_FP64, cache) == ncl
+    lines = cache.read_text().splitlines()
+    assert len(lines) == ncl
+    for k, line in enumerate(lines):
+        f = line.split()
+        assert f[2] == "fp64" and int(f[9]) in (8, 16, 32, 64) and int(f[10]) in (0, 1)
+        assert ctx.tuning(k, HDG_FP64) == (int(f[9]), int(f[10]))
+    # the cache answers a second call without timing
+    assert ctx.autotune(HDG_FP64, cache) == 0
+    assert ctx.autotune(HDG_FP32, cache) == ncl
+    assert len(cache.read_text().splitlines()) == 2 * ncl
+    say("[autotune] tuned: " + ", ".join(f"{ctx.tuning(k, HDG_FP64)}/{ctx.tuning(k, HDG_FP32)}" for k in range(ncl)))
+    # condensation with the chosen shapes
+    lin = S.linearize(inp["q"], inp["u"], inp["uh"], w=inp["w"], dt=inp["dt"], dii=inp["dii"])
+    cond = S.condense(lin, "B")
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    ctx.condense(bhat, HDG_FP64)
+    for i in lin:
+        A_i, b_i = ctx.get_condensed(i)
+        assert _rel(A_i, cond[i]["Ahat"]) < 1e-9 and _rel(b_i, cond[i]["bhat"]) < 1e-9
+    A, b = S.assemble(cond)
+    assert _rel(bhat.cpu().numpy(), b) < 1e-9
+    ctx.condense(bhat, HDG_FP32)
+    ea = max(_rel(ctx.get_condensed(i)[0], cond[i]["Ahat"]) for i in lin)
+    say(f"[autotune] FP32 A-hat {ea:.2e}")
+    assert ea < 5e-4
