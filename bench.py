@@ -357,8 +357,12 @@ def main():
             stage_solution_rel_diff_vs_plain=dict(u=du, uhat=duh),
             apply_ms=round(apply32_ms, 4),
             apply_gbs=round((4.0 * nm * nb * nb + 16.0 * nm * nb + 8.0 * ctx.n_glob) / (apply32_ms * 1e-3) / 1e9, 1))
-        for name, cp in (("plain_fp64_graph", HDG_FP64), ("mixed_fp32_condense_graph", HDG_FP32)):
-            gv = run_variant(cp, HDG_FP64, args.steps, args.warmup, graph_steps=args.graph_steps)
+        # fp64_condense_fp32_inner_graph: FP64 operator for the outer FGMRES,
+        # its FP32 copy for the inner GMRES of the preconditioner
+        for name, cp, ip in (("plain_fp64_graph", HDG_FP64, HDG_FP64),
+                             ("mixed_fp32_condense_graph", HDG_FP32, HDG_FP64),
+                             ("fp64_condense_fp32_inner_graph", HDG_FP64, HDG_FP32)):
+            gv = run_variant(cp, ip, args.steps, args.warmup, graph_steps=args.graph_steps)
             variants[name] = dict(
                 ms_per_stage=round(gv["ms_per_stage"], 3), speedup_vs_plain=round(ms_step / gv["ms_per_stage"], 3),
                 phases_ms={k: round(v, 3) for k, v in gv["phase_ms"].items()}, newton_its=gv["newton_its"],
