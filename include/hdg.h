@@ -58,8 +58,7 @@ typedef enum { HDG_FP64 = 0, HDG_FP32 = 1 } hdg_prec;
  * box macro-elements: along axis k the segments have seg_len[k][0..n_seg[k])
  * elements (host arrays, summing to n_elem[k]; lengths may differ, giving
  * macros of several shapes, each shape one class of reference tables).
- * Degree p in every element (p = 1..3; the SUPG term with 3D p = 3 is
- * HDG_EUNSUPPORTED).
+ * Degree p in every element (p = 1..3).
  * dim = 2 or 3.  Paper Sec. 2.2 (mesh, patches, spaces). */
 typedef struct {
   int dim;

@@ -307,8 +307,6 @@ hdg_status hdg_setup_mesh(const hdg_mesh_desc* mesh, const hdg_phys* phys, void*
   bool any_bnd = false;
   for (int v : c.hm.macro_bnd) any_bnd |= (v != 0);
   if (any_bnd && !phys->bc_state_host) { delete h; return HDG_EINVAL; }
-  // the SUPG element kernel keeps its 3D p = 3 tables in LDS, which do not fit
-  if (phys->supg && mesh->dim == 3 && mesh->p == 3) { delete h; return HDG_EUNSUPPORTED; }
   c.stream = static_cast<hipStream_t>(hip_stream);
   c.hcs.resize(c.hm.n_classes);
   for (int k = 0; k < c.hm.n_classes; ++k) build_class(c.hm, c.hcs[k], c.hm.class_m[k]);

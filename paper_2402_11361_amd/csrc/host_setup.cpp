@@ -589,7 +589,12 @@ void plan_workspace(HdgContext& c) {
                sizeof(unsigned short) * mlp_param_count(hc.cF, LRN_MAX_HIDDEN, hc.cF));
   o.kctl = take(sizeof(double) * 8192);
   // SUPG: the per-element products are formed in batches of up to 4096 elements
-  c.supg_chunk = c.ph.supg ? std::min<long long>(n_el, 4096) : 0;
+  // (at most 4096 elements and about 4 GB of products per batch)
+  c.supg_chunk = 0;
+  if (c.ph.supg) {
+    const long long per = (long long)supg_scratch_per_element(hc.dim, hc.p) * (long long)sizeof(double);
+    c.supg_chunk = std::max<long long>(1, std::min<long long>({n_el, 4096, (4LL << 30) / per}));
+  }
   o.supg = take(sizeof(double) * (size_t)c.supg_chunk * (c.ph.supg ? supg_scratch_per_element(hc.dim, hc.p) : 0));
   o.Ac = take(chunked ? sizeof(double) * (size_t)hm.a32_off[nm] : 0);
   o.bloc = take(chunked ? sizeof(double) * (size_t)hm.b_off[nm] : 0);

@@ -28,6 +28,11 @@ struct SupgSz {
   static constexpr int NSA = NS * A, DNSA = D * NS * A;
   static constexpr int QY = Q * NS;          // inner dimension of the products
   static constexpr int NCOL = NSA + DNSA;    // columns of [Ru | Rq]
+  // nodal flux derivatives and W tau A_k: in LDS when they fit, otherwise in
+  // a per-element global slot (3D p = 3: 229 KB; 3D p = 2 stays in LDS)
+  static constexpr int NJ = A * D * NS * NS, NGQ = A * D * D * NS * NS, NLA = Q * D * NS * NS;
+  static constexpr bool BIG = (NJ + NGQ + NLA) * 8 > 120 * 1024;
+  static constexpr int GSLOT = BIG ? NJ + NGQ + NLA : 0;
 };
 
 constexpr int SUPG_THREADS = 256;
@@ -36,7 +41,7 @@ template <int D, int P>
 __global__ void __launch_bounds__(SUPG_THREADS)
 k_supg_prep(MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg, const double* __restrict__ ug,
             const double* __restrict__ wg, long long el0, double* __restrict__ RUe, double* __restrict__ Lbuf,
-            double* __restrict__ Rbuf) {
+            double* __restrict__ Rbuf, double* __restrict__ Gbuf) {
   using Z = SupgSz<D, P>;
   constexpr int NS = Z::NS, A = Z::A, Q = Z::Q, NSA = Z::NSA, QY = Z::QY, NCOL = Z::NCOL;
   const int tid = threadIdx.x;
@@ -49,10 +54,14 @@ k_supg_prep(MeshDev md, PhysDev ph, StageArgs sa, const double* __restrict__ qg,
 
   __shared__ double s_u[NS * A], s_q[D * NS * A], s_w[NS * A];
   __shared__ double s_NF[A * D * NS];            // nodal F + G: [b][k][y]
-  __shared__ double s_J[A * D * NS * NS];        // [b][k][y][c']
-  __shared__ double s_GQ[A * D * D * NS * NS];   // [b][k][y][l][c']
-  __shared__ double s_LA[Q * D * NS * NS];       // W tau A_k: [q][k][y][c]
+  __shared__ double l_J[Z::BIG ? 1 : Z::NJ];     // [b][k][y][c']
+  __shared__ double l_GQ[Z::BIG ? 1 : Z::NGQ];   // [b][k][y][l][c']
+  __shared__ double l_LA[Z::BIG ? 1 : Z::NLA];   // W tau A_k: [q][k][y][c]
   __shared__ double s_R[Q * NS];                 // strong residual [q][y]
+  double* gs = Gbuf + (size_t)blockIdx.x * Z::GSLOT;
+  double* s_J = Z::BIG ? gs : l_J;
+  double* s_GQ = Z::BIG ? gs + Z::NJ : l_GQ;
+  double* s_LA = Z::BIG ? gs + Z::NJ + Z::NGQ : l_LA;
   __shared__ int s_nodes[A];
 
   const int* en = cd.elem_nodes + (size_t)e * A;
@@ -255,10 +264,11 @@ hipError_t supg_dispatch(HdgContext& c, const double* q, const double* u, const 
   const long long chunk = c.supg_chunk;
   double* Lbuf = c.ws.supg;
   double* Rbuf = Lbuf + (size_t)chunk * Z::NSA * Z::QY;
+  double* Gbuf = Rbuf + (size_t)chunk * Z::QY * Z::NCOL;
   for (long long el0 = 0; el0 < nel; el0 += chunk) {
     const long long ne = std::min(chunk, nel - el0);
     hipLaunchKernelGGL((k_supg_prep<D, P>), dim3((unsigned)ne), dim3(SUPG_THREADS), 0, c.stream, c.md, c.ph, sa, q, u,
-                       w, el0, c.ws.RUe, Lbuf, Rbuf);
+                       w, el0, c.ws.RUe, Lbuf, Rbuf, Gbuf);
     // A_uu^e += L Ru,  A_uq^e += L Rq
     dim3 g1((Z::NSA + GT - 1) / GT, (Z::NSA + GT - 1) / GT, (unsigned)ne);
     hipLaunchKernelGGL(k_supg_gemm, g1, dim3(256), 0, c.stream, Z::NSA, Z::NSA, Z::QY, Lbuf, (long long)Z::NSA * Z::QY,
@@ -273,12 +283,15 @@ hipError_t supg_dispatch(HdgContext& c, const double* q, const double* u, const 
 
 }  // namespace
 
-// Scratch doubles per element of the SUPG products (L and [Ru | Rq]).
+// Scratch doubles per element of the SUPG products (L and [Ru | Rq], plus
+// the global slot of the flux derivatives where they do not fit in LDS).
 size_t supg_scratch_per_element(int dim, int p) {
   const int ns = dim + 2, A = (dim == 3) ? (p + 1) * (p + 1) * (p + 1) : (p + 1) * (p + 1);
   const int Q = (dim == 3) ? (p + 2) * (p + 2) * (p + 2) : (p + 2) * (p + 2);
   const size_t nsa = (size_t)ns * A, qy = (size_t)Q * ns;
-  return nsa * qy + qy * (nsa + (size_t)dim * nsa);
+  size_t gslot = 0;
+  if (dim == 3 && p == 3) gslot = SupgSz<3, 3>::GSLOT;
+  return nsa * qy + qy * (nsa + (size_t)dim * nsa) + gslot;
 }
 
 hipError_t launch_supg(HdgContext& c, const double* q, const double* u, const double* w, StageArgs sa) {
@@ -288,5 +301,6 @@ hipError_t launch_supg(HdgContext& c, const double* q, const double* u, const do
   if (D == 2 && P == 3) return supg_dispatch<2, 3>(c, q, u, w, sa);
   if (D == 3 && P == 1) return supg_dispatch<3, 1>(c, q, u, w, sa);
   if (D == 3 && P == 2) return supg_dispatch<3, 2>(c, q, u, w, sa);
+  if (D == 3 && P == 3) return supg_dispatch<3, 3>(c, q, u, w, sa);
   return hipErrorInvalidValue;
 }

@@ -23,6 +23,7 @@ CASES = {
     "2d_dir_p2_supg": dict(dim=2, n_elem=6, m=3, p=2, periodic=False, state="shear", mach=0.2, supg=True),
     "2d_per_p3_supg": dict(dim=2, n_elem=4, m=2, p=3, periodic=True, supg=True),
     "3d_per_p2_supg": dict(dim=3, n_elem=4, m=2, p=2, periodic=True, supg=True),
+    "3d_per_p3_supg": dict(dim=3, n_elem=2, m=1, p=3, periodic=True, supg=True),
     # macros of different sizes in one mesh (several classes in one launch)
     "2d_dir_uneven_p2": dict(dim=2, seg=[[2, 3], [3, 2]], p=2, periodic=False, state="shear", mach=0.2),
     "3d_per_uneven_p2": dict(dim=3, seg=[[2, 3], [3, 2], [2, 2]], p=2, periodic=True),
@@ -129,11 +130,3 @@ def test_condensed_and_apply_and_solve(pairs, name):
     dq_o, du_o = S.backsolve(lin, cond, x_ref)
     _close(du.cpu().numpy(), du_o, 1e-9, "dU")
     _close(dq.cpu().numpy(), dq_o, 1e-9, "dQ")
-
-
-def test_supg_3d_p3_is_unsupported():
-    from paper_2402_11361_amd.hdg import Context, HdgError
-    spec = dict(dim=3, n_elem=[2, 2, 2], lo=[0.0] * 3, hi=[1.0] * 3, periodic=[True] * 3,
-                seg_len=[[1, 1]] * 3, p=3)
-    with pytest.raises(HdgError, match="EUNSUPPORTED"):
-        Context.from_mesh_spec(spec, gamma=1.4, Pr=0.71, Re=100.0, Mach=0.1, supg=True)
