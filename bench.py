@@ -240,7 +240,7 @@ def main():
     import torch
     from paper_2402_11361_amd import inputs
     from paper_2402_11361_amd.driver import StageDriver, alexander_dirk33
-    from paper_2402_11361_amd.hdg import HDG_FP32, HDG_FP64, Context, mesh_spec_box
+    from paper_2402_11361_amd.hdg import HDG_BF16, HDG_FP32, HDG_FP64, Context, mesh_spec_box
 
     cfg = dict(inputs.CONFIGS[args.config])
     spec = mesh_spec_box(cfg["dim"], cfg["n_elem"], cfg["m"], cfg["p"], cfg["lo"], cfg["hi"], cfg["periodic"])
@@ -357,11 +357,13 @@ def main():
             stage_solution_rel_diff_vs_plain=dict(u=du, uhat=duh),
             apply_ms=round(apply32_ms, 4),
             apply_gbs=round((4.0 * nm * nb * nb + 16.0 * nm * nb + 8.0 * ctx.n_glob) / (apply32_ms * 1e-3) / 1e9, 1))
-        # fp64_condense_fp32_inner_graph: FP64 operator for the outer FGMRES,
-        # its FP32 copy for the inner GMRES of the preconditioner
+        # *_inner_graph: the condensed operator for the outer FGMRES, its FP32
+        # or BF16 copy for the inner GMRES of the preconditioner
         for name, cp, ip in (("plain_fp64_graph", HDG_FP64, HDG_FP64),
                              ("mixed_fp32_condense_graph", HDG_FP32, HDG_FP64),
-                             ("fp64_condense_fp32_inner_graph", HDG_FP64, HDG_FP32)):
+                             ("fp64_condense_fp32_inner_graph", HDG_FP64, HDG_FP32),
+                             ("fp64_condense_bf16_inner_graph", HDG_FP64, HDG_BF16),
+                             ("mixed_fp32_condense_bf16_inner_graph", HDG_FP32, HDG_BF16)):
             gv = run_variant(cp, ip, args.steps, args.warmup, graph_steps=args.graph_steps)
             variants[name] = dict(
                 ms_per_stage=round(gv["ms_per_stage"], 3), speedup_vs_plain=round(ms_step / gv["ms_per_stage"], 3),

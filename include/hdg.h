@@ -52,7 +52,7 @@ typedef enum {
   HDG_EUNSUPPORTED = 8  /* configuration not built (dimension, degree, ...)  */
 } hdg_status;
 
-typedef enum { HDG_FP64 = 0, HDG_FP32 = 1 } hdg_prec;
+typedef enum { HDG_FP64 = 0, HDG_FP32 = 1, HDG_BF16 = 2 } hdg_prec;
 
 /* Box mesh on [lo, hi] with n_elem[k] uniform elements per axis, grouped into
  * box macro-elements: along axis k the segments have seg_len[k][0..n_seg[k])
@@ -97,7 +97,14 @@ typedef struct {
  * max(rtol ||b||_2, atol).  inner_prec selects the precision of the condensed
  * blocks used inside the preconditioner: HDG_FP32 after an FP64 condensation
  * uses an FP32 copy of A-hat there (made on first use); after an FP32
- * condensation both levels use the FP32 blocks. */
+ * condensation both levels use the FP32 blocks.  HDG_BF16: a BF16 copy of
+ * A-hat (rounded to nearest even, made on first use, applied with FP64
+ * sums) inside the preconditioner only; the outer FGMRES keeps the
+ * condensed operator, so the solution is unaffected (FGMRES admits a
+ * preconditioner that differs from the operator), only iteration counts
+ * change.  With chunked condensation: HDG_FP32 needs an FP32 condensation
+ * and HDG_BF16 is HDG_EUNSUPPORTED.  hdg_condense accepts HDG_FP64 and
+ * HDG_FP32 only. */
 typedef struct {
   double rtol, atol;
   int restart, max_outer, inner_its;

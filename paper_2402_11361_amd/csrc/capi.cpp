@@ -385,6 +385,27 @@ hdg_status hdg_node_coords(hdg_ctx ctx, double* macro_xyz, double* face_xyz) {
   return HDG_OK;
 }
 
+// Precision code of the inner operator (0 the condensed blocks, 1 FP32
+// copy, 2 BF16 copy), making the copy on first use after a condensation.
+static hdg_status inner_operator(HdgContext& c, int inner_prec, int* code) {
+  if (inner_prec != HDG_FP64 && inner_prec != HDG_FP32 && inner_prec != HDG_BF16)
+    return fail(&c, HDG_EINVAL, "bad inner precision");
+  if (inner_prec == HDG_FP32 && c.cond_prec == 0 && c.hm.chunked())
+    return fail(&c, HDG_EUNSUPPORTED, "FP32 inner operator with chunked FP64 condensation (condense in FP32 instead)");
+  if (inner_prec == HDG_BF16 && c.hm.chunked())
+    return fail(&c, HDG_EUNSUPPORTED, "BF16 inner operator with chunked condensation");
+  if (inner_prec == HDG_FP32 && c.cond_prec == 0 && !c.have_a32) {
+    HIPCHK(&c, launch_cast_ahat(c));
+    c.have_a32 = true;
+  }
+  if (inner_prec == HDG_BF16 && !c.have_a16) {
+    HIPCHK(&c, launch_cast_ahat16(c));
+    c.have_a16 = true;
+  }
+  *code = inner_prec == HDG_BF16 ? 2 : (inner_prec == HDG_FP32 ? 1 : 0);
+  return HDG_OK;
+}
+
 hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk) {
   if (!ctx) return HDG_EINVAL;
   HdgContext& c = ctx->c;
@@ -405,6 +426,7 @@ hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk) {
   c.ws_bound = false;
   c.lrn_bound = false;
   c.have_a32 = false;
+  c.have_a16 = false;
   clear_graphs(c);
   return HDG_OK;
 }
@@ -421,14 +443,14 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
     auto rebase = [&](auto*& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(base + (reinterpret_cast<const char*>(p) - old)); };
     rebase(c.ws.Kq); rebase(c.ws.AUU); rebase(c.ws.AUQ); rebase(c.ws.RUe); rebase(c.ws.RQe); rebase(c.ws.SUB);
     rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.gloc); rebase(c.ws.Wm);
-    rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.ypart); rebase(c.ws.kry);
+    rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.A16); rebase(c.ws.ypart); rebase(c.ws.kry);
     rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn); rebase(c.ws.kctl); rebase(c.ws.supg);
     rebase(c.ws.Ac); rebase(c.ws.bloc);
   } else {
     auto rebase = [&](auto*& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(base + reinterpret_cast<uintptr_t>(p)); };
     rebase(c.ws.Kq); rebase(c.ws.AUU); rebase(c.ws.AUQ); rebase(c.ws.RUe); rebase(c.ws.RQe); rebase(c.ws.SUB);
     rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.gloc); rebase(c.ws.Wm);
-    rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.ypart); rebase(c.ws.kry);
+    rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.A16); rebase(c.ws.ypart); rebase(c.ws.kry);
     rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn); rebase(c.ws.kctl); rebase(c.ws.supg);
     rebase(c.ws.Ac); rebase(c.ws.bloc);
   }
@@ -438,6 +460,7 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
   c.ws.bytes = bytes;
   c.ws_bound = true;
   c.have_a32 = false;
+  c.have_a16 = false;
   c.linearized = false;
   return HDG_OK;
 }
@@ -546,6 +569,7 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
   if (n_timed) *n_timed = timed;
   // the trials overwrote the condensed matrices
   c.have_a32 = false;
+  c.have_a16 = false;
   return HDG_OK;
 }
 
@@ -574,6 +598,7 @@ hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, co
   HIPCHK(&c, launch_linearize(c, q, u, uhat, w, sa));
   c.linearized = true;
   c.have_a32 = false;
+  c.have_a16 = false;
   if (norms_host) {
     HIPCHK(&c, launch_norms(c, c.ws.small + 2048));
     HIPCHK(&c, hipMemcpyAsync(ctx->pinned, c.ws.small + 2048, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
@@ -603,6 +628,7 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
   HIPCHK(&c, launch_face_precond(c));
   c.cond_prec = p32;
   c.have_a32 = false;
+  c.have_a16 = false;
   std::vector<int> st(nst + 1, 0);
   HIPCHK(&c, hipMemcpyAsync(ctx->pinned, status, sizeof(int) * (nst + 1), hipMemcpyDeviceToHost, c.stream));
   HIPCHK(&c, hipStreamSynchronize(c.stream));
@@ -637,15 +663,11 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
       o->max_outer < 1 || !(o->rtol >= 0) || !(o->atol >= 0) || o->graph_steps < 0)
     return fail(&c, HDG_EINVAL, "bad Krylov options");
   auto t0 = std::chrono::steady_clock::now();
-  if (o->inner_prec == HDG_FP32 && c.cond_prec == 0 && c.hm.chunked())
-    return fail(&c, HDG_EUNSUPPORTED, "FP32 inner operator with chunked FP64 condensation (condense in FP32 instead)");
-  if (o->inner_prec == HDG_FP32 && c.cond_prec == 0 && !c.have_a32) {
-    HIPCHK(&c, launch_cast_ahat(c));
-    c.have_a32 = true;
-  }
+  int icode = 0;
+  if (hdg_status s = inner_operator(c, o->inner_prec, &icode); s != HDG_OK) return s;
   if (o->use_learned && !c.lrn_bound) return fail(&c, HDG_EINVAL, "use_learned without a bound network");
   if (o->harvest_max < 0 || (o->harvest_max > 0 && !o->harvest)) return fail(&c, HDG_EINVAL, "bad harvest buffer");
-  Krylov K(c, o->restart, o->inner_its, ctx->pinned, o->inner_prec == HDG_FP32 ? 1 : 0);
+  Krylov K(c, o->restart, o->inner_its, ctx->pinned, icode);
   K.learned = o->use_learned != 0;
   const long long n = K.n;
   int harvested = 0, fallbacks = 0;
@@ -798,13 +820,9 @@ hdg_status hdg_precond_apply(hdg_ctx ctx, const double* v, double* z, int inner_
   if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
   if (inner_its < 0 || inner_its > c.kry_inner_max) return fail(&c, HDG_EINVAL, "bad inner_its");
   if (use_learned && !c.lrn_bound) return fail(&c, HDG_EINVAL, "use_learned without a bound network");
-  if (inner_prec == HDG_FP32 && c.cond_prec == 0 && c.hm.chunked())
-    return fail(&c, HDG_EUNSUPPORTED, "FP32 inner operator with chunked FP64 condensation (condense in FP32 instead)");
-  if (inner_prec == HDG_FP32 && c.cond_prec == 0 && !c.have_a32) {
-    HIPCHK(&c, launch_cast_ahat(c));
-    c.have_a32 = true;
-  }
-  Krylov K(c, 1, inner_its, ctx->pinned, inner_prec == HDG_FP32 ? 1 : 0);
+  int icode = 0;
+  if (hdg_status s = inner_operator(c, inner_prec, &icode); s != HDG_OK) return s;
+  Krylov K(c, 1, inner_its, ctx->pinned, icode);
   K.learned = use_learned != 0;
   HIPCHK(&c, K.precond(v, z));
   return HDG_OK;

@@ -79,6 +79,7 @@ struct Workspace {
   double* FW = nullptr;     // [faces][2 nf][ldf] face preconditioner
   int* fpiv = nullptr;      // [faces][nf]
   float* A32 = nullptr;     // [macros][n_b][n_b] FP32 copy of A-hat (inner operator)
+  unsigned short* A16 = nullptr;  // [macros][n_b][n_b] BF16 copy of A-hat (inner operator)
   double* ypart = nullptr;  // [macros][n_b]
   double* kry = nullptr;    // Krylov vectors
   double* red = nullptr;    // reduction scratch
@@ -116,6 +117,7 @@ struct HdgContext {
   // offsets of the sub-face block pieces
   int off_AUB = 0, off_ABU = 0, off_ABQ = 0, off_ABB = 0, off_RB = 0;
   bool have_a32 = false;
+  bool have_a16 = false;
   bool linearized = false;  // element blocks hold a linearisation
   int cond_prec = 0;
   long long supg_chunk = 0;  // elements per SUPG product batch

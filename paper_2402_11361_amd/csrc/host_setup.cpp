@@ -551,7 +551,7 @@ void plan_workspace(HdgContext& c) {
   }
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, gloc, Wm, ipiv, FW, fpiv, A32, ypart, kry, red, small, Uinv, lrn, kctl, supg, Ac, bloc; } o;
+  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, gloc, Wm, ipiv, FW, fpiv, A32, A16, ypart, kry, red, small, Uinv, lrn, kctl, supg, Ac, bloc; } o;
   const bool chunked = hm.chunked();
   const size_t kq_bytes = sizeof(double) * n_el * c.Kstride;
   // chunked: Kq (used only inside the linearisation) shares the W buffer
@@ -575,6 +575,7 @@ void plan_workspace(HdgContext& c) {
   o.fpiv = take(sizeof(int) * (size_t)hm.n_faces * c.nf_max);
   // FP32 copy of A-hat for the inner solver (not kept when chunked)
   o.A32 = take(chunked ? 0 : sizeof(float) * (size_t)hm.a32_off[nm]);
+  o.A16 = take(chunked ? 0 : sizeof(unsigned short) * (size_t)hm.a32_off[nm]);
   o.ypart = take(sizeof(double) * (size_t)hm.b_off[nm]);
   o.kry = take(sizeof(double) * (size_t)(2 * c.kry_restart_max + c.kry_inner_max + 8) * hm.n_glob);
   o.red = take(sizeof(double) * (1 << 20));
@@ -618,6 +619,7 @@ void plan_workspace(HdgContext& c) {
   c.ws.FW = reinterpret_cast<double*>(o.FW);
   c.ws.fpiv = reinterpret_cast<int*>(o.fpiv);
   c.ws.A32 = reinterpret_cast<float*>(o.A32);
+  c.ws.A16 = reinterpret_cast<unsigned short*>(o.A16);
   c.ws.ypart = reinterpret_cast<double*>(o.ypart);
   c.ws.kry = reinterpret_cast<double*>(o.kry);
   c.ws.red = reinterpret_cast<double*>(o.red);

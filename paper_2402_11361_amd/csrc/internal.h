@@ -153,6 +153,7 @@ hipError_t launch_norms(HdgContext& c, double* out3_dev);
 hipError_t launch_supg(HdgContext& c, const double* q, const double* u, const double* w, StageArgs sa);
 size_t supg_scratch_per_element(int dim, int p);
 hipError_t launch_cast_ahat(HdgContext& c);
+hipError_t launch_cast_ahat16(HdgContext& c);
 
 // learned coarse correction
 constexpr int LRN_MAX_HIDDEN = 512;

@@ -175,6 +175,33 @@ __global__ void __launch_bounds__(256) k_precond_apply(MeshDev md, const double*
   }
 }
 
+// BF16 storage of the inner operator: the upper 16 bits of an IEEE single,
+// rounded to nearest (ties to even); widened exactly on load.
+struct Bf16 {
+  unsigned short v;
+  __device__ __forceinline__ operator double() const { return (double)__uint_as_float((unsigned)v << 16); }
+};
+
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+  const unsigned u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);  // inf / nan unchanged
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// A16[a32_off[macro] + r n_b + c] = bf16(A-hat^{T_i}[r][c]) from the tiled
+// eliminated matrices (FP64 or FP32 storage)
+template <class TW>
+__global__ void k_cast_ahat16(MeshDev md, const TW* __restrict__ W, unsigned short* __restrict__ out) {
+  const long long total = md.a32_off[md.n_macros];
+  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total; g += (long long)gridDim.x * blockDim.x) {
+    const int macro = find_in(md.a32_off, md.n_macros, g);
+    const ClassDev& cd = class_of(md, macro);
+    const long long rc = g - md.a32_off[macro];
+    const int r = (int)(rc / cd.n_b), c = (int)(rc % cd.n_b);
+    out[g] = to_bf16((float)W[md.w_off[macro] + wtix(cd.n_u + r, cd.n_u + c, cd.ldw)]);
+  }
+}
+
 // A32[a32_off[macro] + r n_b + c] = (float) A-hat^{T_i}[r][c]
 __global__ void k_cast_ahat(MeshDev md, const double* __restrict__ W, float* __restrict__ out) {
   const long long total = md.a32_off[md.n_macros];
@@ -381,12 +408,17 @@ hipError_t launch_bhat(HdgContext& c, double* bhat, int prec) {
   return hipGetLastError();
 }
 
+// prec: 0 the condensed operator itself; 1 its FP32 copy (made by
+// launch_cast_ahat, FP64 condensation only); 2 its BF16 copy (launch_cast_ahat16).
 hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec) {
   int nb = 0;
   for (const HostClass& k : c.hcs) nb = std::max(nb, k.n_b);
   dim3 grid((nb + APPLY_ROWS - 1) / APPLY_ROWS, c.hm.n_macros);
   const size_t shm = (size_t)nb * sizeof(double);
-  if (c.hm.chunked()) {  // compact copy of every macro's A-hat
+  if (!c.hm.chunked() && prec == 2 && c.have_a16) {
+    hipLaunchKernelGGL((k_apply_local<Bf16, false>), grid, dim3(256), shm, c.stream, c.md,
+                       reinterpret_cast<const Bf16*>(c.ws.A16), x, c.ws.ypart);
+  } else if (c.hm.chunked()) {  // compact copy of every macro's A-hat
     if (c.cond_prec == 1)
       hipLaunchKernelGGL((k_apply_local<float, false>), grid, dim3(256), shm, c.stream, c.md,
                          reinterpret_cast<const float*>(c.ws.Ac), x, c.ws.ypart);
@@ -444,6 +476,17 @@ hipError_t launch_extract(HdgContext& c, int prec, int chunk) {
   else
     hipLaunchKernelGGL(k_extract<double>, grid, dim3(256), 0, c.stream, c.md, m0, c.ws.Wm, c.ws.Ac,
                        static_cast<const double*>(nullptr), c.ws.bloc);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_ahat16(HdgContext& c) {
+  const long long total = c.hm.a32_off[c.hm.n_macros];
+  if (c.cond_prec == 1)
+    hipLaunchKernelGGL(k_cast_ahat16<float>, dim3(grid_for(total)), dim3(256), 0, c.stream, c.md,
+                       reinterpret_cast<const float*>(c.ws.Wm), c.ws.A16);
+  else
+    hipLaunchKernelGGL(k_cast_ahat16<double>, dim3(grid_for(total)), dim3(256), 0, c.stream, c.md,
+                       static_cast<const double*>(c.ws.Wm), c.ws.A16);
   return hipGetLastError();
 }
 

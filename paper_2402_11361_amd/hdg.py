@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhdg.so")
 
-HDG_FP64, HDG_FP32 = 0, 1
+HDG_FP64, HDG_FP32, HDG_BF16 = 0, 1, 2
 _STATUS = {0: "HDG_OK", 1: "HDG_EINVAL", 2: "HDG_ENOMEM", 3: "HDG_EDEVICE", 4: "HDG_ESINGULAR",
            5: "HDG_ENOCONV", 6: "HDG_EBREAKDOWN", 7: "HDG_ENAN", 8: "HDG_EUNSUPPORTED"}
 

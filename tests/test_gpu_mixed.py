@@ -93,3 +93,47 @@ def test_fp32_condensation_refined_by_newton(name):
     eq = _rel(q.cpu().numpy(), qo)
     say(f"[fp32 refined] {name}: u {eu:.2e}  uhat {euh:.2e}  q {eq:.2e}")
     assert eu < 1e-8 and euh < 1e-8 and eq < 1e-8
+
+
+@pytest.mark.parametrize("name", ["2d_dir_p3", "3d_per_uneven_p2"])
+def test_bf16_inner_operator_keeps_the_solution(name):
+    """A BF16 copy of A-hat inside the preconditioner only: FGMRES on the FP64
+    operator still reaches the oracle's solution (flexible preconditioning),
+    and the Newton stage solve still matches the oracle's stage solution."""
+    import torch
+    from oracle.newton import newton_solve
+    from paper_2402_11361_amd.driver import StageDriver
+    from paper_2402_11361_amd.hdg import HDG_BF16, HDG_FP64
+    say(f"[bf16 inner] {name}")
+    S, inp, ctx = make_pair(CASES[name])
+    d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
+    ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
+    lin = S.linearize(inp["q"], inp["u"], inp["uh"], w=inp["w"], dt=inp["dt"], dii=inp["dii"])
+    cond = S.condense(lin, "B")
+    A, b = S.assemble(cond)
+    x_ref = S.solve_direct(A, b)
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    ctx.condense(bhat, HDG_FP64)
+    its = {}
+    for ip in (HDG_FP64, HDG_BF16):
+        x = torch.zeros_like(bhat)
+        info = ctx.fgmres_solve(bhat, x, rtol=1e-13, restart=30, max_outer=400, inner_its=5, inner_prec=ip)
+        assert info["converged"], info
+        its[ip] = info["outer_its"]
+        assert _rel(x.cpu().numpy(), x_ref) < 1e-9
+    say(f"[bf16 inner] {name}: outer iterations FP64 {its[HDG_FP64]}, BF16 inner {its[HDG_BF16]}")
+    # the BF16 preconditioner is a different operator, but a close one
+    v = to_dev(np.random.default_rng(3).standard_normal(ctx.n_glob))
+    z64, z16 = torch.zeros_like(v), torch.zeros_like(v)
+    ctx.precond_apply(v, z64, inner_its=5, inner_prec=HDG_FP64)
+    ctx.precond_apply(v, z16, inner_its=5, inner_prec=HDG_BF16)
+    dz = _rel(z16.cpu().numpy(), z64.cpu().numpy())
+    say(f"[bf16 inner] {name}: preconditioner difference {dz:.2e}")
+    assert 1e-6 < dz < 0.2
+    qo, uo, uho, _ = newton_solve(S, inp["q"], inp["u"], inp["uh"], w=inp["w"], dt=inp["dt"], dii=inp["dii"],
+                                  abs_tol=1e-12, rel_tol=1e-12, max_it=12)
+    drv = StageDriver(ctx, rtol=1e-10, newton_abs=1e-12, newton_rel=1e-12, max_newton=12, inner_prec=HDG_BF16)
+    q, u, uh = to_dev(inp["q"]), to_dev(inp["u"]), to_dev(inp["uh"])
+    res = drv.solve_stage(q, u, uh, to_dev(inp["w"]), inp["dt"], inp["dii"])
+    assert res["res_hist"][-1] < 1e-11
+    assert _rel(u.cpu().numpy(), uo) < 1e-10 and _rel(uh.cpu().numpy(), uho) < 1e-10
