@@ -132,6 +132,44 @@ def uneven_variant(args, dev_fn, variants):
     ctx.close()
 
 
+def big_variant(args, dev_fn, variants):
+    """The 48^3 workload (1728 macros of 4^3 elements, p = 2): chunked FP32
+    condensation, FP32 inner operator, graph-captured FGMRES steps; whole
+    DIRK(3,3) time steps from the seeded state."""
+    import torch
+    from paper_2402_11361_amd import inputs
+    from paper_2402_11361_amd.driver import StageDriver
+    from paper_2402_11361_amd.hdg import HDG_FP32, Context, mesh_spec_box
+    cfg = dict(inputs.CONFIGS["C5"])
+    spec = mesh_spec_box(3, cfg["n_elem"], cfg["m"], cfg["p"], cfg["lo"], cfg["hi"], True)
+    stream = torch.cuda.current_stream()
+    ctx = Context.from_mesh_spec(spec, Re=cfg["Re"], Mach=cfg["mach"], stream=stream.cuda_stream)
+    free, _ = torch.cuda.mem_get_info()
+    per = ctx.fit_chunking(free - (8 << 30))
+    ctx.bind_workspace()
+    u0, q0, uh0 = workload_arrays(ctx, cfg)
+    q, u, uh = dev_fn(q0), dev_fn(u0), dev_fn(uh0)
+    dt = inputs.cfl_dt(cfg)
+    drv = StageDriver(ctx, rtol=cfg["rtol"], condense_prec=HDG_FP32, inner_prec=HDG_FP32,
+                      graph_steps=args.graph_steps)
+    steps = []
+    for n in range(args.big_steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = drv.step(q, u, uh, dt)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        steps.append(dict(ms=round(1e3 * wall, 1), ms_per_stage=round(1e3 * wall / len(infos), 1),
+                          newton_its=[i["newton_its"] for i in infos],
+                          fgmres_outer=[[k["outer_its"] for k in i["krylov"]] for i in infos]))
+        print(f"[bench] 48^3 time step {n + 1}: {steps[-1]['ms']} ms", file=sys.stderr, flush=True)
+    variants["tgv48_chunked_fp32_graph_steps"] = dict(
+        workload="48^3 periodic Taylor-Green, 4^3-element macros (1728), p=2, "
+                 f"n_glob {ctx.n_glob}; {per} macros per condensation chunk",
+        macros_per_chunk=per, workspace_gb=round(ctx.workspace_bytes / 1e9, 1), time_steps=steps)
+    ctx.close()
+
+
 def train_learned(ctx, cfg, dev, dii, dt, args):
     """Train the learned coarse correction on pairs harvested from plain FGMRES
     solves of the first Newton step on states with other noise seeds (1, 2, ...);
@@ -228,6 +266,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-macro 32^3 variant")
     ap.add_argument("--graph-steps", type=int, default=10, help="FGMRES steps per captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default elimination launch shapes")
+    ap.add_argument("--big-steps", type=int, default=0,
+                    help="also time this many DIRK(3,3) steps of the 48^3 workload (chunked condensation)")
     ap.add_argument("--tune-cache", default=None, help="text file of earlier autotuner choices (read and appended)")
     ap.add_argument("--train-seeds", type=int, default=2)
     ap.add_argument("--train-vectors", type=int, default=40)
@@ -422,6 +462,14 @@ def main():
         gc.collect()
         torch.cuda.empty_cache()
         uneven_variant(args, dev, variants)
+    if args.big_steps > 0:
+        if "ctx" in locals():
+            ctx.close()
+            del ctx
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+        big_variant(args, dev, variants)
     print(json.dumps(out), flush=True)
 
 
