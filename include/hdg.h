@@ -188,8 +188,10 @@ hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk);
  * the class's elimination (HIP events on the context's stream, after one
  * untimed trial) for each candidate launch shape -- 8, 16, 32 or 64
  * sixteen-row tiles per workgroup of the trailing update with the 512-thread
- * panel factorisation, then the 1024-thread panel with the best of those --
- * on the current linearisation, and keeps the fastest.
+ * panel factorisation, then the 1024-thread panel with the best of those,
+ * then the factorisation of the next pair of column blocks on a second
+ * stream beside the trailing update -- on the current linearisation, and
+ * keeps the fastest.
  * cache_path (host string, may be NULL): text file of earlier choices, one
  * line per (GPU architecture, HIP runtime version, precision, class shape,
  * batch size); classes found there are not timed, new choices are appended.
@@ -203,9 +205,15 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
 hdg_status hdg_class_count(hdg_ctx ctx, int* n_classes);
 
 /* Launch shape in use for class macro_class (0 .. n_classes - 1) and the
- * given precision: tiles per workgroup of the trailing update (default 32)
- * and the wide-panel flag (default 0). */
-hdg_status hdg_get_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int* tpw, int* panel_wide);
+ * given precision: tiles per workgroup of the trailing update (default 32),
+ * the wide-panel flag and the look-ahead-stream flag (default 0); host
+ * pointers, each may be NULL. */
+hdg_status hdg_get_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int* tpw, int* panel_wide, int* lookahead);
+
+/* Sets the launch shape of a class by hand (tpw: multiple of 4 in [4, 256];
+ * flags 0 or 1); HDG_EINVAL otherwise.  Results change only by rounding
+ * order. */
+hdg_status hdg_set_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int tpw, int panel_wide, int lookahead);
 
 /* Linearise eq. (C242) at (q, u, uhat): residuals R_Q, R_U, R_Uhat and the
  * Jacobian blocks of eq. (C312) of every macro, kept in the workspace.

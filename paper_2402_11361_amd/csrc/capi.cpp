@@ -488,14 +488,15 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
     while (std::getline(in, line)) {
       std::istringstream ls(line);
       std::string a, pr;
-      int r, d, m0, m1, m2, p, batch, tpw, wide;
+      int r, d, m0, m1, m2, p, batch, tpw, wide, look;
       double ms;
-      if (ls >> a >> r >> pr >> d >> m0 >> m1 >> m2 >> p >> batch >> tpw >> wide >> ms) {
+      if (ls >> a >> r >> pr >> d >> m0 >> m1 >> m2 >> p >> batch >> tpw >> wide >> look >> ms) {
         std::ostringstream key;
         key << a << ' ' << r << ' ' << pr << ' ' << d << ' ' << m0 << ' ' << m1 << ' ' << m2 << ' ' << p << ' ' << batch;
         LuTune t;
         t.tpw = tpw;
         t.panel_wide = wide;
+        t.lookahead = look;
         if (tpw >= 4 && tpw % 4 == 0) cache[key.str()] = t;
       }
     }
@@ -526,12 +527,14 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
     // with the best of those; one untimed trial first (code loading)
     float best = 1e30f;
     LuTune pick;
-    const int cand[6][2] = {{32, 0}, {8, 0}, {16, 0}, {32, 0}, {64, 0}, {-1, 1}};
-    for (int ci = 0; ci < 6 && st == HDG_OK; ++ci) {
+    // then the look-ahead stream with the best so far
+    const int cand[7][3] = {{32, 0, 0}, {8, 0, 0}, {16, 0, 0}, {32, 0, 0}, {64, 0, 0}, {-1, 1, 0}, {-1, -1, 1}};
+    for (int ci = 0; ci < 7 && st == HDG_OK; ++ci) {
       {
         LuTune t;
         t.tpw = cand[ci][0] > 0 ? cand[ci][0] : pick.tpw;
-        t.panel_wide = cand[ci][1];
+        t.panel_wide = cand[ci][1] >= 0 ? cand[ci][1] : pick.panel_wide;
+        t.lookahead = cand[ci][2];
         h.tune[p32] = t;
         float tmin = 1e30f;
         for (int rep = 0; rep < 1 && st == HDG_OK; ++rep) {
@@ -555,7 +558,7 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
     h.tune[p32] = pick;
     ++timed;
     std::ostringstream line;
-    line << key.str() << ' ' << pick.tpw << ' ' << pick.panel_wide << ' ' << best;
+    line << key.str() << ' ' << pick.tpw << ' ' << pick.panel_wide << ' ' << pick.lookahead << ' ' << best;
     fresh.push_back(line.str());
   }
   (void)hipEventDestroy(ev0);
@@ -579,12 +582,24 @@ hdg_status hdg_class_count(hdg_ctx ctx, int* n_classes) {
   return HDG_OK;
 }
 
-hdg_status hdg_get_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int* tpw, int* panel_wide) {
+hdg_status hdg_set_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int tpw, int panel_wide, int lookahead) {
+  if (!ctx || macro_class < 0 || macro_class >= ctx->c.hm.n_classes || (prec != HDG_FP64 && prec != HDG_FP32) ||
+      tpw < 4 || tpw > 256 || tpw % 4 || (panel_wide != 0 && panel_wide != 1) || (lookahead != 0 && lookahead != 1))
+    return HDG_EINVAL;
+  LuTune& t = ctx->c.hcs[macro_class].tune[prec == HDG_FP32 ? 1 : 0];
+  t.tpw = tpw;
+  t.panel_wide = panel_wide;
+  t.lookahead = lookahead;
+  return HDG_OK;
+}
+
+hdg_status hdg_get_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int* tpw, int* panel_wide, int* lookahead) {
   if (!ctx || macro_class < 0 || macro_class >= ctx->c.hm.n_classes || (prec != HDG_FP64 && prec != HDG_FP32))
     return HDG_EINVAL;
   const LuTune& t = ctx->c.hcs[macro_class].tune[prec == HDG_FP32 ? 1 : 0];
   if (tpw) *tpw = t.tpw;
   if (panel_wide) *panel_wide = t.panel_wide;
+  if (lookahead) *lookahead = t.lookahead;
   return HDG_OK;
 }
 
@@ -925,6 +940,8 @@ hdg_status hdg_destroy(hdg_ctx ctx) {
   if (ctx->c.cap_stream) (void)hipStreamDestroy(ctx->c.cap_stream);
   for (auto s : ctx->c.lu_streams) (void)hipStreamDestroy(s);
   for (auto ev : ctx->c.lu_events) (void)hipEventDestroy(ev);
+  for (auto s : ctx->c.lu_pstreams) (void)hipStreamDestroy(s);
+  for (auto ev : ctx->c.lu_pevents) (void)hipEventDestroy(ev);
   for (void* p : ctx->c.dev_allocs) (void)hipFree(p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;

@@ -133,7 +133,10 @@ struct HdgContext {
   // streams on which the per-class eliminations run concurrently (created on
   // first use when the mesh has several macro classes), with fork/join events
   std::vector<hipStream_t> lu_streams;
-  std::vector<hipEvent_t> lu_events;  // element type of the condensed matrices in Wm: 0 FP64, 1 FP32
+  std::vector<hipEvent_t> lu_events;
+  // per class slot: the look-ahead panel stream and its two hand-off events
+  std::vector<hipStream_t> lu_pstreams;
+  std::vector<hipEvent_t> lu_pevents;  // element type of the condensed matrices in Wm: 0 FP64, 1 FP32
   std::string last_error;
 };
 

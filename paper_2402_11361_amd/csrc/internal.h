@@ -124,10 +124,12 @@ __host__ __device__ __forceinline__ size_t wtix(long long r, long long c, long l
 // Launch choices of the batched elimination, picked per macro class and
 // precision by hdg_autotune: tpw = 16-row tiles per workgroup of the
 // trailing update (4 waves), panel_wide = 1024-thread panel factorisation
-// (fewer rows per thread) where 512 threads would also do.
+// (fewer rows per thread) where 512 threads would also do, lookahead = the
+// next pair's factorisation on a second stream beside the trailing update.
 struct LuTune {
   int tpw = 32;
   int panel_wide = 0;
+  int lookahead = 0;
 };
 
 // ---- kernel launchers (defined in the .hip files) ----------------------

@@ -437,7 +437,8 @@ hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec) {
 
 template <class T>
 hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
-                        int n_cols, int* ipiv, int ipiv_stride, int* status, T* scratch, LuTune tune);
+                        int n_cols, int* ipiv, int ipiv_stride, int* status, T* scratch, LuTune tune,
+                        hipStream_t s2, hipEvent_t evA, hipEvent_t evF);
 
 hipError_t launch_face_precond(HdgContext& c) {
   const long long fs = c.fstride;
@@ -451,7 +452,7 @@ hipError_t launch_face_precond(HdgContext& c) {
     e = lu_eliminate<double>(c.stream, c.ws.FW + (size_t)s0 * fs, cnt, fs, c.ldf, nf, 2 * nf, 2 * nf,
                              c.ws.fpiv + (size_t)s0 * c.nf_max, c.nf_max,
                              reinterpret_cast<int*>(c.ws.small) + c.hm.n_chunks() * c.hm.n_classes, c.ws.Uinv,
-                             LuTune{});
+                             LuTune{}, nullptr, nullptr, nullptr);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

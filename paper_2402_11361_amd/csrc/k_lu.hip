@@ -626,7 +626,8 @@ __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs<T> g) {
 // then (256-byte aligned) batch 128 x 128 unit-lower block inverses (type T).
 template <class T>
 hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, int ld, int n_piv, int n_rows,
-                        int n_cols, int* ipiv, int ipiv_stride, int* status, T* scratch, LuTune tune) {
+                        int n_cols, int* ipiv, int ipiv_stride, int* status, T* scratch, LuTune tune,
+                        hipStream_t s2, hipEvent_t evA, hipEvent_t evF) {
   int* perm = reinterpret_cast<int*>(scratch + (size_t)batch * NB * NB);
   T* Linv = reinterpret_cast<T*>(
       (reinterpret_cast<uintptr_t>(perm + (size_t)batch * 2 * PERM_STRIDE) + 255) & ~uintptr_t(255));
@@ -637,71 +638,98 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
   // up to 12288: 512 threads, 24 rows each of 4-column sub-panels (register budget)
   const int TPW = tune.tpw;  // 16-row tiles per workgroup (TPW / 4 per wave)
   if (TPW < 4 || TPW % 4) return hipErrorInvalidValue;
-  auto panel = [&](int j0, int jb, int lcol0) {
+  auto panel = [&](hipStream_t q, int j0, int jb, int lcol0) {
     if (tune.panel_wide && rpt <= 1)
-      hipLaunchKernelGGL((k_panel<T, 1, 1024>), dim3(batch), dim3(1024), 0, s, a, j0, jb, lcol0);
+      hipLaunchKernelGGL((k_panel<T, 1, 1024>), dim3(batch), dim3(1024), 0, q, a, j0, jb, lcol0);
     else if (tune.panel_wide && rpt <= 4)
-      hipLaunchKernelGGL((k_panel<T, 2, 1024>), dim3(batch), dim3(1024), 0, s, a, j0, jb, lcol0);
-    else if (rpt <= 1) hipLaunchKernelGGL((k_panel<T, 1, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
-    else if (rpt <= 2) hipLaunchKernelGGL((k_panel<T, 2, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
-    else if (rpt <= 4) hipLaunchKernelGGL((k_panel<T, 4, 512>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
-    else if (n_piv <= 4 * 1024) hipLaunchKernelGGL((k_panel<T, 4, 1024>), dim3(batch), dim3(1024), 0, s, a, j0, jb, lcol0);
-    else hipLaunchKernelGGL((k_panel<T, 24, 512, 4>), dim3(batch), dim3(512), 0, s, a, j0, jb, lcol0);
+      hipLaunchKernelGGL((k_panel<T, 2, 1024>), dim3(batch), dim3(1024), 0, q, a, j0, jb, lcol0);
+    else if (rpt <= 1) hipLaunchKernelGGL((k_panel<T, 1, 512>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
+    else if (rpt <= 2) hipLaunchKernelGGL((k_panel<T, 2, 512>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
+    else if (rpt <= 4) hipLaunchKernelGGL((k_panel<T, 4, 512>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
+    else if (n_piv <= 4 * 1024) hipLaunchKernelGGL((k_panel<T, 4, 1024>), dim3(batch), dim3(1024), 0, q, a, j0, jb, lcol0);
+    else hipLaunchKernelGGL((k_panel<T, 24, 512, 4>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
   };
-  auto drows = [&](int j0, int jb) {  // L of the non-pivot rows: A_D,block U11^{-1}
+  auto drows = [&](hipStream_t q, int j0, int jb) {  // L of the non-pivot rows: A_D,block U11^{-1}
     if (n_rows <= n_piv) return;
-    hipLaunchKernelGGL(k_uinv<T>, dim3(batch), dim3(NB), 0, s, a, j0, jb, scratch);
+    hipLaunchKernelGGL(k_uinv<T>, dim3(batch), dim3(NB), 0, q, a, j0, jb, scratch);
     GemmArgs<T> g{W, mat_stride, ld, scratch, (long long)NB * NB, NB, 0, 0, j0, jb, j0, j0, j0 + jb, n_piv, n_rows, T(1), 0, TPW};
     const int ntile = (n_rows - n_piv + 15) / 16;
-    hipLaunchKernelGGL((k_gemm<T, 64>), dim3(1, (ntile + TPW - 1) / TPW, batch), dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_gemm<T, 64>), dim3(1, (ntile + TPW - 1) / TPW, batch), dim3(256), 0, q, g);
   };
-  // A22 -= L21 U12 for the strips [strip0, ...) with U12 in rows [j0, j0 + K) of W
-  auto update = [&](int j0, int K, int live0, int strip0, int nstrip, int col_end) {
+  // A22 -= L21 U12 for the strips [strip0, strip0 + nstrip) with U12 in rows [j0, j0 + K) of W
+  auto update = [&](hipStream_t q, int j0, int K, int live0, int strip0, int nstrip, int col_end) {
     if (n_rows <= live0 || nstrip <= 0) return;
     GemmArgs<T> g{W, mat_stride, ld, W, mat_stride, ld, 1, j0, j0, K, strip0, live0, col_end, live0, n_rows,
                   T(-1), 1, TPW};
     const int ntile = (n_rows - live0 + 15) / 16;
     dim3 grid(nstrip, (ntile + TPW - 1) / TPW, batch);
-    if (K > NB) hipLaunchKernelGGL((k_gemm<T, 2 * NB>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_gemm<T, NB>), grid, dim3(256), 0, s, g);
+    if (K > NB) hipLaunchKernelGGL((k_gemm<T, 2 * NB>), grid, dim3(256), 0, q, g);
+    else hipLaunchKernelGGL((k_gemm<T, NB>), grid, dim3(256), 0, q, g);
   };
   if (n_piv > 12 * 1024) return hipErrorInvalidValue;
+  // Two streams (s2 given): the factorisation of the next pair of blocks
+  // (panels, their non-pivot rows, the pair's own columns) runs on s2 while
+  // s finishes the trailing update of the columns beyond the next pair.
+  // Event evF hands a factored pair from s2 to s, evA hands the updated
+  // next-pair columns (and the free scratch) from s back to s2.  The row
+  // swaps of a pair reach the columns right of it only through its k_u12lin
+  // on s, after the previous update of those columns, as in the one-stream
+  // order.
+  const bool split = tune.lookahead && s2 != nullptr && evA != nullptr && evF != nullptr;
+  const hipStream_t sm = s, sp = split ? s2 : s;
+  hipError_t e;
+  auto handoff = [&](hipEvent_t ev, hipStream_t from, hipStream_t to) -> hipError_t {
+    if (!split) return hipSuccess;
+    hipError_t r = hipEventRecord(ev, from);
+    return r == hipSuccess ? hipStreamWaitEvent(to, ev, 0) : r;
+  };
+  if ((e = handoff(evA, sm, sp)) != hipSuccess) return e;  // fork
   for (int j0 = 0; j0 < n_piv; j0 += 2 * NB) {
     const int jb1 = std::min(NB, n_piv - j0);
-    panel(j0, jb1, j0);
-    drows(j0, jb1);
+    panel(sp, j0, jb1, j0);
+    drows(sp, j0, jb1);
     const bool two = (jb1 == NB) && (j0 + NB < n_piv);
     if (!two) {
+      if ((e = handoff(evF, sp, sm)) != hipSuccess) return e;
       const int live0 = j0 + jb1, strip0 = live0 / NC * NC;
       const int nstrip = (n_cols > live0) ? (n_cols - strip0 + NC - 1) / NC : 0;
       if (nstrip > 0) {
-        hipLaunchKernelGGL(k_u12<T>, dim3(nstrip, batch), dim3(256), 0, s, a, j0, jb1, strip0, ld);
-        update(j0, jb1, live0, strip0, nstrip, ld);
+        hipLaunchKernelGGL(k_u12<T>, dim3(nstrip, batch), dim3(256), 0, sm, a, j0, jb1, strip0, ld);
+        update(sm, j0, jb1, live0, strip0, nstrip, ld);
       }
+      if ((e = handoff(evA, sm, sp)) != hipSuccess) return e;
       continue;
     }
     // look-ahead: bring the second block's columns up to date with the first
-    hipLaunchKernelGGL(k_u12<T>, dim3(1, batch), dim3(256), 0, s, a, j0, NB, j0 + NB, j0 + NB + std::min(NB, n_piv - (j0 + NB)));
-    update(j0, NB, j0 + NB, j0 + NB, 1, j0 + NB + std::min(NB, n_piv - (j0 + NB)));
+    hipLaunchKernelGGL(k_u12<T>, dim3(1, batch), dim3(256), 0, sp, a, j0, NB, j0 + NB, j0 + NB + std::min(NB, n_piv - (j0 + NB)));
+    update(sp, j0, NB, j0 + NB, j0 + NB, 1, j0 + NB + std::min(NB, n_piv - (j0 + NB)));
     const int jb2 = std::min(NB, n_piv - (j0 + NB));
-    panel(j0 + NB, jb2, j0);  // also swaps the first block's L columns
-    drows(j0 + NB, jb2);
+    panel(sp, j0 + NB, jb2, j0);  // also swaps the first block's L columns
+    drows(sp, j0 + NB, jb2);
     // both blocks on the remaining strips with one K = 64 + jb2 update
     const int live0 = j0 + NB + jb2, strip0 = live0 / NC * NC;
     const int nstrip = (n_cols > live0) ? (n_cols - strip0 + NC - 1) / NC : 0;
+    if (nstrip > 0) hipLaunchKernelGGL(k_linv2<T>, dim3(batch), dim3(256), 0, sp, a, j0, jb2, Linv);
+    if ((e = handoff(evF, sp, sm)) != hipSuccess) return e;
     if (nstrip > 0) {
-      hipLaunchKernelGGL(k_linv2<T>, dim3(batch), dim3(256), 0, s, a, j0, jb2, Linv);
-      hipLaunchKernelGGL(k_u12lin<T>, dim3(nstrip, batch), dim3(256), 0, s, a, j0, jb2, strip0, Linv);
-      update(j0, NB + jb2, live0, strip0, nstrip, ld);
+      hipLaunchKernelGGL(k_u12lin<T>, dim3(nstrip, batch), dim3(256), 0, sm, a, j0, jb2, strip0, Linv);
+      // the next pair's two strips first, then hand them over
+      const int na = (live0 < n_piv && live0 % NC == 0) ? std::min(nstrip, 2) : nstrip;
+      update(sm, j0, NB + jb2, live0, strip0, na, ld);
+      if ((e = handoff(evA, sm, sp)) != hipSuccess) return e;
+      update(sm, j0, NB + jb2, live0, strip0 + na * NC, nstrip - na, ld);
+    } else if ((e = handoff(evA, sm, sp)) != hipSuccess) {
+      return e;
     }
   }
+  if ((e = handoff(evF, sp, sm)) != hipSuccess) return e;  // join
   return hipGetLastError();
 }
 
 template hipError_t lu_eliminate<double>(hipStream_t, double*, int, long long, int, int, int, int, int*, int, int*,
-                                         double*, LuTune);
+                                         double*, LuTune, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t lu_eliminate<float>(hipStream_t, float*, int, long long, int, int, int, int, int*, int, int*,
-                                        float*, LuTune);
+                                        float*, LuTune, hipStream_t, hipEvent_t, hipEvent_t);
 
 // Elimination scratch of one class: Uinv, permutations and Linv for `batch`
 // matrices, in doubles (with room for the 256-byte alignment of Linv).
@@ -734,6 +762,18 @@ hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only
     for (auto& ev : c.lu_events)
       if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
   }
+  // one panel stream and two hand-off events per class slot (look-ahead)
+  const int nslots = std::max(nstreams, 1);
+  if ((int)c.lu_pstreams.size() < nslots) {
+    for (auto s : c.lu_pstreams) (void)hipStreamDestroy(s);
+    for (auto ev : c.lu_pevents) (void)hipEventDestroy(ev);
+    c.lu_pstreams.assign(nslots, nullptr);
+    c.lu_pevents.assign(2 * nslots, nullptr);
+    for (auto& s : c.lu_pstreams)
+      if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return e;
+    for (auto& ev : c.lu_pevents)
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+  }
   if (nstreams > 0) {  // fork
     if ((e = hipEventRecord(c.lu_events[nstreams], c.stream)) != hipSuccess) return e;
     for (int i = 0; i < nstreams; ++i)
@@ -754,7 +794,10 @@ hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only
     int* ipiv = c.ws.ipiv + c.hm.class_ipiv_base[k] + (long long)c.hm.chunk_class_rank0[ck] * h.n_u;
     const int batch = cnt[k];
     const int n_rows = top_only ? h.n_u : h.n_rows;
-    hipStream_t s = nstreams > 0 ? c.lu_streams[i % nstreams] : c.stream;
+    const int slot = nstreams > 0 ? (int)(i % nstreams) : 0;
+    hipStream_t s = nstreams > 0 ? c.lu_streams[slot] : c.stream;
+    hipStream_t sp = c.lu_pstreams[slot];
+    hipEvent_t evA = c.lu_pevents[2 * slot], evF = c.lu_pevents[2 * slot + 1];
     double* scratch = c.ws.Uinv + scr;
     scr += class_scratch_doubles(batch);
     if (only_class >= 0 && k != only_class) continue;
@@ -762,10 +805,10 @@ hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only
     if (prec == 1)
       e = lu_eliminate<float>(s, reinterpret_cast<float*>(c.ws.Wm) + c.hm.chunk_class_w[ck], batch, h.wstride, h.ldw,
                               h.n_u, n_rows, h.n_cols, ipiv, h.n_u, status + k, reinterpret_cast<float*>(scratch),
-                              tune);
+                              tune, sp, evA, evF);
     else
       e = lu_eliminate<double>(s, c.ws.Wm + c.hm.chunk_class_w[ck], batch, h.wstride, h.ldw, h.n_u, n_rows, h.n_cols,
-                               ipiv, h.n_u, status + k, scratch, tune);
+                               ipiv, h.n_u, status + k, scratch, tune, sp, evA, evF);
     if (e != hipSuccess) return e;
   }
   if (nstreams > 0) {  // join

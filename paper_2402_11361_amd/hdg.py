@@ -68,7 +68,7 @@ EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_o
            "hdg_get_residuals", "hdg_precond_apply", "hdg_coarse_size", "hdg_coarse_restrict",
            "hdg_coarse_prolong", "hdg_mlp_param_count", "hdg_mlp_work_floats", "hdg_mlp_forward",
            "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking",
-           "hdg_autotune", "hdg_class_count", "hdg_get_tuning"]
+           "hdg_autotune", "hdg_class_count", "hdg_get_tuning", "hdg_set_tuning"]
 
 _lib = None
 
@@ -92,7 +92,8 @@ def load_library(path=LIB_PATH):
     ip = ctypes.POINTER(ctypes.c_int)
     lib.hdg_autotune.argtypes = [vp, i, ctypes.c_char_p, ip]
     lib.hdg_class_count.argtypes = [vp, ip]
-    lib.hdg_get_tuning.argtypes = [vp, i, i, ip, ip]
+    lib.hdg_get_tuning.argtypes = [vp, i, i, ip, ip, ip]
+    lib.hdg_set_tuning.argtypes = [vp, i, i, i, i, i]
     lib.hdg_linearize_stage.argtypes = [vp, vp, vp, vp, vp, dp, dp, dp, vp]
     lib.hdg_condense.argtypes = [vp, i, vp]
     lib.hdg_apply_global.argtypes = [vp, vp, vp]
@@ -247,9 +248,14 @@ class Context:
         return n.value
 
     def tuning(self, macro_class, prec=HDG_FP64):
-        tpw, wide = ctypes.c_int(0), ctypes.c_int(0)
-        self._check(self.lib.hdg_get_tuning(self.h, macro_class, prec, ctypes.byref(tpw), ctypes.byref(wide)))
-        return tpw.value, wide.value
+        """(tiles per workgroup, wide panel, look-ahead stream) of a class."""
+        tpw, wide, look = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        self._check(self.lib.hdg_get_tuning(self.h, macro_class, prec, ctypes.byref(tpw), ctypes.byref(wide),
+                                            ctypes.byref(look)))
+        return tpw.value, wide.value, look.value
+
+    def set_tuning(self, macro_class, prec, tpw, panel_wide=0, lookahead=0):
+        self._check(self.lib.hdg_set_tuning(self.h, macro_class, prec, tpw, panel_wide, lookahead))
 
     def bind_workspace(self, ws=None):
         """Allocate (torch) and bind the device workspace."""

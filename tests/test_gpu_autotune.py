@@ -32,8 +32,8 @@ def test_autotune_caches_and_keeps_parity(tmp_path):
     assert len(lines) == ncl
     for k, line in enumerate(lines):
         f = line.split()
-        assert f[2] == "fp64" and int(f[9]) in (8, 16, 32, 64) and int(f[10]) in (0, 1)
-        assert ctx.tuning(k, HDG_FP64) == (int(f[9]), int(f[10]))
+        assert f[2] == "fp64" and int(f[9]) in (8, 16, 32, 64) and int(f[10]) in (0, 1) and int(f[11]) in (0, 1)
+        assert ctx.tuning(k, HDG_FP64) == (int(f[9]), int(f[10]), int(f[11]))
     # the cache answers a second call without timing
     assert ctx.autotune(HDG_FP64, cache) == 0
     assert ctx.autotune(HDG_FP32, cache) == ncl
@@ -53,3 +53,34 @@ def test_autotune_caches_and_keeps_parity(tmp_path):
     ea = max(_rel(ctx.get_condensed(i)[0], cond[i]["Ahat"]) for i in lin)
     say(f"[autotune] FP32 A-hat {ea:.2e}")
     assert ea < 5e-4
+
+
+@pytest.mark.parametrize("case", [dict(dim=3, n_elem=4, m=2, p=2, periodic=True), CASE])
+@pytest.mark.parametrize("shape", [(16, 1, 1), (64, 0, 1), (8, 1, 0)])
+def test_forced_launch_shapes_keep_parity(case, shape):
+    """Every launch shape the autotuner may pick (the look-ahead stream
+    included) gives the oracle's condensed blocks."""
+    import torch
+    from paper_2402_11361_amd.hdg import HDG_FP64
+    say(f"[shapes] {shape}")
+    S, inp, ctx = make_pair(case)
+    for k in range(ctx.class_count()):
+        ctx.set_tuning(k, HDG_FP64, *shape)
+        assert ctx.tuning(k, HDG_FP64) == shape
+    d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
+    ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
+    lin = S.linearize(inp["q"], inp["u"], inp["uh"], w=inp["w"], dt=inp["dt"], dii=inp["dii"])
+    cond = S.condense(lin, "B")
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    ctx.condense(bhat, HDG_FP64)
+    for i in lin:
+        A_i, b_i = ctx.get_condensed(i)
+        assert _rel(A_i, cond[i]["Ahat"]) < 1e-9 and _rel(b_i, cond[i]["bhat"]) < 1e-9
+    # recovery re-uses the factors
+    A, b = S.assemble(cond)
+    x_ref = S.solve_direct(A, b)
+    dq = torch.zeros(ctx.n_q_tot, dtype=torch.float64, device="cuda")
+    du = torch.zeros(ctx.n_u_tot, dtype=torch.float64, device="cuda")
+    ctx.local_backsolve(to_dev(x_ref), dq, du)
+    dq_o, du_o = S.backsolve(lin, cond, x_ref)
+    assert _rel(du.cpu().numpy(), du_o) < 1e-9 and _rel(dq.cpu().numpy(), dq_o) < 1e-9
