@@ -31,7 +31,7 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by what the counters
 # read for a 1 GiB device copy in the same run (profiles/stage_solve_tgv24_m3_p2_fp64.md),
 # valid only while the kernel sources hash to `sha`.
-CONDENSE_TRAFFIC = {"sha": "2cc0a9ab23aa76d8", "bytes": 1133.0e9}
+CONDENSE_TRAFFIC = {"sha": "7646f1823be222e9", "bytes": 1225.5e9}
 CONDENSE_SOURCES = ("k_form.hip", "k_lu.hip")
 
 
@@ -269,6 +269,8 @@ def main():
     ap.add_argument("--big-steps", type=int, default=0,
                     help="also time this many DIRK(3,3) steps of the 48^3 workload (chunked condensation)")
     ap.add_argument("--tune-cache", default=None, help="text file of earlier autotuner choices (read and appended)")
+    ap.add_argument("--set-tuning", default=None, metavar="TPW,WIDE,LOOK",
+                    help="fixed elimination launch shape for every class instead of the autotuner (profiling)")
     ap.add_argument("--train-seeds", type=int, default=2)
     ap.add_argument("--train-vectors", type=int, default=40)
     ap.add_argument("--train-epochs", type=int, default=60)
@@ -305,7 +307,13 @@ def main():
     # elimination launch shapes per macro class from the autotuner, timed on
     # the linearisation at the initial state (outside the timed region)
     tuning = {}
-    if not args.no_autotune:
+    if args.set_tuning:
+        shape = [int(v) for v in args.set_tuning.split(",")]
+        for prec in (HDG_FP64, HDG_FP32):
+            for k in range(ctx.class_count()):
+                ctx.set_tuning(k, prec, *shape)
+        tuning = dict(fixed=shape)
+    elif not args.no_autotune:
         t0 = time.perf_counter()
         ctx.linearize_stage(q_init, u_init, uh_init, w, dt, dii, norms=False)
         for name, prec in (("fp64", HDG_FP64), ("fp32", HDG_FP32)):
