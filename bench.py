@@ -104,7 +104,12 @@ def uneven_variant(args, dev_fn, variants):
         e.record(stream)
         return e
 
-    if not args.no_autotune:
+    if args.set_tuning:
+        shape = [int(v) for v in args.set_tuning.split(",")]
+        for prec in (HDG_FP64, HDG_FP32):
+            for k in range(ctx.class_count()):
+                ctx.set_tuning(k, prec, *shape)
+    elif not args.no_autotune:
         t0 = time.perf_counter()
         ctx.linearize_stage(q_i, u_i, uh_i, w, dt, dii, norms=False)
         for prec in (HDG_FP64, HDG_FP32):
@@ -269,6 +274,10 @@ def main():
     ap.add_argument("--big-steps", type=int, default=0,
                     help="also time this many DIRK(3,3) steps of the 48^3 workload (chunked condensation)")
     ap.add_argument("--tune-cache", default=None, help="text file of earlier autotuner choices (read and appended)")
+    ap.add_argument("--plain-prec", choices=("fp64", "fp32"), default="fp64",
+                    help="condensation precision of the main timed variant (profiling of the FP32 path)")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="time only the uneven-macro 32^3 variant (profiling); prints its JSON")
     ap.add_argument("--set-tuning", default=None, metavar="TPW,WIDE,LOOK",
                     help="fixed elimination launch shape for every class instead of the autotuner (profiling)")
     ap.add_argument("--train-seeds", type=int, default=2)
@@ -284,6 +293,13 @@ def main():
     from paper_2402_11361_amd.driver import StageDriver, alexander_dirk33
     from paper_2402_11361_amd.hdg import HDG_BF16, HDG_FP32, HDG_FP64, Context, mesh_spec_box
 
+    if args.uneven_only:
+        dev0 = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+        variants = {}
+        uneven_variant(args, dev0, variants)
+        print(json.dumps(dict(metric=METRIC, unit="ms/DIRK-stage", n_gpus=1, data="synthetic", variants=variants)),
+              flush=True)
+        return
     cfg = dict(inputs.CONFIGS[args.config])
     spec = mesh_spec_box(cfg["dim"], cfg["n_elem"], cfg["m"], cfg["p"], cfg["lo"], cfg["hi"], cfg["periodic"])
     stream = torch.cuda.current_stream()
@@ -382,7 +398,8 @@ def main():
 
     nb, nu, nm = ctx.n_b_macro, ctx.n_u_macro, ctx.n_macros
     flops = condense_flops(cfg, nu, nb) * nm
-    plain = run_variant(HDG_FP64, HDG_FP64, args.steps, args.warmup)
+    main_prec = HDG_FP32 if args.plain_prec == "fp32" else HDG_FP64
+    plain = run_variant(main_prec, main_prec, args.steps, args.warmup)
     apply_ms = time_apply()
     ms_step = plain["ms_per_stage"]
     phase_ms, cond_calls = plain["phase_ms"], plain["cond_calls"]
@@ -440,19 +457,23 @@ def main():
     cond_tflops = flops / (cond_ms * 1e-3) / 1e12
     # dominant work: hdg_condense, one launch sequence per Newton step (MFMA-bound)
     traffic = CONDENSE_TRAFFIC["bytes"] if sources_sha() == CONDENSE_TRAFFIC["sha"] else None
-    roofline = dict(bound="mfma", achieved=round(cond_tflops, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                    frac=round(cond_tflops / PEAK_FP64_TFLOPS, 4), traffic=traffic,
+    peak = PEAK_FP64_TFLOPS if main_prec == HDG_FP64 else PEAK_FP32_TFLOPS
+    if main_prec != HDG_FP64:
+        traffic = None
+    roofline = dict(bound="mfma", achieved=round(cond_tflops, 3), peak=peak, unit="TFLOP/s",
+                    frac=round(cond_tflops / peak, 4), traffic=traffic,
                     kernel="hdg_condense: k_form + batched FP64 elimination (k_panel, k_uinv, k_u12, k_linv2, "
                            "k_u12lin, k_gemm) + face-preconditioner factorisation",
                     flops_per_launch=flops, ms_per_launch=round(cond_ms, 3), launches=len(cond_calls))
     out = dict(metric=METRIC, value=round(ms_step, 3), unit="ms/DIRK-stage", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_step, 3), higher_is_better=False, scaling="weak",
-               vs_baseline=None, dtype="f64", data="synthetic",
+               vs_baseline=None, dtype="f64" if main_prec == HDG_FP64 else "f32", data="synthetic",
                config=dict(workload=f"{args.config}: Taylor-Green 24^3 periodic hexes on [-pi,pi]^3, 3^3-element "
                                     f"macros (512), p=2, Mach 0.1, Re 1600, 1e-4 seeded noise; DIRK(3,3) stage 1 "
                                     f"solved by Newton to max(1e-10, 1e-8 |R0|), FGMRES(30) rtol {rtol} with "
                                     f"5 inner GMRES steps",
-                           n_macros=nm, n_u_macro=nu, n_b_macro=nb, n_glob=ctx.n_glob, variant="plain FP64"),
+                           n_macros=nm, n_u_macro=nu, n_b_macro=nb, n_glob=ctx.n_glob,
+                           variant="plain FP64" if main_prec == HDG_FP64 else "FP32 condensation"),
                phases_ms={k: round(v, 3) for k, v in phase_ms.items()},
                newton_its=newton_its, newton_res=plain["newton_res"],
                fgmres=dict(outer_its=outer, inner_its=inner),
