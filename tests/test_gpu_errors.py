@@ -1,0 +1,71 @@
+"""Error paths of the C ABI, forced from the host: calls without a workspace,
+bad arguments, a solve that runs out of iterations, and a non-finite state
+(which every kernel carries through as NaN; the elimination reports the
+zero pivot instead of picking a row)."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import make_pair, to_dev, say
+
+pytestmark = pytest.mark.gpu
+
+CASE = dict(dim=2, n_elem=4, m=2, p=2, periodic=True)
+
+
+def test_calls_without_workspace_and_bad_arguments():
+    import torch
+    from paper_2402_11361_amd.hdg import Context, HdgError, mesh_spec_box
+    say("[errors] no workspace / bad arguments")
+    spec = mesh_spec_box(2, 4, 2, 2, -math.pi, math.pi, True)
+    ctx = Context.from_mesh_spec(spec, Re=100.0, Mach=0.1)
+    b = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    with pytest.raises(HdgError, match="ENOMEM"):
+        ctx.condense(b)
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(HdgError, match="ENOMEM"):
+        ctx.bind_workspace(small)
+    ctx.bind_workspace()
+    with pytest.raises(HdgError, match="EINVAL"):
+        ctx.apply_global(b, b)  # x and y alias
+    with pytest.raises(HdgError, match="EINVAL"):
+        ctx.fgmres_solve(b, torch.zeros_like(b), restart=0)
+    with pytest.raises(HdgError, match="EINVAL"):
+        ctx.set_chunking(-1)
+    with pytest.raises(HdgError, match="EINVAL"):
+        ctx.set_tuning(0, 0, 6)  # tiles per workgroup not a multiple of 4
+    ctx.close()
+
+
+def test_solve_out_of_iterations_returns_best_iterate():
+    import torch
+    say("[errors] ENOCONV")
+    S, inp, ctx = make_pair(CASE)
+    d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
+    ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
+    b = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    ctx.condense(b)
+    x = torch.zeros_like(b)
+    info = ctx.fgmres_solve(b, x, rtol=1e-15, restart=5, max_outer=3, inner_its=1, allow_noconv=True)
+    assert not info["converged"] and info["outer_its"] == 3
+    assert 0 < info["res"] < info["res0"]
+    y = torch.zeros_like(b)
+    ctx.apply_global(x, y)
+    true_res = float(torch.linalg.norm(b - y))
+    assert abs(true_res - info["res"]) <= 1e-8 * info["res0"]
+
+
+def test_non_finite_state_is_reported():
+    from paper_2402_11361_amd.hdg import HdgError
+    import torch
+    say("[errors] ENAN and ESINGULAR")
+    S, inp, ctx = make_pair(CASE)
+    u = inp["u"].copy()
+    u[3] = np.nan
+    d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
+    with pytest.raises(HdgError, match="ENAN"):
+        ctx.linearize_stage(d["q"], to_dev(u), d["uh"], d["w"], inp["dt"], inp["dii"])
+    b = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    with pytest.raises(HdgError, match="ESINGULAR.*macro 0"):
+        ctx.condense(b)
