@@ -74,7 +74,7 @@ def uneven_variant(args, dev_fn, variants):
     from paper_2402_11361_amd import inputs
     from paper_2402_11361_amd.driver import StageDriver, alexander_dirk33
     from paper_2402_11361_amd.hdg import HDG_FP32, HDG_FP64, Context
-    cfg = dict(inputs.CONFIGS["C3"])
+    cfg = dict(inputs.CONFIGS["tgv32_uneven_p2"])
     seg = inputs.segments(cfg)
     spec = dict(dim=3, n_elem=[cfg["n_elem"]] * 3, lo=[cfg["lo"]] * 3, hi=[cfg["hi"]] * 3, periodic=[True] * 3,
                 seg_len=seg, p=cfg["p"])
@@ -145,7 +145,7 @@ def big_variant(args, dev_fn, variants):
     from paper_2402_11361_amd import inputs
     from paper_2402_11361_amd.driver import StageDriver
     from paper_2402_11361_amd.hdg import HDG_FP32, Context, mesh_spec_box
-    cfg = dict(inputs.CONFIGS["C5"])
+    cfg = dict(inputs.CONFIGS["tgv48_m4_p2"])
     spec = mesh_spec_box(3, cfg["n_elem"], cfg["m"], cfg["p"], cfg["lo"], cfg["hi"], True)
     stream = torch.cuda.current_stream()
     ctx = Context.from_mesh_spec(spec, Re=cfg["Re"], Mach=cfg["mach"], stream=stream.cuda_stream)
@@ -263,7 +263,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="C2")
+    ap.add_argument("--config", default="tgv24_m3_p2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--applies", type=int, default=20)
     ap.add_argument("--plain-only", action="store_true", help="time only the plain FP64 variant")

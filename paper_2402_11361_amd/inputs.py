@@ -56,19 +56,19 @@ def noise(seed, shape, amp):
     return amp * rng.uniform(-1.0, 1.0, size=shape)
 
 
-# Workloads (mesh, physics, time step) of the five benchmark configurations.
+# Workloads (mesh, physics, solver tolerance), named by state, mesh, macro size and degree.
 CONFIGS = {
-    "C1": dict(dim=2, n_elem=16, m=4, p=2, lo=0.0, hi=1.0, periodic=False, state="shear",
+    "shear16_m4_p2": dict(dim=2, n_elem=16, m=4, p=2, lo=0.0, hi=1.0, periodic=False, state="shear",
                mach=0.2, Re=100.0, noise=1e-3, rtol=1e-10),
-    "C2": dict(dim=3, n_elem=24, m=3, p=2, lo=-np.pi, hi=np.pi, periodic=True, state="tgv",
+    "tgv24_m3_p2": dict(dim=3, n_elem=24, m=3, p=2, lo=-np.pi, hi=np.pi, periodic=True, state="tgv",
                mach=0.1, Re=1600.0, noise=1e-4, rtol=1e-8),
-    "C4": dict(dim=3, n_elem=32, m=4, p=3, lo=-np.pi, hi=np.pi, periodic=True, state="tgv",
+    "tgv32_m4_p3": dict(dim=3, n_elem=32, m=4, p=3, lo=-np.pi, hi=np.pi, periodic=True, state="tgv",
                mach=0.1, Re=1600.0, noise=1e-4, rtol=1e-8),
-    "C5": dict(dim=3, n_elem=48, m=4, p=2, lo=-np.pi, hi=np.pi, periodic=True, state="tgv",
+    "tgv48_m4_p2": dict(dim=3, n_elem=48, m=4, p=2, lo=-np.pi, hi=np.pi, periodic=True, state="tgv",
                mach=0.1, Re=1600.0, noise=1e-4, rtol=1e-8),
     # macros of uneven sizes: every axis of the 32^3 mesh cut into seeded
     # segments of 2, 3 or 4 elements (one degree for the whole mesh)
-    "C3": dict(dim=3, n_elem=32, m=None, parts=(2, 3, 4), seg_seed=3, p=2, lo=-np.pi, hi=np.pi, periodic=True,
+    "tgv32_uneven_p2": dict(dim=3, n_elem=32, m=None, parts=(2, 3, 4), seg_seed=3, p=2, lo=-np.pi, hi=np.pi, periodic=True,
                state="tgv", mach=0.1, Re=1600.0, noise=1e-4, rtol=1e-8),
 }
 

@@ -19,7 +19,7 @@ def test_tgv24_sampled_macros_and_global_properties():
     from oracle.system import System
     from paper_2402_11361_amd import inputs
     from paper_2402_11361_amd.hdg import Context, mesh_spec_box
-    cfg = dict(inputs.CONFIGS["C2"])
+    cfg = dict(inputs.CONFIGS["tgv24_m3_p2"])
     say("[fullsize] building oracle mesh and inputs")
     M = box_mesh(3, cfg["n_elem"], cfg["m"], cfg["p"], lo=cfg["lo"], hi=cfg["hi"], periodic=True)
     S = System(M, Phys(Re=cfg["Re"], Mach=cfg["mach"]))
@@ -135,12 +135,12 @@ def test_tgv48_m4_p2_chunked_sampled_macros_and_global_properties():
     """48^3, 4^3-element macros (1728), p = 2, FP64: the augmented matrices
     (510 GB) do not fit, so the condensation runs in chunks."""
     import torch
-    S, ctx, inp, d, per = _setup_tgv("C5")
+    S, ctx, inp, d, per = _setup_tgv("tgv48_m4_p2")
     assert 0 < per < ctx.n_macros
-    say("[fullsize C5] GPU linearise")
+    say("[fullsize tgv48] GPU linearise")
     nrm = ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
     sample = [0, 1000]
-    say("[fullsize C5] oracle linearise of sampled macros")
+    say("[fullsize tgv48] oracle linearise of sampled macros")
     lin = S.linearize(inp["q"], inp["u"], inp["uh"], w=inp["w"], dt=inp["dt"], dii=inp["dii"], macros=sample)
     cond = S.condense(lin, "B")
     rq, ru, rb = (t.cpu().numpy() for t in ctx.get_residuals())
@@ -148,14 +148,14 @@ def test_tgv48_m4_p2_chunked_sampled_macros_and_global_properties():
         L = lin[i]
         assert np.abs(ru[S.u_off[i]:S.u_off[i + 1]] - L["RU"]).max() < 1e-10 * np.abs(L["RU"]).max()
         assert np.abs(rq[S.q_off[i]:S.q_off[i + 1]] - L["RQ"]).max() < 1e-10 * np.abs(L["RQ"]).max()
-    say("[fullsize C5] GPU condense (chunked, FP64)")
+    say("[fullsize tgv48] GPU condense (chunked, FP64)")
     ctx._bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
     ctx.condense(ctx._bhat)
     for i in sample:
         A_i, b_i = ctx.get_condensed(i)
         ea = np.abs(A_i - cond[i]["Ahat"]).max() / np.abs(cond[i]["Ahat"]).max()
         eb = np.abs(b_i - cond[i]["bhat"]).max() / np.abs(cond[i]["bhat"]).max()
-        say(f"[fullsize C5] macro {i}: A-hat {ea:.2e} b-hat {eb:.2e}")
+        say(f"[fullsize tgv48] macro {i}: A-hat {ea:.2e} b-hat {eb:.2e}")
         assert ea < 1e-9 and eb < 1e-9
     from paper_2402_11361_amd.hdg import HDG_FP64
     _solve_recover_and_check_newton(ctx, d, inp, nrm, 1e-8, HDG_FP64)
@@ -170,8 +170,8 @@ def test_tgv32_m4_p3_chunked_fp32_residuals_and_global_properties():
     condensed operator is the Jacobian of the residual."""
     import torch
     from paper_2402_11361_amd.hdg import HDG_FP32
-    S, ctx, inp, d, per = _setup_tgv("C4")
-    say("[fullsize C4] GPU linearise")
+    S, ctx, inp, d, per = _setup_tgv("tgv32_m4_p3")
+    say("[fullsize tgv32 p3] GPU linearise")
     nrm = ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
     sample = [0, 300, 511]
     res = S.macro_residuals(inp["q"], inp["u"], inp["uh"], w=inp["w"], dt=inp["dt"], dii=inp["dii"], macros=sample)
@@ -180,7 +180,7 @@ def test_tgv32_m4_p3_chunked_fp32_residuals_and_global_properties():
         RQ_i, RU_i, _ = res[i]
         assert np.abs(ru[S.u_off[i]:S.u_off[i + 1]] - RU_i).max() < 1e-10 * np.abs(RU_i).max()
         assert np.abs(rq[S.q_off[i]:S.q_off[i + 1]] - RQ_i).max() < 1e-10 * np.abs(RQ_i).max()
-    say("[fullsize C4] GPU condense (chunked, FP32)")
+    say("[fullsize tgv32 p3] GPU condense (chunked, FP32)")
     ctx._bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
     ctx.condense(ctx._bhat, HDG_FP32)
     _solve_recover_and_check_newton(ctx, d, inp, nrm, 1e-8, HDG_FP32)
