@@ -11,6 +11,7 @@ its own over repeated calls (HBM roofline).  The CPU baseline runs the
 oracle (test infrastructure) on a bounded sample of the same workload.
 """
 import argparse
+import gc
 import json
 import math
 import os
@@ -175,6 +176,62 @@ def big_variant(args, dev_fn, variants):
     ctx.close()
 
 
+def learned_p3_variant(args, dev_fn, variants):
+    """The learned coarse correction on the 32^3 mesh with 4^3-element macros
+    at p = 3 (512 macros, chunked FP32 condensation): pairs harvested from a
+    plain solve on the seed-100 state, evaluated on the held-out seed-200
+    state (first Newton step), plain and learned preconditioner."""
+    import torch
+    from paper_2402_11361_amd import inputs
+    from paper_2402_11361_amd.hdg import HDG_FP32, Context, mesh_spec_box
+    from paper_2402_11361_amd.learned import CoarseCorrection
+    cfg = dict(inputs.CONFIGS["tgv32_m4_p3"])
+    spec = mesh_spec_box(3, cfg["n_elem"], cfg["m"], cfg["p"], cfg["lo"], cfg["hi"], True)
+    stream = torch.cuda.current_stream()
+    ctx = Context.from_mesh_spec(spec, Re=cfg["Re"], Mach=cfg["mach"], stream=stream.cuda_stream)
+    free, _ = torch.cuda.mem_get_info()
+    per = ctx.fit_chunking(free - (12 << 30))
+    ctx.bind_workspace()
+    dt = inputs.cfl_dt(cfg)
+    dii = 1.0 / 0.435866521508459
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+
+    def condense_state(seed):
+        u0, q0, uh0 = workload_arrays(ctx, cfg, seed=seed)
+        q, u, uh = dev_fn(q0), dev_fn(u0), dev_fn(uh0)
+        ctx.linearize_stage(q, u, uh, -dii * u, dt, dii)
+        ctx.condense(bhat, HDG_FP32)
+
+    t0 = time.perf_counter()
+    cc = CoarseCorrection(ctx, hidden=256, max_batch=1024, seed=0)
+    condense_state(100)
+    cc.harvest(bhat, n_vectors=args.train_vectors, inner_prec=HDG_FP32)
+    X, T = torch.cat(cc.X), torch.cat(cc.T)
+    loss0 = cc.eval_loss(X, T)
+    cc.train(epochs=args.train_epochs, lr=1e-3, batch=1024)
+    loss1 = cc.eval_loss(X, T)
+    cc.bind()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print(f"[bench] p=3 learned: {cc.n_pairs()} pairs, loss {loss0:.3e} -> {loss1:.3e}", file=sys.stderr, flush=True)
+    condense_state(200)
+    evals = {}
+    for name, lrn in (("plain", False), ("learned", True)):
+        x = torch.zeros_like(bhat)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        info = ctx.fgmres_solve(bhat, x, rtol=cfg["rtol"], restart=30, max_outer=300, inner_its=5,
+                                inner_prec=HDG_FP32, use_learned=lrn)
+        torch.cuda.synchronize()
+        evals[name] = dict(outer_its=info["outer_its"], inner_its=info["inner_its"], ms=round(1e3 * (time.perf_counter() - ts), 1),
+                           fallbacks=info["fallbacks"], converged=info["converged"])
+    variants["tgv32_m4_p3_learned"] = dict(
+        workload=f"32^3 periodic Taylor-Green, 4^3-element macros (512), p=3, n_glob {ctx.n_glob}; chunked FP32 "
+                 f"condensation ({per} macros per chunk); train on seed 100, evaluate on seed 200",
+        pairs=cc.n_pairs(), loss_initial=loss0, loss_final=loss1, train_s=round(t1 - t0, 1), solve=evals)
+    ctx.close()
+
+
 def train_learned(ctx, cfg, dev, dii, dt, args):
     """Train the learned coarse correction on pairs harvested from plain FGMRES
     solves of the first Newton step on states with other noise seeds (1, 2, ...);
@@ -271,6 +328,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-macro 32^3 variant")
     ap.add_argument("--graph-steps", type=int, default=10, help="FGMRES steps per captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default elimination launch shapes")
+    ap.add_argument("--learned-p3", action="store_true",
+                    help="also train and evaluate the learned correction on the 32^3 p=3 workload")
     ap.add_argument("--big-steps", type=int, default=0,
                     help="also time this many DIRK(3,3) steps of the 48^3 workload (chunked condensation)")
     ap.add_argument("--tune-cache", default=None, help="text file of earlier autotuner choices (read and appended)")
@@ -491,13 +550,18 @@ def main():
         gc.collect()
         torch.cuda.empty_cache()
         uneven_variant(args, dev, variants)
-    if args.big_steps > 0:
+    if args.big_steps > 0 or args.learned_p3:
         if "ctx" in locals():
             ctx.close()
             del ctx
         import gc
         gc.collect()
         torch.cuda.empty_cache()
+    if args.learned_p3:
+        learned_p3_variant(args, dev, variants)
+        gc.collect()
+        torch.cuda.empty_cache()
+    if args.big_steps > 0:
         big_variant(args, dev, variants)
     print(json.dumps(out), flush=True)
 

@@ -371,6 +371,7 @@ class Context:
         if getattr(self, "h", None):
             self.lib.hdg_destroy(self.h)
             self.h = None
+        self.ws = None  # the workspace goes back to torch's allocator
 
     def __del__(self):
         try:
