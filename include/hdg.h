@@ -233,8 +233,9 @@ hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, co
  * of eq. (C44).  Also factors the face blocks of A_uhat-uhat used by the
  * preconditioner.
  * prec = HDG_FP64: formation and elimination in FP64 (FP64 MFMA).
- * prec = HDG_FP32: the augmented matrices are formed (accumulated in FP64)
- *   and stored in FP32 and eliminated with FP32 arithmetic (FP32 MFMA); the
+ * prec = HDG_FP32: the augmented matrices are formed with FP32 sums (g of
+ *   eq. ASC2b in FP64, kept outside the matrix) and stored in FP32 and
+ *   eliminated with FP32 arithmetic (FP32 MFMA); the
  *   condensed blocks, b-hat, the operator of hdg_apply_global and the factors
  *   used by hdg_local_backsolve then carry FP32 rounding (vectors, sums and
  *   the recovery stay FP64).  A Newton iteration whose residuals are

@@ -480,7 +480,7 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
   std::string arch(prop.gcnArchName);
   arch = arch.substr(0, arch.find(':'));
   // cache: one line per (arch, runtime, precision, class shape, batch):
-  //   key fields ... tpw panel_wide ms
+  //   arch runtime prec dim m0 m1 m2 p batch | tpw panel_wide lookahead ms
   std::map<std::string, LuTune> cache;
   if (cache_path) {
     std::ifstream in(cache_path);
@@ -497,7 +497,8 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
         t.tpw = tpw;
         t.panel_wide = wide;
         t.lookahead = look;
-        if (tpw >= 4 && tpw % 4 == 0) cache[key.str()] = t;
+        if (tpw >= 4 && tpw <= 256 && tpw % 4 == 0 && (wide == 0 || wide == 1) && (look == 0 || look == 1))
+          cache[key.str()] = t;
       }
     }
   }

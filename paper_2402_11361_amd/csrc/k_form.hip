@@ -45,9 +45,9 @@ __device__ __forceinline__ void digits(int x, int base, int d, int* out) {
 //   face targets  row_rr[n_u + nf_off[2k+s] + cp*nf + j(b_tan)] += sgn_face * sign_s * sum_bk coef * Minv_k[e_k p + b_k][end_s]
 // (row_rr = row + rr * ldr).  The coefficient functor returns 0 for element
 // nodes that carry none (trace rows use only the nodes of their sub-face).
-template <int NR, int NT, class Coef>
+template <int NR, int NT, class TL, class Coef>
 __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, double sgn_line, double sgn_face,
-                              double* row, int ldr, int tid) {
+                              TL* row, int ldr, int tid) {
   const int d = cd.dim, p = cd.p, A1 = p + 1, ns = cd.ns;
   int eidx[3] = {0, 0, 0};
   {
@@ -80,7 +80,7 @@ __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, doubl
     }
     const int col = cp * cd.N + node0 + n * stride[k];
 #pragma unroll
-    for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += sgn_line * s[rr];
+    for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += (TL)(sgn_line * s[rr]);
   }
   // face targets on the two macro faces normal to k
   for (int i = tid; i < 2 * ns * T; i += NT) {
@@ -111,7 +111,7 @@ __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, doubl
     const int lf = 2 * k + sidx;
     const int col = cd.n_u + cd.nf_off[lf] + cp * cd.nf_nodes[lf] + j;
 #pragma unroll
-    for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += sgn_face * sgn * s[rr];
+    for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += (TL)(sgn_face * sgn * s[rr]);
   }
 }
 
@@ -133,14 +133,20 @@ __device__ void block_sum(double* v, double* red, int tid) {
   }
 }
 
-// The rows are accumulated in FP64 and stored as TW (double or float).
+// The rows are accumulated and stored as TW (double or float; the f and g
+// sums in FP64).
 // One workgroup per row group; NR = 1: group = one row (rows of all macros
 // numbered consecutively by MeshDev::row_off); NR = n_s: group = the n_s
 // component rows of one u-node or one trace node (row_off / n_s groups
 // before each macro).  Each macro takes the layout of its class.
 template <class TW, int NR, int NT>
 __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __restrict__ Wm) {
-  extern __shared__ double row[];
+  // LDS rows and staged coefficients in the storage type: FP64 for the FP64
+  // path; FP32 for the FP32 path (its sums carry no cancellation beyond
+  // FP32 rounding, and half the LDS lets two workgroups share a CU)
+  using TL = TW;
+  extern __shared__ __align__(16) unsigned char form_smem[];
+  TL* row = reinterpret_cast<TL*>(form_smem);
   __shared__ double red[NR * (NT / 64)];
   const int tid = threadIdx.x;
   const long long G = fp.group0 + blockIdx.x;
@@ -151,8 +157,8 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
   const int ns = cd.ns, d = cd.dim, A = cd.A, T = cd.T, N = cd.N;
   const int nsA = fp.nsA, dnsA = fp.dnsA;
   const int n_cols = cd.n_cols, ldr = n_cols;
-  double* sc = row + fp.coef_off;  // staged coefficient rows
-  for (int i = tid; i < NR * n_cols; i += NT) row[i] = 0.0;
+  TL* sc = row + fp.coef_off;  // staged coefficient rows
+  for (int i = tid; i < NR * n_cols; i += NT) row[i] = TL(0);
   // rows of the group: r_rr = r0 + rr * rstride
   int r0, rstride;
   bool urow;
@@ -201,11 +207,11 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
       const int* en = cd.elem_nodes + (size_t)e * A;
       __syncthreads();
       // the NR rows of A_uq^e, read by every line and face target, go to LDS
-      for (int i = tid; i < NR * dnsA; i += NT) sc[i] = auq[(i / dnsA) * sq + i % dnsA];
+      for (int i = tid; i < NR * dnsA; i += NT) sc[i] = (TL)auq[(i / dnsA) * sq + i % dnsA];
       for (int i = tid; i < nsA; i += NT) {
         const int col = (i / A) * N + en[i % A];
 #pragma unroll
-        for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += auu[rr * su + i];
+        for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += (TL)auu[rr * su + i];
       }
       __syncthreads();
       // f: A_uq A_qq^{-1} R_Q
@@ -213,11 +219,11 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
         const int lc = i / A, b = i % A;
         const double rq = RQt[(size_t)lc * N + en[b]];
 #pragma unroll
-        for (int rr = 0; rr < NR; ++rr) fpart[rr] += sc[rr * dnsA + i] * rq;
+        for (int rr = 0; rr < NR; ++rr) fpart[rr] += auq[rr * sq + i] * rq;  // FP64 coefficients
       }
       for (int k = 0; k < d; ++k) {
         if (k > 0) __syncthreads();
-        auto coef = [&](int rr, int kk, int cp, int b) { return sc[rr * dnsA + (kk * ns + cp) * A + b]; };
+        auto coef = [&](int rr, int kk, int cp, int b) { return (double)sc[rr * dnsA + (kk * ns + cp) * A + b]; };
         add_direction<NR, NT>(cd, e, k, coef, -1.0, 1.0, row, ldr, tid);
       }
       // A_u,uh on the element's macro-boundary faces through node a
@@ -234,7 +240,7 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
           const int cp = i / T, tp = i % T;
           const int col = cd.n_u + cd.nf_off[lf2] + cp * nf2 + cd.sub_tid[(size_t)sid * T + tp];
 #pragma unroll
-          for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += aub[(size_t)((c0 + rr) * T + ta) * nst + i];
+          for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += (TL)aub[(size_t)((c0 + rr) * T + ta) * nst + i];
         }
       }
     }
@@ -242,7 +248,7 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
     if (tid == 0)
 #pragma unroll
       for (int rr = 0; rr < NR; ++rr)
-        row[rr * ldr + n_cols - 1] = fpart[rr] - fp.RU[md.u_off[macro] + r0 + rr * rstride];
+        row[rr * ldr + n_cols - 1] = (TL)(fpart[rr] - fp.RU[md.u_off[macro] + r0 + rr * rstride]);
   } else {
     // ---- trace rows (lf, c0 + rr, j) ----
     const int tj = cd.tn_base[lf] + j;
@@ -260,15 +266,15 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
       const int* finv = cd.finv + (size_t)lf * A;
       __syncthreads();
       const int dnst = d * nst;
-      for (int i = tid; i < NR * dnst; i += NT) sc[i] = abq[(i / dnst) * sbq + i % dnst];
+      for (int i = tid; i < NR * dnst; i += NT) sc[i] = (TL)abq[(i / dnst) * sbq + i % dnst];
       for (int i = tid; i < nst; i += NT) {
         const int cp = i / T, tp = i % T;
         const int cu = cp * N + en[fn[tp]];
         const int cb = cd.n_u + cd.nf_off[lf] + cp * nf + cd.sub_tid[(size_t)sid * T + tp];
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
-          row[rr * ldr + cu] += abu[rr * sb + i];
-          row[rr * ldr + cb] += abb[rr * sb + i];
+          row[rr * ldr + cu] += (TL)abu[rr * sb + i];
+          row[rr * ldr + cb] += (TL)abb[rr * sb + i];
         }
       }
       __syncthreads();
@@ -276,13 +282,13 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
         const int lc = i / T, tp = i % T;
         const double rq = RQt[(size_t)lc * N + en[fn[tp]]];
 #pragma unroll
-        for (int rr = 0; rr < NR; ++rr) fpart[rr] += sc[rr * dnst + i] * rq;
+        for (int rr = 0; rr < NR; ++rr) fpart[rr] += abq[rr * sbq + i] * rq;  // FP64 coefficients (g)
       }
       for (int k = 0; k < d; ++k) {
         if (k > 0) __syncthreads();
         auto coef = [&](int rr, int kk, int cp, int b) {
           const int tb = finv[b];
-          return tb < 0 ? 0.0 : sc[rr * dnst + (kk * ns + cp) * T + tb];
+          return tb < 0 ? 0.0 : (double)sc[rr * dnst + (kk * ns + cp) * T + tb];
         };
         add_direction<NR, NT>(cd, e, k, coef, -1.0, 1.0, row, ldr, tid);
       }
@@ -295,9 +301,9 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
         const double gv = fpart[rr] - fp.RBloc[md.b_off[macro] + rho];
         if (fp.gloc) {
           fp.gloc[md.b_off[macro] + rho] = gv;
-          row[rr * ldr + n_cols - 1] = 0.0;
+          row[rr * ldr + n_cols - 1] = TL(0);
         } else {
-          row[rr * ldr + n_cols - 1] = gv;
+          row[rr * ldr + n_cols - 1] = (TL)gv;
         }
       }
     }
@@ -312,8 +318,8 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
 
 // Row buffers of the largest class and its staged coefficient rows
 // (A_uq^e rows: d n_s A values; trace rows use d n_s T <= that).
-size_t form_lds_bytes(const HdgContext& c, int nr) {
-  return sizeof(double) * (size_t)nr * ((size_t)c.n_cols + (size_t)c.dnsA);
+size_t form_lds_bytes(const HdgContext& c, int nr, size_t elem) {
+  return elem * (size_t)nr * ((size_t)c.n_cols + (size_t)c.dnsA);
 }
 
 template <class TW, int NR, int NT>
@@ -323,7 +329,7 @@ hipError_t form_launch(HdgContext& c, int m0, int m1, TW* W, double* gloc, int o
               NR * c.n_cols, only_class};
   const long long nblk = (c.hm.row_off[m1] - c.hm.row_off[m0]) / NR;
   if (nblk <= 0) return hipSuccess;
-  const size_t shm = form_lds_bytes(c, NR);
+  const size_t shm = form_lds_bytes(c, NR, sizeof(TW));
   hipLaunchKernelGGL((k_form<TW, NR, NT>), dim3((unsigned)nblk), dim3(NT), shm, c.stream, c.md, fp, W);
   return hipGetLastError();
 }
@@ -338,7 +344,7 @@ hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class) 
   // cancels between the two sides of a face in the assembled b-hat)
   double* gloc = prec == 1 ? c.ws.gloc : nullptr;
   const int ns = c.hm.ns;
-  const bool grouped = form_lds_bytes(c, ns) <= 150 * 1024;
+  const bool grouped = form_lds_bytes(c, ns, prec == 1 ? sizeof(float) : sizeof(double)) <= 150 * 1024;
   if (prec == 1) {
     float* W = reinterpret_cast<float*>(c.ws.Wm);
     if (!grouped) return form_launch<float, 1, 256>(c, m0, m1, W, gloc, only_class);
