@@ -542,25 +542,20 @@ def main():
                roofline=roofline, variants=variants, autotune=tuning)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, newton_its)
+    # the other workloads need the device memory of the 24^3 workspace
+    ctx.close()
+
+    def free_device_memory():
+        gc.collect()
+        torch.cuda.empty_cache()
+
+    free_device_memory()
     if not args.plain_only and not args.no_uneven:
-        # free the 24^3 workspace first
-        ctx.close()
-        del ctx
-        import gc
-        gc.collect()
-        torch.cuda.empty_cache()
         uneven_variant(args, dev, variants)
-    if args.big_steps > 0 or args.learned_p3:
-        if "ctx" in locals():
-            ctx.close()
-            del ctx
-        import gc
-        gc.collect()
-        torch.cuda.empty_cache()
+        free_device_memory()
     if args.learned_p3:
         learned_p3_variant(args, dev, variants)
-        gc.collect()
-        torch.cuda.empty_cache()
+        free_device_memory()
     if args.big_steps > 0:
         big_variant(args, dev, variants)
     print(json.dumps(out), flush=True)
