@@ -33,6 +33,7 @@ struct FormPtrs {
   long long group0;  // first row group of the launch (groups of all macros numbered consecutively)
   int coef_off;      // LDS offset (doubles) of the staged coefficient rows, after the row buffers
   int only_class;    // >= 0: rows of other macro classes are skipped
+  int split_cols;    // >= 0: grouped launch takes classes with n_cols <= split_cols, single-row launch the rest
 };
 
 __device__ __forceinline__ void digits(int x, int base, int d, int* out) {
@@ -154,6 +155,7 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
   const int g = (int)(G - md.row_off[macro] / NR);
   if (fp.only_class >= 0 && md.macro_class[macro] != fp.only_class) return;
   const ClassDev& cd = class_of(md, macro);
+  if (fp.split_cols >= 0 && (NR > 1) != (cd.n_cols <= fp.split_cols)) return;
   const int ns = cd.ns, d = cd.dim, A = cd.A, T = cd.T, N = cd.N;
   const int nsA = fp.nsA, dnsA = fp.dnsA;
   const int n_cols = cd.n_cols, ldr = n_cols;
@@ -316,40 +318,52 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
   }
 }
 
-// Row buffers of the largest class and its staged coefficient rows
-// (A_uq^e rows: d n_s A values; trace rows use d n_s T <= that).
-size_t form_lds_bytes(const HdgContext& c, int nr, size_t elem) {
-  return elem * (size_t)nr * ((size_t)c.n_cols + (size_t)c.dnsA);
+// Row buffers (n_cols of the largest class taken) and staged coefficient
+// rows (A_uq^e rows: d n_s A values; trace rows use d n_s T <= that).
+size_t form_lds_bytes(const HdgContext& c, int nr, size_t elem, int n_cols) {
+  return elem * (size_t)nr * ((size_t)n_cols + (size_t)c.dnsA);
 }
 
 template <class TW, int NR, int NT>
-hipError_t form_launch(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only_class) {
+hipError_t form_launch(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only_class, int n_cols,
+                       int split_cols) {
   FormPtrs fp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.ws.RQt, c.ws.RBloc, gloc,
               c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.hm.row_off[m0] / NR,
-              NR * c.n_cols, only_class};
+              NR * n_cols, only_class, split_cols};
   const long long nblk = (c.hm.row_off[m1] - c.hm.row_off[m0]) / NR;
   if (nblk <= 0) return hipSuccess;
-  const size_t shm = form_lds_bytes(c, NR, sizeof(TW));
+  const size_t shm = form_lds_bytes(c, NR, sizeof(TW), n_cols);
   hipLaunchKernelGGL((k_form<TW, NR, NT>), dim3((unsigned)nblk), dim3(NT), shm, c.stream, c.md, fp, W);
   return hipGetLastError();
 }
 
+template <class TW>
+hipError_t form_all(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only_class) {
+  // classes whose n_s row buffers fit in LDS go to the grouped launch
+  const int ns = c.hm.ns;
+  int cols_g = -1, cols_1 = -1;
+  for (const HostClass& k : c.hcs) {
+    if (form_lds_bytes(c, ns, sizeof(TW), k.n_cols) <= 150 * 1024) cols_g = std::max(cols_g, k.n_cols);
+    else cols_1 = std::max(cols_1, k.n_cols);
+  }
+  const int split = (cols_g >= 0 && cols_1 >= 0) ? cols_g : -1;
+  hipError_t e = hipSuccess;
+  if (cols_g >= 0)
+    e = ns == 5 ? form_launch<TW, 5, 512>(c, m0, m1, W, gloc, only_class, cols_g, split)
+                : form_launch<TW, 4, 512>(c, m0, m1, W, gloc, only_class, cols_g, split);
+  if (e == hipSuccess && cols_1 >= 0) e = form_launch<TW, 1, 256>(c, m0, m1, W, gloc, only_class, cols_1, split);
+  return e;
+}
+
 }  // namespace
 
-// Groups of n_s rows when their row buffers fit in LDS (every row of a
-// group shares its target indices; one such workgroup per CU, so 512
-// threads), single rows of 256 threads otherwise.
+// Groups of n_s rows for the classes whose row buffers fit in LDS (every
+// row of a group shares its target indices; 512 threads), single rows of
+// 256 threads for the larger classes.
 hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class) {
   // FP32 storage: g of the trace rows stays in FP64 (it is O(1) per macro but
   // cancels between the two sides of a face in the assembled b-hat)
   double* gloc = prec == 1 ? c.ws.gloc : nullptr;
-  const int ns = c.hm.ns;
-  const bool grouped = form_lds_bytes(c, ns, prec == 1 ? sizeof(float) : sizeof(double)) <= 150 * 1024;
-  if (prec == 1) {
-    float* W = reinterpret_cast<float*>(c.ws.Wm);
-    if (!grouped) return form_launch<float, 1, 256>(c, m0, m1, W, gloc, only_class);
-    return ns == 5 ? form_launch<float, 5, 512>(c, m0, m1, W, gloc, only_class) : form_launch<float, 4, 512>(c, m0, m1, W, gloc, only_class);
-  }
-  if (!grouped) return form_launch<double, 1, 256>(c, m0, m1, c.ws.Wm, gloc, only_class);
-  return ns == 5 ? form_launch<double, 5, 512>(c, m0, m1, c.ws.Wm, gloc, only_class) : form_launch<double, 4, 512>(c, m0, m1, c.ws.Wm, gloc, only_class);
+  if (prec == 1) return form_all<float>(c, m0, m1, reinterpret_cast<float*>(c.ws.Wm), gloc, only_class);
+  return form_all<double>(c, m0, m1, c.ws.Wm, gloc, only_class);
 }

@@ -27,6 +27,8 @@ CASES = {
     # macros of different sizes in one mesh (several classes in one launch)
     "2d_dir_uneven_p2": dict(dim=2, seg=[[2, 3], [3, 2]], p=2, periodic=False, state="shear", mach=0.2),
     "3d_per_uneven_p2": dict(dim=3, seg=[[2, 3], [3, 2], [2, 2]], p=2, periodic=True),
+    # one class too large for the grouped formation beside seven small ones
+    "3d_per_uneven_p2_split_form": dict(dim=3, seg=[[4, 1], [4, 1], [2, 1]], p=2, periodic=True),
     "3d_dir_uneven_p1_supg": dict(dim=3, seg=[[1, 2], [2, 1], [2, 2]], p=1, periodic=False, state="shear",
                                   mach=0.2, supg=True),
 }
