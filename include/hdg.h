@@ -186,8 +186,8 @@ hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk);
 /* Autotuner of the batched elimination of hdg_condense: for every macro
  * class (one per macro shape) and the given condensation precision, times
  * the class's elimination (HIP events on the context's stream, after one
- * untimed trial) for each candidate launch shape -- 8, 16, 32 or 64
- * sixteen-row tiles per workgroup of the trailing update with the 512-thread
+ * untimed trial) for each candidate launch shape -- 8, 16, 32, 64, 128 or
+ * 256 sixteen-row tiles per workgroup of the trailing update with the 512-thread
  * panel factorisation, then the 1024-thread panel with the best of those,
  * then the factorisation of the next pair of column blocks on a second
  * stream beside the trailing update -- on the current linearisation, and

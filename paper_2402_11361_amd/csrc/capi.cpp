@@ -524,13 +524,14 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
       h.tune[p32] = it->second;
       continue;
     }
-    // tiles per workgroup 8..64 with the default panel, then the wide panel
+    // tiles per workgroup 8..256 with the default panel, then the wide panel
     // with the best of those; one untimed trial first (code loading)
     float best = 1e30f;
     LuTune pick;
     // then the look-ahead stream with the best so far
-    const int cand[7][3] = {{32, 0, 0}, {8, 0, 0}, {16, 0, 0}, {32, 0, 0}, {64, 0, 0}, {-1, 1, 0}, {-1, -1, 1}};
-    for (int ci = 0; ci < 7 && st == HDG_OK; ++ci) {
+    const int cand[9][3] = {{32, 0, 0}, {8, 0, 0}, {16, 0, 0}, {32, 0, 0}, {64, 0, 0}, {128, 0, 0}, {256, 0, 0},
+                            {-1, 1, 0}, {-1, -1, 1}};
+    for (int ci = 0; ci < 9 && st == HDG_OK; ++ci) {
       {
         LuTune t;
         t.tpw = cand[ci][0] > 0 ? cand[ci][0] : pick.tpw;

@@ -32,7 +32,7 @@ def test_autotune_caches_and_keeps_parity(tmp_path):
     assert len(lines) == ncl
     for k, line in enumerate(lines):
         f = line.split()
-        assert f[2] == "fp64" and int(f[9]) in (8, 16, 32, 64) and int(f[10]) in (0, 1) and int(f[11]) in (0, 1)
+        assert f[2] == "fp64" and int(f[9]) in (8, 16, 32, 64, 128, 256) and int(f[10]) in (0, 1) and int(f[11]) in (0, 1)
         assert ctx.tuning(k, HDG_FP64) == (int(f[9]), int(f[10]), int(f[11]))
     # the cache answers a second call without timing
     assert ctx.autotune(HDG_FP64, cache) == 0
