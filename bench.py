@@ -405,10 +405,11 @@ def main():
     copy_gbs = 2.0 * src.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
     del src, dst
 
-    def run_variant(cond_prec, inner_prec, steps, warmup, use_learned=False, graph_steps=0):
+    def run_variant(cond_prec, inner_prec, steps, warmup, use_learned=False, graph_steps=0, inner_its=5,
+                    max_outer=300):
         """Warm-up stages, then `steps` timed stage solves from the same state."""
         marks = []
-        drv = StageDriver(ctx, rtol=rtol, restart=30, inner_its=5, max_outer=300, condense_prec=cond_prec,
+        drv = StageDriver(ctx, rtol=rtol, restart=30, inner_its=inner_its, max_outer=max_outer, condense_prec=cond_prec,
                           inner_prec=inner_prec, mark=lambda phase: marks.append((phase, ev())),
                           use_learned=use_learned, graph_steps=graph_steps)
 
@@ -496,6 +497,18 @@ def main():
                 stage_solution_rel_diff_vs_plain=dict(
                     u=float((gv["u"] - plain["u"]).abs().max() / plain["u"].abs().max()),
                     uhat=float((gv["uh"] - plain["uh"]).abs().max() / plain["uh"].abs().max())))
+        # single-level GMRES: the face-block inverse of A_uh,uh alone as the
+        # preconditioner (no inner GMRES), the comparison of the paper's Table 2
+        sl = run_variant(HDG_FP64, HDG_FP64, args.steps, args.warmup, inner_its=0, max_outer=5000,
+                         graph_steps=args.graph_steps)
+        variants["single_level_gmres_fp64_graph"] = dict(
+            ms_per_stage=round(sl["ms_per_stage"], 3), speedup_vs_plain=round(ms_step / sl["ms_per_stage"], 3),
+            phases_ms={k: round(v, 3) for k, v in sl["phase_ms"].items()}, newton_its=sl["newton_its"],
+            fgmres=dict(outer_its=sl["outer"], inner_its=sl["inner"]),
+            multi_level_outer_its=outer, multi_level_inner_its=inner,
+            stage_solution_rel_diff_vs_plain=dict(
+                u=float((sl["u"] - plain["u"]).abs().max() / plain["u"].abs().max()),
+                uhat=float((sl["uh"] - plain["uh"]).abs().max() / plain["uh"].abs().max())))
         if not args.no_learned:
             lrn = train_learned(ctx, cfg, dev, dii, dt, args)
             ml = run_variant(HDG_FP32, HDG_FP64, args.steps, args.warmup, use_learned=True)
