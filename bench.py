@@ -176,6 +176,56 @@ def big_variant(args, dev_fn, variants):
     ctx.close()
 
 
+def first_layer_variant(args, dev_fn, variants):
+    """Standard (first-layer) condensation of (q, u) together against the
+    second layer, both FP64 on the 24^3 workload in two chunks, from the
+    same linearisation: time per condensation and the largest difference of
+    the condensed blocks of a few macros."""
+    import torch
+    from paper_2402_11361_amd import inputs
+    from paper_2402_11361_amd.hdg import HDG_FP64, Context, mesh_spec_box
+    cfg = dict(inputs.CONFIGS["tgv24_m3_p2"])
+    spec = mesh_spec_box(3, cfg["n_elem"], cfg["m"], cfg["p"], cfg["lo"], cfg["hi"], True)
+    stream = torch.cuda.current_stream()
+    ctx = Context.from_mesh_spec(spec, Re=cfg["Re"], Mach=cfg["mach"], stream=stream.cuda_stream)
+    ctx.set_chunking((ctx.n_macros + 1) // 2)
+    ctx.bind_workspace()
+    u0, q0, uh0 = workload_arrays(ctx, cfg)
+    dii = 1.0 / 0.435866521508459
+    dt = inputs.cfl_dt(cfg)
+    u = dev_fn(u0)
+    ctx.linearize_stage(dev_fn(q0), u, dev_fn(uh0), -dii * u, dt, dii, norms=False)
+    if args.set_tuning:
+        ctx.set_tuning(0, HDG_FP64, *[int(v) for v in args.set_tuning.split(",")])
+    else:
+        ctx.autotune(HDG_FP64, args.tune_cache)
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    sample = [0, ctx.n_macros // 2, ctx.n_macros - 1]
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    ms2 = timed(lambda: ctx.condense(bhat, HDG_FP64), 2)
+    second = [ctx.get_condensed(i)[0] for i in sample]
+    print(f"[bench] second-layer condensation {ms2:.1f} ms", file=sys.stderr, flush=True)
+    ms1 = timed(lambda: ctx.condense_first_layer(bhat), 1)
+    print(f"[bench] first-layer condensation {ms1:.1f} ms", file=sys.stderr, flush=True)
+    diff = max(float(np.abs(ctx.get_condensed(i)[0] - a).max() / np.abs(a).max()) for i, a in zip(sample, second))
+    nu, nb = ctx.n_u_macro, ctx.n_b_macro
+    variants["first_vs_second_layer_fp64"] = dict(
+        workload="24^3 periodic Taylor-Green, 3^3-element macros (512), p=2, two condensation chunks",
+        ms_second_layer=round(ms2, 1), ms_first_layer=round(ms1, 1), ratio=round(ms1 / ms2, 2),
+        pivot_order=dict(second=nu, first=4 * nu), ahat_rel_diff=diff, tuning=list(ctx.tuning(0, HDG_FP64)),
+        nb=nb)
+    ctx.close()
+
+
 def learned_p3_variant(args, dev_fn, variants):
     """The learned coarse correction on the 32^3 mesh with 4^3-element macros
     at p = 3 (512 macros, chunked FP32 condensation): pairs harvested from a
@@ -339,6 +389,8 @@ def main():
                     help="time only the uneven-macro 32^3 variant (profiling); prints its JSON")
     ap.add_argument("--set-tuning", default=None, metavar="TPW,WIDE,LOOK",
                     help="fixed elimination launch shape for every class instead of the autotuner (profiling)")
+    ap.add_argument("--first-layer", action="store_true",
+                    help="also time the standard (first-layer) condensation against the second layer at 24^3")
     ap.add_argument("--train-seeds", type=int, default=2)
     ap.add_argument("--train-vectors", type=int, default=40)
     ap.add_argument("--train-epochs", type=int, default=60)
@@ -568,6 +620,9 @@ def main():
         free_device_memory()
     if args.learned_p3:
         learned_p3_variant(args, dev, variants)
+        free_device_memory()
+    if args.first_layer:
+        first_layer_variant(args, dev, variants)
         free_device_memory()
     if args.big_steps > 0:
         big_variant(args, dev, variants)

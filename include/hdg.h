@@ -245,6 +245,21 @@ hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, co
  * Returns HDG_ESINGULAR (message names the macro) on a zero pivot. */
 hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat);
 
+/* First-layer (standard) static condensation (Sec. 3.2, eq. C46/C47), for
+ * comparison with hdg_condense: (q, u) of every macro are eliminated
+ * together -- an LU with partial pivoting of the local matrix
+ * [[A_qq, A_qu], [A_uq, A_uu]] of order n_q + n_u -- giving the same
+ * A-hat^{T_i} and b-hat^{T_i} (to rounding) and the same assembled bhat
+ * (device, n_glob); FP64.  Afterwards hdg_apply_global, hdg_fgmres_solve
+ * and hdg_local_backsolve (which forms and factors S again per chunk) work
+ * as after hdg_condense(HDG_FP64).  Needs chunking (hdg_set_chunking; the W
+ * buffer holds as many first-layer matrices at a time as fit) and a mesh of
+ * one macro shape, and n_q + n_u <= 12288 with a row of at most 150 KiB
+ * in FP64 (HDG_EUNSUPPORTED otherwise); HDG_ENOMEM when the W
+ * buffer cannot hold one first-layer matrix; HDG_ESINGULAR on a zero
+ * pivot. */
+hdg_status hdg_condense_first_layer(hdg_ctx ctx, double* bhat);
+
 /* y = A-hat x = sum_i P_i^T A-hat^{T_i} P_i x (Algorithm 2 with the condensed
  * blocks formed by hdg_condense, in the precision of that call; sums in
  * FP64); x, y device, n_glob, must not alias. */

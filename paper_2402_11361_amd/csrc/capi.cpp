@@ -664,6 +664,35 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
   return HDG_OK;
 }
 
+hdg_status hdg_condense_first_layer(hdg_ctx ctx, double* bhat) {
+  if (!ctx || !bhat) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  if (!c.hm.chunked() || c.hm.n_classes != 1)
+    return fail(&c, HDG_EUNSUPPORTED, "first-layer condensation needs chunking and a single macro shape");
+  int* status = reinterpret_cast<int*>(c.ws.small);
+  const int nst = c.hm.n_chunks() * c.hm.n_classes;
+  HIPCHK(&c, launch_zero_ints(c.stream, status, nst + 1));
+  const hipError_t e = launch_condense_first_layer(c, status);
+  if (e == hipErrorInvalidValue) return fail(&c, HDG_ENOMEM, "the W buffer cannot hold one first-layer matrix");
+  if (e == hipErrorNotSupported)
+    return fail(&c, HDG_EUNSUPPORTED, "first-layer matrix larger than the form and panel kernels take");
+  HIPCHK(&c, e);
+  HIPCHK(&c, launch_bhat(c, bhat, 0));
+  HIPCHK(&c, launch_face_precond(c));
+  c.cond_prec = 0;
+  c.have_a32 = false;
+  c.have_a16 = false;
+  HIPCHK(&c, hipMemcpyAsync(ctx->pinned, status, sizeof(int) * (nst + 1), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  int st[2];
+  std::memcpy(st, ctx->pinned, sizeof(int));
+  std::memcpy(st + 1, reinterpret_cast<const int*>(ctx->pinned) + nst, sizeof(int));
+  if (st[0]) return fail(&c, HDG_ESINGULAR, "singular first-layer local matrix");
+  if (st[1]) return fail(&c, HDG_ESINGULAR, "singular face block of A_uhat-uhat " + std::to_string(st[1] - 1));
+  return HDG_OK;
+}
+
 hdg_status hdg_apply_global(hdg_ctx ctx, const double* x, double* y) {
   if (!ctx || !x || !y || x == y) return HDG_EINVAL;
   HdgContext& c = ctx->c;

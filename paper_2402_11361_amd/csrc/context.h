@@ -12,7 +12,7 @@ struct HostClass {
   int N, E, A, Q, T, Fq, n_u, n_q, n_b, n_sub, nmax1;
   double h[3];
   int nf_nodes[HDG_MAXF], nf_off[HDG_MAXF];
-  std::vector<double> Phi, dPhi, W, Tvol, Mel, Psi, WF, C1D, Minv1D, M1D;
+  std::vector<double> Phi, dPhi, W, Tvol, Mel, Psi, WF, C1D, Minv1D, M1D, B1D;
   int cq = 0, cF = 0, cmaxf = 0;
   std::vector<double> cR, cPhi;
   // tiled augmented matrix
@@ -114,6 +114,7 @@ struct HdgContext {
   int nf_max = 0, ldf = 0;
   int kry_restart_max = 64, kry_inner_max = 16;
   size_t need_bytes = 0;
+  size_t wm_bytes = 0;  // size of the W buffer
   // offsets of the sub-face block pieces
   int off_AUB = 0, off_ABU = 0, off_ABQ = 0, off_ABB = 0, off_RB = 0;
   bool have_a32 = false;

@@ -413,6 +413,7 @@ void build_class(const HostMesh& hm, HostClass& hc, const std::array<int, 3>& m)
   // 1D macro operators per axis: assembled C0 mass M, B[a][b] = int phi_a' phi_b
   const int nm = hc.nmax1;
   hc.C1D.assign((size_t)d * nm * nm, 0.0); hc.Minv1D.assign((size_t)d * nm * nm, 0.0); hc.M1D.assign((size_t)d * nm * nm, 0.0);
+  hc.B1D.assign((size_t)d * nm * nm, 0.0);
   for (int k = 0; k < d; ++k) {
     int n = hc.n1[k];
     std::vector<double> M(n * n, 0.0), B(n * n, 0.0);
@@ -434,6 +435,7 @@ void build_class(const HostMesh& hm, HostClass& hc, const std::array<int, 3>& m)
         hc.C1D[((size_t)k * nm + a) * nm + b] = s;
         hc.Minv1D[((size_t)k * nm + a) * nm + b] = Mi[a * n + b];
         hc.M1D[((size_t)k * nm + a) * nm + b] = M[a * n + b];
+        hc.B1D[((size_t)k * nm + a) * nm + b] = B[a * n + b];
       }
   }
   build_coarse(hc);
@@ -568,7 +570,15 @@ void plan_workspace(HdgContext& c) {
   o.RBglob = take(sizeof(double) * hm.n_glob);
   o.gloc = take(sizeof(double) * (size_t)hm.b_off[nm]);
   c.fstride = (long long)align_up(2 * c.nf_max, 16) * c.ldf;
-  o.Wm = take(std::max(sizeof(double) * (size_t)w_chunk_max, chunked ? kq_bytes : 0));
+  c.wm_bytes = std::max(sizeof(double) * (size_t)w_chunk_max, chunked ? kq_bytes : 0);
+  if (chunked && hm.n_classes == 1) {
+    // room for at least one first-layer matrix (order n_q + n_u + n_b) and its pivots
+    const HostClass& k = c.hcs[0];
+    const size_t rows1 = (size_t)k.n_q + k.n_u + k.n_b, ld1 = (rows1 + 1 + 63) / 64 * 64;
+    c.wm_bytes = std::max(c.wm_bytes, sizeof(double) * ((rows1 + 15) / 16 * 16) * ld1 +
+                                          sizeof(int) * ((size_t)k.n_q + k.n_u) + 256);
+  }
+  o.Wm = take(c.wm_bytes);
   if (chunked) o.Kq = o.Wm;
   o.ipiv = take(sizeof(int) * (size_t)c.n_u_tot);
   o.FW = take(sizeof(double) * (size_t)hm.n_faces * c.fstride);
@@ -703,7 +713,7 @@ static ClassDev upload_class(HdgContext& c, const HostClass& hc) {
   cd.sub_lf = up(c, hc.sub_lf); cd.sub_tid = up(c, hc.sub_tid); cd.node_ne = up(c, hc.node_ne);
   cd.node_e = up(c, hc.node_e); cd.node_a = up(c, hc.node_a); cd.tn_cnt = up(c, hc.tn_cnt);
   cd.tn_sub = up(c, hc.tn_sub); cd.tn_t = up(c, hc.tn_t); cd.tn_base = up(c, hc.tn_base);
-  cd.C1D = up(c, hc.C1D); cd.Minv1D = up(c, hc.Minv1D); cd.M1D = up(c, hc.M1D);
+  cd.C1D = up(c, hc.C1D); cd.Minv1D = up(c, hc.Minv1D); cd.M1D = up(c, hc.M1D); cd.B1D = up(c, hc.B1D);
   cd.cq = hc.cq; cd.cF = hc.cF; cd.cmaxf = hc.cmaxf;
   cd.cR = up(c, hc.cR); cd.cPhi = up(c, hc.cPhi);
   cd.ldw = hc.ldw; cd.n_rows = hc.n_rows; cd.n_cols = hc.n_cols; cd.wstride = hc.wstride;

@@ -52,6 +52,7 @@ struct ClassDev {
   const double* C1D;      // [dim][nmax1][nmax1]
   const double* Minv1D;   // [dim][nmax1][nmax1]
   const double* M1D;      // [dim][nmax1][nmax1]
+  const double* B1D;      // [dim][nmax1][nmax1]: B_k[a][b] = int phi_b d_k phi_a (= M1D_k C1D_k)
   // coarse multilinear space on the macro faces (learned correction):
   // cq = 2^(d-1) functions per face and component, cF = 2d ns cq features per
   // macro, tables per normal axis k over the face nodes (lower axis fastest)
@@ -156,6 +157,8 @@ hipError_t launch_supg(HdgContext& c, const double* q, const double* u, const do
 size_t supg_scratch_per_element(int dim, int p);
 hipError_t launch_cast_ahat(HdgContext& c);
 hipError_t launch_cast_ahat16(HdgContext& c);
+// first-layer condensation (chunked workspace, one macro class)
+hipError_t launch_condense_first_layer(HdgContext& c, int* status);
 
 // learned coarse correction
 constexpr int LRN_MAX_HIDDEN = 512;

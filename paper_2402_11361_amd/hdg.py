@@ -68,7 +68,8 @@ EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_o
            "hdg_get_residuals", "hdg_precond_apply", "hdg_coarse_size", "hdg_coarse_restrict",
            "hdg_coarse_prolong", "hdg_mlp_param_count", "hdg_mlp_work_floats", "hdg_mlp_forward",
            "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking",
-           "hdg_autotune", "hdg_class_count", "hdg_get_tuning", "hdg_set_tuning"]
+           "hdg_autotune", "hdg_class_count", "hdg_get_tuning", "hdg_set_tuning",
+           "hdg_condense_first_layer"]
 
 _lib = None
 
@@ -96,6 +97,7 @@ def load_library(path=LIB_PATH):
     lib.hdg_set_tuning.argtypes = [vp, i, i, i, i, i]
     lib.hdg_linearize_stage.argtypes = [vp, vp, vp, vp, vp, dp, dp, dp, vp]
     lib.hdg_condense.argtypes = [vp, i, vp]
+    lib.hdg_condense_first_layer.argtypes = [vp, vp]
     lib.hdg_apply_global.argtypes = [vp, vp, vp]
     lib.hdg_fgmres_solve.argtypes = [vp, vp, vp, ctypes.POINTER(KrylovOpts), ctypes.POINTER(KrylovStats)]
     lib.hdg_local_backsolve.argtypes = [vp, vp, vp, vp]
@@ -293,6 +295,11 @@ class Context:
 
     def condense(self, bhat, prec=HDG_FP64):
         self._check(self.lib.hdg_condense(self.h, prec, _ptr(bhat)))
+
+    def condense_first_layer(self, bhat):
+        """Standard (first-layer) condensation of (q, u) together (chunked,
+        one macro shape); same A-hat and b-hat as condense()."""
+        self._check(self.lib.hdg_condense_first_layer(self.h, _ptr(bhat)))
 
     def apply_global(self, x, y):
         self._check(self.lib.hdg_apply_global(self.h, _ptr(x), _ptr(y)))
