@@ -93,6 +93,11 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
   __shared__ T s_urow[PWT];
   __shared__ T s_swap[2][PWT];
   __shared__ T s_U[PWT * NB];
+  __shared__ T s_L[PWT * PWT];     // unit-lower L of the sub-panel's own rows
+  __shared__ int s_piv[PWT];       // pivot rows of the sub-panel's columns
+  __shared__ int s_mv[2][2 * PWT];  // net row moves of the sub-panel: dst, src
+  __shared__ int s_nmv;
+  __shared__ T s_mvbuf[2 * PWT * 2 * NB];  // old values of the moved rows
   for (int c0 = j0; c0 < j0 + jb; c0 += PWT) {
     const int pw = min(PWT, j0 + jb - c0);
     // rows owned by this thread: c0 + tid + i * NT
@@ -103,8 +108,10 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
 #pragma unroll
       for (int cc = 0; cc < PWT; ++cc) v[i][cc] = (r < n_piv && cc < pw) ? W[wtix(r, c0 + cc, ld)] : T(0);
     }
-    for (int cc = 0; cc < pw; ++cc) {
-      {
+    // columns of the sub-panel unrolled: register indices known at compile time
+#pragma unroll
+    for (int cc = 0; cc < PWT; ++cc) {
+      if (cc < pw) {  // uniform
       const int col = c0 + cc;
       // pivot search over rows [col, n_piv)
       T bv = T(-1);
@@ -133,7 +140,7 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
           bi0 = col;
         }
         s_prow = bi0;
-        ipiv[col] = bi0;
+        s_piv[cc] = bi0;  // to ipiv after the sub-panel (no global store before the barriers)
       }
       __syncthreads();
       const int prow = s_prow;
@@ -165,14 +172,6 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
             for (int k = 0; k < PWT; ++k) v[i][k] = s_swap[0][k];
           }
         }
-        // the rest of the block row (columns [j0, c0) and [c0 + pw, j0 + jb)) in memory
-        for (int k = tid; k < j0 + jb - lcol0; k += NT) {
-          const int cidx = lcol0 + k;  // L columns of a previous block too (lcol0 < j0)
-          if (cidx >= c0 && cidx < c0 + pw) continue;
-          T t = W[wtix(col, cidx, ld)];
-          W[wtix(col, cidx, ld)] = W[wtix(prow, cidx, ld)];
-          W[wtix(prow, cidx, ld)] = t;
-        }
       }
       // broadcast the pivot row
 #pragma unroll
@@ -203,7 +202,46 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
       __syncthreads();
       }
     }
-    // write the factored sub-panel back
+    // The sub-panel's row swaps on the rest of the block row (columns
+    // [lcol0, c0) and [c0 + pw, j0 + jb); lcol0 < j0 takes the L columns of
+    // the previous block too) as one net permutation: position dst takes the
+    // old row src, all old values loaded before any is stored.
+    if (tid == 0) {
+      int* pos = s_mv[0];   // position pos[t] now holds the old row cont[t]
+      int* cont = s_mv[1];
+      int n = pw;
+      for (int i = 0; i < pw; ++i) pos[i] = cont[i] = c0 + i;
+      for (int cc = 0; cc < pw; ++cc) {
+        const int pb = s_piv[cc];
+        if (pb == c0 + cc) continue;
+        int jb2 = -1;
+        for (int t = 0; t < n; ++t)
+          if (pos[t] == pb) jb2 = t;
+        if (jb2 < 0) { pos[n] = cont[n] = pb; jb2 = n++; }
+        const int t = cont[cc];
+        cont[cc] = cont[jb2];
+        cont[jb2] = t;
+      }
+      int m = 0;  // keep the moves (in place: m <= t)
+      for (int t = 0; t < n; ++t)
+        if (pos[t] != cont[t]) { pos[m] = pos[t]; cont[m] = cont[t]; ++m; }
+      s_nmv = m;
+    }
+    __syncthreads();
+    if (tid < pw) ipiv[c0 + tid] = s_piv[tid];
+    const int nmv = s_nmv, nbr = j0 + jb - lcol0;  // nbr <= 2 NB columns
+    if (nmv > 0) {
+      for (int x = tid; x < nmv * nbr; x += NT) {
+        const int t = x / nbr, cidx = lcol0 + x % nbr;
+        if (cidx < c0 || cidx >= c0 + pw) s_mvbuf[x] = W[wtix(s_mv[1][t], cidx, ld)];
+      }
+      __syncthreads();
+      for (int x = tid; x < nmv * nbr; x += NT) {
+        const int t = x / nbr, cidx = lcol0 + x % nbr;
+        if (cidx < c0 || cidx >= c0 + pw) W[wtix(s_mv[0][t], cidx, ld)] = s_mvbuf[x];
+      }
+    }
+    // write the factored sub-panel back; its own L rows also to LDS
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int r = c0 + tid + i * NT;
@@ -213,15 +251,21 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
           if (cc < pw) W[wtix(r, c0 + cc, ld)] = v[i][cc];
       }
     }
+    if (tid < pw) {
+#pragma unroll
+      for (int cc = 0; cc < PWT; ++cc) s_L[tid * PWT + cc] = v[0][cc];
+    }
     // right-looking update of the rest of the block: columns [c0 + pw, j0 + jb)
     const int rest0 = c0 + pw, nrest = j0 + jb - rest0;
     __syncthreads();
     if (nrest > 0) {
       // U rows of the sub-panel: L_sub^{-1} A[c0:c0+pw, rest]  (unit lower, sequential rows)
       for (int k = tid; k < nrest; k += NT) {
-        for (int i = 0; i < pw; ++i) {
-          T s = W[wtix((c0 + i), rest0 + k, ld)];
-          for (int m = 0; m < i; ++m) s -= W[wtix((c0 + i), c0 + m, ld)] * s_U[m * NB + k];
+#pragma unroll 4
+        for (int i = 0; i < pw; ++i) s_U[i * NB + k] = W[wtix((c0 + i), rest0 + k, ld)];
+        for (int i = 1; i < pw; ++i) {
+          T s = s_U[i * NB + k];
+          for (int m = 0; m < i; ++m) s -= s_L[i * PWT + m] * s_U[m * NB + k];
           s_U[i * NB + k] = s;
         }
       }
@@ -230,19 +274,53 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
         const int i = k / nrest, cidx = k % nrest;
         W[wtix((c0 + i), rest0 + cidx, ld)] = s_U[i * NB + cidx];
       }
-      // rows below the sub-panel: A[r, rest] -= L[r, c0:c0+pw] U
+      // rows below the sub-panel: A[r, rest] -= L[r, c0:c0+pw] U, CB
+      // columns of all the thread's rows loaded at once (16 loads in flight
+      // per thread); with many rows per thread (register budget) row by row
+      constexpr int CB = RPT >= 16 ? 1 : 16 / RPT;
+      if constexpr (RPT >= 16) {
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int r = c0 + tid + i * NT;
-        if (r >= c0 + pw && r < n_piv) {
+        for (int i = 0; i < RPT; ++i) {
+          const int r = c0 + tid + i * NT;
+          if (r >= c0 + pw && r < n_piv) {
 #pragma unroll 4
-          for (int cidx = 0; cidx < nrest; ++cidx) {
-            T s = W[wtix(r, rest0 + cidx, ld)];
+            for (int cidx = 0; cidx < nrest; ++cidx) {
+              T s = W[wtix(r, rest0 + cidx, ld)];
 #pragma unroll
-            for (int m = 0; m < PWT; ++m)
-              if (m < pw) s -= v[i][m] * s_U[m * NB + cidx];
-            W[wtix(r, rest0 + cidx, ld)] = s;
+              for (int m = 0; m < PWT; ++m)
+                if (m < pw) s -= v[i][m] * s_U[m * NB + cidx];
+              W[wtix(r, rest0 + cidx, ld)] = s;
+            }
           }
+        }
+      } else
+      for (int cb = 0; cb < nrest; cb += CB) {
+        T x[RPT][CB];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const int r = c0 + tid + i * NT;
+#pragma unroll
+          for (int q = 0; q < CB; ++q)
+            x[i][q] = (r >= c0 + pw && r < n_piv && cb + q < nrest) ? W[wtix(r, rest0 + cb + q, ld)] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+          if (cb + q >= nrest) break;
+#pragma unroll
+          for (int m = 0; m < PWT; ++m) {
+            if (m < pw) {
+              const T um = s_U[m * NB + cb + q];
+#pragma unroll
+              for (int i = 0; i < RPT; ++i) x[i][q] -= v[i][m] * um;
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+          const int r = c0 + tid + i * NT;
+#pragma unroll
+          for (int q = 0; q < CB; ++q)
+            if (r >= c0 + pw && r < n_piv && cb + q < nrest) W[wtix(r, rest0 + cb + q, ld)] = x[i][q];
         }
       }
       __syncthreads();
