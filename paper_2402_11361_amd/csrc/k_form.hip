@@ -36,8 +36,18 @@ struct FormPtrs {
   int split_cols;    // >= 0: grouped launch takes classes with n_cols <= split_cols, single-row launch the rest
 };
 
+// Quotient and remainder of 0 <= x < 2^22 by 1 <= y < 2^22 through the FP32
+// reciprocal: the relative error of x * rcp(y) is below 2^-22, so the
+// truncated quotient is off by at most one and one correction makes it exact.
+__device__ __forceinline__ int2 divmod(int x, int y) {
+  int q = (int)((float)x * __builtin_amdgcn_rcpf((float)y));
+  int r = x - q * y;
+  if (r < 0) { --q; r += y; } else if (r >= y) { ++q; r -= y; }
+  return make_int2(q, r);
+}
+
 __device__ __forceinline__ void digits(int x, int base, int d, int* out) {
-  for (int k = 0; k < d; ++k) { out[k] = x % base; x /= base; }
+  for (int k = 0; k < d; ++k) { const int2 qr = divmod(x, base); out[k] = qr.y; x = qr.x; }
 }
 
 // Adds, for direction k, the contributions of NR coefficient rows
@@ -53,7 +63,7 @@ __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, doubl
   int eidx[3] = {0, 0, 0};
   {
     int t = e;
-    for (int j = 0; j < d; ++j) { eidx[j] = t % cd.m[j]; t /= cd.m[j]; }
+    for (int j = 0; j < d; ++j) { const int2 qr = divmod(t, cd.m[j]); eidx[j] = qr.y; t = qr.x; }
   }
   const int nk = cd.n1[k], nm = cd.nmax1;
   const int T = cd.T;  // (p+1)^(d-1) tangential combinations of an element
@@ -62,7 +72,8 @@ __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, doubl
   int stride[3] = {1, cd.n1[0], cd.n1[0] * cd.n1[1]};
   // line targets
   for (int i = tid; i < ns * T * nk; i += NT) {
-    const int cp = i / (T * nk), r = i % (T * nk), t = r / nk, n = r % nk;
+    const int2 q1 = divmod(i, T * nk), q2 = divmod(q1.y, nk);
+    const int cp = q1.x, t = q2.x, n = q2.y;
     int td[2] = {0, 0};
     digits(t, A1, d - 1, td);
     int bd[3] = {0, 0, 0}, ti = 0;
@@ -85,7 +96,8 @@ __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, doubl
   }
   // face targets on the two macro faces normal to k
   for (int i = tid; i < 2 * ns * T; i += NT) {
-    const int sidx = i / (ns * T), r = i % (ns * T), cp = r / T, t = r % T;
+    const int2 q1 = divmod(i, ns * T), q2 = divmod(q1.y, T);
+    const int sidx = q1.x, cp = q2.x, t = q2.y;
     int td[2] = {0, 0};
     digits(t, A1, d - 1, td);
     int bd[3] = {0, 0, 0}, ti = 0;
@@ -209,16 +221,21 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
       const int* en = cd.elem_nodes + (size_t)e * A;
       __syncthreads();
       // the NR rows of A_uq^e, read by every line and face target, go to LDS
-      for (int i = tid; i < NR * dnsA; i += NT) sc[i] = (TL)auq[(i / dnsA) * sq + i % dnsA];
+      for (int i = tid; i < NR * dnsA; i += NT) {
+        const int2 qr = divmod(i, dnsA);
+        sc[i] = (TL)auq[qr.x * sq + qr.y];
+      }
       for (int i = tid; i < nsA; i += NT) {
-        const int col = (i / A) * N + en[i % A];
+        const int2 qr = divmod(i, A);
+        const int col = qr.x * N + en[qr.y];
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += (TL)auu[rr * su + i];
       }
       __syncthreads();
       // f: A_uq A_qq^{-1} R_Q
       for (int i = tid; i < dnsA; i += NT) {
-        const int lc = i / A, b = i % A;
+        const int2 qr = divmod(i, A);
+        const int lc = qr.x, b = qr.y;
         const double rq = RQt[(size_t)lc * N + en[b]];
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) fpart[rr] += auq[rr * sq + i] * rq;  // FP64 coefficients
@@ -239,7 +256,8 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
         const int nst = ns * T;
         const int nf2 = cd.nf_nodes[lf2];
         for (int i = tid; i < nst; i += NT) {
-          const int cp = i / T, tp = i % T;
+          const int2 qr = divmod(i, T);
+          const int cp = qr.x, tp = qr.y;
           const int col = cd.n_u + cd.nf_off[lf2] + cp * nf2 + cd.sub_tid[(size_t)sid * T + tp];
 #pragma unroll
           for (int rr = 0; rr < NR; ++rr) row[rr * ldr + col] += (TL)aub[(size_t)((c0 + rr) * T + ta) * nst + i];
@@ -268,9 +286,13 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
       const int* finv = cd.finv + (size_t)lf * A;
       __syncthreads();
       const int dnst = d * nst;
-      for (int i = tid; i < NR * dnst; i += NT) sc[i] = (TL)abq[(i / dnst) * sbq + i % dnst];
+      for (int i = tid; i < NR * dnst; i += NT) {
+        const int2 qr = divmod(i, dnst);
+        sc[i] = (TL)abq[qr.x * sbq + qr.y];
+      }
       for (int i = tid; i < nst; i += NT) {
-        const int cp = i / T, tp = i % T;
+        const int2 qr = divmod(i, T);
+        const int cp = qr.x, tp = qr.y;
         const int cu = cp * N + en[fn[tp]];
         const int cb = cd.n_u + cd.nf_off[lf] + cp * nf + cd.sub_tid[(size_t)sid * T + tp];
 #pragma unroll
@@ -281,7 +303,8 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
       }
       __syncthreads();
       for (int i = tid; i < d * nst; i += NT) {
-        const int lc = i / T, tp = i % T;
+        const int2 qr = divmod(i, T);
+        const int lc = qr.x, tp = qr.y;
         const double rq = RQt[(size_t)lc * N + en[fn[tp]]];
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) fpart[rr] += abq[rr * sbq + i] * rq;  // FP64 coefficients (g)
@@ -312,9 +335,11 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
   }
   __syncthreads();
   TW* Wmac = Wm + md.w_off[macro];
-  for (int i = tid; i < NR * cd.ldw; i += NT) {
-    const int rr = i / cd.ldw, cidx = i % cd.ldw;
-    Wmac[wtix(r0 + rr * rstride, cidx, cd.ldw)] = (cidx < n_cols) ? (TW)row[rr * ldr + cidx] : TW(0);
+#pragma unroll
+  for (int rr = 0; rr < NR; ++rr) {
+    TW* wrow = Wmac + wtix(r0 + rr * rstride, 0, cd.ldw);  // column c at wrow[(c >> 6) * 1024 + (c & 63)]
+    for (int cidx = tid; cidx < cd.ldw; cidx += NT)
+      wrow[(cidx >> 6) * 1024 + (cidx & 63)] = (cidx < n_cols) ? (TW)row[rr * ldr + cidx] : TW(0);
   }
 }
 
