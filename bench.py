@@ -226,6 +226,71 @@ def first_layer_variant(args, dev_fn, variants):
     ctx.close()
 
 
+def tgv_dissipation_variant(args, dev_fn, variants):
+    """Re = 100 Taylor-Green time integration from the clean initial field on
+    two discretisations of equal effective resolution, (m, p) = (3, 2) and
+    (2, 3) (6 macros per axis, N_eff = 42^3): kinetic energy and the
+    dissipation rate of eq. C5321 after every DIRK(3,3) step, with
+    -dE_k/dt by central differences as a check (Sec. 5.3).  FP32
+    condensation with the BF16 inner operator and graph-captured FGMRES
+    steps; Newton refines every stage to the FP64 tolerance."""
+    import torch
+    from paper_2402_11361_amd import inputs
+    from paper_2402_11361_amd.driver import StageDriver
+    from paper_2402_11361_amd.hdg import HDG_BF16, HDG_FP32, Context, mesh_spec_box
+    out = {}
+    for name in ("tgv_re100_m3_p2", "tgv_re100_m2_p3"):
+        cfg = dict(inputs.CONFIGS[name])
+        spec = mesh_spec_box(3, cfg["n_elem"], cfg["m"], cfg["p"], cfg["lo"], cfg["hi"], True)
+        stream = torch.cuda.current_stream()
+        ctx = Context.from_mesh_spec(spec, Re=cfg["Re"], Mach=cfg["mach"], stream=stream.cuda_stream)
+        ctx.bind_workspace()
+        u0, q0, uh0 = workload_arrays(ctx, cfg)
+        q, u, uh = dev_fn(q0), dev_fn(u0), dev_fn(uh0)
+        V0 = cfg["mach"]           # L = 1: t_c = L / V0, E_k in V0^2, eps in V0^3 / L
+        dt = inputs.cfl_dt(cfg)
+        n_steps = int(math.ceil(args.tgv_eps * (1.0 / V0) / dt - 1e-9))
+        drv = StageDriver(ctx, rtol=cfg["rtol"], condense_prec=HDG_FP32, inner_prec=HDG_BF16,
+                          graph_steps=args.graph_steps)
+        ek, eps, _ = ctx.flow_diagnostics(q, u)
+        t_s, ek_s, eps_s, newton, outer = [0.0], [ek / V0 ** 2], [eps / V0 ** 3], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in range(n_steps):
+            infos = drv.step(q, u, uh, dt)
+            ek, eps, _ = ctx.flow_diagnostics(q, u)
+            t_s.append((n + 1) * dt * V0)
+            ek_s.append(ek / V0 ** 2)
+            eps_s.append(eps / V0 ** 3)
+            newton += [i["newton_its"] for i in infos]
+            outer += [k["outer_its"] for i in infos for k in i["krylov"]]
+            if (n + 1) % 10 == 0 or n + 1 == n_steps:
+                print(f"[bench] {name} step {n + 1}/{n_steps} t/t_c {t_s[-1]:.2f} E_k {ek_s[-1]:.5f} "
+                      f"eps {eps_s[-1]:.5f}", file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        t_a, e_a, d_a = np.array(t_s), np.array(ek_s), np.array(eps_s)
+        dedt = -(e_a[2:] - e_a[:-2]) / (t_a[2:] - t_a[:-2])   # at t_a[1:-1]
+        mismatch = float(np.max(np.abs(dedt - d_a[1:-1])) / np.max(d_a))
+        ipk = int(np.argmax(d_a))
+        out[name] = dict(
+            workload=f"Taylor-Green Re 100, Mach 0.1, {cfg['n_elem']}^3 elements in 6^3 macros of "
+                     f"{cfg['m']}^3, p={cfg['p']}, N_eff 42^3, n_glob {ctx.n_glob}",
+            dt_over_tc=round(dt * V0, 5), steps=n_steps, wall_s=round(wall, 1),
+            s_per_step=round(wall / max(n_steps, 1), 3),
+            newton_its=[min(newton), max(newton)] if newton else [], fgmres_outer=[min(outer), max(outer)] if outer else [],
+            eps_peak=round(float(d_a[ipk]), 6), t_eps_peak=round(float(t_a[ipk]), 3),
+            max_rel_diff_minus_dEdt_vs_eps=round(mismatch, 4),
+            t=[round(v, 4) for v in t_s], E_k=[round(v, 7) for v in ek_s], eps=[round(v, 7) for v in eps_s])
+        ctx.close()
+        del q, u, uh, drv
+        gc.collect()
+        torch.cuda.empty_cache()
+    a, b = out["tgv_re100_m3_p2"], out["tgv_re100_m2_p3"]
+    variants["tgv_re100_dissipation_m3p2_vs_m2p3"] = dict(
+        t_end_over_tc=args.tgv_eps, runs=out,
+        eps_peak_rel_diff=round(abs(a["eps_peak"] - b["eps_peak"]) / max(a["eps_peak"], b["eps_peak"]), 4))
+
+
 def learned_p3_variant(args, dev_fn, variants):
     """The learned coarse correction on the 32^3 mesh with 4^3-element macros
     at p = 3 (512 macros, chunked FP32 condensation): pairs harvested from a
@@ -391,6 +456,9 @@ def main():
                     help="fixed elimination launch shape for every class instead of the autotuner (profiling)")
     ap.add_argument("--first-layer", action="store_true",
                     help="also time the standard (first-layer) condensation against the second layer at 24^3")
+    ap.add_argument("--tgv-eps", type=float, default=0.0, metavar="T_END",
+                    help="also integrate the Re = 100 Taylor-Green flow to t/t_c = T_END on (m,p) = (3,2) and (2,3) "
+                         "and report the dissipation rate")
     ap.add_argument("--train-seeds", type=int, default=2)
     ap.add_argument("--train-vectors", type=int, default=40)
     ap.add_argument("--train-epochs", type=int, default=60)
@@ -623,6 +691,9 @@ def main():
         free_device_memory()
     if args.first_layer:
         first_layer_variant(args, dev, variants)
+        free_device_memory()
+    if args.tgv_eps > 0:
+        tgv_dissipation_variant(args, dev, variants)
         free_device_memory()
     if args.big_steps > 0:
         big_variant(args, dev, variants)

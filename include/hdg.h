@@ -260,6 +260,20 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat);
  * pivot. */
 hdg_status hdg_condense_first_layer(hdg_ctx ctx, double* bhat);
 
+/* Flow diagnostics of the Taylor-Green study (Sec. 5.3, eq. C5321) for the
+ * state (q, u) (device, layouts as in hdg_linearize_stage), in the
+ * library's units (rho_inf = c_inf = mu = 1, mu_eff = mu / Re_c):
+ *   out_host[0] = E_k = (1/|Omega|) int 1/2 rho |v|^2,
+ *   out_host[1] = eps = 2 mu_eff / |Omega| int rho |omega|^2 / 2, omega = curl v
+ *                 (2D: the scalar d_x v_y - d_y v_x), the velocity gradient
+ *                 from q by the chain rule d_k v_j = (q_k[m_j] - v_j q_k[rho]) / rho,
+ *   out_host[2] = |Omega|,
+ * integrated with the element quadrature; deterministic (fixed summation
+ * order).  Uses the workspace's reduction buffer; synchronises the stream.
+ * A state with rho <= 0 gives non-finite values (no error).
+ * HDG_EINVAL on null pointers, HDG_ENOMEM without a workspace. */
+hdg_status hdg_flow_diagnostics(hdg_ctx ctx, const double* q, const double* u, double out_host[3]);
+
 /* y = A-hat x = sum_i P_i^T A-hat^{T_i} P_i x (Algorithm 2 with the condensed
  * blocks formed by hdg_condense, in the precision of that call; sums in
  * FP64); x, y device, n_glob, must not alias. */

@@ -696,6 +696,18 @@ hdg_status hdg_condense_first_layer(hdg_ctx ctx, double* bhat) {
   return HDG_OK;
 }
 
+hdg_status hdg_flow_diagnostics(hdg_ctx ctx, const double* q, const double* u, double out_host[3]) {
+  if (!ctx || !q || !u || !out_host) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  double* dev_out = c.ws.small + 2056;
+  HIPCHK(&c, launch_flow_diagnostics(c, q, u, dev_out));
+  HIPCHK(&c, hipMemcpyAsync(ctx->pinned, dev_out, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  for (int i = 0; i < 3; ++i) out_host[i] = ctx->pinned[i];
+  return HDG_OK;
+}
+
 hdg_status hdg_apply_global(hdg_ctx ctx, const double* x, double* y) {
   if (!ctx || !x || !y || x == y) return HDG_EINVAL;
   HdgContext& c = ctx->c;

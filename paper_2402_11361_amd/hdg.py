@@ -69,7 +69,7 @@ EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_o
            "hdg_coarse_prolong", "hdg_mlp_param_count", "hdg_mlp_work_floats", "hdg_mlp_forward",
            "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking",
            "hdg_autotune", "hdg_class_count", "hdg_get_tuning", "hdg_set_tuning",
-           "hdg_condense_first_layer"]
+           "hdg_condense_first_layer", "hdg_flow_diagnostics"]
 
 _lib = None
 
@@ -98,6 +98,7 @@ def load_library(path=LIB_PATH):
     lib.hdg_linearize_stage.argtypes = [vp, vp, vp, vp, vp, dp, dp, dp, vp]
     lib.hdg_condense.argtypes = [vp, i, vp]
     lib.hdg_condense_first_layer.argtypes = [vp, vp]
+    lib.hdg_flow_diagnostics.argtypes = [vp, vp, vp, vp]
     lib.hdg_apply_global.argtypes = [vp, vp, vp]
     lib.hdg_fgmres_solve.argtypes = [vp, vp, vp, ctypes.POINTER(KrylovOpts), ctypes.POINTER(KrylovStats)]
     lib.hdg_local_backsolve.argtypes = [vp, vp, vp, vp]
@@ -300,6 +301,13 @@ class Context:
         """Standard (first-layer) condensation of (q, u) together (chunked,
         one macro shape); same A-hat and b-hat as condense()."""
         self._check(self.lib.hdg_condense_first_layer(self.h, _ptr(bhat)))
+
+    def flow_diagnostics(self, q, u):
+        """(E_k, eps, |Omega|): volume-averaged kinetic energy and the
+        dissipation rate of eq. C5321 of the state (q, u), library units."""
+        out = np.zeros(3)
+        self._check(self.lib.hdg_flow_diagnostics(self.h, _ptr(q), _ptr(u), _np_ptr(out)))
+        return float(out[0]), float(out[1]), float(out[2])
 
     def apply_global(self, x, y):
         self._check(self.lib.hdg_apply_global(self.h, _ptr(x), _ptr(y)))

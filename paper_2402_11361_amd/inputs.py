@@ -66,6 +66,13 @@ CONFIGS = {
                mach=0.1, Re=1600.0, noise=1e-4, rtol=1e-8),
     "tgv48_m4_p2": dict(dim=3, n_elem=48, m=4, p=2, lo=-np.pi, hi=np.pi, periodic=True, state="tgv",
                mach=0.1, Re=1600.0, noise=1e-4, rtol=1e-8),
+    # the Re = 100 Taylor-Green run of the m-versus-p comparison (Sec. 5.3):
+    # 6 macros per axis and m p = 6, so both have N_eff = (6 (m p + 1))^3 = 42^3
+    # and the same n_u and n_b per macro; clean initial field
+    "tgv_re100_m3_p2": dict(dim=3, n_elem=18, m=3, p=2, lo=-np.pi, hi=np.pi, periodic=True, state="tgv",
+               mach=0.1, Re=100.0, noise=0.0, rtol=1e-8),
+    "tgv_re100_m2_p3": dict(dim=3, n_elem=12, m=2, p=3, lo=-np.pi, hi=np.pi, periodic=True, state="tgv",
+               mach=0.1, Re=100.0, noise=0.0, rtol=1e-8),
     # macros of uneven sizes: every axis of the 32^3 mesh cut into seeded
     # segments of 2, 3 or 4 elements (one degree for the whole mesh)
     "tgv32_uneven_p2": dict(dim=3, n_elem=32, m=None, parts=(2, 3, 4), seg_seed=3, p=2, lo=-np.pi, hi=np.pi, periodic=True,
