@@ -69,3 +69,48 @@ def test_first_layer_needs_chunking():
     b = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
     with pytest.raises(HdgError, match="EUNSUPPORTED"):
         ctx.condense_first_layer(b)
+
+
+def test_first_layer_tgv24_sampled_macros():
+    """The 24^3 workload in two chunks: first-layer blocks of sampled macros
+    against the oracle's route A, then the same blocks from the second layer
+    (pivot order 6860: the 24-row panel instance)."""
+    import torch
+    from oracle.mesh import box_mesh
+    from oracle.physics import Phys
+    from oracle.system import System
+    from paper_2402_11361_amd import inputs
+    from paper_2402_11361_amd.hdg import Context, mesh_spec_box
+    cfg = dict(inputs.CONFIGS["tgv24_m3_p2"])
+    say("[first layer tgv24] oracle mesh and inputs")
+    M = box_mesh(3, cfg["n_elem"], cfg["m"], cfg["p"], lo=cfg["lo"], hi=cfg["hi"], periodic=True)
+    S = System(M, Phys(Re=cfg["Re"], Mach=cfg["mach"]))
+    mc = [M.macro_node_coords(i) for i in range(M.n_macros)]
+    fc = [M.face_node_coords(f) for f in range(M.n_faces)]
+    u, q, uh = inputs.make_state(cfg, mc, fc, seed=0)
+    dii = 1.0 / 0.435866521508459
+    dt = inputs.cfl_dt(cfg)
+    w = -dii * u
+    ctx = Context.from_mesh_spec(mesh_spec_box(3, cfg["n_elem"], cfg["m"], cfg["p"], cfg["lo"], cfg["hi"], True),
+                                 Re=cfg["Re"], Mach=cfg["mach"])
+    ctx.set_chunking((ctx.n_macros + 1) // 2)
+    ctx.bind_workspace()
+    ctx.linearize_stage(to_dev(q), to_dev(u), to_dev(uh), to_dev(w), dt, dii)
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    say("[first layer tgv24] GPU first-layer condensation")
+    ctx.condense_first_layer(bhat)
+    sample = [0, 511]
+    first = {i: ctx.get_condensed(i) for i in sample}
+    say("[first layer tgv24] oracle route A of sampled macros")
+    lin = S.linearize(q, u, uh, w=w, dt=dt, dii=dii, macros=sample)
+    cond = S.condense(lin, "A")
+    for i in sample:
+        ea, eb = _rel(first[i][0], cond[i]["Ahat"]), _rel(first[i][1], cond[i]["bhat"])
+        say(f"[first layer tgv24] macro {i}: A-hat {ea:.2e} b-hat {eb:.2e}")
+        assert ea < 1e-9 and eb < 1e-9
+    b1 = bhat.clone()
+    ctx.condense(bhat)
+    for i in sample:
+        assert _rel(ctx.get_condensed(i)[0], first[i][0]) < 1e-10
+    assert _rel(b1.cpu().numpy(), bhat.cpu().numpy()) < 1e-9
+    ctx.close()
