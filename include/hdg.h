@@ -191,7 +191,8 @@ hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk);
  * panel factorisation, then the 1024-thread panel with the best of those,
  * then the factorisation of the next pair of column blocks on a second
  * stream beside the trailing update -- on the current linearisation, and
- * keeps the fastest.
+ * keeps the fastest (the wider panel and the second stream only when they
+ * gain more than 2%, the spread of single timings).
  * cache_path (host string, may be NULL): text file of earlier choices, one
  * line per (GPU architecture, HIP runtime version, precision, class shape,
  * batch size); classes found there are not timed, new choices are appended.
