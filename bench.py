@@ -32,7 +32,7 @@ PEAK_HBM_GBS = 8000.0
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by what the counters
 # read for a 1 GiB device copy in the same run (profiles/stage_solve_tgv24_m3_p2_fp64.md),
 # valid only while the kernel sources hash to `sha`.
-CONDENSE_TRAFFIC = {"sha": "6a5e9a9798690406", "bytes": 1165.0e9}
+CONDENSE_TRAFFIC = {"sha": "e0ebc3daaf95b564", "bytes": 1161.2e9}
 CONDENSE_SOURCES = ("k_form.hip", "k_lu.hip")
 
 

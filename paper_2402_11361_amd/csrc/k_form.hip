@@ -34,7 +34,17 @@ struct FormPtrs {
   int coef_off;      // LDS offset (doubles) of the staged coefficient rows, after the row buffers
   int only_class;    // >= 0: rows of other macro classes are skipped
   int split_cols;    // >= 0: grouped launch takes classes with n_cols <= split_cols, single-row launch the rest
+  int tab_off;       // LDS byte offset of the class's 1D operators C1D and Minv1D (FP64)
 };
+
+// Macro of row group G: a guess from the mean group count per macro (exact
+// when every macro has the same size), else the binary search.
+__device__ __forceinline__ int macro_of_row(const long long* off, int n, long long g) {
+  int i = (int)((double)g / (double)off[n] * n);
+  i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+  if (off[i] <= g && g < off[i + 1]) return i;
+  return find_in(off, n, g);
+}
 
 // Quotient and remainder of 0 <= x < 2^22 by 1 <= y < 2^22 through the FP32
 // reciprocal: the relative error of x * rcp(y) is below 2^-22, so the
@@ -57,8 +67,8 @@ __device__ __forceinline__ void digits(int x, int base, int d, int* out) {
 // (row_rr = row + rr * ldr).  The coefficient functor returns 0 for element
 // nodes that carry none (trace rows use only the nodes of their sub-face).
 template <int NR, int NT, class TL, class Coef>
-__device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, double sgn_line, double sgn_face,
-                              TL* row, int ldr, int tid) {
+__device__ void add_direction(const ClassDev& cd, const double* C1Ds, const double* Minv1Ds, int e, int k, Coef coef,
+                              double sgn_line, double sgn_face, TL* row, int ldr, int tid) {
   const int d = cd.dim, p = cd.p, A1 = p + 1, ns = cd.ns;
   int eidx[3] = {0, 0, 0};
   {
@@ -67,8 +77,8 @@ __device__ void add_direction(const ClassDev& cd, int e, int k, Coef coef, doubl
   }
   const int nk = cd.n1[k], nm = cd.nmax1;
   const int T = cd.T;  // (p+1)^(d-1) tangential combinations of an element
-  const double* Ck = cd.C1D + (size_t)k * nm * nm;
-  const double* Mk = cd.Minv1D + (size_t)k * nm * nm;
+  const double* Ck = C1Ds + (size_t)k * nm * nm;     // LDS copies of cd.C1D, cd.Minv1D
+  const double* Mk = Minv1Ds + (size_t)k * nm * nm;
   int stride[3] = {1, cd.n1[0], cd.n1[0] * cd.n1[1]};
   // line targets
   for (int i = tid; i < ns * T * nk; i += NT) {
@@ -163,7 +173,7 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
   __shared__ double red[NR * (NT / 64)];
   const int tid = threadIdx.x;
   const long long G = fp.group0 + blockIdx.x;
-  const int macro = find_in(md.row_off, md.n_macros, G * NR);
+  const int macro = macro_of_row(md.row_off, md.n_macros, G * NR);
   const int g = (int)(G - md.row_off[macro] / NR);
   if (fp.only_class >= 0 && md.macro_class[macro] != fp.only_class) return;
   const ClassDev& cd = class_of(md, macro);
@@ -173,6 +183,14 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
   const int n_cols = cd.n_cols, ldr = n_cols;
   TL* sc = row + fp.coef_off;  // staged coefficient rows
   for (int i = tid; i < NR * n_cols; i += NT) row[i] = TL(0);
+  // the class's 1D operators, read by every line and face target
+  double* C1Ds = reinterpret_cast<double*>(form_smem + fp.tab_off);
+  const int tsz = d * cd.nmax1 * cd.nmax1;
+  double* Minv1Ds = C1Ds + tsz;
+  for (int i = tid; i < tsz; i += NT) {
+    C1Ds[i] = cd.C1D[i];
+    Minv1Ds[i] = cd.Minv1D[i];
+  }
   // rows of the group: r_rr = r0 + rr * rstride
   int r0, rstride;
   bool urow;
@@ -243,7 +261,7 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
       for (int k = 0; k < d; ++k) {
         if (k > 0) __syncthreads();
         auto coef = [&](int rr, int kk, int cp, int b) { return (double)sc[rr * dnsA + (kk * ns + cp) * A + b]; };
-        add_direction<NR, NT>(cd, e, k, coef, -1.0, 1.0, row, ldr, tid);
+        add_direction<NR, NT>(cd, C1Ds, Minv1Ds, e, k, coef, -1.0, 1.0, row, ldr, tid);
       }
       // A_u,uh on the element's macro-boundary faces through node a
       for (int lf2 = 0; lf2 < 2 * d; ++lf2) {
@@ -315,7 +333,7 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
           const int tb = finv[b];
           return tb < 0 ? 0.0 : (double)sc[rr * dnst + (kk * ns + cp) * T + tb];
         };
-        add_direction<NR, NT>(cd, e, k, coef, -1.0, 1.0, row, ldr, tid);
+        add_direction<NR, NT>(cd, C1Ds, Minv1Ds, e, k, coef, -1.0, 1.0, row, ldr, tid);
       }
     }
     block_sum<NR, NT>(fpart, red, tid);
@@ -344,9 +362,15 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
 }
 
 // Row buffers (n_cols of the largest class taken) and staged coefficient
-// rows (A_uq^e rows: d n_s A values; trace rows use d n_s T <= that).
+// rows (A_uq^e rows: d n_s A values; trace rows use d n_s T <= that), then
+// (8-byte aligned) the 1D operators C1D and Minv1D of the largest class.
+size_t form_tab_off(const HdgContext& c, int nr, size_t elem, int n_cols) {
+  return (elem * (size_t)nr * ((size_t)n_cols + (size_t)c.dnsA) + 7) / 8 * 8;
+}
 size_t form_lds_bytes(const HdgContext& c, int nr, size_t elem, int n_cols) {
-  return elem * (size_t)nr * ((size_t)n_cols + (size_t)c.dnsA);
+  int nm = 1;
+  for (const HostClass& k : c.hcs) nm = std::max(nm, k.nmax1);
+  return form_tab_off(c, nr, elem, n_cols) + sizeof(double) * 2 * (size_t)c.hm.dim * nm * nm;
 }
 
 template <class TW, int NR, int NT>
@@ -354,7 +378,7 @@ hipError_t form_launch(HdgContext& c, int m0, int m1, TW* W, double* gloc, int o
                        int split_cols) {
   FormPtrs fp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.ws.RQt, c.ws.RBloc, gloc,
               c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.hm.row_off[m0] / NR,
-              NR * n_cols, only_class, split_cols};
+              NR * n_cols, only_class, split_cols, (int)form_tab_off(c, NR, sizeof(TW), n_cols)};
   const long long nblk = (c.hm.row_off[m1] - c.hm.row_off[m0]) / NR;
   if (nblk <= 0) return hipSuccess;
   const size_t shm = form_lds_bytes(c, NR, sizeof(TW), n_cols);
