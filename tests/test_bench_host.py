@@ -1,0 +1,32 @@
+"""Host-side logic of bench.py: the one-GPU guard and the algorithmic flop
+count of the condensation the roofline line is priced with."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_condense_flops_24cubed():
+    sys.path.insert(0, ROOT)
+    import bench
+    cfg = dict(dim=3, p=2, m=3)
+    n_u, n_b = 1715, 1470
+    lu = 2.0 / 3.0 * n_u ** 3
+    schur = 2.0 * n_u ** 2 * n_b + 2.0 * n_b ** 2 * n_u
+    # formation: 2 d n_s^2 (p+1)^(2d) per (node, element) pair and twice that per trace row
+    form = 2 * 3 * 25 * 3 ** 6 * 343 * 27 + 4 * 3 * 25 * 3 ** 6 * (n_b / 5) * 27
+    f = bench.condense_flops(cfg, n_u, n_b)
+    assert f == pytest.approx(lu + schur + form, rel=1e-12)
+    # 2.22e10 per macro, 1.135e13 for the 512 macros of the workload
+    assert f == pytest.approx(2.217e10, rel=2e-3)
+    assert 512 * f == pytest.approx(1.135e13, rel=2e-3)
