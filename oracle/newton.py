@@ -28,7 +28,7 @@ def newton_solve(S, q, u, uhat, w=None, dt=np.inf, dii=1.0, ptc=False, tau_init=
                  abs_tol=1e-10, rel_tol=1e-8, max_it=20, linear="direct", krylov_opts=None):
     """Solve R(q, u, uhat) = 0 for one stage.  Returns (q, u, uhat, info)."""
     q, u, uhat = q.copy(), u.copy(), uhat.copy()
-    hist = []
+    hist, dtaus = [], []
     dtau = tau_init if ptc else np.inf
     RQ, RU, RB = S.residual(q, u, uhat, w, dt, dii)
     r0 = np.sqrt(RQ @ RQ + RU @ RU + RB @ RB)
@@ -39,6 +39,7 @@ def newton_solve(S, q, u, uhat, w=None, dt=np.inf, dii=1.0, ptc=False, tau_init=
         if rn <= max(abs_tol, rel_tol * r0):
             break
         lin = S.linearize(q, u, uhat, w, dt, dii, dtau)
+        dtaus.append(dtau)
         cond = S.condense(lin, "B")
         A, b = S.assemble(cond)
         if linear == "direct":
@@ -57,7 +58,7 @@ def newton_solve(S, q, u, uhat, w=None, dt=np.inf, dii=1.0, ptc=False, tau_init=
             rU = np.linalg.norm(RU)
             dtau = min(dtau * rU_prev / max(rU, 1e-300), tau_max)
             rU_prev = rU
-    return q, u, uhat, dict(res_hist=hist, its=len(hist) - 1)
+    return q, u, uhat, dict(res_hist=hist, its=len(hist) - 1, dtau_hist=dtaus)
 
 
 def dirk_step(S, q, u, uhat, dt, newton_kw=None):

@@ -29,14 +29,16 @@ def test_gradient_equation_exact_for_linear_fields(dim):
     S, q, u, uh, _ = small_case(dim=dim, n_elem=4, m=2, p=2, periodic=False, state="shear")
     M = S.mesh
     ns = dim + 2
-    A = np.random.default_rng(3).standard_normal((ns, dim))
-    c0 = np.random.default_rng(4).standard_normal(ns)
+    # a physical linear state (rho > 0 and pressure > 0 on the unit box)
+    A = 0.1 * np.random.default_rng(3).standard_normal((ns, dim))
+    c0 = np.array([1.0] + list(0.05 * np.random.default_rng(4).standard_normal(dim)) + [2.5])
     lin = lambda X: (c0[:, None] + A @ X.T)
     u = np.concatenate([lin(M.macro_node_coords(i)).reshape(-1) for i in range(M.n_macros)])
     uh = np.concatenate([lin(M.face_node_coords(f)).reshape(-1) for f in range(M.n_faces)])
     q = np.concatenate([np.repeat(A.T[:, :, None], S.cls(i).N, axis=2).reshape(-1) for i in range(M.n_macros)])
-    RQ, _, _ = S.residual(q, u, uh)
+    RQ, RU, RB = S.residual(q, u, uh)
     assert abs(RQ).max() < 1e-13
+    assert np.all(np.isfinite(RU)) and np.all(np.isfinite(RB))
 
 
 @pytest.mark.parametrize("supg", [False, True])
