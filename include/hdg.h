@@ -109,12 +109,18 @@ typedef struct {
   double rtol, atol;
   int restart, max_outer, inner_its;
   hdg_prec inner_prec;
-  /* 1: add the learned coarse correction bound by hdg_learned_bind to every
-   * preconditioner application, with fallback to the plain preconditioner
-   * for the rest of the solve once the learned steps reduce the residual
-   * less, on average over at least 3 steps, than the plain steps seen so far
-   * on this context (or once a learned step fails to reduce it). */
+  /* 1: add the learned coarse correction bound by hdg_learned_bind to the
+   * preconditioner.  The plain preconditioner is the judge: the first 3
+   * steps of the solve run plain and give the mean per-step residual
+   * reduction |g_{j+1}| / |g_j| of this operator; then the learned stage is
+   * switched on, and it falls back to the plain preconditioner for the rest
+   * of the solve once its mean reduction over at least 3 steps is worse than
+   * the plain mean, or once one of its steps reduces the residual by less
+   * than 1% (ratio >= 0.99). */
   int use_learned;
+  /* 1: keep the learned stage for the whole solve (no fallback; for
+   * measuring what the network gains or loses on its own). */
+  int no_fallback;
   /* optional (device, may be NULL): the vectors the preconditioner is
    * applied to are copied here, harvest_max vectors of n_glob doubles at
    * most, in the order they occur (training data of the learned stage). */

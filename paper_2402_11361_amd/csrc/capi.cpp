@@ -729,11 +729,16 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
   if (o->use_learned && !c.lrn_bound) return fail(&c, HDG_EINVAL, "use_learned without a bound network");
   if (o->harvest_max < 0 || (o->harvest_max > 0 && !o->harvest)) return fail(&c, HDG_EINVAL, "bad harvest buffer");
   Krylov K(c, o->restart, o->inner_its, ctx->pinned, icode);
-  K.learned = o->use_learned != 0;
+  // the learned stage is judged against the plain preconditioner of this
+  // solve: the first LRN_JUDGE_STEPS steps run plain and measure its mean
+  // residual reduction, then the learned stage is switched on
+  const bool use_learned = o->use_learned != 0;
+  const int judge_steps = use_learned ? LRN_JUDGE_STEPS : 0;
+  K.learned = use_learned && judge_steps == 0;
   const long long n = K.n;
   int harvested = 0, fallbacks = 0;
-  double lrn_log = 0.0;
-  int lrn_steps = 0;
+  double lrn_log = 0.0, plain_log = 0.0;
+  int lrn_steps = 0, plain_n = 0;
   double bnorm, beta;
   HIPCHK(&c, K.norm(b, bnorm));
   const double tol = std::max(o->rtol * bnorm, o->atol);
@@ -743,24 +748,28 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
   int its = 0;
   const int m = o->restart;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  // residual reduction of one step: plain steps feed the context's running
-  // average; learned steps are compared with it (fallback rule of the options)
+  // residual reduction |g_{j+1}| / |g_j| of one step (at most 1 in FGMRES):
+  // plain steps feed this solve's mean plain rate; learned steps are compared
+  // with it (fallback rule of the options)
   auto account = [&](bool step_learned, double rate) {
     if (!(rate > 0.0)) return;
     if (!step_learned) {
-      c.plain_log_rate += std::log(rate);
-      ++c.plain_steps;
+      plain_log += std::log(rate);
+      ++plain_n;
+      if (use_learned && !fallbacks && plain_n >= judge_steps) K.learned = true;
       return;
     }
     lrn_log += std::log(rate);
     ++lrn_steps;
-    const bool worse_than_plain =
-        lrn_steps >= 3 && c.plain_steps >= 3 && lrn_log / lrn_steps > c.plain_log_rate / c.plain_steps;
-    if (rate >= 1.0 || worse_than_plain) {
+    if (o->no_fallback) return;
+    const bool worse_than_plain = lrn_steps >= 3 && plain_n >= 1 && lrn_log / lrn_steps > plain_log / plain_n;
+    if (rate >= LRN_STAGNATION || worse_than_plain) {
       K.learned = false;
       fallbacks = 1;
     }
   };
+  // steps left before the learned stage may switch on (graph batches stop there)
+  auto judging_left = [&]() { return (use_learned && !fallbacks && !K.learned) ? judge_steps - plain_n : 0; };
   const bool dev_mode = o->graph_steps > 0 && o->harvest_max == 0;
   if (dev_mode) K.dev_init();
   while (beta > tol && its < o->max_outer) {
@@ -778,7 +787,8 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
       bool done = false;
       int batch = o->graph_steps;
       for (int j = 0; j < m && !done;) {
-        const int kk = std::min(std::min(batch, m - j), o->max_outer - its);
+        int kk = std::min(std::min(batch, m - j), o->max_outer - its);
+        if (judging_left() > 0) kk = std::min(kk, judging_left());
         const double res_in = prev;
         const bool step_learned = K.learned;
         HIPCHK(&c, K.steps_graph(j, kk, m));
@@ -960,6 +970,8 @@ hdg_status hdg_learned_bind(hdg_ctx ctx, const hdg_mlp* net) {
     return fail(&c, HDG_EINVAL, "network shape does not match the coarse space (or n_hidden > 512)");
   unsigned short* q = reinterpret_cast<unsigned short*>(c.ws.lrn + 2 * (size_t)c.hm.n_macros * c.cd.cF);
   HIPCHK(&c, launch_to_bf16(c.stream, (long long)mlp_param_count(net->n_in, net->n_hidden, net->n_out), net->params, q));
+  // captured FGMRES steps hold the inference launch shape of the old width
+  if (c.lrn_hidden != net->n_hidden) clear_graphs(c);
   c.lrn_hidden = net->n_hidden;
   c.lrn_bound = true;
   return HDG_OK;

@@ -125,8 +125,6 @@ struct HdgContext {
   // learned coarse correction
   bool lrn_bound = false;
   int lrn_hidden = 0;
-  double plain_log_rate = 0.0;  // sum of log(residual reduction) over plain FGMRES steps
-  long long plain_steps = 0;
   // captured FGMRES steps: key (first step, steps, restart, inner its, inner prec,
   // condensed prec, learned, FP32 copy present) -> executable graph
   std::map<std::array<int, 8>, hipGraphExec_t> graphs;

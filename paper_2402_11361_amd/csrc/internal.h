@@ -163,6 +163,10 @@ hipError_t launch_flow_diagnostics(HdgContext& c, const double* q, const double*
 
 // learned coarse correction
 constexpr int LRN_MAX_HIDDEN = 512;
+// learned-stage judge: plain FGMRES steps at the start of a solve that give
+// the plain mean reduction, and the per-step reduction counted as stagnation
+constexpr int LRN_JUDGE_STEPS = 3;
+constexpr double LRN_STAGNATION = 0.99;
 size_t mlp_param_count(int n_in, int n_hidden, int n_out);
 size_t mlp_work_floats(int n_in, int n_hidden, int n_out, int max_batch);
 hipError_t launch_coarse_restrict(HdgContext& c, const double* v, float* X);

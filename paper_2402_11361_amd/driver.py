@@ -64,7 +64,7 @@ class StageDriver:
         """Newton iterations on (q, u, uh) in place until ||R_F|| <= max(abs, rel ||R_F^0||)."""
         ctx = self.ctx
         dtau = tau_init if ptc else math.inf
-        hist, krylov = [], []
+        hist, krylov, dtaus = [], [], []
         rU_prev = None
         r0 = None
         mark = self.mark
@@ -81,6 +81,7 @@ class StageDriver:
             rU_prev = nrm[1]
             if rn <= max(self.newton_abs, self.newton_rel * r0) or it == self.max_newton:
                 break
+            dtaus.append(dtau)
             mark("condense")
             ctx.condense(self.bhat, self.condense_prec)
             mark("fgmres")
@@ -92,7 +93,7 @@ class StageDriver:
             ctx.axpy(1.0, self.du, u)
             ctx.axpy(1.0, self.x, uh)
         mark("end")
-        return dict(newton_its=len(hist) - 1, res_hist=hist, krylov=krylov)
+        return dict(newton_its=len(hist) - 1, res_hist=hist, krylov=krylov, dtau_hist=dtaus)
 
     def step(self, q, u, uh, dt):
         """One DIRK(3,3) time step in place; returns per-stage infos."""

@@ -45,8 +45,8 @@ class _Sizes(ctypes.Structure):
 class KrylovOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("restart", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("inner_its", ctypes.c_int), ("inner_prec", ctypes.c_int),
-                ("use_learned", ctypes.c_int), ("harvest", ctypes.c_void_p), ("harvest_max", ctypes.c_int),
-                ("graph_steps", ctypes.c_int)]
+                ("use_learned", ctypes.c_int), ("no_fallback", ctypes.c_int), ("harvest", ctypes.c_void_p),
+                ("harvest_max", ctypes.c_int), ("graph_steps", ctypes.c_int)]
 
 
 class KrylovStats(ctypes.Structure):
@@ -313,14 +313,16 @@ class Context:
         self._check(self.lib.hdg_apply_global(self.h, _ptr(x), _ptr(y)))
 
     def fgmres_solve(self, b, x, rtol=1e-8, atol=0.0, restart=30, max_outer=300, inner_its=5,
-                     inner_prec=HDG_FP64, allow_noconv=False, use_learned=False, harvest=None, graph_steps=0):
+                     inner_prec=HDG_FP64, allow_noconv=False, use_learned=False, harvest=None, graph_steps=0,
+                     no_fallback=False):
         """harvest: optional device tensor [k, n_glob] receiving the vectors the
         preconditioner is applied to (first k).  graph_steps > 0: device-resident
-        Arnoldi steps replayed from HIP graphs of that many steps."""
+        Arnoldi steps replayed from HIP graphs of that many steps.  no_fallback:
+        keep the learned stage for the whole solve."""
         hv = _ptr(harvest) if harvest is not None else None
         hk = int(harvest.shape[0]) if harvest is not None else 0
-        o = KrylovOpts(rtol, atol, restart, max_outer, inner_its, inner_prec, int(bool(use_learned)), hv, hk,
-                       int(graph_steps))
+        o = KrylovOpts(rtol, atol, restart, max_outer, inner_its, inner_prec, int(bool(use_learned)),
+                       int(bool(no_fallback)), hv, hk, int(graph_steps))
         st = KrylovStats()
         code = self.lib.hdg_fgmres_solve(self.h, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(st))
         if not (allow_noconv and code == 5):

@@ -10,7 +10,9 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("case", [dict(dim=2, n_elem=4, m=2, p=2, periodic=True, mach=0.1, Re=100.0),
                                   dict(dim=2, n_elem=4, m=2, p=1, periodic=False, state="shear", mach=0.2),
-                                  dict(dim=2, n_elem=4, m=2, p=2, periodic=True, mach=0.1, Re=100.0, supg=True)])
+                                  dict(dim=2, n_elem=4, m=2, p=2, periodic=True, mach=0.1, Re=100.0, supg=True),
+                                  dict(dim=3, n_elem=2, m=1, p=2, periodic=True, mach=0.1, Re=100.0, supg=True,
+                                       noise=1e-2)])
 def test_dirk_step_matches_oracle(case):
     from oracle.newton import dirk_step
     from paper_2402_11361_amd.driver import StageDriver, alexander_dirk33
@@ -35,3 +37,38 @@ def test_dirk_step_matches_oracle(case):
     assert du < 1e-10 and duh < 1e-10 and dq < 1e-8, (du, duh, dq)
     # the step changed the state (not a trivial pass)
     assert np.abs(uo - inp["u"]).max() > 1e-6
+
+
+@pytest.mark.parametrize("case,tau0", [(dict(dim=2, n_elem=4, m=2, p=2, periodic=True, mach=0.1, Re=100.0,
+                                              noise=1e-2), 0.3),
+                                        (dict(dim=3, n_elem=2, m=1, p=2, periodic=False, state="shear", mach=0.2,
+                                              noise=1e-2), 0.1)])
+def test_ptc_stage_matches_oracle(case, tau0):
+    """A DIRK stage solved by Newton with pseudo-transient continuation (finite
+    dtau adds M / dtau to A_uu; SER update of eq. C31222) against the oracle's
+    newton_solve with the same continuation: the same dtau sequence, the same
+    stage solution, which is also the solution without continuation."""
+    from oracle.newton import newton_solve
+    from paper_2402_11361_amd.driver import StageDriver
+    say(f"[ptc] {case}")
+    S, inp, ctx = make_pair(case)
+    drv = StageDriver(ctx, rtol=1e-13, newton_abs=1e-12, newton_rel=1e-12, max_newton=30)
+    q, u, uh, w = (to_dev(inp[k]) for k in ("q", "u", "uh", "w"))
+    info = drv.solve_stage(q, u, uh, w, inp["dt"], inp["dii"], ptc=True, tau_init=tau0)
+    qo, uo, uho, oinfo = newton_solve(S, inp["q"], inp["u"], inp["uh"], w=inp["w"], dt=inp["dt"], dii=inp["dii"],
+                                      ptc=True, tau_init=tau0, abs_tol=1e-12, rel_tol=1e-12, max_it=30)
+    _, u_plain, uh_plain, pinfo = newton_solve(S, inp["q"], inp["u"], inp["uh"], w=inp["w"], dt=inp["dt"],
+                                               dii=inp["dii"], abs_tol=1e-12, rel_tol=1e-12, max_it=30)
+    say(f"[ptc] GPU {info['newton_its']} its, oracle {oinfo['its']} its, plain Newton {pinfo['its']} its")
+    assert info["res_hist"][-1] < 1e-11 and oinfo["res_hist"][-1] < 1e-11
+    # the continuation slows Newton down from this pseudo-time step: it ran
+    assert oinfo["its"] > pinfo["its"]
+    g, o = info["dtau_hist"], oinfo["dtau_hist"]
+    assert g[0] == o[0] == tau0
+    # the sequences agree while the residuals are far above rounding
+    for k in range(min(len(g), len(o), 4)):
+        assert abs(g[k] - o[k]) <= 1e-6 * o[k], (g, o)
+    du = np.abs(u.cpu().numpy() - uo).max() / np.abs(uo).max()
+    duh = np.abs(uh.cpu().numpy() - uho).max() / np.abs(uho).max()
+    assert du < 1e-10 and duh < 1e-10, (du, duh)
+    assert np.abs(uo - u_plain).max() < 1e-10 * np.abs(u_plain).max()

@@ -108,12 +108,12 @@ def test_condensed_and_apply_and_solve(pairs, name):
     ctx.condense(bhat)
     for i in lin:
         A_i, b_i = ctx.get_condensed(i)
-        _close(A_i, cond[i]["Ahat"], 1e-9, f"Ahat macro {i}")
-        _close(b_i, cond[i]["bhat"], 1e-9, f"bhat macro {i}")
+        _close(A_i, cond[i]["Ahat"], 1e-10, f"Ahat macro {i}")
+        _close(b_i, cond[i]["bhat"], 1e-10, f"bhat macro {i}")
     if len(lin) < S.mesh.n_macros:
         return  # global checks need every macro in the oracle
     A, b = S.assemble(cond)
-    _close(bhat.cpu().numpy(), b, 1e-9, "assembled bhat")
+    _close(bhat.cpu().numpy(), b, 1e-10, "assembled bhat")
     say(f"[apply] {name}")
     x = np.random.default_rng(7).standard_normal(ctx.n_glob)
     y = torch.zeros_like(bhat)
@@ -122,13 +122,82 @@ def test_condensed_and_apply_and_solve(pairs, name):
     say(f"[fgmres] {name}")
     x_ref = S.solve_direct(A, b)
     xg = torch.zeros_like(bhat)
+    # run to rtol 1e-13 (near stagnation): the error is bounded by
+    # kappa(A-hat) * 1e-13 plus the rounding of the operator, well inside 1e-10
+    # for these small condensed systems
     info = ctx.fgmres_solve(bhat, xg, rtol=1e-13, restart=30, max_outer=400, inner_its=5)
     assert info["converged"], info
-    _close(xg.cpu().numpy(), x_ref, 1e-9, "FGMRES solution")
+    _close(xg.cpu().numpy(), x_ref, 1e-10, "FGMRES solution")
     say(f"[backsolve] {name}")
     dq = torch.zeros(ctx.n_q_tot, dtype=torch.float64, device="cuda")
     du = torch.zeros(ctx.n_u_tot, dtype=torch.float64, device="cuda")
     ctx.local_backsolve(to_dev(x_ref), dq, du)
     dq_o, du_o = S.backsolve(lin, cond, x_ref)
-    _close(du.cpu().numpy(), du_o, 1e-9, "dU")
-    _close(dq.cpu().numpy(), dq_o, 1e-9, "dQ")
+    _close(du.cpu().numpy(), du_o, 1e-10, "dU")
+    _close(dq.cpu().numpy(), dq_o, 1e-10, "dQ")
+
+
+def _assembled(pairs, name):
+    import torch
+    S, inp, ctx, d, nrm, lin, cond = _get(pairs, name)
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    ctx.condense(bhat)
+    A, b = S.assemble(cond)
+    return S, ctx, lin, A, b, bhat
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_precond_apply_matches_oracle(pairs, name):
+    """The preconditioner of Sec. 4.2 element by element: the inverse face
+    blocks of A_uhat-uhat alone (inner_its = 0), and inner GMRES with 5 steps
+    left-preconditioned by them, against the oracle's face_block_precond and
+    gmres_left_fixed on the assembled A-hat."""
+    import torch
+    from oracle import krylov, newton
+    S, ctx, lin, A, b, bhat = _assembled(pairs, name)
+    say(f"[precond] {name}")
+    v = np.random.default_rng(21).standard_normal(ctx.n_glob)
+    Minv = newton.face_block_precond(S, lin)
+    z = torch.zeros_like(bhat)
+    ctx.precond_apply(to_dev(v), z, 0)
+    _close(z.cpu().numpy(), Minv(v), 1e-11, "face-block inverse")
+    ctx.precond_apply(to_dev(v), z, 5)
+    ref = krylov.gmres_left_fixed(lambda x: A @ x, Minv, v, 5)
+    _close(z.cpu().numpy(), ref, 1e-9, "inner GMRES(5)")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_outer_iterations_match_oracle(pairs, name):
+    """Outer FGMRES iterations to rtol 1e-8 on the same A-hat and b-hat with the
+    same multi-level preconditioner: the library and the oracle's fgmres agree
+    to one iteration."""
+    import torch
+    from oracle import krylov, newton
+    S, ctx, lin, A, b, bhat = _assembled(pairs, name)
+    say(f"[iterations] {name}")
+    Minv = newton.face_block_precond(S, lin)
+    P = lambda v: krylov.gmres_left_fixed(lambda x: A @ x, Minv, v, 5)
+    xo, io = krylov.fgmres(lambda v: A @ v, b, precond=P, restart=30, rtol=1e-8, max_outer=400)
+    xg = torch.zeros_like(bhat)
+    ig = ctx.fgmres_solve(bhat, xg, rtol=1e-8, restart=30, max_outer=400, inner_its=5)
+    say(f"[iterations] {name}: library {ig['outer_its']}, oracle {io['its']}")
+    assert io["converged"] and ig["converged"]
+    assert abs(ig["outer_its"] - io["its"]) <= 1, (ig["outer_its"], io["its"])
+
+
+@pytest.mark.parametrize("name", ["3d_per_p2", "3d_per_uneven_p2", "2d_dir_p3"])
+def test_apply_is_bitwise_repeatable(pairs, name):
+    """The global apply sums each face's contributions in a fixed order: the
+    same x gives the same bits on every call, also after applies to other
+    vectors in between."""
+    import torch
+    S, ctx, lin, A, b, bhat = _assembled(pairs, name)
+    say(f"[repeat] {name}")
+    x = to_dev(np.random.default_rng(31).standard_normal(ctx.n_glob))
+    x2 = to_dev(np.random.default_rng(32).standard_normal(ctx.n_glob))
+    y1, y2, y3 = (torch.zeros_like(bhat) for _ in range(3))
+    ctx.apply_global(x, y1)
+    ctx.apply_global(x2, y3)
+    ctx.apply_global(x, y2)
+    assert torch.equal(y1, y2)
+    assert not torch.equal(y1, y3)
