@@ -281,6 +281,20 @@ hdg_status hdg_condense_first_layer(hdg_ctx ctx, double* bhat);
  * HDG_EINVAL on null pointers, HDG_ENOMEM without a workspace. */
 hdg_status hdg_flow_diagnostics(hdg_ctx ctx, const double* q, const double* u, double out_host[3]);
 
+/* hdg_flow_diagnostics for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, bit for bit, but the
+ * per-workgroup partial sums and the three results live in a static device
+ * array of the library (4 + 3 * 65536 doubles, about 1.5 MiB per device,
+ * held until the process ends) instead of the workspace, so no workspace
+ * needs to be bound and the call allocates nothing (the host result goes
+ * through a pinned buffer made at set-up).  The array holds a fixed number of
+ * partial sums whatever the mesh size (larger meshes fold more elements into
+ * each); HDG_EINVAL if a mesh would need more.  Every call on one GPU shares
+ * that GPU's array and overwrites it before reading it: calls that overlap
+ * on one GPU (several threads or streams) race.  Synchronises the stream. */
+hdg_status hdg_flow_diagnostics_noalloc(hdg_ctx ctx, const double* q, const double* u, double out_host[3]);
+
 /* y = A-hat x = sum_i P_i^T A-hat^{T_i} P_i x (Algorithm 2 with the condensed
  * blocks formed by hdg_condense, in the precision of that call; sums in
  * FP64); x, y device, n_glob, must not alias. */

@@ -308,6 +308,7 @@ hdg_status hdg_setup_mesh(const hdg_mesh_desc* mesh, const hdg_phys* phys, void*
   for (int v : c.hm.macro_bnd) any_bnd |= (v != 0);
   if (any_bnd && !phys->bc_state_host) { delete h; return HDG_EINVAL; }
   c.stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c.device) != hipSuccess || diag_scratch_setup(c.device) != hipSuccess) { delete h; return HDG_EDEVICE; }
   c.hcs.resize(c.hm.n_classes);
   for (int k = 0; k < c.hm.n_classes; ++k) build_class(c.hm, c.hcs[k], c.hm.class_m[k]);
   c.hc = c.hcs[0];
@@ -702,6 +703,19 @@ hdg_status hdg_flow_diagnostics(hdg_ctx ctx, const double* q, const double* u, d
   if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
   double* dev_out = c.ws.small + 2056;
   HIPCHK(&c, launch_flow_diagnostics(c, q, u, dev_out));
+  HIPCHK(&c, hipMemcpyAsync(ctx->pinned, dev_out, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  for (int i = 0; i < 3; ++i) out_host[i] = ctx->pinned[i];
+  return HDG_OK;
+}
+
+hdg_status hdg_flow_diagnostics_noalloc(hdg_ctx ctx, const double* q, const double* u, double out_host[3]) {
+  if (!ctx || !q || !u || !out_host) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  double* dev_out = nullptr;
+  std::string err;
+  hipError_t e = launch_flow_diagnostics_static(c, q, u, &dev_out, err);
+  if (e != hipSuccess) return err.empty() ? hip_fail(&c, e, "flow diagnostics") : fail(&c, HDG_EINVAL, err);
   HIPCHK(&c, hipMemcpyAsync(ctx->pinned, dev_out, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
   HIPCHK(&c, hipStreamSynchronize(c.stream));
   for (int i = 0; i < 3; ++i) out_host[i] = ctx->pinned[i];

@@ -102,6 +102,7 @@ struct HdgContext {
   PhysDev ph{};
   MeshDev md{};
   hipStream_t stream = nullptr;
+  int device = -1;                // HIP device current at set-up (the stream's device)
   std::vector<void*> dev_allocs;  // small tables owned by the context
   Workspace ws;
   bool ws_bound = false;

@@ -160,6 +160,9 @@ hipError_t launch_cast_ahat16(HdgContext& c);
 // first-layer condensation (chunked workspace, one macro class)
 hipError_t launch_condense_first_layer(HdgContext& c, int* status);
 hipError_t launch_flow_diagnostics(HdgContext& c, const double* q, const double* u, double* out3_dev);
+hipError_t diag_scratch_setup(int device);
+hipError_t launch_flow_diagnostics_static(HdgContext& c, const double* q, const double* u, double** out3_dev,
+                                          std::string& err);
 
 // learned coarse correction
 constexpr int LRN_MAX_HIDDEN = 512;

@@ -8,6 +8,7 @@
 // loop: the element's nodal u and q go to LDS, each lane takes quadrature
 // points; per-workgroup sums, then one fixed-order sum (deterministic).
 #include "context.h"
+#include <mutex>
 
 namespace {
 
@@ -102,12 +103,13 @@ __global__ void __launch_bounds__(DIAG_THREADS)
 
 }  // namespace
 
-hipError_t launch_flow_diagnostics(HdgContext& c, const double* q, const double* u, double* out3_dev) {
+namespace {
+
+hipError_t launch_diag(HdgContext& c, const double* q, const double* u, double* partial, double* out3_dev) {
   const long long nel = c.hm.el_off[c.hm.n_macros];
   const int nblk = (int)std::min<long long>(nel, DIAG_MAX_BLOCKS);
   if (nblk < 1) return hipErrorInvalidValue;
   const size_t shm = sizeof(double) * (size_t)(1 + c.hm.dim) * c.hm.ns * c.cd.A;  // one degree for every class
-  double* partial = c.ws.red;  // 3 DIAG_MAX_BLOCKS doubles of the 2^20 reduction buffer
   if (c.hm.dim == 3)
     hipLaunchKernelGGL(k_flow_diag<3>, dim3(nblk), dim3(DIAG_THREADS), shm, c.stream, c.md, q, u, nel, partial);
   else
@@ -117,4 +119,62 @@ hipError_t launch_flow_diagnostics(HdgContext& c, const double* q, const double*
   hipLaunchKernelGGL(k_flow_diag_finish, dim3(1), dim3(DIAG_THREADS), 0, c.stream, partial, nblk, c.ph.mu / c.ph.Re_c,
                      out3_dev);
   return hipGetLastError();
+}
+
+// Scratch of the variant without allocation: the three results, then the
+// per-workgroup partial sums (3 per workgroup, at most DIAG_MAX_BLOCKS
+// workgroups whatever the mesh size: the grid-stride loop folds further
+// elements into them).  Every call on a device shares that device's copy and
+// overwrites all of it before reading it; calls that overlap on one device
+// race.  In host code the array's name is not a device address: kernels get
+// the address looked up once per device by diag_scratch_setup.
+constexpr int DIAG_SCRATCH_OUT = 4;
+constexpr long long DIAG_SCRATCH_DOUBLES = DIAG_SCRATCH_OUT + 3LL * DIAG_MAX_BLOCKS;
+static __device__ __align__(256) double scratch[DIAG_SCRATCH_DOUBLES];
+
+constexpr int DIAG_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_ptr[DIAG_MAX_DEVICES] = {};
+
+}  // namespace
+
+// Called at context set-up with the context's device current: looks up this
+// device's address of `scratch` once.
+hipError_t diag_scratch_setup(int device) {
+  if (device < 0 || device >= DIAG_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_ptr[device]) return hipSuccess;
+  double* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+hipError_t launch_flow_diagnostics(HdgContext& c, const double* q, const double* u, double* out3_dev) {
+  return launch_diag(c, q, u, c.ws.red /* 3 DIAG_MAX_BLOCKS doubles of the 2^20 reduction buffer */, out3_dev);
+}
+
+// The same kernels with the static scratch of c.device; *out3_dev receives
+// the device address of the three results (inside the scratch).
+hipError_t launch_flow_diagnostics_static(HdgContext& c, const double* q, const double* u, double** out3_dev,
+                                          std::string& err) {
+  double* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (c.device >= 0 && c.device < DIAG_MAX_DEVICES) ptr = scratch_ptr[c.device];
+  }
+  if (!ptr) {
+    err = "static scratch of the device was not set up";
+    return hipErrorNotInitialized;
+  }
+  const long long nel = c.hm.el_off[c.hm.n_macros];
+  const long long nblk = std::min<long long>(nel, DIAG_MAX_BLOCKS);
+  if (DIAG_SCRATCH_OUT + 3 * nblk > DIAG_SCRATCH_DOUBLES) {
+    err = "partial sums exceed the static scratch";
+    return hipErrorInvalidValue;
+  }
+  *out3_dev = ptr;
+  return launch_diag(c, q, u, ptr + DIAG_SCRATCH_OUT, ptr);
 }

@@ -69,7 +69,7 @@ EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_o
            "hdg_coarse_prolong", "hdg_mlp_param_count", "hdg_mlp_work_floats", "hdg_mlp_forward",
            "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking",
            "hdg_autotune", "hdg_class_count", "hdg_get_tuning", "hdg_set_tuning",
-           "hdg_condense_first_layer", "hdg_flow_diagnostics"]
+           "hdg_condense_first_layer", "hdg_flow_diagnostics", "hdg_flow_diagnostics_noalloc"]
 
 _lib = None
 
@@ -99,6 +99,7 @@ def load_library(path=LIB_PATH):
     lib.hdg_condense.argtypes = [vp, i, vp]
     lib.hdg_condense_first_layer.argtypes = [vp, vp]
     lib.hdg_flow_diagnostics.argtypes = [vp, vp, vp, vp]
+    lib.hdg_flow_diagnostics_noalloc.argtypes = [vp, vp, vp, vp]
     lib.hdg_apply_global.argtypes = [vp, vp, vp]
     lib.hdg_fgmres_solve.argtypes = [vp, vp, vp, ctypes.POINTER(KrylovOpts), ctypes.POINTER(KrylovStats)]
     lib.hdg_local_backsolve.argtypes = [vp, vp, vp, vp]
@@ -307,6 +308,13 @@ class Context:
         dissipation rate of eq. C5321 of the state (q, u), library units."""
         out = np.zeros(3)
         self._check(self.lib.hdg_flow_diagnostics(self.h, _ptr(q), _ptr(u), _np_ptr(out)))
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def flow_diagnostics_noalloc(self, q, u):
+        """flow_diagnostics through the entry point that allocates nothing
+        (static device scratch; no workspace needed)."""
+        out = np.zeros(3)
+        self._check(self.lib.hdg_flow_diagnostics_noalloc(self.h, _ptr(q), _ptr(u), _np_ptr(out)))
         return float(out[0]), float(out[1]), float(out[2])
 
     def apply_global(self, x, y):
