@@ -1,14 +1,18 @@
-"""Benchmark: one DIRK stage of the macro-element HDG method solved by Newton's
-method on one MI355X (each Newton step: linearise -> second-layer condensation
--> FGMRES to 1e-8 -> local recovery -> update), on the Taylor-Green workload: 24^3 periodic hexes
-on [-pi, pi]^3, macros of 3^3 elements (512 macros), p = 2, Mach 0.1,
-Re 1600, seeded 1e-4 noise, first stage of Alexander's DIRK(3,3) with
-dt = CFL h / (V0 (p+1)), CFL = 1.
+"""Benchmark of the macro-element HDG hot path on one MI355X.
+
+Headline: Newton steps of the first DIRK(3,3) stage on the largest
+single-GPU workload, Taylor-Green 48^3 periodic hexes on [-pi, pi]^3 with
+macros of 4^3 elements (1728 macros), p = 2, Mach 0.1, Re 1600, seeded 1e-4
+noise, dt = CFL h / (V0 (p+1)), CFL = 1, plain FP64.  One timed step is one
+pass of the whole path from the same initial state: linearise -> second-layer
+condensation (in chunks of macros) -> FGMRES(30) to rtol 1e-8 with 5 inner
+GMRES steps -> local recovery -> update.  Extra keys: the mixed-precision
+path on the same workload, the 24^3 workload (3^3-element macros, 512) with
+its variants (whole stages), and the CPU oracle on a bounded sample.
 
 Prints one JSON line.  Per-phase times come from HIP events recorded on the
 library's stream around each C-ABI call; the global apply is also timed on
-its own over repeated calls (HBM roofline).  The CPU baseline runs the
-oracle (test infrastructure) on a bounded sample of the same workload.
+its own over repeated calls (HBM roofline).
 """
 import argparse
 import gc
@@ -26,13 +30,14 @@ sys.path.insert(0, ROOT)
 METRIC = "DIRK-stage solve time to FGMRES tol 1e-8 + condense TFLOP/s, plain vs mixed/learned"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per hdg_condense call of the FP64 path on this workload, from two
+# HBM bytes per hdg_condense call of the FP64 path, per workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by what the counters
-# read for a 1 GiB device copy in the same run (profiles/stage_solve_tgv24_m3_p2_fp64.md),
-# valid only while the kernel sources hash to `sha`.
-CONDENSE_TRAFFIC = {"sha": "e0ebc3daaf95b564", "bytes": 1161.2e9}
+# read for a 1 GiB device copy in the same run (profiles/), valid only while
+# the kernel sources hash to `sha`.
+CONDENSE_TRAFFIC = {"sha": "e0ebc3daaf95b564", "tgv24_m3_p2": 1161.2e9}
 CONDENSE_SOURCES = ("k_form.hip", "k_lu.hip")
 
 
@@ -390,15 +395,19 @@ def blas_threads():
     return len(os.sched_getaffinity(0))
 
 
-def cpu_baseline(cfg, newton_its, n_sample=2):
-    """Oracle leg: complex-step linearisation, route-B condensation and local
-    recovery of n_sample macros of the same workload, scaled to all macros and
-    to the Newton iterations the GPU took for one stage (the oracle's global
-    solve is not included, so this under-counts the CPU time)."""
+def cpu_baseline(cfg, gpu, n_sample=1, single_thread=False):
+    """Oracle leg on a bounded sample of the headline workload: route-B
+    condensation (LAPACK), the condensed apply and the local recovery of
+    n_sample macros, and the FGMRES vector work (two classical Gram-Schmidt
+    passes) on full-size trace vectors, scaled to one Newton step of the whole
+    mesh with the GPU's iteration counts.  The complex-step linearisation of
+    the sampled macros is timed on its own (not a fair baseline: it
+    differentiates the residual column group by column group).  Returns the
+    summary and the oracle's condensed blocks of the sampled macros."""
     from oracle.mesh import box_mesh
     from oracle.physics import Phys
     from oracle.system import System
-    from oracle import dirk
+    from oracle import dirk, krylov
     from paper_2402_11361_amd import inputs
     M = box_mesh(cfg["dim"], cfg["n_elem"], cfg["m"], cfg["p"], lo=cfg["lo"], hi=cfg["hi"], periodic=cfg["periodic"])
     S = System(M, Phys(Re=cfg["Re"], Mach=cfg["mach"]))
@@ -410,6 +419,7 @@ def cpu_baseline(cfg, newton_its, n_sample=2):
     dt = inputs.cfl_dt(cfg)
     w = -dii * u
     sample = list(range(n_sample))
+    S.geo(S.mclass[0])            # reference matrices of the class (set-up, not timed)
     t0 = time.perf_counter()
     lin = S.linearize(q, u, uh, w=w, dt=dt, dii=dii, macros=sample)
     t1 = time.perf_counter()
@@ -418,16 +428,244 @@ def cpu_baseline(cfg, newton_its, n_sample=2):
     x = np.random.default_rng(5).uniform(-1, 1, M.n_glob)
     S.backsolve(lin, con, x)
     t3 = time.perf_counter()
-    per_macro = (t3 - t0) / n_sample
-    scale = M.n_macros * max(newton_its, 1)
-    return dict(value=round(1e3 * per_macro * scale, 1),
-                unit="ms/DIRK-stage (local work only, extrapolated)",
-                cores=blas_threads(), kind="oracle",
-                sample=f"{n_sample} of {M.n_macros} macros, one Newton step: complex-step linearisation "
-                       f"{1e3 * (t1 - t0) / n_sample:.0f} ms/macro + LAPACK route-B condensation "
-                       f"{1e3 * (t2 - t1) / n_sample:.0f} ms/macro + recovery "
-                       f"{1e3 * (t3 - t2) / n_sample:.0f} ms/macro, scaled x{M.n_macros} macros "
-                       f"x{max(newton_its, 1)} Newton steps; oracle global solve excluded")
+    reps = 20
+    for _ in range(reps):
+        for i in sample:
+            con[i]["Ahat"] @ x[M.macro_trace_index(i)]
+    t4 = time.perf_counter()
+    # FGMRES vector work: CGS2 of one new vector against j + 1 basis vectors
+    # for j = 0 .. outer - 1 (the GPU's outer iterations), plus one face-block
+    # preconditioner solve per inner step is left out (small next to these)
+    n = M.n_glob
+    outer = max(gpu["outer_its"], 1)
+    jmax = min(outer, 30)
+    V = np.random.default_rng(6).standard_normal((jmax + 1, n))
+    wv = np.random.default_rng(7).standard_normal(n)
+    t5 = time.perf_counter()
+    for j in range(0, jmax, 5):
+        krylov._cgs2(V, wv, j)
+    t6 = time.perf_counter()
+    cgs_per_step = (t6 - t5) / len(range(0, jmax, 5))   # mean over the basis sizes of a cycle, sampled every 5
+    nm = M.n_macros
+    per_cond = (t2 - t1) / n_sample
+    per_back = (t3 - t2) / n_sample
+    per_apply = (t4 - t3) / (reps * n_sample)
+    applies = gpu["applies"]
+    ms = 1e3 * (per_cond * nm + per_back * nm + per_apply * nm * applies + cgs_per_step * outer)
+    out = dict(value=round(ms, 1), unit="ms/Newton-step (extrapolated from the sample; linearisation separate)",
+               cores=1 if single_thread else blas_threads(), kind="oracle",
+               sample=f"{n_sample} of {nm} macros of the headline workload, first Newton step of DIRK stage 1: "
+                      f"route-B condensation {1e3 * per_cond:.0f} ms/macro, recovery {1e3 * per_back:.1f} ms/macro, "
+                      f"condensed apply {1e3 * per_apply:.2f} ms/macro x {applies} applies, CGS2 on "
+                      f"{n}-vectors {1e3 * cgs_per_step:.0f} ms per outer step (x{outer}); scaled to {nm} macros",
+               phases_ms=dict(condense=round(1e3 * per_cond * nm, 1), backsolve=round(1e3 * per_back * nm, 1),
+                              apply=round(1e3 * per_apply * nm * applies, 1),
+                              krylov_vectors=round(1e3 * cgs_per_step * outer, 1)),
+               linearisation_not_a_fair_baseline=dict(
+                   ms_per_macro=round(1e3 * (t1 - t0) / n_sample, 1),
+                   ms_per_newton_step_extrapolated=round(1e3 * (t1 - t0) / n_sample * nm, 1),
+                   note="complex-step Jacobian of the residual, column group by column group"))
+    blocks = {i: (con[i]["Ahat"], con[i]["bhat"]) for i in sample}
+    return out, blocks
+
+
+def _rel_max(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+class NewtonBench:
+    """Times whole Newton steps (linearise -> condense -> FGMRES -> recovery ->
+    update) from one initial state on one context, with HIP events on the
+    library's stream around each phase."""
+
+    def __init__(self, ctx, stream, state, w, dt, dii, rtol):
+        import torch
+        self.t, self.ctx, self.stream = torch, ctx, stream
+        self.q0, self.u0, self.uh0 = state
+        self.w, self.dt, self.dii, self.rtol = w, dt, dii, rtol
+        dev = dict(dtype=torch.float64, device="cuda")
+        self.q, self.u, self.uh = self.q0.clone(), self.u0.clone(), self.uh0.clone()
+        self.bhat = torch.zeros(ctx.n_glob, **dev)
+        self.x = torch.zeros(ctx.n_glob, **dev)
+        self.dq = torch.zeros(ctx.n_q_tot, **dev)
+        self.du = torch.zeros(ctx.n_u_tot, **dev)
+
+    def ev(self):
+        e = self.t.cuda.Event(enable_timing=True)
+        e.record(self.stream)
+        return e
+
+    def step(self, marks, cond_prec, inner_prec, graph_steps=0, use_learned=False):
+        ctx = self.ctx
+        self.q.copy_(self.q0); self.u.copy_(self.u0); self.uh.copy_(self.uh0)
+        marks.append(("linearize", self.ev()))
+        ctx.linearize_stage(self.q, self.u, self.uh, self.w, self.dt, self.dii, norms=False)
+        marks.append(("condense", self.ev()))
+        ctx.condense(self.bhat, cond_prec)
+        marks.append(("fgmres", self.ev()))
+        self.x.zero_()
+        info = ctx.fgmres_solve(self.bhat, self.x, rtol=self.rtol, restart=30, max_outer=300, inner_its=5,
+                                inner_prec=inner_prec, graph_steps=graph_steps, use_learned=use_learned)
+        marks.append(("backsolve", self.ev()))
+        ctx.local_backsolve(self.x, self.dq, self.du)
+        marks.append(("update", self.ev()))
+        ctx.axpy(1.0, self.dq, self.q)
+        ctx.axpy(1.0, self.du, self.u)
+        ctx.axpy(1.0, self.x, self.uh)
+        marks.append(("end", self.ev()))
+        return info
+
+    def run(self, steps, warmup, cond_prec, inner_prec, graph_steps=0, use_learned=False, progress=None):
+        marks = []
+        for k in range(warmup):
+            self.step(marks, cond_prec, inner_prec, graph_steps, use_learned)
+            if progress:
+                progress(f"warm-up step {k + 1}/{warmup}")
+        self.t.cuda.synchronize()
+        marks.clear()
+        infos = []
+        t0 = time.perf_counter()
+        for k in range(steps):
+            infos.append(self.step(marks, cond_prec, inner_prec, graph_steps, use_learned))
+            if progress:
+                progress(f"timed step {k + 1}/{steps}")
+        self.t.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        phase_ms, cond_calls = {}, []
+        for (ph, e), (_, e2) in zip(marks[:-1], marks[1:]):
+            if ph == "end":
+                continue
+            dtm = e.elapsed_time(e2)
+            phase_ms[ph] = phase_ms.get(ph, 0.0) + dtm / steps
+            if ph == "condense":
+                cond_calls.append(dtm)
+        return dict(ms_per_step=1e3 * wall / steps, phase_ms=phase_ms, cond_calls=cond_calls,
+                    outer=[k["outer_its"] for k in infos], inner=[k["inner_its"] for k in infos],
+                    fallbacks=[k["fallbacks"] for k in infos])
+
+    def newton_reduction(self):
+        """||R_F|| before and after one step from the initial state (the state
+        the last step left)."""
+        import numpy as _np
+        r1 = self.ctx.linearize_stage(self.q, self.u, self.uh, self.w, self.dt, self.dii)
+        r0 = self.ctx.linearize_stage(self.q0, self.u0, self.uh0, self.w, self.dt, self.dii)
+        return float(_np.sqrt(_np.sum(r0 ** 2))), float(_np.sqrt(_np.sum(r1 ** 2)))
+
+
+def time_apply(ctx, stream, reps):
+    """Global apply on its own (HBM-bound GEMV over the condensed blocks)."""
+    import torch
+    xa = torch.randn(ctx.n_glob, dtype=torch.float64, device="cuda")
+    ya = torch.zeros_like(xa)
+    for _ in range(3):
+        ctx.apply_global(xa, ya)
+    torch.cuda.synchronize()
+    ea = torch.cuda.Event(enable_timing=True); ea.record(stream)
+    for _ in range(reps):
+        ctx.apply_global(xa, ya)
+    eb = torch.cuda.Event(enable_timing=True); eb.record(stream)
+    torch.cuda.synchronize()
+    return ea.elapsed_time(eb) / reps
+
+
+def apply_bytes(ctx, w):
+    """Algorithmic bytes of one global apply: the condensed blocks (w bytes per
+    entry), the gathered and partial local vectors and the output."""
+    nb = np.diff(np.asarray(ctx.b_off, dtype=np.float64))
+    return float(w * (nb * nb).sum() + 16.0 * nb.sum() + 8.0 * ctx.n_glob)
+
+
+def c2_variants(args, dev, variants, say):
+    """Whole DIRK-stage solves (Newton to max(1e-10, 1e-8 ||R^0||)) on the 24^3
+    workload: plain FP64, FP32 condensation with the BF16 inner operator and
+    graph-captured FGMRES steps, and the same with the learned coarse
+    correction (judged by the plain preconditioner)."""
+    import torch
+    from paper_2402_11361_amd import inputs
+    from paper_2402_11361_amd.driver import StageDriver, alexander_dirk33
+    from paper_2402_11361_amd.hdg import HDG_BF16, HDG_FP32, HDG_FP64, Context, mesh_spec_box
+    cfg = dict(inputs.CONFIGS["tgv24_m3_p2"])
+    spec = mesh_spec_box(3, cfg["n_elem"], cfg["m"], cfg["p"], cfg["lo"], cfg["hi"], True)
+    stream = torch.cuda.current_stream()
+    ctx = Context.from_mesh_spec(spec, Re=cfg["Re"], Mach=cfg["mach"], stream=stream.cuda_stream)
+    ctx.bind_workspace()
+    u0, q0, uh0 = workload_arrays(ctx, cfg)
+    q_i, u_i, uh_i = dev(q0), dev(u0), dev(uh0)
+    A, _, _ = alexander_dirk33()
+    dii = 1.0 / A[0, 0]
+    dt = inputs.cfl_dt(cfg)
+    w = -dii * u_i
+    q, u, uh = q_i.clone(), u_i.clone(), uh_i.clone()
+    ctx.linearize_stage(q_i, u_i, uh_i, w, dt, dii, norms=False)
+    tuning = {}
+    for name, prec in (("fp64", HDG_FP64), ("fp32", HDG_FP32)):
+        if args.set_tuning:
+            ctx.set_tuning(0, prec, *[int(v) for v in args.set_tuning.split(",")])
+        else:
+            ctx.autotune(prec, args.tune_cache)
+        tuning[name] = list(ctx.tuning(0, prec))
+    nm, nu, nb = ctx.n_macros, ctx.n_u_macro, ctx.n_b_macro
+    flops = condense_flops(cfg, nu, nb) * nm
+    out = dict(workload="tgv24_m3_p2: Taylor-Green 24^3 periodic hexes, 3^3-element macros (512), p=2, Mach 0.1, "
+                        "Re 1600, 1e-4 seeded noise; DIRK(3,3) stage 1 solved by Newton to max(1e-10, 1e-8 |R0|)",
+               n_macros=nm, n_u_macro=nu, n_b_macro=nb, n_glob=ctx.n_glob, condense_flops=flops, autotune=tuning)
+    ref = None
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    def stage_runs(name, cond_prec, inner_prec, graph_steps, use_learned=False):
+        marks = []
+        drv = StageDriver(ctx, rtol=cfg["rtol"], condense_prec=cond_prec, inner_prec=inner_prec,
+                          graph_steps=graph_steps, use_learned=use_learned,
+                          mark=lambda ph: marks.append((ph, ev())))
+        walls, info = [], None
+        for rep in range(1 + args.c2_stages):
+            q.copy_(q_i); u.copy_(u_i); uh.copy_(uh_i)
+            marks.clear()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = drv.solve_stage(q, u, uh, w, dt, dii)
+            torch.cuda.synchronize()
+            if rep > 0:
+                walls.append(time.perf_counter() - t0)
+        cond = [e.elapsed_time(e2) for (ph, e), (_, e2) in zip(marks[:-1], marks[1:]) if ph == "condense"]
+        cm = float(np.mean(cond))
+        peak = {HDG_FP64: PEAK_FP64_TFLOPS, HDG_FP32: PEAK_FP32_TFLOPS}.get(cond_prec, PEAK_BF16_TFLOPS)
+        say(f"c2 {name}: {1e3 * np.mean(walls):.1f} ms per stage")
+        return dict(ms_per_stage=round(1e3 * float(np.mean(walls)), 3), stages_timed=len(walls),
+                    newton_its=info["newton_its"], newton_res=info["res_hist"],
+                    fgmres_outer=[k["outer_its"] for k in info["krylov"]],
+                    fallbacks=[k["fallbacks"] for k in info["krylov"]],
+                    condense_ms=round(cm, 3), condense_tflops=round(flops / (cm * 1e-3) / 1e12, 3),
+                    condense_frac_peak=round(flops / (cm * 1e-3) / 1e12 / peak, 4))
+
+    plain = stage_runs("plain_fp64", HDG_FP64, HDG_FP64, 0)
+    u_ref, uh_ref = u.clone(), uh.clone()
+    out["plain_fp64"] = plain
+    out["plain_fp64"]["apply_ms"] = round(time_apply(ctx, stream, args.applies), 4)
+    for name, cp, ip, gs in (("mixed_fp32_condense_bf16_inner_graph", HDG_FP32, HDG_BF16, args.graph_steps),
+                             ("mixed_bf16_update_condense_bf16_inner_graph", HDG_BF16, HDG_BF16, args.graph_steps)):
+        r = stage_runs(name, cp, ip, gs)
+        r["speedup_vs_plain"] = round(plain["ms_per_stage"] / r["ms_per_stage"], 3)
+        r["stage_solution_rel_diff_vs_plain_fp64"] = dict(u=_rel_t(u, u_ref), uhat=_rel_t(uh, uh_ref))
+        out[name] = r
+    if not args.no_learned:
+        lrn = train_learned(ctx, cfg, dev, dii, dt, args)
+        r = stage_runs("mixed_fp32_condense_learned_graph", HDG_FP32, HDG_BF16, args.graph_steps, use_learned=True)
+        r["speedup_vs_plain"] = round(plain["ms_per_stage"] / r["ms_per_stage"], 3)
+        r["stage_solution_rel_diff_vs_plain_fp64"] = dict(u=_rel_t(u, u_ref), uhat=_rel_t(uh, uh_ref))
+        r["training"] = lrn
+        out["mixed_fp32_condense_learned_graph"] = r
+        ctx.learned_bind(None)
+    variants["tgv24_m3_p2_stages"] = out
+    ctx.close()
+
+
+def _rel_t(a, b):
+    return float((a - b).abs().max() / b.abs().max())
 
 
 def main():
@@ -435,21 +673,26 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="tgv24_m3_p2")
+    ap.add_argument("--config", default="tgv48_m4_p2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1, help="macros of the CPU oracle's sample")
+    ap.add_argument("--cpu-single-thread", action="store_true",
+                    help="also time the oracle's sample with one BLAS thread")
     ap.add_argument("--applies", type=int, default=20)
-    ap.add_argument("--plain-only", action="store_true", help="time only the plain FP64 variant")
+    ap.add_argument("--headline-only", action="store_true", help="time only the plain FP64 headline")
+    ap.add_argument("--mixed-steps", type=int, default=2, help="timed Newton steps of the mixed-precision variant")
+    ap.add_argument("--c2-stages", type=int, default=1, help="timed stages per 24^3 variant (0: skip them)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction variant")
-    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-macro 32^3 variant")
+    ap.add_argument("--uneven", action="store_true", help="also time the uneven-macro 32^3 variant")
     ap.add_argument("--graph-steps", type=int, default=10, help="FGMRES steps per captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default elimination launch shapes")
     ap.add_argument("--learned-p3", action="store_true",
                     help="also train and evaluate the learned correction on the 32^3 p=3 workload")
     ap.add_argument("--big-steps", type=int, default=0,
-                    help="also time this many DIRK(3,3) steps of the 48^3 workload (chunked condensation)")
+                    help="also time this many DIRK(3,3) steps of the 48^3 workload (chunked FP32 condensation)")
     ap.add_argument("--tune-cache", default=None, help="text file of earlier autotuner choices (read and appended)")
     ap.add_argument("--plain-prec", choices=("fp64", "fp32"), default="fp64",
-                    help="condensation precision of the main timed variant (profiling of the FP32 path)")
+                    help="condensation precision of the headline (profiling of the FP32 path)")
     ap.add_argument("--uneven-only", action="store_true",
                     help="time only the uneven-macro 32^3 variant (profiling); prints its JSON")
     ap.add_argument("--set-tuning", default=None, metavar="TPW,WIDE,LOOK",
@@ -469,13 +712,17 @@ def main():
         sys.exit(2)
     import torch
     from paper_2402_11361_amd import inputs
-    from paper_2402_11361_amd.driver import StageDriver, alexander_dirk33
-    from paper_2402_11361_amd.hdg import HDG_BF16, HDG_FP32, HDG_FP64, Context, mesh_spec_box
+    from paper_2402_11361_amd.driver import alexander_dirk33
+    from paper_2402_11361_amd.hdg import HDG_FP32, HDG_FP64, Context, mesh_spec_box
+    t_start = time.perf_counter()
 
+    def say(msg):
+        print(f"[bench {time.perf_counter() - t_start:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
     if args.uneven_only:
-        dev0 = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
         variants = {}
-        uneven_variant(args, dev0, variants)
+        uneven_variant(args, dev, variants)
         print(json.dumps(dict(metric=METRIC, unit="ms/DIRK-stage", n_gpus=1, data="synthetic", variants=variants)),
               flush=True)
         return
@@ -483,25 +730,23 @@ def main():
     spec = mesh_spec_box(cfg["dim"], cfg["n_elem"], cfg["m"], cfg["p"], cfg["lo"], cfg["hi"], cfg["periodic"])
     stream = torch.cuda.current_stream()
     ctx = Context.from_mesh_spec(spec, Re=cfg["Re"], Mach=cfg["mach"], stream=stream.cuda_stream)
+    free, _ = torch.cuda.mem_get_info()
+    per_chunk = ctx.fit_chunking(free - (8 << 30))
     ctx.bind_workspace()
+    say(f"{args.config}: {ctx.n_macros} macros, n_glob {ctx.n_glob}, workspace {ctx.workspace_bytes / 1e9:.1f} GB, "
+        f"{per_chunk or ctx.n_macros} macros per condensation chunk")
     u0, q0, uh0 = workload_arrays(ctx, cfg)
-    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
     q_init, u_init, uh_init = dev(q0), dev(u0), dev(uh0)
     A, _, _ = alexander_dirk33()
     dii = 1.0 / A[0, 0]
     dt = inputs.cfl_dt(cfg)
     w = -dii * u_init
-    q, u, uh = q_init.clone(), u_init.clone(), uh_init.clone()
-    rtol = cfg["rtol"]
+    main_prec = HDG_FP32 if args.plain_prec == "fp32" else HDG_FP64
 
-    def ev():
-        e = torch.cuda.Event(enable_timing=True)
-        e.record(stream)
-        return e
-
-    # elimination launch shapes per macro class from the autotuner, timed on
-    # the linearisation at the initial state (outside the timed region)
+    # elimination launch shapes from the autotuner, timed on the linearisation
+    # at the initial state (outside the timed region)
     tuning = {}
+    ctx.linearize_stage(q_init, u_init, uh_init, w, dt, dii, norms=False)
     if args.set_tuning:
         shape = [int(v) for v in args.set_tuning.split(",")]
         for prec in (HDG_FP64, HDG_FP32):
@@ -510,193 +755,128 @@ def main():
         tuning = dict(fixed=shape)
     elif not args.no_autotune:
         t0 = time.perf_counter()
-        ctx.linearize_stage(q_init, u_init, uh_init, w, dt, dii, norms=False)
-        for name, prec in (("fp64", HDG_FP64), ("fp32", HDG_FP32)):
+        precs = (("fp64", HDG_FP64),) if args.headline_only else (("fp64", HDG_FP64), ("fp32", HDG_FP32))
+        for name, prec in precs:
             ctx.autotune(prec, args.tune_cache)
             tuning[name] = [list(ctx.tuning(k, prec)) for k in range(ctx.class_count())]
         tuning["seconds"] = round(time.perf_counter() - t0, 2)
+        say(f"autotune {tuning}")
 
     # plain copy of 1 GiB: the reference for scaling HBM byte counters
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").uniform_()
     dst = torch.empty_like(src)
     dst.copy_(src)
-    c0 = ev(); dst.copy_(src); c1 = ev()
+    c0 = torch.cuda.Event(enable_timing=True); c0.record(stream)
+    dst.copy_(src)
+    c1 = torch.cuda.Event(enable_timing=True); c1.record(stream)
     torch.cuda.synchronize()
     copy_gbs = 2.0 * src.numel() * 8 / (c0.elapsed_time(c1) * 1e-3) / 1e9
     del src, dst
 
-    def run_variant(cond_prec, inner_prec, steps, warmup, use_learned=False, graph_steps=0, inner_its=5,
-                    max_outer=300):
-        """Warm-up stages, then `steps` timed stage solves from the same state."""
-        marks = []
-        drv = StageDriver(ctx, rtol=rtol, restart=30, inner_its=inner_its, max_outer=max_outer, condense_prec=cond_prec,
-                          inner_prec=inner_prec, mark=lambda phase: marks.append((phase, ev())),
-                          use_learned=use_learned, graph_steps=graph_steps)
-
-        def stage():
-            q.copy_(q_init); u.copy_(u_init); uh.copy_(uh_init)
-            return drv.solve_stage(q, u, uh, w, dt, dii)
-
-        for _ in range(warmup):
-            stage()
-        torch.cuda.synchronize()
-        marks.clear()
-        infos = []
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            infos.append(stage())
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        phase_ms, cond_calls = {}, []
-        for (ph, e), (_, e2) in zip(marks[:-1], marks[1:]):
-            if ph == "end":
-                continue
-            t = e.elapsed_time(e2)
-            phase_ms[ph] = phase_ms.get(ph, 0.0) + t / steps
-            if ph == "condense":
-                cond_calls.append(t)
-        return dict(ms_per_stage=1e3 * wall / steps, phase_ms=phase_ms, cond_calls=cond_calls,
-                    newton_its=infos[-1]["newton_its"], newton_res=infos[-1]["res_hist"],
-                    outer=[[k["outer_its"] for k in inf["krylov"]] for inf in infos],
-                    inner=[[k["inner_its"] for k in inf["krylov"]] for inf in infos],
-                    fallbacks=[[k.get("fallbacks", 0) for k in inf["krylov"]] for inf in infos],
-                    u=u.clone(), uh=uh.clone())
-
-    def time_apply():
-        """Global apply on its own (HBM-bound GEMV over the condensed blocks)."""
-        xa = torch.randn(ctx.n_glob, dtype=torch.float64, device="cuda")
-        ya = torch.zeros_like(xa)
-        for _ in range(3):
-            ctx.apply_global(xa, ya)
-        torch.cuda.synchronize()
-        ea = ev()
-        for _ in range(args.applies):
-            ctx.apply_global(xa, ya)
-        eb = ev()
-        torch.cuda.synchronize()
-        return ea.elapsed_time(eb) / args.applies
-
-    nb, nu, nm = ctx.n_b_macro, ctx.n_u_macro, ctx.n_macros
+    nb_ = NewtonBench(ctx, stream, (q_init, u_init, uh_init), w, dt, dii, cfg["rtol"])
+    nm, nu, nb = ctx.n_macros, ctx.n_u_macro, ctx.n_b_macro
     flops = condense_flops(cfg, nu, nb) * nm
-    main_prec = HDG_FP32 if args.plain_prec == "fp32" else HDG_FP64
-    plain = run_variant(main_prec, main_prec, args.steps, args.warmup)
-    apply_ms = time_apply()
-    ms_step = plain["ms_per_stage"]
-    phase_ms, cond_calls = plain["phase_ms"], plain["cond_calls"]
-    newton_its, outer, inner = plain["newton_its"], plain["outer"], plain["inner"]
+    plain = nb_.run(args.steps, args.warmup, main_prec, main_prec, progress=say)
+    r0, r1 = nb_.newton_reduction()
+    blocks_gpu = {0: ctx.get_condensed(0)}
+    apply_ms = time_apply(ctx, stream, args.applies)
+    say(f"headline: {plain['ms_per_step']:.1f} ms per Newton step, phases {plain['phase_ms']}")
     variants = {}
-    if not args.plain_only:
-        mixed = run_variant(HDG_FP32, HDG_FP64, args.steps, args.warmup)
+    if not args.headline_only and args.mixed_steps > 0:
+        mixed = nb_.run(args.mixed_steps, 1, HDG_FP32, HDG_FP32, graph_steps=args.graph_steps, progress=say)
+        mr0, mr1 = nb_.newton_reduction()
+        blocks32 = {0: ctx.get_condensed(0)}
+        apply32_ms = time_apply(ctx, stream, args.applies)
         cm = float(np.mean(mixed["cond_calls"]))
-        apply32_ms = time_apply()
-        du = float((mixed["u"] - plain["u"]).abs().max() / plain["u"].abs().max())
-        duh = float((mixed["uh"] - plain["uh"]).abs().max() / plain["uh"].abs().max())
-        variants["mixed_fp32_condense"] = dict(
-            ms_per_stage=round(mixed["ms_per_stage"], 3),
-            speedup_vs_plain=round(ms_step / mixed["ms_per_stage"], 3),
+        variants["mixed_fp32_condense_fp32_inner_graph"] = dict(
+            workload=args.config, ms_per_step=round(mixed["ms_per_step"], 3),
+            speedup_vs_plain=round(plain["ms_per_step"] / mixed["ms_per_step"], 3),
             phases_ms={k: round(v, 3) for k, v in mixed["phase_ms"].items()},
-            newton_its=mixed["newton_its"], newton_res=mixed["newton_res"],
-            fgmres=dict(outer_its=mixed["outer"], inner_its=mixed["inner"]),
+            fgmres=dict(outer_its=mixed["outer"], inner_its=mixed["inner"]), graph_steps=args.graph_steps,
+            newton_residual=dict(before=r0, after_step=mr1),
             condense_ms=round(cm, 3), condense_tflops=round(flops / (cm * 1e-3) / 1e12, 3),
             condense_frac_fp32_peak=round(flops / (cm * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
-            stage_solution_rel_diff_vs_plain=dict(u=du, uhat=duh),
             apply_ms=round(apply32_ms, 4),
-            apply_gbs=round((4.0 * nm * nb * nb + 16.0 * nm * nb + 8.0 * ctx.n_glob) / (apply32_ms * 1e-3) / 1e9, 1))
-        # *_inner_graph: the condensed operator for the outer FGMRES, its FP32
-        # or BF16 copy for the inner GMRES of the preconditioner
-        for name, cp, ip in (("plain_fp64_graph", HDG_FP64, HDG_FP64),
-                             ("mixed_fp32_condense_graph", HDG_FP32, HDG_FP64),
-                             ("fp64_condense_fp32_inner_graph", HDG_FP64, HDG_FP32),
-                             ("fp64_condense_bf16_inner_graph", HDG_FP64, HDG_BF16),
-                             ("mixed_fp32_condense_bf16_inner_graph", HDG_FP32, HDG_BF16)):
-            gv = run_variant(cp, ip, args.steps, args.warmup, graph_steps=args.graph_steps)
-            variants[name] = dict(
-                ms_per_stage=round(gv["ms_per_stage"], 3), speedup_vs_plain=round(ms_step / gv["ms_per_stage"], 3),
-                phases_ms={k: round(v, 3) for k, v in gv["phase_ms"].items()}, newton_its=gv["newton_its"],
-                fgmres=dict(outer_its=gv["outer"], inner_its=gv["inner"]), graph_steps=args.graph_steps,
-                stage_solution_rel_diff_vs_plain=dict(
-                    u=float((gv["u"] - plain["u"]).abs().max() / plain["u"].abs().max()),
-                    uhat=float((gv["uh"] - plain["uh"]).abs().max() / plain["uh"].abs().max())))
-        # single-level GMRES: the face-block inverse of A_uh,uh alone as the
-        # preconditioner (no inner GMRES), the comparison of the paper's Table 2
-        sl = run_variant(HDG_FP64, HDG_FP64, args.steps, args.warmup, inner_its=0, max_outer=5000,
-                         graph_steps=args.graph_steps)
-        variants["single_level_gmres_fp64_graph"] = dict(
-            ms_per_stage=round(sl["ms_per_stage"], 3), speedup_vs_plain=round(ms_step / sl["ms_per_stage"], 3),
-            phases_ms={k: round(v, 3) for k, v in sl["phase_ms"].items()}, newton_its=sl["newton_its"],
-            fgmres=dict(outer_its=sl["outer"], inner_its=sl["inner"]),
-            multi_level_outer_its=outer, multi_level_inner_its=inner,
-            stage_solution_rel_diff_vs_plain=dict(
-                u=float((sl["u"] - plain["u"]).abs().max() / plain["u"].abs().max()),
-                uhat=float((sl["uh"] - plain["uh"]).abs().max() / plain["uh"].abs().max())))
-        if not args.no_learned:
-            lrn = train_learned(ctx, cfg, dev, dii, dt, args)
-            ml = run_variant(HDG_FP32, HDG_FP64, args.steps, args.warmup, use_learned=True)
-            variants["mixed_fp32_condense_learned"] = dict(
-                ms_per_stage=round(ml["ms_per_stage"], 3),
-                speedup_vs_plain=round(ms_step / ml["ms_per_stage"], 3),
-                phases_ms={k: round(v, 3) for k, v in ml["phase_ms"].items()},
-                newton_its=ml["newton_its"], newton_res=ml["newton_res"],
-                fgmres=dict(outer_its=ml["outer"], inner_its=ml["inner"], fallbacks=ml["fallbacks"]),
-                stage_solution_rel_diff_vs_plain=dict(
-                    u=float((ml["u"] - plain["u"]).abs().max() / plain["u"].abs().max()),
-                    uhat=float((ml["uh"] - plain["uh"]).abs().max() / plain["uh"].abs().max())),
-                training=lrn)
-            ctx.learned_bind(None)
-    apply_bytes = 8.0 * nm * nb * nb + 8.0 * nm * nb + 8.0 * nm * nb + 8.0 * ctx.n_glob
-    apply_gbs = apply_bytes / (apply_ms * 1e-3) / 1e9
+            apply_gbs=round(apply_bytes(ctx, 4.0) / (apply32_ms * 1e-3) / 1e9, 1))
+        say(f"mixed: {mixed['ms_per_step']:.1f} ms per Newton step")
+    bytes64, n_glob = apply_bytes(ctx, 8.0), ctx.n_glob
+    ctx.close()
+    del nb_
+    gc.collect()
+    torch.cuda.empty_cache()
+
+    apply_gbs = bytes64 / (apply_ms * 1e-3) / 1e9
+    cond_calls = plain["cond_calls"]
     cond_ms = float(np.mean(cond_calls))
     cond_tflops = flops / (cond_ms * 1e-3) / 1e12
-    # dominant work: hdg_condense, one launch sequence per Newton step (MFMA-bound)
-    traffic = CONDENSE_TRAFFIC["bytes"] if sources_sha() == CONDENSE_TRAFFIC["sha"] else None
+    traffic = CONDENSE_TRAFFIC.get(args.config) if sources_sha() == CONDENSE_TRAFFIC["sha"] else None
     peak = PEAK_FP64_TFLOPS if main_prec == HDG_FP64 else PEAK_FP32_TFLOPS
     if main_prec != HDG_FP64:
         traffic = None
     roofline = dict(bound="mfma", achieved=round(cond_tflops, 3), peak=peak, unit="TFLOP/s",
                     frac=round(cond_tflops / peak, 4), traffic=traffic,
-                    kernel="hdg_condense: k_form + batched FP64 elimination (k_panel, k_uinv, k_u12, k_linv2, "
-                           "k_u12lin, k_gemm) + face-preconditioner factorisation",
+                    kernel="hdg_condense (chunked): k_form + batched elimination (k_panel, k_uinv, k_u12, k_linv2, "
+                           "k_u12lin, k_gemm on FP64 MFMA) + k_extract + face-preconditioner factorisation",
                     flops_per_launch=flops, ms_per_launch=round(cond_ms, 3), launches=len(cond_calls))
-    out = dict(metric=METRIC, value=round(ms_step, 3), unit="ms/DIRK-stage", n_gpus=1, steps=args.steps,
+    ms_step = plain["ms_per_step"]
+    out = dict(metric=METRIC, value=round(ms_step, 3), unit="ms/Newton-step", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_step, 3), higher_is_better=False, scaling="weak",
                vs_baseline=None, dtype="f64" if main_prec == HDG_FP64 else "f32", data="synthetic",
-               config=dict(workload=f"{args.config}: Taylor-Green 24^3 periodic hexes on [-pi,pi]^3, 3^3-element "
-                                    f"macros (512), p=2, Mach 0.1, Re 1600, 1e-4 seeded noise; DIRK(3,3) stage 1 "
-                                    f"solved by Newton to max(1e-10, 1e-8 |R0|), FGMRES(30) rtol {rtol} with "
-                                    f"5 inner GMRES steps",
-                           n_macros=nm, n_u_macro=nu, n_b_macro=nb, n_glob=ctx.n_glob,
+               config=dict(workload=f"{args.config}: Taylor-Green {cfg['n_elem']}^3 periodic hexes on [-pi,pi]^3, "
+                                    f"{cfg['m']}^3-element macros ({nm}), p={cfg['p']}, Mach 0.1, Re 1600, 1e-4 "
+                                    f"seeded noise; one Newton step of DIRK(3,3) stage 1 from the initial state: "
+                                    f"linearise, second-layer condensation in {(nm + (per_chunk or nm) - 1) // (per_chunk or nm)} "
+                                    f"chunks, FGMRES(30) rtol {cfg['rtol']} with 5 inner GMRES steps, recovery, update",
+                           n_macros=nm, n_u_macro=nu, n_b_macro=nb, n_glob=n_glob,
+                           macros_per_chunk=per_chunk,
                            variant="plain FP64" if main_prec == HDG_FP64 else "FP32 condensation"),
-               phases_ms={k: round(v, 3) for k, v in phase_ms.items()},
-               newton_its=newton_its, newton_res=plain["newton_res"],
-               fgmres=dict(outer_its=outer, inner_its=inner),
+               phases_ms={k: round(v, 3) for k, v in plain["phase_ms"].items()},
+               fgmres=dict(outer_its=plain["outer"], inner_its=plain["inner"]),
+               newton_residual=dict(before=r0, after_step=r1),
                condense_tflops=round(cond_tflops, 3), condense_ms=round(cond_ms, 3),
                apply_ms=round(apply_ms, 4), apply_gbs=round(apply_gbs, 1),
                apply_frac_hbm=round(apply_gbs / PEAK_HBM_GBS, 4), copy_gbs=round(copy_gbs, 1),
                roofline=roofline, variants=variants, autotune=tuning)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, newton_its)
-    # the other workloads need the device memory of the 24^3 workspace
-    ctx.close()
-
-    def free_device_memory():
+        say("cpu baseline")
+        gpu_counts = dict(outer_its=int(np.mean(plain["outer"])),
+                          applies=int(np.mean(plain["outer"])) + int(np.mean(plain["inner"])) + 2)
+        cb, oblocks = cpu_baseline(cfg, gpu_counts, n_sample=args.cpu_sample)
+        if args.cpu_single_thread:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(1):
+                cb1, _ = cpu_baseline(cfg, gpu_counts, n_sample=args.cpu_sample, single_thread=True)
+            cb["single_thread"] = dict(value=cb1["value"], phases_ms=cb1["phases_ms"], sample=cb1["sample"])
+        out["cpu_baseline"] = cb
+        # error against the FP64 oracle on the sampled macros' condensed blocks
+        err = {}
+        for i, (Ao, bo) in oblocks.items():
+            Ag, bg = blocks_gpu[i]
+            err[f"macro_{i}"] = dict(plain_fp64=dict(ahat=_rel_max(Ag, Ao), bhat=_rel_max(bg, bo)))
+            if "mixed_fp32_condense_fp32_inner_graph" in variants:
+                A3, b3 = blocks32[i]
+                err[f"macro_{i}"]["mixed_fp32"] = dict(ahat=_rel_max(A3, Ao), bhat=_rel_max(b3, bo))
+        out["error_vs_fp64_oracle"] = err
+        say(f"cpu baseline {cb['value']} ms; block errors {err}")
+    if not args.headline_only and args.c2_stages > 0:
+        c2_variants(args, dev, variants, say)
         gc.collect()
         torch.cuda.empty_cache()
-
-    free_device_memory()
-    if not args.plain_only and not args.no_uneven:
+    if args.uneven:
         uneven_variant(args, dev, variants)
-        free_device_memory()
+        gc.collect(); torch.cuda.empty_cache()
     if args.learned_p3:
         learned_p3_variant(args, dev, variants)
-        free_device_memory()
+        gc.collect(); torch.cuda.empty_cache()
     if args.first_layer:
         first_layer_variant(args, dev, variants)
-        free_device_memory()
+        gc.collect(); torch.cuda.empty_cache()
     if args.tgv_eps > 0:
         tgv_dissipation_variant(args, dev, variants)
-        free_device_memory()
+        gc.collect(); torch.cuda.empty_cache()
     if args.big_steps > 0:
         big_variant(args, dev, variants)
+    say("done")
     print(json.dumps(out), flush=True)
 
 

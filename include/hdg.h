@@ -103,8 +103,7 @@ typedef struct {
  * condensed operator, so the solution is unaffected (FGMRES admits a
  * preconditioner that differs from the operator), only iteration counts
  * change.  With chunked condensation: HDG_FP32 needs an FP32 condensation
- * and HDG_BF16 is HDG_EUNSUPPORTED.  hdg_condense accepts HDG_FP64 and
- * HDG_FP32 only. */
+ * and HDG_BF16 is HDG_EUNSUPPORTED. */
 typedef struct {
   double rtol, atol;
   int restart, max_outer, inner_its;
@@ -179,8 +178,8 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes);
  * eliminates consecutive ranges of that many macros through one buffer and
  * keeps only the condensed blocks A-hat^{T_i} (compact, in the condensation
  * precision) and b-hat^{T_i}; hdg_local_backsolve forms and factors each
- * range's S again (the S rows only: LU and L^{-1} P (-C), no trace-row
- * update).  0 (default) or >= n_macros: everything at once.
+ * range's S again (the S rows only, with the right-hand side f + C duhat of
+ * eq. Csc4a folded into one column: the LU of S carries that column alone).  0 (default) or >= n_macros: everything at once.
  * Re-plans the workspace: call hdg_query_sizes and hdg_bind_workspace again
  * afterwards (any bound workspace and learned network are released).
  * With chunking, an FP32 inner operator (hdg_krylov_opts.inner_prec) needs
@@ -243,11 +242,18 @@ hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, co
  * prec = HDG_FP32: the augmented matrices are formed with FP32 sums (g of
  *   eq. ASC2b in FP64, kept outside the matrix) and stored in FP32 and
  *   eliminated with FP32 arithmetic (FP32 MFMA); the
- *   condensed blocks, b-hat, the operator of hdg_apply_global and the factors
- *   used by hdg_local_backsolve then carry FP32 rounding (vectors, sums and
- *   the recovery stay FP64).  A Newton iteration whose residuals are
+ *   condensed blocks, b-hat and the operator of hdg_apply_global then carry
+ *   FP32 rounding (vectors and sums stay FP64; hdg_local_backsolve refines
+ *   its S-solves to FP64).  A Newton iteration whose residuals are
  *   evaluated in FP64 (hdg_linearize_stage) refines the result back to the
  *   FP64 level.  The precision stays in effect until the next hdg_condense.
+ * prec = HDG_BF16: as HDG_FP32 (FP32 storage, formation and panel
+ *   factorisations) but the trailing updates of the elimination (the Schur
+ *   products L21 U12, which carry nearly all the flops) take BF16 operands
+ *   (rounded to nearest even) with FP32 accumulation on the BF16 MFMA units:
+ *   the condensed blocks carry errors of about 1e-3 to 1e-2 relative, which
+ *   the Newton iteration refines at a correspondingly slower rate; the
+ *   recovery's FP64 refinement takes more sweeps.
  * The face blocks of the preconditioner are always FP64.
  * Returns HDG_ESINGULAR (message names the macro) on a zero pivot. */
 hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat);
@@ -307,7 +313,13 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
                             hdg_krylov_stats* stats_host);
 
 /* Local recovery (eq. Csc4a then Csc4b): dU and dQ of every macro from the
- * trace increment duhat (device, n_glob).  dq, du device, layouts of q, u. */
+ * trace increment duhat (device, n_glob).  dq, du device, layouts of q, u.
+ * After an FP32 condensation the S-solve is refined in FP64: two sweeps of
+ * dU += S_32^{-1} r with r = -(R_U + A_uq dQ + A_uu dU + A_u,uh duhat), the
+ * FP64 residual of the u-rows of the Newton system (eq. C312) from the
+ * linearisation's blocks, so dU and dQ are FP64-accurate.  The residual uses
+ * the Krylov vectors of the workspace as scratch (HDG_EDEVICE if n_u_tot
+ * exceeds them). */
 hdg_status hdg_local_backsolve(hdg_ctx ctx, const double* duhat, double* dq, double* du);
 
 /* y += a x on n doubles (device): the Newton update. */

@@ -634,8 +634,12 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
   if (!ctx || !bhat) return HDG_EINVAL;
   HdgContext& c = ctx->c;
   if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
-  if (prec != HDG_FP64 && prec != HDG_FP32) return fail(&c, HDG_EUNSUPPORTED, "condensation precision not built");
-  const int p32 = (prec == HDG_FP32) ? 1 : 0;
+  if (prec != HDG_FP64 && prec != HDG_FP32 && prec != HDG_BF16)
+    return fail(&c, HDG_EINVAL, "unknown condensation precision");
+  // HDG_BF16: FP32 storage, formation and panels; the trailing updates take
+  // BF16 operands with FP32 accumulation
+  const int p32 = (prec == HDG_FP32 || prec == HDG_BF16) ? 1 : 0;
+  c.bf16_update = (prec == HDG_BF16);
   // status flags: one per (chunk, macro class), then one for the face blocks
   const int ncl = c.hm.n_classes, nch = c.hm.n_chunks(), nst = nch * ncl;
   int* status = reinterpret_cast<int*>(c.ws.small);

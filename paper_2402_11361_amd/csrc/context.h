@@ -122,6 +122,7 @@ struct HdgContext {
   bool have_a16 = false;
   bool linearized = false;  // element blocks hold a linearisation
   int cond_prec = 0;
+  bool bf16_update = false;  // the last condensation took BF16 operands in its trailing updates
   long long supg_chunk = 0;  // elements per SUPG product batch
   // learned coarse correction
   bool lrn_bound = false;

@@ -735,7 +735,7 @@ void upload_tables(HdgContext& c) {
   md.macro_class = up(c, hm.macro_class);
   md.u_off = up(c, hm.u_off); md.b_off = up(c, hm.b_off); md.el_off = up(c, hm.el_off);
   md.elem_macro = up(c, hm.elem_macro); md.sub_off = up(c, hm.sub_off); md.row_off = up(c, hm.row_off);
-  md.w_off = up(c, hm.w_off); md.a32_off = up(c, hm.a32_off);
+  md.w_off = up(c, hm.w_off); md.a32_off = up(c, hm.a32_off); md.ipiv_off = up(c, hm.ipiv_off);
   md.face_slot = up(c, hm.face_slot);
 }
 

@@ -95,6 +95,7 @@ struct MeshDev {
   const long long* sub_off;    // [n_macros + 1] first global sub-face
   const long long* row_off;    // [n_macros + 1] first row of the macro in the list of all augmented rows
   const long long* w_off;      // [n_macros] offset (elements) of the macro's tiled matrix, grouped by class
+  const long long* ipiv_off;   // [n_macros] offset of the macro's pivot rows in the pivot array
   const long long* a32_off;    // [n_macros + 1] offset of the macro's compact FP32 copy of A-hat
   const int* face_slot;        // [n_faces] slot of the face's preconditioner block (grouped by size)
 };
@@ -131,6 +132,7 @@ struct LuTune {
   int tpw = 32;
   int panel_wide = 0;
   int lookahead = 0;
+  int bf16_update = 0;  // FP32 storage: trailing update with BF16 operands, FP32 accumulation
 };
 
 // ---- kernel launchers (defined in the .hip files) ----------------------
@@ -142,8 +144,12 @@ hipError_t launch_linearize(HdgContext& c, const double* q, const double* u, con
 // prec: 0 FP64, 1 FP32 element type of the augmented matrices
 // formation and elimination of the macros [m0, m1) = chunk j (rows of the
 // trace block skipped in the elimination when top_only)
-hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class = -1);
-hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only_class = -1);
+// rhs_duhat non-null: recovery form (S rows with f + C duhat in column n_u)
+hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class = -1,
+                       const double* rhs_duhat = nullptr);
+// top_only: eliminate the S rows only; rhs_only (with top_only): the columns
+// [0, n_u] only (the recovery form's right-hand side in column n_u)
+hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only_class = -1, bool rhs_only = false);
 // chunked condensation: A-hat^{T_i} and b-hat^{T_i} of chunk j out of W
 hipError_t launch_extract(HdgContext& c, int prec, int chunk);
 hipError_t launch_bhat(HdgContext& c, double* bhat, int prec);

@@ -4,6 +4,17 @@
 //     dU = S^{-1} (f + C duhat) = U^{-1} (w - U12 duhat_i)          (Csc4a)
 //     dQ_k = A_qq^{-1}(-R_Q - A_qu dU - A_q,uh duhat)_k
 //          = -M^{-1} R_Q,k - C_k dU + sum_s sign_s M_k^{-1}[:, end_s] (x) duhat_(k,s)   (Csc4b)
+//
+// After an FP32 condensation the factors carry FP32 rounding; the recovery
+// then refines dU in FP64 (iterative refinement of the S-solve): with dQ from
+// Csc4b, the u-rows of the Newton system (eq. C312) give the FP64 residual
+//     r = -(R_U + A_uq dQ + A_uu dU + A_u,uh duhat) = f + C duhat - S dU
+// from the FP64 element and sub-face blocks of the linearisation, and
+// dU += U^{-1} L^{-1} P r with the FP32 factors, a fixed number of sweeps.
+// The elimination stores L column pair by column pair (128 columns), each
+// pair's columns in the row order reached at the end of that pair, so
+// L^{-1} P is applied pair by pair: the pair's row swaps, then its unit-lower
+// columns.
 #include "context.h"
 #include <algorithm>
 
@@ -51,6 +62,17 @@ __global__ void __launch_bounds__(256) k_bs_rhs(MeshDev md, int m0, const T* __r
   }
 }
 
+// z = column n_u of the S rows: L^{-1} P (f + C duhat) after the elimination
+// of the recovery form (the right-hand side folded into that column).
+template <class T>
+__global__ void __launch_bounds__(256) k_bs_col(MeshDev md, int m0, const T* __restrict__ Wm, double* __restrict__ z) {
+  const int macro = m0 + blockIdx.y;
+  const ClassDev& cd = class_of(md, macro);
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= cd.n_u) return;
+  z[md.u_off[macro] + r] = (double)Wm[md.w_off[macro] + wtix(r, cd.n_u, cd.ldw)];
+}
+
 // Backward substitution U du = z in place (z -> du), one workgroup per macro,
 // blocks of 64 rows from the bottom.
 template <class T>
@@ -94,11 +116,11 @@ __global__ void __launch_bounds__(256) k_bs_trsv(MeshDev md, int m0, const T* __
   }
 }
 
-// dQ for one (macro, direction k, component c) field.
-__global__ void k_bs_dq(MeshDev md, const double* __restrict__ RQt, const double* __restrict__ du,
+// dQ for one (macro, direction k, component c) field, macros from m0.
+__global__ void k_bs_dq(MeshDev md, int m0, const double* __restrict__ RQt, const double* __restrict__ du,
                         const double* __restrict__ duhat, double* __restrict__ dq) {
   const int ns = md.ns, d = md.dim;
-  const int macro = blockIdx.x / (d * ns), f = blockIdx.x % (d * ns);
+  const int macro = m0 + blockIdx.x / (d * ns), f = blockIdx.x % (d * ns);
   const ClassDev& cd = class_of(md, macro);
   const int N = cd.N, nm = cd.nmax1;
   const int k = f / ns, c = f % ns;
@@ -132,44 +154,198 @@ __global__ void k_bs_dq(MeshDev md, const double* __restrict__ RQt, const double
   }
 }
 
+struct ResidPtrs {
+  const double *AUU, *AUQ, *SUB, *RU;
+  int nsA, dnsA, sub_stride, off_AUB;
+};
+
+// r = -(R_U + A_uq dQ + A_uu dU + A_u,uh duhat) on the u-nodes of macro
+// m0 + blockIdx.y: one wave per macro node (its n_s component rows), the
+// elements through the node in their fixed order (deterministic sums).
+__global__ void __launch_bounds__(256) k_bs_resid(MeshDev md, int m0, ResidPtrs rp, const double* __restrict__ du,
+                                                  const double* __restrict__ dq, const double* __restrict__ duhat,
+                                                  double* __restrict__ r) {
+  const int macro = m0 + blockIdx.y;
+  const ClassDev& cd = class_of(md, macro);
+  const int lane = threadIdx.x & 63;
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (a >= cd.N) return;  // whole waves only; no barrier below
+  const int ns = cd.ns, d = cd.dim, A = cd.A, T = cd.T, N = cd.N;
+  const int nsA = rp.nsA, dnsA = rp.dnsA, nst = ns * T;
+  const long long uo = md.u_off[macro];
+  const double* dU = du + uo;
+  const double* dQ = dq + (size_t)d * uo;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int ie = 0; ie < cd.node_ne[a]; ++ie) {
+    const int e = cd.node_e[a * 8 + ie], ae = cd.node_a[a * 8 + ie];
+    const long long el = md.el_off[macro] + e;
+    const int* en = cd.elem_nodes + (size_t)e * A;
+    for (int c = 0; c < ns; ++c) {
+      const double* auu = rp.AUU + ((size_t)el * nsA + (size_t)(c * A + ae)) * nsA;
+      const double* auq = rp.AUQ + ((size_t)el * nsA + (size_t)(c * A + ae)) * dnsA;
+      double s = 0.0;
+      for (int i = lane; i < nsA; i += 64) s += auu[i] * dU[(size_t)(i / A) * N + en[i % A]];
+      for (int i = lane; i < dnsA; i += 64) s += auq[i] * dQ[(size_t)(i / A) * N + en[i % A]];
+      acc[c] += s;
+    }
+    for (int lf2 = 0; lf2 < 2 * d; ++lf2) {
+      const int sid = cd.elem_sub[(size_t)e * 2 * d + lf2];
+      if (sid < 0) continue;
+      const int ta = cd.finv[(size_t)lf2 * A + ae];
+      if (ta < 0) continue;
+      const int F = md.macro_face[(size_t)macro * 2 * d + lf2];
+      const int nf2 = cd.nf_nodes[lf2];
+      const double* xh = duhat + md.face_off[F];
+      const double* aub = rp.SUB + ((size_t)md.sub_off[macro] + sid) * rp.sub_stride + rp.off_AUB;
+      const int* tid = cd.sub_tid + (size_t)sid * T;
+      for (int c = 0; c < ns; ++c) {
+        double s = 0.0;
+        for (int i = lane; i < nst; i += 64) s += aub[(size_t)(c * T + ta) * nst + i] * xh[(i / T) * nf2 + tid[i % T]];
+        acc[c] += s;
+      }
+    }
+  }
+  for (int c = 0; c < ns; ++c) {
+    const double v = wave_sum(acc[c]);
+    if (lane == 0) r[uo + (size_t)c * N + a] = -(rp.RU[uo + (size_t)c * N + a] + v);
+  }
+}
+
+// r <- L^{-1} P r for macro m0 + blockIdx.x with the factors of its S rows in
+// W (storage type T): per column pair, its row swaps (ipiv, in column order)
+// then its unit-lower columns in 64-column blocks; r staged in LDS (n_u doubles).
+template <class T>
+__global__ void __launch_bounds__(256) k_bs_fwd(MeshDev md, int m0, const T* __restrict__ Wm,
+                                                const int* __restrict__ ipiv_all, double* __restrict__ r) {
+  extern __shared__ double rs[];
+  __shared__ double sL[BS_ROWS][BS_ROWS + 1];
+  const int macro = m0 + blockIdx.x;
+  const ClassDev& cd = class_of(md, macro);
+  const int nu = cd.n_u, ld = cd.ldw;
+  const T* W = Wm + md.w_off[macro];
+  const int* ipiv = ipiv_all + md.ipiv_off[macro];
+  double* x = r + md.u_off[macro];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < nu; i += blockDim.x) rs[i] = x[i];
+  __syncthreads();
+  for (int j0 = 0; j0 < nu; j0 += 2 * BS_ROWS) {
+    const int jend = min(nu, j0 + 2 * BS_ROWS);
+    if (tid == 0)
+      for (int col = j0; col < jend; ++col) {
+        const int p = ipiv[col];
+        if (p != col) { const double t = rs[col]; rs[col] = rs[p]; rs[p] = t; }
+      }
+    __syncthreads();
+    for (int b0 = j0; b0 < jend; b0 += BS_ROWS) {
+      const int nb = min(BS_ROWS, jend - b0);
+      for (int i = tid; i < nb * nb; i += blockDim.x) {
+        const int rr = i / nb, cc = i % nb;
+        sL[rr][cc] = (double)W[wtix(b0 + rr, b0 + cc, ld)];
+      }
+      __syncthreads();
+      if (wave == 0) {
+        double xv = (lane < nb) ? rs[b0 + lane] : 0.0;
+        for (int cc = 0; cc < nb; ++cc) {
+          const double xc = __shfl(xv, cc, 64);
+          if (lane > cc && lane < nb) xv -= sL[lane][cc] * xc;
+        }
+        if (lane < nb) rs[b0 + lane] = xv;
+      }
+      __syncthreads();
+      const double xb = (lane < nb) ? rs[b0 + lane] : 0.0;
+      for (int i = b0 + nb + wave; i < nu; i += 4) {
+        double sv = (lane < nb) ? (double)W[wtix(i, b0 + lane, ld)] * xb : 0.0;
+        sv = wave_sum(sv);
+        if (lane == 0) rs[i] -= sv;
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < nu; i += blockDim.x) x[i] = rs[i];
+}
+
+__global__ void k_add_range(long long n, const double* __restrict__ x, double* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] += x[i];
+}
+
 }  // namespace
 
+// FP64 refinement sweeps of the recovery after an FP32 condensation (each
+// gains about the relative accuracy of the factors: ~1e-5 for FP32, ~1e-2
+// after trailing updates with BF16 operands).
+constexpr int BS_REFINE_SWEEPS = 2;
+constexpr int BS_REFINE_SWEEPS_BF16 = 8;
+
 // Macros [m0, m1) from their eliminated matrices in W.
-static hipError_t backsolve_range(HdgContext& c, const double* duhat, double* du, int m0, int m1, int nu, int nb) {
+// rhs_in_w: W holds the eliminated recovery form (right-hand side in column
+// n_u) instead of the condensation's [U | U12 | w].
+static hipError_t backsolve_range(HdgContext& c, const double* duhat, double* dq, double* du, int m0, int m1, int nu,
+                                  int nb, bool rhs_in_w) {
   const int nm = m1 - m0;
   if (nm <= 0) return hipSuccess;
   const dim3 grid_rhs((nu + BS_ROWS - 1) / BS_ROWS, nm);
+  const dim3 grid_col((nu + 255) / 256, nm);
   if (c.cond_prec == 1) {
     const float* W32 = reinterpret_cast<const float*>(c.ws.Wm);
-    hipLaunchKernelGGL(k_bs_rhs<float>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, m0, W32,
-                       duhat, du);
+    if (rhs_in_w)
+      hipLaunchKernelGGL(k_bs_col<float>, grid_col, dim3(256), 0, c.stream, c.md, m0, W32, du);
+    else
+      hipLaunchKernelGGL(k_bs_rhs<float>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, m0, W32,
+                         duhat, du);
     hipLaunchKernelGGL(k_bs_trsv<float>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, W32, du);
+    // FP64 refinement: the Krylov vectors are free during the recovery and
+    // hold the residual (n_u_tot doubles)
+    double* r = c.ws.kry;
+    int nmax = 0;
+    for (const HostClass& k : c.hcs) nmax = std::max(nmax, k.N);
+    const ResidPtrs rp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.nsA, c.dnsA, c.sub_stride, c.off_AUB};
+    const long long u0 = c.hm.u_off[m0], nr = c.hm.u_off[m1] - u0;
+    const int sweeps = (c.bf16_update && !rhs_in_w) ? BS_REFINE_SWEEPS_BF16 : BS_REFINE_SWEEPS;
+    for (int sweep = 0; sweep < sweeps; ++sweep) {
+      hipLaunchKernelGGL(k_bs_dq, dim3(nm * c.cd.dim * c.cd.ns), dim3(256), 0, c.stream, c.md, m0, c.ws.RQt, du, duhat,
+                         dq);
+      hipLaunchKernelGGL(k_bs_resid, dim3((nmax + 3) / 4, nm), dim3(256), 0, c.stream, c.md, m0, rp, du, dq, duhat, r);
+      hipLaunchKernelGGL(k_bs_fwd<float>, dim3(nm), dim3(256), (size_t)nu * sizeof(double), c.stream, c.md, m0, W32,
+                         c.ws.ipiv, r);
+      hipLaunchKernelGGL(k_bs_trsv<float>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, W32, r);
+      const int nblk = (int)std::min<long long>((nr + 255) / 256, 65536);
+      hipLaunchKernelGGL(k_add_range, dim3(nblk), dim3(256), 0, c.stream, nr, r + u0, du + u0);
+    }
   } else {
-    hipLaunchKernelGGL(k_bs_rhs<double>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, m0, c.ws.Wm,
-                       duhat, du);
+    if (rhs_in_w)
+      hipLaunchKernelGGL(k_bs_col<double>, grid_col, dim3(256), 0, c.stream, c.md, m0, c.ws.Wm, du);
+    else
+      hipLaunchKernelGGL(k_bs_rhs<double>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, m0,
+                         c.ws.Wm, duhat, du);
     hipLaunchKernelGGL(k_bs_trsv<double>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, c.ws.Wm, du);
   }
   return hipGetLastError();
 }
 
-// Unchunked: W still holds every macro's elimination.  Chunked: each chunk
-// is formed and its S rows eliminated again (the trace rows are not needed),
-// in the precision of the last condensation, then recovered.
+// Unchunked: W still holds every macro's elimination.  Chunked: each chunk's
+// S rows are formed again with the right-hand side f + C duhat folded into
+// column n_u (the trace rows and the C columns are not needed) and
+// eliminated, in the precision of the last condensation, then recovered.
 hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, double* du) {
   int nu = 0, nb = 0;
   for (const HostClass& k : c.hcs) { nu = std::max(nu, k.n_u); nb = std::max(nb, k.n_b); }
   const int nm = c.hm.n_macros;
   hipError_t e;
+  // the refinement's residual lives in the Krylov vectors
+  if (c.cond_prec == 1 &&
+      c.n_u_tot > (long long)(2 * c.kry_restart_max + c.kry_inner_max + 8) * c.hm.n_glob)
+    return hipErrorInvalidValue;
   if (!c.hm.chunked()) {
-    if ((e = backsolve_range(c, duhat, du, 0, nm, nu, nb)) != hipSuccess) return e;
+    if ((e = backsolve_range(c, duhat, dq, du, 0, nm, nu, nb, false)) != hipSuccess) return e;
   } else {
     for (int j = 0; j < c.hm.n_chunks(); ++j) {
       const int m0 = c.hm.chunk_first[j], m1 = c.hm.chunk_first[j + 1];
-      if ((e = launch_form(c, c.cond_prec, m0, m1)) != hipSuccess) return e;
-      if ((e = launch_lu(c, c.cond_prec, j, true)) != hipSuccess) return e;
-      if ((e = backsolve_range(c, duhat, du, m0, m1, nu, nb)) != hipSuccess) return e;
+      if ((e = launch_form(c, c.cond_prec, m0, m1, -1, duhat)) != hipSuccess) return e;
+      if ((e = launch_lu(c, c.cond_prec, j, true, -1, true)) != hipSuccess) return e;
+      if ((e = backsolve_range(c, duhat, dq, du, m0, m1, nu, nb, true)) != hipSuccess) return e;
     }
   }
-  hipLaunchKernelGGL(k_bs_dq, dim3(nm * c.cd.dim * c.cd.ns), dim3(256), 0, c.stream, c.md, c.ws.RQt, du, duhat, dq);
+  hipLaunchKernelGGL(k_bs_dq, dim3(nm * c.cd.dim * c.cd.ns), dim3(256), 0, c.stream, c.md, 0, c.ws.RQt, du, duhat, dq);
   return hipGetLastError();
 }

@@ -35,6 +35,10 @@ struct FormPtrs {
   int only_class;    // >= 0: rows of other macro classes are skipped
   int split_cols;    // >= 0: grouped launch takes classes with n_cols <= split_cols, single-row launch the rest
   int tab_off;       // LDS byte offset of the class's 1D operators C1D and Minv1D (FP64)
+  // non-null: recovery form (the S rows only, for the local recovery after a
+  // chunked condensation): the right-hand side f + C duhat of eq. Csc4a goes
+  // to column n_u and the row is stored up to the end of that column's strip
+  const double* duhat;
 };
 
 // Macro of row group G: a guess from the mean group count per macro (exact
@@ -208,12 +212,14 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
       c0 = loc / nf; j = loc % nf;
     }
     r0 = r; rstride = 0;
+    if (fp.duhat && !urow) return;  // uniform per workgroup
   } else {
     urow = g < N;
     if (urow) {
       a = g; c0 = 0;
       r0 = a; rstride = N;
     } else {
+      if (fp.duhat) return;  // recovery form: S rows only (uniform per workgroup)
       int rho = g - N;  // trace node index over the local faces
       while (lf + 1 < 2 * d && rho >= cd.nf_nodes[lf]) { rho -= cd.nf_nodes[lf]; ++lf; }
       nf = cd.nf_nodes[lf];
@@ -353,6 +359,34 @@ __global__ void __launch_bounds__(NT) k_form(MeshDev md, FormPtrs fp, TW* __rest
   }
   __syncthreads();
   TW* Wmac = Wm + md.w_off[macro];
+  if (fp.duhat) {
+    // f + C duhat = f - (-C) duhat from the row's trace columns
+    double dot[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) dot[rr] = 0.0;
+    for (int s = tid; s < cd.n_b; s += NT) {
+      int lf2 = 0;
+      while (lf2 + 1 < 2 * d && s >= cd.nf_off[lf2 + 1]) ++lf2;
+      const int F = md.macro_face[(size_t)macro * 2 * d + lf2];
+      const double xv = fp.duhat[md.face_off[F] + (s - cd.nf_off[lf2])];
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr) dot[rr] += (double)row[rr * ldr + cd.n_u + s] * xv;
+    }
+    block_sum<NR, NT>(dot, red, tid);
+    __syncthreads();  // every thread has read the trace columns
+    if (tid == 0)
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr) row[rr * ldr + cd.n_u] = (TL)((double)row[rr * ldr + n_cols - 1] - dot[rr]);
+    __syncthreads();
+    const int cend = min(cd.ldw, (cd.n_u + 1 + 63) / 64 * 64);
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) {
+      TW* wrow = Wmac + wtix(r0 + rr * rstride, 0, cd.ldw);
+      for (int cidx = tid; cidx < cend; cidx += NT)
+        wrow[(cidx >> 6) * 1024 + (cidx & 63)] = (cidx <= cd.n_u) ? (TW)row[rr * ldr + cidx] : TW(0);
+    }
+    return;
+  }
 #pragma unroll
   for (int rr = 0; rr < NR; ++rr) {
     TW* wrow = Wmac + wtix(r0 + rr * rstride, 0, cd.ldw);  // column c at wrow[(c >> 6) * 1024 + (c & 63)]
@@ -375,10 +409,10 @@ size_t form_lds_bytes(const HdgContext& c, int nr, size_t elem, int n_cols) {
 
 template <class TW, int NR, int NT>
 hipError_t form_launch(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only_class, int n_cols,
-                       int split_cols) {
+                       int split_cols, const double* duhat) {
   FormPtrs fp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.ws.RQt, c.ws.RBloc, gloc,
               c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.hm.row_off[m0] / NR,
-              NR * n_cols, only_class, split_cols, (int)form_tab_off(c, NR, sizeof(TW), n_cols)};
+              NR * n_cols, only_class, split_cols, (int)form_tab_off(c, NR, sizeof(TW), n_cols), duhat};
   const long long nblk = (c.hm.row_off[m1] - c.hm.row_off[m0]) / NR;
   if (nblk <= 0) return hipSuccess;
   const size_t shm = form_lds_bytes(c, NR, sizeof(TW), n_cols);
@@ -387,7 +421,7 @@ hipError_t form_launch(HdgContext& c, int m0, int m1, TW* W, double* gloc, int o
 }
 
 template <class TW>
-hipError_t form_all(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only_class) {
+hipError_t form_all(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only_class, const double* duhat) {
   // classes whose n_s row buffers fit in LDS go to the grouped launch
   const int ns = c.hm.ns;
   int cols_g = -1, cols_1 = -1;
@@ -398,9 +432,10 @@ hipError_t form_all(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only
   const int split = (cols_g >= 0 && cols_1 >= 0) ? cols_g : -1;
   hipError_t e = hipSuccess;
   if (cols_g >= 0)
-    e = ns == 5 ? form_launch<TW, 5, 512>(c, m0, m1, W, gloc, only_class, cols_g, split)
-                : form_launch<TW, 4, 512>(c, m0, m1, W, gloc, only_class, cols_g, split);
-  if (e == hipSuccess && cols_1 >= 0) e = form_launch<TW, 1, 256>(c, m0, m1, W, gloc, only_class, cols_1, split);
+    e = ns == 5 ? form_launch<TW, 5, 512>(c, m0, m1, W, gloc, only_class, cols_g, split, duhat)
+                : form_launch<TW, 4, 512>(c, m0, m1, W, gloc, only_class, cols_g, split, duhat);
+  if (e == hipSuccess && cols_1 >= 0)
+    e = form_launch<TW, 1, 256>(c, m0, m1, W, gloc, only_class, cols_1, split, duhat);
   return e;
 }
 
@@ -409,10 +444,11 @@ hipError_t form_all(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only
 // Groups of n_s rows for the classes whose row buffers fit in LDS (every
 // row of a group shares its target indices; 512 threads), single rows of
 // 256 threads for the larger classes.
-hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class) {
+hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class, const double* rhs_duhat) {
   // FP32 storage: g of the trace rows stays in FP64 (it is O(1) per macro but
   // cancels between the two sides of a face in the assembled b-hat)
   double* gloc = prec == 1 ? c.ws.gloc : nullptr;
-  if (prec == 1) return form_all<float>(c, m0, m1, reinterpret_cast<float*>(c.ws.Wm), gloc, only_class);
-  return form_all<double>(c, m0, m1, c.ws.Wm, gloc, only_class);
+  if (prec == 1)
+    return form_all<float>(c, m0, m1, reinterpret_cast<float*>(c.ws.Wm), gloc, only_class, rhs_duhat);
+  return form_all<double>(c, m0, m1, c.ws.Wm, gloc, only_class, rhs_duhat);
 }

@@ -27,6 +27,7 @@
 // float); the FP32 instance is the low-precision condensation.
 #include "context.h"
 #include <algorithm>
+#include <type_traits>
 
 namespace {
 
@@ -48,6 +49,15 @@ template <> struct Mfma<float> {
   }
   static __device__ __forceinline__ int row(int i, int grp) { return 4 * grp + i; }
 };
+
+// BF16 operands with FP32 accumulation (16x16x16): lane l supplies
+// A[l % 16][4 (l / 16) + j] and B[4 (l / 16) + j][l % 16], j = 0..3; the
+// result registers are laid out as for the FP32 16x16x4 instruction.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ short to_bf16(float x) {  // round to nearest even
+  const unsigned u = __float_as_uint(x);
+  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
 
 constexpr int NB = 64;     // block width of the trailing update
 constexpr int PW = 16;     // sub-panel width held in registers
@@ -596,7 +606,7 @@ struct GemmArgs {
   int tiles_per_wg;
 };
 
-template <class T, int KB, int NT, bool PIPE>
+template <class T, int KB, int NT, bool PIPE, bool B16 = false>
 __device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int KS = KB / 4;  // MFMA k-steps; lane group grp covers k in [KS grp, KS grp + KS)
@@ -651,12 +661,29 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
     }
   };
   auto mma = [&](const T* af, v4* acc) {
+    if constexpr (B16) {
+      // four k values per lane and instruction: k = KS grp + 4 s4 + j
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
+      for (int s4 = 0; s4 < KS / 4; ++s4) {
+        bf16x4 a4;
 #pragma unroll
-      for (int ct = 0; ct < NC / 16; ++ct) {
-        const T bv = sB[(KS * grp + s) * NC + ct * 16 + col];
-        acc[ct] = Mfma<T>::op(af[s], bv, acc[ct]);
+        for (int j = 0; j < 4; ++j) a4[j] = to_bf16(af[4 * s4 + j]);
+#pragma unroll
+        for (int ct = 0; ct < NC / 16; ++ct) {
+          bf16x4 b4;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b4[j] = to_bf16(sB[(KS * grp + 4 * s4 + j) * NC + ct * 16 + col]);
+          acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a4, b4, acc[ct], 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+#pragma unroll
+        for (int ct = 0; ct < NC / 16; ++ct) {
+          const T bv = sB[(KS * grp + s) * NC + ct * 16 + col];
+          acc[ct] = Mfma<T>::op(af[s], bv, acc[ct]);
+        }
       }
     }
   };
@@ -695,6 +722,12 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
 template <class T, int KB>
 __global__ void __launch_bounds__(256, 2) k_gemm(GemmArgs<T> g) {
   gemm_body<T, KB, 256, true>(g);
+}
+
+// The trailing update with BF16 operands and FP32 accumulation (FP32 storage).
+template <int KB>
+__global__ void __launch_bounds__(256, 2) k_gemm_bf16(GemmArgs<float> g) {
+  gemm_body<float, KB, 256, true, true>(g);
 }
 
 }  // namespace
@@ -741,6 +774,13 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
                   T(-1), 1, TPW};
     const int ntile = (n_rows - live0 + 15) / 16;
     dim3 grid(nstrip, (ntile + TPW - 1) / TPW, batch);
+    if constexpr (std::is_same<T, float>::value) {
+      if (tune.bf16_update) {
+        if (K > NB) hipLaunchKernelGGL((k_gemm_bf16<2 * NB>), grid, dim3(256), 0, q, g);
+        else hipLaunchKernelGGL((k_gemm_bf16<NB>), grid, dim3(256), 0, q, g);
+        return;
+      }
+    }
     if (K > NB) hipLaunchKernelGGL((k_gemm<T, 2 * NB>), grid, dim3(256), 0, q, g);
     else hipLaunchKernelGGL((k_gemm<T, NB>), grid, dim3(256), 0, q, g);
   };
@@ -822,7 +862,7 @@ static size_t class_scratch_doubles(int batch) {
 // stream), each class with its own scratch slice.  top_only: only the rows
 // of S are eliminated (U, L^{-1} P (-C) and L^{-1} P f for the recovery).
 // only_class >= 0: that class alone (timing by the autotuner).
-hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only_class) {
+hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only_class, bool rhs_only) {
   const int ncl = c.hm.n_classes;
   int* status = reinterpret_cast<int*>(c.ws.small) + (size_t)chunk * ncl;
   const int* cnt = &c.hm.chunk_class_cnt[(size_t)chunk * ncl];
@@ -872,6 +912,7 @@ hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only
     int* ipiv = c.ws.ipiv + c.hm.class_ipiv_base[k] + (long long)c.hm.chunk_class_rank0[ck] * h.n_u;
     const int batch = cnt[k];
     const int n_rows = top_only ? h.n_u : h.n_rows;
+    const int n_cols = (top_only && rhs_only) ? h.n_u + 1 : h.n_cols;
     const int slot = nstreams > 0 ? (int)(i % nstreams) : 0;
     hipStream_t s = nstreams > 0 ? c.lu_streams[slot] : c.stream;
     hipStream_t sp = c.lu_pstreams[slot];
@@ -879,13 +920,14 @@ hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only
     double* scratch = c.ws.Uinv + scr;
     scr += class_scratch_doubles(batch);
     if (only_class >= 0 && k != only_class) continue;
-    const LuTune tune = h.tune[prec == 1 ? 1 : 0];
+    LuTune tune = h.tune[prec == 1 ? 1 : 0];
+    tune.bf16_update = (prec == 1 && c.bf16_update && !top_only) ? 1 : 0;
     if (prec == 1)
       e = lu_eliminate<float>(s, reinterpret_cast<float*>(c.ws.Wm) + c.hm.chunk_class_w[ck], batch, h.wstride, h.ldw,
-                              h.n_u, n_rows, h.n_cols, ipiv, h.n_u, status + k, reinterpret_cast<float*>(scratch),
+                              h.n_u, n_rows, n_cols, ipiv, h.n_u, status + k, reinterpret_cast<float*>(scratch),
                               tune, sp, evA, evF);
     else
-      e = lu_eliminate<double>(s, c.ws.Wm + c.hm.chunk_class_w[ck], batch, h.wstride, h.ldw, h.n_u, n_rows, h.n_cols,
+      e = lu_eliminate<double>(s, c.ws.Wm + c.hm.chunk_class_w[ck], batch, h.wstride, h.ldw, h.n_u, n_rows, n_cols,
                                ipiv, h.n_u, status + k, scratch, tune, sp, evA, evF);
     if (e != hipSuccess) return e;
   }

@@ -30,3 +30,17 @@ def test_condense_flops_24cubed():
     # 2.22e10 per macro, 1.135e13 for the 512 macros of the workload
     assert f == pytest.approx(2.217e10, rel=2e-3)
     assert 512 * f == pytest.approx(1.135e13, rel=2e-3)
+
+
+def test_condense_flops_48cubed_headline():
+    """The headline workload (48^3, 4^3-element macros, p = 2): n_u = 3645,
+    n_b = 2430 per macro, 1.52e11 flop per macro, 2.62e14 per condensation of
+    the 1728 macros."""
+    sys.path.insert(0, ROOT)
+    import bench
+    cfg = dict(dim=3, p=2, m=4)
+    n_u, n_b = 5 * 9 ** 3, 5 * 6 * 9 ** 2
+    assert (n_u, n_b) == (3645, 2430)
+    f = bench.condense_flops(cfg, n_u, n_b)
+    assert f == pytest.approx(1.52e11, rel=5e-3)
+    assert 1728 * f == pytest.approx(2.62e14, rel=5e-3)

@@ -46,9 +46,9 @@ def test_autotune_caches_and_keeps_parity(tmp_path):
     ctx.condense(bhat, HDG_FP64)
     for i in lin:
         A_i, b_i = ctx.get_condensed(i)
-        assert _rel(A_i, cond[i]["Ahat"]) < 1e-9 and _rel(b_i, cond[i]["bhat"]) < 1e-9
+        assert _rel(A_i, cond[i]["Ahat"]) < 1e-10 and _rel(b_i, cond[i]["bhat"]) < 1e-10
     A, b = S.assemble(cond)
-    assert _rel(bhat.cpu().numpy(), b) < 1e-9
+    assert _rel(bhat.cpu().numpy(), b) < 1e-10
     ctx.condense(bhat, HDG_FP32)
     ea = max(_rel(ctx.get_condensed(i)[0], cond[i]["Ahat"]) for i in lin)
     say(f"[autotune] FP32 A-hat {ea:.2e}")
@@ -75,7 +75,7 @@ def test_forced_launch_shapes_keep_parity(case, shape):
     ctx.condense(bhat, HDG_FP64)
     for i in lin:
         A_i, b_i = ctx.get_condensed(i)
-        assert _rel(A_i, cond[i]["Ahat"]) < 1e-9 and _rel(b_i, cond[i]["bhat"]) < 1e-9
+        assert _rel(A_i, cond[i]["Ahat"]) < 1e-10 and _rel(b_i, cond[i]["bhat"]) < 1e-10
     # recovery re-uses the factors
     A, b = S.assemble(cond)
     x_ref = S.solve_direct(A, b)
@@ -83,4 +83,4 @@ def test_forced_launch_shapes_keep_parity(case, shape):
     du = torch.zeros(ctx.n_u_tot, dtype=torch.float64, device="cuda")
     ctx.local_backsolve(to_dev(x_ref), dq, du)
     dq_o, du_o = S.backsolve(lin, cond, x_ref)
-    assert _rel(du.cpu().numpy(), du_o) < 1e-9 and _rel(dq.cpu().numpy(), dq_o) < 1e-9
+    assert _rel(du.cpu().numpy(), du_o) < 1e-10 and _rel(dq.cpu().numpy(), dq_o) < 1e-10

@@ -53,10 +53,10 @@ def test_chunked_fp64_matches_oracle(pairs, name):
     ctx.condense(bhat)
     for i in lin:
         A_i, b_i = ctx.get_condensed(i)
-        assert _rel(A_i, cond[i]["Ahat"]) < 1e-9, f"Ahat macro {i}"
-        assert _rel(b_i, cond[i]["bhat"]) < 1e-9, f"bhat macro {i}"
+        assert _rel(A_i, cond[i]["Ahat"]) < 1e-10, f"Ahat macro {i}"
+        assert _rel(b_i, cond[i]["bhat"]) < 1e-10, f"bhat macro {i}"
     A, b = S.assemble(cond)
-    assert _rel(bhat.cpu().numpy(), b) < 1e-9
+    assert _rel(bhat.cpu().numpy(), b) < 1e-10
     x = np.random.default_rng(7).standard_normal(ctx.n_glob)
     y = torch.zeros_like(bhat)
     ctx.apply_global(to_dev(x), y)
@@ -65,14 +65,14 @@ def test_chunked_fp64_matches_oracle(pairs, name):
     xg = torch.zeros_like(bhat)
     info = ctx.fgmres_solve(bhat, xg, rtol=1e-13, restart=30, max_outer=400, inner_its=5)
     assert info["converged"], info
-    assert _rel(xg.cpu().numpy(), x_ref) < 1e-9
+    assert _rel(xg.cpu().numpy(), x_ref) < 1e-10
     dq = torch.zeros(ctx.n_q_tot, dtype=torch.float64, device="cuda")
     du = torch.zeros(ctx.n_u_tot, dtype=torch.float64, device="cuda")
     ctx.local_backsolve(to_dev(x_ref), dq, du)
     dq_o, du_o = S.backsolve(lin, cond, x_ref)
     edu, edq = _rel(du.cpu().numpy(), du_o), _rel(dq.cpu().numpy(), dq_o)
     say(f"[chunked fp64] {name}: dU {edu:.2e} dQ {edq:.2e}")
-    assert edu < 1e-9 and edq < 1e-9
+    assert edu < 1e-10 and edq < 1e-10
     # an FP32 inner operator needs an FP32 condensation when chunked
     from paper_2402_11361_amd.hdg import HDG_FP32, HdgError
     with pytest.raises(HdgError, match="EUNSUPPORTED"):
@@ -106,7 +106,8 @@ def test_chunked_fp32_matches_oracle(pairs, name):
     du = torch.zeros(ctx.n_u_tot, dtype=torch.float64, device="cuda")
     ctx.local_backsolve(to_dev(x_ref), dq, du)
     dq_o, du_o = S.backsolve(lin, cond, x_ref)
-    assert _rel(du.cpu().numpy(), du_o) < TOL32 and _rel(dq.cpu().numpy(), dq_o) < TOL32
+    # refined in FP64 against the u-rows' residual (FP32 factors only precondition it)
+    assert _rel(du.cpu().numpy(), du_o) < 1e-10 and _rel(dq.cpu().numpy(), dq_o) < 1e-10
 
 
 def test_chunked_formed_matrix_of_a_middle_chunk(pairs):

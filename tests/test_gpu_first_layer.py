@@ -37,10 +37,10 @@ def test_first_layer_matches_route_a_and_second_layer(name):
     for i in lin:
         A_i, b_i = ctx.get_condensed(i)
         first[i] = (A_i, b_i)
-        assert _rel(A_i, cond_a[i]["Ahat"]) < 1e-9, f"Ahat macro {i}"
-        assert _rel(b_i, cond_a[i]["bhat"]) < 1e-9, f"bhat macro {i}"
+        assert _rel(A_i, cond_a[i]["Ahat"]) < 1e-10, f"Ahat macro {i}"
+        assert _rel(b_i, cond_a[i]["bhat"]) < 1e-10, f"bhat macro {i}"
     A, b = S.assemble(cond_a)
-    assert _rel(bhat.cpu().numpy(), b) < 1e-9
+    assert _rel(bhat.cpu().numpy(), b) < 1e-10
     x = np.random.default_rng(7).standard_normal(ctx.n_glob)
     y = torch.zeros_like(bhat)
     ctx.apply_global(to_dev(x), y)
@@ -48,18 +48,18 @@ def test_first_layer_matches_route_a_and_second_layer(name):
     x_ref = S.solve_direct(A, b)
     xg = torch.zeros_like(bhat)
     info = ctx.fgmres_solve(bhat, xg, rtol=1e-13, restart=30, max_outer=400, inner_its=5)
-    assert info["converged"] and _rel(xg.cpu().numpy(), x_ref) < 1e-9
+    assert info["converged"] and _rel(xg.cpu().numpy(), x_ref) < 1e-10
     dq = torch.zeros(ctx.n_q_tot, dtype=torch.float64, device="cuda")
     du = torch.zeros(ctx.n_u_tot, dtype=torch.float64, device="cuda")
     ctx.local_backsolve(to_dev(x_ref), dq, du)
     dq_o, du_o = S.backsolve(lin, S.condense(lin, "B"), x_ref)
-    assert _rel(du.cpu().numpy(), du_o) < 1e-9 and _rel(dq.cpu().numpy(), dq_o) < 1e-9
+    assert _rel(du.cpu().numpy(), du_o) < 1e-10 and _rel(dq.cpu().numpy(), dq_o) < 1e-10
     # the second layer gives the same blocks
     b2 = torch.zeros_like(bhat)
     ctx.condense(b2)
     ea = max(_rel(ctx.get_condensed(i)[0], first[i][0]) for i in lin)
     say(f"[first layer] {name}: first vs second layer A-hat {ea:.2e}")
-    assert ea < 1e-10 and _rel(b2.cpu().numpy(), bhat.cpu().numpy()) < 1e-9
+    assert ea < 1e-10 and _rel(b2.cpu().numpy(), bhat.cpu().numpy()) < 1e-10
 
 
 def test_first_layer_needs_chunking():
@@ -107,10 +107,10 @@ def test_first_layer_tgv24_sampled_macros():
     for i in sample:
         ea, eb = _rel(first[i][0], cond[i]["Ahat"]), _rel(first[i][1], cond[i]["bhat"])
         say(f"[first layer tgv24] macro {i}: A-hat {ea:.2e} b-hat {eb:.2e}")
-        assert ea < 1e-9 and eb < 1e-9
+        assert ea < 1e-10 and eb < 1e-10
     b1 = bhat.clone()
     ctx.condense(bhat)
     for i in sample:
         assert _rel(ctx.get_condensed(i)[0], first[i][0]) < 1e-10
-    assert _rel(b1.cpu().numpy(), bhat.cpu().numpy()) < 1e-9
+    assert _rel(b1.cpu().numpy(), bhat.cpu().numpy()) < 1e-10
     ctx.close()
