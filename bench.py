@@ -690,7 +690,9 @@ def main():
                     help="also train and evaluate the learned correction on the 32^3 p=3 workload")
     ap.add_argument("--big-steps", type=int, default=0,
                     help="also time this many DIRK(3,3) steps of the 48^3 workload (chunked FP32 condensation)")
-    ap.add_argument("--tune-cache", default=None, help="text file of earlier autotuner choices (read and appended)")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2402_11361_amd", "tune_mi355x.txt"),
+                    help="text file of earlier autotuner choices (read; new choices are appended); the default holds "
+                         "the choices measured on MI355X for the bench workloads")
     ap.add_argument("--plain-prec", choices=("fp64", "fp32"), default="fp64",
                     help="condensation precision of the headline (profiling of the FP32 path)")
     ap.add_argument("--uneven-only", action="store_true",

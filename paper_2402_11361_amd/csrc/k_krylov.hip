@@ -55,6 +55,7 @@ __global__ void k_face_gather_sum(MeshDev md, const TB* __restrict__ base, int t
 }
 
 constexpr int APPLY_ROWS = 64;
+constexpr int APPLY_RB = 8;  // rows per pass of a wave (APPLY_ROWS / 4 divisible by it)
 
 // ypart[b_off[macro] + r] = (A-hat^{T_i} x_i)_r.  TILED: A-hat inside the
 // macro's tiled augmented matrix at (n_u, n_u); otherwise the compact
@@ -80,39 +81,38 @@ __global__ void __launch_bounds__(256) k_apply_local(MeshDev md, const TA* __res
   const TA* Am = Ab + (TILED ? md.w_off[macro] : md.a32_off[macro]);
   const long long ld = TILED ? cd.ldw : nb;
   const int off = TILED ? cd.n_u : 0;
-  for (int rr = 0; rr < APPLY_ROWS / 4; rr += 4) {
+  // APPLY_RB rows at a time: that many independent row streams per lane
+  for (int rr = 0; rr < APPLY_ROWS / 4; rr += APPLY_RB) {
     const int r = r0 + rr;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double acc[APPLY_RB];
+#pragma unroll
+    for (int i = 0; i < APPLY_RB; ++i) acc[i] = 0.0;
     if (TILED) {
-      const int q0 = off + min(r + 0, nb - 1), q1 = off + min(r + 1, nb - 1);
-      const int q2 = off + min(r + 2, nb - 1), q3 = off + min(r + 3, nb - 1);
+      int q[APPLY_RB];
+#pragma unroll
+      for (int i = 0; i < APPLY_RB; ++i) q[i] = off + min(r + i, nb - 1);
       for (int s = lane; s < nb; s += 64) {
         const double xv = xs[s];
-        a0 += (double)Am[wtix(q0, off + s, ld)] * xv;
-        a1 += (double)Am[wtix(q1, off + s, ld)] * xv;
-        a2 += (double)Am[wtix(q2, off + s, ld)] * xv;
-        a3 += (double)Am[wtix(q3, off + s, ld)] * xv;
+#pragma unroll
+        for (int i = 0; i < APPLY_RB; ++i) acc[i] += (double)Am[wtix(q[i], off + s, ld)] * xv;
       }
     } else {
-      const TA* p0 = Am + (size_t)min(r + 0, nb - 1) * ld;
-      const TA* p1 = Am + (size_t)min(r + 1, nb - 1) * ld;
-      const TA* p2 = Am + (size_t)min(r + 2, nb - 1) * ld;
-      const TA* p3 = Am + (size_t)min(r + 3, nb - 1) * ld;
+      const TA* p[APPLY_RB];
+#pragma unroll
+      for (int i = 0; i < APPLY_RB; ++i) p[i] = Am + (size_t)min(r + i, nb - 1) * ld;
       for (int s = lane; s < nb; s += 64) {
         const double xv = xs[s];
-        a0 += (double)p0[s] * xv;
-        a1 += (double)p1[s] * xv;
-        a2 += (double)p2[s] * xv;
-        a3 += (double)p3[s] * xv;
+#pragma unroll
+        for (int i = 0; i < APPLY_RB; ++i) acc[i] += (double)p[i][s] * xv;
       }
     }
-    a0 = wave_sum(a0); a1 = wave_sum(a1); a2 = wave_sum(a2); a3 = wave_sum(a3);
+#pragma unroll
+    for (int i = 0; i < APPLY_RB; ++i) acc[i] = wave_sum(acc[i]);
     if (lane == 0) {
       double* yp = ypart + md.b_off[macro];
-      if (r + 0 < nb) yp[r + 0] = a0;
-      if (r + 1 < nb) yp[r + 1] = a1;
-      if (r + 2 < nb) yp[r + 2] = a2;
-      if (r + 3 < nb) yp[r + 3] = a3;
+#pragma unroll
+      for (int i = 0; i < APPLY_RB; ++i)
+        if (r + i < nb) yp[r + i] = acc[i];
     }
   }
 }

@@ -745,8 +745,9 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
   LuArgs<T> a{W, mat_stride, ld, n_piv, n_rows, n_cols, ipiv, ipiv_stride, status, perm};
   if (ld % NC != 0) return hipErrorInvalidValue;
   const int rpt = (n_piv + PANEL_THREADS - 1) / PANEL_THREADS;
-  // up to 2048 rows: 512 threads, 1..4 rows each; up to 4096: 1024 threads, 4 rows each;
-  // up to 12288: 512 threads, 24 rows each of 4-column sub-panels (register budget)
+  // up to 2048 rows: 512 threads, 1..4 rows each; up to 4096: 512 threads with 8
+  // rows or 1024 threads with 4 rows; up to 12288: 512 threads, 24 rows each of
+  // 4-column sub-panels (register budget)
   const int TPW = tune.tpw;  // 16-row tiles per workgroup (TPW / 4 per wave)
   if (TPW < 4 || TPW % 4) return hipErrorInvalidValue;
   auto panel = [&](hipStream_t q, int j0, int jb, int lcol0) {
@@ -757,7 +758,16 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
     else if (rpt <= 1) hipLaunchKernelGGL((k_panel<T, 1, 512>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
     else if (rpt <= 2) hipLaunchKernelGGL((k_panel<T, 2, 512>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
     else if (rpt <= 4) hipLaunchKernelGGL((k_panel<T, 4, 512>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
-    else if (n_piv <= 4 * 1024) hipLaunchKernelGGL((k_panel<T, 4, 1024>), dim3(batch), dim3(1024), 0, q, a, j0, jb, lcol0);
+    // up to 4096 rows: 512 threads with 8 rows of an 8-column sub-panel each,
+    // or (wide) 1024 threads with 4 rows (FP64 with 8-column sub-panels: a
+    // 16-column FP64 sub-panel of 4 rows does not fit the register budget of
+    // 1024 threads)
+    else if (n_piv <= 4 * 1024 && tune.panel_wide && sizeof(T) == 4)
+      hipLaunchKernelGGL((k_panel<T, 4, 1024>), dim3(batch), dim3(1024), 0, q, a, j0, jb, lcol0);
+    else if (n_piv <= 4 * 1024 && tune.panel_wide)
+      hipLaunchKernelGGL((k_panel<T, 4, 1024, 8>), dim3(batch), dim3(1024), 0, q, a, j0, jb, lcol0);
+    else if (n_piv <= 4 * 1024)
+      hipLaunchKernelGGL((k_panel<T, 8, 512, 8>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
     else hipLaunchKernelGGL((k_panel<T, 24, 512, 4>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
   };
   auto drows = [&](hipStream_t q, int j0, int jb) {  // L of the non-pivot rows: A_D,block U11^{-1}
