@@ -35,9 +35,10 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per hdg_condense call of the FP64 path, per workload, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by what the counters
-# read for a 1 GiB device copy in the same run (profiles/), valid only while
-# the kernel sources hash to `sha`.
-CONDENSE_TRAFFIC = {"sha": "e0ebc3daaf95b564", "tgv24_m3_p2": 1161.2e9}
+# read for a 1 GiB device copy in the same run
+# (profiles/newton_step_tgv48_m4_p2_fp64.md), valid only while the kernel
+# sources hash to `sha`.
+CONDENSE_TRAFFIC = {"sha": "3c38d1927ff50f82", "tgv48_m4_p2": 28.23e12}
 CONDENSE_SOURCES = ("k_form.hip", "k_lu.hip")
 
 
