@@ -299,9 +299,11 @@ def tgv_dissipation_variant(args, dev_fn, variants):
 
 def learned_p3_variant(args, dev_fn, variants):
     """The learned coarse correction on the 32^3 mesh with 4^3-element macros
-    at p = 3 (512 macros, chunked FP32 condensation): pairs harvested from a
-    plain solve on the seed-100 state, evaluated on the held-out seed-200
-    state (first Newton step), plain and learned preconditioner."""
+    at p = 3 (512 macros, chunked FP32 condensation): pairs harvested from
+    plain solves on the states of seeds 100, 101, ... (training), evaluated on
+    the held-out states of seeds 200, 201, ... (first Newton step): plain
+    multi-level preconditioner, learned stage judged by it (fallback on), and
+    the learned stage kept for the whole solve (no fallback)."""
     import torch
     from paper_2402_11361_amd import inputs
     from paper_2402_11361_amd.hdg import HDG_FP32, Context, mesh_spec_box
@@ -323,10 +325,14 @@ def learned_p3_variant(args, dev_fn, variants):
         ctx.linearize_stage(q, u, uh, -dii * u, dt, dii)
         ctx.condense(bhat, HDG_FP32)
 
+    train_seeds = list(range(100, 100 + args.learned_train_seeds))
+    eval_seeds = list(range(200, 200 + args.learned_eval_seeds))
     t0 = time.perf_counter()
     cc = CoarseCorrection(ctx, hidden=256, max_batch=1024, seed=0)
-    condense_state(100)
-    cc.harvest(bhat, n_vectors=args.train_vectors, inner_prec=HDG_FP32)
+    for s_ in train_seeds:
+        condense_state(s_)
+        cc.harvest(bhat, n_vectors=args.train_vectors, inner_prec=HDG_FP32)
+        print(f"[bench] p=3 learned: seed {s_} harvested, {cc.n_pairs()} pairs", file=sys.stderr, flush=True)
     X, T = torch.cat(cc.X), torch.cat(cc.T)
     loss0 = cc.eval_loss(X, T)
     cc.train(epochs=args.train_epochs, lr=1e-3, batch=1024)
@@ -335,20 +341,26 @@ def learned_p3_variant(args, dev_fn, variants):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     print(f"[bench] p=3 learned: {cc.n_pairs()} pairs, loss {loss0:.3e} -> {loss1:.3e}", file=sys.stderr, flush=True)
-    condense_state(200)
     evals = {}
-    for name, lrn in (("plain", False), ("learned", True)):
-        x = torch.zeros_like(bhat)
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        info = ctx.fgmres_solve(bhat, x, rtol=cfg["rtol"], restart=30, max_outer=300, inner_its=5,
-                                inner_prec=HDG_FP32, use_learned=lrn)
-        torch.cuda.synchronize()
-        evals[name] = dict(outer_its=info["outer_its"], inner_its=info["inner_its"], ms=round(1e3 * (time.perf_counter() - ts), 1),
-                           fallbacks=info["fallbacks"], converged=info["converged"])
+    for s_ in eval_seeds:
+        condense_state(s_)
+        ev = {}
+        for name, lrn, nofb in (("plain", False, False), ("learned", True, False), ("learned_no_fallback", True, True)):
+            x = torch.zeros_like(bhat)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            info = ctx.fgmres_solve(bhat, x, rtol=cfg["rtol"], restart=30, max_outer=300, inner_its=5,
+                                    inner_prec=HDG_FP32, use_learned=lrn, no_fallback=nofb, allow_noconv=True)
+            torch.cuda.synchronize()
+            ev[name] = dict(outer_its=info["outer_its"], inner_its=info["inner_its"],
+                            ms=round(1e3 * (time.perf_counter() - ts), 1), fallbacks=info["fallbacks"],
+                            converged=info["converged"])
+        evals[f"seed_{s_}"] = ev
+        print(f"[bench] p=3 learned: held-out seed {s_}: {ev}", file=sys.stderr, flush=True)
     variants["tgv32_m4_p3_learned"] = dict(
         workload=f"32^3 periodic Taylor-Green, 4^3-element macros (512), p=3, n_glob {ctx.n_glob}; chunked FP32 "
-                 f"condensation ({per} macros per chunk); train on seed 100, evaluate on seed 200",
+                 f"condensation ({per} macros per chunk); train on seeds {train_seeds}, evaluate on held-out seeds "
+                 f"{eval_seeds}",
         pairs=cc.n_pairs(), loss_initial=loss0, loss_final=loss1, train_s=round(t1 - t0, 1), solve=evals)
     ctx.close()
 
@@ -705,6 +717,8 @@ def main():
     ap.add_argument("--tgv-eps", type=float, default=0.0, metavar="T_END",
                     help="also integrate the Re = 100 Taylor-Green flow to t/t_c = T_END on (m,p) = (3,2) and (2,3) "
                          "and report the dissipation rate")
+    ap.add_argument("--learned-train-seeds", type=int, default=1, help="training states of --learned-p3 (seeds 100..)")
+    ap.add_argument("--learned-eval-seeds", type=int, default=1, help="held-out states of --learned-p3 (seeds 200..)")
     ap.add_argument("--train-seeds", type=int, default=2)
     ap.add_argument("--train-vectors", type=int, default=40)
     ap.add_argument("--train-epochs", type=int, default=60)

@@ -31,6 +31,10 @@ CASES = {
     "3d_per_uneven_p2_split_form": dict(dim=3, seg=[[4, 1], [4, 1], [2, 1]], p=2, periodic=True),
     "3d_dir_uneven_p1_supg": dict(dim=3, seg=[[1, 2], [2, 1], [2, 2]], p=1, periodic=False, state="shear",
                                   mach=0.2, supg=True),
+    # degenerate meshes: one periodic macro (each face is its own neighbour),
+    # standard HDG with one element per macro at p = 1
+    "2d_per_single_macro_p2": dict(dim=2, n_elem=2, m=2, p=2, periodic=True),
+    "3d_per_m1_p1": dict(dim=3, n_elem=2, m=1, p=1, periodic=True),
 }
 
 

@@ -20,12 +20,19 @@ def _full_system(S, lin):
         idx = dict(q=qi, u=ui, b=bi)
         for r in "qub":
             for c in "qub":
-                J[np.ix_(idx[r], idx[c])] += L["blk"][f"A_{r}{c}"]
+                # np.add.at: a macro can see one face from both sides (a single
+                # periodic macro), so trace indices repeat and must accumulate
+                rr, cc = np.meshgrid(idx[r], idx[c], indexing="ij")
+                np.add.at(J, (rr, cc), L["blk"][f"A_{r}{c}"])
         R[qi] += L["RQ"]; R[ui] += L["RU"]; np.add.at(R, bi, L["RB"])
     return J, R
 
 
 CASES = [dict(dim=2, n_elem=4, m=2, p=2, periodic=True, supg=True),
+         # one periodic macro: each of its faces is its own neighbour
+         dict(dim=2, n_elem=2, m=2, p=2, periodic=True),
+         # standard HDG (one element per macro) at p = 1
+         dict(dim=3, n_elem=2, m=1, p=1, periodic=True),
          dict(dim=2, n_elem=6, m=[3, 2], p=1, periodic=False, state="shear", supg=True),
          dict(dim=3, n_elem=2, m=1, p=2, periodic=True, supg=False)]
 
