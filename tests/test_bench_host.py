@@ -44,3 +44,20 @@ def test_condense_flops_48cubed_headline():
     f = bench.condense_flops(cfg, n_u, n_b)
     assert f == pytest.approx(1.52e11, rel=5e-3)
     assert 1728 * f == pytest.approx(2.62e14, rel=5e-3)
+
+
+def test_cpu_baseline_leg_on_the_small_2d_workload():
+    """The oracle leg of the bench (host only): phases present, positive,
+    scaled to the mesh, and the sampled condensed block returned for the
+    error against the GPU."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2402_11361_amd import inputs
+    cfg = dict(inputs.CONFIGS["shear16_m4_p2"])
+    out, blocks = bench.cpu_baseline(cfg, dict(outer_its=10, applies=60), n_sample=1)
+    assert out["kind"] == "oracle" and out["value"] > 0 and out["cores"] >= 1
+    for k in ("condense", "backsolve", "apply", "krylov_vectors"):
+        assert out["phases_ms"][k] >= 0
+    assert out["linearisation_not_a_fair_baseline"]["ms_per_macro"] > 0
+    A, b = blocks[0]
+    assert A.shape == (b.size, b.size) and abs(A).max() > 0
