@@ -604,14 +604,26 @@ struct GemmArgs {
   T alpha;
   int beta;
   int tiles_per_wg;
+  int gx, gy;        // strips and row groups per matrix (one-dimensional grid of gx gy batch workgroups)
 };
+
+// Workgroups go to the 8 XCDs round-robin (workgroup id modulo 8).  Renumber
+// them so that every XCD takes one contiguous run of work items: consecutive
+// items are consecutive strips of the same rows and matrix, so the rows of
+// L21 they all read stay in that XCD's L2 instead of being fetched by each XCD.
+__device__ __forceinline__ unsigned xcd_work_item(unsigned id, unsigned n) {
+  const unsigned x = id % 8u, s = id / 8u, q = n / 8u, r = n % 8u;
+  return (x < r ? x * (q + 1u) : r * (q + 1u) + (x - r) * q) + s;
+}
 
 template <class T, int KB, int NT, bool PIPE, bool B16 = false>
 __device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int KS = KB / 4;  // MFMA k-steps; lane group grp covers k in [KS grp, KS grp + KS)
-  const int mat = blockIdx.z;
-  const int cs = g.cs0 + blockIdx.x * NC;
+  const unsigned wi = xcd_work_item(blockIdx.x, gridDim.x);
+  const int strip = (int)(wi % (unsigned)g.gx), rgrp = (int)((wi / (unsigned)g.gx) % (unsigned)g.gy);
+  const int mat = (int)(wi / ((unsigned)g.gx * (unsigned)g.gy));
+  const int cs = g.cs0 + strip * NC;
   T* W = g.W + (size_t)mat * g.mat_stride;
   const T* B = g.B + (size_t)mat * g.b_mat_stride;
   const int ld = g.ld, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -622,7 +634,7 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
     sB[i] = (k < g.K && cs + c >= g.c_lo && cs + c < g.c_hi) ? (g.b_col_follow ? W[wtix(g.b_row0 + k, cs + c, ld)] : B[(size_t)k * g.ldb + c]) : T(0);
   }
   __syncthreads();
-  const int tile0 = blockIdx.y * g.tiles_per_wg;
+  const int tile0 = rgrp * g.tiles_per_wg;
   auto load_a = [&](int r0, T* af) {
     const int ra = r0 + col;
     const int kb = KS * grp;
@@ -750,6 +762,9 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
   // 4-column sub-panels (register budget)
   const int TPW = tune.tpw;  // 16-row tiles per workgroup (TPW / 4 per wave)
   if (TPW < 4 || TPW % 4) return hipErrorInvalidValue;
+  // one-dimensional update grids: at most 2^32 - 1 work-items
+  if ((long long)(ld / NC) * ((n_rows + 16 * TPW - 1) / (16 * TPW)) * batch * 256 > 0xffffffffLL)
+    return hipErrorInvalidValue;
   auto panel = [&](hipStream_t q, int j0, int jb, int lcol0) {
     if (tune.panel_wide && rpt <= 1)
       hipLaunchKernelGGL((k_panel<T, 1, 1024>), dim3(batch), dim3(1024), 0, q, a, j0, jb, lcol0);
@@ -773,17 +788,18 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
   auto drows = [&](hipStream_t q, int j0, int jb) {  // L of the non-pivot rows: A_D,block U11^{-1}
     if (n_rows <= n_piv) return;
     hipLaunchKernelGGL(k_uinv<T>, dim3(batch), dim3(NB), 0, q, a, j0, jb, scratch);
-    GemmArgs<T> g{W, mat_stride, ld, scratch, (long long)NB * NB, NB, 0, 0, j0, jb, j0, j0, j0 + jb, n_piv, n_rows, T(1), 0, TPW};
-    const int ntile = (n_rows - n_piv + 15) / 16;
-    hipLaunchKernelGGL((k_gemm<T, 64>), dim3(1, (ntile + TPW - 1) / TPW, batch), dim3(256), 0, q, g);
+    const int ntile = (n_rows - n_piv + 15) / 16, ny = (ntile + TPW - 1) / TPW;
+    GemmArgs<T> g{W, mat_stride, ld, scratch, (long long)NB * NB, NB, 0, 0, j0, jb, j0, j0, j0 + jb, n_piv, n_rows,
+                  T(1), 0, TPW, 1, ny};
+    hipLaunchKernelGGL((k_gemm<T, 64>), dim3((unsigned)(ny * batch)), dim3(256), 0, q, g);
   };
   // A22 -= L21 U12 for the strips [strip0, strip0 + nstrip) with U12 in rows [j0, j0 + K) of W
   auto update = [&](hipStream_t q, int j0, int K, int live0, int strip0, int nstrip, int col_end) {
     if (n_rows <= live0 || nstrip <= 0) return;
+    const int ntile = (n_rows - live0 + 15) / 16, ny = (ntile + TPW - 1) / TPW;
     GemmArgs<T> g{W, mat_stride, ld, W, mat_stride, ld, 1, j0, j0, K, strip0, live0, col_end, live0, n_rows,
-                  T(-1), 1, TPW};
-    const int ntile = (n_rows - live0 + 15) / 16;
-    dim3 grid(nstrip, (ntile + TPW - 1) / TPW, batch);
+                  T(-1), 1, TPW, nstrip, ny};
+    dim3 grid((unsigned)((long long)nstrip * ny * batch));
     if constexpr (std::is_same<T, float>::value) {
       if (tune.bf16_update) {
         if (K > NB) hipLaunchKernelGGL((k_gemm_bf16<2 * NB>), grid, dim3(256), 0, q, g);
