@@ -193,18 +193,19 @@ hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk);
  * the class's elimination (HIP events on the context's stream, after one
  * untimed trial) for each candidate launch shape -- 8, 16, 32, 64, 128 or
  * 256 sixteen-row tiles per workgroup of the trailing update with the 512-thread
- * panel factorisation, then the 1024-thread panel with the best of those,
- * then the factorisation of the next pair of column blocks on a second
- * stream beside the trailing update -- on the current linearisation, and
- * keeps the fastest (the wider panel and the second stream only when they
- * gain more than 2%, the spread of single timings).
+ * panel factorisation, then the 1024-thread panel and tournament pivoting
+ * with the best of those, then the factorisation of the next pair of column
+ * blocks on a second stream beside the trailing update -- on the current
+ * linearisation, and keeps the fastest (another panel and the second stream
+ * only when they gain more than 2%, the spread of single timings).
  * cache_path (host string, may be NULL): text file of earlier choices, one
  * line per (GPU architecture, HIP runtime version, precision, class shape,
  * batch size); classes found there are not timed, new choices are appended.
  * n_timed (host, may be NULL) receives the number of classes timed.
  * Needs a bound workspace and a prior hdg_linearize_stage; the trials
  * overwrite the condensed blocks, so hdg_condense must follow.  The choices
- * change launch shapes only, not results beyond rounding order. */
+ * change launch shapes and, with tournament pivoting, the pivot order; the
+ * results differ by rounding only. */
 hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int* n_timed);
 
 /* Number of macro classes (distinct macro shapes) of the mesh. */
@@ -212,14 +213,18 @@ hdg_status hdg_class_count(hdg_ctx ctx, int* n_classes);
 
 /* Launch shape in use for class macro_class (0 .. n_classes - 1) and the
  * given precision: tiles per workgroup of the trailing update (default 32),
- * the wide-panel flag and the look-ahead-stream flag (default 0); host
- * pointers, each may be NULL. */
-hdg_status hdg_get_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int* tpw, int* panel_wide, int* lookahead);
+ * the panel kind (default 2) and the look-ahead-stream flag (default 0);
+ * host pointers, each may be NULL.  Panel kinds: 0 partial pivoting in one
+ * 512-thread workgroup per matrix (LAPACK's pivot order), 1 the same with
+ * 1024 threads, 2 tournament pivoting (the block's pivot rows chosen by
+ * rounds of partial pivoting over groups of 256 rows, then L21 = A21 U11^-1
+ * on MFMA). */
+hdg_status hdg_get_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int* tpw, int* panel, int* lookahead);
 
 /* Sets the launch shape of a class by hand (tpw: multiple of 4 in [4, 256];
- * flags 0 or 1); HDG_EINVAL otherwise.  Results change only by rounding
- * order. */
-hdg_status hdg_set_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int tpw, int panel_wide, int lookahead);
+ * panel 0, 1 or 2; lookahead 0 or 1); HDG_EINVAL otherwise.  Results change
+ * only by rounding. */
+hdg_status hdg_set_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int tpw, int panel, int lookahead);
 
 /* Linearise eq. (C242) at (q, u, uhat): residuals R_Q, R_U, R_Uhat and the
  * Jacobian blocks of eq. (C312) of every macro, kept in the workspace.

@@ -481,7 +481,7 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
   std::string arch(prop.gcnArchName);
   arch = arch.substr(0, arch.find(':'));
   // cache: one line per (arch, runtime, precision, class shape, batch):
-  //   arch runtime prec dim m0 m1 m2 p batch | tpw panel_wide lookahead ms
+  //   arch runtime prec dim m0 m1 m2 p batch | tpw panel lookahead ms
   std::map<std::string, LuTune> cache;
   if (cache_path) {
     std::ifstream in(cache_path);
@@ -496,9 +496,9 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
         key << a << ' ' << r << ' ' << pr << ' ' << d << ' ' << m0 << ' ' << m1 << ' ' << m2 << ' ' << p << ' ' << batch;
         LuTune t;
         t.tpw = tpw;
-        t.panel_wide = wide;
+        t.panel = wide;
         t.lookahead = look;
-        if (tpw >= 4 && tpw <= 256 && tpw % 4 == 0 && (wide == 0 || wide == 1) && (look == 0 || look == 1))
+        if (tpw >= 4 && tpw <= 256 && tpw % 4 == 0 && wide >= 0 && wide <= 2 && (look == 0 || look == 1))
           cache[key.str()] = t;
       }
     }
@@ -526,17 +526,19 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
       continue;
     }
     // tiles per workgroup 8..256 with the default panel, then the wide panel
-    // with the best of those; one untimed trial first (code loading)
+    // and the tournament with the best of those; one untimed trial first
+    // (code loading)
     float best = 1e30f;
     LuTune pick;
     // then the look-ahead stream with the best so far
-    const int cand[9][3] = {{32, 0, 0}, {8, 0, 0}, {16, 0, 0}, {32, 0, 0}, {64, 0, 0}, {128, 0, 0}, {256, 0, 0},
-                            {-1, 1, 0}, {-1, -1, 1}};
-    for (int ci = 0; ci < 9 && st == HDG_OK; ++ci) {
+    constexpr int NCAND = 10;
+    const int cand[NCAND][3] = {{32, 0, 0}, {8, 0, 0},  {16, 0, 0}, {32, 0, 0}, {64, 0, 0}, {128, 0, 0}, {256, 0, 0},
+                                {-1, 1, 0}, {-1, 2, 0}, {-1, -1, 1}};
+    for (int ci = 0; ci < NCAND && st == HDG_OK; ++ci) {
       {
         LuTune t;
         t.tpw = cand[ci][0] > 0 ? cand[ci][0] : pick.tpw;
-        t.panel_wide = cand[ci][1] >= 0 ? cand[ci][1] : pick.panel_wide;
+        t.panel = cand[ci][1] >= 0 ? cand[ci][1] : pick.panel;
         t.lookahead = cand[ci][2];
         h.tune[p32] = t;
         float tmin = 1e30f;
@@ -555,7 +557,7 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
           }
           tmin = std::min(tmin, ms);
         }
-        // the wide panel and the second stream only for a gain beyond the
+        // another panel and the second stream only for a gain beyond the
         // spread of single timings (about 2%)
         const float need = (cand[ci][1] != 0 || cand[ci][2] != 0) ? 0.98f : 1.0f;
         if (ci > 0 && tmin < need * best) { best = tmin; pick = t; }
@@ -564,7 +566,7 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
     h.tune[p32] = pick;
     ++timed;
     std::ostringstream line;
-    line << key.str() << ' ' << pick.tpw << ' ' << pick.panel_wide << ' ' << pick.lookahead << ' ' << best;
+    line << key.str() << ' ' << pick.tpw << ' ' << pick.panel << ' ' << pick.lookahead << ' ' << best;
     fresh.push_back(line.str());
   }
   (void)hipEventDestroy(ev0);
@@ -588,23 +590,23 @@ hdg_status hdg_class_count(hdg_ctx ctx, int* n_classes) {
   return HDG_OK;
 }
 
-hdg_status hdg_set_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int tpw, int panel_wide, int lookahead) {
+hdg_status hdg_set_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int tpw, int panel, int lookahead) {
   if (!ctx || macro_class < 0 || macro_class >= ctx->c.hm.n_classes || (prec != HDG_FP64 && prec != HDG_FP32) ||
-      tpw < 4 || tpw > 256 || tpw % 4 || (panel_wide != 0 && panel_wide != 1) || (lookahead != 0 && lookahead != 1))
+      tpw < 4 || tpw > 256 || tpw % 4 || panel < 0 || panel > 2 || (lookahead != 0 && lookahead != 1))
     return HDG_EINVAL;
   LuTune& t = ctx->c.hcs[macro_class].tune[prec == HDG_FP32 ? 1 : 0];
   t.tpw = tpw;
-  t.panel_wide = panel_wide;
+  t.panel = panel;
   t.lookahead = lookahead;
   return HDG_OK;
 }
 
-hdg_status hdg_get_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int* tpw, int* panel_wide, int* lookahead) {
+hdg_status hdg_get_tuning(hdg_ctx ctx, int macro_class, hdg_prec prec, int* tpw, int* panel, int* lookahead) {
   if (!ctx || macro_class < 0 || macro_class >= ctx->c.hm.n_classes || (prec != HDG_FP64 && prec != HDG_FP32))
     return HDG_EINVAL;
   const LuTune& t = ctx->c.hcs[macro_class].tune[prec == HDG_FP32 ? 1 : 0];
   if (tpw) *tpw = t.tpw;
-  if (panel_wide) *panel_wide = t.panel_wide;
+  if (panel) *panel = t.panel;
   if (lookahead) *lookahead = t.lookahead;
   return HDG_OK;
 }

@@ -590,10 +590,10 @@ void plan_workspace(HdgContext& c) {
   o.kry = take(sizeof(double) * (size_t)(2 * c.kry_restart_max + c.kry_inner_max + 8) * hm.n_glob);
   o.red = take(sizeof(double) * (1 << 20));
   o.small = take(sizeof(double) * 4096);
-  // elimination scratch per matrix: a 64 x 64 block inverse, two row permutations
-  // and a 128 x 128 unit-lower block inverse
-  // (per class slices when there are several classes)
-  o.Uinv = take(sizeof(double) * ((size_t)std::max(hm.n_macros, hm.n_faces) * (64 * 64 + 128 * 128 + 512) +
+  // elimination scratch per matrix: a 64 x 64 block inverse, two row permutations,
+  // a 128 x 128 unit-lower block inverse and two rounds of tournament candidates
+  // (48 sets of 64 rows each) (per class slices when there are several classes)
+  o.Uinv = take(sizeof(double) * ((size_t)std::max(hm.n_macros, hm.n_faces) * (64 * 64 + 128 * 128 + 512 + 48 * 64) +
                                   64 * (size_t)hm.n_classes + 64));
   // learned stage: X and Y per macro, then the BF16 copy of the largest network
   o.lrn = take(sizeof(float) * (2 * (size_t)hm.n_macros * hc.cF + 16) +

@@ -125,12 +125,14 @@ __host__ __device__ __forceinline__ size_t wtix(long long r, long long c, long l
 
 // Launch choices of the batched elimination, picked per macro class and
 // precision by hdg_autotune: tpw = 16-row tiles per workgroup of the
-// trailing update (4 waves), panel_wide = 1024-thread panel factorisation
-// (fewer rows per thread) where 512 threads would also do, lookahead = the
-// next pair's factorisation on a second stream beside the trailing update.
+// trailing update (4 waves); panel = how a block's pivots are found: 0 the
+// one-workgroup register panel (512 threads), 1 the same with 1024 threads
+// (fewer rows per thread), 2 tournament pivoting over groups of 256 rows;
+// lookahead = the next pair's factorisation on a second stream beside the
+// trailing update.
 struct LuTune {
   int tpw = 32;
-  int panel_wide = 0;
+  int panel = 2;
   int lookahead = 0;
   int bf16_update = 0;  // FP32 storage: trailing update with BF16 operands, FP32 accumulation
 };

@@ -362,6 +362,259 @@ __global__ void __launch_bounds__(NT) k_panel(LuArgs<T> a, int j0, int jb, int l
   }
 }
 
+// ---- tournament pivoting of one block ------------------------------------
+// Communication-avoiding choice of the block's pivot rows: every workgroup
+// factors up to TR rows of the block with partial pivoting (rows stay with
+// their thread, the chosen ones are marked) and hands on the rows it chose;
+// the chosen rows of up to TSETS groups meet again in the next round until
+// one group is left.  That group's pivot order is the block's row order; its
+// rows, factored once more in that order (no pivoting: the same arithmetic),
+// give L11 \ U11.  The last round also moves the rows (the block, and the L
+// columns from lcol0 of the previous block) and records ipiv and the net
+// permutation as k_panel does.  The rows below the block then get
+// L21 = A21 U11^{-1} from k_uinv + k_gemm, as the non-pivot rows always do.
+constexpr int TR = 256;                 // rows per tournament group (one per thread)
+constexpr int TSETS = TR / NB;          // candidate sets that meet in one group
+constexpr int TMAXG = 12 * 1024 / TR;   // first-round groups for up to 12288 pivot rows
+constexpr int TMOVE = 48;               // moved values per thread in the last round
+
+template <class T>
+__device__ __forceinline__ T piv_mag(T x) {  // |x| with NaN read as 0 (a row is always chosen)
+  const T m = fabs(x);
+  return (m >= T(0)) ? m : T(0);
+}
+
+// The block's columns of the thread's row in v[0 .. NB) (window shifted by 8
+// columns per sub-panel); steps of partial pivoting over the rows with
+// active = true.  chosen[j] receives the row picked at step j (or -1), the
+// picked rows turn inactive.  With `track`, *bmin receives the smallest pivot
+// magnitude (for the singularity flag).
+template <class T>
+__device__ __forceinline__ void tslu_steps(T (&v)[NB], int row, bool& active, int jb, T* s_bv, int* s_bi, T* s_urow,
+                                           int* chosen, T* bmin) {
+  const int tid = threadIdx.x;
+  for (int c0 = 0; c0 < jb; c0 += 8) {
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      if (c0 + cc < jb) {  // uniform
+        T bv = active ? piv_mag<T>(v[cc]) : T(-1);
+        int bi = active ? row : 0x7fffffff;
+        for (int off = 32; off > 0; off >>= 1) {
+          const T ov = __shfl_xor(bv, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          argmax_update<T>(bv, bi, ov, oi);
+        }
+        if ((tid & 63) == 0) { s_bv[tid >> 6] = bv; s_bi[tid >> 6] = bi; }
+        __syncthreads();
+        T b = s_bv[0];
+        int w = s_bi[0];
+#pragma unroll
+        for (int q = 1; q < TR / 64; ++q) argmax_update<T>(b, w, s_bv[q], s_bi[q]);
+        const bool mine = active && row == w;
+        if (mine) {
+          active = false;
+#pragma unroll
+          for (int k = 0; k < NB; ++k) s_urow[k] = v[k];
+        }
+        if (tid == 0) {
+          chosen[c0 + cc] = (b >= T(0)) ? w : -1;
+          if (bmin && b < *bmin) *bmin = b;
+        }
+        __syncthreads();
+        if (active) {
+          const T piv = s_urow[cc];
+          const T ipv = (piv != T(0)) ? T(1) / piv : T(0);
+          const T l = v[cc] * ipv;
+          v[cc] = l;
+#pragma unroll
+          for (int k = cc + 1; k < NB; ++k) v[k] -= l * s_urow[k];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NB - 8; ++k) v[k] = v[k + 8];
+#pragma unroll
+    for (int k = NB - 8; k < NB; ++k) v[k] = T(0);
+  }
+}
+
+// One round of the tournament: group g of matrix blockIdx.y takes the rows
+// [j0 + g TR, j0 + (g + 1) TR) below n_piv (cand_in == null) or the candidate
+// sets [g TSETS, (g + 1) TSETS) of cand_in (n_in sets, -1 = no row) and
+// writes the rows it chose to set g of cand_out.
+template <class T>
+__global__ void __launch_bounds__(TR) k_tslu_round(LuArgs<T> a, int j0, int jb, const int* __restrict__ cand_in,
+                                                   int n_in, int* __restrict__ cand_out) {
+  const int tid = threadIdx.x, g = blockIdx.x, mat = blockIdx.y;
+  const T* W = a.W + (size_t)mat * a.mat_stride;
+  const int ld = a.ld;
+  __shared__ T s_bv[TR / 64];
+  __shared__ int s_bi[TR / 64];
+  __shared__ T s_urow[NB];
+  __shared__ int s_win[NB];
+  int row;
+  if (cand_in == nullptr) {
+    row = j0 + g * TR + tid;
+    if (row >= a.n_piv) row = -1;
+  } else {
+    const int set = g * TSETS + tid / NB, i = tid % NB;
+    row = (set < n_in && i < jb) ? cand_in[((size_t)mat * TMAXG + set) * NB + i] : -1;
+  }
+  T v[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) v[k] = (row >= 0 && k < jb) ? W[wtix(row, j0 + k, ld)] : T(0);
+  bool active = row >= 0;
+  tslu_steps<T>(v, row, active, jb, s_bv, s_bi, s_urow, s_win, nullptr);
+  if (tid < NB) cand_out[((size_t)mat * TMAXG + g) * NB + tid] = tid < jb ? s_win[tid] : -1;
+}
+
+// Last round (one group per matrix): the pivot order, L11 \ U11 of the chosen
+// rows, the row moves, ipiv (LAPACK sequential-swap form) and the net
+// permutation of the block.
+template <class T>
+__global__ void __launch_bounds__(TR) k_tslu_final(LuArgs<T> a, int j0, int jb, int lcol0,
+                                                   const int* __restrict__ cand_in, int n_in) {
+  const int tid = threadIdx.x, mat = blockIdx.x;
+  T* W = a.W + (size_t)mat * a.mat_stride;
+  int* ipiv = a.ipiv + (size_t)mat * a.ipiv_stride;
+  const int ld = a.ld;
+  __shared__ T s_bv[TR / 64];
+  __shared__ int s_bi[TR / 64];
+  __shared__ T s_urow[NB];
+  __shared__ int s_win[NB];
+  __shared__ T s_bmin;
+  __shared__ T s_top[NB * NB];        // L11 \ U11, row j = the row chosen at step j
+  __shared__ int s_pos[2 * NB], s_cont[2 * NB];
+  __shared__ int s_n;
+  int row;
+  if (cand_in == nullptr) {
+    row = j0 + tid;
+    if (row >= a.n_piv || tid >= TR) row = -1;
+  } else {
+    const int set = tid / NB, i = tid % NB;
+    row = (set < n_in && i < jb) ? cand_in[((size_t)mat * TMAXG + set) * NB + i] : -1;
+  }
+  if (tid == 0) s_bmin = T(1);
+  T v[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) v[k] = (row >= 0 && k < jb) ? W[wtix(row, j0 + k, ld)] : T(0);
+  bool active = row >= 0;
+  __syncthreads();
+  tslu_steps<T>(v, row, active, jb, s_bv, s_bi, s_urow, s_win, &s_bmin);
+  if (tid == 0 && !(s_bmin > T(0)) && a.status) atomicCAS(a.status, 0, mat + 1);
+  // the chosen rows again, in pivot order, without pivoting: row j on thread j
+  const int prow = tid < jb ? s_win[tid] : -1;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) v[k] = (prow >= 0 && k < jb) ? W[wtix(prow, j0 + k, ld)] : T(0);
+  for (int c0 = 0; c0 < jb; c0 += 8) {
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      const int j = c0 + cc;
+      if (j < jb) {
+        if (tid == j) {
+#pragma unroll
+          for (int k = 0; k < NB; ++k) s_urow[k] = v[k];
+        }
+        __syncthreads();
+        if (tid > j && tid < jb) {
+          const T piv = s_urow[cc];
+          const T ipv = (piv != T(0)) ? T(1) / piv : T(0);
+          const T l = v[cc] * ipv;
+          v[cc] = l;
+#pragma unroll
+          for (int k = cc + 1; k < NB; ++k) v[k] -= l * s_urow[k];
+        }
+        __syncthreads();
+      }
+    }
+    if (tid < jb) {
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc)
+        if (c0 + cc < jb) s_top[tid * NB + c0 + cc] = v[cc];
+    }
+#pragma unroll
+    for (int k = 0; k < NB - 8; ++k) v[k] = v[k + 8];
+#pragma unroll
+    for (int k = NB - 8; k < NB; ++k) v[k] = T(0);
+  }
+  // sequential swaps: position j0 + j takes the row chosen at step j from
+  // where it is now (wave 0 searches the touched positions in parallel)
+  if (tid < 64) {
+    for (int i = tid; i < 2 * NB; i += 64) { s_pos[i] = j0 + i; s_cont[i] = j0 + i; }
+    int n = jb;
+    for (int j = 0; j < jb; ++j) {
+      const int pb = s_win[j];
+      int t = -1;
+      for (int i = tid; i < n; i += 64)
+        if (s_cont[i] == pb) t = i;
+      // at most one lane holds the row
+      for (int off = 32; off > 0; off >>= 1) t = max(t, __shfl_xor(t, off, 64));
+      if (t < 0) {  // untouched row below the block: add its position
+        t = n;
+        if (tid == 0) { s_pos[n] = pb; s_cont[n] = pb; }
+        ++n;
+      }
+      if (tid == 0) {
+        ipiv[j0 + j] = s_pos[t];
+        const int x = s_cont[j];
+        s_cont[j] = s_cont[t];
+        s_cont[t] = x;
+      }
+      // lane 0's LDS writes reach the wave before the next search
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (tid == 0) s_n = n;
+  }
+  __syncthreads();
+  const int n = s_n;
+  // net permutation for the strips to the right (k_u12, k_u12lin)
+  if (tid == 0) {
+    int* pm = perm_slot(a, mat, j0);
+    int nout = 0;
+    for (int i = 0; i < NB; ++i) pm[i] = i < jb ? s_cont[i] : j0 + i;
+    for (int t = jb; t < n; ++t)
+      if (s_pos[t] != s_cont[t]) { pm[NB + nout] = s_pos[t]; pm[2 * NB + nout] = s_cont[t]; ++nout; }
+    pm[3 * NB] = nout;
+  }
+  // row moves in columns [lcol0, j0 + jb): positions j0 .. j0 + jb - 1 take the
+  // chosen rows (columns left of the block moved, block columns from s_top),
+  // positions t >= jb of the list take the rows displaced from the top (all
+  // columns); every old value is read before any is written
+  const int nl = j0 - lcol0, nw = j0 + jb - lcol0;
+  const int n_top = jb * nl, n_all = n_top + (n - jb) * nw;
+  T buf[TMOVE];
+#pragma unroll
+  for (int i = 0; i < TMOVE; ++i) {
+    const int x = tid + i * TR;
+    buf[i] = T(0);
+    if (x < n_top) {
+      const int m = x / nl, col = lcol0 + x % nl;
+      if (s_cont[m] != j0 + m) buf[i] = W[wtix(s_cont[m], col, ld)];
+    } else if (x < n_all) {
+      const int y = x - n_top, t = jb + y / nw, col = lcol0 + y % nw;
+      if (s_pos[t] != s_cont[t]) buf[i] = W[wtix(s_cont[t], col, ld)];
+    }
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // every load has returned before any store below
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < TMOVE; ++i) {
+    const int x = tid + i * TR;
+    if (x < n_top) {
+      const int m = x / nl, col = lcol0 + x % nl;
+      if (s_cont[m] != j0 + m) W[wtix(j0 + m, col, ld)] = buf[i];
+    } else if (x < n_all) {
+      const int y = x - n_top, t = jb + y / nw, col = lcol0 + y % nw;
+      if (s_pos[t] != s_cont[t]) W[wtix(s_pos[t], col, ld)] = buf[i];
+    }
+  }
+  for (int x = tid; x < jb * jb; x += TR) {
+    const int r = x / jb, col = x % jb;
+    W[wtix(j0 + r, j0 + col, ld)] = s_top[r * NB + col];
+  }
+}
+
 // U11^{-1} of the block (identity-padded to NB x NB) into Uinv[mat]: one
 // thread per column, backward substitution in LDS.
 template <class T>
@@ -754,6 +1007,8 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
   int* perm = reinterpret_cast<int*>(scratch + (size_t)batch * NB * NB);
   T* Linv = reinterpret_cast<T*>(
       (reinterpret_cast<uintptr_t>(perm + (size_t)batch * 2 * PERM_STRIDE) + 255) & ~uintptr_t(255));
+  int* cand0 = reinterpret_cast<int*>(Linv + (size_t)batch * 4 * NB * NB);  // tournament candidates, two rounds
+  int* cand1 = cand0 + (size_t)batch * TMAXG * NB;
   LuArgs<T> a{W, mat_stride, ld, n_piv, n_rows, n_cols, ipiv, ipiv_stride, status, perm};
   if (ld % NC != 0) return hipErrorInvalidValue;
   const int rpt = (n_piv + PANEL_THREADS - 1) / PANEL_THREADS;
@@ -765,10 +1020,29 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
   // one-dimensional update grids: at most 2^32 - 1 work-items
   if ((long long)(ld / NC) * ((n_rows + 16 * TPW - 1) / (16 * TPW)) * batch * 256 > 0xffffffffLL)
     return hipErrorInvalidValue;
+  const bool tour = tune.panel == 2;
   auto panel = [&](hipStream_t q, int j0, int jb, int lcol0) {
-    if (tune.panel_wide && rpt <= 1)
+    if (tour) {
+      const int g0 = (n_piv - j0 + TR - 1) / TR;
+      if (g0 == 1) {
+        hipLaunchKernelGGL(k_tslu_final<T>, dim3(batch), dim3(TR), 0, q, a, j0, jb, lcol0, nullptr, 0);
+        return;
+      }
+      hipLaunchKernelGGL(k_tslu_round<T>, dim3(g0, batch), dim3(TR), 0, q, a, j0, jb, nullptr, 0, cand0);
+      int n = g0;
+      int *in = cand0, *out = cand1;
+      while (n > TSETS) {
+        const int ng = (n + TSETS - 1) / TSETS;
+        hipLaunchKernelGGL(k_tslu_round<T>, dim3(ng, batch), dim3(TR), 0, q, a, j0, jb, in, n, out);
+        n = ng;
+        std::swap(in, out);
+      }
+      hipLaunchKernelGGL(k_tslu_final<T>, dim3(batch), dim3(TR), 0, q, a, j0, jb, lcol0, in, n);
+      return;
+    }
+    if (tune.panel == 1 && rpt <= 1)
       hipLaunchKernelGGL((k_panel<T, 1, 1024>), dim3(batch), dim3(1024), 0, q, a, j0, jb, lcol0);
-    else if (tune.panel_wide && rpt <= 4)
+    else if (tune.panel == 1 && rpt <= 4)
       hipLaunchKernelGGL((k_panel<T, 2, 1024>), dim3(batch), dim3(1024), 0, q, a, j0, jb, lcol0);
     else if (rpt <= 1) hipLaunchKernelGGL((k_panel<T, 1, 512>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
     else if (rpt <= 2) hipLaunchKernelGGL((k_panel<T, 2, 512>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
@@ -777,19 +1051,22 @@ hipError_t lu_eliminate(hipStream_t s, T* W, int batch, long long mat_stride, in
     // or (wide) 1024 threads with 4 rows (FP64 with 8-column sub-panels: a
     // 16-column FP64 sub-panel of 4 rows does not fit the register budget of
     // 1024 threads)
-    else if (n_piv <= 4 * 1024 && tune.panel_wide && sizeof(T) == 4)
+    else if (n_piv <= 4 * 1024 && tune.panel == 1 && sizeof(T) == 4)
       hipLaunchKernelGGL((k_panel<T, 4, 1024>), dim3(batch), dim3(1024), 0, q, a, j0, jb, lcol0);
-    else if (n_piv <= 4 * 1024 && tune.panel_wide)
+    else if (n_piv <= 4 * 1024 && tune.panel == 1)
       hipLaunchKernelGGL((k_panel<T, 4, 1024, 8>), dim3(batch), dim3(1024), 0, q, a, j0, jb, lcol0);
     else if (n_piv <= 4 * 1024)
       hipLaunchKernelGGL((k_panel<T, 8, 512, 8>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
     else hipLaunchKernelGGL((k_panel<T, 24, 512, 4>), dim3(batch), dim3(512), 0, q, a, j0, jb, lcol0);
   };
-  auto drows = [&](hipStream_t q, int j0, int jb) {  // L of the non-pivot rows: A_D,block U11^{-1}
-    if (n_rows <= n_piv) return;
+  // L of the rows below the pivot rows, A_block U11^{-1}: the non-pivot rows
+  // (D), and with the tournament all rows below the block
+  auto drows = [&](hipStream_t q, int j0, int jb) {
+    const int r0 = tour ? j0 + jb : n_piv;
+    if (n_rows <= r0) return;
     hipLaunchKernelGGL(k_uinv<T>, dim3(batch), dim3(NB), 0, q, a, j0, jb, scratch);
-    const int ntile = (n_rows - n_piv + 15) / 16, ny = (ntile + TPW - 1) / TPW;
-    GemmArgs<T> g{W, mat_stride, ld, scratch, (long long)NB * NB, NB, 0, 0, j0, jb, j0, j0, j0 + jb, n_piv, n_rows,
+    const int ntile = (n_rows - r0 + 15) / 16, ny = (ntile + TPW - 1) / TPW;
+    GemmArgs<T> g{W, mat_stride, ld, scratch, (long long)NB * NB, NB, 0, 0, j0, jb, j0, j0, j0 + jb, r0, n_rows,
                   T(1), 0, TPW, 1, ny};
     hipLaunchKernelGGL((k_gemm<T, 64>), dim3((unsigned)(ny * batch)), dim3(256), 0, q, g);
   };
@@ -878,7 +1155,7 @@ template hipError_t lu_eliminate<float>(hipStream_t, float*, int, long long, int
 // Elimination scratch of one class: Uinv, permutations and Linv for `batch`
 // matrices, in doubles (with room for the 256-byte alignment of Linv).
 static size_t class_scratch_doubles(int batch) {
-  return (size_t)batch * (NB * NB + 4 * NB * NB + (2 * PERM_STRIDE + 1) / 2) + 64;
+  return (size_t)batch * (NB * NB + 4 * NB * NB + (2 * PERM_STRIDE + 1) / 2 + TMAXG * NB) + 64;
 }
 
 // One batched elimination per macro class of chunk j (the chunk's matrices

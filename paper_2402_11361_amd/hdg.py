@@ -252,14 +252,14 @@ class Context:
         return n.value
 
     def tuning(self, macro_class, prec=HDG_FP64):
-        """(tiles per workgroup, wide panel, look-ahead stream) of a class."""
-        tpw, wide, look = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
-        self._check(self.lib.hdg_get_tuning(self.h, macro_class, prec, ctypes.byref(tpw), ctypes.byref(wide),
+        """(tiles per workgroup, panel kind, look-ahead stream) of a class."""
+        tpw, panel, look = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        self._check(self.lib.hdg_get_tuning(self.h, macro_class, prec, ctypes.byref(tpw), ctypes.byref(panel),
                                             ctypes.byref(look)))
-        return tpw.value, wide.value, look.value
+        return tpw.value, panel.value, look.value
 
-    def set_tuning(self, macro_class, prec, tpw, panel_wide=0, lookahead=0):
-        self._check(self.lib.hdg_set_tuning(self.h, macro_class, prec, tpw, panel_wide, lookahead))
+    def set_tuning(self, macro_class, prec, tpw, panel=0, lookahead=0):
+        self._check(self.lib.hdg_set_tuning(self.h, macro_class, prec, tpw, panel, lookahead))
 
     def bind_workspace(self, ws=None):
         """Allocate (torch) and bind the device workspace."""

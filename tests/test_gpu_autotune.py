@@ -32,7 +32,7 @@ def test_autotune_caches_and_keeps_parity(tmp_path):
     assert len(lines) == ncl
     for k, line in enumerate(lines):
         f = line.split()
-        assert f[2] == "fp64" and int(f[9]) in (8, 16, 32, 64, 128, 256) and int(f[10]) in (0, 1) and int(f[11]) in (0, 1)
+        assert f[2] == "fp64" and int(f[9]) in (8, 16, 32, 64, 128, 256) and int(f[10]) in (0, 1, 2) and int(f[11]) in (0, 1)
         assert ctx.tuning(k, HDG_FP64) == (int(f[9]), int(f[10]), int(f[11]))
     # the cache answers a second call without timing
     assert ctx.autotune(HDG_FP64, cache) == 0
@@ -56,10 +56,11 @@ def test_autotune_caches_and_keeps_parity(tmp_path):
 
 
 @pytest.mark.parametrize("case", [dict(dim=3, n_elem=4, m=2, p=2, periodic=True), CASE])
-@pytest.mark.parametrize("shape", [(16, 1, 1), (64, 0, 1), (8, 1, 0)])
+@pytest.mark.parametrize("shape", [(16, 1, 1), (64, 0, 1), (8, 1, 0), (16, 2, 1), (32, 2, 0)])
 def test_forced_launch_shapes_keep_parity(case, shape):
-    """Every launch shape the autotuner may pick (the look-ahead stream
-    included) gives the oracle's condensed blocks."""
+    """Every launch shape the autotuner may pick (the look-ahead stream and
+    tournament pivoting included) gives the oracle's condensed blocks and
+    recovery."""
     import torch
     from paper_2402_11361_amd.hdg import HDG_FP64
     say(f"[shapes] {shape}")
