@@ -955,12 +955,10 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
   T af[KS];
   v4 acc[NC / 16];
   if constexpr (PIPE) {
-    // C is loaded after A and added after the MFMA chain, so its latency
-    // hides behind the chain (the chain starts from zero)
-    v4 cv[NC / 16];
-    for (int t = wave; t < g.tiles_per_wg; t += NT / 64) {
-      const int r0 = g.r_lo + (tile0 + t) * 16;
-      if (r0 >= g.r_hi) break;
+    // one tile with masks: C is loaded after A and added after the MFMA chain,
+    // so its latency hides behind the chain (the chain starts from zero)
+    auto masked_tile = [&](int r0) {
+      v4 cv[NC / 16];
       load_a(r0, af);
       load_c(r0, cv);
 #pragma unroll
@@ -969,6 +967,54 @@ __device__ __forceinline__ void gemm_body(const GemmArgs<T>& g) {
 #pragma unroll
       for (int ct = 0; ct < NC / 16; ++ct) acc[ct] += cv[ct];
       store_c(r0, acc);
+    };
+    constexpr int WST = NT / 64;  // waves per workgroup: the tile stride of a wave
+    int t = wave;
+    // Whole tiles of an aligned strip (rows from a multiple of 16, all 64
+    // columns live, full K): A of the wave's next tile is loaded before the
+    // MFMA chain of the current one; C comes from the tile's base without
+    // masks at the start of the tile and joins after the chain, with alpha.
+    const bool aligned = g.beta && (g.r_lo & 15) == 0 && cs >= g.c_lo && cs + NC <= g.c_hi && g.K == KB;
+    if (aligned) {
+      auto full = [&](int tt) { return tt < g.tiles_per_wg && g.r_lo + (tile0 + tt) * 16 + 16 <= g.r_hi; };
+      auto load_a_full = [&](int r0, T* dst) {
+        const T* ap = W + wtix(r0 + col, g.ak0 + KS * grp, ld);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) dst[s] = ap[s];
+      };
+      T an[KS];
+      if (full(t)) load_a_full(g.r_lo + (tile0 + t) * 16, an);
+      for (; full(t); t += WST) {
+        const int r0 = g.r_lo + (tile0 + t) * 16;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) af[s] = an[s];
+        // unconditional (the current tile again when there is no next whole
+        // tile), so that the loads stay in this block ahead of the chain
+        load_a_full(full(t + WST) ? r0 + 16 * WST : r0, an);
+        T* cp = W + wtix(r0, cs, ld);  // the 16 x 64 tile, contiguous
+        v4 cv[NC / 16];
+#pragma unroll
+        for (int ct = 0; ct < NC / 16; ++ct)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) cv[ct][i] = cp[Mfma<T>::row(i, grp) * NC + ct * 16 + col];
+        // keep the loads above ahead of the chain (the scheduler would sink
+        // them next to their uses)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ct = 0; ct < NC / 16; ++ct) acc[ct] = v4{T(0), T(0), T(0), T(0)};
+        mma(af, acc);
+#pragma unroll
+        for (int ct = 0; ct < NC / 16; ++ct)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            cp[Mfma<T>::row(i, grp) * NC + ct * 16 + col] = cv[ct][i] + g.alpha * acc[ct][i];
+      }
+    }
+    // the rest (all tiles when not aligned, else a last partial tile)
+    for (; t < g.tiles_per_wg; t += WST) {
+      const int r0 = g.r_lo + (tile0 + t) * 16;
+      if (r0 >= g.r_hi) break;
+      masked_tile(r0);
     }
   } else {
     for (int t = wave; t < g.tiles_per_wg; t += NT / 64) {
