@@ -712,48 +712,81 @@ __global__ void __launch_bounds__(256) k_u12(LuArgs<T> a, int j0, int jb, int st
 // 64-column blocks b1 = [j0, j0 + 64), b2 = [j0 + 64, j0 + 64 + jb2):
 //   L = [[L11, 0], [L21, L22]],  L^{-1} = [[L11^{-1}, 0], [-L22^{-1} L21 L11^{-1}, L22^{-1}]],
 // identity-padded beyond 64 + jb2, row-major into Linv[mat] (128 x 128).
-// One workgroup per matrix.
+// One workgroup per matrix, two 64 x 64 LDS buffers (66.5 KB, so that it
+// fits on a CU beside one trailing-update workgroup): L11^{-1} by forward
+// substitution, X = L21 L11^{-1}, then -L22^{-1} X and L22^{-1} by forward
+// substitution with L22, one column per thread.
 template <class T>
 __global__ void __launch_bounds__(256) k_linv2(LuArgs<T> a, int j0, int jb2, T* __restrict__ Linv) {
   const int mat = blockIdx.x, tid = threadIdx.x;
   const T* W = a.W + (size_t)mat * a.mat_stride;
   const int ld = a.ld;
-  __shared__ T sL[2][NB][NB + 1];   // L11, L22 (unit lower, strict parts used)
-  __shared__ T sI[2][NB][NB + 1];   // their inverses
+  __shared__ T sA[NB][NB + 1];
+  __shared__ T sB[NB][NB + 1];
+  T* out = Linv + (size_t)mat * 4 * NB * NB;
+  // sA <- strict lower part of L11
   for (int i = tid; i < NB * NB; i += 256) {
     const int r = i / NB, c = i % NB;
-    sL[0][r][c] = (c < r) ? W[wtix(j0 + r, j0 + c, ld)] : T(0);
-    sL[1][r][c] = (c < r && r < jb2) ? W[wtix(j0 + NB + r, j0 + NB + c, ld)] : T(0);
+    sA[r][c] = (c < r) ? W[wtix(j0 + r, j0 + c, ld)] : T(0);
   }
   __syncthreads();
-  if (tid < 2 * NB) {  // forward substitution, one column per thread
-    const int b = tid / NB, j = tid % NB;
+  if (tid < NB) {  // sB <- L11^{-1}, column tid
+    const int j = tid;
     for (int i = 0; i < NB; ++i) {
       T x = (i == j) ? T(1) : T(0);
       if (i > j)
-        for (int k = j; k < i; ++k) x -= sL[b][i][k] * sI[b][k][j];
-      sI[b][i][j] = (i >= j) ? x : T(0);
+        for (int k = j; k < i; ++k) x -= sA[i][k] * sB[k][j];
+      sB[i][j] = (i >= j) ? x : T(0);
     }
   }
   __syncthreads();
-  // sL[0] <- L21 L11^{-1} (rows beyond jb2 are zero)
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e / NB, c = e % NB;
+    out[(size_t)r * 2 * NB + c] = sB[r][c];
+    out[(size_t)r * 2 * NB + NB + c] = T(0);
+  }
+  // sA <- X = L21 L11^{-1} (rows beyond jb2 are zero)
   for (int e = tid; e < NB * NB; e += 256) {
     const int r = e / NB, c = e % NB;
     T s = T(0);
     if (r < jb2)
-      for (int k = c; k < NB; ++k) s += W[wtix(j0 + NB + r, j0 + k, ld)] * sI[0][k][c];
-    sL[0][r][c] = s;
+      for (int k = c; k < NB; ++k) s += W[wtix(j0 + NB + r, j0 + k, ld)] * sB[k][c];
+    sA[r][c] = s;
   }
   __syncthreads();
-  T* out = Linv + (size_t)mat * 4 * NB * NB;
+  // sB <- strict lower part of L22 (zero beyond jb2)
+  for (int i = tid; i < NB * NB; i += 256) {
+    const int r = i / NB, c = i % NB;
+    sB[r][c] = (c < r && r < jb2) ? W[wtix(j0 + NB + r, j0 + NB + c, ld)] : T(0);
+  }
+  __syncthreads();
+  if (tid < NB) {  // sA <- -L22^{-1} X in place, column tid
+    const int j = tid;
+    for (int i = 0; i < NB; ++i) {
+      T x = -sA[i][j];
+      for (int k = 0; k < i; ++k) x -= sB[i][k] * sA[k][j];
+      sA[i][j] = x;
+    }
+  }
+  __syncthreads();
   for (int e = tid; e < NB * NB; e += 256) {
     const int r = e / NB, c = e % NB;
-    T s = T(0);
-    for (int k = 0; k <= r; ++k) s += sI[1][r][k] * sL[0][k][c];
-    out[(size_t)r * 2 * NB + c] = sI[0][r][c];
-    out[(size_t)r * 2 * NB + NB + c] = T(0);
-    out[(size_t)(NB + r) * 2 * NB + c] = -s;
-    out[(size_t)(NB + r) * 2 * NB + NB + c] = sI[1][r][c];
+    out[(size_t)(NB + r) * 2 * NB + c] = sA[r][c];
+  }
+  __syncthreads();
+  if (tid < NB) {  // sA <- L22^{-1}, column tid
+    const int j = tid;
+    for (int i = 0; i < NB; ++i) {
+      T x = (i == j) ? T(1) : T(0);
+      if (i > j)
+        for (int k = j; k < i; ++k) x -= sB[i][k] * sA[k][j];
+      sA[i][j] = (i >= j) ? x : T(0);
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e / NB, c = e % NB;
+    out[(size_t)(NB + r) * 2 * NB + NB + c] = sA[r][c];
   }
 }
 
