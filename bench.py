@@ -38,7 +38,7 @@ PEAK_HBM_GBS = 8000.0
 # read for a 1 GiB device copy in the same run
 # (profiles/newton_step_tgv48_m4_p2_fp64.md), valid only while the kernel
 # sources hash to `sha`.
-CONDENSE_TRAFFIC = {"sha": "3c38d1927ff50f82", "tgv48_m4_p2": 28.23e12}
+CONDENSE_TRAFFIC = {"sha": "b8b5f29f55ccbac0", "tgv48_m4_p2": 21.48e12}
 CONDENSE_SOURCES = ("k_form.hip", "k_lu.hip")
 
 
@@ -229,6 +229,56 @@ def first_layer_variant(args, dev_fn, variants):
         ms_second_layer=round(ms2, 1), ms_first_layer=round(ms1, 1), ratio=round(ms1 / ms2, 2),
         pivot_order=dict(second=nu, first=4 * nu), ahat_rel_diff=diff, tuning=list(ctx.tuning(0, HDG_FP64)),
         nb=nb)
+    ctx.close()
+
+
+def nested_variant(args, dev_fn, variants):
+    """Nested hybridisation inside a macro (third condensation layer) on the
+    24^3 Taylor-Green workload at p = 2: every element hybridised on its own
+    (one element per macro, 13824 elements), element-level condensation,
+    then blocks of 3^3 elements whose internal-face traces (2430 per block)
+    are eliminated.  Times per step and the skeleton size, next to the C0
+    macro-element method on 3^3-element macros of the same mesh."""
+    import torch
+    from paper_2402_11361_amd import inputs
+    from paper_2402_11361_amd.hdg import HDG_FP64, Context, mesh_spec_box
+    cfg = dict(inputs.CONFIGS["tgv24_m3_p2"])
+    cfg["m"] = 1
+    spec = mesh_spec_box(3, cfg["n_elem"], 1, cfg["p"], cfg["lo"], cfg["hi"], True)
+    stream = torch.cuda.current_stream()
+    ctx = Context.from_mesh_spec(spec, Re=cfg["Re"], Mach=cfg["mach"], stream=stream.cuda_stream)
+    ctx.bind_workspace()
+    u0, q0, uh0 = workload_arrays(ctx, cfg)
+    dii = 1.0 / 0.435866521508459
+    dt = inputs.cfl_dt(cfg)
+    u = dev_fn(u0)
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    M = 3
+    nb, nI, nB = ctx.nested_dims(M)
+    Ag = torch.zeros(nb * nB * nB, dtype=torch.float64, device="cuda")
+    bg = torch.zeros(nb * nB, dtype=torch.float64, device="cuda")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    ms_lin = timed(lambda: ctx.linearize_stage(dev_fn(q0), u, dev_fn(uh0), -dii * u, dt, dii, norms=False), 2)
+    ms_el = timed(lambda: ctx.condense(bhat, HDG_FP64), 2)
+    ms_nest = timed(lambda: ctx.condense_nested(M, Ag, bg), 2)
+    print(f"[bench] nested: linearise {ms_lin:.1f} ms, element condensation {ms_el:.1f} ms, "
+          f"block condensation {ms_nest:.1f} ms", file=sys.stderr, flush=True)
+    n_skel_elem = ctx.n_glob - nb * nI
+    variants["nested_hdg_in_macro_fp64"] = dict(
+        workload="24^3 periodic Taylor-Green, p=2, every element hybridised (13824 elements), blocks of 3^3 "
+                 "elements (512) whose internal-face traces are eliminated",
+        ms_linearize=round(ms_lin, 1), ms_element_condense=round(ms_el, 1), ms_block_condense=round(ms_nest, 1),
+        element_trace_unknowns=ctx.n_glob, internal_per_block=nI, boundary_per_block=nB,
+        skeleton_unknowns=n_skel_elem, blocks=nb)
     ctx.close()
 
 
@@ -712,6 +762,8 @@ def main():
                     help="time only the uneven-macro 32^3 variant (profiling); prints its JSON")
     ap.add_argument("--set-tuning", default=None, metavar="TPW,WIDE,LOOK",
                     help="fixed elimination launch shape for every class instead of the autotuner (profiling)")
+    ap.add_argument("--nested", action="store_true",
+                    help="also time the nested (third-layer) condensation on the 24^3 workload")
     ap.add_argument("--first-layer", action="store_true",
                     help="also time the standard (first-layer) condensation against the second layer at 24^3")
     ap.add_argument("--tgv-eps", type=float, default=0.0, metavar="T_END",
@@ -885,6 +937,9 @@ def main():
         gc.collect(); torch.cuda.empty_cache()
     if args.learned_p3:
         learned_p3_variant(args, dev, variants)
+        gc.collect(); torch.cuda.empty_cache()
+    if args.nested:
+        nested_variant(args, dev, variants)
         gc.collect(); torch.cuda.empty_cache()
     if args.first_layer:
         first_layer_variant(args, dev, variants)

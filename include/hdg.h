@@ -278,6 +278,41 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat);
  * pivot. */
 hdg_status hdg_condense_first_layer(hdg_ctx ctx, double* bhat);
 
+/* Nested hybridisation inside a macro: a third static-condensation layer,
+ * the alternative local structure in which every element is hybridised on
+ * its own (u, q discontinuous between elements, a trace on every element
+ * face; the paper's Sec. 2.2 patches instead keep u, q continuous inside a
+ * macro).  On a mesh of one element per macro (all macros of one shape,
+ * m = 1 on every axis), the elements are grouped into blocks of block_m
+ * elements per axis (block (g0, g1[, g2]) = g0 + n0 (g1 + n1 g2), element
+ * s belongs to block s_k / block_m per axis).  Each block assembles the
+ * element blocks A-hat^{T_e}, b-hat^{T_e} of the last FP64 hdg_condense
+ * (eq. C44 pieces) over the faces of its elements and eliminates the traces
+ * of the faces inside the block, as eq. ASC2 eliminates u:
+ *   A-hat^G = A_BB - A_BI A_II^{-1} A_IB,  b-hat^G = b_B - A_BI A_II^{-1} b_I,
+ * which leaves a system on the block skeleton (faces between blocks and on
+ * the domain boundary), assembled like eq. C44.  Block-local trace order:
+ * the block's internal faces in increasing face id, then its boundary faces
+ * likewise, each face's unknowns in their global order (hdg_face_offsets).
+ *
+ * hdg_nested_dims: number of blocks and, per block, the internal-face and
+ * boundary-face trace unknowns (host pointers, each may be NULL).
+ * hdg_condense_nested: ahat (device, n_blocks x n_B x n_B row-major) and bhat
+ * (device, n_blocks x n_B) receive A-hat^G and b-hat^G on each block's
+ * boundary faces; synchronises.  Needs a bound workspace and an FP64
+ * hdg_condense of the current linearisation (HDG_EINVAL otherwise; a later
+ * linearisation, autotune or first-layer condensation invalidates it).
+ * HDG_EINVAL when the element count of an axis is not a multiple of
+ * block_m; HDG_EUNSUPPORTED for other meshes (several macro shapes, m > 1,
+ * a periodic axis of one element, blocks of unequal face counts, more than
+ * 12288 internal-face unknowns per block); HDG_ENOMEM when its buffers do
+ * not fit; HDG_ESINGULAR on a zero pivot of A_II.  The block structure and
+ * its device buffers (n_blocks tiled matrices of order n_I + n_B) are
+ * allocated on the first call for a block size and kept until the block
+ * size changes or hdg_destroy. */
+hdg_status hdg_nested_dims(hdg_ctx ctx, int block_m, int* n_blocks, int* n_internal, int* n_boundary);
+hdg_status hdg_condense_nested(hdg_ctx ctx, int block_m, double* ahat, double* bhat);
+
 /* Flow diagnostics of the Taylor-Green study (Sec. 5.3, eq. C5321) for the
  * state (q, u) (device, layouts as in hdg_linearize_stage), in the
  * library's units (rho_inf = c_inf = mu = 1, mu_eff = mu / Re_c):

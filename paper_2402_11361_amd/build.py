@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhdg.so")
 SOURCES = ["host_setup.cpp", "capi.cpp", "k_linearize.hip", "k_form.hip", "k_lu.hip", "k_krylov.hip", "k_backsolve.hip",
-           "k_learned.hip", "k_supg.hip", "k_form1.hip", "k_diag.hip"]
+           "k_learned.hip", "k_supg.hip", "k_form1.hip", "k_diag.hip", "k_nested.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-Wno-unused-variable"]

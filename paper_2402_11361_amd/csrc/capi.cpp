@@ -426,6 +426,7 @@ hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk) {
   // the previous binding no longer matches the layout
   c.ws_bound = false;
   c.lrn_bound = false;
+  c.condensed64 = false;
   c.have_a32 = false;
   c.have_a16 = false;
   clear_graphs(c);
@@ -463,6 +464,7 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
   c.have_a32 = false;
   c.have_a16 = false;
   c.linearized = false;
+  c.condensed64 = false;
   return HDG_OK;
 }
 
@@ -581,6 +583,7 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
   // the trials overwrote the condensed matrices
   c.have_a32 = false;
   c.have_a16 = false;
+  c.condensed64 = false;
   return HDG_OK;
 }
 
@@ -620,6 +623,7 @@ hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, co
   StageArgs sa{dt, d_ii, dtau};
   HIPCHK(&c, launch_linearize(c, q, u, uhat, w, sa));
   c.linearized = true;
+  c.condensed64 = false;
   c.have_a32 = false;
   c.have_a16 = false;
   if (norms_host) {
@@ -642,6 +646,7 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
   // BF16 operands with FP32 accumulation
   const int p32 = (prec == HDG_FP32 || prec == HDG_BF16) ? 1 : 0;
   c.bf16_update = (prec == HDG_BF16);
+  c.condensed64 = false;
   // status flags: one per (chunk, macro class), then one for the face blocks
   const int ncl = c.hm.n_classes, nch = c.hm.n_chunks(), nst = nch * ncl;
   int* status = reinterpret_cast<int*>(c.ws.small);
@@ -671,6 +676,47 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
       return fail(&c, HDG_ESINGULAR, "singular Schur complement in macro " + std::to_string(macro));
     }
   if (st[nst]) return fail(&c, HDG_ESINGULAR, "singular face block of A_uhat-uhat " + std::to_string(st[nst] - 1));
+  c.condensed64 = (p32 == 0);
+  return HDG_OK;
+}
+
+static hdg_status nested_get(hdg_ctx ctx, int block_m) {
+  HdgContext& c = ctx->c;
+  if (block_m < 1) return fail(&c, HDG_EINVAL, "block size must be positive");
+  if (c.nested && c.nested_m == block_m) return HDG_OK;
+  c.nested.reset();
+  c.nested_m = 0;
+  std::shared_ptr<NestedPlan> P;
+  const std::string err = nested_plan(c, block_m, P);
+  if (err.empty()) {
+    c.nested = P;
+    c.nested_m = block_m;
+    return HDG_OK;
+  }
+  if (err.find("memory") != std::string::npos) return fail(&c, HDG_ENOMEM, err);
+  if (err.find("multiple") != std::string::npos) return fail(&c, HDG_EINVAL, err);
+  if (err.find("upload") != std::string::npos) return fail(&c, HDG_EDEVICE, err);
+  return fail(&c, HDG_EUNSUPPORTED, err);
+}
+
+hdg_status hdg_nested_dims(hdg_ctx ctx, int block_m, int* n_blocks, int* n_internal, int* n_boundary) {
+  if (!ctx) return HDG_EINVAL;
+  const hdg_status s = nested_get(ctx, block_m);
+  if (s != HDG_OK) return s;
+  nested_dims(*ctx->c.nested, n_blocks, n_internal, n_boundary);
+  return HDG_OK;
+}
+
+hdg_status hdg_condense_nested(hdg_ctx ctx, int block_m, double* ahat, double* bhat) {
+  if (!ctx || !ahat || !bhat) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  if (!c.condensed64) return fail(&c, HDG_EINVAL, "nested condensation needs an FP64 hdg_condense of the current linearisation");
+  const hdg_status s = nested_get(ctx, block_m);
+  if (s != HDG_OK) return s;
+  int singular = 0;
+  HIPCHK(&c, launch_condense_nested(c, *c.nested, ahat, bhat, &singular));
+  if (singular) return fail(&c, HDG_ESINGULAR, "singular internal-face block of nested block " + std::to_string(singular - 1));
   return HDG_OK;
 }
 
@@ -691,6 +737,7 @@ hdg_status hdg_condense_first_layer(hdg_ctx ctx, double* bhat) {
   HIPCHK(&c, launch_bhat(c, bhat, 0));
   HIPCHK(&c, launch_face_precond(c));
   c.cond_prec = 0;
+  c.condensed64 = false;
   c.have_a32 = false;
   c.have_a16 = false;
   HIPCHK(&c, hipMemcpyAsync(ctx->pinned, status, sizeof(int) * (nst + 1), hipMemcpyDeviceToHost, c.stream));
@@ -1092,7 +1139,10 @@ hdg_status hdg_get_formed(hdg_ctx ctx, size_t macro, double* w_host) {
   int j = 0;  // the chunk holding the macro
   while (c.hm.chunk_first[j + 1] <= (int)macro) ++j;
   HIPCHK(&c, launch_form(c, 0, c.hm.chunk_first[j], c.hm.chunk_first[j + 1]));
-  if (!c.hm.chunked()) c.cond_prec = 0;  // W no longer holds the condensed operator
+  if (!c.hm.chunked()) {  // W no longer holds the condensed operator
+    c.cond_prec = 0;
+    c.condensed64 = false;
+  }
   std::vector<double> tiled;
   hdg_status s = copy_tiled_macro(ctx, macro, tiled, 0);
   if (s != HDG_OK) return s;

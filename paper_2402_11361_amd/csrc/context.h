@@ -6,6 +6,8 @@
 #include <map>
 #include <memory>
 
+struct NestedPlan;  // block structure and buffers of the nested (third-layer) condensation, k_nested.hip
+
 struct HostClass {
   int dim, p, nq, ns;
   int m[3], n1[3];
@@ -122,6 +124,9 @@ struct HdgContext {
   bool have_a16 = false;
   bool linearized = false;  // element blocks hold a linearisation
   int cond_prec = 0;
+  bool condensed64 = false;  // the element blocks of the last FP64 hdg_condense are in place
+  std::shared_ptr<NestedPlan> nested;  // nested condensation for one block size (built on first use)
+  int nested_m = 0;                    // its block size
   bool bf16_update = false;  // the last condensation took BF16 operands in its trailing updates
   long long supg_chunk = 0;  // elements per SUPG product batch
   // learned coarse correction
@@ -150,6 +155,11 @@ struct HdgMeshIn {
   const int* seg_len[3];
   int p;
 };
+
+// k_nested.hip
+std::string nested_plan(HdgContext& c, int M, std::shared_ptr<NestedPlan>& out);
+hipError_t launch_condense_nested(HdgContext& c, NestedPlan& P, double* ahat, double* bhat, int* singular);
+void nested_dims(const NestedPlan& P, int* n_blocks, int* n_internal, int* n_boundary);
 
 // host_setup.cpp
 bool build_mesh(const HdgMeshIn& in, HostMesh& hm, std::string& err);

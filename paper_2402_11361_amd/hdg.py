@@ -69,7 +69,8 @@ EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_o
            "hdg_coarse_prolong", "hdg_mlp_param_count", "hdg_mlp_work_floats", "hdg_mlp_forward",
            "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking",
            "hdg_autotune", "hdg_class_count", "hdg_get_tuning", "hdg_set_tuning",
-           "hdg_condense_first_layer", "hdg_flow_diagnostics", "hdg_flow_diagnostics_noalloc"]
+           "hdg_condense_first_layer", "hdg_flow_diagnostics", "hdg_flow_diagnostics_noalloc",
+           "hdg_nested_dims", "hdg_condense_nested"]
 
 _lib = None
 
@@ -98,6 +99,8 @@ def load_library(path=LIB_PATH):
     lib.hdg_linearize_stage.argtypes = [vp, vp, vp, vp, vp, dp, dp, dp, vp]
     lib.hdg_condense.argtypes = [vp, i, vp]
     lib.hdg_condense_first_layer.argtypes = [vp, vp]
+    lib.hdg_nested_dims.argtypes = [vp, i, ip, ip, ip]
+    lib.hdg_condense_nested.argtypes = [vp, i, vp, vp]
     lib.hdg_flow_diagnostics.argtypes = [vp, vp, vp, vp]
     lib.hdg_flow_diagnostics_noalloc.argtypes = [vp, vp, vp, vp]
     lib.hdg_apply_global.argtypes = [vp, vp, vp]
@@ -303,6 +306,21 @@ class Context:
         one macro shape); same A-hat and b-hat as condense()."""
         self._check(self.lib.hdg_condense_first_layer(self.h, _ptr(bhat)))
 
+
+    def nested_dims(self, block_m):
+        """(blocks, internal-face and boundary-face trace unknowns per block) of
+        the nested condensation with blocks of block_m elements per axis."""
+        nb, ni, nbd = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        self._check(self.lib.hdg_nested_dims(self.h, block_m, ctypes.byref(nb), ctypes.byref(ni), ctypes.byref(nbd)))
+        return nb.value, ni.value, nbd.value
+
+    def condense_nested(self, block_m, ahat, bhat):
+        """A-hat^G (n_blocks x n_B x n_B) and b-hat^G (n_blocks x n_B) into
+        the given float64 device tensors."""
+        nb, _, nbd = self.nested_dims(block_m)
+        if ahat.numel() != nb * nbd * nbd or bhat.numel() != nb * nbd:
+            raise ValueError("ahat / bhat sizes do not match hdg_nested_dims")
+        self._check(self.lib.hdg_condense_nested(self.h, block_m, _ptr(ahat), _ptr(bhat)))
     def flow_diagnostics(self, q, u):
         """(E_k, eps, |Omega|): volume-averaged kinetic energy and the
         dissipation rate of eq. C5321 of the state (q, u), library units."""
