@@ -313,6 +313,23 @@ hdg_status hdg_condense_first_layer(hdg_ctx ctx, double* bhat);
 hdg_status hdg_nested_dims(hdg_ctx ctx, int block_m, int* n_blocks, int* n_internal, int* n_boundary);
 hdg_status hdg_condense_nested(hdg_ctx ctx, int block_m, double* ahat, double* bhat);
 
+/* Solve of the nested (block-skeleton) system of the last hdg_condense_nested
+ * with this block size (HDG_EINVAL otherwise): FGMRES as in hdg_fgmres_solve
+ * (sec. 4.2; options o as there, but host-controlled FP64 steps only:
+ * graph_steps, use_learned and harvest_max 0, inner_prec HDG_FP64, else
+ * HDG_EUNSUPPORTED) from a zero start, the inner GMRES preconditioned by the
+ * diagonal of the skeleton operator, applied matrix-free as
+ * sum_G P_G^T A-hat^G P_G (deterministic owner sums).  Then the traces of
+ * every block's internal faces, x_I = A_II^{-1} (b_I - A_IB x_B), from the
+ * factors the elimination left in the block matrices.  x_full (device,
+ * n_glob) receives the whole element-trace increment in the layout of
+ * hdg_face_offsets; hdg_local_backsolve turns it into dq, du as after
+ * hdg_fgmres_solve.  st (host, may be NULL) as for hdg_fgmres_solve.
+ * HDG_ENOCONV when max_outer is reached (x_full then holds the recovery of
+ * the last iterate). */
+hdg_status hdg_nested_solve(hdg_ctx ctx, int block_m, double* x_full, const hdg_krylov_opts* o,
+                            hdg_krylov_stats* st);
+
 /* Flow diagnostics of the Taylor-Green study (Sec. 5.3, eq. C5321) for the
  * state (q, u) (device, layouts as in hdg_linearize_stage), in the
  * library's units (rho_inf = c_inf = mu = 1, mu_eff = mu / Re_c):

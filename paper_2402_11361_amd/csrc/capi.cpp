@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <new>
 #include <sstream>
@@ -59,8 +60,13 @@ struct Krylov {
   int inner_total = 0;
   bool learned = false;  // add the learned coarse correction in precond()
 
-  Krylov(HdgContext& cc, int rs, int in, double* hostbuf, int prec) : c(cc), restart(rs), inner(in), host(hostbuf), inner_prec(prec) {
-    n = c.md.n_glob;
+  // another operator and preconditioner on vectors of length n_op (the nested
+  // block skeleton); default: the condensed trace operator of the context
+  std::function<hipError_t(const double*, double*)> opA, opM;
+
+  Krylov(HdgContext& cc, int rs, int in, double* hostbuf, int prec, long long n_op = 0)
+      : c(cc), restart(rs), inner(in), host(hostbuf), inner_prec(prec) {
+    n = n_op > 0 ? n_op : c.md.n_glob;
     double* k = c.ws.kry;
     V = k; k += (size_t)(restart + 1) * n;
     Z = k; k += (size_t)restart * n;
@@ -100,8 +106,8 @@ struct Krylov {
     }
     return hipSuccess;
   }
-  hipError_t apply_A(const double* x, double* y, int prec) { return launch_apply(c, x, y, prec); }
-  hipError_t apply_M(const double* x, double* y) { return launch_precond_apply(c, x, y); }
+  hipError_t apply_A(const double* x, double* y, int prec) { return opA ? opA(x, y) : launch_apply(c, x, y, prec); }
+  hipError_t apply_M(const double* x, double* y) { return opM ? opM(x, y) : launch_precond_apply(c, x, y); }
 
   // ---- device-resident Arnoldi steps (no host synchronisation) -------------
   // control block: H [(restart+1) x restart], cs, sn [restart], g [restart+1],
@@ -133,7 +139,7 @@ struct Krylov {
   hipError_t precond_dev(const double* v, double* z) {
     hipError_t e;
     if (inner <= 0) {
-      e = launch_precond_apply(c, v, z);
+      e = apply_M(v, z);
     } else {
       if ((e = apply_M(v, Vi)) != hipSuccess) return e;
       if ((e = normalize_dev(Vi, dsc + 1)) != hipSuccess) return e;  // beta of the inner solve
@@ -204,7 +210,7 @@ struct Krylov {
     return launch_learned_correction(c, v, z);
   }
   hipError_t precond_plain(const double* v, double* z) {
-    if (inner <= 0) return launch_precond_apply(c, v, z);
+    if (inner <= 0) return apply_M(v, z);
     hipError_t e = apply_M(v, Vi);
     if (e != hipSuccess) return e;
     double beta;
@@ -717,6 +723,94 @@ hdg_status hdg_condense_nested(hdg_ctx ctx, int block_m, double* ahat, double* b
   int singular = 0;
   HIPCHK(&c, launch_condense_nested(c, *c.nested, ahat, bhat, &singular));
   if (singular) return fail(&c, HDG_ESINGULAR, "singular internal-face block of nested block " + std::to_string(singular - 1));
+  return HDG_OK;
+}
+
+hdg_status hdg_nested_solve(hdg_ctx ctx, int block_m, double* x_full, const hdg_krylov_opts* o,
+                            hdg_krylov_stats* st) {
+  if (!ctx || !x_full || !o) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  if (!c.nested || c.nested_m != block_m || !nested_condensed(*c.nested))
+    return fail(&c, HDG_EINVAL, "hdg_nested_solve needs hdg_condense_nested with the same block size first");
+  if (o->restart < 1 || o->restart > c.kry_restart_max || o->inner_its < 0 || o->inner_its > c.kry_inner_max ||
+      o->max_outer < 1 || !(o->rtol >= 0) || !(o->atol >= 0))
+    return fail(&c, HDG_EINVAL, "bad Krylov options");
+  if (o->use_learned || o->harvest_max || o->graph_steps || o->inner_prec != HDG_FP64)
+    return fail(&c, HDG_EUNSUPPORTED, "the skeleton solve takes FP64 host-controlled steps only");
+  auto t0 = std::chrono::steady_clock::now();
+  NestedPlan& P = *c.nested;
+  const long long n = nested_skeleton_size(P);
+  Krylov K(c, o->restart, o->inner_its, ctx->pinned, 0, n);
+  K.opA = [&](const double* x, double* y) { return launch_nested_apply(c, P, x, y); };
+  K.opM = [&](const double* v, double* z) { return launch_nested_jacobi(c, P, v, z); };
+  const double* b = nested_rhs(P);
+  double* x = nested_xskel(P);
+  HIPCHK(&c, launch_scale_copy(c.stream, n, 0.0, b, x));  // zero start
+  double bnorm, beta;
+  HIPCHK(&c, K.norm(b, bnorm));
+  const double tol = std::max(o->rtol * bnorm, o->atol);
+  HIPCHK(&c, launch_scale_copy(c.stream, n, 1.0, b, K.r));
+  beta = bnorm;
+  const int m = o->restart;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  int its = 0;
+  while (beta > tol && its < o->max_outer) {
+    HIPCHK(&c, launch_scale_copy(c.stream, n, 1.0 / beta, K.r, K.V));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      HIPCHK(&c, K.precond_plain(K.V + (size_t)j * n, K.Z + (size_t)j * n));
+      double* wv = K.V + (size_t)(j + 1) * n;
+      HIPCHK(&c, K.apply_A(K.Z + (size_t)j * n, wv, 0));
+      double h[128];
+      HIPCHK(&c, K.cgs2(K.V, j, wv, h));
+      double hn;
+      HIPCHK(&c, K.norm(wv, hn));
+      for (int i = 0; i < j; ++i) {
+        const double a = h[i], bb = h[i + 1];
+        h[i] = cs[i] * a + sn[i] * bb;
+        h[i + 1] = -sn[i] * a + cs[i] * bb;
+      }
+      const double rr = std::hypot(h[j], hn);
+      cs[j] = rr > 0 ? h[j] / rr : 1.0;
+      sn[j] = rr > 0 ? hn / rr : 0.0;
+      h[j] = rr;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
+      const double g0 = g[j];
+      g[j] = cs[j] * g0;
+      g[j + 1] = -sn[j] * g0;
+      ++its;
+      k = j + 1;
+      if (hn == 0.0 || std::fabs(g[j + 1]) <= tol || its >= o->max_outer) break;
+      HIPCHK(&c, launch_scale_copy(c.stream, n, 1.0 / hn, wv, wv));
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double sum = g[i];
+      for (int j = i + 1; j < k; ++j) sum -= H[(size_t)i * m + j] * y[j];
+      y[i] = H[(size_t)i * m + i] != 0.0 ? sum / H[(size_t)i * m + i] : 0.0;
+    }
+    for (int i = 0; i < k; ++i) ctx->pinned[i] = y[i];
+    HIPCHK(&c, hipMemcpyAsync(K.dev_coef + 256, ctx->pinned, sizeof(double) * k, hipMemcpyHostToDevice, c.stream));
+    HIPCHK(&c, launch_lincomb(c.stream, n, k, K.Z, n, K.dev_coef + 256, x, 1));
+    HIPCHK(&c, K.apply_A(x, K.t, 0));
+    HIPCHK(&c, launch_sub(c.stream, n, b, K.t, K.r));
+    HIPCHK(&c, K.norm(K.r, beta));
+    if (!std::isfinite(beta)) return fail(&c, HDG_ENAN, "non-finite Krylov residual");
+  }
+  HIPCHK(&c, launch_nested_recover(c, P, x, x_full));
+  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  if (st) {
+    st->outer_its = its;
+    st->inner_its_total = K.inner_total;
+    st->res0 = bnorm;
+    st->res_final = beta;
+    st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    st->fallbacks = 0;
+    st->harvested = 0;
+  }
+  if (beta > tol) return fail(&c, HDG_ENOCONV, "FGMRES on the block skeleton reached max_outer");
   return HDG_OK;
 }
 

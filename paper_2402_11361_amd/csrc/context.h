@@ -160,6 +160,13 @@ struct HdgMeshIn {
 std::string nested_plan(HdgContext& c, int M, std::shared_ptr<NestedPlan>& out);
 hipError_t launch_condense_nested(HdgContext& c, NestedPlan& P, double* ahat, double* bhat, int* singular);
 void nested_dims(const NestedPlan& P, int* n_blocks, int* n_internal, int* n_boundary);
+hipError_t launch_nested_apply(HdgContext& c, NestedPlan& P, const double* x, double* y);
+hipError_t launch_nested_jacobi(HdgContext& c, NestedPlan& P, const double* v, double* z);
+hipError_t launch_nested_recover(HdgContext& c, NestedPlan& P, const double* xskel, double* xfull);
+long long nested_skeleton_size(const NestedPlan& P);
+bool nested_condensed(const NestedPlan& P);
+double* nested_rhs(NestedPlan& P);
+double* nested_xskel(NestedPlan& P);
 
 // host_setup.cpp
 bool build_mesh(const HdgMeshIn& in, HostMesh& hm, std::string& err);

@@ -2,8 +2,9 @@
 optional pseudo-transient continuation (paper Sec. 2.4, Sec. 3.1, Algorithm 1).
 
 Host-side control only: every vector update and every solve goes through the
-C ABI (hdg_linearize_stage, hdg_condense, hdg_fgmres_solve,
-hdg_local_backsolve, hdg_axpy); torch provides the device buffers.
+C ABI (hdg_linearize_stage, hdg_condense, hdg_fgmres_solve or the nested
+hdg_condense_nested + hdg_nested_solve, hdg_local_backsolve, hdg_axpy);
+torch provides the device buffers.
 
 Time integrator: Alexander's three-stage L-stable SDIRK, alpha the root in
 (0, 1) of 6a^3 - 18a^2 + 9a - 1, stiffly accurate (c_3 = 1, b = last row of
@@ -41,9 +42,13 @@ class StageDriver:
 
     def __init__(self, ctx, rtol=1e-8, restart=30, inner_its=5, max_outer=300, newton_abs=1e-10, newton_rel=1e-8,
                  max_newton=20, inner_prec=HDG_FP64, condense_prec=HDG_FP64, mark=None, use_learned=False,
-                 graph_steps=0):
+                 graph_steps=0, nested_block=0):
+        """nested_block > 0 (one element per macro, FP64): every Newton step
+        goes through the nested path, hdg_condense_nested with blocks of that
+        many elements per axis and hdg_nested_solve on the block skeleton."""
         import torch
         self.ctx = ctx
+        self.nested_block = int(nested_block)
         # optional callback mark(phase) at phase boundaries ("linearize", "condense",
         # "fgmres", "backsolve"), e.g. to record stream events
         self.mark = mark if mark is not None else (lambda phase: None)
@@ -59,6 +64,7 @@ class StageDriver:
         self.du = torch.zeros(ctx.n_u_tot, **dev)
         self.A, self.b, self.c = alexander_dirk33()
         self.Ainv = np.linalg.inv(self.A)
+        self.nested_A = self.nested_b = None  # the block systems (output of hdg_condense_nested)
 
     def solve_stage(self, q, u, uh, w, dt, dii, ptc=False, tau_init=1.0, tau_max=1e8):
         """Newton iterations on (q, u, uh) in place until ||R_F|| <= max(abs, rel ||R_F^0||)."""
@@ -86,7 +92,17 @@ class StageDriver:
             ctx.condense(self.bhat, self.condense_prec)
             mark("fgmres")
             self.x.zero_()
-            krylov.append(ctx.fgmres_solve(self.bhat, self.x, **self.kry))
+            if self.nested_block > 0:
+                if self.nested_A is None:
+                    nb, _, nB = ctx.nested_dims(self.nested_block)
+                    self.nested_A = self.t.empty(nb * nB * nB, dtype=self.t.float64, device="cuda")
+                    self.nested_b = self.t.empty(nb * nB, dtype=self.t.float64, device="cuda")
+                ctx.condense_nested(self.nested_block, self.nested_A, self.nested_b)
+                krylov.append(ctx.nested_solve(self.nested_block, self.x, rtol=self.kry["rtol"],
+                                               restart=self.kry["restart"], max_outer=self.kry["max_outer"],
+                                               inner_its=self.kry["inner_its"]))
+            else:
+                krylov.append(ctx.fgmres_solve(self.bhat, self.x, **self.kry))
             mark("backsolve")
             ctx.local_backsolve(self.x, self.dq, self.du)
             ctx.axpy(1.0, self.dq, q)

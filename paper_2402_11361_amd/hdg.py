@@ -70,7 +70,7 @@ EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_o
            "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking",
            "hdg_autotune", "hdg_class_count", "hdg_get_tuning", "hdg_set_tuning",
            "hdg_condense_first_layer", "hdg_flow_diagnostics", "hdg_flow_diagnostics_noalloc",
-           "hdg_nested_dims", "hdg_condense_nested"]
+           "hdg_nested_dims", "hdg_condense_nested", "hdg_nested_solve"]
 
 _lib = None
 
@@ -101,6 +101,7 @@ def load_library(path=LIB_PATH):
     lib.hdg_condense_first_layer.argtypes = [vp, vp]
     lib.hdg_nested_dims.argtypes = [vp, i, ip, ip, ip]
     lib.hdg_condense_nested.argtypes = [vp, i, vp, vp]
+    lib.hdg_nested_solve.argtypes = [vp, i, vp, ctypes.POINTER(KrylovOpts), ctypes.POINTER(KrylovStats)]
     lib.hdg_flow_diagnostics.argtypes = [vp, vp, vp, vp]
     lib.hdg_flow_diagnostics_noalloc.argtypes = [vp, vp, vp, vp]
     lib.hdg_apply_global.argtypes = [vp, vp, vp]
@@ -321,6 +322,20 @@ class Context:
         if ahat.numel() != nb * nbd * nbd or bhat.numel() != nb * nbd:
             raise ValueError("ahat / bhat sizes do not match hdg_nested_dims")
         self._check(self.lib.hdg_condense_nested(self.h, block_m, _ptr(ahat), _ptr(bhat)))
+
+    def nested_solve(self, block_m, x_full, rtol=1e-8, atol=0.0, restart=30, max_outer=300, inner_its=5,
+                     allow_noconv=False):
+        """FGMRES on the block skeleton of the last condense_nested, then the
+        internal-face traces: the whole element-trace increment in x_full."""
+        if x_full.numel() != self.n_glob:
+            raise ValueError("x_full must hold n_glob values")
+        o = KrylovOpts(rtol, atol, restart, max_outer, inner_its, HDG_FP64, 0, 0, None, 0, 0)
+        st = KrylovStats()
+        code = self.lib.hdg_nested_solve(self.h, block_m, _ptr(x_full), ctypes.byref(o), ctypes.byref(st))
+        if not (allow_noconv and code == 5):
+            self._check(code)
+        return dict(outer_its=st.outer_its, inner_its=st.inner_its_total, res0=st.res0, res=st.res_final,
+                    ms=st.ms, converged=(code == 0))
     def flow_diagnostics(self, q, u):
         """(E_k, eps, |Omega|): volume-averaged kinetic energy and the
         dissipation rate of eq. C5321 of the state (q, u), library units."""

@@ -60,6 +60,18 @@ def test_nested_blocks_match_oracle(name):
     x_ref = S.solve_direct(A, b)
     skel = np.concatenate([S.mesh.face_offset[f] + np.arange(S.mesh.face_ndof[f]) for f in B.skeleton])
     assert _rel(xs, x_ref[skel]) < 1e-9
+    # the skeleton solve and the recovery of the internal traces on the GPU
+    x = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    info = ctx.nested_solve(M, x, rtol=1e-13, restart=30, max_outer=400, inner_its=5)
+    ex = _rel(x.cpu().numpy(), x_ref)
+    dq = torch.zeros(ctx.n_q_tot, dtype=torch.float64, device="cuda")
+    du = torch.zeros(ctx.n_u_tot, dtype=torch.float64, device="cuda")
+    ctx.local_backsolve(x, dq, du)
+    dq_o, du_o = S.backsolve(lin, cond, x_ref)
+    eu, eq = _rel(du.cpu().numpy(), du_o), _rel(dq.cpu().numpy(), dq_o)
+    say(f"[nested] {name}: skeleton FGMRES {info['outer_its']} outer / {info['inner_its']} inner, "
+        f"traces {ex:.2e}, dU {eu:.2e}, dQ {eq:.2e}")
+    assert info["converged"] and ex < 1e-10 and eu < 1e-10 and eq < 1e-10
     # a second call with the same block size reuses the plan
     ctx.condense_nested(M, torch.zeros(nb * nB * nB, dtype=torch.float64, device="cuda"),
                         torch.zeros(nb * nB, dtype=torch.float64, device="cuda"))
@@ -76,6 +88,8 @@ def test_nested_needs_condensation_and_a_fitting_mesh():
     with pytest.raises(HdgError, match="EINVAL"):
         ctx.condense_nested(2, Ag, bg)  # no condensation yet
     with pytest.raises(HdgError, match="EINVAL"):
+        ctx.nested_solve(2, torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda"))  # no nested condensation
+    with pytest.raises(HdgError, match="EINVAL"):
         ctx.nested_dims(3)  # 4 elements per axis
     d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
     ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
@@ -89,3 +103,28 @@ def test_nested_needs_condensation_and_a_fitting_mesh():
     with pytest.raises(HdgError, match="EUNSUPPORTED"):
         ctx2.nested_dims(1)  # macros of two elements per axis
     ctx2.close()
+
+
+def test_dirk_step_through_the_nested_path_matches_oracle():
+    """One DIRK(3,3) step whose Newton steps all go through the nested path
+    (element condensation, block condensation, skeleton FGMRES, internal
+    traces, element recovery) against the oracle's time step, which solves
+    the element system directly: the nested path is an exact reformulation."""
+    from oracle.newton import dirk_step
+    from paper_2402_11361_amd.driver import StageDriver
+    case = dict(dim=2, n_elem=4, m=1, p=2, periodic=True, mach=0.1, Re=100.0)
+    say(f"[nested driver] {case}")
+    S, inp, ctx = make_pair(case)
+    drv = StageDriver(ctx, rtol=1e-13, newton_abs=1e-12, newton_rel=1e-12, max_newton=12, nested_block=2)
+    q, u, uh = to_dev(inp["q"]), to_dev(inp["u"]), to_dev(inp["uh"])
+    infos = drv.step(q, u, uh, inp["dt"])
+    qo, uo, uho, _ = dirk_step(S, inp["q"], inp["u"], inp["uh"], inp["dt"],
+                               newton_kw=dict(abs_tol=1e-12, rel_tol=1e-12, max_it=12))
+    for st in infos:
+        assert st["res_hist"][-1] < 1e-11, st["res_hist"]
+    du = _rel(u.cpu().numpy(), uo)
+    duh = _rel(uh.cpu().numpy(), uho)
+    say(f"[nested driver] u {du:.2e}, u-hat {duh:.2e}")
+    assert du < 1e-10 and duh < 1e-10
+    assert np.abs(uo - inp["u"]).max() > 1e-6
+    ctx.close()
