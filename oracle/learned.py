@@ -16,6 +16,9 @@ stage.  Definitions used here:
 * Coarse prolongation P_c: the coarse functions evaluated at the face nodes;
   a face receives the mean over the macros that own it (two, or one on the
   domain boundary).
+* Neighbour features: a macro's coefficients followed by those of the macro
+  across each local face (zeros on the domain boundary), (1 + 2d) times the
+  per-macro count, as an input that reaches beyond the macro.
 * Network: y = W2 tanh(W1 x~ + b1) + b2 applied to x~ = x / ||x||_2 and
   rescaled by ||x||_2 (homogeneous of degree one in x); x = 0 maps to 0.
 * Loss on a batch (x_b, t_b): mean over the batch and the outputs of
@@ -118,6 +121,29 @@ def coarse_prolong(mesh, Y):
         acc /= len(sides)
         z[mesh.face_offset[f]:mesh.face_offset[f] + ns * Phi.shape[0]] = acc.reshape(-1)
     return z
+
+
+def neighbour_of(mesh, i, lf):
+    """The macro across local face lf of macro i, or -1 on the domain boundary."""
+    fc = mesh.faces[mesh.macro_faces[i, lf]]
+    return fc["plus"] if lf % 2 == 1 else fc["minus"]
+
+
+def neighbour_features(mesh, X):
+    """Xe [n_macros, (1 + 2d) n_features]: a macro's own coarse coefficients,
+    then those of the macro across each of its local faces in order (zeros
+    where the face is on the domain boundary), so that the network sees the
+    coarse state of the face neighbours as well."""
+    d = mesh.dim
+    F = X.shape[1]
+    Xe = np.zeros((mesh.n_macros, (1 + 2 * d) * F))
+    for i in range(mesh.n_macros):
+        Xe[i, :F] = X[i]
+        for lf in range(2 * d):
+            j = neighbour_of(mesh, i, lf)
+            if j >= 0:
+                Xe[i, (1 + lf) * F:(2 + lf) * F] = X[j]
+    return Xe
 
 
 # ---- network ---------------------------------------------------------------

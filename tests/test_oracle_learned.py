@@ -155,3 +155,38 @@ def test_zero_rows_carry_no_loss_gradient_of_the_input_layer():
     y0 = P["W2"] @ h0 + P["b2"]
     assert abs(loss - np.mean(y0 ** 2)) < 1e-15
     assert np.all(G["W1"] == 0.0)
+
+
+def test_neighbour_features_hand_example_and_shared_faces():
+    """2 x 3 macros, periodic in x only: the blocks are the right macros'
+    coefficients (checked against macro indices by hand), zero across the
+    Dirichlet walls, and the coefficients of a shared face agree from both
+    sides (the same face field restricted twice)."""
+    mesh = box_mesh(2, [4, 6], [2, 2], 2, periodic=[True, False])
+    assert mesh.n_macros == 6
+    F = Ld.n_features(2)
+    X = np.arange(mesh.n_macros * F, dtype=float).reshape(mesh.n_macros, F) + 1.0
+    Xe = Ld.neighbour_features(mesh, X)
+    assert Xe.shape == (6, 5 * F)
+    # macro (s0, s1) = s0 + 2 s1; local faces (x-low, x-high, y-low, y-high)
+    expect = {0: [1, 1, -1, 2], 1: [0, 0, -1, 3], 2: [3, 3, 0, 4], 5: [4, 4, 3, -1]}
+    for i, nbs in expect.items():
+        assert np.array_equal(Xe[i, :F], X[i])
+        for lf, j in enumerate(nbs):
+            blk = Xe[i, (1 + lf) * F:(2 + lf) * F]
+            assert np.array_equal(blk, X[j] if j >= 0 else np.zeros(F)), (i, lf)
+    # a smooth field: both sides restrict a shared face to the same coefficients
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(mesh.n_glob)
+    Xr = Ld.coarse_restrict(mesh, v)
+    Xe = Ld.neighbour_features(mesh, Xr)
+    ns, nq = mesh.ns, 2
+    for i in range(mesh.n_macros):
+        for lf in range(4):
+            j = Ld.neighbour_of(mesh, i, lf)
+            if j < 0:
+                continue
+            opp = lf ^ 1
+            own = Xr[i, lf * ns * nq:(lf + 1) * ns * nq]
+            theirs = Xe[i, (1 + lf) * F + opp * ns * nq:(1 + lf) * F + (opp + 1) * ns * nq]
+            assert np.array_equal(own, theirs)
