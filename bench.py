@@ -392,7 +392,7 @@ def learned_p3_variant(args, dev_fn, variants):
     train_seeds = list(range(100, 100 + args.learned_train_seeds))
     eval_seeds = list(range(200, 200 + args.learned_eval_seeds))
     t0 = time.perf_counter()
-    cc = CoarseCorrection(ctx, hidden=256, max_batch=1024, seed=0)
+    cc = CoarseCorrection(ctx, hidden=256, max_batch=1024, seed=0, neighbours=args.learned_neighbours)
     for s_ in train_seeds:
         condense_state(s_)
         cc.harvest(bhat, n_vectors=args.train_vectors, inner_prec=HDG_FP32)
@@ -421,10 +421,13 @@ def learned_p3_variant(args, dev_fn, variants):
                             converged=info["converged"])
         evals[f"seed_{s_}"] = ev
         print(f"[bench] p=3 learned: held-out seed {s_}: {ev}", file=sys.stderr, flush=True)
-    variants["tgv32_m4_p3_learned"] = dict(
+    key = "tgv32_m4_p3_learned" + ("_neighbours" if args.learned_neighbours else "")
+    variants[key] = dict(
         workload=f"32^3 periodic Taylor-Green, 4^3-element macros (512), p=3, n_glob {ctx.n_glob}; chunked FP32 "
                  f"condensation ({per} macros per chunk); train on seeds {train_seeds}, evaluate on held-out seeds "
-                 f"{eval_seeds}",
+                 f"{eval_seeds}; network inputs: own macro" + (" and its face neighbours" if args.learned_neighbours
+                                                              else ""),
+        n_in=cc.n_in,
         pairs=cc.n_pairs(), loss_initial=loss0, loss_final=loss1, train_s=round(t1 - t0, 1), solve=evals)
     ctx.close()
 
@@ -785,6 +788,8 @@ def main():
                          "and report the dissipation rate")
     ap.add_argument("--learned-train-seeds", type=int, default=1, help="training states of --learned-p3 (seeds 100..)")
     ap.add_argument("--learned-eval-seeds", type=int, default=1, help="held-out states of --learned-p3 (seeds 200..)")
+    ap.add_argument("--learned-neighbours", action="store_true",
+                    help="--learned-p3 with a network that also sees the face neighbours' coarse coefficients")
     ap.add_argument("--train-seeds", type=int, default=2)
     ap.add_argument("--train-vectors", type=int, default=40)
     ap.add_argument("--train-epochs", type=int, default=60)

@@ -410,6 +410,13 @@ hdg_status hdg_coarse_restrict(hdg_ctx ctx, const double* v, float* X);
  * nodes), each face taking the mean over the macros that own it. */
 hdg_status hdg_coarse_prolong(hdg_ctx ctx, const float* Y, double alpha, double* z);
 
+/* Xe [n_macros][(1 + 2d) n_features] (device, FP32; X and Xe must not
+ * overlap) = per macro its own row of X, then the rows of the macros across
+ * its local faces 0 .. 2d-1 (zeros across a face on the domain boundary):
+ * the input of a network that sees the coarse state of the face
+ * neighbours. */
+hdg_status hdg_coarse_neighbours(hdg_ctx ctx, const float* X, float* Xe);
+
 /* Two-layer network y = ||x|| (W2 tanh(W1 x / ||x|| + b1) + b2) (y = 0 for
  * x = 0).  All arrays are caller-owned device memory in FP32. */
 typedef struct {
@@ -440,8 +447,10 @@ hdg_status hdg_mlp_loss_grad(hdg_ctx ctx, const hdg_mlp* net, const float* X, co
 hdg_status hdg_mlp_adam(hdg_ctx ctx, const hdg_mlp* net, float lr, float beta1, float beta2, float eps, int step);
 
 /* Copy the network's parameters to BF16 inside the context for use by the
- * preconditioner (n_in = n_out = hdg_coarse_size, n_hidden <= 512); NULL
- * unbinds.  The copy is taken when the call's work runs on the stream. */
+ * preconditioner (n_out = hdg_coarse_size; n_in = hdg_coarse_size, or
+ * (1 + 2d) hdg_coarse_size for a network fed by hdg_coarse_neighbours;
+ * n_hidden <= 512); NULL unbinds.  The copy is taken when the call's work
+ * runs on the stream. */
 hdg_status hdg_learned_bind(hdg_ctx ctx, const hdg_mlp* net);
 
 hdg_status hdg_destroy(hdg_ctx ctx);

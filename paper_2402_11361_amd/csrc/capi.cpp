@@ -1072,6 +1072,12 @@ hdg_status hdg_coarse_restrict(hdg_ctx ctx, const double* v, float* X) {
   return HDG_OK;
 }
 
+hdg_status hdg_coarse_neighbours(hdg_ctx ctx, const float* X, float* Xe) {
+  if (!ctx || !X || !Xe || X == Xe) return HDG_EINVAL;
+  HIPCHK(&ctx->c, launch_coarse_neighbours(ctx->c, X, Xe));
+  return HDG_OK;
+}
+
 hdg_status hdg_coarse_prolong(hdg_ctx ctx, const float* Y, double alpha, double* z) {
   if (!ctx || !Y || !z) return HDG_EINVAL;
   HIPCHK(&ctx->c, launch_coarse_prolong(ctx->c, Y, alpha, z));
@@ -1126,14 +1132,16 @@ hdg_status hdg_learned_bind(hdg_ctx ctx, const hdg_mlp* net) {
     return HDG_OK;
   }
   if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
-  if (!net->params || net->n_in != c.cd.cF || net->n_out != c.cd.cF || net->n_hidden <= 0 ||
+  const int F = c.cd.cF, Fe = (1 + 2 * c.cd.dim) * F;
+  if (!net->params || (net->n_in != F && net->n_in != Fe) || net->n_out != F || net->n_hidden <= 0 ||
       net->n_hidden > LRN_MAX_HIDDEN)
     return fail(&c, HDG_EINVAL, "network shape does not match the coarse space (or n_hidden > 512)");
-  unsigned short* q = reinterpret_cast<unsigned short*>(c.ws.lrn + 2 * (size_t)c.hm.n_macros * c.cd.cF);
+  unsigned short* q = const_cast<unsigned short*>(learned_weights(c));
   HIPCHK(&c, launch_to_bf16(c.stream, (long long)mlp_param_count(net->n_in, net->n_hidden, net->n_out), net->params, q));
-  // captured FGMRES steps hold the inference launch shape of the old width
-  if (c.lrn_hidden != net->n_hidden) clear_graphs(c);
+  // captured FGMRES steps hold the inference launch shape of the old network
+  if (c.lrn_hidden != net->n_hidden || c.lrn_in != net->n_in) clear_graphs(c);
   c.lrn_hidden = net->n_hidden;
+  c.lrn_in = net->n_in;
   c.lrn_bound = true;
   return HDG_OK;
 }

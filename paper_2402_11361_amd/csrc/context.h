@@ -132,6 +132,7 @@ struct HdgContext {
   // learned coarse correction
   bool lrn_bound = false;
   int lrn_hidden = 0;
+  int lrn_in = 0;  // network inputs: cF (own macro) or (1 + 2d) cF (with the face neighbours)
   // captured FGMRES steps: key (first step, steps, restart, inner its, inner prec,
   // condensed prec, learned, FP32 copy present) -> executable graph
   std::map<std::array<int, 8>, hipGraphExec_t> graphs;

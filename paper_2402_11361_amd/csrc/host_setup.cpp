@@ -595,9 +595,11 @@ void plan_workspace(HdgContext& c) {
   // (48 sets of 64 rows each) (per class slices when there are several classes)
   o.Uinv = take(sizeof(double) * ((size_t)std::max(hm.n_macros, hm.n_faces) * (64 * 64 + 128 * 128 + 512 + 48 * 64) +
                                   64 * (size_t)hm.n_classes + 64));
-  // learned stage: X and Y per macro, then the BF16 copy of the largest network
-  o.lrn = take(sizeof(float) * (2 * (size_t)hm.n_macros * hc.cF + 16) +
-               sizeof(unsigned short) * mlp_param_count(hc.cF, LRN_MAX_HIDDEN, hc.cF));
+  // learned stage: X and Y per macro, the neighbour features (1 + 2d) X,
+  // then the BF16 copy of the largest network (neighbour inputs)
+  const int lrn_in_max = (1 + 2 * hc.dim) * hc.cF;
+  o.lrn = take(sizeof(float) * ((2 + 1 + 2 * (size_t)hc.dim) * (size_t)hm.n_macros * hc.cF + 16) +
+               sizeof(unsigned short) * mlp_param_count(lrn_in_max, LRN_MAX_HIDDEN, hc.cF));
   o.kctl = take(sizeof(double) * 8192);
   // SUPG: the per-element products are formed in batches of up to 4096 elements
   // (at most 4096 elements and about 4 GB of products per batch)

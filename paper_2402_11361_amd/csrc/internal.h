@@ -182,6 +182,7 @@ size_t mlp_param_count(int n_in, int n_hidden, int n_out);
 size_t mlp_work_floats(int n_in, int n_hidden, int n_out, int max_batch);
 hipError_t launch_coarse_restrict(HdgContext& c, const double* v, float* X);
 hipError_t launch_coarse_prolong(HdgContext& c, const float* Y, double alpha, double* z);
+hipError_t launch_coarse_neighbours(HdgContext& c, const float* X, float* Xe);
 hipError_t launch_mlp_forward(hipStream_t s, int n_in, int n_hidden, int n_out, const float* params, float* work,
                               const float* X, const int* idx, int batch, float* Y);
 hipError_t launch_mlp_loss_grad(hipStream_t s, int n_in, int n_hidden, int n_out, const float* params, float* grads,
@@ -190,6 +191,7 @@ hipError_t launch_mlp_adam(hipStream_t s, long long n, float* p, const float* g,
                            float b1, float b2, float eps, int t);
 hipError_t launch_to_bf16(hipStream_t s, long long n, const float* p, unsigned short* q);
 hipError_t launch_learned_correction(HdgContext& c, const double* v, double* z);
+const unsigned short* learned_weights(const HdgContext& c);
 
 // vector kernels for the Krylov solver
 hipError_t launch_multidot(hipStream_t s, long long n, int k, const double* V, long long ldv,

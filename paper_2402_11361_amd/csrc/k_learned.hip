@@ -216,6 +216,22 @@ __global__ void k_coarse_prolong(MeshDev md, const float* __restrict__ Y, double
   }
 }
 
+// Xe[macro] = [X[macro] | X[macro across local face lf] for lf = 0 .. 2d-1],
+// zeros across a face on the domain boundary.
+__global__ void k_coarse_neighbours(MeshDev md, int F, const float* __restrict__ X, float* __restrict__ Xe) {
+  const int macro = blockIdx.x, d = md.dim, nin = (1 + 2 * d) * F;
+  for (int x = threadIdx.x; x < nin; x += blockDim.x) {
+    const int blk = x / F, f = x % F;
+    int src = macro;
+    if (blk > 0) {
+      const int lf = blk - 1;
+      const int Fc = md.macro_face[(size_t)macro * 2 * d + lf];
+      src = (lf % 2 == 1) ? md.face_plus[Fc] : md.face_minus[Fc];
+    }
+    Xe[(size_t)macro * nin + x] = src >= 0 ? X[(size_t)src * F + f] : 0.f;
+  }
+}
+
 // Inference with BF16 weights, one workgroup per macro (row of X):
 // y = ||x|| (W2 tanh(W1 x / ||x|| + b1) + b2).
 __global__ void __launch_bounds__(256) k_learned_infer(int n_in, int n_hidden, int n_out,
@@ -276,6 +292,11 @@ size_t mlp_work_floats(int n_in, int n_hidden, int n_out, int max_batch) {
 
 hipError_t launch_coarse_restrict(HdgContext& c, const double* v, float* X) {
   hipLaunchKernelGGL(k_coarse_restrict, dim3(c.hm.n_macros), dim3(128), 0, c.stream, c.md, v, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_neighbours(HdgContext& c, const float* X, float* Xe) {
+  hipLaunchKernelGGL(k_coarse_neighbours, dim3(c.hm.n_macros), dim3(128), 0, c.stream, c.md, c.cd.cF, X, Xe);
   return hipGetLastError();
 }
 
@@ -357,16 +378,30 @@ hipError_t launch_to_bf16(hipStream_t s, long long n, const float* p, unsigned s
   return hipGetLastError();
 }
 
-// z += P_c f(R_c v) with the bound BF16 network; X, Y: [n_macros][cF] scratch.
+// BF16 network of the learned stage inside the workspace: after X, Y and Xe
+const unsigned short* learned_weights(const HdgContext& c) {
+  const size_t F = (size_t)c.cd.cF, nm = (size_t)c.hm.n_macros;
+  return reinterpret_cast<const unsigned short*>(c.ws.lrn + (2 + 1 + 2 * (size_t)c.cd.dim) * nm * F);
+}
+
+// z += P_c f(R_c v) with the bound BF16 network; X, Y: [n_macros][cF] and
+// Xe: [n_macros][(1 + 2d) cF] scratch (the neighbour features, when the
+// network takes them).
 hipError_t launch_learned_correction(HdgContext& c, const double* v, double* z) {
   const int F = c.cd.cF;
   float* X = c.ws.lrn;
   float* Y = X + (size_t)c.hm.n_macros * F;
+  float* Xe = Y + (size_t)c.hm.n_macros * F;
   hipError_t e = launch_coarse_restrict(c, v, X);
   if (e != hipSuccess) return e;
-  const size_t shm = sizeof(float) * (F + c.lrn_hidden);
-  hipLaunchKernelGGL(k_learned_infer, dim3(c.hm.n_macros), dim3(256), shm, c.stream, F, c.lrn_hidden, F,
-                     reinterpret_cast<const unsigned short*>(Y + (size_t)c.hm.n_macros * F), X, Y);
+  const float* in = X;
+  if (c.lrn_in != F) {
+    if ((e = launch_coarse_neighbours(c, X, Xe)) != hipSuccess) return e;
+    in = Xe;
+  }
+  const size_t shm = sizeof(float) * (c.lrn_in + c.lrn_hidden);
+  hipLaunchKernelGGL(k_learned_infer, dim3(c.hm.n_macros), dim3(256), shm, c.stream, c.lrn_in, c.lrn_hidden, F,
+                     learned_weights(c), in, Y);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_coarse_prolong(c, Y, 1.0, z);

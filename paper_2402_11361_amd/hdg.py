@@ -65,7 +65,7 @@ class Mlp(ctypes.Structure):
 EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_offsets", "hdg_node_coords", "hdg_bind_workspace", "hdg_linearize_stage",
            "hdg_condense", "hdg_apply_global", "hdg_fgmres_solve", "hdg_local_backsolve", "hdg_axpy",
            "hdg_destroy", "hdg_status_string", "hdg_last_error", "hdg_get_condensed", "hdg_get_formed",
-           "hdg_get_residuals", "hdg_precond_apply", "hdg_coarse_size", "hdg_coarse_restrict",
+           "hdg_get_residuals", "hdg_precond_apply", "hdg_coarse_size", "hdg_coarse_restrict", "hdg_coarse_neighbours",
            "hdg_coarse_prolong", "hdg_mlp_param_count", "hdg_mlp_work_floats", "hdg_mlp_forward",
            "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking",
            "hdg_autotune", "hdg_class_count", "hdg_get_tuning", "hdg_set_tuning",
@@ -121,6 +121,7 @@ def load_library(path=LIB_PATH):
     lib.hdg_precond_apply.argtypes = [vp, vp, vp, i, i, i]
     lib.hdg_coarse_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.hdg_coarse_restrict.argtypes = [vp, vp, vp]
+    lib.hdg_coarse_neighbours.argtypes = [vp, vp, vp]
     lib.hdg_coarse_prolong.argtypes = [vp, vp, dp, vp]
     lib.hdg_mlp_param_count.argtypes = [i, i, i]
     lib.hdg_mlp_work_floats.argtypes = [i, i, i, i]
@@ -381,6 +382,10 @@ class Context:
 
     def coarse_restrict(self, v, X):
         self._check(self.lib.hdg_coarse_restrict(self.h, _ptr(v), _ptr(X)))
+
+    def coarse_neighbours(self, X, Xe):
+        """Xe = [own | face neighbours'] coarse coefficients per macro."""
+        self._check(self.lib.hdg_coarse_neighbours(self.h, _ptr(X), _ptr(Xe)))
 
     def coarse_prolong(self, Y, alpha, z):
         self._check(self.lib.hdg_coarse_prolong(self.h, _ptr(Y), float(alpha), _ptr(z)))

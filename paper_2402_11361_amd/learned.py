@@ -16,20 +16,24 @@ from .hdg import HDG_FP64, Mlp
 
 
 class CoarseCorrection:
-    def __init__(self, ctx, hidden=256, max_batch=1024, seed=0):
+    def __init__(self, ctx, hidden=256, max_batch=1024, seed=0, neighbours=False):
+        """neighbours: the network also sees the coarse coefficients of the
+        macros across each face (hdg_coarse_neighbours), (1 + 2d) F inputs."""
         import torch
         self.t = torch
         self.ctx = ctx
         F = ctx.coarse_size()
-        self.F, self.hidden, self.max_batch = F, hidden, max_batch
+        self.neighbours = bool(neighbours)
+        n_in = (1 + 2 * ctx.dim) * F if self.neighbours else F
+        self.F, self.n_in, self.hidden, self.max_batch = F, n_in, hidden, max_batch
         lib = ctx.lib
-        n = int(lib.hdg_mlp_param_count(F, hidden, F))
-        nw = int(lib.hdg_mlp_work_floats(F, hidden, F, max_batch))
+        n = int(lib.hdg_mlp_param_count(n_in, hidden, F))
+        nw = int(lib.hdg_mlp_work_floats(n_in, hidden, F, max_batch))
         # Glorot-uniform weights, zero biases, from a seeded host generator
         rng = np.random.default_rng(seed)
-        a1 = np.sqrt(6.0 / (F + hidden))
+        a1 = np.sqrt(6.0 / (n_in + hidden))
         a2 = np.sqrt(6.0 / (hidden + F))
-        p0 = np.concatenate([rng.uniform(-a1, a1, hidden * F), np.zeros(hidden),
+        p0 = np.concatenate([rng.uniform(-a1, a1, hidden * n_in), np.zeros(hidden),
                              rng.uniform(-a2, a2, F * hidden), np.zeros(F)]).astype(np.float32)
         assert p0.size == n
         dev = dict(dtype=torch.float32, device="cuda")
@@ -39,7 +43,7 @@ class CoarseCorrection:
         self.adam_v = torch.zeros(n, **dev)
         self.work = torch.zeros(nw, **dev)
         self.loss = torch.zeros(1, **dev)
-        self.net = Mlp(F, hidden, F, max_batch, self.params.data_ptr(), self.grads.data_ptr(),
+        self.net = Mlp(n_in, hidden, F, max_batch, self.params.data_ptr(), self.grads.data_ptr(),
                        self.adam_m.data_ptr(), self.adam_v.data_ptr(), self.work.data_ptr())
         self.X, self.T = [], []
         self.step = 0
@@ -69,6 +73,10 @@ class CoarseCorrection:
             Tj = t.empty_like(Xj)
             ctx.coarse_restrict(v, Xj)
             ctx.coarse_restrict(e, Tj)
+            if self.neighbours:
+                Xe = t.empty(ctx.n_macros, self.n_in, dtype=t.float32, device="cuda")
+                ctx.coarse_neighbours(Xj, Xe)
+                Xj = Xe
             self.X.append(Xj)
             self.T.append(Tj)
         return k

@@ -262,3 +262,103 @@ def test_graphs_follow_rebound_network_width(trained):
         assert ih["converged"] and ig["converged"]
         assert abs(ih["outer_its"] - ig["outer_its"]) <= 1
         assert float((xg - xh).norm() / xh.norm()) < 1e-8
+
+
+@pytest.mark.parametrize("case", [dict(dim=3, n_elem=4, m=2, p=2, periodic=True),
+                                  dict(dim=2, n_elem=6, m=3, p=2, periodic=False, state="shear", mach=0.2)])
+def test_neighbour_features_and_inference_against_oracle(case):
+    """hdg_coarse_neighbours against the oracle's neighbour features, and the
+    learned stage of a network fed by them (n_in = (1 + 2d) F) inside the
+    preconditioner against the FP64 oracle."""
+    import torch
+    from oracle import learned as Ld
+    from paper_2402_11361_amd.learned import CoarseCorrection
+    say(f"[neighbours] {case}")
+    S, inp, ctx = make_pair(case)
+    M = S.mesh
+    F = ctx.coarse_size()
+    v = np.random.default_rng(21).standard_normal(M.n_glob)
+    X = torch.empty(M.n_macros, F, dtype=torch.float32, device="cuda")
+    ctx.coarse_restrict(to_dev(v), X)
+    Xe = torch.empty(M.n_macros, (1 + 2 * M.dim) * F, dtype=torch.float32, device="cuda")
+    ctx.coarse_neighbours(X, Xe)
+    # the gather is a copy: exact against the oracle's gather of the GPU's X
+    assert np.array_equal(Xe.cpu().numpy(), Ld.neighbour_features(M, X.cpu().numpy().astype(np.float64)))
+    Xo = Ld.neighbour_features(M, Ld.coarse_restrict(M, v))
+    e = _rel(Xe.cpu().numpy(), Xo)
+    say(f"[neighbours] features rel err {e:.2e}")
+    assert e < 1e-6
+    d = {k: (to_dev(w) if isinstance(w, np.ndarray) else w) for k, w in inp.items()}
+    ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    ctx.condense(bhat)
+    hidden = 128
+    cc = CoarseCorrection(ctx, hidden=hidden, max_batch=64, seed=3, neighbours=True)
+    rng = np.random.default_rng(33)
+    n_in = cc.n_in
+    P = Ld.init_params(n_in, hidden, F, rng)
+    P["b1"] = 0.1 * rng.standard_normal(hidden)
+    P["b2"] = 0.1 * rng.standard_normal(F)
+    flat32 = Ld.flat(P).astype(np.float32)
+    cc.params.copy_(torch.tensor(flat32, device="cuda"))
+    P32 = Ld.unflat(flat32.astype(np.float64), n_in, hidden, F)
+    cc.bind()
+    zp = torch.empty(ctx.n_glob, dtype=torch.float64, device="cuda")
+    zl = torch.empty_like(zp)
+    ctx.precond_apply(to_dev(v), zp, 5)
+    ctx.precond_apply(to_dev(v), zl, 5, use_learned=True)
+    got = (zl - zp).cpu().numpy()
+    ref = Ld.coarse_prolong(M, Ld.forward(P32, Xo))
+    e = _rel(got, ref)
+    say(f"[neighbours] correction rel err vs FP64 oracle {e:.2e}")
+    assert 1e-6 < e < 2e-2  # BF16 weights, FP32 sums
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def trained_neighbours():
+    """The trained network of the other fixture's recipe, fed the coarse
+    coefficients of the face neighbours too."""
+    import torch
+    from paper_2402_11361_amd.learned import CoarseCorrection
+    cc = None
+    for seed in (0, 1):
+        ctx, bhat = _condensed(seed)
+        if cc is None:
+            cc = CoarseCorrection(ctx, hidden=256, max_batch=512, seed=0, neighbours=True)
+        else:
+            cc.ctx = ctx
+        cc.harvest(bhat, n_vectors=30)
+    X = torch.cat(cc.X)
+    T = torch.cat(cc.T)
+    loss0 = cc.eval_loss(X, T)
+    cc.train(epochs=150, lr=1e-3, batch=512)
+    loss1 = cc.eval_loss(X, T)
+    say(f"[train neighbours] {cc.n_pairs()} pairs, loss {loss0:.4e} -> {loss1:.4e}")
+    return cc, loss0, loss1
+
+
+def test_training_with_neighbours_reduces_loss(trained_neighbours, trained):
+    cc, loss0, loss1 = trained_neighbours
+    _, p0, p1 = trained
+    say(f"[train neighbours] final loss {loss1:.4e} (own macro only: {p1:.4e})")
+    assert loss1 < 0.7 * loss0
+
+
+@pytest.mark.xfail(reason="no gain measured: the held-out solve with the neighbour-fed network kept for the whole "
+                          "solve needs as many or more outer iterations than the plain preconditioner", strict=False)
+def test_learned_gain_with_neighbours_without_fallback(trained_neighbours):
+    """The held-out solve with the neighbour-fed network kept for the whole
+    solve against the plain multi-level preconditioner."""
+    import torch
+    cc, _, _ = trained_neighbours
+    ctx, bhat, xp, ip = _held_out(cc)
+    cc.ctx = ctx
+    cc.bind()
+    xl = torch.zeros_like(bhat)
+    il = ctx.fgmres_solve(bhat, xl, rtol=1e-10, restart=30, inner_its=5, use_learned=True, no_fallback=True)
+    say(f"[gain neighbours] plain: {ip['outer_its']} outer its, {ip['ms']:.1f} ms;  learned (no fallback): "
+        f"{il['outer_its']} outer its, {il['ms']:.1f} ms")
+    assert il["converged"] and il["fallbacks"] == 0
+    assert float((xl - xp).norm() / xp.norm()) < 1e-6
+    assert il["outer_its"] < ip["outer_its"]
