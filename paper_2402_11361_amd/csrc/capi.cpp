@@ -726,6 +726,9 @@ hdg_status hdg_condense_nested(hdg_ctx ctx, int block_m, double* ahat, double* b
   return HDG_OK;
 }
 
+static hdg_status fgmres_run(hdg_ctx ctx, Krylov& K, const double* b, double* x, const hdg_krylov_opts* o,
+                             hdg_krylov_stats* st, std::chrono::steady_clock::time_point t0);
+
 hdg_status hdg_nested_solve(hdg_ctx ctx, int block_m, double* x_full, const hdg_krylov_opts* o,
                             hdg_krylov_stats* st) {
   if (!ctx || !x_full || !o) return HDG_EINVAL;
@@ -738,7 +741,7 @@ hdg_status hdg_nested_solve(hdg_ctx ctx, int block_m, double* x_full, const hdg_
     return fail(&c, HDG_EINVAL, "bad Krylov options");
   if (o->use_learned || o->harvest_max || o->graph_steps || o->inner_prec != HDG_FP64)
     return fail(&c, HDG_EUNSUPPORTED, "the skeleton solve takes FP64 host-controlled steps only");
-  auto t0 = std::chrono::steady_clock::now();
+  const auto t0 = std::chrono::steady_clock::now();
   NestedPlan& P = *c.nested;
   const long long n = nested_skeleton_size(P);
   Krylov K(c, o->restart, o->inner_its, ctx->pinned, 0, n);
@@ -747,71 +750,13 @@ hdg_status hdg_nested_solve(hdg_ctx ctx, int block_m, double* x_full, const hdg_
   const double* b = nested_rhs(P);
   double* x = nested_xskel(P);
   HIPCHK(&c, launch_scale_copy(c.stream, n, 0.0, b, x));  // zero start
-  double bnorm, beta;
-  HIPCHK(&c, K.norm(b, bnorm));
-  const double tol = std::max(o->rtol * bnorm, o->atol);
-  HIPCHK(&c, launch_scale_copy(c.stream, n, 1.0, b, K.r));
-  beta = bnorm;
-  const int m = o->restart;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
-  int its = 0;
-  while (beta > tol && its < o->max_outer) {
-    HIPCHK(&c, launch_scale_copy(c.stream, n, 1.0 / beta, K.r, K.V));
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
-      HIPCHK(&c, K.precond_plain(K.V + (size_t)j * n, K.Z + (size_t)j * n));
-      double* wv = K.V + (size_t)(j + 1) * n;
-      HIPCHK(&c, K.apply_A(K.Z + (size_t)j * n, wv, 0));
-      double h[128];
-      HIPCHK(&c, K.cgs2(K.V, j, wv, h));
-      double hn;
-      HIPCHK(&c, K.norm(wv, hn));
-      for (int i = 0; i < j; ++i) {
-        const double a = h[i], bb = h[i + 1];
-        h[i] = cs[i] * a + sn[i] * bb;
-        h[i + 1] = -sn[i] * a + cs[i] * bb;
-      }
-      const double rr = std::hypot(h[j], hn);
-      cs[j] = rr > 0 ? h[j] / rr : 1.0;
-      sn[j] = rr > 0 ? hn / rr : 0.0;
-      h[j] = rr;
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
-      const double g0 = g[j];
-      g[j] = cs[j] * g0;
-      g[j + 1] = -sn[j] * g0;
-      ++its;
-      k = j + 1;
-      if (hn == 0.0 || std::fabs(g[j + 1]) <= tol || its >= o->max_outer) break;
-      HIPCHK(&c, launch_scale_copy(c.stream, n, 1.0 / hn, wv, wv));
-    }
-    for (int i = k - 1; i >= 0; --i) {
-      double sum = g[i];
-      for (int j = i + 1; j < k; ++j) sum -= H[(size_t)i * m + j] * y[j];
-      y[i] = H[(size_t)i * m + i] != 0.0 ? sum / H[(size_t)i * m + i] : 0.0;
-    }
-    for (int i = 0; i < k; ++i) ctx->pinned[i] = y[i];
-    HIPCHK(&c, hipMemcpyAsync(K.dev_coef + 256, ctx->pinned, sizeof(double) * k, hipMemcpyHostToDevice, c.stream));
-    HIPCHK(&c, launch_lincomb(c.stream, n, k, K.Z, n, K.dev_coef + 256, x, 1));
-    HIPCHK(&c, K.apply_A(x, K.t, 0));
-    HIPCHK(&c, launch_sub(c.stream, n, b, K.t, K.r));
-    HIPCHK(&c, K.norm(K.r, beta));
-    if (!std::isfinite(beta)) return fail(&c, HDG_ENAN, "non-finite Krylov residual");
-  }
+  const hdg_status s = fgmres_run(ctx, K, b, x, o, st, t0);
+  if (s != HDG_OK && s != HDG_ENOCONV) return s;
+  // the internal traces (of the last iterate when max_outer was reached)
   HIPCHK(&c, launch_nested_recover(c, P, x, x_full));
   HIPCHK(&c, hipStreamSynchronize(c.stream));
-  if (st) {
-    st->outer_its = its;
-    st->inner_its_total = K.inner_total;
-    st->res0 = bnorm;
-    st->res_final = beta;
-    st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    st->fallbacks = 0;
-    st->harvested = 0;
-  }
-  if (beta > tol) return fail(&c, HDG_ENOCONV, "FGMRES on the block skeleton reached max_outer");
-  return HDG_OK;
+  if (st) st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return s;
 }
 
 hdg_status hdg_condense_first_layer(hdg_ctx ctx, double* bhat) {
@@ -877,19 +822,13 @@ hdg_status hdg_apply_global(hdg_ctx ctx, const double* x, double* y) {
   return HDG_OK;
 }
 
-hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_krylov_opts* o, hdg_krylov_stats* st) {
-  if (!ctx || !b || !x || !o) return HDG_EINVAL;
+// FGMRES (Sec. 4.2) on the operator of K from the start x: the body of
+// hdg_fgmres_solve, shared with the nested skeleton solve (whose K carries
+// another operator and preconditioner; it takes no learned stage, harvest
+// or graphs).
+static hdg_status fgmres_run(hdg_ctx ctx, Krylov& K, const double* b, double* x, const hdg_krylov_opts* o,
+                             hdg_krylov_stats* st, std::chrono::steady_clock::time_point t0) {
   HdgContext& c = ctx->c;
-  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
-  if (o->restart < 1 || o->restart > c.kry_restart_max || o->inner_its < 0 || o->inner_its > c.kry_inner_max ||
-      o->max_outer < 1 || !(o->rtol >= 0) || !(o->atol >= 0) || o->graph_steps < 0)
-    return fail(&c, HDG_EINVAL, "bad Krylov options");
-  auto t0 = std::chrono::steady_clock::now();
-  int icode = 0;
-  if (hdg_status s = inner_operator(c, o->inner_prec, &icode); s != HDG_OK) return s;
-  if (o->use_learned && !c.lrn_bound) return fail(&c, HDG_EINVAL, "use_learned without a bound network");
-  if (o->harvest_max < 0 || (o->harvest_max > 0 && !o->harvest)) return fail(&c, HDG_EINVAL, "bad harvest buffer");
-  Krylov K(c, o->restart, o->inner_its, ctx->pinned, icode);
   // the learned stage is judged against the plain preconditioner of this
   // solve: the first LRN_JUDGE_STEPS steps run plain and measure its mean
   // residual reduction, then the learned stage is switched on
@@ -1043,6 +982,22 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
   }
   if (beta > tol) return fail(&c, HDG_ENOCONV, "FGMRES reached max_outer");
   return HDG_OK;
+}
+
+hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_krylov_opts* o, hdg_krylov_stats* st) {
+  if (!ctx || !b || !x || !o) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
+  if (o->restart < 1 || o->restart > c.kry_restart_max || o->inner_its < 0 || o->inner_its > c.kry_inner_max ||
+      o->max_outer < 1 || !(o->rtol >= 0) || !(o->atol >= 0) || o->graph_steps < 0)
+    return fail(&c, HDG_EINVAL, "bad Krylov options");
+  const auto t0 = std::chrono::steady_clock::now();
+  int icode = 0;
+  if (hdg_status s = inner_operator(c, o->inner_prec, &icode); s != HDG_OK) return s;
+  if (o->use_learned && !c.lrn_bound) return fail(&c, HDG_EINVAL, "use_learned without a bound network");
+  if (o->harvest_max < 0 || (o->harvest_max > 0 && !o->harvest)) return fail(&c, HDG_EINVAL, "bad harvest buffer");
+  Krylov K(c, o->restart, o->inner_its, ctx->pinned, icode);
+  return fgmres_run(ctx, K, b, x, o, st, t0);
 }
 
 hdg_status hdg_precond_apply(hdg_ctx ctx, const double* v, double* z, int inner_its, hdg_prec inner_prec,
