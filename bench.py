@@ -157,6 +157,7 @@ def big_variant(args, dev_fn, variants):
     stream = torch.cuda.current_stream()
     ctx = Context.from_mesh_spec(spec, Re=cfg["Re"], Mach=cfg["mach"], stream=stream.cuda_stream)
     free, _ = torch.cuda.mem_get_info()
+    ctx.set_chunk_buffers(args.chunk_slots)
     per = ctx.fit_chunking(free - (8 << 30))
     ctx.bind_workspace()
     u0, q0, uh0 = workload_arrays(ctx, cfg)
@@ -193,7 +194,7 @@ def big_variant(args, dev_fn, variants):
                  f"n_glob {ctx.n_glob}; {per} macros per condensation chunk; FP32 condensation refined by Newton, "
                  "FP32 inner operator, graph-captured FGMRES steps"
                  + ("; learned coarse correction judged by the plain preconditioner" if learned else ""),
-        macros_per_chunk=per, workspace_gb=round(ctx.workspace_bytes / 1e9, 1), learned=learned,
+        macros_per_chunk=per, chunk_slots=args.chunk_slots, workspace_gb=round(ctx.workspace_bytes / 1e9, 1), learned=learned,
         ms_per_step_mean=round(float(np.mean(ms)), 1) if ms else None,
         ms_per_stage_mean=round(float(np.mean(ms)) / 3, 1) if ms else None, time_steps=steps)
     ctx.close()
@@ -772,6 +773,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="tgv48_m4_p2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--chunk-slots", type=int, default=1, choices=(1, 2),
+                    help="chunk slots of the condensation buffer (2: the next chunk is formed beside the "
+                         "elimination of this one)")
     ap.add_argument("--cpu-sample", type=int, default=1, help="macros of the CPU oracle's sample")
     ap.add_argument("--cpu-single-thread", action="store_true",
                     help="also time the oracle's sample with one BLAS thread")
@@ -838,6 +842,7 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = Context.from_mesh_spec(spec, Re=cfg["Re"], Mach=cfg["mach"], stream=stream.cuda_stream)
     free, _ = torch.cuda.mem_get_info()
+    ctx.set_chunk_buffers(args.chunk_slots)
     per_chunk = ctx.fit_chunking(free - (8 << 30))
     ctx.bind_workspace()
     say(f"{args.config}: {ctx.n_macros} macros, n_glob {ctx.n_glob}, workspace {ctx.workspace_bytes / 1e9:.1f} GB, "
@@ -936,7 +941,7 @@ def main():
                                     f"linearise, second-layer condensation in {(nm + (per_chunk or nm) - 1) // (per_chunk or nm)} "
                                     f"chunks, FGMRES(30) rtol {cfg['rtol']} with 5 inner GMRES steps, recovery, update",
                            n_macros=nm, n_u_macro=nu, n_b_macro=nb, n_glob=n_glob,
-                           macros_per_chunk=per_chunk,
+                           macros_per_chunk=per_chunk, chunk_slots=args.chunk_slots,
                            variant="plain FP64" if main_prec == HDG_FP64 else "FP32 condensation"),
                phases_ms={k: round(v, 3) for k, v in plain["phase_ms"].items()},
                fgmres=dict(outer_its=plain["outer"], inner_its=plain["inner"]),

@@ -188,6 +188,20 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes);
  * of chunks times the number of macro classes exceeds 4095. */
 hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk);
 
+/* Chunk slots of the W buffer under chunked condensation: 1 (default) or 2.
+ * With 2, W holds two chunks (chunk j in slot j % 2, so twice the W bytes for
+ * the same macros_per_chunk): hdg_condense forms chunk j + 1 on a second
+ * stream of the library's while chunk j is eliminated on the library's
+ * stream (the local problems of different macros are independent, Sec. 3.3);
+ * hdg_local_backsolve does the same for the chunks it forms again.  With
+ * either setting, hdg_local_backsolve recovers the chunks whose eliminations
+ * W still holds from the last hdg_condense (one per slot) from those factors,
+ * when no call that writes W (hdg_linearize_stage, hdg_autotune,
+ * hdg_get_formed, hdg_condense_first_layer, a recovery that formed chunks
+ * again) came in between.  No effect without chunking.  Re-plans the
+ * workspace like hdg_set_chunking.  HDG_EINVAL for other values. */
+hdg_status hdg_set_chunk_buffers(hdg_ctx ctx, int n_buffers);
+
 /* Autotuner of the batched elimination of hdg_condense: for every macro
  * class (one per macro shape) and the given condensation precision, times
  * the class's elimination (HIP events on the context's stream, after one

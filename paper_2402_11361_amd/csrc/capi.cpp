@@ -433,6 +433,29 @@ hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk) {
   c.ws_bound = false;
   c.lrn_bound = false;
   c.condensed64 = false;
+  c.forget_w();
+  c.have_a32 = false;
+  c.have_a16 = false;
+  clear_graphs(c);
+  return HDG_OK;
+}
+
+hdg_status hdg_set_chunk_buffers(hdg_ctx ctx, int n_buffers) {
+  if (!ctx) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (n_buffers != 1 && n_buffers != 2) return fail(&c, HDG_EINVAL, "n_buffers must be 1 or 2");
+  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  c.hm.chunk_buffers = n_buffers;
+  plan_workspace(c);
+  try {
+    upload_w_offsets(c);
+  } catch (const std::exception& ex) {
+    return fail(&c, HDG_EDEVICE, ex.what());
+  }
+  c.ws_bound = false;
+  c.lrn_bound = false;
+  c.condensed64 = false;
+  c.forget_w();
   c.have_a32 = false;
   c.have_a16 = false;
   clear_graphs(c);
@@ -471,6 +494,7 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
   c.have_a16 = false;
   c.linearized = false;
   c.condensed64 = false;
+  c.forget_w();
   return HDG_OK;
 }
 
@@ -481,6 +505,8 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
   if (!c.linearized) return fail(&c, HDG_EINVAL, "autotune needs a linearisation (hdg_linearize_stage) first");
   if (prec != HDG_FP64 && prec != HDG_FP32) return fail(&c, HDG_EUNSUPPORTED, "condensation precision not built");
   const int p32 = prec == HDG_FP32 ? 1 : 0;
+  c.condensed64 = false;  // the trials overwrite W (also when one fails)
+  c.forget_w();
   int dev = 0, rt = 0;
   HIPCHK(&c, hipGetDevice(&dev));
   hipDeviceProp_t prop;
@@ -590,6 +616,7 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
   c.have_a32 = false;
   c.have_a16 = false;
   c.condensed64 = false;
+  c.forget_w();
   return HDG_OK;
 }
 
@@ -630,6 +657,7 @@ hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, co
   HIPCHK(&c, launch_linearize(c, q, u, uhat, w, sa));
   c.linearized = true;
   c.condensed64 = false;
+  c.forget_w();
   c.have_a32 = false;
   c.have_a16 = false;
   if (norms_host) {
@@ -640,6 +668,47 @@ hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, co
     if (!std::isfinite(norms_host[0] + norms_host[1] + norms_host[2])) return fail(&c, HDG_ENAN, "non-finite residual");
   }
   return HDG_OK;
+}
+
+// Formation, elimination and (chunked) extraction of every chunk.  With two
+// slots, chunk j + 1 is formed on the formation stream into the other slot
+// while chunk j is eliminated and extracted on the library's stream; a slot is
+// formed again once the extraction of the chunk before has read it.
+static hipError_t condense_chunks(HdgContext& c, int p32) {
+  const int nch = c.hm.n_chunks();
+  hipError_t e;
+  if (c.hm.slots() < 2) {
+    for (int j = 0; j < nch; ++j) {
+      if ((e = launch_form(c, p32, c.hm.chunk_first[j], c.hm.chunk_first[j + 1])) != hipSuccess) return e;
+      if ((e = launch_lu(c, p32, j, false)) != hipSuccess) return e;
+      if (c.hm.chunked() && (e = launch_extract(c, p32, j)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  if ((e = form_stream_ready(c)) != hipSuccess) return e;
+  hipStream_t fs = c.form_stream;
+  hipEvent_t* ev = c.form_events;  // [0] start, [1 + b] slot b formed, [3 + b] slot b free
+  // the linearisation (whose element products share W) and earlier work come first
+  if ((e = hipEventRecord(ev[0], c.stream)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(fs, ev[0], 0)) != hipSuccess) return e;
+  auto form = [&](int j) -> hipError_t {
+    hipError_t r;
+    const int b = j % 2;
+    if (j >= 2 && (r = hipStreamWaitEvent(fs, ev[3 + b], 0)) != hipSuccess) return r;
+    if ((r = launch_form(c, p32, c.hm.chunk_first[j], c.hm.chunk_first[j + 1], -1, nullptr, fs)) != hipSuccess)
+      return r;
+    return hipEventRecord(ev[1 + b], fs);
+  };
+  if ((e = form(0)) != hipSuccess) return e;
+  for (int j = 0; j < nch; ++j) {
+    const int b = j % 2;
+    if (j + 1 < nch && (e = form(j + 1)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(c.stream, ev[1 + b], 0)) != hipSuccess) return e;
+    if ((e = launch_lu(c, p32, j, false)) != hipSuccess) return e;
+    if ((e = launch_extract(c, p32, j)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev[3 + b], c.stream)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
@@ -653,15 +722,12 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
   const int p32 = (prec == HDG_FP32 || prec == HDG_BF16) ? 1 : 0;
   c.bf16_update = (prec == HDG_BF16);
   c.condensed64 = false;
+  c.forget_w();
   // status flags: one per (chunk, macro class), then one for the face blocks
   const int ncl = c.hm.n_classes, nch = c.hm.n_chunks(), nst = nch * ncl;
   int* status = reinterpret_cast<int*>(c.ws.small);
   HIPCHK(&c, launch_zero_ints(c.stream, status, nst + 1));
-  for (int j = 0; j < nch; ++j) {
-    HIPCHK(&c, launch_form(c, p32, c.hm.chunk_first[j], c.hm.chunk_first[j + 1]));
-    HIPCHK(&c, launch_lu(c, p32, j, false));
-    if (c.hm.chunked()) HIPCHK(&c, launch_extract(c, p32, j));
-  }
+  HIPCHK(&c, condense_chunks(c, p32));
   HIPCHK(&c, launch_bhat(c, bhat, p32));
   HIPCHK(&c, launch_face_precond(c));
   c.cond_prec = p32;
@@ -683,6 +749,8 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
     }
   if (st[nst]) return fail(&c, HDG_ESINGULAR, "singular face block of A_uhat-uhat " + std::to_string(st[nst] - 1));
   c.condensed64 = (p32 == 0);
+  if (c.hm.chunked())  // the last chunk of each slot
+    for (int i = 0; i < c.hm.slots(); ++i) c.w_res[i] = nch - 1 - i;
   return HDG_OK;
 }
 
@@ -765,6 +833,7 @@ hdg_status hdg_condense_first_layer(hdg_ctx ctx, double* bhat) {
   if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
   if (!c.hm.chunked() || c.hm.n_classes != 1)
     return fail(&c, HDG_EUNSUPPORTED, "first-layer condensation needs chunking and a single macro shape");
+  c.forget_w();  // W holds the first-layer matrices from here on
   int* status = reinterpret_cast<int*>(c.ws.small);
   const int nst = c.hm.n_chunks() * c.hm.n_classes;
   HIPCHK(&c, launch_zero_ints(c.stream, status, nst + 1));
@@ -1124,6 +1193,9 @@ hdg_status hdg_destroy(hdg_ctx ctx) {
   for (auto ev : ctx->c.lu_events) (void)hipEventDestroy(ev);
   for (auto s : ctx->c.lu_pstreams) (void)hipStreamDestroy(s);
   for (auto ev : ctx->c.lu_pevents) (void)hipEventDestroy(ev);
+  if (ctx->c.form_stream) (void)hipStreamDestroy(ctx->c.form_stream);
+  for (auto ev : ctx->c.form_events)
+    if (ev) (void)hipEventDestroy(ev);
   for (void* p : ctx->c.dev_allocs) (void)hipFree(p);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
@@ -1195,6 +1267,7 @@ hdg_status hdg_get_formed(hdg_ctx ctx, size_t macro, double* w_host) {
   if (!c.ws_bound || macro >= (size_t)c.hm.n_macros) return HDG_EINVAL;
   int j = 0;  // the chunk holding the macro
   while (c.hm.chunk_first[j + 1] <= (int)macro) ++j;
+  c.forget_w();  // W no longer holds a chunk's elimination
   HIPCHK(&c, launch_form(c, 0, c.hm.chunk_first[j], c.hm.chunk_first[j + 1]));
   if (!c.hm.chunked()) {  // W no longer holds the condensed operator
     c.cond_prec = 0;

@@ -2,6 +2,7 @@
 // macro shape, workspace layout.  Internal.
 #pragma once
 #include "internal.h"
+#include <algorithm>
 #include <array>
 #include <map>
 #include <memory>
@@ -49,16 +50,19 @@ struct HostMesh {
   std::vector<int> face_slot;
   std::vector<std::array<int, 3>> face_groups;
   // chunked condensation: the macros are condensed in consecutive ranges
-  // [chunk_first[j], chunk_first[j + 1]) through one W buffer sized for the
-  // largest range; w_off is then relative to that buffer.  Per (chunk, class):
-  // offset of the class's matrices in the buffer, their count and the rank
-  // (within the class) of the first of them.
+  // [chunk_first[j], chunk_first[j + 1]) through W, which holds chunk_buffers
+  // slots each sized for the largest range (chunk j in slot j % chunk_buffers);
+  // w_off is then relative to W.  Per (chunk, class): offset of the class's
+  // matrices in W, their count and the rank (within the class) of the first
+  // of them.
   int chunk_macros = 0;                  // requested macros per chunk (0: all at once)
+  int chunk_buffers = 1;                 // chunk slots in W (2: the next chunk is formed beside this one's elimination)
   std::vector<int> chunk_first;          // [n_chunks + 1]
   std::vector<long long> chunk_class_w;  // [n_chunks * n_classes]
   std::vector<int> chunk_class_cnt, chunk_class_rank0;
   int n_chunks() const { return (int)chunk_first.size() - 1; }
   bool chunked() const { return n_chunks() > 1; }
+  int slots() const { return chunked() ? std::min(chunk_buffers, n_chunks()) : 1; }
 };
 
 struct Workspace {
@@ -123,8 +127,12 @@ struct HdgContext {
   bool have_a32 = false;
   bool have_a16 = false;
   bool linearized = false;  // element blocks hold a linearisation
-  int cond_prec = 0;
+  int cond_prec = 0;  // element type of the condensed matrices in W: 0 FP64, 1 FP32
   bool condensed64 = false;  // the element blocks of the last FP64 hdg_condense are in place
+  // chunked: the chunks whose condensations W still holds (-1: none), the
+  // last ones condensed, one per slot
+  int w_res[2] = {-1, -1};
+  void forget_w() { w_res[0] = w_res[1] = -1; }
   std::shared_ptr<NestedPlan> nested;  // nested condensation for one block size (built on first use)
   int nested_m = 0;                    // its block size
   bool bf16_update = false;  // the last condensation took BF16 operands in its trailing updates
@@ -143,7 +151,11 @@ struct HdgContext {
   std::vector<hipEvent_t> lu_events;
   // per class slot: the look-ahead panel stream and its two hand-off events
   std::vector<hipStream_t> lu_pstreams;
-  std::vector<hipEvent_t> lu_pevents;  // element type of the condensed matrices in Wm: 0 FP64, 1 FP32
+  std::vector<hipEvent_t> lu_pevents;
+  // two chunk slots: the formation stream and its events (start, formed per
+  // slot, slot free per slot), created on first use
+  hipStream_t form_stream = nullptr;
+  hipEvent_t form_events[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   std::string last_error;
 };
 

@@ -525,6 +525,14 @@ void plan_workspace(HdgContext& c) {
     }
     for (int k = 0; k < ncl; ++k) rank[k] += cnt[k];
   }
+  // slot j % slots of W for chunk j
+  const int slots = hm.slots();
+  if (slots > 1)
+    for (int j = 0; j < nch; ++j) {
+      const long long base = (long long)(j % slots) * w_chunk_max;
+      for (int k = 0; k < ncl; ++k) hm.chunk_class_w[(size_t)j * ncl + k] += base;
+      for (int i = hm.chunk_first[j]; i < hm.chunk_first[j + 1]; ++i) hm.w_off[i] += base;
+    }
   const long long n_el = hm.el_off[nm];
   c.n_u_tot = hm.u_off[nm];
   c.n_q_tot = (long long)d * hm.u_off[nm];
@@ -570,7 +578,7 @@ void plan_workspace(HdgContext& c) {
   o.RBglob = take(sizeof(double) * hm.n_glob);
   o.gloc = take(sizeof(double) * (size_t)hm.b_off[nm]);
   c.fstride = (long long)align_up(2 * c.nf_max, 16) * c.ldf;
-  c.wm_bytes = std::max(sizeof(double) * (size_t)w_chunk_max, chunked ? kq_bytes : 0);
+  c.wm_bytes = std::max(sizeof(double) * (size_t)w_chunk_max * hm.slots(), chunked ? kq_bytes : 0);
   if (chunked && hm.n_classes == 1) {
     // room for at least one first-layer matrix (order n_q + n_u + n_b) and its pivots
     const HostClass& k = c.hcs[0];

@@ -146,9 +146,12 @@ hipError_t launch_linearize(HdgContext& c, const double* q, const double* u, con
 // prec: 0 FP64, 1 FP32 element type of the augmented matrices
 // formation and elimination of the macros [m0, m1) = chunk j (rows of the
 // trace block skipped in the elimination when top_only)
-// rhs_duhat non-null: recovery form (S rows with f + C duhat in column n_u)
+// rhs_duhat non-null: recovery form (S rows with f + C duhat in column n_u);
+// on stream s (null: the library's stream)
 hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class = -1,
-                       const double* rhs_duhat = nullptr);
+                       const double* rhs_duhat = nullptr, hipStream_t s = nullptr);
+// chunks in two slots of W: the formation stream and its events
+hipError_t form_stream_ready(HdgContext& c);
 // top_only: eliminate the S rows only; rhs_only (with top_only): the columns
 // [0, n_u] only (the recovery form's right-hand side in column n_u)
 hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only_class = -1, bool rhs_only = false);

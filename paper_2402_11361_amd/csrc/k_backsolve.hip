@@ -17,6 +17,7 @@
 // columns.
 #include "context.h"
 #include <algorithm>
+#include <vector>
 
 namespace {
 
@@ -326,7 +327,11 @@ static hipError_t backsolve_range(HdgContext& c, const double* duhat, double* dq
 // Unchunked: W still holds every macro's elimination.  Chunked: each chunk's
 // S rows are formed again with the right-hand side f + C duhat folded into
 // column n_u (the trace rows and the C columns are not needed) and
-// eliminated, in the precision of the last condensation, then recovered.
+// eliminated, in the precision of the last condensation, then recovered;
+// the chunks condensed last (one per slot of W), whose eliminations W still
+// holds when nothing has written W since, are recovered first and from there,
+// as if unchunked.  With two slots the next chunk is formed on the formation
+// stream while the current one is eliminated and recovered.
 hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, double* du) {
   int nu = 0, nb = 0;
   for (const HostClass& k : c.hcs) { nu = std::max(nu, k.n_u); nb = std::max(nb, k.n_b); }
@@ -339,11 +344,57 @@ hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, doub
   if (!c.hm.chunked()) {
     if ((e = backsolve_range(c, duhat, dq, du, 0, nm, nu, nb, false)) != hipSuccess) return e;
   } else {
-    for (int j = 0; j < c.hm.n_chunks(); ++j) {
-      const int m0 = c.hm.chunk_first[j], m1 = c.hm.chunk_first[j + 1];
-      if ((e = launch_form(c, c.cond_prec, m0, m1, -1, duhat)) != hipSuccess) return e;
-      if ((e = launch_lu(c, c.cond_prec, j, true, -1, true)) != hipSuccess) return e;
-      if ((e = backsolve_range(c, duhat, dq, du, m0, m1, nu, nb, true)) != hipSuccess) return e;
+    const int nch = c.hm.n_chunks();
+    std::vector<char> done(nch, 0);
+    for (int r : c.w_res)
+      if (r >= 0 && r < nch && !done[r]) {
+        if ((e = backsolve_range(c, duhat, dq, du, c.hm.chunk_first[r], c.hm.chunk_first[r + 1], nu, nb, false)) !=
+            hipSuccess)
+          return e;
+        done[r] = 1;
+      }
+    std::vector<int> todo;
+    for (int j = 0; j < nch; ++j)
+      if (!done[j]) todo.push_back(j);
+    if (!todo.empty()) c.forget_w();  // W now takes recovery forms
+    if (c.hm.slots() < 2) {
+      for (int j : todo) {
+        const int m0 = c.hm.chunk_first[j], m1 = c.hm.chunk_first[j + 1];
+        if ((e = launch_form(c, c.cond_prec, m0, m1, -1, duhat)) != hipSuccess) return e;
+        if ((e = launch_lu(c, c.cond_prec, j, true, -1, true)) != hipSuccess) return e;
+        if ((e = backsolve_range(c, duhat, dq, du, m0, m1, nu, nb, true)) != hipSuccess) return e;
+      }
+    } else if (!todo.empty()) {
+      if ((e = form_stream_ready(c)) != hipSuccess) return e;
+      hipStream_t fs = c.form_stream;
+      hipEvent_t* ev = c.form_events;  // [0] start, [1 + b] slot b formed, [3 + b] slot b free
+      // duhat and the recoveries from the resident chunks (which read both slots) come first
+      if ((e = hipEventRecord(ev[0], c.stream)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(fs, ev[0], 0)) != hipSuccess) return e;
+      bool used[2] = {false, false};
+      auto form = [&](int j) -> hipError_t {
+        hipError_t r;
+        const int b = j % 2;
+        if (used[b] && (r = hipStreamWaitEvent(fs, ev[3 + b], 0)) != hipSuccess) return r;
+        used[b] = true;
+        if ((r = launch_form(c, c.cond_prec, c.hm.chunk_first[j], c.hm.chunk_first[j + 1], -1, duhat, fs)) !=
+            hipSuccess)
+          return r;
+        return hipEventRecord(ev[1 + b], fs);
+      };
+      if ((e = form(todo[0])) != hipSuccess) return e;
+      for (size_t t = 0; t < todo.size(); ++t) {
+        const int j = todo[t], b = j % 2;
+        // the next chunk is formed ahead when it goes to the other slot
+        const bool ahead = t + 1 < todo.size() && todo[t + 1] % 2 != b;
+        if (ahead && (e = form(todo[t + 1])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(c.stream, ev[1 + b], 0)) != hipSuccess) return e;
+        if ((e = launch_lu(c, c.cond_prec, j, true, -1, true)) != hipSuccess) return e;
+        const int m0 = c.hm.chunk_first[j], m1 = c.hm.chunk_first[j + 1];
+        if ((e = backsolve_range(c, duhat, dq, du, m0, m1, nu, nb, true)) != hipSuccess) return e;
+        if ((e = hipEventRecord(ev[3 + b], c.stream)) != hipSuccess) return e;
+        if (t + 1 < todo.size() && !ahead && (e = form(todo[t + 1])) != hipSuccess) return e;
+      }
     }
   }
   hipLaunchKernelGGL(k_bs_dq, dim3(nm * c.cd.dim * c.cd.ns), dim3(256), 0, c.stream, c.md, 0, c.ws.RQt, du, duhat, dq);

@@ -408,7 +408,7 @@ size_t form_lds_bytes(const HdgContext& c, int nr, size_t elem, int n_cols) {
 }
 
 template <class TW, int NR, int NT>
-hipError_t form_launch(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only_class, int n_cols,
+hipError_t form_launch(HdgContext& c, hipStream_t s, int m0, int m1, TW* W, double* gloc, int only_class, int n_cols,
                        int split_cols, const double* duhat) {
   FormPtrs fp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.ws.RQt, c.ws.RBloc, gloc,
               c.nsA, c.dnsA, c.sub_stride, c.off_AUB, c.off_ABU, c.off_ABQ, c.off_ABB, c.hm.row_off[m0] / NR,
@@ -416,12 +416,13 @@ hipError_t form_launch(HdgContext& c, int m0, int m1, TW* W, double* gloc, int o
   const long long nblk = (c.hm.row_off[m1] - c.hm.row_off[m0]) / NR;
   if (nblk <= 0) return hipSuccess;
   const size_t shm = form_lds_bytes(c, NR, sizeof(TW), n_cols);
-  hipLaunchKernelGGL((k_form<TW, NR, NT>), dim3((unsigned)nblk), dim3(NT), shm, c.stream, c.md, fp, W);
+  hipLaunchKernelGGL((k_form<TW, NR, NT>), dim3((unsigned)nblk), dim3(NT), shm, s, c.md, fp, W);
   return hipGetLastError();
 }
 
 template <class TW>
-hipError_t form_all(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only_class, const double* duhat) {
+hipError_t form_all(HdgContext& c, hipStream_t s, int m0, int m1, TW* W, double* gloc, int only_class,
+                    const double* duhat) {
   // classes whose n_s row buffers fit in LDS go to the grouped launch
   const int ns = c.hm.ns;
   int cols_g = -1, cols_1 = -1;
@@ -432,10 +433,10 @@ hipError_t form_all(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only
   const int split = (cols_g >= 0 && cols_1 >= 0) ? cols_g : -1;
   hipError_t e = hipSuccess;
   if (cols_g >= 0)
-    e = ns == 5 ? form_launch<TW, 5, 512>(c, m0, m1, W, gloc, only_class, cols_g, split, duhat)
-                : form_launch<TW, 4, 512>(c, m0, m1, W, gloc, only_class, cols_g, split, duhat);
+    e = ns == 5 ? form_launch<TW, 5, 512>(c, s, m0, m1, W, gloc, only_class, cols_g, split, duhat)
+                : form_launch<TW, 4, 512>(c, s, m0, m1, W, gloc, only_class, cols_g, split, duhat);
   if (e == hipSuccess && cols_1 >= 0)
-    e = form_launch<TW, 1, 256>(c, m0, m1, W, gloc, only_class, cols_1, split, duhat);
+    e = form_launch<TW, 1, 256>(c, s, m0, m1, W, gloc, only_class, cols_1, split, duhat);
   return e;
 }
 
@@ -444,11 +445,21 @@ hipError_t form_all(HdgContext& c, int m0, int m1, TW* W, double* gloc, int only
 // Groups of n_s rows for the classes whose row buffers fit in LDS (every
 // row of a group shares its target indices; 512 threads), single rows of
 // 256 threads for the larger classes.
-hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class, const double* rhs_duhat) {
+hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class, const double* rhs_duhat,
+                       hipStream_t s) {
   // FP32 storage: g of the trace rows stays in FP64 (it is O(1) per macro but
   // cancels between the two sides of a face in the assembled b-hat)
   double* gloc = prec == 1 ? c.ws.gloc : nullptr;
+  if (!s) s = c.stream;
   if (prec == 1)
-    return form_all<float>(c, m0, m1, reinterpret_cast<float*>(c.ws.Wm), gloc, only_class, rhs_duhat);
-  return form_all<double>(c, m0, m1, c.ws.Wm, gloc, only_class, rhs_duhat);
+    return form_all<float>(c, s, m0, m1, reinterpret_cast<float*>(c.ws.Wm), gloc, only_class, rhs_duhat);
+  return form_all<double>(c, s, m0, m1, c.ws.Wm, gloc, only_class, rhs_duhat);
+}
+
+hipError_t form_stream_ready(HdgContext& c) {
+  hipError_t e;
+  if (!c.form_stream && (e = hipStreamCreateWithFlags(&c.form_stream, hipStreamNonBlocking)) != hipSuccess) return e;
+  for (hipEvent_t& ev : c.form_events)
+    if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+  return hipSuccess;
 }

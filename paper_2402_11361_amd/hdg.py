@@ -67,7 +67,7 @@ EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_o
            "hdg_destroy", "hdg_status_string", "hdg_last_error", "hdg_get_condensed", "hdg_get_formed",
            "hdg_get_residuals", "hdg_precond_apply", "hdg_coarse_size", "hdg_coarse_restrict", "hdg_coarse_neighbours",
            "hdg_coarse_prolong", "hdg_mlp_param_count", "hdg_mlp_work_floats", "hdg_mlp_forward",
-           "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking",
+           "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking", "hdg_set_chunk_buffers",
            "hdg_autotune", "hdg_class_count", "hdg_get_tuning", "hdg_set_tuning",
            "hdg_condense_first_layer", "hdg_flow_diagnostics", "hdg_flow_diagnostics_noalloc",
            "hdg_nested_dims", "hdg_condense_nested", "hdg_nested_solve"]
@@ -91,6 +91,7 @@ def load_library(path=LIB_PATH):
     lib.hdg_node_coords.argtypes = [vp, vp, vp]
     lib.hdg_bind_workspace.argtypes = [vp, vp, sz]
     lib.hdg_set_chunking.argtypes = [vp, i]
+    lib.hdg_set_chunk_buffers.argtypes = [vp, i]
     ip = ctypes.POINTER(ctypes.c_int)
     lib.hdg_autotune.argtypes = [vp, i, ctypes.c_char_p, ip]
     lib.hdg_class_count.argtypes = [vp, ip]
@@ -191,6 +192,7 @@ class Context:
         self.n_u_macro, self.n_b_macro = s.n_u_macro, s.n_b_macro
         self.workspace_bytes = s.workspace_bytes
         self.chunk_macros = 0
+        self.chunk_buffers = 1
         self.dim = dim
         self.ws = None
         # per-macro offsets in u (q: dim * u_off) and in the local trace vectors
@@ -219,6 +221,17 @@ class Context:
         self._check(self.lib.hdg_query_sizes(self.h, ctypes.byref(s)))
         self.workspace_bytes = s.workspace_bytes
         self.chunk_macros = int(macros_per_chunk)
+
+    def set_chunk_buffers(self, n_buffers):
+        """Chunk slots of W (1 or 2; with 2 the next chunk is formed beside
+        the elimination of this one).  Re-plans the workspace like
+        set_chunking; bind_workspace() must follow."""
+        self._check(self.lib.hdg_set_chunk_buffers(self.h, int(n_buffers)))
+        self.ws = None
+        s = _Sizes()
+        self._check(self.lib.hdg_query_sizes(self.h, ctypes.byref(s)))
+        self.workspace_bytes = s.workspace_bytes
+        self.chunk_buffers = int(n_buffers)
 
     def fit_chunking(self, budget_bytes):
         """Largest macros per chunk (0 = no chunking) whose workspace fits in

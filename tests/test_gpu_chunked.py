@@ -8,13 +8,20 @@ from gpu_common import make_pair, to_dev, say
 
 pytestmark = pytest.mark.gpu
 
+# (mesh, macros per chunk, chunk slots of W)
 CASES = {
     # 8 macros in chunks of 3, 3, 2
-    "3d_per_p2_chunk3": (dict(dim=3, n_elem=4, m=2, p=2, periodic=True), 3),
+    "3d_per_p2_chunk3": (dict(dim=3, n_elem=4, m=2, p=2, periodic=True), 3, 1),
     # 4 macro shapes; chunks of 2 hold macros of different classes
-    "3d_per_uneven_p2_chunk2": (dict(dim=3, seg=[[2, 3], [3, 2], [2, 2]], p=2, periodic=True), 2),
+    "3d_per_uneven_p2_chunk2": (dict(dim=3, seg=[[2, 3], [3, 2], [2, 2]], p=2, periodic=True), 2, 1),
     # boundary faces; single-macro chunks
-    "2d_dir_p3_chunk1": (dict(dim=2, n_elem=4, m=2, p=3, periodic=False, state="shear", mach=0.2), 1),
+    "2d_dir_p3_chunk1": (dict(dim=2, n_elem=4, m=2, p=3, periodic=False, state="shear", mach=0.2), 1, 1),
+    # two slots: chunk j + 1 formed beside the elimination of chunk j; the
+    # recovery starts from the last two chunks and forms the other two again
+    "3d_per_p2_chunk2_2slots": (dict(dim=3, n_elem=4, m=2, p=2, periodic=True), 2, 2),
+    # two slots, several classes per chunk, chunks of 3, 3, 2 in slots 0, 1, 0
+    # (the recovery forms the first chunk again)
+    "3d_per_uneven_p2_chunk3_2slots": (dict(dim=3, seg=[[2, 3], [3, 2], [2, 3]], p=2, periodic=True), 3, 2),
 }
 
 TOL32 = 5e-4
@@ -31,10 +38,11 @@ def pairs():
 
 def _get(pairs, name):
     if name not in pairs:
-        case, per = CASES[name]
+        case, per, slots = CASES[name]
         say(f"[chunked setup] {name}")
         S, inp, ctx = make_pair(case)
         ctx.set_chunking(per)
+        ctx.set_chunk_buffers(slots)
         ctx.bind_workspace()
         d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
         ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
@@ -73,6 +81,19 @@ def test_chunked_fp64_matches_oracle(pairs, name):
     edu, edq = _rel(du.cpu().numpy(), du_o), _rel(dq.cpu().numpy(), dq_o)
     say(f"[chunked fp64] {name}: dU {edu:.2e} dQ {edq:.2e}")
     assert edu < 1e-10 and edq < 1e-10
+    # the chunk condensed last was recovered from its elimination left in W;
+    # a second recovery (W then holds recovery forms), and one after the
+    # inspection of a formed matrix wrote W, form every chunk again
+    for redo in ("second recovery", "after get_formed"):
+        if redo == "after get_formed":
+            ctx.condense(bhat)
+            ctx.get_formed(0)
+        dq.zero_()
+        du.zero_()
+        ctx.local_backsolve(to_dev(x_ref), dq, du)
+        edu, edq = _rel(du.cpu().numpy(), du_o), _rel(dq.cpu().numpy(), dq_o)
+        say(f"[chunked fp64] {name}, {redo}: dU {edu:.2e} dQ {edq:.2e}")
+        assert edu < 1e-10 and edq < 1e-10
     # an FP32 inner operator needs an FP32 condensation when chunked
     from paper_2402_11361_amd.hdg import HDG_FP32, HdgError
     with pytest.raises(HdgError, match="EUNSUPPORTED"):
@@ -108,6 +129,11 @@ def test_chunked_fp32_matches_oracle(pairs, name):
     dq_o, du_o = S.backsolve(lin, cond, x_ref)
     # refined in FP64 against the u-rows' residual (FP32 factors only precondition it)
     assert _rel(du.cpu().numpy(), du_o) < 1e-10 and _rel(dq.cpu().numpy(), dq_o) < 1e-10
+    # the last chunk from the condensation's factors above; every chunk formed again here
+    dq.zero_()
+    du.zero_()
+    ctx.local_backsolve(to_dev(x_ref), dq, du)
+    assert _rel(du.cpu().numpy(), du_o) < 1e-10 and _rel(dq.cpu().numpy(), dq_o) < 1e-10
 
 
 def test_chunked_formed_matrix_of_a_middle_chunk(pairs):
@@ -131,7 +157,7 @@ def test_chunked_newton_refines_fp32_to_oracle():
     from oracle.newton import newton_solve
     from paper_2402_11361_amd.driver import StageDriver
     from paper_2402_11361_amd.hdg import HDG_FP32
-    case, per = CASES["3d_per_uneven_p2_chunk2"]
+    case, per, _ = CASES["3d_per_uneven_p2_chunk2"]
     say("[chunked newton] 3d_per_uneven_p2 chunks of 2, FP32")
     S, inp, ctx = make_pair(case)
     ctx.set_chunking(per)

@@ -34,6 +34,8 @@ def test_calls_without_workspace_and_bad_arguments():
     with pytest.raises(HdgError, match="EINVAL"):
         ctx.set_chunking(-1)
     with pytest.raises(HdgError, match="EINVAL"):
+        ctx.set_chunk_buffers(3)
+    with pytest.raises(HdgError, match="EINVAL"):
         ctx.set_tuning(0, 0, 6)  # tiles per workgroup not a multiple of 4
     ctx.close()
 
