@@ -151,7 +151,7 @@ def big_variant(args, dev_fn, variants):
     import torch
     from paper_2402_11361_amd import inputs
     from paper_2402_11361_amd.driver import StageDriver
-    from paper_2402_11361_amd.hdg import HDG_FP32, Context, mesh_spec_box
+    from paper_2402_11361_amd.hdg import HDG_FP32, HDG_FP64, Context, mesh_spec_box
     cfg = dict(inputs.CONFIGS["tgv48_m4_p2"])
     spec = mesh_spec_box(3, cfg["n_elem"], cfg["m"], cfg["p"], cfg["lo"], cfg["hi"], True)
     stream = torch.cuda.current_stream()
@@ -159,6 +159,12 @@ def big_variant(args, dev_fn, variants):
     free, _ = torch.cuda.mem_get_info()
     ctx.set_chunk_buffers(args.chunk_slots)
     per = ctx.fit_chunking(free - (8 << 30))
+    store = None
+    if args.factor_store != "none" and per:
+        per = max(1, int(per * args.store_chunk_frac))
+        ctx.set_chunking(per)
+        store = dict(prec=args.factor_store,
+                     macros=ctx.fit_factor_store(free - (8 << 30), HDG_FP32 if args.factor_store == "fp32" else HDG_FP64))
     ctx.bind_workspace()
     u0, q0, uh0 = workload_arrays(ctx, cfg)
     q, u, uh = dev_fn(q0), dev_fn(u0), dev_fn(uh0)
@@ -194,7 +200,7 @@ def big_variant(args, dev_fn, variants):
                  f"n_glob {ctx.n_glob}; {per} macros per condensation chunk; FP32 condensation refined by Newton, "
                  "FP32 inner operator, graph-captured FGMRES steps"
                  + ("; learned coarse correction judged by the plain preconditioner" if learned else ""),
-        macros_per_chunk=per, chunk_slots=args.chunk_slots, workspace_gb=round(ctx.workspace_bytes / 1e9, 1), learned=learned,
+        macros_per_chunk=per, chunk_slots=args.chunk_slots, factor_store=store, workspace_gb=round(ctx.workspace_bytes / 1e9, 1), learned=learned,
         ms_per_step_mean=round(float(np.mean(ms)), 1) if ms else None,
         ms_per_stage_mean=round(float(np.mean(ms)) / 3, 1) if ms else None, time_steps=steps)
     ctx.close()
@@ -773,6 +779,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="tgv48_m4_p2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--factor-store", default="fp32", choices=("none", "fp32", "fp64"),
+                    help="keep the S factors of the leading chunks for the recovery (FP32 copies refined in FP64, "
+                         "or FP64)")
+    ap.add_argument("--store-chunk-frac", type=float, default=0.5,
+                    help="with --factor-store: chunk size as a fraction of the largest that fits")
     ap.add_argument("--chunk-slots", type=int, default=1, choices=(1, 2),
                     help="chunk slots of the condensation buffer (2: the next chunk is formed beside the "
                          "elimination of this one)")
@@ -844,9 +855,16 @@ def main():
     free, _ = torch.cuda.mem_get_info()
     ctx.set_chunk_buffers(args.chunk_slots)
     per_chunk = ctx.fit_chunking(free - (8 << 30))
+    store = None
+    if args.factor_store != "none" and per_chunk:
+        # smaller chunks leave room for the factor store of the leading chunks
+        per_chunk = max(1, int(per_chunk * args.store_chunk_frac))
+        ctx.set_chunking(per_chunk)
+        sprec = HDG_FP32 if args.factor_store == "fp32" else HDG_FP64
+        store = dict(prec=args.factor_store, macros=ctx.fit_factor_store(free - (8 << 30), sprec))
     ctx.bind_workspace()
     say(f"{args.config}: {ctx.n_macros} macros, n_glob {ctx.n_glob}, workspace {ctx.workspace_bytes / 1e9:.1f} GB, "
-        f"{per_chunk or ctx.n_macros} macros per condensation chunk")
+        f"{per_chunk or ctx.n_macros} macros per condensation chunk, factor store {store}")
     u0, q0, uh0 = workload_arrays(ctx, cfg)
     q_init, u_init, uh_init = dev(q0), dev(u0), dev(uh0)
     A, _, _ = alexander_dirk33()
@@ -941,7 +959,7 @@ def main():
                                     f"linearise, second-layer condensation in {(nm + (per_chunk or nm) - 1) // (per_chunk or nm)} "
                                     f"chunks, FGMRES(30) rtol {cfg['rtol']} with 5 inner GMRES steps, recovery, update",
                            n_macros=nm, n_u_macro=nu, n_b_macro=nb, n_glob=n_glob,
-                           macros_per_chunk=per_chunk, chunk_slots=args.chunk_slots,
+                           macros_per_chunk=per_chunk, chunk_slots=args.chunk_slots, factor_store=store,
                            variant="plain FP64" if main_prec == HDG_FP64 else "FP32 condensation"),
                phases_ms={k: round(v, 3) for k, v in plain["phase_ms"].items()},
                fgmres=dict(outer_its=plain["outer"], inner_its=plain["inner"]),

@@ -202,6 +202,24 @@ hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk);
  * workspace like hdg_set_chunking.  HDG_EINVAL for other values. */
 hdg_status hdg_set_chunk_buffers(hdg_ctx ctx, int n_buffers);
 
+/* Factor store for the recovery under chunked condensation: hdg_condense
+ * copies the LU factors of S (P S = L U of eq. ASC2, the top-left n_u x n_u
+ * of each eliminated matrix, 16 x 64 tiles with ld = n_u rounded up to 64)
+ * of the macros of the leading whole chunks that fit in n_macros (never the
+ * last chunk of a W slot, which stays in W) into workspace memory of type
+ * prec (HDG_FP64: 8, HDG_FP32: 4 bytes per entry).  hdg_local_backsolve then
+ * solves S dU = r for those macros from the store, with r the residual of
+ * the u-rows of eq. C44 in FP64 (dQ from eq. Csc4b): once for FP64 factors
+ * of an FP64 condensation, three FP64 refinement sweeps for FP32 factors
+ * (or an FP32 condensation), instead of forming and factoring their S again.
+ * The pivots are the condensation's.  hdg_linearize_stage, hdg_autotune,
+ * hdg_condense_first_layer and any re-planning invalidate the store until
+ * the next hdg_condense.  Re-plans the workspace like hdg_set_chunking.
+ * HDG_EINVAL for n_macros < 0, HDG_EUNSUPPORTED for other precisions. */
+hdg_status hdg_set_factor_store(hdg_ctx ctx, int n_macros, hdg_prec prec);
+/* Macros the factor store holds under the current plan (whole chunks). */
+hdg_status hdg_factor_store_macros(hdg_ctx ctx, int* n_stored);
+
 /* Autotuner of the batched elimination of hdg_condense: for every macro
  * class (one per macro shape) and the given condensation precision, times
  * the class's elimination (HIP events on the context's stream, after one

@@ -434,6 +434,7 @@ hdg_status hdg_set_chunking(hdg_ctx ctx, int macros_per_chunk) {
   c.lrn_bound = false;
   c.condensed64 = false;
   c.forget_w();
+  c.store_valid = false;
   c.have_a32 = false;
   c.have_a16 = false;
   clear_graphs(c);
@@ -456,9 +457,42 @@ hdg_status hdg_set_chunk_buffers(hdg_ctx ctx, int n_buffers) {
   c.lrn_bound = false;
   c.condensed64 = false;
   c.forget_w();
+  c.store_valid = false;
   c.have_a32 = false;
   c.have_a16 = false;
   clear_graphs(c);
+  return HDG_OK;
+}
+
+hdg_status hdg_set_factor_store(hdg_ctx ctx, int n_macros, hdg_prec prec) {
+  if (!ctx) return HDG_EINVAL;
+  HdgContext& c = ctx->c;
+  if (n_macros < 0) return fail(&c, HDG_EINVAL, "n_macros must be >= 0");
+  if (prec != HDG_FP64 && prec != HDG_FP32) return fail(&c, HDG_EUNSUPPORTED, "factor store precision not built");
+  HIPCHK(&c, hipStreamSynchronize(c.stream));
+  c.hm.store_macros = n_macros;
+  c.hm.store_prec = prec == HDG_FP32 ? 1 : 0;
+  plan_workspace(c);
+  try {
+    upload_w_offsets(c);
+  } catch (const std::exception& ex) {
+    return fail(&c, HDG_EDEVICE, ex.what());
+  }
+  c.ws_bound = false;
+  c.lrn_bound = false;
+  c.condensed64 = false;
+  c.forget_w();
+  c.store_valid = false;
+  c.have_a32 = false;
+  c.have_a16 = false;
+  clear_graphs(c);
+  return HDG_OK;
+}
+
+hdg_status hdg_factor_store_macros(hdg_ctx ctx, int* n_stored) {
+  if (!ctx || !n_stored) return HDG_EINVAL;
+  const HostMesh& hm = ctx->c.hm;
+  *n_stored = hm.store_chunks > 0 ? hm.chunk_first[hm.store_chunks] : 0;
   return HDG_OK;
 }
 
@@ -476,14 +510,14 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
     rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.gloc); rebase(c.ws.Wm);
     rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.A16); rebase(c.ws.ypart); rebase(c.ws.kry);
     rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn); rebase(c.ws.kctl); rebase(c.ws.supg);
-    rebase(c.ws.Ac); rebase(c.ws.bloc);
+    rebase(c.ws.Ac); rebase(c.ws.bloc); rebase(c.ws.Fst);
   } else {
     auto rebase = [&](auto*& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(base + reinterpret_cast<uintptr_t>(p)); };
     rebase(c.ws.Kq); rebase(c.ws.AUU); rebase(c.ws.AUQ); rebase(c.ws.RUe); rebase(c.ws.RQe); rebase(c.ws.SUB);
     rebase(c.ws.RU); rebase(c.ws.RQ); rebase(c.ws.RQt); rebase(c.ws.RBloc); rebase(c.ws.RBglob); rebase(c.ws.gloc); rebase(c.ws.Wm);
     rebase(c.ws.ipiv); rebase(c.ws.FW); rebase(c.ws.fpiv); rebase(c.ws.A32); rebase(c.ws.A16); rebase(c.ws.ypart); rebase(c.ws.kry);
     rebase(c.ws.red); rebase(c.ws.small); rebase(c.ws.Uinv); rebase(c.ws.lrn); rebase(c.ws.kctl); rebase(c.ws.supg);
-    rebase(c.ws.Ac); rebase(c.ws.bloc);
+    rebase(c.ws.Ac); rebase(c.ws.bloc); rebase(c.ws.Fst);
   }
   c.ws.base = base;
   c.lrn_bound = false;
@@ -495,6 +529,7 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes) {
   c.linearized = false;
   c.condensed64 = false;
   c.forget_w();
+  c.store_valid = false;
   return HDG_OK;
 }
 
@@ -507,6 +542,7 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
   const int p32 = prec == HDG_FP32 ? 1 : 0;
   c.condensed64 = false;  // the trials overwrite W (also when one fails)
   c.forget_w();
+  c.store_valid = false;
   int dev = 0, rt = 0;
   HIPCHK(&c, hipGetDevice(&dev));
   hipDeviceProp_t prop;
@@ -617,6 +653,7 @@ hdg_status hdg_autotune(hdg_ctx ctx, hdg_prec prec, const char* cache_path, int*
   c.have_a16 = false;
   c.condensed64 = false;
   c.forget_w();
+  c.store_valid = false;
   return HDG_OK;
 }
 
@@ -654,12 +691,14 @@ hdg_status hdg_linearize_stage(hdg_ctx ctx, const double* q, const double* u, co
   if (!c.ws_bound) return fail(&c, HDG_ENOMEM, "no workspace bound");
   if (!(dt > 0) || !(dtau > 0) || std::isnan(d_ii)) return fail(&c, HDG_EINVAL, "dt and dtau must be positive");
   StageArgs sa{dt, d_ii, dtau};
-  HIPCHK(&c, launch_linearize(c, q, u, uhat, w, sa));
-  c.linearized = true;
+  // the element blocks (and, chunked, W) change from here on
   c.condensed64 = false;
   c.forget_w();
+  c.store_valid = false;
   c.have_a32 = false;
   c.have_a16 = false;
+  HIPCHK(&c, launch_linearize(c, q, u, uhat, w, sa));
+  c.linearized = true;
   if (norms_host) {
     HIPCHK(&c, launch_norms(c, c.ws.small + 2048));
     HIPCHK(&c, hipMemcpyAsync(ctx->pinned, c.ws.small + 2048, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
@@ -681,6 +720,7 @@ static hipError_t condense_chunks(HdgContext& c, int p32) {
     for (int j = 0; j < nch; ++j) {
       if ((e = launch_form(c, p32, c.hm.chunk_first[j], c.hm.chunk_first[j + 1])) != hipSuccess) return e;
       if ((e = launch_lu(c, p32, j, false)) != hipSuccess) return e;
+      if ((e = launch_store_factors(c, p32, j)) != hipSuccess) return e;
       if (c.hm.chunked() && (e = launch_extract(c, p32, j)) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -705,6 +745,7 @@ static hipError_t condense_chunks(HdgContext& c, int p32) {
     if (j + 1 < nch && (e = form(j + 1)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(c.stream, ev[1 + b], 0)) != hipSuccess) return e;
     if ((e = launch_lu(c, p32, j, false)) != hipSuccess) return e;
+    if ((e = launch_store_factors(c, p32, j)) != hipSuccess) return e;
     if ((e = launch_extract(c, p32, j)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev[3 + b], c.stream)) != hipSuccess) return e;
   }
@@ -723,6 +764,7 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
   c.bf16_update = (prec == HDG_BF16);
   c.condensed64 = false;
   c.forget_w();
+  c.store_valid = false;
   // status flags: one per (chunk, macro class), then one for the face blocks
   const int ncl = c.hm.n_classes, nch = c.hm.n_chunks(), nst = nch * ncl;
   int* status = reinterpret_cast<int*>(c.ws.small);
@@ -751,6 +793,7 @@ hdg_status hdg_condense(hdg_ctx ctx, hdg_prec prec, double* bhat) {
   c.condensed64 = (p32 == 0);
   if (c.hm.chunked())  // the last chunk of each slot
     for (int i = 0; i < c.hm.slots(); ++i) c.w_res[i] = nch - 1 - i;
+  c.store_valid = c.hm.store_chunks > 0;
   return HDG_OK;
 }
 
@@ -834,6 +877,7 @@ hdg_status hdg_condense_first_layer(hdg_ctx ctx, double* bhat) {
   if (!c.hm.chunked() || c.hm.n_classes != 1)
     return fail(&c, HDG_EUNSUPPORTED, "first-layer condensation needs chunking and a single macro shape");
   c.forget_w();  // W holds the first-layer matrices from here on
+  c.store_valid = false;
   int* status = reinterpret_cast<int*>(c.ws.small);
   const int nst = c.hm.n_chunks() * c.hm.n_classes;
   HIPCHK(&c, launch_zero_ints(c.stream, status, nst + 1));

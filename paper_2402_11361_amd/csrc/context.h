@@ -57,6 +57,14 @@ struct HostMesh {
   // of them.
   int chunk_macros = 0;                  // requested macros per chunk (0: all at once)
   int chunk_buffers = 1;                 // chunk slots in W (2: the next chunk is formed beside this one's elimination)
+  // factor store: copies of the LU factors of S (the top-left n_u x n_u of the
+  // eliminated W, tiled 16 x 64 with ld = n_u rounded up to 64) of the macros
+  // of the leading chunks [0, store_chunks), in store_prec (0 FP64, 1 FP32),
+  // at st_off[macro] (-1: not stored) in elements of that type
+  int store_macros = 0;                  // requested number of macros
+  int store_prec = 1;
+  int store_chunks = 0;
+  std::vector<long long> st_off;         // [n_macros]
   std::vector<int> chunk_first;          // [n_chunks + 1]
   std::vector<long long> chunk_class_w;  // [n_chunks * n_classes]
   std::vector<int> chunk_class_cnt, chunk_class_rank0;
@@ -97,6 +105,7 @@ struct Workspace {
   // chunked condensation only (Wm then holds one chunk and shares its memory with Kq)
   double* Ac = nullptr;     // [macros][n_b][n_b] compact A-hat (FP64, or FP32 in the first half)
   double* bloc = nullptr;   // [macros][n_b] b-hat^{T_i}
+  double* Fst = nullptr;    // factor store (FP64 or FP32 elements at HostMesh::st_off)
 };
 
 struct HdgContext {
@@ -133,6 +142,8 @@ struct HdgContext {
   // last ones condensed, one per slot
   int w_res[2] = {-1, -1};
   void forget_w() { w_res[0] = w_res[1] = -1; }
+  bool store_valid = false;             // the factor store holds the factors of the last hdg_condense
+  const long long* st_off_dev = nullptr; // device copy of HostMesh::st_off
   std::shared_ptr<NestedPlan> nested;  // nested condensation for one block size (built on first use)
   int nested_m = 0;                    // its block size
   bool bf16_update = false;  // the last condensation took BF16 operands in its trailing updates

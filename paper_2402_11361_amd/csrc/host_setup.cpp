@@ -525,6 +525,20 @@ void plan_workspace(HdgContext& c) {
     }
     for (int k = 0; k < ncl; ++k) rank[k] += cnt[k];
   }
+  // factor store: whole leading chunks, never the last chunk of a slot
+  // (whose eliminations stay in W)
+  hm.store_chunks = 0;
+  hm.st_off.assign(nm, -1);
+  long long st_elems = 0;
+  if (hm.chunked() && hm.store_macros > 0)
+    for (int j = 0; j < nch - hm.slots() && hm.chunk_first[j + 1] <= hm.store_macros; ++j) {
+      for (int i = hm.chunk_first[j]; i < hm.chunk_first[j + 1]; ++i) {
+        const int nu = c.hcs[hm.macro_class[i]].n_u;
+        hm.st_off[i] = st_elems;
+        st_elems += (long long)((nu + 15) / 16 * 16) * ((nu + 63) / 64 * 64);
+      }
+      hm.store_chunks = j + 1;
+    }
   // slot j % slots of W for chunk j
   const int slots = hm.slots();
   if (slots > 1)
@@ -561,7 +575,7 @@ void plan_workspace(HdgContext& c) {
   }
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
-  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, gloc, Wm, ipiv, FW, fpiv, A32, A16, ypart, kry, red, small, Uinv, lrn, kctl, supg, Ac, bloc; } o;
+  struct { size_t Kq, AUU, AUQ, RUe, RQe, SUB, RU, RQ, RQt, RBloc, RBglob, gloc, Wm, ipiv, FW, fpiv, A32, A16, ypart, kry, red, small, Uinv, lrn, kctl, supg, Ac, bloc, Fst; } o;
   const bool chunked = hm.chunked();
   const size_t kq_bytes = sizeof(double) * n_el * c.Kstride;
   // chunked: Kq (used only inside the linearisation) shares the W buffer
@@ -619,6 +633,7 @@ void plan_workspace(HdgContext& c) {
   o.supg = take(sizeof(double) * (size_t)c.supg_chunk * (c.ph.supg ? supg_scratch_per_element(hc.dim, hc.p) : 0));
   o.Ac = take(chunked ? sizeof(double) * (size_t)hm.a32_off[nm] : 0);
   o.bloc = take(chunked ? sizeof(double) * (size_t)hm.b_off[nm] : 0);
+  o.Fst = take((hm.store_prec == 1 ? sizeof(float) : sizeof(double)) * (size_t)st_elems);
   c.need_bytes = off;
   // remember offsets in the workspace struct (resolved on bind)
   c.ws.bytes = 0;
@@ -650,6 +665,7 @@ void plan_workspace(HdgContext& c) {
   c.ws.supg = reinterpret_cast<double*>(o.supg);
   c.ws.Ac = reinterpret_cast<double*>(o.Ac);
   c.ws.bloc = reinterpret_cast<double*>(o.bloc);
+  c.ws.Fst = reinterpret_cast<double*>(o.Fst);
 }
 
 void node_coords(const HdgContext& c, double* macro_xyz, double* face_xyz) {
@@ -747,17 +763,20 @@ void upload_tables(HdgContext& c) {
   md.elem_macro = up(c, hm.elem_macro); md.sub_off = up(c, hm.sub_off); md.row_off = up(c, hm.row_off);
   md.w_off = up(c, hm.w_off); md.a32_off = up(c, hm.a32_off); md.ipiv_off = up(c, hm.ipiv_off);
   md.face_slot = up(c, hm.face_slot);
+  c.st_off_dev = up(c, hm.st_off);
 }
 
 // Replaces the device copy of the per-macro W offsets (after a new chunking).
 void upload_w_offsets(HdgContext& c) {
-  const void* old = c.md.w_off;
+  const void* old[2] = {c.md.w_off, c.st_off_dev};
   c.md.w_off = up(c, c.hm.w_off);
-  for (auto it = c.dev_allocs.begin(); it != c.dev_allocs.end(); ++it)
-    if (*it == old) {
-      (void)hipFree(*it);
-      c.dev_allocs.erase(it);
-      break;
-    }
+  c.st_off_dev = up(c, c.hm.st_off);
+  for (const void* o : old)
+    for (auto it = c.dev_allocs.begin(); it != c.dev_allocs.end(); ++it)
+      if (*it == o) {
+        (void)hipFree(*it);
+        c.dev_allocs.erase(it);
+        break;
+      }
 }
 

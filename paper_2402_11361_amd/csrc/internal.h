@@ -157,6 +157,9 @@ hipError_t form_stream_ready(HdgContext& c);
 hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only_class = -1, bool rhs_only = false);
 // chunked condensation: A-hat^{T_i} and b-hat^{T_i} of chunk j out of W
 hipError_t launch_extract(HdgContext& c, int prec, int chunk);
+// chunked condensation: the factors of S of chunk j into the factor store
+// (nothing for chunks it does not keep)
+hipError_t launch_store_factors(HdgContext& c, int prec, int chunk);
 hipError_t launch_bhat(HdgContext& c, double* bhat, int prec);
 hipError_t launch_face_precond(HdgContext& c);
 hipError_t launch_apply(HdgContext& c, const double* x, double* y, int prec);

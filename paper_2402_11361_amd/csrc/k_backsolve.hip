@@ -74,17 +74,53 @@ __global__ void __launch_bounds__(256) k_bs_col(MeshDev md, int m0, const T* __r
   z[md.u_off[macro] + r] = (double)Wm[md.w_off[macro] + wtix(r, cd.n_u, cd.ldw)];
 }
 
+// Where the factors of macro's S are: its eliminated matrix in W, or (st_off
+// non-null) its copy in the factor store (n_u x n_u, ld = n_u rounded up to 64).
+template <class T>
+__device__ __forceinline__ const T* factors_of(const MeshDev& md, const ClassDev& cd, int macro, const T* base,
+                                               const long long* st_off, int& ld) {
+  if (st_off) {
+    ld = (cd.n_u + 63) / 64 * 64;
+    return base + st_off[macro];
+  }
+  ld = cd.ldw;
+  return base + md.w_off[macro];
+}
+
+// Copy of the LU factors of S (the top-left n_u x n_u of each eliminated
+// matrix of macros [m0, m0 + gridDim.y)) from W (type TW) to the factor
+// store (type TS), tile by tile (16 x 64 tiles, the store's ld = n_u rounded
+// up to 64; the columns past n_u of the last tile column carry W's values,
+// which the solves never read).
+template <class TW, class TS>
+__global__ void __launch_bounds__(256) k_store_factors(MeshDev md, int m0, const TW* __restrict__ Wm,
+                                                       const long long* __restrict__ st_off, TS* __restrict__ Fst) {
+  const int macro = m0 + blockIdx.y;
+  const ClassDev& cd = class_of(md, macro);
+  const int nu = cd.n_u, ldu = (nu + 63) / 64 * 64;
+  const long long n = (long long)((nu + 15) / 16 * 16) * ldu;  // elements of the stored tiles
+  const TW* W = Wm + md.w_off[macro];
+  TS* F = Fst + st_off[macro];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    // i -> (tile row R, tile column Cb, element within the 16 x 64 tile)
+    const long long R = i / (16LL * ldu), rem = i % (16LL * ldu);
+    const int Cb = (int)(rem >> 10), e = (int)(rem & 1023);
+    F[i] = (TS)W[R * 16 * (long long)cd.ldw + (long long)Cb * 1024 + e];
+  }
+}
+
 // Backward substitution U du = z in place (z -> du), one workgroup per macro,
 // blocks of 64 rows from the bottom.
 template <class T>
 __global__ void __launch_bounds__(256) k_bs_trsv(MeshDev md, int m0, const T* __restrict__ Wm,
-                                                 double* __restrict__ du) {
+                                                 double* __restrict__ du, const long long* __restrict__ st_off = nullptr) {
   __shared__ double sU[BS_ROWS][BS_ROWS + 1];
   __shared__ double sz[BS_ROWS];
   const int macro = m0 + blockIdx.x;
   const ClassDev& cd = class_of(md, macro);
-  const int nu = cd.n_u, ld = cd.ldw;
-  const T* U = Wm + md.w_off[macro];
+  const int nu = cd.n_u;
+  int ld;
+  const T* U = factors_of(md, cd, macro, Wm, st_off, ld);
   double* x = du + md.u_off[macro];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nblk = (nu + BS_ROWS - 1) / BS_ROWS;
@@ -217,13 +253,15 @@ __global__ void __launch_bounds__(256) k_bs_resid(MeshDev md, int m0, ResidPtrs 
 // then its unit-lower columns in 64-column blocks; r staged in LDS (n_u doubles).
 template <class T>
 __global__ void __launch_bounds__(256) k_bs_fwd(MeshDev md, int m0, const T* __restrict__ Wm,
-                                                const int* __restrict__ ipiv_all, double* __restrict__ r) {
+                                                const int* __restrict__ ipiv_all, double* __restrict__ r,
+                                                const long long* __restrict__ st_off = nullptr) {
   extern __shared__ double rs[];
   __shared__ double sL[BS_ROWS][BS_ROWS + 1];
   const int macro = m0 + blockIdx.x;
   const ClassDev& cd = class_of(md, macro);
-  const int nu = cd.n_u, ld = cd.ldw;
-  const T* W = Wm + md.w_off[macro];
+  const int nu = cd.n_u;
+  int ld;
+  const T* W = factors_of(md, cd, macro, Wm, st_off, ld);
   const int* ipiv = ipiv_all + md.ipiv_off[macro];
   double* x = r + md.u_off[macro];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -265,6 +303,11 @@ __global__ void __launch_bounds__(256) k_bs_fwd(MeshDev md, int m0, const T* __r
   for (int i = tid; i < nu; i += blockDim.x) x[i] = rs[i];
 }
 
+__global__ void k_zero_range(long long n, double* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = 0.0;
+}
+
 __global__ void k_add_range(long long n, const double* __restrict__ x, double* __restrict__ y) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     y[i] += x[i];
@@ -277,6 +320,40 @@ __global__ void k_add_range(long long n, const double* __restrict__ x, double* _
 // after trailing updates with BF16 operands).
 constexpr int BS_REFINE_SWEEPS = 2;
 constexpr int BS_REFINE_SWEEPS_BF16 = 8;
+
+// Sweeps of du += S^{-1} r with r = the residual of the u-rows of eq. C44
+// (FP64, from the element blocks: dQ from du and duhat, then
+// -(R_U + A_uu du + A_uq dQ + A_u,uh duhat)) and S^{-1} applied with the
+// factors in W (st_off null) or in the factor store, of storage type T.
+// Starting from du = 0 the first sweep is the solve itself.  The Krylov
+// vectors are free during the recovery and hold r (n_u_tot doubles).
+template <class T>
+static void refine_range(HdgContext& c, const double* duhat, double* dq, double* du, int m0, int m1, int nu,
+                         const T* F, const long long* st_off, int sweeps) {
+  const int nm = m1 - m0;
+  double* r = c.ws.kry;
+  int nmax = 0;
+  for (const HostClass& k : c.hcs) nmax = std::max(nmax, k.N);
+  const ResidPtrs rp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.nsA, c.dnsA, c.sub_stride, c.off_AUB};
+  const long long u0 = c.hm.u_off[m0], nr = c.hm.u_off[m1] - u0;
+  const int nblk = (int)std::min<long long>((nr + 255) / 256, 65536);
+  for (int sweep = 0; sweep < sweeps; ++sweep) {
+    hipLaunchKernelGGL(k_bs_dq, dim3(nm * c.cd.dim * c.cd.ns), dim3(256), 0, c.stream, c.md, m0, c.ws.RQt, du, duhat,
+                       dq);
+    hipLaunchKernelGGL(k_bs_resid, dim3((nmax + 3) / 4, nm), dim3(256), 0, c.stream, c.md, m0, rp, du, dq, duhat, r);
+    hipLaunchKernelGGL(k_bs_fwd<T>, dim3(nm), dim3(256), (size_t)nu * sizeof(double), c.stream, c.md, m0, F,
+                       c.ws.ipiv, r, st_off);
+    hipLaunchKernelGGL(k_bs_trsv<T>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, F, r, st_off);
+    hipLaunchKernelGGL(k_add_range, dim3(nblk), dim3(256), 0, c.stream, nr, r + u0, du + u0);
+  }
+}
+
+// Sweeps of the recovery from the factor store: the FP64 factors of an FP64
+// condensation need the solve alone; FP32 factors (an FP32 store or an FP32
+// condensation) precondition FP64 refinement, each sweep gaining about the
+// FP32 rounding times the conditioning of S.
+constexpr int BS_STORE_SWEEPS_FP64 = 1;
+constexpr int BS_STORE_SWEEPS_FP32 = 3;
 
 // Macros [m0, m1) from their eliminated matrices in W.
 // rhs_in_w: W holds the eliminated recovery form (right-hand side in column
@@ -294,32 +371,17 @@ static hipError_t backsolve_range(HdgContext& c, const double* duhat, double* dq
     else
       hipLaunchKernelGGL(k_bs_rhs<float>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, m0, W32,
                          duhat, du);
-    hipLaunchKernelGGL(k_bs_trsv<float>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, W32, du);
-    // FP64 refinement: the Krylov vectors are free during the recovery and
-    // hold the residual (n_u_tot doubles)
-    double* r = c.ws.kry;
-    int nmax = 0;
-    for (const HostClass& k : c.hcs) nmax = std::max(nmax, k.N);
-    const ResidPtrs rp{c.ws.AUU, c.ws.AUQ, c.ws.SUB, c.ws.RU, c.nsA, c.dnsA, c.sub_stride, c.off_AUB};
-    const long long u0 = c.hm.u_off[m0], nr = c.hm.u_off[m1] - u0;
+    hipLaunchKernelGGL(k_bs_trsv<float>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, W32, du, nullptr);
+    // FP64 refinement against the u-rows' residual
     const int sweeps = (c.bf16_update && !rhs_in_w) ? BS_REFINE_SWEEPS_BF16 : BS_REFINE_SWEEPS;
-    for (int sweep = 0; sweep < sweeps; ++sweep) {
-      hipLaunchKernelGGL(k_bs_dq, dim3(nm * c.cd.dim * c.cd.ns), dim3(256), 0, c.stream, c.md, m0, c.ws.RQt, du, duhat,
-                         dq);
-      hipLaunchKernelGGL(k_bs_resid, dim3((nmax + 3) / 4, nm), dim3(256), 0, c.stream, c.md, m0, rp, du, dq, duhat, r);
-      hipLaunchKernelGGL(k_bs_fwd<float>, dim3(nm), dim3(256), (size_t)nu * sizeof(double), c.stream, c.md, m0, W32,
-                         c.ws.ipiv, r);
-      hipLaunchKernelGGL(k_bs_trsv<float>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, W32, r);
-      const int nblk = (int)std::min<long long>((nr + 255) / 256, 65536);
-      hipLaunchKernelGGL(k_add_range, dim3(nblk), dim3(256), 0, c.stream, nr, r + u0, du + u0);
-    }
+    refine_range<float>(c, duhat, dq, du, m0, m1, nu, W32, nullptr, sweeps);
   } else {
     if (rhs_in_w)
       hipLaunchKernelGGL(k_bs_col<double>, grid_col, dim3(256), 0, c.stream, c.md, m0, c.ws.Wm, du);
     else
       hipLaunchKernelGGL(k_bs_rhs<double>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, m0,
                          c.ws.Wm, duhat, du);
-    hipLaunchKernelGGL(k_bs_trsv<double>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, c.ws.Wm, du);
+    hipLaunchKernelGGL(k_bs_trsv<double>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, c.ws.Wm, du, nullptr);
   }
   return hipGetLastError();
 }
@@ -338,7 +400,7 @@ hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, doub
   const int nm = c.hm.n_macros;
   hipError_t e;
   // the refinement's residual lives in the Krylov vectors
-  if (c.cond_prec == 1 &&
+  if ((c.cond_prec == 1 || (c.store_valid && c.hm.store_chunks > 0)) &&
       c.n_u_tot > (long long)(2 * c.kry_restart_max + c.kry_inner_max + 8) * c.hm.n_glob)
     return hipErrorInvalidValue;
   if (!c.hm.chunked()) {
@@ -346,6 +408,24 @@ hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, doub
   } else {
     const int nch = c.hm.n_chunks();
     std::vector<char> done(nch, 0);
+    if (c.store_valid && c.hm.store_chunks > 0) {
+      // the leading chunks from the factor store, from du = 0
+      const int m1 = c.hm.chunk_first[c.hm.store_chunks];
+      const long long nr = c.hm.u_off[m1];
+      hipLaunchKernelGGL(k_zero_range, dim3((unsigned)std::min<long long>((nr + 255) / 256, 65536)), dim3(256), 0,
+                         c.stream, nr, du);
+      // the factors carry the precision of the condensation at best
+      const int sweeps = c.bf16_update ? 1 + BS_REFINE_SWEEPS_BF16
+                                       : ((c.cond_prec == 1 || c.hm.store_prec == 1) ? BS_STORE_SWEEPS_FP32
+                                                                                     : BS_STORE_SWEEPS_FP64);
+      if (c.hm.store_prec == 1)
+        refine_range<float>(c, duhat, dq, du, 0, m1, nu, reinterpret_cast<const float*>(c.ws.Fst), c.st_off_dev,
+                            sweeps);
+      else
+        refine_range<double>(c, duhat, dq, du, 0, m1, nu, c.ws.Fst, c.st_off_dev, sweeps);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      for (int j = 0; j < c.hm.store_chunks; ++j) done[j] = 1;
+    }
     for (int r : c.w_res)
       if (r >= 0 && r < nch && !done[r]) {
         if ((e = backsolve_range(c, duhat, dq, du, c.hm.chunk_first[r], c.hm.chunk_first[r + 1], nu, nb, false)) !=
@@ -398,5 +478,30 @@ hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, doub
     }
   }
   hipLaunchKernelGGL(k_bs_dq, dim3(nm * c.cd.dim * c.cd.ns), dim3(256), 0, c.stream, c.md, 0, c.ws.RQt, du, duhat, dq);
+  return hipGetLastError();
+}
+
+// After the elimination of chunk j (condensation precision prec): the
+// factors of S of its macros that the factor store keeps.
+hipError_t launch_store_factors(HdgContext& c, int prec, int chunk) {
+  if (chunk >= c.hm.store_chunks) return hipSuccess;
+  const int m0 = c.hm.chunk_first[chunk], nmc = c.hm.chunk_first[chunk + 1] - m0;
+  const dim3 grid(1024, (unsigned)nmc);
+  if (prec == 1) {
+    const float* W = reinterpret_cast<const float*>(c.ws.Wm);
+    if (c.hm.store_prec == 1)
+      hipLaunchKernelGGL((k_store_factors<float, float>), grid, dim3(256), 0, c.stream, c.md, m0, W, c.st_off_dev,
+                         reinterpret_cast<float*>(c.ws.Fst));
+    else
+      hipLaunchKernelGGL((k_store_factors<float, double>), grid, dim3(256), 0, c.stream, c.md, m0, W, c.st_off_dev,
+                         c.ws.Fst);
+  } else {
+    if (c.hm.store_prec == 1)
+      hipLaunchKernelGGL((k_store_factors<double, float>), grid, dim3(256), 0, c.stream, c.md, m0, c.ws.Wm,
+                         c.st_off_dev, reinterpret_cast<float*>(c.ws.Fst));
+    else
+      hipLaunchKernelGGL((k_store_factors<double, double>), grid, dim3(256), 0, c.stream, c.md, m0, c.ws.Wm,
+                         c.st_off_dev, c.ws.Fst);
+  }
   return hipGetLastError();
 }

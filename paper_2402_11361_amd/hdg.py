@@ -68,6 +68,7 @@ EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_o
            "hdg_get_residuals", "hdg_precond_apply", "hdg_coarse_size", "hdg_coarse_restrict", "hdg_coarse_neighbours",
            "hdg_coarse_prolong", "hdg_mlp_param_count", "hdg_mlp_work_floats", "hdg_mlp_forward",
            "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking", "hdg_set_chunk_buffers",
+           "hdg_set_factor_store", "hdg_factor_store_macros",
            "hdg_autotune", "hdg_class_count", "hdg_get_tuning", "hdg_set_tuning",
            "hdg_condense_first_layer", "hdg_flow_diagnostics", "hdg_flow_diagnostics_noalloc",
            "hdg_nested_dims", "hdg_condense_nested", "hdg_nested_solve"]
@@ -92,6 +93,8 @@ def load_library(path=LIB_PATH):
     lib.hdg_bind_workspace.argtypes = [vp, vp, sz]
     lib.hdg_set_chunking.argtypes = [vp, i]
     lib.hdg_set_chunk_buffers.argtypes = [vp, i]
+    lib.hdg_set_factor_store.argtypes = [vp, i, i]
+    lib.hdg_factor_store_macros.argtypes = [vp, ctypes.POINTER(i)]
     ip = ctypes.POINTER(ctypes.c_int)
     lib.hdg_autotune.argtypes = [vp, i, ctypes.c_char_p, ip]
     lib.hdg_class_count.argtypes = [vp, ip]
@@ -232,6 +235,35 @@ class Context:
         self._check(self.lib.hdg_query_sizes(self.h, ctypes.byref(s)))
         self.workspace_bytes = s.workspace_bytes
         self.chunk_buffers = int(n_buffers)
+
+    def set_factor_store(self, n_macros, prec=None):
+        """Keep the S factors of up to n_macros macros (whole leading chunks)
+        from the condensation for the recovery, in prec (HDG_FP32 default or
+        HDG_FP64).  Re-plans the workspace; bind_workspace() must follow.
+        Returns the number of macros the plan keeps."""
+        prec = HDG_FP32 if prec is None else prec
+        self._check(self.lib.hdg_set_factor_store(self.h, int(n_macros), int(prec)))
+        self.ws = None
+        s = _Sizes()
+        self._check(self.lib.hdg_query_sizes(self.h, ctypes.byref(s)))
+        self.workspace_bytes = s.workspace_bytes
+        n = ctypes.c_int(0)
+        self._check(self.lib.hdg_factor_store_macros(self.h, ctypes.byref(n)))
+        self.store_macros = n.value
+        return n.value
+
+    def fit_factor_store(self, budget_bytes, prec=None):
+        """Largest factor store (in macros) whose workspace fits in
+        budget_bytes under the current chunking; returns the macros kept."""
+        lo, hi, best = 0, self.n_macros, 0
+        while lo <= hi:
+            mid = (lo + hi) // 2
+            self.set_factor_store(mid, prec)
+            if self.workspace_bytes <= budget_bytes:
+                best, lo = mid, mid + 1
+            else:
+                hi = mid - 1
+        return self.set_factor_store(best, prec)
 
     def fit_chunking(self, budget_bytes):
         """Largest macros per chunk (0 = no chunking) whose workspace fits in

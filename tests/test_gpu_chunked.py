@@ -8,21 +8,31 @@ from gpu_common import make_pair, to_dev, say
 
 pytestmark = pytest.mark.gpu
 
-# (mesh, macros per chunk, chunk slots of W)
+# (mesh, macros per chunk, chunk slots of W, factor store (macros, precision) or None)
 CASES = {
     # 8 macros in chunks of 3, 3, 2
-    "3d_per_p2_chunk3": (dict(dim=3, n_elem=4, m=2, p=2, periodic=True), 3, 1),
+    "3d_per_p2_chunk3": (dict(dim=3, n_elem=4, m=2, p=2, periodic=True), 3, 1, None),
     # 4 macro shapes; chunks of 2 hold macros of different classes
-    "3d_per_uneven_p2_chunk2": (dict(dim=3, seg=[[2, 3], [3, 2], [2, 2]], p=2, periodic=True), 2, 1),
+    "3d_per_uneven_p2_chunk2": (dict(dim=3, seg=[[2, 3], [3, 2], [2, 2]], p=2, periodic=True), 2, 1, None),
     # boundary faces; single-macro chunks
-    "2d_dir_p3_chunk1": (dict(dim=2, n_elem=4, m=2, p=3, periodic=False, state="shear", mach=0.2), 1, 1),
+    "2d_dir_p3_chunk1": (dict(dim=2, n_elem=4, m=2, p=3, periodic=False, state="shear", mach=0.2), 1, 1, None),
     # two slots: chunk j + 1 formed beside the elimination of chunk j; the
     # recovery starts from the last two chunks and forms the other two again
-    "3d_per_p2_chunk2_2slots": (dict(dim=3, n_elem=4, m=2, p=2, periodic=True), 2, 2),
+    "3d_per_p2_chunk2_2slots": (dict(dim=3, n_elem=4, m=2, p=2, periodic=True), 2, 2, None),
     # two slots, several classes per chunk, chunks of 3, 3, 2 in slots 0, 1, 0
     # (the recovery forms the first chunk again)
-    "3d_per_uneven_p2_chunk3_2slots": (dict(dim=3, seg=[[2, 3], [3, 2], [2, 3]], p=2, periodic=True), 3, 2),
+    "3d_per_uneven_p2_chunk3_2slots": (dict(dim=3, seg=[[2, 3], [3, 2], [2, 3]], p=2, periodic=True), 3, 2, None),
+    # factor store: chunks 0 and 1 from FP32 copies of their factors, chunk 2
+    # formed again, chunk 3 from W
+    "3d_per_p2_chunk2_store32": (dict(dim=3, n_elem=4, m=2, p=2, periodic=True), 2, 1, (4, "fp32")),
+    # FP64 store of chunks 0 to 2 over several classes, chunk 3 from W
+    "3d_per_uneven_p2_chunk2_store64": (dict(dim=3, seg=[[2, 3], [3, 2], [2, 2]], p=2, periodic=True), 2, 1,
+                                        (8, "fp64")),
+    # two slots and a store: chunk 0 stored, chunk 1 formed again, 2 and 3 from W
+    "2d_dir_p3_chunk1_2slots_store32": (dict(dim=2, n_elem=4, m=2, p=3, periodic=False, state="shear", mach=0.2), 1, 2,
+                                        (1, "fp32")),
 }
+STORED = {"3d_per_p2_chunk2_store32": 4, "3d_per_uneven_p2_chunk2_store64": 6, "2d_dir_p3_chunk1_2slots_store32": 1}
 
 TOL32 = 5e-4
 
@@ -38,11 +48,15 @@ def pairs():
 
 def _get(pairs, name):
     if name not in pairs:
-        case, per, slots = CASES[name]
+        from paper_2402_11361_amd.hdg import HDG_FP32, HDG_FP64
+        case, per, slots, store = CASES[name]
         say(f"[chunked setup] {name}")
         S, inp, ctx = make_pair(case)
         ctx.set_chunking(per)
         ctx.set_chunk_buffers(slots)
+        if store:
+            kept = ctx.set_factor_store(store[0], HDG_FP32 if store[1] == "fp32" else HDG_FP64)
+            assert kept == STORED[name], kept
         ctx.bind_workspace()
         d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
         ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
@@ -157,7 +171,7 @@ def test_chunked_newton_refines_fp32_to_oracle():
     from oracle.newton import newton_solve
     from paper_2402_11361_amd.driver import StageDriver
     from paper_2402_11361_amd.hdg import HDG_FP32
-    case, per, _ = CASES["3d_per_uneven_p2_chunk2"]
+    case, per, _, _ = CASES["3d_per_uneven_p2_chunk2"]
     say("[chunked newton] 3d_per_uneven_p2 chunks of 2, FP32")
     S, inp, ctx = make_pair(case)
     ctx.set_chunking(per)
@@ -171,3 +185,27 @@ def test_chunked_newton_refines_fp32_to_oracle():
     eu, euh, eq = _rel(u.cpu().numpy(), uo), _rel(uh.cpu().numpy(), uho), _rel(q.cpu().numpy(), qo)
     say(f"[chunked newton] u {eu:.2e} uhat {euh:.2e} q {eq:.2e}")
     assert eu < 1e-8 and euh < 1e-8 and eq < 1e-8
+
+
+def test_chunked_newton_with_factor_store_matches_oracle():
+    """FP64 chunked condensation with an FP32 factor store inside the Newton
+    stage solve: every linearisation invalidates the store and the next
+    condensation refills it; the stage solution is the oracle's."""
+    from oracle.newton import newton_solve
+    from paper_2402_11361_amd.driver import StageDriver
+    from paper_2402_11361_amd.hdg import HDG_FP32
+    case, per, _, _ = CASES["3d_per_p2_chunk2_store32"]
+    say("[chunked newton] 3d_per_p2 chunks of 2, FP64 with an FP32 factor store of 4 macros")
+    S, inp, ctx = make_pair(case)
+    ctx.set_chunking(per)
+    assert ctx.set_factor_store(4, HDG_FP32) == 4
+    ctx.bind_workspace()
+    qo, uo, uho, _ = newton_solve(S, inp["q"], inp["u"], inp["uh"], w=inp["w"], dt=inp["dt"], dii=inp["dii"],
+                                  abs_tol=1e-12, rel_tol=1e-12, max_it=12)
+    drv = StageDriver(ctx, rtol=1e-12, newton_abs=1e-12, newton_rel=1e-12, max_newton=12)
+    q, u, uh = to_dev(inp["q"]), to_dev(inp["u"]), to_dev(inp["uh"])
+    res = drv.solve_stage(q, u, uh, to_dev(inp["w"]), inp["dt"], inp["dii"])
+    assert res["res_hist"][-1] < 1e-11
+    eu, euh, eq = _rel(u.cpu().numpy(), uo), _rel(uh.cpu().numpy(), uho), _rel(q.cpu().numpy(), qo)
+    say(f"[chunked newton store] u {eu:.2e} uhat {euh:.2e} q {eq:.2e}")
+    assert eu < 1e-10 and euh < 1e-10 and eq < 1e-10
