@@ -109,48 +109,86 @@ __global__ void __launch_bounds__(256) k_store_factors(MeshDev md, int m0, const
   }
 }
 
-// Backward substitution U du = z in place (z -> du), one workgroup per macro,
-// blocks of 64 rows from the bottom.
+// Sum over c < nb of row[c] * xb[c], row = the 64 entries of one row of a
+// 16 x 64 tile (contiguous, 16-byte aligned, read as 16-byte vectors), xb in
+// LDS.  Entries past nb are read but not used.
+__device__ __forceinline__ double row_dot64(const float* __restrict__ row, const double* xb, int nb) {
+  const float4* v = reinterpret_cast<const float4*>(row);
+  float4 a[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) a[k] = v[k];
+  double s = 0.0;
+  if (nb == 64) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      s += (double)a[k].x * xb[4 * k] + (double)a[k].y * xb[4 * k + 1] + (double)a[k].z * xb[4 * k + 2] +
+           (double)a[k].w * xb[4 * k + 3];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const float e[4] = {a[k].x, a[k].y, a[k].z, a[k].w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) s += (4 * k + t < nb) ? (double)e[t] * xb[4 * k + t] : 0.0;
+    }
+  }
+  return s;
+}
+__device__ __forceinline__ double row_dot64(const double* __restrict__ row, const double* xb, int nb) {
+  const double2* v = reinterpret_cast<const double2*>(row);
+  double s = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {  // two halves of 16 loads each
+    double2 a[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) a[k] = v[16 * h + k];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int c = 32 * h + 2 * k;
+      s += (c < nb ? a[k].x * xb[c] : 0.0) + (c + 1 < nb ? a[k].y * xb[c + 1] : 0.0);
+    }
+  }
+  return s;
+}
+
+// Backward substitution U du = z in place (z -> du), one workgroup per macro:
+// blocks of 64 rows from the bottom, each solved by one wave (column by
+// column), then subtracted from the rows above it (a thread per row, the
+// block's 64 columns of that row read as vectors); z staged in LDS.
 template <class T>
 __global__ void __launch_bounds__(256) k_bs_trsv(MeshDev md, int m0, const T* __restrict__ Wm,
                                                  double* __restrict__ du, const long long* __restrict__ st_off = nullptr) {
+  extern __shared__ double xs[];  // n_u
   __shared__ double sU[BS_ROWS][BS_ROWS + 1];
-  __shared__ double sz[BS_ROWS];
   const int macro = m0 + blockIdx.x;
   const ClassDev& cd = class_of(md, macro);
   const int nu = cd.n_u;
   int ld;
   const T* U = factors_of(md, cd, macro, Wm, st_off, ld);
   double* x = du + md.u_off[macro];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < nu; i += blockDim.x) xs[i] = x[i];
   const int nblk = (nu + BS_ROWS - 1) / BS_ROWS;
   for (int b = nblk - 1; b >= 0; --b) {
-    const int i0 = b * BS_ROWS, i1 = min(nu, i0 + BS_ROWS), nr = i1 - i0;
-    // z[i0:i1] -= U[i0:i1, i1:nu] x[i1:nu]
-    for (int rr = wave; rr < nr; rr += 4) {
-      const int r = i0 + rr;
-      double s = 0.0;
-      for (int c = i1 + lane; c < nu; c += 64) s += (double)U[wtix(r, c, ld)] * x[c];
-      s = wave_sum(s);
-      if (lane == 0) sz[rr] = x[r] - s;
-    }
-    for (int i = threadIdx.x; i < nr * nr; i += blockDim.x) {
+    const int i0 = b * BS_ROWS, nr = min(nu, i0 + BS_ROWS) - i0;
+    for (int i = tid; i < nr * nr; i += blockDim.x) {
       const int r = i / nr, c = i % nr;
       sU[r][c] = (double)U[wtix(i0 + r, i0 + c, ld)];
     }
     __syncthreads();
     if (wave == 0) {
-      // lane j keeps x_j of the block in a register
-      double xv = (lane < nr) ? sz[lane] : 0.0;
+      double zv = (lane < nr) ? xs[i0 + lane] : 0.0;
       for (int r = nr - 1; r >= 0; --r) {
-        double s = (lane > r && lane < nr) ? sU[r][lane] * xv : 0.0;
-        s = wave_sum(s);
-        if (lane == r) xv = (xv - s) / sU[r][r];
+        if (lane == r) zv /= sU[r][r];
+        const double xr = __shfl(zv, r, 64);
+        if (lane < r) zv -= sU[lane][r] * xr;
       }
-      if (lane < nr) x[i0 + lane] = xv;
+      if (lane < nr) xs[i0 + lane] = zv;
     }
     __syncthreads();
+    for (int i = tid; i < i0; i += blockDim.x) xs[i] -= row_dot64(U + wtix(i, i0, ld), xs + i0, nr);
+    __syncthreads();
   }
+  for (int i = tid; i < nu; i += blockDim.x) x[i] = xs[i];
 }
 
 // dQ for one (macro, direction k, component c) field, macros from m0.
@@ -249,8 +287,10 @@ __global__ void __launch_bounds__(256) k_bs_resid(MeshDev md, int m0, ResidPtrs 
 }
 
 // r <- L^{-1} P r for macro m0 + blockIdx.x with the factors of its S rows in
-// W (storage type T): per column pair, its row swaps (ipiv, in column order)
-// then its unit-lower columns in 64-column blocks; r staged in LDS (n_u doubles).
+// W or the factor store (storage type T): per column pair, its row swaps
+// (ipiv, in column order) then its unit-lower columns in 64-column blocks,
+// each solved by one wave and subtracted from the rows below it (a thread per
+// row, as in k_bs_trsv); r staged in LDS (n_u doubles).
 template <class T>
 __global__ void __launch_bounds__(256) k_bs_fwd(MeshDev md, int m0, const T* __restrict__ Wm,
                                                 const int* __restrict__ ipiv_all, double* __restrict__ r,
@@ -291,12 +331,7 @@ __global__ void __launch_bounds__(256) k_bs_fwd(MeshDev md, int m0, const T* __r
         if (lane < nb) rs[b0 + lane] = xv;
       }
       __syncthreads();
-      const double xb = (lane < nb) ? rs[b0 + lane] : 0.0;
-      for (int i = b0 + nb + wave; i < nu; i += 4) {
-        double sv = (lane < nb) ? (double)W[wtix(i, b0 + lane, ld)] * xb : 0.0;
-        sv = wave_sum(sv);
-        if (lane == 0) rs[i] -= sv;
-      }
+      for (int i = b0 + nb + tid; i < nu; i += blockDim.x) rs[i] -= row_dot64(W + wtix(i, b0, ld), rs + b0, nb);
       __syncthreads();
     }
   }
@@ -343,7 +378,8 @@ static void refine_range(HdgContext& c, const double* duhat, double* dq, double*
     hipLaunchKernelGGL(k_bs_resid, dim3((nmax + 3) / 4, nm), dim3(256), 0, c.stream, c.md, m0, rp, du, dq, duhat, r);
     hipLaunchKernelGGL(k_bs_fwd<T>, dim3(nm), dim3(256), (size_t)nu * sizeof(double), c.stream, c.md, m0, F,
                        c.ws.ipiv, r, st_off);
-    hipLaunchKernelGGL(k_bs_trsv<T>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, F, r, st_off);
+    hipLaunchKernelGGL(k_bs_trsv<T>, dim3(nm), dim3(256), (size_t)nu * sizeof(double), c.stream, c.md, m0, F, r,
+                       st_off);
     hipLaunchKernelGGL(k_add_range, dim3(nblk), dim3(256), 0, c.stream, nr, r + u0, du + u0);
   }
 }
@@ -371,7 +407,8 @@ static hipError_t backsolve_range(HdgContext& c, const double* duhat, double* dq
     else
       hipLaunchKernelGGL(k_bs_rhs<float>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, m0, W32,
                          duhat, du);
-    hipLaunchKernelGGL(k_bs_trsv<float>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, W32, du, nullptr);
+    hipLaunchKernelGGL(k_bs_trsv<float>, dim3(nm), dim3(256), (size_t)nu * sizeof(double), c.stream, c.md, m0, W32,
+                       du, nullptr);
     // FP64 refinement against the u-rows' residual
     const int sweeps = (c.bf16_update && !rhs_in_w) ? BS_REFINE_SWEEPS_BF16 : BS_REFINE_SWEEPS;
     refine_range<float>(c, duhat, dq, du, m0, m1, nu, W32, nullptr, sweeps);
@@ -381,7 +418,8 @@ static hipError_t backsolve_range(HdgContext& c, const double* duhat, double* dq
     else
       hipLaunchKernelGGL(k_bs_rhs<double>, grid_rhs, dim3(256), (size_t)nb * sizeof(double), c.stream, c.md, m0,
                          c.ws.Wm, duhat, du);
-    hipLaunchKernelGGL(k_bs_trsv<double>, dim3(nm), dim3(256), 0, c.stream, c.md, m0, c.ws.Wm, du, nullptr);
+    hipLaunchKernelGGL(k_bs_trsv<double>, dim3(nm), dim3(256), (size_t)nu * sizeof(double), c.stream, c.md, m0,
+                       c.ws.Wm, du, nullptr);
   }
   return hipGetLastError();
 }
