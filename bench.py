@@ -782,7 +782,7 @@ def main():
     ap.add_argument("--factor-store", default="fp32", choices=("none", "fp32", "fp64"),
                     help="keep the S factors of the leading chunks for the recovery (FP32 copies refined in FP64, "
                          "or FP64)")
-    ap.add_argument("--store-chunk-frac", type=float, default=0.5,
+    ap.add_argument("--store-chunk-frac", type=float, default=0.35,
                     help="with --factor-store: chunk size as a fraction of the largest that fits")
     ap.add_argument("--chunk-slots", type=int, default=1, choices=(1, 2),
                     help="chunk slots of the condensation buffer (2: the next chunk is formed beside the "
