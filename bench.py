@@ -784,6 +784,8 @@ def main():
                          "or FP64)")
     ap.add_argument("--store-chunk-frac", type=float, default=0.35,
                     help="with --factor-store: chunk size as a fraction of the largest that fits")
+    ap.add_argument("--progress", action="store_true",
+                    help="a line per finished condensation/recovery chunk (for profiled runs; syncs per chunk)")
     ap.add_argument("--chunk-slots", type=int, default=1, choices=(1, 2),
                     help="chunk slots of the condensation buffer (2: the next chunk is formed beside the "
                          "elimination of this one)")
@@ -863,6 +865,8 @@ def main():
         sprec = HDG_FP32 if args.factor_store == "fp32" else HDG_FP64
         store = dict(prec=args.factor_store, macros=ctx.fit_factor_store(free - (8 << 30), sprec))
     ctx.bind_workspace()
+    if args.progress:
+        ctx.set_progress(True)
     say(f"{args.config}: {ctx.n_macros} macros, n_glob {ctx.n_glob}, workspace {ctx.workspace_bytes / 1e9:.1f} GB, "
         f"{per_chunk or ctx.n_macros} macros per condensation chunk, factor store {store}")
     u0, q0, uh0 = workload_arrays(ctx, cfg)

@@ -220,6 +220,12 @@ hdg_status hdg_set_factor_store(hdg_ctx ctx, int n_macros, hdg_prec prec);
 /* Macros the factor store holds under the current plan (whole chunks). */
 hdg_status hdg_factor_store_macros(hdg_ctx ctx, int* n_stored);
 
+/* Progress lines for long runs (for instance under a profiler that
+ * serialises every kernel): with on != 0, hdg_condense and
+ * hdg_local_backsolve wait for the library's stream after each chunk and
+ * print "[hdg] <phase> <i> of <n> done" on stderr.  Off by default. */
+hdg_status hdg_set_progress(hdg_ctx ctx, int on);
+
 /* Autotuner of the batched elimination of hdg_condense: for every macro
  * class (one per macro shape) and the given condensation precision, times
  * the class's elimination (HIP events on the context's stream, after one

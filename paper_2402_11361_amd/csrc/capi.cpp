@@ -489,6 +489,12 @@ hdg_status hdg_set_factor_store(hdg_ctx ctx, int n_macros, hdg_prec prec) {
   return HDG_OK;
 }
 
+hdg_status hdg_set_progress(hdg_ctx ctx, int on) {
+  if (!ctx) return HDG_EINVAL;
+  ctx->c.progress = on != 0;
+  return HDG_OK;
+}
+
 hdg_status hdg_factor_store_macros(hdg_ctx ctx, int* n_stored) {
   if (!ctx || !n_stored) return HDG_EINVAL;
   const HostMesh& hm = ctx->c.hm;
@@ -722,6 +728,7 @@ static hipError_t condense_chunks(HdgContext& c, int p32) {
       if ((e = launch_lu(c, p32, j, false)) != hipSuccess) return e;
       if ((e = launch_store_factors(c, p32, j)) != hipSuccess) return e;
       if (c.hm.chunked() && (e = launch_extract(c, p32, j)) != hipSuccess) return e;
+      if ((e = report_progress(c, "condensation: chunk", j + 1, nch)) != hipSuccess) return e;
     }
     return hipSuccess;
   }
@@ -748,6 +755,7 @@ static hipError_t condense_chunks(HdgContext& c, int p32) {
     if ((e = launch_store_factors(c, p32, j)) != hipSuccess) return e;
     if ((e = launch_extract(c, p32, j)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev[3 + b], c.stream)) != hipSuccess) return e;
+    if ((e = report_progress(c, "condensation: chunk", j + 1, nch)) != hipSuccess) return e;
   }
   return hipSuccess;
 }

@@ -143,6 +143,7 @@ struct HdgContext {
   int w_res[2] = {-1, -1};
   void forget_w() { w_res[0] = w_res[1] = -1; }
   bool store_valid = false;             // the factor store holds the factors of the last hdg_condense
+  bool progress = false;                // a line on stderr per finished chunk (hdg_set_progress)
   const long long* st_off_dev = nullptr; // device copy of HostMesh::st_off
   std::shared_ptr<NestedPlan> nested;  // nested condensation for one block size (built on first use)
   int nested_m = 0;                    // its block size

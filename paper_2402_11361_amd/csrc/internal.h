@@ -152,6 +152,9 @@ hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class =
                        const double* rhs_duhat = nullptr, hipStream_t s = nullptr);
 // chunks in two slots of W: the formation stream and its events
 hipError_t form_stream_ready(HdgContext& c);
+// with progress reporting on: waits for the library's stream and prints
+// "<what> <i> of <n> done" on stderr
+hipError_t report_progress(HdgContext& c, const char* what, int i, int n);
 // top_only: eliminate the S rows only; rhs_only (with top_only): the columns
 // [0, n_u] only (the recovery form's right-hand side in column n_u)
 hipError_t launch_lu(HdgContext& c, int prec, int chunk, bool top_only, int only_class = -1, bool rhs_only = false);

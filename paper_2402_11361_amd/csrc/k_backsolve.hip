@@ -463,6 +463,7 @@ hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, doub
         refine_range<double>(c, duhat, dq, du, 0, m1, nu, c.ws.Fst, c.st_off_dev, sweeps);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       for (int j = 0; j < c.hm.store_chunks; ++j) done[j] = 1;
+      if ((e = report_progress(c, "recovery: stored chunks", c.hm.store_chunks, nch)) != hipSuccess) return e;
     }
     for (int r : c.w_res)
       if (r >= 0 && r < nch && !done[r]) {
@@ -481,6 +482,7 @@ hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, doub
         if ((e = launch_form(c, c.cond_prec, m0, m1, -1, duhat)) != hipSuccess) return e;
         if ((e = launch_lu(c, c.cond_prec, j, true, -1, true)) != hipSuccess) return e;
         if ((e = backsolve_range(c, duhat, dq, du, m0, m1, nu, nb, true)) != hipSuccess) return e;
+        if ((e = report_progress(c, "recovery: chunk", j + 1, nch)) != hipSuccess) return e;
       }
     } else if (!todo.empty()) {
       if ((e = form_stream_ready(c)) != hipSuccess) return e;
@@ -511,6 +513,7 @@ hipError_t launch_backsolve(HdgContext& c, const double* duhat, double* dq, doub
         const int m0 = c.hm.chunk_first[j], m1 = c.hm.chunk_first[j + 1];
         if ((e = backsolve_range(c, duhat, dq, du, m0, m1, nu, nb, true)) != hipSuccess) return e;
         if ((e = hipEventRecord(ev[3 + b], c.stream)) != hipSuccess) return e;
+        if ((e = report_progress(c, "recovery: chunk", j + 1, nch)) != hipSuccess) return e;
         if (t + 1 < todo.size() && !ahead && (e = form(todo[t + 1])) != hipSuccess) return e;
       }
     }

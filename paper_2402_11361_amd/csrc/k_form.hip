@@ -22,6 +22,7 @@
 // by element (and direction by direction) into LDS row buffers, in a fixed
 // order.
 #include "context.h"
+#include <cstdio>
 
 namespace {
 
@@ -454,6 +455,15 @@ hipError_t launch_form(HdgContext& c, int prec, int m0, int m1, int only_class, 
   if (prec == 1)
     return form_all<float>(c, s, m0, m1, reinterpret_cast<float*>(c.ws.Wm), gloc, only_class, rhs_duhat);
   return form_all<double>(c, s, m0, m1, c.ws.Wm, gloc, only_class, rhs_duhat);
+}
+
+hipError_t report_progress(HdgContext& c, const char* what, int i, int n) {
+  if (!c.progress) return hipSuccess;
+  const hipError_t e = hipStreamSynchronize(c.stream);
+  if (e != hipSuccess) return e;
+  std::fprintf(stderr, "[hdg] %s %d of %d done\n", what, i, n);
+  std::fflush(stderr);
+  return hipSuccess;
 }
 
 hipError_t form_stream_ready(HdgContext& c) {

@@ -68,7 +68,7 @@ EXPORTS = ["hdg_setup_mesh", "hdg_query_sizes", "hdg_macro_offsets", "hdg_face_o
            "hdg_get_residuals", "hdg_precond_apply", "hdg_coarse_size", "hdg_coarse_restrict", "hdg_coarse_neighbours",
            "hdg_coarse_prolong", "hdg_mlp_param_count", "hdg_mlp_work_floats", "hdg_mlp_forward",
            "hdg_mlp_loss_grad", "hdg_mlp_adam", "hdg_learned_bind", "hdg_set_chunking", "hdg_set_chunk_buffers",
-           "hdg_set_factor_store", "hdg_factor_store_macros",
+           "hdg_set_factor_store", "hdg_factor_store_macros", "hdg_set_progress",
            "hdg_autotune", "hdg_class_count", "hdg_get_tuning", "hdg_set_tuning",
            "hdg_condense_first_layer", "hdg_flow_diagnostics", "hdg_flow_diagnostics_noalloc",
            "hdg_nested_dims", "hdg_condense_nested", "hdg_nested_solve"]
@@ -95,6 +95,7 @@ def load_library(path=LIB_PATH):
     lib.hdg_set_chunk_buffers.argtypes = [vp, i]
     lib.hdg_set_factor_store.argtypes = [vp, i, i]
     lib.hdg_factor_store_macros.argtypes = [vp, ctypes.POINTER(i)]
+    lib.hdg_set_progress.argtypes = [vp, i]
     ip = ctypes.POINTER(ctypes.c_int)
     lib.hdg_autotune.argtypes = [vp, i, ctypes.c_char_p, ip]
     lib.hdg_class_count.argtypes = [vp, ip]
@@ -251,6 +252,11 @@ class Context:
         self._check(self.lib.hdg_factor_store_macros(self.h, ctypes.byref(n)))
         self.store_macros = n.value
         return n.value
+
+    def set_progress(self, on=True):
+        """Progress lines on stderr per finished chunk of the condensation and
+        the recovery (waits for the stream after each chunk)."""
+        self._check(self.lib.hdg_set_progress(self.h, 1 if on else 0))
 
     def fit_factor_store(self, budget_bytes, prec=None):
         """Largest factor store (in macros) whose workspace fits in
