@@ -175,7 +175,8 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes);
  * (n_u + n_b)^2 per macro do not fit in device memory at once (the local
  * problems are independent per macro, Sec. 3.3, so they can be processed in
  * groups).  macros_per_chunk > 0 and below n_macros: hdg_condense forms and
- * eliminates consecutive ranges of that many macros through one buffer and
+ * eliminates consecutive ranges of that many macros (the first range takes
+ * the remainder of n_macros / macros_per_chunk) through one buffer and
  * keeps only the condensed blocks A-hat^{T_i} (compact, in the condensation
  * precision) and b-hat^{T_i}; hdg_local_backsolve forms and factors each
  * range's S again (the S rows only, with the right-hand side f + C duhat of

@@ -494,10 +494,14 @@ void plan_workspace(HdgContext& c) {
     pb += (long long)hm.class_count[k] * c.hcs[k].n_u;
   }
   // chunks of consecutive macros; inside a chunk's W buffer the matrices are
-  // grouped by class (one chunk holding every macro when chunking is off)
+  // grouped by class (one chunk holding every macro when chunking is off).
+  // The first chunk takes the remainder, so that the chunks condensed last,
+  // whose eliminations the recovery reuses from W, are full.
   const int per = (hm.chunk_macros > 0 && hm.chunk_macros < nm) ? hm.chunk_macros : nm;
   hm.chunk_first.clear();
-  for (int i = 0; i < nm; i += per) hm.chunk_first.push_back(i);
+  hm.chunk_first.push_back(0);
+  for (int i = nm % per; i < nm; i += per)
+    if (i > 0) hm.chunk_first.push_back(i);
   hm.chunk_first.push_back(nm);
   const int nch = hm.n_chunks();
   hm.chunk_class_w.assign((size_t)nch * ncl, 0);

@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 # (mesh, macros per chunk, chunk slots of W, factor store (macros, precision) or None)
 CASES = {
-    # 8 macros in chunks of 3, 3, 2
+    # 8 macros in chunks of 2, 3, 3 (the first chunk takes the remainder)
     "3d_per_p2_chunk3": (dict(dim=3, n_elem=4, m=2, p=2, periodic=True), 3, 1, None),
     # 4 macro shapes; chunks of 2 hold macros of different classes
     "3d_per_uneven_p2_chunk2": (dict(dim=3, seg=[[2, 3], [3, 2], [2, 2]], p=2, periodic=True), 2, 1, None),
@@ -19,7 +19,7 @@ CASES = {
     # two slots: chunk j + 1 formed beside the elimination of chunk j; the
     # recovery starts from the last two chunks and forms the other two again
     "3d_per_p2_chunk2_2slots": (dict(dim=3, n_elem=4, m=2, p=2, periodic=True), 2, 2, None),
-    # two slots, several classes per chunk, chunks of 3, 3, 2 in slots 0, 1, 0
+    # two slots, several classes per chunk, chunks of 2, 3, 3 in slots 0, 1, 0
     # (the recovery forms the first chunk again)
     "3d_per_uneven_p2_chunk3_2slots": (dict(dim=3, seg=[[2, 3], [3, 2], [2, 3]], p=2, periodic=True), 3, 2, None),
     # factor store: chunks 0 and 1 from FP32 copies of their factors, chunk 2
