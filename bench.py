@@ -33,13 +33,13 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per hdg_condense call of the FP64 path, per workload, from two
-# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by what the counters
-# read for a 1 GiB device copy in the same run
+# HBM bytes per hdg_condense call of the FP64 path, per workload and macros
+# per chunk, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by
+# what the counters read for a 1 GiB device copy in the same run
 # (profiles/newton_step_tgv48_m4_p2_fp64.md), valid only while the kernel
 # sources hash to `sha`.
-CONDENSE_TRAFFIC = {"sha": "b8b5f29f55ccbac0", "tgv48_m4_p2": 21.48e12}
-CONDENSE_SOURCES = ("k_form.hip", "k_lu.hip")
+CONDENSE_TRAFFIC = {"sha": "d982f9e5811eff96", "tgv48_m4_p2/122": 20.69e12}
+CONDENSE_SOURCES = ("k_form.hip", "k_lu.hip", "k_backsolve.hip", "k_krylov.hip")
 
 
 def sources_sha():
@@ -943,7 +943,8 @@ def main():
     cond_calls = plain["cond_calls"]
     cond_ms = float(np.mean(cond_calls))
     cond_tflops = flops / (cond_ms * 1e-3) / 1e12
-    traffic = CONDENSE_TRAFFIC.get(args.config) if sources_sha() == CONDENSE_TRAFFIC["sha"] else None
+    traffic = (CONDENSE_TRAFFIC.get(f"{args.config}/{per_chunk or nm}") if sources_sha() == CONDENSE_TRAFFIC["sha"]
+               else None)
     peak = PEAK_FP64_TFLOPS if main_prec == HDG_FP64 else PEAK_FP32_TFLOPS
     if main_prec != HDG_FP64:
         traffic = None
