@@ -952,7 +952,7 @@ def main():
                     frac=round(cond_tflops / peak, 4), traffic=traffic,
                     kernel="hdg_condense (chunked): k_form + batched elimination (tournament pivoting k_tslu_round/"
                            "k_tslu_final or the register panel k_panel, k_uinv, k_u12, k_linv2, k_u12lin, k_gemm on "
-                           "FP64 MFMA) + k_extract + face-preconditioner factorisation",
+                           "FP64 MFMA) + k_extract + k_store_factors (factor store) + face-preconditioner factorisation",
                     flops_per_launch=flops, ms_per_launch=round(cond_ms, 3), launches=len(cond_calls))
     ms_step = plain["ms_per_step"]
     out = dict(metric=METRIC, value=round(ms_step, 3), unit="ms/Newton-step", n_gpus=1, steps=args.steps,
