@@ -180,7 +180,10 @@ hdg_status hdg_bind_workspace(hdg_ctx ctx, void* dev_ptr, size_t bytes);
  * keeps only the condensed blocks A-hat^{T_i} (compact, in the condensation
  * precision) and b-hat^{T_i}; hdg_local_backsolve forms and factors each
  * range's S again (the S rows only, with the right-hand side f + C duhat of
- * eq. Csc4a folded into one column: the LU of S carries that column alone).  0 (default) or >= n_macros: everything at once.
+ * eq. Csc4a folded into one column: the LU of S carries that column alone),
+ * except the ranges whose factors it still has (the last range condensed,
+ * left in W, see hdg_set_chunk_buffers, and the factor store, see
+ * hdg_set_factor_store).  0 (default) or >= n_macros: everything at once.
  * Re-plans the workspace: call hdg_query_sizes and hdg_bind_workspace again
  * afterwards (any bound workspace and learned network are released).
  * With chunking, an FP32 inner operator (hdg_krylov_opts.inner_prec) needs
@@ -413,9 +416,10 @@ hdg_status hdg_fgmres_solve(hdg_ctx ctx, const double* b, double* x, const hdg_k
  * After an FP32 condensation the S-solve is refined in FP64: two sweeps of
  * dU += S_32^{-1} r with r = -(R_U + A_uq dQ + A_uu dU + A_u,uh duhat), the
  * FP64 residual of the u-rows of the Newton system (eq. C312) from the
- * linearisation's blocks, so dU and dQ are FP64-accurate.  The residual uses
- * the Krylov vectors of the workspace as scratch (HDG_EDEVICE if n_u_tot
- * exceeds them). */
+ * linearisation's blocks, so dU and dQ are FP64-accurate.  Chunked, the
+ * macros of the factor store are solved the same way from dU = 0 (see
+ * hdg_set_factor_store).  The residual uses the Krylov vectors of the
+ * workspace as scratch (HDG_EDEVICE if n_u_tot exceeds them). */
 hdg_status hdg_local_backsolve(hdg_ctx ctx, const double* duhat, double* dq, double* du);
 
 /* y += a x on n doubles (device): the Newton update. */
