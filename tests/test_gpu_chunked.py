@@ -209,3 +209,36 @@ def test_chunked_newton_with_factor_store_matches_oracle():
     eu, euh, eq = _rel(u.cpu().numpy(), uo), _rel(uh.cpu().numpy(), uho), _rel(q.cpu().numpy(), qo)
     say(f"[chunked newton store] u {eu:.2e} uhat {euh:.2e} q {eq:.2e}")
     assert eu < 1e-10 and euh < 1e-10 and eq < 1e-10
+
+
+def test_progress_lines_name_every_chunk(capfd):
+    """hdg_set_progress: one line per finished chunk of the condensation and
+    of the recovery (stored chunks together, the resident chunk none)."""
+    import torch
+    from paper_2402_11361_amd.hdg import HDG_FP32
+    case, per, _, _ = CASES["3d_per_p2_chunk2_store32"]
+    say("[chunked progress] 3d_per_p2 chunks of 2, store of 4")
+    S, inp, ctx = make_pair(case)
+    ctx.set_chunking(per)
+    ctx.set_factor_store(4, HDG_FP32)
+    ctx.bind_workspace()
+    ctx.set_progress(True)
+    d = {k: (to_dev(v) if isinstance(v, np.ndarray) else v) for k, v in inp.items()}
+    ctx.linearize_stage(d["q"], d["u"], d["uh"], d["w"], inp["dt"], inp["dii"])
+    bhat = torch.zeros(ctx.n_glob, dtype=torch.float64, device="cuda")
+    ctx.condense(bhat)
+    dq = torch.zeros(ctx.n_q_tot, dtype=torch.float64, device="cuda")
+    du = torch.zeros(ctx.n_u_tot, dtype=torch.float64, device="cuda")
+    ctx.local_backsolve(bhat, dq, du)
+    torch.cuda.synchronize()
+    err = capfd.readouterr().err
+    for j in range(1, 5):
+        assert f"[hdg] condensation: chunk {j} of 4 done" in err, err
+    assert "[hdg] recovery: stored chunks 2 of 4 done" in err, err
+    assert "[hdg] recovery: chunk 3 of 4 done" in err, err
+    assert "[hdg] recovery: chunk 4 of 4 done" not in err  # left in W by the condensation
+    ctx.set_progress(False)
+    ctx.condense(bhat)
+    torch.cuda.synchronize()
+    assert "[hdg]" not in capfd.readouterr().err
+    ctx.close()
