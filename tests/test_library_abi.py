@@ -41,3 +41,15 @@ def test_status_strings_and_null_checks():
     assert lib.hdg_setup_mesh(None, None, None, None) == 1
     lib.hdg_query_sizes.restype = ctypes.c_int
     assert lib.hdg_query_sizes(None, None) == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhdg.so not built")
+def test_chunk_plan_entry_points_reject_a_null_context():
+    lib = ctypes.CDLL(LIB)
+    n = ctypes.c_int(0)
+    for name, args in [("hdg_set_chunking", (None, 2)), ("hdg_set_chunk_buffers", (None, 2)),
+                       ("hdg_set_factor_store", (None, 4, 1)), ("hdg_factor_store_macros", (None, ctypes.byref(n))),
+                       ("hdg_set_progress", (None, 1))]:
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        assert f(*args) == 1, name  # HDG_EINVAL
