@@ -17,6 +17,10 @@ The discrete time derivative of a DIRK stage (eq. C242) is written
 dt_u = (d_ii u + w) / dt with w = sum_{j<i} d_ij (u^{n,j} - u^n) - d_ii u^n;
 dt = inf means steady (no time term).
 
+With a degree per macro (mixed degrees; this oracle only), a macro's face
+whose trace degree exceeds the macro's (a neighbour of higher degree) is
+integrated with its own Gauss rule (MacroClass).
+
 Readings (the paper defers these to its references; parity unpinned against
 the paper, fixed here and in the HIP library by convention):
   * lambda_max = |v.n| + c of the trace state, frozen in the Jacobian;
@@ -41,12 +45,20 @@ _ein = partial(np.einsum, optimize=True)
 
 
 class MacroClass:
-    """Reference tables for all macros of one shape (m per axis, p, h per axis)."""
+    """Reference tables for all macros of one shape (m per axis, p, h per axis)
+    and trace degrees of its 2d local faces (face_deg, default p each).
 
-    def __init__(self, dim, m, p, h, nq=None):
+    A face of trace degree pf > p (a neighbour of higher degree) carries
+    Tf = (pf + 1)^(d-1) trace nodes per sub-face and its own Gauss rule of
+    max(p, pf) + 2 points per direction; the per-element face arrays are
+    padded to the largest Tf (T), the padding inactive (Tf and the trace
+    basis Psi's zero columns mark it)."""
+
+    def __init__(self, dim, m, p, h, nq=None, face_deg=None):
         self.dim = d = dim
         self.m = list(m)
         self.p = p
+        self.face_deg = [p] * (2 * d) if face_deg is None else [int(v) for v in face_deg]
         self.h = list(h)
         self.ns = d + 2
         self.nq1 = nq if nq is not None else p + 2
@@ -85,44 +97,57 @@ class MacroClass:
             self.elem_nodes[e] = np.ravel_multi_index(gidx.T, self.n1, order="F")
         # macro faces: 2d local faces, sub-faces, face quadrature
         self.nf_nodes = []   # trace nodes per local face
-        self.face_sub = []   # per local face: list of (element, trace node ids [T])
+        self.face_sub = []   # per local face: list of (element, trace node ids [Tf], padded to T with 0)
+        self.Tf = [(pf + 1) ** (d - 1) for pf in self.face_deg]
+        self.T = max(self.Tf)
         self.Fq = self.nq1 ** (d - 1)
-        self.T = A1 ** (d - 1)
         self.face_tabs = []
         for lf in range(2 * d):
             k, s = divmod(lf, 2)
             tang = [j for j in range(d) if j != k]
-            tn = [self.n1[j] for j in tang]
+            pf = self.face_deg[lf]
+            tn = [mk * pf + 1 for mk in (self.m[j] for j in tang)]
             self.nf_nodes.append(int(np.prod(tn)))
-            fq = np.array(np.unravel_index(np.arange(self.Fq), [self.nq1] * (d - 1), order="F")).T
-            tt = np.array(np.unravel_index(np.arange(self.T), [A1] * (d - 1), order="F")).T
-            # volume basis evaluated at face quadrature points
-            PhiF = np.ones((self.Fq, self.A))
-            Psi = np.ones((self.Fq, self.T))
-            WF = np.ones(self.Fq)
+            if pf == p:
+                nqf, xqf, wqf, V1f, Vt = self.nq1, xq, wq, V1, V1
+            else:
+                nqf = max(p, pf) + 2
+                xqf, wqf = gauss_rule(nqf)
+                V1f, _ = lagrange(g, xqf)
+                Vt, _ = lagrange(gll_nodes(pf), xqf)
+            Fq = nqf ** (d - 1)
+            fq = np.array(np.unravel_index(np.arange(Fq), [nqf] * (d - 1), order="F")).T
+            tt = np.array(np.unravel_index(np.arange(self.Tf[lf]), [pf + 1] * (d - 1), order="F")).T
+            # volume basis and trace basis at the face quadrature points
+            PhiF = np.ones((Fq, self.A))
+            Psi = np.ones((Fq, self.Tf[lf]))
+            WF = np.ones(Fq)
             for j in range(d):
                 if j == k:
                     PhiF *= Vend[s][aidx[:, j]][None, :]
                 else:
                     t = tang.index(j)
-                    PhiF *= V1[fq[:, t]][:, aidx[:, j]]
-                    Psi *= V1[fq[:, t]][:, tt[:, t]]
-                    WF *= wq[fq[:, t]] * self.h[j] / 2.0
+                    PhiF *= V1f[fq[:, t]][:, aidx[:, j]]
+                    Psi *= Vt[fq[:, t]][:, tt[:, t]]
+                    WF *= wqf[fq[:, t]] * self.h[j] / 2.0
+            if self.Tf[lf] < self.T:
+                Psi = np.concatenate([Psi, np.zeros((Fq, self.T - self.Tf[lf]))], axis=1)
             nvec = np.zeros(d); nvec[k] = -1.0 if s == 0 else 1.0
-            fqref = np.zeros((self.Fq, d))
+            fqref = np.zeros((Fq, d))
             for j in range(d):
                 if j == k:
                     fqref[:, j] = 0.0 if s == 0 else 1.0
                 else:
-                    fqref[:, j] = (xq[fq[:, tang.index(j)]] + 1.0) / 2.0
+                    fqref[:, j] = (xqf[fq[:, tang.index(j)]] + 1.0) / 2.0
             subs = []
             for e in range(self.E):
                 if eidx[e][k] != (0 if s == 0 else self.m[k] - 1):
                     continue
                 tid = []
-                for r in range(self.T):
-                    tcoord = [eidx[e][tang[t]] * p + tt[r, t] for t in range(d - 1)]
+                for r in range(self.Tf[lf]):
+                    tcoord = [eidx[e][tang[t]] * pf + tt[r, t] for t in range(d - 1)]
                     tid.append(np.ravel_multi_index(tcoord, tn, order="F") if d == 3 else tcoord[0])
+                tid += [0] * (self.T - self.Tf[lf])
                 subs.append((e, np.array(tid, dtype=int)))
             self.face_sub.append(subs)
             self.face_tabs.append(dict(PhiF=PhiF, Psi=Psi, WF=WF, n=nvec, k=k, s=s, xref=fqref))
@@ -230,8 +255,11 @@ class _ElemMaps:
             bmap[:, lf] = (mc.n_q + mc.n_u + mc.nf_off[lf] + np.arange(ns)[None, :, None] * mc.nf_nodes[lf]
                            + self.tid[:, lf][:, None, :])
         self.dof = np.concatenate([qmap.reshape(E, -1), umap.reshape(E, -1), bmap.reshape(E, -1)], axis=1)
-        self.active = np.concatenate([np.ones((E, d * ns * A + ns * A)),
-                                      np.repeat(self.face_on, ns * T, axis=1)], axis=1).astype(bool)
+        # trace dofs of a face on the macro boundary, without the padding past Tf
+        fa = np.zeros((E, 2 * d, ns, T), dtype=bool)
+        for lf in range(2 * d):
+            fa[:, lf, :, :mc.Tf[lf]] = self.face_on[:, lf][:, None, None] > 0
+        self.active = np.concatenate([np.ones((E, d * ns * A + ns * A), dtype=bool), fa.reshape(E, -1)], axis=1)
         self.ne = self.dof.shape[1]
 
 
@@ -358,11 +386,11 @@ def mass_matrix(mc):
 def face_mass(mc, lf):
     """Trace mass matrix <mu_i, mu_j> on local face lf (dense)."""
     tab = mc.face_tabs[lf]
-    nf = mc.nf_nodes[lf]
+    nf, tf = mc.nf_nodes[lf], mc.Tf[lf]
     Mf = np.zeros((nf, nf))
-    Me = _ein("f,fs,ft->st", tab["WF"], tab["Psi"], tab["Psi"])
+    Me = _ein("f,fs,ft->st", tab["WF"], tab["Psi"], tab["Psi"])[:tf, :tf]
     for (e, tid) in mc.face_sub[lf]:
-        Mf[np.ix_(tid, tid)] += Me
+        Mf[np.ix_(tid[:tf], tid[:tf])] += Me
     return Mf
 
 
@@ -386,9 +414,10 @@ def face_matrices(mc):
     col = 0
     for lf in range(2 * mc.dim):
         tab = mc.face_tabs[lf]
-        Ee = _ein("f,fa,ft->at", tab["WF"], tab["PhiF"], tab["Psi"])
+        tf = mc.Tf[lf]
+        Ee = _ein("f,fa,ft->at", tab["WF"], tab["PhiF"], tab["Psi"])[:, :tf]
         for (e, tid) in mc.face_sub[lf]:
             for k in range(mc.dim):
-                out[k][np.ix_(mc.elem_nodes[e], col + tid)] += Ee * tab["n"][k]
+                out[k][np.ix_(mc.elem_nodes[e], col + tid[:tf])] += Ee * tab["n"][k]
         col += mc.nf_nodes[lf]
     return out

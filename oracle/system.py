@@ -24,9 +24,15 @@ class System:
         self.classes = {}
         self.mclass = []
         for i in range(mesh.n_macros):
+            # shape; with mixed degrees also the macro's degree and its faces' trace degrees
             key = tuple(mesh.macro_m(i))
+            if mesh.mixed:
+                key = key + (mesh.macro_deg(i),) + tuple(mesh.macro_face_degs(i))
             if key not in self.classes:
-                self.classes[key] = MacroClass(d, list(key), mesh.p, mesh.h)
+                if mesh.mixed:
+                    self.classes[key] = MacroClass(d, list(key[:d]), key[d], mesh.h, face_deg=list(key[d + 1:]))
+                else:
+                    self.classes[key] = MacroClass(d, list(key), mesh.p, mesh.h)
             self.mclass.append(key)
         nu = [self.cls(i).n_u for i in range(mesh.n_macros)]
         nq = [self.cls(i).n_q for i in range(mesh.n_macros)]
