@@ -19,6 +19,8 @@ def gpu_available():
 
 def mesh_spec_from(S):
     M = S.mesh
+    if M.mixed:
+        raise ValueError("the library takes one degree per mesh; mixed degrees are an oracle-only case")
     return dict(dim=M.dim, n_elem=M.n_elem, lo=M.lo, hi=M.hi, periodic=M.periodic,
                 seg_len=[list(s) for s in M.seg_len], p=M.p)
 
