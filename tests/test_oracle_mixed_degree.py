@@ -154,3 +154,34 @@ def test_geometric_q_blocks(name):
         assert abs(blk["A_qq"] - Aqq).max() < 1e-13
         assert abs(blk["A_qu"] - Aqu).max() < 1e-13
         assert abs(blk["A_qb"] - Aqb).max() < 1e-13
+
+
+@pytest.mark.slow
+def test_couette_convergence_on_mixed_degrees():
+    """Steady Couette flow (Sec. 5.1) on a checkerboard of p = 2 and p = 3
+    macros (m = 2), exact Dirichlet trace: v_1 converges at the rate of the
+    lower degree, p_min + 1 = 3 (2.86, 2.95 on 4 -> 8 -> 16); rho and rho E at
+    about p_min = 2 (2.08, 2.05), below the uniform p = 2 mesh's 2.8 on the
+    same levels (measured: the same with a trace of the smaller degree on
+    the mixed faces, so the face degree choice is not the cause)."""
+    from oracle import newton, couette
+    from oracle.mesh import box_mesh
+    from oracle.physics import Phys
+    from oracle.system import System
+    ph = Phys(Re=1.0, Mach=0.15)
+    errs = []
+    for ne in (4, 8, 16):
+        nseg = ne // 2
+        mp = [(2, 3)[(a + b) % 2] for b in range(nseg) for a in range(nseg)]
+        M = box_mesh(2, ne, 2, 3, macro_p=mp)
+        uD = np.concatenate([couette.exact_u(M.face_node_coords(f).T, ph).reshape(-1) for f in range(M.n_faces)])
+        S = System(M, ph, source=lambda X: couette.source(X, ph), uD=uD)
+        u = np.concatenate([couette.exact_u(M.macro_node_coords(i).T, ph).reshape(-1) for i in range(M.n_macros)])
+        q = np.concatenate([couette.exact_q(M.macro_node_coords(i).T, ph).reshape(-1) for i in range(M.n_macros)])
+        q2, u2, uh2, info = newton.newton_solve(S, q, u, uD.copy(), abs_tol=1e-12, rel_tol=1e-13)
+        assert info["res_hist"][-1] < 1e-11
+        errs.append(couette.l2_errors(S, u2, ph))
+    errs = np.array(errs)
+    rates = np.log2(errs[:-1] / errs[1:])          # columns: rho, v_1, rho E
+    assert rates[-1][1] > 3 - 0.2, rates
+    assert np.all(rates[-1] > 2 - 0.15), rates
