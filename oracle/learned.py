@@ -76,8 +76,9 @@ def coarse_basis(tn_m, p):
 
 def _face_ops(mesh, f):
     fc = mesh.faces[f]
-    tn_m = [(n - 1) // mesh.p for n in fc["tn"]]
-    return coarse_basis(tn_m, mesh.p)
+    deg = fc["deg"]  # the face's trace degree (the mesh degree unless degrees are mixed)
+    tn_m = [(n - 1) // deg for n in fc["tn"]]
+    return coarse_basis(tn_m, deg)
 
 
 def n_features(dim):

@@ -14,6 +14,7 @@ from test_oracle_solvers import _full_system
 # 2 x 2 macros of 2 x 2 elements (2D), 2 x 1 x 2 macros of one element (3D)
 MIXED = {
     "2d_per": dict(dim=2, n_elem=4, m=2, p=2, periodic=True, macro_p=[1, 3, 2, 1]),
+    "2d_per_supg": dict(dim=2, n_elem=4, m=2, p=2, periodic=True, supg=True, macro_p=[2, 1, 3, 2]),
     "2d_dir": dict(dim=2, n_elem=4, m=2, p=2, periodic=False, state="shear", macro_p=[3, 1, 1, 2]),
     "3d_per": dict(dim=3, seg=[[1, 1], [2], [1, 1]], p=1, periodic=True, macro_p=[1, 2, 2, 1]),
 }
