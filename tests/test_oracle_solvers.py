@@ -108,22 +108,25 @@ def test_couette_source_x1_momentum_matches_printed_entry():
     assert np.allclose(s[0], 0, atol=1e-15) and np.allclose(s[2], 0, atol=1e-15)
 
 
-COUETTE_LEVELS = {1: (8, 16, 32), 2: (8, 16, 32), 3: (4, 8, 16), 4: (4, 8, 16)}
+COUETTE_LEVELS = {1: (8, 16, 32), 2: (8, 16, 32), 3: (4, 8, 16), 4: (4, 8, 16), 5: (4, 8, 16)}
+# how far below p + 1 the energy (and every variable) may stay on the finest pair
+COUETTE_SLACK = {1: (0.45, 0.5), 2: (0.2, 0.5), 3: (0.45, 0.5), 4: (0.45, 0.5), 5: (0.7, 0.7)}
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 def test_couette_optimal_convergence(p):
     """Steady Couette flow with the exact Dirichlet trace, m = 2 (Sec. 5.1):
     L2 errors of v_1 converge at the optimal rate p + 1 at every degree
-    (finest pair 1.92 / 2.93 / 3.91 / 4.86 at p = 1 / 2 / 3 / 4).  The energy
+    (finest pair 1.92 / 2.93 / 3.91 / 4.86 / 5.86 at p = 1 to 5).  The energy
     rho E reaches p + 1 at p = 2 (2.97) and approaches it from below at p = 1
     (1.58, 1.61 on these pairs; 1.63 on 32 -> 64), p = 3 (3.60, 3.59) and
-    p = 4 (4.39, 4.66); rho alone (a purely convected variable) stays between
-    p + 1/2 and p + 1.  The paper reads p + 1 for velocity and energy off
-    plots on tetrahedra (p = 1 to 5); the bounds below are what this
-    discretisation reaches on these meshes.  The library's kernels stop at
-    p = 3; the oracle takes any degree."""
+    p = 4 (4.39, 4.66); at p = 5 it stays at 5.35-5.37 (errors near 1e-12 on
+    the finest mesh).  rho alone (a purely convected variable) stays between
+    p + 1/2 and p + 1 up to p = 4 (5.37 at p = 5).  The paper reads p + 1
+    for velocity and energy off plots on tetrahedra (p = 1 to 5); the bounds
+    below are what this discretisation reaches on these meshes.  The
+    library's kernels stop at p = 3; the oracle takes any degree."""
     ph = Phys(Re=1.0, Mach=0.15)
     errs = []
     for ne in COUETTE_LEVELS[p]:
@@ -138,8 +141,8 @@ def test_couette_optimal_convergence(p):
     errs = np.array(errs)
     rates = np.log2(errs[:-1] / errs[1:])          # columns: rho, v_1, rho E
     assert rates[-1][1] > p + 1 - 0.2, rates
-    assert rates[-1][2] > p + 1 - (0.2 if p == 2 else 0.45), rates
-    assert np.all(rates[-1] > p + 1 - 0.5), rates
+    assert rates[-1][2] > p + 1 - COUETTE_SLACK[p][0], rates
+    assert np.all(rates[-1] > p + 1 - COUETTE_SLACK[p][1]), rates
     assert rates[-1][2] >= rates[0][2] - 0.05, rates
 
 
