@@ -5,7 +5,8 @@ single-GPU workload, Taylor-Green 48^3 periodic hexes on [-pi, pi]^3 with
 macros of 4^3 elements (1728 macros), p = 2, Mach 0.1, Re 1600, seeded 1e-4
 noise, dt = CFL h / (V0 (p+1)), CFL = 1, plain FP64.  One timed step is one
 pass of the whole path from the same initial state: linearise -> second-layer
-condensation (in chunks of macros) -> FGMRES(30) to rtol 1e-8 with 5 inner
+condensation (in chunks of macros, keeping FP32 copies of the S factors of
+the leading chunks for the recovery) -> FGMRES(30) to rtol 1e-8 with 5 inner
 GMRES steps -> local recovery -> update.  Extra keys: the mixed-precision
 path on the same workload, the 24^3 workload (3^3-element macros, 512) with
 its variants (whole stages), and the CPU oracle on a bounded sample.
