@@ -217,8 +217,9 @@ class Context:
         return cls(spec["dim"], spec["n_elem"], spec["lo"], spec["hi"], spec["periodic"], spec["seg_len"], spec["p"], **kw)
 
     def set_chunking(self, macros_per_chunk):
-        """Condense in ranges of macros_per_chunk macros (0: all at once).
-        Re-plans the workspace; bind_workspace() must follow."""
+        """Condense in ranges of macros_per_chunk macros (0: all at once; the
+        first range takes the remainder).  Re-plans the workspace;
+        bind_workspace() must follow."""
         self._check(self.lib.hdg_set_chunking(self.h, int(macros_per_chunk)))
         self.ws = None
         s = _Sizes()
